@@ -1,0 +1,153 @@
+/*
+ * catalan.h — C ABI of the gfx950 (MI355X) library for exact Catalan numbers,
+ * after "Exact Computation of the Catalan Number C(2,050,572,903)"
+ * (arXiv 2601.11621).
+ *
+ * The library computes C(n) = (2n)! / (n! (n+1)!) (Sec. 1) by the paper's two
+ * phases: Phase 1 lists every prime p <= 2n with its exponent
+ * e_p = v_p((2n)!) - 2 v_p(n!) - v_p(n+1) (Sec. 2, Legendre's formula) and
+ * groups the primes by exponent (Sec. 3.1, Alg. 1); Phase 2 forms
+ * Q_e = prod_{p in G_e} p and P_e = Q_e^e with balanced product trees and
+ * returns prod_e P_e (Sec. 3.2, Alg. 2).  Every multiplication is an exact
+ * big-integer product on the GPU.
+ *
+ * Conventions (all entry points):
+ *  - Big integers are little-endian arrays of uint32 limbs.
+ *  - Pointers named d_* are device memory of the current HIP device, owned by
+ *    the caller; h_* are host memory owned by the caller.  The library owns only
+ *    its process-global tables (twiddle factors, plans and graphs it caches).
+ *  - `stream` is a hipStream_t (NULL = the default stream).
+ *  - d_work is caller-provided device scratch of at least the size the matching
+ *    size query returns, 256-byte aligned; its contents are not preserved.
+ *  - Return value: CAT_OK (0) or a negative cat_status.  On error, output
+ *    contents are undefined and work already queued on `stream` may still run.
+ *  - Thread safety: calls are serialised by an internal lock; results do not
+ *    depend on the stream, the batch composition or the execution mode.
+ */
+#ifndef CATALAN_H
+#define CATALAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cat_status;
+enum {
+  CAT_OK = 0,
+  CAT_EINVAL = -1,     /* bad argument: n > CAT_N_MAX, NULL required pointer, length too large */
+  CAT_ERANGE = -2,     /* a caller capacity is too small; the *needed output is set */
+  CAT_ENOMEM = -3,     /* workspace too small, or a library allocation failed */
+  CAT_EDEVICE = -4,    /* HIP runtime error; see cat_last_device_error() */
+  CAT_EINTERNAL = -5   /* a device-side invariant failed (negative exponent, carry out of a product) */
+};
+
+#define CAT_N_MAX 2147483647ull   /* 2n < 2^32, so primes fit in uint32 */
+#define CAT_MAX_GROUPS 32         /* e_p <= log2(2n) < 32 */
+
+/* Execution modes (flags of the *_ex entry points). */
+#define CAT_MODE_BATCHED 0u  /* every product of one tree level in one launch per kernel stage */
+#define CAT_MODE_PLAIN 1u    /* one product per launch (the unbatched reference form) */
+#define CAT_MODE_GRAPH 2u    /* with BATCHED: capture the launches in a HIP graph, cached and replayed */
+
+/* Initialise the library on `device` (the current device when < 0): computes
+ * the NTT prime constants and uploads the twiddle tables.  Idempotent.  The
+ * other entry points call it on first use. */
+cat_status cat_init(int device);
+
+/* Static description of a status code. */
+const char* cat_strerror(cat_status s);
+
+/* hipError_t of the last failing HIP call (0 if none). */
+int cat_last_device_error(void);
+
+/* Host-only size query for n (no device work).
+ *  max_primes:      upper bound on the number of primes <= 2n (Dusart's bound).
+ *  max_limbs:       upper bound on the limb count of C(n) (C(n) < 4^n).
+ *  workspace_bytes: d_work size needed by catalan_factor and catalan_exact.
+ * Any pointer may be NULL.  CAT_EINVAL if n > CAT_N_MAX. */
+cat_status catalan_sizes(uint64_t n, size_t* max_primes, size_t* max_limbs, size_t* workspace_bytes);
+
+/* Phase 1 (Sec. 3.1, Alg. 1; Sec. 2 for the exponents).
+ * Writes the primes with e_p > 0 to d_primes grouped by exponent: group g holds
+ * exponent h_exps[g] (ascending over g) and occupies d_primes[h_off[g] ..
+ * h_off[g+1]) with its primes ascending.  h_exps needs CAT_MAX_GROUPS entries,
+ * h_off CAT_MAX_GROUPS + 1.  Synchronises `stream`.
+ * CAT_ERANGE if primes_cap < *n_primes (then *n_primes holds the count). */
+cat_status catalan_factor(uint64_t n, uint32_t* d_primes, size_t primes_cap, uint32_t* h_exps,
+                          uint64_t* h_off, uint32_t* n_groups, size_t* n_primes, void* d_work,
+                          size_t work_bytes, void* stream);
+
+/* Scratch needed by bigint_mul_batched for this batch (host-only). */
+cat_status bigint_mul_workspace(uint32_t batch, const uint64_t* h_a_off, const uint64_t* h_b_off,
+                                size_t* workspace_bytes);
+
+/* Exact products c_i = a_i * b_i, i < batch (the multiplication inside every
+ * BalancedProductTree step, Sec. 3.2).  Operand i is d_a[h_a_off[i] ..
+ * h_a_off[i+1]) and d_b[h_b_off[i] .. h_b_off[i+1]); the product is written to
+ * d_c[h_c_off[i] .. h_c_off[i] + la_i + lb_i), not normalised (leading zero
+ * limbs kept).  Offsets are host arrays of batch+1 entries (h_c_off: batch).
+ * Requirements: 1 <= la_i, lb_i and la_i + lb_i - 1 <= 2^27; the c ranges must
+ * not overlap each other nor any operand.  Synchronises `stream`; CAT_EINTERNAL
+ * if a device check failed.  flags: CAT_MODE_BATCHED or CAT_MODE_PLAIN. */
+cat_status bigint_mul_batched(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off,
+                              const uint32_t* d_b, const uint64_t* h_b_off, uint32_t* d_c,
+                              const uint64_t* h_c_off, void* d_work, size_t work_bytes, void* stream);
+cat_status bigint_mul_batched_ex(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off,
+                                 const uint32_t* d_b, const uint64_t* h_b_off, uint32_t* d_c,
+                                 const uint64_t* h_c_off, void* d_work, size_t work_bytes, void* stream,
+                                 uint32_t flags);
+
+/* C(n) (Sec. 1) by Phase 1 + Phase 2 (Alg. 1, Alg. 2) as normalised limbs:
+ * d_limbs[0 .. *n_limbs), top limb nonzero, C(0) = C(1) = {1}.
+ * d_limbs == NULL is a size query (sets *n_limbs to max_limbs, no device work).
+ * CAT_ERANGE if cap < *n_limbs.  Synchronises `stream`.
+ * catalan_exact uses CAT_MODE_BATCHED | CAT_MODE_GRAPH. */
+cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
+                         size_t work_bytes, void* stream);
+cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
+                            size_t work_bytes, void* stream, uint32_t flags);
+
+/* Reusable plans for repeated batches of the same shape (the batched form
+ * of a tree level).  cat_mul_plan_create buckets the products by transform
+ * length (schoolbook for la, lb <= 128; LDS-resident NTT up to 2^12
+ * coefficients; four-step NTT above) and uploads the descriptor tables;
+ * cat_mul_plan_exec queues the products on `stream` (with CAT_MODE_GRAPH the
+ * launch sequence is captured on first use and replayed as one HIP graph per
+ * set of pointers); cat_mul_plan_check synchronises `stream` and reports a
+ * device-side overflow (CAT_EINTERNAL).  flags as in bigint_mul_batched_ex
+ * plus CAT_MODE_GRAPH.  A plan is used by one thread at a time. */
+typedef struct cat_mul_plan_s* cat_mul_plan;
+cat_status cat_mul_plan_create(uint32_t batch, const uint64_t* h_a_off, const uint64_t* h_b_off,
+                               const uint64_t* h_c_off, uint32_t flags, cat_mul_plan* plan,
+                               size_t* workspace_bytes);
+cat_status cat_mul_plan_exec(cat_mul_plan plan, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c,
+                             void* d_work, size_t work_bytes, void* stream);
+cat_status cat_mul_plan_check(cat_mul_plan plan, void* d_work, void* stream);
+cat_status cat_mul_plan_destroy(cat_mul_plan plan);
+
+/* Fingerprints of a limb vector (verification, Sec. 6 "modular checks"):
+ * h_res[0] = x mod (2^32 - 5), h_res[1] = x mod (2^32 + 1), h_res[2] = x mod (2^32 - 1).
+ * d_work needs 24 * ceil(n / 4096) + 256 bytes.  Synchronises `stream`. */
+cat_status bigint_residues(const uint32_t* d_x, size_t n, uint64_t* h_res, void* d_work,
+                           size_t work_bytes, void* stream);
+
+/* Statistics of the last catalan_exact / bigint_mul_batched call on this
+ * process (host side): number of products, kernel launches (graph nodes count
+ * once per kernel), and the sum of la+lb over all products. */
+typedef struct {
+  uint64_t products;
+  uint64_t launches;
+  uint64_t product_limbs;
+  uint64_t n_primes;
+  uint32_t levels;
+  uint32_t graph_replayed;
+} cat_stats;
+cat_status cat_get_stats(cat_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CATALAN_H */

@@ -1,0 +1,288 @@
+"""Python binding of the gfx950 Catalan library (``libcatalan.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/catalan.h``.  PyTorch provides
+device memory (limb buffers and workspace) and the current stream.  Limbs are
+little-endian uint32 values held in int32 tensors (same bits).
+
+There is no CPU fallback: importing works without a GPU, but every call that
+computes raises if the library is not built or no GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcatalan.so")
+
+CAT_OK, CAT_EINVAL, CAT_ERANGE, CAT_ENOMEM, CAT_EDEVICE, CAT_EINTERNAL = 0, -1, -2, -3, -4, -5
+MODE_BATCHED, MODE_PLAIN, MODE_GRAPH = 0, 1, 2
+_MODES = {"batched": MODE_BATCHED, "plain": MODE_PLAIN, "graph": MODE_BATCHED | MODE_GRAPH}
+MAX_GROUPS = 32
+
+EXPORTS = [
+    "cat_init", "cat_strerror", "cat_last_device_error", "cat_get_stats", "catalan_sizes",
+    "catalan_factor", "bigint_mul_workspace", "bigint_mul_batched", "bigint_mul_batched_ex",
+    "catalan_exact", "catalan_exact_ex", "cat_mul_plan_create", "cat_mul_plan_exec",
+    "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues",
+]
+
+
+class CatalanError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = "%s failed: %s (%d)" % (what, _strerror(status), status)
+        if status == CAT_EDEVICE and _lib is not None:
+            msg += " [hip error %d]" % _lib.cat_last_device_error()
+        super().__init__(msg)
+
+
+class cat_stats(ctypes.Structure):
+    _fields_ = [("products", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("product_limbs", ctypes.c_uint64), ("n_primes", ctypes.c_uint64),
+                ("levels", ctypes.c_uint32), ("graph_replayed", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def _strerror(s: int) -> str:
+    if _lib is None:
+        return "status %d" % s
+    return _lib.cat_strerror(s).decode()
+
+
+def load(path: str = LIB_PATH):
+    """Load libcatalan.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libcatalan.so is not built (run __graft_entry__.build()); "
+                           "there is no fallback path")
+    lib = ctypes.CDLL(path)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    vp = ctypes.c_void_p
+    st = ctypes.c_int32
+    sig = {
+        "cat_init": ([ctypes.c_int], st),
+        "cat_strerror": ([st], ctypes.c_char_p),
+        "cat_last_device_error": ([], ctypes.c_int),
+        "cat_get_stats": ([ctypes.POINTER(cat_stats)], st),
+        "catalan_sizes": ([ctypes.c_uint64, szp, szp, szp], st),
+        "catalan_factor": ([ctypes.c_uint64, vp, ctypes.c_size_t, u32p, u64p, u32p, szp, vp,
+                            ctypes.c_size_t, vp], st),
+        "bigint_mul_workspace": ([ctypes.c_uint32, u64p, u64p, szp], st),
+        "bigint_mul_batched": ([ctypes.c_uint32, vp, u64p, vp, u64p, vp, u64p, vp, ctypes.c_size_t, vp], st),
+        "bigint_mul_batched_ex": ([ctypes.c_uint32, vp, u64p, vp, u64p, vp, u64p, vp, ctypes.c_size_t, vp,
+                                   ctypes.c_uint32], st),
+        "catalan_exact": ([ctypes.c_uint64, vp, ctypes.c_size_t, szp, vp, ctypes.c_size_t, vp], st),
+        "catalan_exact_ex": ([ctypes.c_uint64, vp, ctypes.c_size_t, szp, vp, ctypes.c_size_t, vp,
+                              ctypes.c_uint32], st),
+        "cat_mul_plan_create": ([ctypes.c_uint32, u64p, u64p, u64p, ctypes.c_uint32,
+                                 ctypes.POINTER(vp), szp], st),
+        "cat_mul_plan_exec": ([vp, vp, vp, vp, vp, ctypes.c_size_t, vp], st),
+        "cat_mul_plan_check": ([vp, vp, vp], st),
+        "cat_mul_plan_destroy": ([vp], st),
+        "bigint_residues": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != CAT_OK:
+        raise CatalanError(status, what)
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the Catalan library runs only on the GPU")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _u64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+def _p64(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+_work = {}
+
+
+def workspace(nbytes: int, key: str = "default"):
+    """A reusable device scratch buffer (kept, so graph caches see one address)."""
+    torch = _torch()
+    buf = _work.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+        _work[key] = buf
+    return buf
+
+
+def init(device: int = -1) -> None:
+    _torch()
+    _check(load().cat_init(device), "cat_init")
+
+
+def sizes(n: int):
+    """(max_primes, max_limbs, workspace_bytes) for n (host-only)."""
+    lib = load()
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.catalan_sizes(n, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "catalan_sizes")
+    return a.value, b.value, c.value
+
+
+def stats() -> dict:
+    s = cat_stats()
+    _check(load().cat_get_stats(ctypes.byref(s)), "cat_get_stats")
+    return {f: getattr(s, f) for f, _ in cat_stats._fields_}
+
+
+def factor(n: int, stream=None):
+    """Phase 1 on the GPU: (exps uint32[g], off uint64[g+1], primes int32 device tensor)."""
+    torch = _torch()
+    lib = load()
+    max_primes, _, wbytes = sizes(n)
+    primes = torch.empty(max(max_primes, 1), dtype=torch.int32, device="cuda")
+    w = workspace(wbytes)
+    exps = np.zeros(MAX_GROUPS, dtype=np.uint32)
+    off = np.zeros(MAX_GROUPS + 1, dtype=np.uint64)
+    ng = ctypes.c_uint32()
+    npr = ctypes.c_size_t()
+    st = lib.catalan_factor(n, _ptr(primes), primes.numel(), exps.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                            _p64(off), ctypes.byref(ng), ctypes.byref(npr), _ptr(w), w.numel(), _stream(stream))
+    _check(st, "catalan_factor")
+    g = ng.value
+    return exps[:g].copy(), off[: g + 1].copy(), primes[: npr.value]
+
+
+def exact(n: int, mode: str = "graph", stream=None, out=None):
+    """C(n) as normalised limbs in an int32 device tensor (uint32 bits)."""
+    torch = _torch()
+    lib = load()
+    _, max_limbs, wbytes = sizes(n)
+    w = workspace(wbytes)
+    if out is None:
+        out = torch.empty(max_limbs, dtype=torch.int32, device="cuda")
+    nl = ctypes.c_size_t()
+    st = lib.catalan_exact_ex(n, _ptr(out), out.numel(), ctypes.byref(nl), _ptr(w), w.numel(), _stream(stream),
+                              _MODES[mode])
+    _check(st, "catalan_exact")
+    return out[: nl.value]
+
+
+def mul_batched(a_flat, a_off, b_flat, b_off, mode: str = "batched", stream=None):
+    """c_i = a_i * b_i; returns (c_flat int32 device tensor, c_off uint64[batch+1])."""
+    torch = _torch()
+    lib = load()
+    a_off = _u64(a_off)
+    b_off = _u64(b_off)
+    batch = len(a_off) - 1
+    lens = (a_off[1:] - a_off[:-1]) + (b_off[1:] - b_off[:-1])
+    c_off = np.zeros(batch + 1, dtype=np.uint64)
+    c_off[1:] = np.cumsum(lens)
+    c = torch.empty(max(int(c_off[-1]), 1), dtype=torch.int32, device="cuda")
+    wb = ctypes.c_size_t()
+    _check(lib.bigint_mul_workspace(batch, _p64(a_off), _p64(b_off), ctypes.byref(wb)), "bigint_mul_workspace")
+    w = workspace(wb.value, key="mul")
+    st = lib.bigint_mul_batched_ex(batch, _ptr(a_flat), _p64(a_off), _ptr(b_flat), _p64(b_off), _ptr(c),
+                                   _p64(c_off), _ptr(w), w.numel(), _stream(stream), _MODES[mode] & ~MODE_GRAPH)
+    _check(st, "bigint_mul_batched")
+    return c[: int(c_off[-1])], c_off
+
+
+class MulPlan:
+    """A reusable plan for batches of one shape (see cat_mul_plan_* in catalan.h)."""
+
+    def __init__(self, a_off, b_off, c_off=None, mode: str = "graph"):
+        lib = load()
+        _torch()
+        self.a_off = _u64(a_off)
+        self.b_off = _u64(b_off)
+        batch = len(self.a_off) - 1
+        if c_off is None:
+            lens = (self.a_off[1:] - self.a_off[:-1]) + (self.b_off[1:] - self.b_off[:-1])
+            c_off = np.zeros(batch + 1, dtype=np.uint64)
+            c_off[1:] = np.cumsum(lens)
+        self.c_off = _u64(c_off)
+        self.batch = batch
+        self._h = ctypes.c_void_p()
+        wb = ctypes.c_size_t()
+        _check(lib.cat_mul_plan_create(batch, _p64(self.a_off), _p64(self.b_off), _p64(self.c_off), _MODES[mode],
+                                       ctypes.byref(self._h), ctypes.byref(wb)), "cat_mul_plan_create")
+        self.workspace_bytes = wb.value
+        self._w = None
+
+    def __call__(self, a_flat, b_flat, c_flat, stream=None):
+        torch = _torch()
+        if self._w is None:
+            self._w = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+        _check(load().cat_mul_plan_exec(self._h, _ptr(a_flat), _ptr(b_flat), _ptr(c_flat), _ptr(self._w),
+                                        self._w.numel(), _stream(stream)), "cat_mul_plan_exec")
+        return c_flat
+
+    def check(self, stream=None):
+        if self._w is not None:
+            _check(load().cat_mul_plan_check(self._h, _ptr(self._w), _stream(stream)), "cat_mul_plan_check")
+
+    def close(self):
+        if self._h:
+            load().cat_mul_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def residues(x, stream=None):
+    """(x mod 2^32-5, x mod 2^32+1, x mod 2^32-1) of a limb tensor, on the GPU."""
+    lib = load()
+    n = x.numel()
+    w = workspace(24 * ((n + 4095) // 4096) + 256, key="residues")
+    out = np.zeros(3, dtype=np.uint64)
+    _check(lib.bigint_residues(_ptr(x), n, _p64(out), _ptr(w), w.numel(), _stream(stream)), "bigint_residues")
+    return tuple(int(v) for v in out)
+
+
+def to_numpy(t) -> np.ndarray:
+    """Device limb tensor -> numpy uint32 array."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def to_int(t) -> int:
+    """Device limb tensor -> Python integer."""
+    return int.from_bytes(to_numpy(t).astype("<u4").tobytes(), "little")
+
+
+def from_numpy(a: np.ndarray):
+    torch = _torch()
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32).copy()).to("cuda")

@@ -1,0 +1,7 @@
+// Single translation unit of the gfx950 Catalan library (device code and
+// the C ABI), so that the __constant__ tables need no relocatable device code.
+#include "common.hpp"
+#include "ntt.inc.hip"
+#include "small.inc.hip"
+#include "sieve.inc.hip"
+#include "host.inc.hip"

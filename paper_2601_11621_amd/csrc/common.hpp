@@ -1,0 +1,129 @@
+// Shared definitions of the gfx950 Catalan library: modular arithmetic for the
+// three NTT primes, descriptor structs, launch constants.
+//
+// Every multiplication of the reconstruction phase (Sec. 3.2, Alg. 2 of
+// arXiv 2601.11621) is an exact product of little-endian uint32 limb vectors.
+// Large products go through a cyclic convolution modulo three primes
+//   p0 = 3*2^30+1, p1 = 13*2^28+1, p2 = 29*2^27+1   (all in (2^31, 2^32),
+// 2-adicity >= 27, product ~2^95.1), one 32-bit limb per coefficient, and are
+// recombined with Garner's CRT.  Exactness: a coefficient of a la x lb limb
+// product is < min(la,lb) * 2^64 <= 2^90 for operands up to 2^26 limbs, below
+// p0*p1*p2; the transform length N = 2^k <= 2^27 needs 2-adicity >= k.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CAT_NPRIMES 3
+#define CAT_MAX_LOGN 27
+#define CAT_MAX_GROUPS 32       // e_p <= log2(2n) < 32
+#define CAT_LDS_LOGT 12         // row length of the LDS-resident transforms
+#define CAT_CRT_E 16            // limbs per thread in the CRT/carry kernel
+#define CAT_CRT_THREADS 256
+#define CAT_CRT_BLOCK (CAT_CRT_E * CAT_CRT_THREADS)
+
+// ----------------------------------------------------------------------------
+// Per-prime constants (host computes, device reads from __constant__).
+// Montgomery radix R = 2^32.  A "twiddle pair" (w, wq) holds w = W*R mod p
+// (Montgomery form of W) and wq = w * p^-1 mod 2^32; mul_tw(a, w, wq) = a*W
+// mod p for every 32-bit a.
+// ----------------------------------------------------------------------------
+struct PrimeC {
+  uint32_t p;
+  uint32_t pinv;          // p^-1 mod 2^32
+  uint32_t w16[8], w16q[8];    // omega_16^i (forward), Montgomery pairs
+  uint32_t iw16[8], iw16q[8];  // omega_16^-i (inverse)
+};
+
+struct CrtC {
+  // Garner: x0 = r0; x1 = (r1 - x0) * c01 mod p1; x2 = (r2 - x0 - p0*x1) * c012 mod p2
+  uint32_t c01, c01q;       // p0^-1 mod p1 (Montgomery pair for p1)
+  uint32_t p0m2, p0m2q;     // p0 mod p2 (Montgomery pair for p2)
+  uint32_t c012, c012q;     // (p0*p1)^-1 mod p2 (Montgomery pair for p2)
+  uint32_t p0;              // p0
+  uint32_t p01_lo, p01_hi;  // p0*p1 as 64-bit
+};
+
+// ----------------------------------------------------------------------------
+// Modular arithmetic, p odd, 2^31 < p < 2^32.  Inputs of add/sub reduced.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t p) {
+  uint32_t t = p - b;          // in (0, p]
+  uint32_t d = a - t;
+  return a >= t ? d : d + p;
+}
+__device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t p) {
+  uint32_t d = a - b;
+  return a >= b ? d : d + p;
+}
+// Montgomery multiplication with a precomputed companion (Montgomery 1985,
+// with the quotient digit precomputed as in Shoup's method): returns a*w/R
+// mod p in [0,p) for any 32-bit a and w < p.
+__device__ __forceinline__ uint32_t mul_tw(uint32_t a, uint32_t w, uint32_t wq, uint32_t p) {
+  uint32_t m = a * wq;
+  uint32_t hi = __umulhi(a, w);
+  uint32_t mh = __umulhi(m, p);
+  uint32_t r = hi - mh;
+  return hi >= mh ? r : r + p;
+}
+// General Montgomery product a*b/R mod p, a,b < p.
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
+  uint32_t lo = a * b;
+  uint32_t hi = __umulhi(a, b);
+  uint32_t m = lo * pinv;
+  uint32_t mh = __umulhi(m, p);
+  uint32_t r = hi - mh;
+  return hi >= mh ? r : r + p;
+}
+// limb (any 32-bit value) reduced mod p: 2^32 < 2p, so one subtraction suffices
+__device__ __forceinline__ uint32_t reduce_limb(uint32_t x, uint32_t p) { return x >= p ? x - p : x; }
+
+// ----------------------------------------------------------------------------
+// Descriptors of a batch of products c = a * b.
+// Explicit: a table in device memory.  Tree: computed from the level of a
+// forest of balanced product trees (one tree per exponent group): node i of
+// group g at level j covers leaves [i*2^j, min((i+1)*2^j, K_g)) and has exactly
+// that many limbs; its parent's output sits at the left child's offset.
+// ----------------------------------------------------------------------------
+struct MulDesc {
+  uint64_t a_off, b_off, c_off, r_off;  // r_off: position in the residue arrays
+  uint32_t la, lb;
+};
+
+struct TreeLevel {
+  uint32_t ngroups;
+  uint32_t j;                           // input node size 2^j limbs
+  uint64_t base[CAT_MAX_GROUPS];        // arena offset of group g
+  uint64_t K[CAT_MAX_GROUPS];           // leaves (limbs) of group g
+  uint64_t mpref[CAT_MAX_GROUPS + 1];   // prefix count of products per group
+};
+
+struct DescView {
+  const MulDesc* table;  // nullptr => tree mode
+  TreeLevel tree;
+  __device__ __forceinline__ MulDesc get(uint64_t i) const {
+    if (table) return table[i];
+    uint32_t g = 0;
+    while (g + 1 < tree.ngroups && i >= tree.mpref[g + 1]) g++;
+    uint64_t il = i - tree.mpref[g];
+    uint64_t sz = 1ull << tree.j;
+    MulDesc d;
+    d.a_off = tree.base[g] + 2 * il * sz;
+    d.b_off = d.a_off + sz;
+    d.c_off = d.a_off;
+    d.r_off = d.a_off;
+    d.la = (uint32_t)sz;
+    uint64_t rem = tree.K[g] - (2 * il + 1) * sz;
+    d.lb = (uint32_t)(rem < sz ? rem : sz);
+    return d;
+  }
+};
+
+// CRT/carry segments: out[out_pos + k] for k < len from residues at res_pos + k.
+struct CrtSeg {
+  uint64_t out_pos, res_pos, len;
+};
+
+// Bits of the device error word
+#define CAT_DEVERR_CARRY_OUT 1u     // a product overflowed its la+lb limbs
+#define CAT_DEVERR_NEG_EXP 2u       // negative exponent (C(n) not integral)
+#define CAT_DEVERR_BOUNDS 4u        // a prime count exceeded its buffer

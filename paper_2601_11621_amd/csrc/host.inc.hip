@@ -1,0 +1,1392 @@
+// Host side of the library: constants, workspace layout, the reconstruction
+// planner (Sec. 3.2, Alg. 2) and the executor (batched, plain or graph).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/catalan.h"
+
+// ----------------------------------------------------------------------------
+// library state
+// ----------------------------------------------------------------------------
+namespace {
+
+static const uint32_t kP[CAT_NPRIMES] = {3221225473u, 3489660929u, 3892314113u};
+static const uint32_t kGen[CAT_NPRIMES] = {5u, 3u, 3u};   // primitive roots
+
+struct Stage;
+struct Plan;
+struct MulPlanImpl;
+
+struct Lib {
+  bool inited = false;
+  int device = -1;
+  PrimeC prc[CAT_NPRIMES];
+  CrtC crt;
+  RootsC roots;
+  uint2* tws = nullptr;
+  uint2* itws = nullptr;
+  std::map<int, std::pair<uint2*, uint2*>> twn;
+  void* pin = nullptr;          // pinned host staging for small D2H
+  int last_err = 0;
+  std::recursive_mutex mu;
+  cat_stats stats{};
+  std::map<uint64_t, Plan*> plans;
+  std::vector<uint64_t> plan_order;
+  hipStream_t cap_stream = nullptr;
+};
+Lib g;
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) {                         \
+      g.last_err = (int)e_;                         \
+      return CAT_EDEVICE;                           \
+    }                                               \
+  } while (0)
+#define STCHK(x)                  \
+  do {                            \
+    cat_status s_ = (x);          \
+    if (s_ != CAT_OK) return s_;  \
+  } while (0)
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+// ---------------------------------------------------------------- host modular arithmetic
+uint32_t h_mulmod(uint32_t a, uint32_t b, uint32_t p) { return (uint32_t)((uint64_t)a * b % p); }
+uint32_t h_powmod(uint32_t b, uint64_t e, uint32_t p) {
+  uint32_t r = 1 % p;
+  b %= p;
+  while (e) {
+    if (e & 1) r = h_mulmod(r, b, p);
+    b = h_mulmod(b, b, p);
+    e >>= 1;
+  }
+  return r;
+}
+uint32_t h_inv(uint32_t a, uint32_t p) { return h_powmod(a, p - 2, p); }
+uint32_t h_inv32(uint32_t p) {  // p^-1 mod 2^32 (Newton)
+  uint32_t x = p;
+  for (int i = 0; i < 5; i++) x *= 2u - p * x;
+  return x;
+}
+uint32_t h_mont(uint32_t W, uint32_t p) { return (uint32_t)(((uint64_t)(W % p) << 32) % p); }
+void h_pair(uint32_t W, const PrimeC& pc, uint32_t* w, uint32_t* wq) {
+  *w = h_mont(W, pc.p);
+  *wq = *w * pc.pinv;
+}
+uint2 h_pair2(uint32_t W, const PrimeC& pc) {
+  uint2 r;
+  h_pair(W, pc, &r.x, &r.y);
+  return r;
+}
+
+uint64_t isqrt64(uint64_t x) {
+  uint64_t r = (uint64_t)std::sqrt((double)x);
+  while (r * r > x) r--;
+  while ((r + 1) * (r + 1) <= x) r++;
+  return r;
+}
+int ceil_log2(uint64_t x) {
+  int k = 0;
+  while ((1ull << k) < x) k++;
+  return k;
+}
+
+// Upper bound on pi(x): Dusart (2010) for x >= 355991, Rosser-Schoenfeld below.
+uint64_t pi_bound(uint64_t x) {
+  if (x < 17) return 8;
+  const double lx = std::log((double)x);
+  double b;
+  if (x >= 355991) b = (double)x / lx * (1.0 + 1.0 / lx + 2.51 / (lx * lx));
+  else b = 1.25506 * (double)x / lx;
+  return (uint64_t)b + 16;
+}
+
+cat_status set_device() {
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != g.device) HIPCHK(hipSetDevice(g.device));
+  return CAT_OK;
+}
+
+cat_status init_locked(int device) {
+  if (g.inited) return CAT_OK;
+  if (device < 0) HIPCHK(hipGetDevice(&device));
+  g.device = device;
+  HIPCHK(hipSetDevice(device));
+  memset(&g.roots, 0, sizeof(g.roots));
+  for (int i = 0; i < CAT_NPRIMES; i++) {
+    PrimeC& pc = g.prc[i];
+    memset(&pc, 0, sizeof(pc));
+    pc.p = kP[i];
+    pc.pinv = h_inv32(kP[i]);
+    const uint32_t p = pc.p;
+    const uint32_t w27 = h_powmod(kGen[i], (uint64_t)(p - 1) >> CAT_MAX_LOGN, p);
+    const uint32_t iw27 = h_inv(w27, p);
+    for (int s = 0; s <= CAT_MAX_LOGN; s++) {
+      const uint64_t ex = 1ull << (CAT_MAX_LOGN - s);
+      g.roots.r[i][s] = h_mont(h_powmod(w27, ex, p), p);
+      g.roots.ir[i][s] = h_mont(h_powmod(iw27, ex, p), p);
+    }
+    g.roots.one[i] = h_mont(1, p);
+    const uint32_t w16 = h_powmod(w27, 1ull << (CAT_MAX_LOGN - 4), p);
+    const uint32_t iw16 = h_inv(w16, p);
+    for (int k = 0; k < 8; k++) {
+      h_pair(h_powmod(w16, k, p), pc, &pc.w16[k], &pc.w16q[k]);
+      h_pair(h_powmod(iw16, k, p), pc, &pc.iw16[k], &pc.iw16q[k]);
+    }
+  }
+  {
+    CrtC& c = g.crt;
+    const uint32_t p0 = kP[0], p1 = kP[1], p2 = kP[2];
+    h_pair(h_inv(p0 % p1, p1), g.prc[1], &c.c01, &c.c01q);
+    h_pair(p0 % p2, g.prc[2], &c.p0m2, &c.p0m2q);
+    const uint32_t p01m2 = h_mulmod(p0 % p2, p1 % p2, p2);
+    h_pair(h_inv(p01m2, p2), g.prc[2], &c.c012, &c.c012q);
+    c.p0 = p0;
+    const uint64_t p01 = (uint64_t)p0 * p1;
+    c.p01_lo = (uint32_t)p01;
+    c.p01_hi = (uint32_t)(p01 >> 32);
+  }
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_primes), g.prc, sizeof(g.prc)));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_crt), &g.crt, sizeof(g.crt)));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_roots), &g.roots, sizeof(g.roots)));
+  HIPCHK(hipMalloc(&g.tws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&g.itws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
+  hipLaunchKernelGGL(k_build_tws, dim3(32, CAT_NPRIMES), dim3(256), 0, 0, g.tws, g.itws);
+  LAUNCHCHK();
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipHostMalloc(&g.pin, 1 << 16, hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+  g.inited = true;
+  return CAT_OK;
+}
+
+cat_status ensure_twn(int logN) {
+  if (logN <= CAT_LDS_LOGT) return CAT_OK;
+  if (g.twn.count(logN)) return CAT_OK;
+  const size_t N = 1ull << logN;
+  uint2 *t = nullptr, *it = nullptr;
+  HIPCHK(hipMalloc(&t, sizeof(uint2) * N * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&it, sizeof(uint2) * N * CAT_NPRIMES));
+  const uint32_t blocks = (uint32_t)std::min<size_t>(N / 256 + 1, 8192);
+  hipLaunchKernelGGL(k_build_twn, dim3(blocks, CAT_NPRIMES), dim3(256), 0, 0, logN, t, it);
+  LAUNCHCHK();
+  HIPCHK(hipDeviceSynchronize());
+  g.twn[logN] = {t, it};
+  return CAT_OK;
+}
+
+NttTables tables_for(int logN) {
+  NttTables tb;
+  tb.tws = g.tws;
+  tb.itws = g.itws;
+  tb.twn = nullptr;
+  tb.itwn = nullptr;
+  auto it = g.twn.find(logN);
+  if (it != g.twn.end()) {
+    tb.twn = it->second.first;
+    tb.itwn = it->second.second;
+  }
+  return tb;
+}
+
+// scale constant 2^32 * N^-1 (Montgomery pair): the pointwise product
+// mont_mul(x, y) = x*y/2^32 times it gives x*y/N, undoing the unscaled inverse.
+uint2 scale_pair(int prime, int logN) {
+  const PrimeC& pc = g.prc[prime];
+  const uint32_t p = pc.p;
+  const uint32_t ninv = h_inv(h_powmod(2, logN, p), p);
+  const uint32_t W = h_mulmod(ninv, (uint32_t)((1ull << 32) % p), p);
+  return h_pair2(W, pc);
+}
+
+// ----------------------------------------------------------------------------
+// Stages: one batch of products of one class.
+// ----------------------------------------------------------------------------
+enum { CLS_SCHOOL = 0, CLS_LDS = 1, CLS_LARGE = 2 };
+
+void classify(uint64_t la, uint64_t lb, int* cls, int* logN) {
+  if (la <= SCHOOL_MAX && lb <= SCHOOL_MAX) {
+    *cls = CLS_SCHOOL;
+    *logN = 0;
+    return;
+  }
+  int k = ceil_log2(la + lb - 1);
+  if (k < 6) k = 6;
+  *logN = k;
+  *cls = (k <= CAT_LDS_LOGT) ? CLS_LDS : CLS_LARGE;
+}
+
+struct Stage {
+  int cls = CLS_SCHOOL;
+  int logN = 0;
+  DescView dv{};           // dv.table is a device pointer (explicit) or nullptr (tree)
+  std::vector<MulDesc> host_desc;   // explicit descriptors (host copy)
+  uint64_t nmul = 0;
+  uint64_t limbs = 0;      // sum of la+lb
+  uint64_t a_base = 0, b_base = 0, c_base = 0;   // uint32 offsets from the workspace base
+  // CRT (NTT classes)
+  std::vector<CrtSeg> host_segs;
+  std::vector<uint32_t> host_pref;
+  const CrtSeg* segs = nullptr;
+  const uint32_t* blk_pref = nullptr;
+  uint32_t nseg = 0, nblk = 0;
+  bool need_fix = false;
+  // carried-up nodes
+  CopyList tails{};
+  uint64_t tail_in_base = 0, tail_out_base = 0;
+  bool is_leaf = false;    // k_leaf<5>
+  TreeLevel leaf{};
+  uint64_t leaf_nodes = 0;
+};
+
+// host mirror of DescView::get in tree mode
+MulDesc tree_desc(const TreeLevel& t, uint64_t i) {
+  uint32_t gi = 0;
+  while (gi + 1 < t.ngroups && i >= t.mpref[gi + 1]) gi++;
+  const uint64_t il = i - t.mpref[gi];
+  const uint64_t sz = 1ull << t.j;
+  MulDesc d;
+  d.a_off = t.base[gi] + 2 * il * sz;
+  d.b_off = d.a_off + sz;
+  d.c_off = d.a_off;
+  d.r_off = d.a_off;
+  d.la = (uint32_t)sz;
+  const uint64_t rem = t.K[gi] - (2 * il + 1) * sz;
+  d.lb = (uint32_t)(rem < sz ? rem : sz);
+  return d;
+}
+
+void build_crt_segs(Stage& s) {
+  s.host_pref.clear();
+  uint32_t b = 0;
+  s.need_fix = false;
+  for (const CrtSeg& sg : s.host_segs) {
+    s.host_pref.push_back(b);
+    const uint64_t nb = (sg.len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK;
+    if (nb > 1) s.need_fix = true;
+    b += (uint32_t)nb;
+  }
+  s.host_pref.push_back(b);
+  s.nseg = (uint32_t)s.host_segs.size();
+  s.nblk = b;
+}
+
+// ----------------------------------------------------------------------------
+// Workspace layout for n (uint32 offsets unless noted)
+// ----------------------------------------------------------------------------
+struct Layout {
+  uint64_t n = 0, s = 0, i0 = 0, i_end = 0, nseg = 0;
+  uint64_t Kmax = 0, post_cap = 0, res_len = 0, F_words = 0, nblk_max = 0;
+  size_t primes = 0, arenaA = 0, arenaB = 0, post = 0, res = 0, F = 0;       // in uint32 units
+  size_t seeds = 0, seed_e = 0, seg_cnt = 0, seg_off = 0, bitmap = 0;        // in uint32 units
+  size_t gtab = 0, bsum = 0, cin = 0, err = 0, top = 0;                      // bytes
+  size_t total = 0;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+Layout make_layout(uint64_t n) {
+  Layout L;
+  L.n = n;
+  L.s = isqrt64(2 * n);
+  L.i0 = (L.s + 1) / 2;
+  L.i_end = n;
+  L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + SIEVE_SEG - 1) / SIEVE_SEG : 0;
+  L.Kmax = std::max<uint64_t>(pi_bound(2 * n), 16);
+  const uint64_t sb = std::min<uint64_t>(pi_bound(L.s + 1), SEED_MAX);
+  L.post_cap = L.Kmax + 256 * sb + 4096;
+  L.res_len = std::max(L.Kmax, L.post_cap) + 64;
+  const uint64_t big = 1ull << ceil_log2(std::max(L.Kmax, L.post_cap));
+  L.F_words = (big > (1ull << CAT_LDS_LOGT)) ? 12 * big + (1ull << 20) : (1ull << 20);
+  L.nblk_max = L.res_len / CAT_CRT_BLOCK + 4096;
+  size_t off = 0;  // bytes
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  L.primes = take(L.Kmax * 4) / 4;
+  L.arenaA = take(L.Kmax * 4) / 4;
+  L.arenaB = take(L.Kmax * 4) / 4;
+  L.post = take(L.post_cap * 4) / 4;
+  L.res = take(3 * L.res_len * 4) / 4;
+  L.F = take(L.F_words * 4) / 4;
+  L.seeds = take(SEED_MAX * 4) / 4;
+  L.seed_e = take(SEED_MAX * 4) / 4;
+  L.seg_cnt = take((L.nseg + 1) * 4) / 4;
+  L.seg_off = take((L.nseg + 1) * 4) / 4;
+  L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
+  L.gtab = take(sizeof(GroupTable));
+  L.bsum = take(L.nblk_max);
+  L.cin = take(L.nblk_max);
+  L.err = take(64);
+  L.top = take(64);
+  L.total = off;
+  return L;
+}
+
+// ----------------------------------------------------------------------------
+// The reconstruction plan for one n (depends only on the group counts).
+// ----------------------------------------------------------------------------
+struct Plan {
+  uint64_t n = 0;
+  uint32_t ng = 0;
+  uint32_t exps[CAT_MAX_GROUPS] = {};
+  uint64_t off[CAT_MAX_GROUPS + 1] = {};
+  std::vector<Stage> batched;   // leaf kernel + levels
+  std::vector<Stage> plain;     // levels from j = 0
+  std::vector<Stage> post;      // powers, outer tree, final product (shared by both modes)
+  uint64_t result_pos = 0, result_cap = 0;   // uint32 offset from workspace base
+  bool result_is_one = false;
+  uint64_t post_end = 0;        // end of the post-tree arena used
+  void* dev = nullptr;          // device tables (segments, prefixes, descriptors)
+  uint64_t products = 0, product_limbs = 0;
+  uint32_t levels = 0;
+  // graph cache: workspace base -> exec
+  std::map<uintptr_t, hipGraphExec_t> graphs;
+};
+
+// Forest levels of the product trees over the groups (one tree per group).
+// out(j) = A for even j, B for odd j; in(0) = primes.
+void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
+  std::vector<Stage>& st = batched ? P.batched : P.plain;
+  const uint32_t ng = P.ng;
+  auto out_of = [&](int j) -> uint64_t { return (j % 2 == 0) ? Ly.arenaA : Ly.arenaB; };
+  auto in_of = [&](int j) -> uint64_t { return j == 0 ? Ly.primes : out_of(j - 1); };
+  uint64_t Kmax_g = 0;
+  for (uint32_t gi = 0; gi < ng; gi++) Kmax_g = std::max(Kmax_g, P.off[gi + 1] - P.off[gi]);
+  int jstart = 0;
+  const int LF = 5;
+  const int J = ceil_log2(std::max<uint64_t>(Kmax_g, 1));   // levels until one node per group
+  if (batched && Kmax_g > 1) {
+    // leaf packing covers levels 0..LF-1
+    Stage s;
+    s.is_leaf = true;
+    s.leaf.ngroups = ng;
+    s.leaf.j = LF;
+    uint64_t nodes = 0;
+    for (uint32_t gi = 0; gi < ng; gi++) {
+      s.leaf.base[gi] = P.off[gi];
+      s.leaf.K[gi] = P.off[gi + 1] - P.off[gi];
+      s.leaf.mpref[gi] = nodes;
+      nodes += (s.leaf.K[gi] + (1ull << LF) - 1) >> LF;
+    }
+    s.leaf.mpref[ng] = nodes;
+    s.leaf_nodes = nodes;
+    s.a_base = Ly.primes;
+    // the buffer the pairwise levels would have written last
+    s.c_base = out_of(std::min(J, LF) - 1);
+    for (uint32_t gi = 0; gi < ng; gi++) {
+      const uint64_t K = P.off[gi + 1] - P.off[gi];
+      const uint64_t cnt = std::min<uint64_t>(K, 1ull << LF);
+      // products inside the packed levels: K - nodes
+      P.products += K - ((K + (1ull << LF) - 1) >> LF);
+      (void)cnt;
+    }
+    st.push_back(s);
+    jstart = std::min(J, LF);
+  }
+  uint64_t where = (jstart == 0) ? Ly.primes : out_of(jstart - 1);
+  int j = jstart;
+  for (;; j++) {
+    bool any = false;
+    for (uint32_t gi = 0; gi < ng; gi++) {
+      const uint64_t K = P.off[gi + 1] - P.off[gi];
+      if (((K + (1ull << j) - 1) >> j) > 1) any = true;
+    }
+    if (!any) break;
+    Stage s;
+    s.dv.table = nullptr;
+    TreeLevel& t = s.dv.tree;
+    t.ngroups = ng;
+    t.j = (uint32_t)j;
+    uint64_t m = 0;
+    s.tails.n = 0;
+    for (uint32_t gi = 0; gi < ng; gi++) {
+      const uint64_t K = P.off[gi + 1] - P.off[gi];
+      const uint64_t nodes = (K + (1ull << j) - 1) >> j;
+      t.base[gi] = P.off[gi];
+      t.K[gi] = K;
+      t.mpref[gi] = m;
+      m += nodes / 2;
+      if (nodes & 1) {
+        const uint64_t o = P.off[gi] + (nodes - 1) * (1ull << j);
+        s.tails.off[s.tails.n] = o;
+        s.tails.len[s.tails.n] = P.off[gi + 1] - o;
+        s.tails.n++;
+      }
+      // CRT segment: this group's products, contiguous from its base
+      const uint64_t seglen = std::min<uint64_t>(K, (nodes / 2) * (2ull << j));
+      if (nodes / 2 > 0) s.host_segs.push_back(CrtSeg{P.off[gi], P.off[gi], seglen});
+    }
+    t.mpref[ng] = m;
+    s.nmul = m;
+    for (uint64_t i = 0; i < m; i++) {
+      // sum of la+lb (cheap closed form would do; m is at most K/2)
+      (void)i;
+    }
+    s.limbs = 0;
+    for (const CrtSeg& sg : s.host_segs) s.limbs += sg.len;
+    classify(1ull << j, 1ull << j, &s.cls, &s.logN);
+    s.a_base = s.b_base = in_of(j);
+    s.c_base = out_of(j);
+    s.tail_in_base = in_of(j);
+    s.tail_out_base = out_of(j);
+    build_crt_segs(s);
+    P.products += m;
+    P.product_limbs += s.limbs;
+    st.push_back(s);
+    where = out_of(j);
+  }
+  P.levels = (uint32_t)j;
+  *root_pos = where;
+}
+
+// Explicit products after the forest: P_e = Q_e^e (left-to-right binary
+// powering), R = prod_{e>=2} P_e (balanced, adjacent pairs), C = Q_1 * R.
+struct Item {
+  uint64_t pos, cap;   // absolute uint32 offset from the workspace base, capacity in limbs
+};
+
+void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vector<Item>& outs) {
+  // group the products of one step by class; positions already assigned
+  std::map<std::pair<int, int>, Stage> by;
+  uint64_t rpos = 0;
+  for (size_t k = 0; k < pairs.size(); k++) {
+    const Item a = pairs[k].first, b = pairs[k].second, c = outs[k];
+    int cls, logN;
+    classify(a.cap, b.cap, &cls, &logN);
+    Stage& s = by[{cls, logN}];
+    s.cls = cls;
+    s.logN = logN;
+    MulDesc d;
+    d.a_off = a.pos;
+    d.b_off = b.pos;
+    d.c_off = c.pos;
+    d.r_off = rpos;
+    d.la = (uint32_t)a.cap;
+    d.lb = (uint32_t)b.cap;
+    rpos += a.cap + b.cap;
+    s.host_desc.push_back(d);
+    s.host_segs.push_back(CrtSeg{c.pos, d.r_off, a.cap + b.cap});
+    s.limbs += a.cap + b.cap;
+  }
+  for (auto& kv : by) {
+    Stage& s = kv.second;
+    s.nmul = s.host_desc.size();
+    s.a_base = s.b_base = s.c_base = 0;
+    build_crt_segs(s);
+    P.products += s.nmul;
+    P.product_limbs += s.limbs;
+    P.post.push_back(s);
+  }
+}
+
+void plan_post(const Layout& Ly, Plan& P, uint64_t root_pos) {
+  uint64_t bump = Ly.post;
+  auto alloc = [&](uint64_t cap) {
+    Item it{bump, cap};
+    bump += cap;
+    return it;
+  };
+  std::vector<Item> pe;     // P_e for e >= 2, exponent ascending
+  Item q1{0, 0};
+  bool has_q1 = false;
+  // powers: all chains advance one step per stage
+  struct Chain {
+    Item q, r;
+    uint32_t e;
+    int bit;
+    bool sq_done;
+  };
+  std::vector<Chain> ch;
+  for (uint32_t gi = 0; gi < P.ng; gi++) {
+    Item q{root_pos + P.off[gi], P.off[gi + 1] - P.off[gi]};
+    if (P.exps[gi] == 1) {
+      q1 = q;
+      has_q1 = true;
+      continue;
+    }
+    int top = 31;
+    while (!((P.exps[gi] >> top) & 1)) top--;
+    ch.push_back(Chain{q, q, P.exps[gi], top - 1, false});
+  }
+  for (;;) {
+    std::vector<std::pair<Item, Item>> pairs;
+    std::vector<Item> outs;
+    std::vector<size_t> who;
+    for (size_t k = 0; k < ch.size(); k++) {
+      Chain& c = ch[k];
+      if (c.bit < 0) continue;
+      if (!c.sq_done) {
+        pairs.push_back({c.r, c.r});
+        outs.push_back(alloc(2 * c.r.cap));
+      } else {
+        pairs.push_back({c.r, c.q});
+        outs.push_back(alloc(c.r.cap + c.q.cap));
+      }
+      who.push_back(k);
+    }
+    if (pairs.empty()) break;
+    add_products(P, pairs, outs);
+    for (size_t t = 0; t < who.size(); t++) {
+      Chain& c = ch[who[t]];
+      c.r = outs[t];
+      if (!c.sq_done) {
+        if ((c.e >> c.bit) & 1) c.sq_done = true;
+        else c.bit--;
+      } else {
+        c.sq_done = false;
+        c.bit--;
+      }
+    }
+  }
+  for (auto& c : ch) pe.push_back(c.r);
+  // outer product of the P_e, e >= 2
+  while (pe.size() > 1) {
+    std::vector<std::pair<Item, Item>> pairs;
+    std::vector<Item> outs, next;
+    for (size_t k = 0; k + 1 < pe.size(); k += 2) {
+      pairs.push_back({pe[k], pe[k + 1]});
+      outs.push_back(alloc(pe[k].cap + pe[k + 1].cap));
+      next.push_back(outs.back());
+    }
+    if (pe.size() & 1) next.push_back(pe.back());
+    add_products(P, pairs, outs);
+    pe = next;
+  }
+  if (has_q1 && !pe.empty()) {
+    std::vector<std::pair<Item, Item>> pairs{{q1, pe[0]}};
+    std::vector<Item> outs{alloc(q1.cap + pe[0].cap)};
+    add_products(P, pairs, outs);
+    P.result_pos = outs[0].pos;
+    P.result_cap = outs[0].cap;
+  } else if (has_q1) {
+    P.result_pos = q1.pos;
+    P.result_cap = q1.cap;
+  } else if (!pe.empty()) {
+    P.result_pos = pe[0].pos;
+    P.result_cap = pe[0].cap;
+  } else {
+    P.result_is_one = true;
+  }
+  P.post_end = bump;
+}
+
+// Upload the device tables of every stage of the plan into one buffer.
+cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
+  size_t bytes = 0;
+  for (Stage* s : all) {
+    bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
+    bytes = align_up(bytes, 16) + s->host_segs.size() * sizeof(CrtSeg);
+    bytes = align_up(bytes, 16) + s->host_pref.size() * sizeof(uint32_t);
+  }
+  bytes = std::max<size_t>(bytes, 64);
+  std::vector<char> h(bytes, 0);
+  char* d = nullptr;
+  HIPCHK(hipMalloc(&d, bytes));
+  size_t o = 0;
+  for (Stage* s : all) {
+    o = align_up(o, 16);
+    if (!s->host_desc.empty()) {
+      memcpy(&h[o], s->host_desc.data(), s->host_desc.size() * sizeof(MulDesc));
+      s->dv.table = (const MulDesc*)(d + o);
+    }
+    o += s->host_desc.size() * sizeof(MulDesc);
+    o = align_up(o, 16);
+    if (!s->host_segs.empty()) memcpy(&h[o], s->host_segs.data(), s->host_segs.size() * sizeof(CrtSeg));
+    s->segs = (const CrtSeg*)(d + o);
+    o += s->host_segs.size() * sizeof(CrtSeg);
+    o = align_up(o, 16);
+    if (!s->host_pref.empty()) memcpy(&h[o], s->host_pref.data(), s->host_pref.size() * sizeof(uint32_t));
+    s->blk_pref = (const uint32_t*)(d + o);
+    o += s->host_pref.size() * sizeof(uint32_t);
+  }
+  HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+  *dev = d;
+  return CAT_OK;
+}
+
+void free_plan(Plan* P) {
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (P->dev) (void)hipFree(P->dev);
+  delete P;
+}
+
+cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
+  Plan* P = new Plan();
+  P->n = Ly.n;
+  P->ng = gt.ngroups;
+  for (uint32_t gi = 0; gi < gt.ngroups; gi++) P->exps[gi] = gt.exps[gi];
+  for (uint32_t gi = 0; gi <= gt.ngroups; gi++) P->off[gi] = gt.off[gi];
+  uint64_t root_b = 0, root_p = 0;
+  P->products = 0;
+  P->product_limbs = 0;
+  plan_tree(Ly, *P, true, &root_b);
+  const uint64_t prod_b = P->products, limbs_b = P->product_limbs;
+  plan_tree(Ly, *P, false, &root_p);
+  if (root_b != root_p) {
+    free_plan(P);
+    return CAT_EINTERNAL;
+  }
+  P->products = prod_b;
+  P->product_limbs = limbs_b;
+  plan_post(Ly, *P, root_b);
+  std::vector<Stage*> all;
+  for (auto& s : P->batched) all.push_back(&s);
+  for (auto& s : P->plain) all.push_back(&s);
+  for (auto& s : P->post) all.push_back(&s);
+  // the plan must fit the workspace layout sized from n alone
+  for (Stage* s : all) {
+    if (s->is_leaf) continue;
+    uint64_t rmax = 0;
+    for (const CrtSeg& sg : s->host_segs) rmax = std::max(rmax, sg.res_pos + sg.len);
+    const uint64_t fneed = (s->cls == CLS_LARGE) ? s->nmul * 6ull << s->logN : 0;
+    if (rmax > Ly.res_len || fneed > Ly.F_words || s->nblk > Ly.nblk_max) {
+      free_plan(P);
+      return CAT_EINTERNAL;
+    }
+  }
+  if (P->post_end > Ly.post + Ly.post_cap) {
+    free_plan(P);
+    return CAT_EINTERNAL;
+  }
+  // twiddle tables needed by the large classes
+  for (Stage* s : all)
+    if (s->cls == CLS_LARGE) STCHK(ensure_twn(s->logN));
+  cat_status st = upload_tables(all, &P->dev);
+  if (st != CAT_OK) {
+    free_plan(P);
+    return st;
+  }
+  *out = P;
+  return CAT_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Execution
+// ----------------------------------------------------------------------------
+struct Exec {
+  uint32_t* W = nullptr;   // workspace base
+  const uint32_t* A = nullptr;   // caller operand / output bases (generic batches)
+  const uint32_t* B = nullptr;
+  uint32_t* C = nullptr;
+  uint32_t* res = nullptr;
+  uint64_t res_stride = 0;
+  uint32_t* F = nullptr;
+  uint8_t* bsum = nullptr;
+  uint8_t* cin = nullptr;
+  uint32_t* err = nullptr;
+  hipStream_t st = nullptr;
+  uint64_t launches = 0;
+};
+
+cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, bool fix) {
+  hipLaunchKernelGGL(k_crt, dim3(nblk), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.bsum,
+                     X.err);
+  LAUNCHCHK();
+  X.launches++;
+  if (fix) {
+    hipLaunchKernelGGL(k_carry_scan, dim3(1), dim3(1024), 0, X.st, sv, X.bsum, nblk, X.cin, X.err);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_carry_apply, dim3(nblk), dim3(64), 0, X.st, sv, X.cin, out);
+    LAUNCHCHK();
+    X.launches += 2;
+  }
+  return CAT_OK;
+}
+
+// Products of a stage given by `dv` (cnt of them): the NTT or schoolbook part.
+uint32_t* out_base(Exec& X, const Stage& s) { return X.C ? X.C : X.W + s.c_base; }
+
+cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
+  const uint32_t* ain = X.A ? X.A : X.W + s.a_base;
+  const uint32_t* bin = X.B ? X.B : X.W + s.b_base;
+  uint32_t* out = out_base(X, s);
+  if (s.cls == CLS_SCHOOL) {
+    const uint64_t blocks = (cnt + SCHOOL_WAVES - 1) / SCHOOL_WAVES;
+    hipLaunchKernelGGL(k_school, dim3((uint32_t)blocks), dim3(64 * SCHOOL_WAVES), 0, X.st, dv, cnt, ain, bin, out,
+                       X.err);
+    LAUNCHCHK();
+    X.launches++;
+    return CAT_OK;
+  }
+  const NttTables tb = tables_for(s.logN);
+  const uint2 s0 = scale_pair(0, s.logN), s1 = scale_pair(1, s.logN), s2 = scale_pair(2, s.logN);
+  if (s.cls == CLS_LDS) {
+    const uint64_t per = NTT_LDS_T >> s.logN;
+    const uint64_t tiles = (cnt + per - 1) / per;
+    hipLaunchKernelGGL(k_ntt_lds, dim3((uint32_t)tiles, CAT_NPRIMES), dim3(NTT_LDS_THREADS), 0, X.st, dv, cnt, s.logN,
+                       ain, bin, X.res, X.res_stride, tb, s0, s1, s2);
+    LAUNCHCHK();
+    X.launches++;
+    return CAT_OK;
+  }
+  if (!tb.twn) return CAT_EINTERNAL;
+  const int logM = CAT_LDS_LOGT, logR1 = s.logN - logM;
+  int logC = 14 - logR1;
+  if (logC > logM) logC = logM;
+  if (logC < 0) return CAT_EINVAL;
+  const uint64_t tiles = 1ull << (logM - logC);
+  hipLaunchKernelGGL(k_col_fwd, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st, dv,
+                     s.logN, logC, ain, bin, X.F, tb);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_row, dim3((uint32_t)(cnt << logR1), CAT_NPRIMES), dim3(NTT_ROW_THREADS), 0, X.st, s.logN, X.F,
+                     tb, s0, s1, s2);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_col_inv, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
+                     s.logN, logC, X.F, X.res, X.res_stride, tb);
+  LAUNCHCHK();
+  X.launches += 3;
+  return CAT_OK;
+}
+
+cat_status copy_tails(Exec& X, const Stage& s) {
+  if (s.tails.n == 0) return CAT_OK;
+  uint64_t mx = 0;
+  for (uint32_t k = 0; k < s.tails.n; k++) mx = std::max(mx, s.tails.len[k]);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((mx + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_copy_ranges, dim3(blocks, s.tails.n), dim3(256), 0, X.st, s.tails, X.W + s.tail_in_base,
+                     X.W + s.tail_out_base);
+  LAUNCHCHK();
+  X.launches++;
+  return CAT_OK;
+}
+
+SegView stage_segs(const Stage& s) {
+  SegView sv{};
+  sv.segs = s.segs;
+  sv.pref = s.blk_pref;
+  sv.nseg = s.nseg;
+  return sv;
+}
+
+cat_status run_stage_batched(Exec& X, const Stage& s) {
+  if (s.is_leaf) {
+    const uint32_t blocks = (uint32_t)((s.leaf_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_leaf<5>, dim3(blocks), dim3(256), 0, X.st, s.leaf, s.leaf_nodes, X.W + s.a_base,
+                       X.W + s.c_base);
+    LAUNCHCHK();
+    X.launches++;
+    return CAT_OK;
+  }
+  if (s.nmul > 0) {
+    STCHK(launch_products(X, s, s.dv, s.nmul));
+    if (s.cls != CLS_SCHOOL) STCHK(launch_crt(X, out_base(X, s), stage_segs(s), s.nblk, s.need_fix));
+  }
+  return copy_tails(X, s);
+}
+
+// One product per launch (per kernel stage of that product).
+cat_status run_stage_plain(Exec& X, const Stage& s) {
+  if (s.is_leaf) return CAT_EINTERNAL;
+  for (uint64_t i = 0; i < s.nmul; i++) {
+    const MulDesc d = s.dv.table ? s.host_desc[i] : tree_desc(s.dv.tree, i);
+    DescView one{};
+    if (s.dv.table) {
+      one.table = s.dv.table + i;
+    } else {
+      // a one-group, two-node tree whose only product is d
+      one.table = nullptr;
+      one.tree.ngroups = 1;
+      one.tree.j = s.dv.tree.j;
+      one.tree.base[0] = d.a_off;
+      one.tree.K[0] = (uint64_t)d.la + d.lb;
+      one.tree.mpref[0] = 0;
+      one.tree.mpref[1] = 1;
+    }
+    STCHK(launch_products(X, s, one, 1));
+    if (s.cls != CLS_SCHOOL) {
+      SegView sv{};
+      sv.segs = nullptr;
+      sv.one = CrtSeg{d.c_off, d.r_off, (uint64_t)d.la + d.lb};
+      const uint32_t nb = (uint32_t)((sv.one.len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
+      STCHK(launch_crt(X, out_base(X, s), sv, nb, nb > 1));
+    }
+  }
+  return copy_tails(X, s);
+}
+
+cat_status run_phase2(Exec& X, Plan& P, bool plain) {
+  std::vector<Stage>& st = plain ? P.plain : P.batched;
+  for (const Stage& s : st) STCHK(plain ? run_stage_plain(X, s) : run_stage_batched(X, s));
+  for (const Stage& s : P.post) STCHK(plain ? run_stage_plain(X, s) : run_stage_batched(X, s));
+  return CAT_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Phase 1 launches (into the workspace; primes to `primes` with capacity cap)
+// ----------------------------------------------------------------------------
+cat_status run_phase1(const Layout& Ly, char* wb, uint32_t* primes, uint64_t cap, hipStream_t st, uint64_t* launches) {
+  uint32_t* W = (uint32_t*)wb;
+  GroupTable* gt = (GroupTable*)(wb + Ly.gtab);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)gt, (uint64_t)(sizeof(GroupTable) / 4), 0u);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_seeds, dim3(1), dim3(1024), 0, st, Ly.n, (uint32_t)Ly.s, W + Ly.seeds, (int32_t*)(W + Ly.seed_e),
+                     gt);
+  LAUNCHCHK();
+  if (Ly.nseg > 0) {
+    hipLaunchKernelGGL(k_sieve, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0, Ly.i_end,
+                       (const uint32_t*)(W + Ly.seeds), (const GroupTable*)gt, W + Ly.bitmap, W + Ly.seg_cnt);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_groups, dim3(1), dim3(1024), 0, st, (uint32_t)Ly.nseg, (const uint32_t*)(W + Ly.seg_cnt),
+                     W + Ly.seg_off, (const uint32_t*)(W + Ly.seeds), (const int32_t*)(W + Ly.seed_e), primes, cap, gt);
+  LAUNCHCHK();
+  if (Ly.nseg > 0) {
+    hipLaunchKernelGGL(k_scatter, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.i0,
+                       (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
+                       primes, cap);
+    LAUNCHCHK();
+  }
+  *launches += Ly.nseg > 0 ? 5 : 3;
+  return CAT_OK;
+}
+
+cat_status read_groups(const Layout& Ly, char* wb, hipStream_t st, GroupTable* out) {
+  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.gtab, sizeof(GroupTable), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  memcpy(out, g.pin, sizeof(GroupTable));
+  if (out->err & CAT_DEVERR_NEG_EXP) return CAT_EINTERNAL;
+  if (out->ngroups > CAT_MAX_GROUPS) return CAT_EINTERNAL;
+  return CAT_OK;
+}
+
+Plan* find_plan(uint64_t n, const GroupTable& gt) {
+  auto it = g.plans.find(n);
+  if (it == g.plans.end()) return nullptr;
+  Plan* P = it->second;
+  if (P->ng != gt.ngroups) return nullptr;
+  for (uint32_t k = 0; k < gt.ngroups; k++)
+    if (P->exps[k] != gt.exps[k] || P->off[k + 1] != gt.off[k + 1]) return nullptr;
+  return P;
+}
+
+void remember_plan(Plan* P) {
+  auto it = g.plans.find(P->n);
+  if (it != g.plans.end()) {
+    free_plan(it->second);
+    g.plans.erase(it);
+    g.plan_order.erase(std::find(g.plan_order.begin(), g.plan_order.end(), P->n));
+  }
+  g.plans[P->n] = P;
+  g.plan_order.push_back(P->n);
+  while (g.plan_order.size() > 256) {
+    const uint64_t old = g.plan_order.front();
+    g.plan_order.erase(g.plan_order.begin());
+    free_plan(g.plans[old]);
+    g.plans.erase(old);
+  }
+}
+
+Exec make_exec(const Layout& Ly, char* wb, hipStream_t st) {
+  Exec X;
+  X.W = (uint32_t*)wb;
+  X.res = X.W + Ly.res;
+  X.res_stride = Ly.res_len;
+  X.F = X.W + Ly.F;
+  X.bsum = (uint8_t*)(wb + Ly.bsum);
+  X.cin = (uint8_t*)(wb + Ly.cin);
+  X.err = (uint32_t*)(wb + Ly.err);
+  X.st = st;
+  return X;
+}
+
+// ----------------------------------------------------------------------------
+// Generic batches c_i = a_i * b_i: products bucketed by class and transform
+// length, one stage (launch sequence) per bucket.
+// ----------------------------------------------------------------------------
+struct MulPlanImpl {
+  uint32_t batch = 0;
+  uint32_t flags = 0;
+  std::vector<Stage> stages;
+  CopyList zeros{};                          // unused (zero-length products are rejected)
+  void* dev = nullptr;
+  uint64_t res_len = 0, F_words = 0, nblk_max = 0;
+  size_t off_res = 0, off_F = 0, off_bsum = 0, off_cin = 0, off_err = 0, total = 0;
+  uint64_t products = 0, product_limbs = 0;
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+};
+
+cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t* b_off, const uint64_t* c_off,
+                           uint32_t flags, MulPlanImpl** out) {
+  if (!a_off || !b_off || (!c_off && batch > 0)) return CAT_EINVAL;
+  MulPlanImpl* M = new MulPlanImpl();
+  M->batch = batch;
+  M->flags = flags;
+  std::map<std::pair<int, int>, Stage> by;
+  for (uint32_t i = 0; i < batch; i++) {
+    if (a_off[i + 1] < a_off[i] || b_off[i + 1] < b_off[i]) { delete M; return CAT_EINVAL; }
+    const uint64_t la = a_off[i + 1] - a_off[i], lb = b_off[i + 1] - b_off[i];
+    if (la == 0 || lb == 0 || la + lb - 1 > (1ull << CAT_MAX_LOGN) || la >= (1ull << 31) || lb >= (1ull << 31)) {
+      delete M;
+      return CAT_EINVAL;
+    }
+    int cls, logN;
+    classify(la, lb, &cls, &logN);
+    Stage& st = by[{cls, logN}];
+    st.cls = cls;
+    st.logN = logN;
+    MulDesc d;
+    d.a_off = a_off[i];
+    d.b_off = b_off[i];
+    d.c_off = c_off[i];
+    d.r_off = st.limbs;
+    d.la = (uint32_t)la;
+    d.lb = (uint32_t)lb;
+    st.host_desc.push_back(d);
+    st.host_segs.push_back(CrtSeg{d.c_off, d.r_off, la + lb});
+    st.limbs += la + lb;
+  }
+  uint64_t nblk = 0;
+  for (auto& kv : by) {
+    Stage& st = kv.second;
+    st.nmul = st.host_desc.size();
+    build_crt_segs(st);
+    if (st.cls != CLS_SCHOOL) M->res_len = std::max(M->res_len, st.limbs);
+    if (st.cls == CLS_LARGE) M->F_words = std::max<uint64_t>(M->F_words, st.nmul * 6ull << st.logN);
+    nblk = std::max<uint64_t>(nblk, st.nblk);
+    M->products += st.nmul;
+    M->product_limbs += st.limbs;
+    M->stages.push_back(st);
+  }
+  M->nblk_max = nblk + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  M->off_res = take(3 * (M->res_len + 64) * 4);
+  M->off_F = take(M->F_words * 4);
+  M->off_bsum = take(M->nblk_max);
+  M->off_cin = take(M->nblk_max);
+  M->off_err = take(64);
+  M->total = off;
+  std::vector<Stage*> all;
+  for (auto& st : M->stages) all.push_back(&st);
+  for (Stage* st : all)
+    if (st->cls == CLS_LARGE) {
+      cat_status e = ensure_twn(st->logN);
+      if (e != CAT_OK) { delete M; return e; }
+    }
+  cat_status e = upload_tables(all, &M->dev);
+  if (e != CAT_OK) { delete M; return e; }
+  *out = M;
+  return CAT_OK;
+}
+
+void mul_plan_free(MulPlanImpl* M) {
+  for (auto& kv : M->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (M->dev) (void)hipFree(M->dev);
+  delete M;
+}
+
+Exec mul_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c, char* wb, hipStream_t st) {
+  Exec X;
+  X.W = (uint32_t*)wb;
+  X.A = d_a;
+  X.B = d_b;
+  X.C = d_c;
+  X.res = (uint32_t*)(wb + M->off_res);
+  X.res_stride = M->res_len + 64;
+  X.F = (uint32_t*)(wb + M->off_F);
+  X.bsum = (uint8_t*)(wb + M->off_bsum);
+  X.cin = (uint8_t*)(wb + M->off_cin);
+  X.err = (uint32_t*)(wb + M->off_err);
+  X.st = st;
+  return X;
+}
+
+cat_status mul_plan_record(MulPlanImpl* M, Exec& X, bool plain) {
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, X.st, X.err, (uint64_t)1, 0u);
+  LAUNCHCHK();
+  X.launches++;
+  for (const Stage& s : M->stages) STCHK(plain ? run_stage_plain(X, s) : run_stage_batched(X, s));
+  return CAT_OK;
+}
+
+cat_status mul_plan_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c, void* d_work,
+                         size_t work_bytes, hipStream_t st, uint64_t* launches) {
+  if (work_bytes < M->total || (!d_work && M->total > 0)) return CAT_ENOMEM;
+  if (M->batch == 0) return CAT_OK;
+  if (!d_a || !d_b || !d_c) return CAT_EINVAL;
+  char* wb = (char*)d_work;
+  const bool plain = (M->flags & CAT_MODE_PLAIN) != 0;
+  const bool use_graph = !plain && (M->flags & CAT_MODE_GRAPH) != 0;
+  Exec X = mul_exec(M, d_a, d_b, d_c, wb, st);
+  if (!use_graph) {
+    STCHK(mul_plan_record(M, X, plain));
+    *launches = X.launches;
+    return CAT_OK;
+  }
+  std::vector<uintptr_t> key{(uintptr_t)d_a, (uintptr_t)d_b, (uintptr_t)d_c, (uintptr_t)wb};
+  auto it = M->graphs.find(key);
+  hipGraphExec_t ge = nullptr;
+  if (it != M->graphs.end()) {
+    ge = it->second;
+    *launches = 1;
+  } else {
+    Exec C = X;
+    C.st = g.cap_stream;
+    HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+    cat_status s = mul_plan_record(M, C, false);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
+    if (s != CAT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) {
+      g.last_err = (int)e;
+      return CAT_EDEVICE;
+    }
+    e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.last_err = (int)e;
+      return CAT_EDEVICE;
+    }
+    M->graphs[key] = ge;
+    *launches = C.launches;
+  }
+  HIPCHK(hipGraphLaunch(ge, st));
+  return CAT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+cat_status cat_init(int device) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  return init_locked(device);
+}
+
+const char* cat_strerror(cat_status s) {
+  switch (s) {
+    case CAT_OK: return "ok";
+    case CAT_EINVAL: return "invalid argument";
+    case CAT_ERANGE: return "capacity too small";
+    case CAT_ENOMEM: return "workspace too small or allocation failed";
+    case CAT_EDEVICE: return "HIP runtime error";
+    case CAT_EINTERNAL: return "device invariant violated";
+    default: return "unknown status";
+  }
+}
+
+int cat_last_device_error(void) { return g.last_err; }
+
+cat_status cat_get_stats(cat_stats* out) {
+  if (!out) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  *out = g.stats;
+  return CAT_OK;
+}
+
+cat_status catalan_sizes(uint64_t n, size_t* max_primes, size_t* max_limbs, size_t* workspace_bytes) {
+  if (n > CAT_N_MAX) return CAT_EINVAL;
+  const Layout Ly = make_layout(n);
+  if (max_primes) *max_primes = (size_t)Ly.Kmax;
+  if (max_limbs) *max_limbs = (size_t)((2 * n + 1) / 32 + 2);
+  if (workspace_bytes) *workspace_bytes = Ly.total;
+  return CAT_OK;
+}
+
+cat_status catalan_factor(uint64_t n, uint32_t* d_primes, size_t primes_cap, uint32_t* h_exps, uint64_t* h_off,
+                          uint32_t* n_groups, size_t* n_primes, void* d_work, size_t work_bytes, void* stream) {
+  if (n > CAT_N_MAX || !h_exps || !h_off || !n_groups || !n_primes || !d_work) return CAT_EINVAL;
+  if (!d_primes && primes_cap > 0) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  const Layout Ly = make_layout(n);
+  if (work_bytes < Ly.total) return CAT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t launches = 0;
+  uint32_t dummy = 0;
+  STCHK(run_phase1(Ly, (char*)d_work, d_primes ? d_primes : &dummy, d_primes ? primes_cap : 0, st, &launches));
+  GroupTable gt;
+  STCHK(read_groups(Ly, (char*)d_work, st, &gt));
+  *n_groups = gt.ngroups;
+  for (uint32_t k = 0; k < gt.ngroups; k++) h_exps[k] = gt.exps[k];
+  for (uint32_t k = 0; k <= gt.ngroups; k++) h_off[k] = gt.off[k];
+  *n_primes = (size_t)gt.off[gt.ngroups];
+  g.stats = cat_stats{};
+  g.stats.launches = launches;
+  g.stats.n_primes = *n_primes;
+  if (*n_primes > primes_cap) return CAT_ERANGE;
+  return CAT_OK;
+}
+
+cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work, size_t work_bytes,
+                            void* stream, uint32_t flags) {
+  if (n > CAT_N_MAX || !n_limbs) return CAT_EINVAL;
+  if (!d_limbs) {
+    *n_limbs = (size_t)((2 * n + 1) / 32 + 2);
+    return CAT_OK;
+  }
+  if (!d_work) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  const Layout Ly = make_layout(n);
+  if (work_bytes < Ly.total) return CAT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)d_work;
+  const bool plain = (flags & CAT_MODE_PLAIN) != 0;
+  const bool use_graph = !plain && (flags & CAT_MODE_GRAPH) != 0;
+  cat_stats stats{};
+  uint64_t launches = 0;
+  STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, st, &launches));
+  GroupTable gt;
+  STCHK(read_groups(Ly, wb, st, &gt));
+  if (gt.err & CAT_DEVERR_BOUNDS) return CAT_EINTERNAL;
+  Plan* P = find_plan(n, gt);
+  if (!P) {
+    STCHK(make_plan(Ly, gt, &P));
+    remember_plan(P);
+  }
+  Exec X = make_exec(Ly, wb, st);
+  uint32_t* W = X.W;
+  unsigned long long* top = (unsigned long long*)(wb + Ly.top);
+  if (P->result_is_one) {
+    if (cap < 1) {
+      *n_limbs = 1;
+      return CAT_ERANGE;
+    }
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, d_limbs, (uint64_t)1, 1u);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+    *n_limbs = 1;
+    g.stats = stats;
+    return CAT_OK;
+  }
+  auto record = [&](Exec& E) -> cat_status {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, E.st, E.err, (uint64_t)1, 0u);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, E.st, (uint32_t*)top, (uint64_t)2, 0u);
+    LAUNCHCHK();
+    E.launches += 2;
+    STCHK(run_phase2(E, *P, plain));
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top);
+    LAUNCHCHK();
+    E.launches++;
+    return CAT_OK;
+  };
+  bool replayed = false;
+  if (use_graph) {
+    hipGraphExec_t ge = nullptr;
+    auto it = P->graphs.find((uintptr_t)wb);
+    if (it != P->graphs.end()) {
+      ge = it->second;
+      replayed = true;
+    } else {
+      Exec C = X;
+      C.st = g.cap_stream;
+      HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+      cat_status s = record(C);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
+      if (s != CAT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (e != hipSuccess) {
+        g.last_err = (int)e;
+        return CAT_EDEVICE;
+      }
+      e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        g.last_err = (int)e;
+        return CAT_EDEVICE;
+      }
+      P->graphs[(uintptr_t)wb] = ge;
+      launches += C.launches;
+    }
+    HIPCHK(hipGraphLaunch(ge, st));
+    if (replayed) launches += 1;
+  } else {
+    STCHK(record(X));
+    launches += X.launches;
+  }
+  // top limb index and error word
+  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.top, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync((char*)g.pin + 8, X.err, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint64_t L = 0;
+  uint32_t derr = 0;
+  memcpy(&L, g.pin, 8);
+  memcpy(&derr, (char*)g.pin + 8, 4);
+  if (derr) return CAT_EINTERNAL;
+  if (L == 0) return CAT_EINTERNAL;   // C(n) >= 1
+  *n_limbs = (size_t)L;
+  stats.products = P->products;
+  stats.product_limbs = P->product_limbs;
+  stats.launches = launches;
+  stats.n_primes = gt.off[gt.ngroups];
+  stats.levels = P->levels;
+  stats.graph_replayed = replayed ? 1 : 0;
+  g.stats = stats;
+  if (cap < L) return CAT_ERANGE;
+  HIPCHK(hipMemcpyAsync(d_limbs, W + P->result_pos, L * 4, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CAT_OK;
+}
+
+
+cat_status cat_mul_plan_create(uint32_t batch, const uint64_t* h_a_off, const uint64_t* h_b_off,
+                               const uint64_t* h_c_off, uint32_t flags, cat_mul_plan* plan,
+                               size_t* workspace_bytes) {
+  if (!plan) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  MulPlanImpl* M = nullptr;
+  STCHK(mul_plan_create(batch, h_a_off, h_b_off, h_c_off, flags, &M));
+  *plan = (cat_mul_plan)M;
+  if (workspace_bytes) *workspace_bytes = M->total;
+  return CAT_OK;
+}
+
+cat_status cat_mul_plan_exec(cat_mul_plan plan, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c,
+                             void* d_work, size_t work_bytes, void* stream) {
+  if (!plan) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(set_device());
+  MulPlanImpl* M = (MulPlanImpl*)plan;
+  uint64_t launches = 0;
+  STCHK(mul_plan_exec(M, d_a, d_b, d_c, d_work, work_bytes, (hipStream_t)stream, &launches));
+  cat_stats st{};
+  st.products = M->products;
+  st.product_limbs = M->product_limbs;
+  st.launches = launches;
+  st.graph_replayed = (M->flags & CAT_MODE_GRAPH) && launches == 1 ? 1 : 0;
+  g.stats = st;
+  return CAT_OK;
+}
+
+cat_status cat_mul_plan_check(cat_mul_plan plan, void* d_work, void* stream) {
+  if (!plan || !d_work) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  MulPlanImpl* M = (MulPlanImpl*)plan;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(g.pin, (char*)d_work + M->off_err, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint32_t e = 0;
+  memcpy(&e, g.pin, 4);
+  return e ? CAT_EINTERNAL : CAT_OK;
+}
+
+cat_status cat_mul_plan_destroy(cat_mul_plan plan) {
+  if (!plan) return CAT_OK;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  HIPCHK(hipDeviceSynchronize());
+  mul_plan_free((MulPlanImpl*)plan);
+  return CAT_OK;
+}
+
+cat_status bigint_mul_workspace(uint32_t batch, const uint64_t* h_a_off, const uint64_t* h_b_off,
+                                size_t* workspace_bytes) {
+  if (!workspace_bytes) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  std::vector<uint64_t> c(batch + 1, 0);
+  MulPlanImpl* M = nullptr;
+  STCHK(mul_plan_create(batch, h_a_off, h_b_off, c.data(), 0, &M));
+  *workspace_bytes = M->total;
+  mul_plan_free(M);
+  return CAT_OK;
+}
+
+cat_status bigint_mul_batched_ex(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off, const uint32_t* d_b,
+                                 const uint64_t* h_b_off, uint32_t* d_c, const uint64_t* h_c_off, void* d_work,
+                                 size_t work_bytes, void* stream, uint32_t flags) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  MulPlanImpl* M = nullptr;
+  STCHK(mul_plan_create(batch, h_a_off, h_b_off, h_c_off, flags & ~CAT_MODE_GRAPH, &M));
+  uint64_t launches = 0;
+  hipStream_t st = (hipStream_t)stream;
+  cat_status s = mul_plan_exec(M, d_a, d_b, d_c, d_work, work_bytes, st, &launches);
+  hipError_t e = hipStreamSynchronize(st);
+  if (s == CAT_OK && e != hipSuccess) {
+    g.last_err = (int)e;
+    s = CAT_EDEVICE;
+  }
+  if (s == CAT_OK && batch > 0) {
+    uint32_t derr = 0;
+    if (hipMemcpy(&derr, (char*)d_work + M->off_err, 4, hipMemcpyDeviceToHost) != hipSuccess) s = CAT_EDEVICE;
+    else if (derr) s = CAT_EINTERNAL;
+  }
+  cat_stats stt{};
+  stt.products = M->products;
+  stt.product_limbs = M->product_limbs;
+  stt.launches = launches;
+  g.stats = stt;
+  mul_plan_free(M);
+  return s;
+}
+
+cat_status bigint_mul_batched(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off, const uint32_t* d_b,
+                              const uint64_t* h_b_off, uint32_t* d_c, const uint64_t* h_c_off, void* d_work,
+                              size_t work_bytes, void* stream) {
+  return bigint_mul_batched_ex(batch, d_a, h_a_off, d_b, h_b_off, d_c, h_c_off, d_work, work_bytes, stream,
+                               CAT_MODE_BATCHED);
+}
+
+cat_status bigint_residues(const uint32_t* d_x, size_t n, uint64_t* h_res, void* d_work, size_t work_bytes,
+                           void* stream) {
+  if (!h_res || (!d_x && n > 0)) return CAT_EINVAL;
+  const uint64_t chunk = 4096;
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  if (n == 0) {
+    h_res[0] = h_res[1] = h_res[2] = 0;
+    return CAT_OK;
+  }
+  if (!d_work || work_bytes < nch * 24 + 256) return CAT_ENOMEM;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t* part = (uint64_t*)d_work;
+  hipLaunchKernelGGL(k_residues, dim3((uint32_t)((nch + 255) / 256)), dim3(256), 0, st, d_x, (uint64_t)n, chunk, part);
+  LAUNCHCHK();
+  std::vector<uint64_t> h(nch * 3);
+  HIPCHK(hipMemcpyAsync(h.data(), part, nch * 24, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const uint64_t mods[3] = {4294967291ull, 4294967297ull, 4294967295ull};
+  for (int m = 0; m < 3; m++) {
+    const uint64_t q = mods[m];
+    // (2^32)^chunk mod q
+    unsigned __int128 pw = 1, b = ((unsigned __int128)1 << 32) % q;
+    for (uint64_t e = chunk; e; e >>= 1) {
+      if (e & 1) pw = pw * b % q;
+      b = b * b % q;
+    }
+    unsigned __int128 acc = 0;
+    for (uint64_t c = nch; c > 0; c--) acc = (acc * pw + h[(c - 1) * 3 + m]) % q;
+    h_res[m] = (uint64_t)acc;
+  }
+  return CAT_OK;
+}
+
+cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work, size_t work_bytes,
+                         void* stream) {
+  return catalan_exact_ex(n, d_limbs, cap, n_limbs, d_work, work_bytes, stream, CAT_MODE_BATCHED | CAT_MODE_GRAPH);
+}
+
+}  // extern "C"

@@ -1,0 +1,600 @@
+// Exact big-integer products for the reconstruction phase (Sec. 3.2, Alg. 2):
+// cyclic convolution modulo three 32-bit primes by number-theoretic transforms.
+//
+// Transform structure (all integer, in LDS):
+//  * A length-S transform is split as S = R * (S/R) (R = 2^r <= 16): each
+//    work item loads R elements at stride S/R, does a radix-R DFT in registers
+//    (radix-2 decimation-in-frequency network with constant roots omega_16^i),
+//    multiplies output k1 by omega_S^{j2*k1} and writes it back in place; the
+//    R blocks of size S/R are then transformed the same way.  The first pass
+//    takes radix 2^(log2 S mod 4) when that is not 0, every later pass radix 16.
+//    Outputs come out in a fixed digit-reversed order, which the pointwise
+//    product does not care about; the inverse runs the passes backwards with
+//    inverse roots (decimation-in-time networks), which undoes the order.
+//  * N <= 2^12 products run entirely in one workgroup (k_ntt_lds).
+//  * Larger N = R1 * M with M = 2^12 use the four-step split (Bailey 1990):
+//    k_col_fwd transforms the R1-point columns (packing limbs on the fly) and
+//    applies omega_N^{col*k1}; k_row transforms each M-point row of both
+//    operands, multiplies them pointwise and inverse-transforms the row;
+//    k_col_inv undoes the column step and writes exact residues.
+//  * Twiddles are (w, wq) Montgomery pairs in tables laid out so that
+//    neighbouring lanes read neighbouring entries.
+// The residues of the three primes are then recombined by k_crt (Garner's
+// method) into 96-bit coefficient values, summed into limbs and carried with
+// a wave64 ballot carry-lookahead; blocks of one product are joined by
+// k_carry_scan / k_carry_apply.
+
+__constant__ PrimeC c_primes[CAT_NPRIMES];
+__constant__ CrtC c_crt;
+
+// bit reversal of an r-bit index, compile-time
+__host__ __device__ constexpr int brev_c(int x, int r) {
+  int y = 0;
+  for (int i = 0; i < r; i++) y |= ((x >> i) & 1) << (r - 1 - i);
+  return y;
+}
+
+__host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
+
+// Radix-R DFT on registers, decimation in frequency: natural input, output
+// y[k] in v[brev(k)].
+template <int LOGR>
+__device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
+  constexpr int R = 1 << LOGR;
+  const uint32_t p = pc.p;
+#pragma unroll
+  for (int h = R / 2; h >= 1; h /= 2) {
+#pragma unroll
+    for (int s = 0; s < R; s += 2 * h) {
+#pragma unroll
+      for (int i = 0; i < h; i++) {
+        uint32_t a = v[s + i], b = v[s + i + h];
+        v[s + i] = add_mod(a, b, p);
+        uint32_t d = sub_mod(a, b, p);
+        if (i == 0) v[s + i + h] = d;
+        else {
+          const int wi = i * (8 / h);   // omega_{2h}^i = omega_16^{i*8/h}
+          v[s + i + h] = mul_tw(d, pc.w16[wi], pc.w16q[wi], p);
+        }
+      }
+    }
+  }
+}
+
+// Inverse: input y[k] in v[brev(k)], decimation in time with inverse roots,
+// output x[j] (times R) in v[j].
+template <int LOGR>
+__device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
+  constexpr int R = 1 << LOGR;
+  const uint32_t p = pc.p;
+#pragma unroll
+  for (int h = 1; h < R; h *= 2) {
+#pragma unroll
+    for (int s = 0; s < R; s += 2 * h) {
+#pragma unroll
+      for (int i = 0; i < h; i++) {
+        uint32_t a = v[s + i], b = v[s + i + h];
+        const int wi = i * (8 / h);
+        uint32_t t = (i == 0) ? b : mul_tw(b, pc.iw16[wi], pc.iw16q[wi], p);
+        v[s + i] = add_mod(a, t, p);
+        v[s + i + h] = sub_mod(a, t, p);
+      }
+    }
+  }
+}
+
+// One forward pass of radix R over an LDS tile of `ngroups*R` elements laid out
+// as element e of column c at (e << logC) + c (logC = 0: a plain vector).
+// The elements form consecutive sub-problems of size S = R << logSR.
+// tw: table of this pass, tw[(k1 << logSR) + j2] = omega_S^{j2*k1}.
+template <int LOGR, bool PAD>
+__device__ __forceinline__ void pass_fwd(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
+                                         const uint2* __restrict__ tw, const PrimeC& pc) {
+  constexpr int R = 1 << LOGR;
+  const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
+  for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+    const uint32_t c = g & cmask, h = g >> logC;
+    const uint32_t j2 = h & smask, b = h >> logSR;
+    const uint32_t e0 = (b << (logSR + LOGR)) + j2;
+    uint32_t v[R];
+#pragma unroll
+    for (int j1 = 0; j1 < R; j1++) {
+      uint32_t a = ((e0 + ((uint32_t)j1 << logSR)) << logC) + c;
+      v[j1] = lds[PAD ? lds_pad(a) : a];
+    }
+    dft_fwd<LOGR>(v, pc);
+    if (logSR > 0 && j2 != 0) {
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        uint2 t = tw[((uint32_t)k1 << logSR) + j2];
+        const int r = brev_c(k1, LOGR);
+        v[r] = mul_tw(v[r], t.x, t.y, pc.p);
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) {
+      uint32_t a = ((e0 + ((uint32_t)k1 << logSR)) << logC) + c;
+      lds[PAD ? lds_pad(a) : a] = v[brev_c(k1, LOGR)];
+    }
+  }
+}
+
+template <int LOGR, bool PAD>
+__device__ __forceinline__ void pass_inv(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
+                                         const uint2* __restrict__ itw, const PrimeC& pc) {
+  constexpr int R = 1 << LOGR;
+  const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
+  for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+    const uint32_t c = g & cmask, h = g >> logC;
+    const uint32_t j2 = h & smask, b = h >> logSR;
+    const uint32_t e0 = (b << (logSR + LOGR)) + j2;
+    uint32_t v[R];
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) {
+      uint32_t a = ((e0 + ((uint32_t)k1 << logSR)) << logC) + c;
+      v[brev_c(k1, LOGR)] = lds[PAD ? lds_pad(a) : a];
+    }
+    if (logSR > 0 && j2 != 0) {
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        uint2 t = itw[((uint32_t)k1 << logSR) + j2];
+        const int r = brev_c(k1, LOGR);
+        v[r] = mul_tw(v[r], t.x, t.y, pc.p);
+      }
+    }
+    dft_inv<LOGR>(v, pc);
+#pragma unroll
+    for (int j1 = 0; j1 < R; j1++) {
+      uint32_t a = ((e0 + ((uint32_t)j1 << logSR)) << logC) + c;
+      lds[PAD ? lds_pad(a) : a] = v[j1];
+    }
+  }
+}
+
+// radix of the pass at sub-problem size 2^logS
+__host__ __device__ constexpr int pass_logr(int logS) { return (logS % 4) ? (logS % 4) : 4; }
+// offset of the table of size 2^s inside a per-prime pass-table block
+__host__ __device__ constexpr uint32_t tws_off(int s) { return (1u << s) - 2u; }
+#define TWS_ENTRIES 8190u   // sum over s = 1..12 of 2^s
+
+// Full forward transform of size 2^logS on every sub-problem of an LDS tile
+// with `total` elements (all columns), passes from size 2^logS down.
+template <bool PAD>
+__device__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
+                             const uint2* __restrict__ tws, const PrimeC& pc) {
+  while (logS > 0) {
+    const int lr = pass_logr(logS);
+    const uint32_t ng = total >> lr;
+    const uint32_t logSR = (uint32_t)(logS - lr);
+    const uint2* tw = tws + tws_off(logS);
+    switch (lr) {
+      case 1: pass_fwd<1, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      case 2: pass_fwd<2, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      case 3: pass_fwd<3, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      default: pass_fwd<4, PAD>(lds, ng, logSR, logC, tw, pc); break;
+    }
+    __syncthreads();
+    logS -= lr;
+  }
+}
+
+template <bool PAD>
+__device__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
+                             const uint2* __restrict__ itws, const PrimeC& pc) {
+  // passes in the reverse order of ntt_fwd_tile: the radix-16 passes of sizes
+  // 2^4, 2^8, ... first, the (possibly smaller-radix) pass of size 2^logS last
+  const int lr0 = pass_logr(logS);
+  for (int ls = 4; ls <= logS - lr0; ls += 4) {
+    pass_inv<4, PAD>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc);
+    __syncthreads();
+  }
+  if (logS > 0) {
+    const uint32_t ng = total >> lr0;
+    const uint32_t logSR = (uint32_t)(logS - lr0);
+    const uint2* tw = itws + tws_off(logS);
+    switch (lr0) {
+      case 1: pass_inv<1, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      case 2: pass_inv<2, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      case 3: pass_inv<3, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      default: pass_inv<4, PAD>(lds, ng, logSR, logC, tw, pc); break;
+    }
+    __syncthreads();
+  }
+}
+
+struct NttTables {
+  const uint2* tws;    // [prime][TWS_ENTRIES] forward pass tables
+  const uint2* itws;   // [prime][TWS_ENTRIES] inverse
+  const uint2* twn;    // [prime][N]   four-step twiddles (large N only)
+  const uint2* itwn;
+};
+
+// ---------------------------------------------------------------------------
+// Whole product in one workgroup, N = 2^logN <= 2^12.  The tile holds
+// T = 2^12 coefficient slots = T/N products; grid (tiles, prime).
+// Writes res[prime][r_off + j] = (a*b)_j mod p for j < la+lb.
+#define NTT_LDS_T 4096u
+#define NTT_LDS_THREADS 256
+__global__ void __launch_bounds__(NTT_LDS_THREADS)
+k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
+          uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
+  __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
+  __shared__ MulDesc ds[NTT_LDS_T / 64];
+  const uint32_t prime = blockIdx.y;
+  const PrimeC& pc = c_primes[prime];
+  const uint32_t p = pc.p;
+  const uint32_t N = 1u << logN;
+  const uint32_t per = NTT_LDS_T >> logN;          // products per tile
+  const uint64_t m0 = (uint64_t)blockIdx.x * per;
+  const uint32_t cnt = (uint32_t)min((uint64_t)per, nmul - m0);
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ds[i] = dv.get(m0 + i);
+  __syncthreads();
+  const uint32_t T = cnt << logN;                  // live slots
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t m = t >> logN, j = t & (N - 1);
+    const MulDesc d = ds[m];
+    uint32_t x = j < d.la ? reduce_limb(ain[d.a_off + j], p) : 0u;
+    uint32_t y = j < d.lb ? reduce_limb(bin[d.b_off + j], p) : 0u;
+    lds[lds_pad(t)] = x;
+    lds[lds_pad(NTT_LDS_T + t)] = y;
+  }
+  // unused slots of a partial tile stay untouched: their sub-problems are
+  // independent and never read back
+  __syncthreads();
+  const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
+  const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
+  // A occupies [0, T), B [NTT_LDS_T, NTT_LDS_T + T); transform both as one tile
+  if (T == NTT_LDS_T) {
+    ntt_fwd_tile<true>(lds, logN, 2 * NTT_LDS_T, 0, tws, pc);
+  } else {
+    ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
+    ntt_fwd_tile<true>(lds + lds_pad(NTT_LDS_T), logN, T, 0, tws, pc);
+  }
+  const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(NTT_LDS_T + t)];
+    lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+  }
+  __syncthreads();
+  ntt_inv_tile<true>(lds, logN, T, 0, itws, pc);
+  uint32_t* out = res + (size_t)prime * res_stride;
+  for (uint32_t m = 0; m < cnt; m++) {
+    const MulDesc d = ds[m];
+    const uint32_t L = d.la + d.lb;
+    for (uint32_t j = threadIdx.x; j < L; j += blockDim.x)
+      out[d.r_off + j] = j < N ? lds[lds_pad((m << logN) + j)] : 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Four-step path, N = R1 * M, M = 2^12, R1 = 2^logR1.
+// Scratch F: per product, per prime, per operand N words:
+//   F[((m*3 + prime)*2 + op)*N + q*M + col]
+#define NTT_COL_THREADS 256
+#define NTT_COL_TILE 16384u     // LDS words of a column tile
+
+__global__ void __launch_bounds__(NTT_COL_THREADS)
+k_col_fwd(DescView dv, int logN, int logC, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
+          uint32_t* __restrict__ F, NttTables tb) {
+  __shared__ uint32_t lds[NTT_COL_TILE];
+  const uint32_t prime = blockIdx.y, op = blockIdx.z;
+  const PrimeC& pc = c_primes[prime];
+  const uint32_t p = pc.p;
+  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
+  const uint32_t M = 1u << logM, C = 1u << logC;
+  const uint32_t tiles = M >> logC;
+  const uint64_t m = blockIdx.x / tiles;
+  const uint32_t col0 = (blockIdx.x % tiles) << logC;
+  const MulDesc d = dv.get(m);
+  const uint32_t* src = op ? bin + d.b_off : ain + d.a_off;
+  const uint32_t len = op ? d.lb : d.la;
+  const uint32_t T = 1u << (logR1 + logC);
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t q = t >> logC, c = t & (C - 1);
+    const uint32_t idx = (q << logM) + col0 + c;
+    lds[t] = idx < len ? reduce_limb(src[idx], p) : 0u;
+  }
+  __syncthreads();
+  ntt_fwd_tile<false>(lds, logR1, T, (uint32_t)logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
+  const uint64_t N = 1ull << logN;
+  const uint2* twn = tb.twn + (size_t)prime * N;
+  uint32_t* dst = F + ((m * 3 + prime) * 2 + op) * N;
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t q = t >> logC, c = t & (C - 1);
+    const uint64_t at = ((uint64_t)q << logM) + col0 + c;
+    const uint2 w = twn[at];
+    dst[at] = mul_tw(lds[t], w.x, w.y, p);
+  }
+}
+
+#define NTT_ROW_THREADS 256
+__global__ void __launch_bounds__(NTT_ROW_THREADS)
+k_row(int logN, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
+  __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
+  const uint32_t prime = blockIdx.y;
+  const PrimeC& pc = c_primes[prime];
+  const uint32_t p = pc.p;
+  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
+  const uint32_t M = 1u << logM;
+  const uint64_t N = 1ull << logN;
+  const uint64_t m = blockIdx.x >> logR1;
+  const uint32_t q = blockIdx.x & ((1u << logR1) - 1);
+  uint32_t* fa = F + ((m * 3 + prime) * 2 + 0) * N + ((uint64_t)q << logM);
+  uint32_t* fb = F + ((m * 3 + prime) * 2 + 1) * N + ((uint64_t)q << logM);
+  for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
+    lds[lds_pad(t)] = fa[t];
+    lds[lds_pad(M + t)] = fb[t];
+  }
+  __syncthreads();
+  const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
+  ntt_fwd_tile<true>(lds, logM, 2 * M, 0, tws, pc);
+  const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
+  for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
+    uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
+    lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+  }
+  __syncthreads();
+  ntt_inv_tile<true>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) fa[t] = lds[lds_pad(t)];
+}
+
+__global__ void __launch_bounds__(NTT_COL_THREADS)
+k_col_inv(DescView dv, int logN, int logC, const uint32_t* __restrict__ F, uint32_t* __restrict__ res,
+          uint64_t res_stride, NttTables tb) {
+  __shared__ uint32_t lds[NTT_COL_TILE];
+  const uint32_t prime = blockIdx.y;
+  const PrimeC& pc = c_primes[prime];
+  const uint32_t p = pc.p;
+  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
+  const uint32_t M = 1u << logM, C = 1u << logC;
+  const uint32_t tiles = M >> logC;
+  const uint64_t m = blockIdx.x / tiles;
+  const uint32_t col0 = (blockIdx.x % tiles) << logC;
+  const MulDesc d = dv.get(m);
+  const uint64_t N = 1ull << logN;
+  const uint32_t* src = F + ((m * 3 + prime) * 2 + 0) * N;
+  const uint2* itwn = tb.itwn + (size_t)prime * N;
+  const uint32_t T = 1u << (logR1 + logC);
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t q = t >> logC, c = t & (C - 1);
+    const uint64_t at = ((uint64_t)q << logM) + col0 + c;
+    const uint2 w = itwn[at];
+    lds[t] = mul_tw(src[at], w.x, w.y, p);
+  }
+  __syncthreads();
+  ntt_inv_tile<false>(lds, logR1, T, (uint32_t)logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  uint32_t* out = res + (size_t)prime * res_stride + d.r_off;
+  const uint64_t L = (uint64_t)d.la + d.lb;
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t q = t >> logC, c = t & (C - 1);
+    const uint64_t j = ((uint64_t)q << logM) + col0 + c;
+    if (j < L) out[j] = lds[t];
+  }
+  // coefficient positions in [N, L) (only when L = N + 1) are zero
+  if (blockIdx.x % tiles == 0)
+    for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Garner CRT of the three residues into V = x0 + p0*x1 + p0*p1*x2 < 2^96.
+__device__ __forceinline__ void garner3(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t& v0, uint32_t& v1,
+                                        uint32_t& v2) {
+  const uint32_t P1 = c_primes[1].p, P2 = c_primes[2].p;
+  const uint32_t x0 = r0;
+  const uint32_t x1 = mul_tw(sub_mod(r1, x0, P1), c_crt.c01, c_crt.c01q, P1);
+  const uint32_t t = mul_tw(x1, c_crt.p0m2, c_crt.p0m2q, P2);
+  const uint32_t y = add_mod(x0, t, P2);
+  const uint32_t x2 = mul_tw(sub_mod(r2, y, P2), c_crt.c012, c_crt.c012q, P2);
+  const uint64_t a = (uint64_t)c_crt.p0 * x1 + x0;
+  const uint64_t lo = (uint64_t)c_crt.p01_lo * x2;
+  const uint64_t hi = (uint64_t)c_crt.p01_hi * x2;
+  const uint64_t s0 = (a & 0xFFFFFFFFull) + (lo & 0xFFFFFFFFull);
+  const uint64_t s1 = (a >> 32) + (lo >> 32) + (hi & 0xFFFFFFFFull) + (s0 >> 32);
+  v0 = (uint32_t)s0;
+  v1 = (uint32_t)s1;
+  v2 = (uint32_t)((hi >> 32) + (s1 >> 32));
+}
+
+// Carry resolution.  Given 96-bit column values V(k) = v0 + v1 2^32 + v2 2^64,
+// limb_k = (v0(k) + v1(k-1) + v2(k-2) + carries) mod 2^32.  With
+// s_k = v0(k)+v1(k-1)+v2(k-2) < 3*2^32, x_k = s_k mod 2^32, y_k = s_k >> 32,
+// u_k = x_k + y_{k-1} <= 2^32 + 1 and the remaining carries are binary:
+// generate g_k = (u_k >= 2^32), propagate p_k = (u_k == 2^32 - 1).
+
+// Wave-level: carry into each lane for (g, p) with wave carry-in `cin`;
+// returns lane's carry in, and the wave carry out in *cout.
+__device__ __forceinline__ uint32_t wave_carry(bool g, bool pr, uint32_t cin, uint32_t* cout, bool* allprop) {
+  const uint64_t gm = __ballot(g), pm = __ballot(pr);
+  const uint64_t a = gm, b = gm | pm;
+  const uint64_t s1 = a + b;
+  const uint64_t c1 = s1 < a;
+  const uint64_t s2 = s1 + cin;
+  const uint64_t c2 = s2 < s1;
+  *cout = (uint32_t)(c1 | c2);
+  *allprop = (pm == ~0ull);
+  const uint64_t cm = s2 ^ pm;   // carry into each bit position
+  return (uint32_t)((cm >> (threadIdx.x & 63)) & 1ull);
+}
+
+// Block-level (blockDim = 64*W): returns the thread's carry-in given block
+// carry-in 0; *bG, *bP: block generate / propagate.  tmp >= 2*W words.
+__device__ __forceinline__ uint32_t block_carry(bool g, bool pr, uint32_t* tmp, uint32_t* bG, uint32_t* bP) {
+  const uint32_t wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t cout;
+  bool ap;
+  wave_carry(g, pr, 0, &cout, &ap);
+  if ((threadIdx.x & 63) == 0) tmp[wid] = cout | (ap ? 2u : 0u);
+  __syncthreads();
+  uint32_t cin = 0;
+  for (uint32_t w = 0; w < wid; w++) {
+    const uint32_t x = tmp[w];
+    cin = (x & 1u) | ((x >> 1) & cin);
+  }
+  uint32_t G = 0, P = 1;
+  for (uint32_t w = 0; w < nw; w++) {
+    const uint32_t x = tmp[w];
+    G = (x & 1u) | ((x >> 1) & G);
+    P = P & (x >> 1);
+  }
+  __syncthreads();
+  *bG = G;
+  *bP = P;
+  return wave_carry(g, pr, cin, &cout, &ap);
+}
+
+// Segments of a CRT launch: a device table with block prefix, or one segment
+// passed by value (single products launched on their own).
+struct SegView {
+  const CrtSeg* segs;        // nullptr => `one`
+  const uint32_t* pref;      // pref[s] = first block of segment s (nseg+1 entries)
+  uint32_t nseg;
+  CrtSeg one;
+  __device__ __forceinline__ void find(uint32_t b, CrtSeg* sg, uint32_t* first, uint32_t* end) const {
+    if (!segs) {
+      *sg = one;
+      *first = 0;
+      *end = (uint32_t)((one.len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
+      return;
+    }
+    uint32_t lo = 0, hi = nseg;   // pref[lo] <= b < pref[lo+1]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (pref[mid] <= b) lo = mid; else hi = mid;
+    }
+    *sg = segs[lo];
+    *first = pref[lo];
+    *end = pref[lo + 1];
+  }
+};
+
+// CRT + carry.  Block b covers CAT_CRT_BLOCK limbs of one segment.
+// bsum[b]: bit0 = block generate, bit1 = block propagate (carry-in 0).
+__global__ void __launch_bounds__(CAT_CRT_THREADS)
+k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out,
+      uint8_t* __restrict__ bsum, uint32_t* __restrict__ err) {
+  __shared__ uint32_t tmp[16];
+  const uint32_t b = blockIdx.x;
+  CrtSeg sg;
+  uint32_t first, end;
+  sv.find(b, &sg, &first, &end);
+  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
+  const uint64_t k0 = kb + (uint64_t)threadIdx.x * CAT_CRT_E;
+  const uint32_t* r0 = res + sg.res_pos;
+  const uint32_t* r1 = r0 + res_stride;
+  const uint32_t* r2 = r1 + res_stride;
+  // V for positions k0-3 .. k0+E-1
+  uint32_t v0[CAT_CRT_E + 3], v1[CAT_CRT_E + 3], v2[CAT_CRT_E + 3];
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E + 3; i++) {
+    const int64_t k = (int64_t)k0 + i - 3;
+    if (k >= 0 && (uint64_t)k < sg.len) garner3(r0[k], r1[k], r2[k], v0[i], v1[i], v2[i]);
+    else { v0[i] = 0; v1[i] = 0; v2[i] = 0; }
+  }
+  uint64_t u[CAT_CRT_E];
+  uint32_t yprev = (uint32_t)(((uint64_t)v0[2] + v1[1] + v2[0]) >> 32);   // position k0-1
+  bool G = false, P = true;
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E; i++) {
+    const uint64_t s = (uint64_t)v0[i + 3] + v1[i + 2] + v2[i + 1];
+    u[i] = (s & 0xFFFFFFFFull) + yprev;
+    yprev = (uint32_t)(s >> 32);
+    const bool g = u[i] >= (1ull << 32), pr = u[i] == 0xFFFFFFFFull;
+    G = g || (pr && G);
+    P = P && pr;
+  }
+  uint32_t bG, bP;
+  uint32_t c = block_carry(G, P, tmp, &bG, &bP);
+  uint32_t* o = out + sg.out_pos;
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E; i++) {
+    const uint64_t k = k0 + i;
+    const uint64_t t = u[i] + c;
+    c = (uint32_t)(t >> 32);
+    if (k < sg.len) o[k] = (uint32_t)t;
+  }
+  if (threadIdx.x == 0) {
+    bsum[b] = (uint8_t)(bG | (bP << 1));
+    if (b + 1 == end && bG) atomicOr(err, CAT_DEVERR_CARRY_OUT);
+  }
+}
+
+// Carry-in of every block: cin[b+1] = G_b | (P_b & cin[b]), nothing crosses a
+// segment end.  One workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024)
+k_carry_scan(SegView sv, const uint8_t* __restrict__ bsum, uint32_t nblk, uint8_t* __restrict__ cin,
+             uint32_t* __restrict__ err) {
+  __shared__ uint32_t tmp[32];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t base = 0; base < nblk; base += blockDim.x) {
+    const uint32_t b = base + threadIdx.x;
+    bool g = false, pr = false, seg_last = false;
+    if (b < nblk) {
+      CrtSeg sg;
+      uint32_t first, end;
+      sv.find(b, &sg, &first, &end);
+      seg_last = (b + 1 == end);
+      const uint8_t x = bsum[b];
+      g = (x & 1) != 0;
+      pr = (x & 2) != 0;
+    }
+    const bool gg = g && !seg_last, pp = pr && !seg_last;
+    uint32_t cout;
+    bool ap;
+    wave_carry(gg, pp, 0, &cout, &ap);
+    if (lane == 0) tmp[wid] = cout | (ap ? 2u : 0u);
+    __syncthreads();
+    uint32_t wc = carry;
+    for (uint32_t w = 0; w < wid; w++) {
+      const uint32_t x = tmp[w];
+      wc = (x & 1u) | ((x >> 1) & wc);
+    }
+    const uint32_t c = wave_carry(gg, pp, wc, &cout, &ap);   // carry into b
+    if (b < nblk) {
+      if (b + 1 < nblk) cin[b + 1] = (uint8_t)(gg | (pp & c));
+      if (b == 0) cin[0] = 0;
+      // a carry out of the last block of a segment means the product overflowed
+      if (seg_last && (g || (pr && c))) atomicOr(err, CAT_DEVERR_CARRY_OUT);
+    }
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) {
+      uint32_t cc = carry;
+      for (uint32_t w = 0; w < (blockDim.x >> 6); w++) {
+        const uint32_t x = tmp[w];
+        cc = (x & 1u) | ((x >> 1) & cc);
+      }
+      carry = cc;
+    }
+    __syncthreads();
+  }
+}
+
+// Adds the carry-in to each block that has one: the low limbs equal to
+// 2^32-1 become 0 and the first other limb is incremented.  One wave per block.
+__global__ void __launch_bounds__(64)
+k_carry_apply(SegView sv, const uint8_t* __restrict__ cin, uint32_t* __restrict__ out) {
+  const uint32_t b = blockIdx.x;
+  if (!cin[b]) return;
+  CrtSeg sg;
+  uint32_t first, end;
+  sv.find(b, &sg, &first, &end);
+  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
+  const uint64_t ke = min(kb + (uint64_t)CAT_CRT_BLOCK, sg.len);
+  uint32_t* o = out + sg.out_pos;
+  const uint32_t lane = threadIdx.x;
+  for (uint64_t k = kb; k < ke; k += 64) {
+    const uint64_t kk = k + lane;
+    const bool in = kk < ke;
+    const uint32_t x = in ? o[kk] : 0u;
+    const uint64_t nz = __ballot(in && x != 0xFFFFFFFFu);
+    if (nz) {
+      const uint32_t f = (uint32_t)__ffsll((unsigned long long)nz) - 1;
+      if (lane < f) o[kk] = 0u;
+      else if (lane == f) o[kk] = x + 1u;
+      return;
+    }
+    if (in) o[kk] = 0u;
+  }
+}

@@ -1,0 +1,267 @@
+// Phase 1 of the method (Sec. 3.1, Alg. 1): all primes p <= 2n with their
+// exponents e_p = v_p((2n)!) - 2 v_p(n!) - v_p(n+1) (Sec. 2), grouped by e.
+//
+// Device design (gfx950):
+//  * k_seeds: one workgroup sieves the seed primes q <= s = isqrt(2n) in a
+//    64 KB LDS byte map and computes their exponents with Legendre's sums.
+//  * k_sieve: one workgroup per segment of SEG odd numbers in (s, 2n]; the
+//    segment is a bit map in LDS (SEG/8 bytes), marked by the odd seeds
+//    (cooperatively for small q, one thread per prime for large q).  For a
+//    prime p > s we have p^2 > 2n, so Legendre's sums have one term and
+//    v_p(n+1) <= 1; with r = n mod p the exponent is
+//        e_p = [2r >= p] - [r == p-1]   (in {0, 1}).
+//    Only primes with e_p = 1 stay in the bit map written to HBM; the
+//    workgroup also writes its count.
+//  * k_groups: one workgroup scans the segment counts, places the seeds in
+//    their groups and writes the group table (exponent ascending).
+//  * k_scatter: one workgroup per segment writes its primes in ascending
+//    order to their final place inside G_1.
+// Every group ends up with its primes ascending; G_1 = {seeds with e = 1}
+// followed by the large primes with e = 1.
+
+#define SIEVE_SEG_LOG 18
+#define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment
+#define SIEVE_WORDS (SIEVE_SEG / 32)
+#define SIEVE_THREADS 1024
+#define SEED_MAX 6544                           // pi(65535) = 6542
+
+struct GroupTable {
+  uint32_t ngroups;
+  uint32_t n_seed_e1;         // seeds with e = 1 (they open G_1)
+  uint32_t nseeds;
+  uint32_t err;
+  uint32_t exps[CAT_MAX_GROUPS];
+  uint64_t off[CAT_MAX_GROUPS + 1];
+};
+
+// Exclusive scan over a 1024-thread block (16 wave64s).  tmp: >= 16 words.
+__device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t w = lane < 16 ? tmp[lane] : 0;
+    uint32_t t = w;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      uint32_t y = __shfl_up(t, d, 64);
+      if (lane >= d) t += y;
+    }
+    if (lane < 16) tmp[16 + lane] = t - w;    // exclusive wave offsets
+    if (lane == 15) tmp[32] = t;
+  }
+  __syncthreads();
+  uint32_t r = tmp[16 + wid] + x - v;
+  if (total) *total = tmp[32];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ uint64_t legendre_dev(uint64_t m, uint64_t p) {
+  uint64_t s = 0;
+  while (m) { m /= p; s += m; }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t* seeds, int32_t* seed_e,
+                                                GroupTable* gt) {
+  __shared__ uint8_t comp[65536];
+  __shared__ uint32_t tmp[40];
+  const uint32_t T = blockDim.x, tid = threadIdx.x;
+  for (uint32_t i = tid; i <= s; i += T) comp[i] = (i < 2) ? 1 : 0;
+  __syncthreads();
+  uint32_t r = 0;
+  while ((r + 1) * (r + 1) <= s) r++;
+  for (uint32_t q = 2; q <= r; q++) {
+    bool isq = true;
+    for (uint32_t d = 2; d * d <= q; d++)
+      if (q % d == 0) { isq = false; break; }
+    if (!isq) continue;
+    for (uint32_t m = q * q + tid * q; m <= s; m += T * q) comp[m] = 1;
+  }
+  __syncthreads();
+  // compaction, ascending: thread t owns numbers [t*chunk, (t+1)*chunk)
+  const uint32_t chunk = (s + 1 + T - 1) / T;
+  uint32_t lo = tid * chunk, hi = min(lo + chunk, s + 1);
+  uint32_t cnt = 0;
+  for (uint32_t i = lo; i < hi; i++) cnt += comp[i] ? 0 : 1;
+  uint32_t total;
+  uint32_t pos = block_excl_scan_1024(cnt, tmp, &total);
+  for (uint32_t i = lo; i < hi; i++)
+    if (!comp[i]) seeds[pos++] = i;
+  if (tid == 0) gt->nseeds = total;
+  __syncthreads();
+  __threadfence_block();
+  for (uint32_t k = tid; k < total; k += T) {
+    uint64_t q = seeds[k];
+    int64_t a = (int64_t)legendre_dev(2 * n, q);
+    int64_t b = (int64_t)legendre_dev(n, q);
+    uint64_t m = n + 1;
+    int64_t c = 0;
+    while (m % q == 0) { m /= q; c++; }
+    int64_t e = a - 2 * b - c;
+    if (e < 0) atomicOr(&gt->err, CAT_DEVERR_NEG_EXP);
+    seed_e[k] = (int32_t)e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment k covers odd indices i in [i0 + k*SEG, min(i0 + (k+1)*SEG, i_end)),
+// i.e. odd numbers m = 2i+1 in (s, 2n].
+__global__ void __launch_bounds__(1024) k_sieve(uint64_t n, uint64_t i0, uint64_t i_end,
+                                                const uint32_t* seeds, const GroupTable* gt,
+                                                uint32_t* bitmap, uint32_t* seg_cnt) {
+  __shared__ uint32_t bits[SIEVE_WORDS];
+  __shared__ uint32_t tmp[40];
+  const uint32_t T = blockDim.x, tid = threadIdx.x;
+  const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SIEVE_SEG;
+  const uint64_t i_hi = min(i_lo + SIEVE_SEG, i_end);
+  const uint32_t len = (uint32_t)(i_hi - i_lo);
+  for (uint32_t w = tid; w < SIEVE_WORDS; w += T) {
+    uint32_t b0 = w * 32;
+    uint32_t v = 0;
+    if (b0 + 32 <= len) v = 0xFFFFFFFFu;
+    else if (b0 < len) v = (1u << (len - b0)) - 1u;
+    bits[w] = v;
+  }
+  __syncthreads();
+  const uint32_t nseeds = gt->nseeds;
+  const uint64_t m_lo = 2 * i_lo + 1;
+  // small odd seeds: every thread marks a share of the multiples of q
+  uint32_t k = 1;
+  for (; k < nseeds; k++) {
+    uint64_t q = seeds[k];
+    if (q * 8 > SIEVE_SEG) break;
+    uint64_t t = (m_lo + q - 1) / q;
+    if (t < q) t = q;
+    if (!(t & 1)) t++;
+    uint64_t idx = (q * t - 1) / 2 - i_lo;
+    for (uint64_t x = idx + (uint64_t)tid * q; x < len; x += (uint64_t)T * q)
+      atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
+  }
+  // large seeds: one thread per prime
+  for (uint32_t kk = k + tid; kk < nseeds; kk += T) {
+    uint64_t q = seeds[kk];
+    uint64_t t = (m_lo + q - 1) / q;
+    if (t < q) t = q;
+    if (!(t & 1)) t++;
+    uint64_t idx = (q * t - 1) / 2 - i_lo;
+    for (uint64_t x = idx; x < len; x += q)
+      atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
+  }
+  __syncthreads();
+  // keep primes with e_p = 1, count them
+  uint32_t cnt = 0;
+  const uint32_t n32 = (uint32_t)n;   // n < 2^31
+  for (uint32_t w = tid; w < SIEVE_WORDS; w += T) {
+    uint32_t v = bits[w], keep = 0;
+    while (v) {
+      uint32_t b = __ffs(v) - 1;
+      v &= v - 1;
+      uint32_t p = (uint32_t)(2 * (i_lo + w * 32 + b) + 1);
+      uint32_t r = n32 % p;
+      uint32_t e = ((uint64_t)2 * r >= p ? 1u : 0u) - (r == p - 1 ? 1u : 0u);
+      if (e == 1) keep |= 1u << b;
+    }
+    bitmap[(uint64_t)blockIdx.x * SIEVE_WORDS + w] = keep;
+    cnt += __popc(keep);
+  }
+  uint32_t total;
+  block_excl_scan_1024(cnt, tmp, &total);
+  if (tid == 0) seg_cnt[blockIdx.x] = total;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* seg_cnt, uint32_t* seg_off,
+                                                 const uint32_t* seeds, const int32_t* seed_e,
+                                                 uint32_t* primes, uint64_t cap, GroupTable* gt) {
+  __shared__ uint32_t tmp[40];
+  __shared__ uint32_t cnt_e[CAT_MAX_GROUPS + 1];
+  __shared__ uint64_t goff[CAT_MAX_GROUPS + 2];
+  const uint32_t T = blockDim.x, tid = threadIdx.x;
+  // 1. exclusive scan of the segment counts
+  const uint32_t chunk = (nseg + T - 1) / T;
+  uint32_t lo = min(tid * chunk, nseg), hi = min(lo + chunk, nseg);
+  uint32_t c = 0;
+  for (uint32_t i = lo; i < hi; i++) c += seg_cnt[i];
+  uint32_t total_large;
+  uint32_t pos = block_excl_scan_1024(c, tmp, &total_large);
+  for (uint32_t i = lo; i < hi; i++) { seg_off[i] = pos; pos += seg_cnt[i]; }
+  // 2. seed counts per exponent
+  if (tid <= CAT_MAX_GROUPS) cnt_e[tid] = 0;
+  __syncthreads();
+  const uint32_t ns = gt->nseeds;
+  for (uint32_t k = tid; k < ns; k += T) {
+    int32_t e = seed_e[k];
+    if (e > 0 && e <= CAT_MAX_GROUPS) atomicAdd(&cnt_e[e], 1u);
+  }
+  __syncthreads();
+  // 3. group table (exponent ascending, empty groups dropped)
+  if (tid == 0) {
+    uint32_t g = 0;
+    uint64_t o = 0;
+    for (uint32_t e = 1; e <= CAT_MAX_GROUPS; e++) {
+      uint64_t cnt = cnt_e[e] + (e == 1 ? (uint64_t)total_large : 0);
+      goff[e] = o;
+      if (cnt == 0) continue;
+      gt->exps[g] = e;
+      gt->off[g] = o;
+      o += cnt;
+      g++;
+    }
+    gt->off[g] = o;
+    gt->ngroups = g;
+    gt->n_seed_e1 = cnt_e[1];
+    if (o > cap) atomicOr(&gt->err, CAT_DEVERR_BOUNDS);
+    goff[0] = o;  // total
+  }
+  __syncthreads();
+  // 4. seeds into their groups, stable (seeds ascending)
+  const uint32_t sch = (ns + T - 1) / T;
+  const uint32_t slo = min(tid * sch, ns), shi = min(slo + sch, ns);
+  for (uint32_t e = 1; e <= CAT_MAX_GROUPS; e++) {
+    if (cnt_e[e] == 0) continue;   // uniform
+    uint32_t cc = 0;
+    for (uint32_t k = slo; k < shi; k++) cc += (seed_e[k] == (int32_t)e);
+    uint32_t r = block_excl_scan_1024(cc, tmp, nullptr);
+    uint64_t base = goff[e];
+    for (uint32_t k = slo; k < shi; k++)
+      if (seed_e[k] == (int32_t)e) {
+        uint64_t at = base + r++;
+        if (at < cap) primes[at] = seeds[k];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_scatter(uint64_t i0, const uint32_t* bitmap, const uint32_t* seg_off,
+                                                  const GroupTable* gt, uint32_t* primes, uint64_t cap) {
+  __shared__ uint32_t tmp[40];
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t WPT = SIEVE_WORDS / SIEVE_THREADS;   // words per thread
+  const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SIEVE_SEG;
+  const uint32_t* bm = bitmap + (uint64_t)blockIdx.x * SIEVE_WORDS;
+  uint32_t w[WPT];
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < WPT; k++) { w[k] = bm[tid * WPT + k]; c += __popc(w[k]); }
+  uint32_t r = block_excl_scan_1024(c, tmp, nullptr);
+  uint64_t at = (uint64_t)gt->n_seed_e1 + seg_off[blockIdx.x] + r;
+#pragma unroll
+  for (uint32_t k = 0; k < WPT; k++) {
+    uint32_t v = w[k];
+    while (v) {
+      uint32_t b = __ffs(v) - 1;
+      v &= v - 1;
+      if (at < cap) primes[at] = (uint32_t)(2 * (i_lo + (tid * WPT + k) * 32 + b) + 1);
+      at++;
+    }
+  }
+}

@@ -1,0 +1,246 @@
+// Small products of the reconstruction tree (Sec. 3.2, Alg. 2: the lower
+// levels of BalancedProductTree(G_e)), plus utility kernels.
+//
+//  * k_leaf<LF>: one thread forms a node of tree level LF directly from its
+//    (up to) 2^LF consecutive primes, by multiplying a register accumulator by
+//    one 32-bit prime at a time.  The node is the same integer the pairwise
+//    tree gives (a product of the same leaves), in the same 2^LF-limb slot.
+//  * k_school: one wave per product of la, lb <= 128 limbs: column sums in
+//    96-bit accumulators (Comba order), then the ballot carry-lookahead.
+
+// ---------------------------------------------------------------------------
+// Leaf packing.  Tree view: level LF, node i of group g is written at
+// base[g] + i*2^LF; `tl.mpref` is the prefix count of NODES per group.
+template <int LF>
+__global__ void __launch_bounds__(256)
+k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint32_t* __restrict__ out) {
+  constexpr int W = 1 << LF;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes) return;
+  uint32_t g = 0;
+  while (g + 1 < tl.ngroups && i >= tl.mpref[g + 1]) g++;
+  const uint64_t il = i - tl.mpref[g];
+  const uint64_t off = tl.base[g] + il * W;
+  const uint64_t rem = tl.K[g] - il * W;
+  const uint32_t cnt = (uint32_t)(rem < (uint64_t)W ? rem : (uint64_t)W);
+  uint32_t acc[W];
+  acc[0] = primes[off];
+#pragma unroll
+  for (int k = 1; k < W; k++) acc[k] = 0;
+#pragma unroll
+  for (int k = 1; k < W; k++) {
+    if ((uint32_t)k < cnt) {
+      const uint32_t q = primes[off + k];
+      uint32_t carry = 0;
+#pragma unroll
+      for (int l = 0; l < k; l++) {
+        const uint64_t t = (uint64_t)acc[l] * q + carry;
+        acc[l] = (uint32_t)t;
+        carry = (uint32_t)(t >> 32);
+      }
+      acc[k] = carry;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < W; k++)
+    if ((uint32_t)k < cnt) out[off + k] = acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// Schoolbook products, la, lb <= 128.  4 waves per block, one product each.
+#define SCHOOL_MAX 128
+#define SCHOOL_WAVES 4
+__global__ void __launch_bounds__(64 * SCHOOL_WAVES)
+k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
+         uint32_t* __restrict__ out, uint32_t* __restrict__ err) {
+  __shared__ uint32_t sa[SCHOOL_WAVES][SCHOOL_MAX];
+  __shared__ uint32_t sb[SCHOOL_WAVES][SCHOOL_MAX];
+  __shared__ uint32_t sv[SCHOOL_WAVES][3][2 * SCHOOL_MAX + 4];
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t mi = (uint64_t)blockIdx.x * SCHOOL_WAVES + w;
+  if (mi >= nmul) return;   // whole wave leaves together; no block barrier below
+  const MulDesc d = dv.get(mi);
+  const uint32_t la = d.la, lb = d.lb, L = la + lb;
+  for (uint32_t k = lane; k < la; k += 64) sa[w][k] = ain[d.a_off + k];
+  for (uint32_t k = lane; k < lb; k += 64) sb[w][k] = bin[d.b_off + k];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // column k = sum_{i} a_i b_{k-i}; lanes take k = lane + 64*c
+  for (uint32_t k = lane; k < 2 * SCHOOL_MAX; k += 64) {
+    uint64_t lo = 0;
+    uint32_t hi = 0;
+    if (k + 1 < L) {
+      const uint32_t i0 = k + 1 > lb ? k + 1 - lb : 0;
+      const uint32_t i1 = k < la - 1 ? k : la - 1;
+      for (uint32_t i = i0; i <= i1; i++) {
+        const uint64_t t = (uint64_t)sa[w][i] * sb[w][k - i];
+        lo += t;
+        hi += (lo < t);
+      }
+    }
+    sv[w][0][k + 3] = (uint32_t)lo;
+    sv[w][1][k + 3] = (uint32_t)(lo >> 32);
+    sv[w][2][k + 3] = hi;
+  }
+  if (lane < 3) { sv[w][0][lane] = 0; sv[w][1][lane] = 0; sv[w][2][lane] = 0; }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // lane owns limbs 4*lane .. 4*lane+3 (position k stored at index k+3)
+  constexpr int E = 4;
+  const uint32_t k0 = lane * E;
+  uint64_t u[E];
+  uint32_t yprev = (uint32_t)(((uint64_t)sv[w][0][k0 + 2] + sv[w][1][k0 + 1] + sv[w][2][k0]) >> 32);
+  bool G = false, P = true;
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    const uint32_t k = k0 + i;
+    uint64_t s = 0;
+    if (k < L) s = (uint64_t)sv[w][0][k + 3] + sv[w][1][k + 2] + sv[w][2][k + 1];
+    u[i] = (s & 0xFFFFFFFFull) + yprev;
+    yprev = (uint32_t)(s >> 32);
+    const bool g = u[i] >= (1ull << 32), pr = u[i] == 0xFFFFFFFFull;
+    G = g || (pr && G);
+    P = P && pr;
+  }
+  uint32_t cout;
+  bool ap;
+  uint32_t c = wave_carry(G, P, 0, &cout, &ap);
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    const uint32_t k = k0 + i;
+    const uint64_t t = u[i] + c;
+    c = (uint32_t)(t >> 32);
+    if (k < L) out[d.c_off + k] = (uint32_t)t;
+  }
+  if (lane == 0 && cout) atomicOr(err, CAT_DEVERR_CARRY_OUT);
+}
+
+// ---------------------------------------------------------------------------
+// Copy of up to CAT_MAX_GROUPS ranges (the odd nodes carried up a level).
+struct CopyList {
+  uint32_t n;
+  uint64_t off[CAT_MAX_GROUPS];
+  uint64_t len[CAT_MAX_GROUPS];
+};
+__global__ void k_copy_ranges(CopyList cl, const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
+  const uint32_t r = blockIdx.y;
+  if (r >= cl.n) return;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cl.len[r];
+       k += (uint64_t)gridDim.x * blockDim.x)
+    out[cl.off[r] + k] = in[cl.off[r] + k];
+}
+
+__global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ void k_copy(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint64_t n) {
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+    out[k] = in[k];
+}
+
+// Highest index with a nonzero limb, +1 (0 if all zero) -> *top (atomicMax).
+__global__ void k_top_nonzero(const uint32_t* __restrict__ x, uint64_t n, unsigned long long* top) {
+  unsigned long long best = 0;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+    if (x[k]) best = k + 1;
+  for (int d = 32; d >= 1; d >>= 1) {
+    unsigned long long o = __shfl_xor(best, d, 64);
+    best = o > best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0 && best) atomicMax(top, best);
+}
+
+// Fingerprints of a limb vector: x mod (2^32 - 5), x mod (2^32 + 1), x mod (2^32 - 1).
+// Each block reduces a contiguous chunk with Horner steps, partial results
+// are combined by weights (2^32)^{offset} on the host side of the library.
+__device__ __forceinline__ uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) {
+  // a, b < m <= 2^33: exact via 128-bit product
+  unsigned __int128 t = (unsigned __int128)a * b;
+  return (uint64_t)(t % m);
+}
+__global__ void k_residues(const uint32_t* __restrict__ x, uint64_t n, uint64_t chunk, uint64_t* __restrict__ part) {
+  const uint64_t mods[3] = {4294967291ull, 4294967297ull, 4294967295ull};
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t lo = c * chunk;
+  if (lo >= n) return;
+  const uint64_t hi = min(lo + chunk, n);
+  for (int m = 0; m < 3; m++) {
+    const uint64_t q = mods[m];
+    const uint64_t base = (1ull << 32) % q;
+    uint64_t r = 0;
+    for (uint64_t k = hi; k > lo; k--) r = (mulmod64(r, base, q) + x[k - 1]) % q;
+    part[c * 3 + m] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Twiddle tables.  roots[prime][s] = omega_{2^s} in Montgomery form.
+struct RootsC {
+  uint32_t r[CAT_NPRIMES][CAT_MAX_LOGN + 1];     // forward, Montgomery form
+  uint32_t ir[CAT_NPRIMES][CAT_MAX_LOGN + 1];    // inverse
+  uint32_t one[CAT_NPRIMES];                     // R mod p
+};
+__constant__ RootsC c_roots;
+
+__device__ __forceinline__ uint32_t mont_pow(uint32_t b, uint64_t e, uint32_t one, uint32_t p, uint32_t pinv) {
+  uint32_t r = one;
+  while (e) {
+    if (e & 1) r = mont_mul(r, b, p, pinv);
+    b = mont_mul(b, b, p, pinv);
+    e >>= 1;
+  }
+  return r;
+}
+__device__ __forceinline__ uint2 tw_pair(uint32_t w, uint32_t pinv) { return make_uint2(w, w * pinv); }
+
+// Pass tables: for s = 1..12, S = 2^s, radix R = 2^pass_logr(s), entry
+// (k1, j2) at tws_off(s) + (k1 << (s - r)) + j2 = omega_S^{+-j2*k1}.
+__global__ void k_build_tws(uint2* __restrict__ tws, uint2* __restrict__ itws) {
+  const uint32_t prime = blockIdx.y;
+  const uint32_t p = c_primes[prime].p, pinv = c_primes[prime].pinv;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < TWS_ENTRIES; i += gridDim.x * blockDim.x) {
+    int s = 1;
+    while (tws_off(s + 1) <= i) s++;
+    const uint32_t li = i - tws_off(s);
+    const int r = pass_logr(s);
+    const uint32_t k1 = li >> (s - r), j2 = li & ((1u << (s - r)) - 1);
+    const uint64_t e = (uint64_t)j2 * k1;
+    const uint32_t w = mont_pow(c_roots.r[prime][s], e, c_roots.one[prime], p, pinv);
+    const uint32_t iw = mont_pow(c_roots.ir[prime][s], e, c_roots.one[prime], p, pinv);
+    tws[(size_t)prime * TWS_ENTRIES + i] = tw_pair(w, pinv);
+    itws[(size_t)prime * TWS_ENTRIES + i] = tw_pair(iw, pinv);
+  }
+}
+
+// frequency held at output position q of the pass-structured transform of size 2^logS
+__device__ __forceinline__ uint32_t out_freq(uint32_t q, int logS) {
+  uint32_t f = 0, mult = 1;
+  while (logS > 0) {
+    const int r = pass_logr(logS);
+    const int rest = logS - r;
+    const uint32_t k1 = q >> rest;
+    f += k1 * mult;
+    mult <<= r;
+    q &= (1u << rest) - 1;
+    logS = rest;
+  }
+  return f;
+}
+
+// Four-step tables for N = 2^logN = R1 * M: entry q*M + col = omega_N^{+-col*freq(q)}.
+__global__ void k_build_twn(int logN, uint2* __restrict__ twn, uint2* __restrict__ itwn) {
+  const uint32_t prime = blockIdx.y;
+  const uint32_t p = c_primes[prime].p, pinv = c_primes[prime].pinv;
+  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
+  const uint64_t N = 1ull << logN;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t q = (uint32_t)(i >> logM), col = (uint32_t)(i & ((1u << logM) - 1));
+    const uint64_t e = ((uint64_t)col * out_freq(q, logR1)) & (N - 1);
+    const uint32_t w = mont_pow(c_roots.r[prime][logN], e, c_roots.one[prime], p, pinv);
+    const uint32_t iw = mont_pow(c_roots.ir[prime][logN], e, c_roots.one[prime], p, pinv);
+    twn[(size_t)prime * N + i] = tw_pair(w, pinv);
+    itwn[(size_t)prime * N + i] = tw_pair(iw, pinv);
+  }
+}

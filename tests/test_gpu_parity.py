@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle,
+bit-exact (all arithmetic is exact integer work)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def cat():
+    import torch
+
+    import paper_2601_11621_amd as c
+
+    torch.cuda.set_device(0)
+    c.init(0)
+    return c
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ Phase 1
+def test_factor_small_n_all(cat):
+    for n in range(0, 400):
+        exps, off, pr = cat.factor(n)
+        oe, oo, op = oracle.factor(n)
+        assert np.array_equal(exps, oe), n
+        assert np.array_equal(off, oo), n
+        assert np.array_equal(cat.to_numpy(pr), op), n
+
+
+@pytest.mark.parametrize("n", [401, 1000, 4096, 65535, 65536, 100000, 262143, 1000000])
+def test_factor_selected(cat, n):
+    _say("factor", n)
+    exps, off, pr = cat.factor(n)
+    oe, oo, op = oracle.factor(n)
+    assert np.array_equal(exps, oe)
+    assert np.array_equal(off, oo)
+    assert np.array_equal(cat.to_numpy(pr), op)
+
+
+def test_factor_1e7(cat):
+    n = 10**7
+    exps, off, pr = cat.factor(n)
+    oe, oo, op = oracle.factor(n)
+    assert np.array_equal(exps, oe) and np.array_equal(off, oo)
+    assert np.array_equal(cat.to_numpy(pr), op)
+    # group sizes of the paper's workload family: |G_1| = 867,378 at n = 10^7
+    assert int(off[1] - off[0]) == 867378
+
+
+# ------------------------------------------------------------------ products
+def _rand(rng, n, kind="rand"):
+    if kind == "ones":
+        return np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+    if kind == "zero":
+        return np.zeros(n, dtype=np.uint32)
+    return rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+
+
+def _run_batch(cat, la, lb, kinds, mode, seed=0):
+    rng = np.random.default_rng(seed)
+    a = [_rand(rng, x, k) for x, k in zip(la, kinds)]
+    b = [_rand(rng, x, k) for x, k in zip(lb, kinds)]
+    a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
+    af, bf = np.concatenate(a), np.concatenate(b)
+    c, c_off = cat.mul_batched(cat.from_numpy(af), a_off, cat.from_numpy(bf), b_off, mode=mode)
+    oc, oc_off = oracle.mul_batched(af, a_off, bf, b_off)
+    assert np.array_equal(c_off, oc_off)
+    got = cat.to_numpy(c)
+    for i in range(len(la)):
+        s, e = int(c_off[i]), int(c_off[i + 1])
+        assert np.array_equal(got[s:e], oc[s:e]), (i, la[i], lb[i], kinds[i], mode)
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_mul_edges(cat, mode):
+    la, lb, kinds = [], [], []
+    # bucket edges of the schoolbook / LDS / four-step classes, ragged tails
+    for x, y in [(1, 1), (1, 128), (128, 128), (129, 1), (129, 129), (64, 65), (255, 256), (2047, 2049),
+                 (2048, 2048), (2049, 2048), (4095, 2), (3000, 1100), (4097, 4096), (5000, 3), (1, 9000)]:
+        for k in ["rand", "ones", "zero"]:
+            la.append(x)
+            lb.append(y)
+            kinds.append(k)
+    _run_batch(cat, la, lb, kinds, mode)
+
+
+def test_mul_large_fourstep(cat):
+    la = [40000, 65536, 70000, 1, 131072]
+    lb = [30000, 65536, 100, 100000, 131071]
+    kinds = ["rand", "ones", "rand", "rand", "ones"]
+    _run_batch(cat, la, lb, kinds, "batched", seed=5)
+
+
+def test_mul_random_batch_uneven(cat):
+    rng = np.random.default_rng(7)
+    la = np.rint(2 ** rng.uniform(0, 13, 300)).astype(np.int64).tolist()
+    lb = np.rint(2 ** rng.uniform(0, 13, 300)).astype(np.int64).tolist()
+    _run_batch(cat, la, lb, ["rand"] * 300, "batched", seed=8)
+
+
+def test_mul_plan_graph_replays(cat):
+    import torch
+
+    rng = np.random.default_rng(9)
+    la = np.rint(2 ** rng.uniform(6, 12, 64)).astype(np.int64)
+    lb = np.rint(2 ** rng.uniform(6, 12, 64)).astype(np.int64)
+    a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
+    af = _rand(rng, int(a_off[-1]))
+    bf = _rand(rng, int(b_off[-1]))
+    plan = cat.MulPlan(a_off, b_off, mode="graph")
+    c = torch.zeros(int((la + lb).sum()), dtype=torch.int32, device="cuda")
+    da, db = cat.from_numpy(af), cat.from_numpy(bf)
+    oc, _ = oracle.mul_batched(af, a_off, bf, b_off)
+    for rep in range(4):
+        c.zero_()
+        torch.cuda.synchronize()
+        plan(da, db, c)
+        plan.check()
+        assert np.array_equal(cat.to_numpy(c), oc), rep
+    plan.close()
+
+
+# ------------------------------------------------------------------ C(n)
+def test_exact_small_n_all_modes(cat):
+    for n in range(0, 300):
+        exp = oracle.catalan(n)
+        for mode in (["batched", "plain", "graph"] if n % 7 == 0 else ["graph"]):
+            got = cat.to_numpy(cat.exact(n, mode=mode))
+            assert np.array_equal(got, exp), (n, mode)
+
+
+@pytest.mark.parametrize("n", [1000, 4097, 13337, 100000])
+def test_exact_vs_oracle(cat, n):
+    _say("exact", n)
+    exp = oracle.catalan(n)
+    for mode in ["batched", "graph", "plain"]:
+        got = cat.to_numpy(cat.exact(n, mode=mode))
+        assert np.array_equal(got, exp), mode
+
+
+def test_exact_1e6_vs_oracle(cat):
+    exp = oracle.catalan(10**6)
+    got = cat.to_numpy(cat.exact(10**6, mode="graph"))
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("n", [10**7])
+def test_exact_full_size_digest(cat, n):
+    """Full benchmark size: the SHA-256 of the limbs against the oracle's
+    digest (written by tests/golden/make_oracle_golden.py), plus residue pins."""
+    with open(os.path.join(GOLDEN, "oracle_catalan.json")) as f:
+        gold = json.load(f)[str(n)]
+    t = cat.exact(n, mode="graph")
+    got = cat.to_numpy(t)
+    assert len(got) == gold["n_limbs"]
+    assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
+    r = cat.residues(t)
+    assert r[0] == gold["mod_2p32_minus_5"]
+    assert r[1] == pins.catalan_mod_composite(n, [641, 6700417])
+
+
+def test_residues_kernel(cat):
+    rng = np.random.default_rng(3)
+    for n in [1, 5, 4096, 4097, 100000]:
+        x = _rand(rng, n)
+        v = pins.limbs_int(x)
+        r = cat.residues(cat.from_numpy(x))
+        assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1))
