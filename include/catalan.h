@@ -147,6 +147,17 @@ typedef struct {
 } cat_stats;
 cat_status cat_get_stats(cat_stats* out);
 
+/* Kernel timer (measurement only).  cat_timer_set(name) brackets every later
+ * launch of the named kernel ("k_ntt_lds", "k_row", "k_col_fwd", "k_col_inv",
+ * "k_crt", "k_school", "k_leaf") with HIP events on the stream it is launched
+ * on, outside graph capture; NULL or "" stops it.  Each call resets the
+ * counters.  cat_timer_get waits for the recorded events and returns the summed
+ * kernel time, the launch count and the algorithmic work of those launches
+ * (radix-2 butterflies for NTT kernels, limbs for k_crt and k_school, nodes for
+ * k_leaf). */
+cat_status cat_timer_set(const char* kernel);
+cat_status cat_timer_get(double* ms, uint64_t* launches, double* work);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,7 @@ EXPORTS = [
     "cat_init", "cat_strerror", "cat_last_device_error", "cat_get_stats", "catalan_sizes",
     "catalan_factor", "bigint_mul_workspace", "bigint_mul_batched", "bigint_mul_batched_ex",
     "catalan_exact", "catalan_exact_ex", "cat_mul_plan_create", "cat_mul_plan_exec",
-    "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues",
+    "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues", "cat_timer_set", "cat_timer_get",
 ]
 
 
@@ -91,6 +91,8 @@ def load(path: str = LIB_PATH):
         "cat_mul_plan_check": ([vp, vp, vp], st),
         "cat_mul_plan_destroy": ([vp], st),
         "bigint_residues": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
+        "cat_timer_set": ([ctypes.c_char_p], st),
+        "cat_timer_get": ([ctypes.POINTER(ctypes.c_double), u64p, ctypes.POINTER(ctypes.c_double)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -260,6 +262,20 @@ class MulPlan:
             self.close()
         except Exception:
             pass
+
+
+def timer_set(kernel: Optional[str]) -> None:
+    """Bracket every later launch of `kernel` with HIP events (None stops)."""
+    _check(load().cat_timer_set(kernel.encode() if kernel else None), "cat_timer_set")
+
+
+def timer_get():
+    """(summed kernel ms, launches, algorithmic work) since timer_set."""
+    ms = ctypes.c_double()
+    ln = ctypes.c_uint64()
+    wk = ctypes.c_double()
+    _check(load().cat_timer_get(ctypes.byref(ms), ctypes.byref(ln), ctypes.byref(wk)), "cat_timer_get")
+    return ms.value, ln.value, wk.value
 
 
 def residues(x, stream=None):

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/catalan.h"
@@ -37,8 +38,38 @@ struct Lib {
   std::map<uint64_t, Plan*> plans;
   std::vector<uint64_t> plan_order;
   hipStream_t cap_stream = nullptr;
+  // kernel timer: events around every launch of one named kernel
+  std::string timer_name;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_ev;
+  size_t timer_used = 0;
+  double timer_work = 0;
 };
 Lib g;
+
+// Brackets a launch of kernel `name` with events when the timer watches it.
+struct KTime {
+  bool on = false;
+  hipStream_t st;
+  size_t idx = 0;
+  KTime(const char* name, hipStream_t s, double work) : st(s) {
+    if (g.timer_name.empty() || g.timer_name != name) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (g.timer_used == g.timer_ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+      g.timer_ev.push_back({a, b});
+    }
+    idx = g.timer_used++;
+    g.timer_work += work;
+    on = hipEventRecord(g.timer_ev[idx].first, s) == hipSuccess;
+  }
+  ~KTime() {
+    if (on) (void)hipEventRecord(g.timer_ev[idx].second, st);
+  }
+};
+// radix-2 butterflies of `t` length-2^logN transforms
+double bfly(double t, int logN) { return t * (double)(1ull << logN) / 2.0 * logN; }
 
 #define HIPCHK(x)                                   \
   do {                                              \
@@ -626,17 +657,19 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
   for (uint32_t gi = 0; gi < gt.ngroups; gi++) P->exps[gi] = gt.exps[gi];
   for (uint32_t gi = 0; gi <= gt.ngroups; gi++) P->off[gi] = gt.off[gi];
   uint64_t root_b = 0, root_p = 0;
-  P->products = 0;
-  P->product_limbs = 0;
   plan_tree(Ly, *P, true, &root_b);
   const uint64_t prod_b = P->products, limbs_b = P->product_limbs;
+  P->products = 0;
+  P->product_limbs = 0;
   plan_tree(Ly, *P, false, &root_p);
   if (root_b != root_p) {
     free_plan(P);
     return CAT_EINTERNAL;
   }
-  P->products = prod_b;
-  P->product_limbs = limbs_b;
+  // products and their limbs are counted from the pairwise levels of the plain
+  // form (the leaf kernel of the batched form folds the lowest levels)
+  (void)prod_b;
+  (void)limbs_b;
   plan_post(Ly, *P, root_b);
   std::vector<Stage*> all;
   for (auto& s : P->batched) all.push_back(&s);
@@ -688,8 +721,11 @@ struct Exec {
 };
 
 cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, bool fix) {
-  hipLaunchKernelGGL(k_crt, dim3(nblk), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.bsum,
-                     X.err);
+  {
+    KTime kt("k_crt", X.st, (double)nblk * CAT_CRT_BLOCK);
+    hipLaunchKernelGGL(k_crt, dim3(nblk), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.bsum,
+                       X.err);
+  }
   LAUNCHCHK();
   X.launches++;
   if (fix) {
@@ -711,8 +747,11 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
   uint32_t* out = out_base(X, s);
   if (s.cls == CLS_SCHOOL) {
     const uint64_t blocks = (cnt + SCHOOL_WAVES - 1) / SCHOOL_WAVES;
-    hipLaunchKernelGGL(k_school, dim3((uint32_t)blocks), dim3(64 * SCHOOL_WAVES), 0, X.st, dv, cnt, ain, bin, out,
-                       X.err);
+    {
+      KTime kt("k_school", X.st, (double)s.limbs);
+      hipLaunchKernelGGL(k_school, dim3((uint32_t)blocks), dim3(64 * SCHOOL_WAVES), 0, X.st, dv, cnt, ain, bin, out,
+                         X.err);
+    }
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;
@@ -722,8 +761,11 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
   if (s.cls == CLS_LDS) {
     const uint64_t per = NTT_LDS_T >> s.logN;
     const uint64_t tiles = (cnt + per - 1) / per;
-    hipLaunchKernelGGL(k_ntt_lds, dim3((uint32_t)tiles, CAT_NPRIMES), dim3(NTT_LDS_THREADS), 0, X.st, dv, cnt, s.logN,
-                       ain, bin, X.res, X.res_stride, tb, s0, s1, s2);
+    {
+      KTime kt("k_ntt_lds", X.st, bfly(9.0 * cnt, s.logN));
+      hipLaunchKernelGGL(k_ntt_lds, dim3((uint32_t)tiles, CAT_NPRIMES), dim3(NTT_LDS_THREADS), 0, X.st, dv, cnt,
+                         s.logN, ain, bin, X.res, X.res_stride, tb, s0, s1, s2);
+    }
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;
@@ -734,14 +776,26 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
   if (logC > logM) logC = logM;
   if (logC < 0) return CAT_EINVAL;
   const uint64_t tiles = 1ull << (logM - logC);
-  hipLaunchKernelGGL(k_col_fwd, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                     s.logN, logC, ain, bin, X.F, tb);
+  const double rows = (double)cnt * (1ull << logR1), cols = (double)cnt * (1ull << logM);
+  {
+    // column DFTs of both operands, 3 primes
+    KTime kt("k_col_fwd", X.st, bfly(6.0 * cols, logR1));
+    hipLaunchKernelGGL(k_col_fwd, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st, dv,
+                       s.logN, logC, ain, bin, X.F, tb);
+  }
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_row, dim3((uint32_t)(cnt << logR1), CAT_NPRIMES), dim3(NTT_ROW_THREADS), 0, X.st, s.logN, X.F,
-                     tb, s0, s1, s2);
+  {
+    // row DFTs: two forward and one inverse per row, 3 primes
+    KTime kt("k_row", X.st, bfly(9.0 * rows, logM));
+    hipLaunchKernelGGL(k_row, dim3((uint32_t)(cnt << logR1), CAT_NPRIMES), dim3(NTT_ROW_THREADS), 0, X.st, s.logN,
+                       X.F, tb, s0, s1, s2);
+  }
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_col_inv, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                     s.logN, logC, X.F, X.res, X.res_stride, tb);
+  {
+    KTime kt("k_col_inv", X.st, bfly(3.0 * cols, logR1));
+    hipLaunchKernelGGL(k_col_inv, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
+                       s.logN, logC, X.F, X.res, X.res_stride, tb);
+  }
   LAUNCHCHK();
   X.launches += 3;
   return CAT_OK;
@@ -770,8 +824,11 @@ SegView stage_segs(const Stage& s) {
 cat_status run_stage_batched(Exec& X, const Stage& s) {
   if (s.is_leaf) {
     const uint32_t blocks = (uint32_t)((s.leaf_nodes + 255) / 256);
-    hipLaunchKernelGGL(k_leaf<5>, dim3(blocks), dim3(256), 0, X.st, s.leaf, s.leaf_nodes, X.W + s.a_base,
-                       X.W + s.c_base);
+    {
+      KTime kt("k_leaf", X.st, (double)s.leaf_nodes);
+      hipLaunchKernelGGL(k_leaf<5>, dim3(blocks), dim3(256), 0, X.st, s.leaf, s.leaf_nodes, X.W + s.a_base,
+                         X.W + s.c_base);
+    }
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;
@@ -1085,6 +1142,29 @@ const char* cat_strerror(cat_status s) {
 }
 
 int cat_last_device_error(void) { return g.last_err; }
+
+cat_status cat_timer_set(const char* kernel) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  g.timer_name = kernel ? kernel : "";
+  g.timer_used = 0;
+  g.timer_work = 0;
+  return CAT_OK;
+}
+
+cat_status cat_timer_get(double* ms, uint64_t* launches, double* work) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  double tot = 0;
+  for (size_t i = 0; i < g.timer_used; i++) {
+    HIPCHK(hipEventSynchronize(g.timer_ev[i].second));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, g.timer_ev[i].first, g.timer_ev[i].second));
+    tot += t;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = g.timer_used;
+  if (work) *work = g.timer_work;
+  return CAT_OK;
+}
 
 cat_status cat_get_stats(cat_stats* out) {
   if (!out) return CAT_EINVAL;
