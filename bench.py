@@ -81,12 +81,27 @@ def kernel_times(cat, n, out):
     return res
 
 
+def source_sha1():
+    import glob
+
+    h = hashlib.sha1()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_11621_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def load_traffic(kernel, n):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernels changed after the counters were taken."""
     path = os.path.join(PROFILES, "traffic_%s_n%d.json" % (kernel, n))
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        return json.load(f)
+        t = json.load(f)
+    if t.get("source_sha1") != source_sha1():
+        return None
+    return t
 
 
 def cpu_baseline(n, product_limbs):
