@@ -379,8 +379,10 @@ struct Plan {
   void* dev = nullptr;          // device tables (segments, prefixes, descriptors)
   uint64_t products = 0, product_limbs = 0;
   uint32_t levels = 0;
-  // graph cache: workspace base -> exec
+  // graph caches: workspace base -> exec (Phase 2 only); (workspace, output,
+  // capacity) -> exec of the whole call (Phase 1 + Phase 2 + copy)
   std::map<uintptr_t, hipGraphExec_t> graphs;
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> full_graphs;
 };
 
 // Forest levels of the product trees over the groups (one tree per group).
@@ -646,6 +648,7 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
 
 void free_plan(Plan* P) {
   for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : P->full_graphs) (void)hipGraphExecDestroy(kv.second);
   if (P->dev) (void)hipFree(P->dev);
   delete P;
 }
@@ -729,11 +732,9 @@ cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, bool fi
   LAUNCHCHK();
   X.launches++;
   if (fix) {
-    hipLaunchKernelGGL(k_carry_scan, dim3(1), dim3(1024), 0, X.st, sv, X.bsum, nblk, X.cin, X.err);
+    hipLaunchKernelGGL(k_carry_fix, dim3(1), dim3(1024), 0, X.st, sv, X.bsum, nblk, X.cin, out, X.err);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_carry_apply, dim3(nblk), dim3(64), 0, X.st, sv, X.cin, out);
-    LAUNCHCHK();
-    X.launches += 2;
+    X.launches += 1;
   }
   return CAT_OK;
 }
@@ -868,6 +869,29 @@ cat_status run_stage_plain(Exec& X, const Stage& s) {
     }
   }
   return copy_tails(X, s);
+}
+
+template <class F>
+cat_status capture_graph(F&& rec, hipGraphExec_t* out) {
+  HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+  cat_status s = rec(g.cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
+  if (s != CAT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) {
+    g.last_err = (int)e;
+    return CAT_EDEVICE;
+  }
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g.last_err = (int)e;
+    return CAT_EDEVICE;
+  }
+  return CAT_OK;
 }
 
 cat_status run_phase2(Exec& X, Plan& P, bool plain) {
@@ -1227,6 +1251,71 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
   const bool use_graph = !plain && (flags & CAT_MODE_GRAPH) != 0;
   cat_stats stats{};
   uint64_t launches = 0;
+  unsigned long long* top = (unsigned long long*)(wb + Ly.top);
+  // Fast path: the plan of n is known (it depends only on n).  One graph runs
+  // Phase 1, Phase 2, the normalisation and the copy out; the group table the
+  // device computed is checked against the plan afterwards.
+  auto pit = g.plans.find(n);
+  if (use_graph && pit != g.plans.end() && !pit->second->result_is_one) {
+    Plan* P = pit->second;
+    const std::vector<uintptr_t> key{(uintptr_t)wb, (uintptr_t)d_limbs, (uintptr_t)cap};
+    hipGraphExec_t ge = nullptr;
+    bool replayed = false;
+    auto git = P->full_graphs.find(key);
+    if (git != P->full_graphs.end()) {
+      ge = git->second;
+      replayed = true;
+    } else {
+      uint64_t nl = 0;
+      STCHK(capture_graph(
+          [&](hipStream_t cs) -> cat_status {
+            STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, cs, &nl));
+            Exec E = make_exec(Ly, wb, cs);
+            hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, cs, E.err, (uint64_t)1, 0u);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, cs, (uint32_t*)top, (uint64_t)2, 0u);
+            LAUNCHCHK();
+            STCHK(run_phase2(E, *P, false));
+            const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+            hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, cs, E.W + P->result_pos, P->result_cap,
+                               top);
+            LAUNCHCHK();
+            const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
+            hipLaunchKernelGGL(k_copy, dim3((uint32_t)std::min<uint64_t>((ncopy + 255) / 256, 2048)), dim3(256), 0,
+                               cs, E.W + P->result_pos, d_limbs, ncopy);
+            LAUNCHCHK();
+            nl += E.launches + 4;
+            return CAT_OK;
+          },
+          &ge));
+      P->full_graphs[key] = ge;
+      launches = nl;
+    }
+    HIPCHK(hipGraphLaunch(ge, st));
+    char* pin = (char*)g.pin;
+    HIPCHK(hipMemcpyAsync(pin, wb + Ly.gtab, sizeof(GroupTable), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + 1024, wb + Ly.top, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + 1032, wb + Ly.err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    GroupTable gt;
+    memcpy(&gt, pin, sizeof(GroupTable));
+    uint64_t L = 0;
+    uint32_t derr = 0;
+    memcpy(&L, pin + 1024, 8);
+    memcpy(&derr, pin + 1032, 4);
+    if (gt.err || find_plan(n, gt) != P) return CAT_EINTERNAL;
+    if (derr || L == 0) return CAT_EINTERNAL;
+    *n_limbs = (size_t)L;
+    stats.products = P->products;
+    stats.product_limbs = P->product_limbs;
+    stats.launches = replayed ? 1 : launches;
+    stats.n_primes = gt.off[gt.ngroups];
+    stats.levels = P->levels;
+    stats.graph_replayed = replayed ? 1 : 0;
+    g.stats = stats;
+    if (cap < L) return CAT_ERANGE;
+    return CAT_OK;
+  }
   STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, st, &launches));
   GroupTable gt;
   STCHK(read_groups(Ly, wb, st, &gt));
@@ -1238,7 +1327,6 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
   }
   Exec X = make_exec(Ly, wb, st);
   uint32_t* W = X.W;
-  unsigned long long* top = (unsigned long long*)(wb + Ly.top);
   if (P->result_is_one) {
     if (cap < 1) {
       *n_limbs = 1;
@@ -1258,7 +1346,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
     LAUNCHCHK();
     E.launches += 2;
     STCHK(run_phase2(E, *P, plain));
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 2048);
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
     hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top);
     LAUNCHCHK();
     E.launches++;

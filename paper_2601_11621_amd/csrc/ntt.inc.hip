@@ -518,16 +518,19 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
   }
 }
 
-// Carry-in of every block: cin[b+1] = G_b | (P_b & cin[b]), nothing crosses a
-// segment end.  One workgroup of 1024 threads.
+// Carry fix-up of a CRT launch in one workgroup: the carry into every block is
+// cin[b+1] = G_b | (P_b & cin[b]) (nothing crosses a segment end), found with
+// the wave carry-lookahead 1024 blocks at a time; then each wave adds the
+// carry-in of its blocks: the low limbs equal to 2^32-1 become 0 and the first
+// other limb is incremented (every walk stops at its block end).
 __global__ void __launch_bounds__(1024)
-k_carry_scan(SegView sv, const uint8_t* __restrict__ bsum, uint32_t nblk, uint8_t* __restrict__ cin,
-             uint32_t* __restrict__ err) {
+k_carry_fix(SegView sv, const uint8_t* __restrict__ bsum, uint32_t nblk, uint8_t* __restrict__ cin,
+            uint32_t* __restrict__ out, uint32_t* __restrict__ err) {
   __shared__ uint32_t tmp[32];
   __shared__ uint32_t carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (uint32_t base = 0; base < nblk; base += blockDim.x) {
     const uint32_t b = base + threadIdx.x;
     bool g = false, pr = false, seg_last = false;
@@ -555,13 +558,12 @@ k_carry_scan(SegView sv, const uint8_t* __restrict__ bsum, uint32_t nblk, uint8_
     if (b < nblk) {
       if (b + 1 < nblk) cin[b + 1] = (uint8_t)(gg | (pp & c));
       if (b == 0) cin[0] = 0;
-      // a carry out of the last block of a segment means the product overflowed
       if (seg_last && (g || (pr && c))) atomicOr(err, CAT_DEVERR_CARRY_OUT);
     }
     __syncthreads();
     if (threadIdx.x == blockDim.x - 1) {
       uint32_t cc = carry;
-      for (uint32_t w = 0; w < (blockDim.x >> 6); w++) {
+      for (uint32_t w = 0; w < nw; w++) {
         const uint32_t x = tmp[w];
         cc = (x & 1u) | ((x >> 1) & cc);
       }
@@ -569,32 +571,28 @@ k_carry_scan(SegView sv, const uint8_t* __restrict__ bsum, uint32_t nblk, uint8_
     }
     __syncthreads();
   }
-}
-
-// Adds the carry-in to each block that has one: the low limbs equal to
-// 2^32-1 become 0 and the first other limb is incremented.  One wave per block.
-__global__ void __launch_bounds__(64)
-k_carry_apply(SegView sv, const uint8_t* __restrict__ cin, uint32_t* __restrict__ out) {
-  const uint32_t b = blockIdx.x;
-  if (!cin[b]) return;
-  CrtSeg sg;
-  uint32_t first, end;
-  sv.find(b, &sg, &first, &end);
-  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
-  const uint64_t ke = min(kb + (uint64_t)CAT_CRT_BLOCK, sg.len);
-  uint32_t* o = out + sg.out_pos;
-  const uint32_t lane = threadIdx.x;
-  for (uint64_t k = kb; k < ke; k += 64) {
-    const uint64_t kk = k + lane;
-    const bool in = kk < ke;
-    const uint32_t x = in ? o[kk] : 0u;
-    const uint64_t nz = __ballot(in && x != 0xFFFFFFFFu);
-    if (nz) {
-      const uint32_t f = (uint32_t)__ffsll((unsigned long long)nz) - 1;
-      if (lane < f) o[kk] = 0u;
-      else if (lane == f) o[kk] = x + 1u;
-      return;
+  __threadfence_block();
+  __syncthreads();
+  for (uint32_t b = wid; b < nblk; b += nw) {
+    if (!cin[b]) continue;
+    CrtSeg sg;
+    uint32_t first, end;
+    sv.find(b, &sg, &first, &end);
+    const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
+    const uint64_t ke = min(kb + (uint64_t)CAT_CRT_BLOCK, sg.len);
+    uint32_t* o = out + sg.out_pos;
+    for (uint64_t k = kb; k < ke; k += 64) {
+      const uint64_t kk = k + lane;
+      const bool in = kk < ke;
+      const uint32_t x = in ? o[kk] : 0u;
+      const uint64_t nz = __ballot(in && x != 0xFFFFFFFFu);
+      if (nz) {
+        const uint32_t f = (uint32_t)__ffsll((unsigned long long)nz) - 1;
+        if (lane < f) o[kk] = 0u;
+        else if (lane == f) o[kk] = x + 1u;
+        break;
+      }
+      if (in) o[kk] = 0u;
     }
-    if (in) o[kk] = 0u;
   }
 }

@@ -19,10 +19,10 @@
 // Every group ends up with its primes ascending; G_1 = {seeds with e = 1}
 // followed by the large primes with e = 1.
 
-#define SIEVE_SEG_LOG 18
+#define SIEVE_SEG_LOG 15
 #define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment
 #define SIEVE_WORDS (SIEVE_SEG / 32)
-#define SIEVE_THREADS 1024
+#define SIEVE_THREADS 256
 #define SEED_MAX 6544                           // pi(65535) = 6542
 
 struct GroupTable {
@@ -34,9 +34,10 @@ struct GroupTable {
   uint64_t off[CAT_MAX_GROUPS + 1];
 };
 
-// Exclusive scan over a 1024-thread block (16 wave64s).  tmp: >= 16 words.
+// Exclusive scan over a block of up to 16 wave64s.  tmp: >= 40 words.
 __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* tmp, uint32_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (int)(blockDim.x >> 6);
   uint32_t x = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -46,7 +47,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* t
   if (lane == 63) tmp[wid] = x;
   __syncthreads();
   if (wid == 0) {
-    uint32_t w = lane < 16 ? tmp[lane] : 0;
+    uint32_t w = lane < nw ? tmp[lane] : 0;
     uint32_t t = w;
 #pragma unroll
     for (int d = 1; d < 16; d <<= 1) {
@@ -54,7 +55,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* t
       if (lane >= d) t += y;
     }
     if (lane < 16) tmp[16 + lane] = t - w;    // exclusive wave offsets
-    if (lane == 15) tmp[32] = t;
+    if (lane == nw - 1) tmp[32] = t;
   }
   __syncthreads();
   uint32_t r = tmp[16 + wid] + x - v;
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t
 // ---------------------------------------------------------------------------
 // Segment k covers odd indices i in [i0 + k*SEG, min(i0 + (k+1)*SEG, i_end)),
 // i.e. odd numbers m = 2i+1 in (s, 2n].
-__global__ void __launch_bounds__(1024) k_sieve(uint64_t n, uint64_t i0, uint64_t i_end,
+__global__ void __launch_bounds__(SIEVE_THREADS) k_sieve(uint64_t n, uint64_t i0, uint64_t i_end,
                                                 const uint32_t* seeds, const GroupTable* gt,
                                                 uint32_t* bitmap, uint32_t* seg_cnt) {
   __shared__ uint32_t bits[SIEVE_WORDS];
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(1024) k_sieve(uint64_t n, uint64_t i0, uint64_
   uint32_t k = 1;
   for (; k < nseeds; k++) {
     uint64_t q = seeds[k];
-    if (q * 8 > SIEVE_SEG) break;
+    if (q * SIEVE_THREADS > 2 * SIEVE_SEG) break;   // fewer multiples than 2 per thread
     uint64_t t = (m_lo + q - 1) / q;
     if (t < q) t = q;
     if (!(t & 1)) t++;
@@ -241,7 +242,7 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_scatter(uint64_t i0, const uint32_t* bitmap, const uint32_t* seg_off,
+__global__ void __launch_bounds__(SIEVE_THREADS) k_scatter(uint64_t i0, const uint32_t* bitmap, const uint32_t* seg_off,
                                                   const GroupTable* gt, uint32_t* primes, uint64_t cap) {
   __shared__ uint32_t tmp[40];
   const uint32_t tid = threadIdx.x;

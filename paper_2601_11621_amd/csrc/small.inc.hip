@@ -140,8 +140,11 @@ __global__ void k_copy(const uint32_t* __restrict__ in, uint32_t* __restrict__ o
     out[k] = in[k];
 }
 
-// Highest index with a nonzero limb, +1 (0 if all zero) -> *top (atomicMax).
-__global__ void k_top_nonzero(const uint32_t* __restrict__ x, uint64_t n, unsigned long long* top) {
+// Highest index with a nonzero limb, +1 (0 if all zero) -> *top.  Each block
+// reduces in LDS and issues one atomicMax.
+__global__ void __launch_bounds__(256) k_top_nonzero(const uint32_t* __restrict__ x, uint64_t n,
+                                                     unsigned long long* top) {
+  __shared__ unsigned long long part[4];
   unsigned long long best = 0;
   for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
     if (x[k]) best = k + 1;
@@ -149,7 +152,12 @@ __global__ void k_top_nonzero(const uint32_t* __restrict__ x, uint64_t n, unsign
     unsigned long long o = __shfl_xor(best, d, 64);
     best = o > best ? o : best;
   }
-  if ((threadIdx.x & 63) == 0 && best) atomicMax(top, best);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++) best = part[w] > best ? part[w] : best;
+    if (best) atomicMax(top, best);
+  }
 }
 
 // Fingerprints of a limb vector: x mod (2^32 - 5), x mod (2^32 + 1), x mod (2^32 - 1).

@@ -159,7 +159,7 @@ def test_exact_1e6_vs_oracle(cat):
     assert np.array_equal(got, exp)
 
 
-@pytest.mark.parametrize("n", [10**7])
+@pytest.mark.parametrize("n", [10**7, 10**8])
 def test_exact_full_size_digest(cat, n):
     """Full benchmark size: the SHA-256 of the limbs against the oracle's
     digest (written by tests/golden/make_oracle_golden.py), plus residue pins."""
@@ -172,6 +172,20 @@ def test_exact_full_size_digest(cat, n):
     r = cat.residues(t)
     assert r[0] == gold["mod_2p32_minus_5"]
     assert r[1] == pins.catalan_mod_composite(n, [641, 6700417])
+
+
+def test_exact_graph_replays_are_identical(cat):
+    """The whole-call graph (cached plan) replayed several times, with other
+    work in between, gives the oracle's result every time."""
+    import torch
+
+    n = 250000
+    exp = oracle.catalan(n)
+    for rep in range(4):
+        got = cat.to_numpy(cat.exact(n, mode="graph"))
+        assert np.array_equal(got, exp), rep
+        cat.exact(1000 + rep, mode="graph")          # other n in between
+        torch.cuda.synchronize()
 
 
 def test_residues_kernel(cat):
