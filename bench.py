@@ -36,8 +36,8 @@ BFLY_OPS = 14.0
 PEAK_BFLY = VALU_LANE_OPS / BFLY_OPS
 HBM_PEAK_GBS = 8000.0
 
-CANDIDATES = ["k_row", "k_col_fwd", "k_col_inv", "k_ntt_lds", "k_crt", "k_school", "k_leaf"]
-NTT_KERNELS = {"k_row", "k_col_fwd", "k_col_inv", "k_ntt_lds"}
+CANDIDATES = ["k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds", "k_crt", "k_school", "k_leaf"]
+NTT_KERNELS = {"k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds"}
 
 
 def log(*a):

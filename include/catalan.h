@@ -148,7 +148,7 @@ typedef struct {
 cat_status cat_get_stats(cat_stats* out);
 
 /* Kernel timer (measurement only).  cat_timer_set(name) brackets every later
- * launch of the named kernel ("k_ntt_lds", "k_row", "k_col_fwd", "k_col_inv",
+ * launch of the named kernel ("k_ntt_lds", "k_row", "k_pass_fwd", "k_pass_inv",
  * "k_crt", "k_school", "k_leaf") with HIP events on the stream it is launched
  * on, outside graph capture; NULL or "" stops it.  Each call resets the
  * counters.  cat_timer_get waits for the recorded events and returns the summed

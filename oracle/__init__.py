@@ -75,6 +75,10 @@ def _load():
     lib.orc_set_fault.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_catalan_mod_prime.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.orc_catalan_mod_prime.restype = ctypes.c_uint64
+    lib.orc_catalan_low64.argtypes = [ctypes.c_uint64]
+    lib.orc_catalan_low64.restype = ctypes.c_uint64
     _lib = lib
     return lib
 
@@ -193,6 +197,16 @@ def product(items) -> np.ndarray:
     if st != ORC_OK:
         raise RuntimeError("orc_product failed: %d" % st)
     return out[: ln.value].copy()
+
+
+def catalan_mod_prime(n: int, q: int) -> int:
+    """C(n) mod a prime q > 2n from the factorial definition, O(n)."""
+    return int(_load().orc_catalan_mod_prime(n, q))
+
+
+def catalan_low64(n: int) -> int:
+    """C(n) mod 2^64 from odd-part products and v_2 = popcount(n+1) - 1, O(n)."""
+    return int(_load().orc_catalan_low64(n))
 
 
 def limbs_to_int(limbs) -> int:

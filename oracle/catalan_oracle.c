@@ -430,3 +430,43 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------------
+ * Residues of C(n) straight from the definition C(n) = (2n)!/(n!(n+1)!)
+ * (Sec. 1), in O(n) word operations: used to check results at sizes where a
+ * full product on the CPU would take hours.
+ * ------------------------------------------------------------------------- */
+static uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t q)
+{
+    return (uint64_t)((unsigned __int128)a * b % q);
+}
+static uint64_t powmod_u64(uint64_t b, uint64_t e, uint64_t q)
+{
+    uint64_t r = 1 % q;
+    b %= q;
+    while (e) { if (e & 1) r = mulmod_u64(r, b, q); b = mulmod_u64(b, b, q); e >>= 1; }
+    return r;
+}
+
+/* C(n) mod q for a prime q > 2n: (prod_{k=n+2}^{2n} k) / n! mod q. */
+uint64_t orc_catalan_mod_prime(uint64_t n, uint64_t q)
+{
+    uint64_t num = 1 % q, den = 1 % q;
+    for (uint64_t k = n + 2; k <= 2 * n; k++) num = mulmod_u64(num, k, q);
+    for (uint64_t k = 2; k <= n; k++) den = mulmod_u64(den, k, q);
+    return mulmod_u64(num, powmod_u64(den, q - 2, q), q);
+}
+
+/* C(n) mod 2^64: the power of two is 2^{v}, v = popcount(n+1) - 1 (Kummer);
+ * the odd part is (odd parts of k = n+2..2n) * (odd parts of k = 2..n)^-1. */
+uint64_t orc_catalan_low64(uint64_t n)
+{
+    uint64_t num = 1, den = 1;
+    for (uint64_t k = n + 2; k <= 2 * n; k++) { uint64_t t = k; while (!(t & 1)) t >>= 1; num *= t; }
+    for (uint64_t k = 2; k <= n; k++) { uint64_t t = k; while (!(t & 1)) t >>= 1; den *= t; }
+    /* inverse of an odd number mod 2^64 by Newton's iteration */
+    uint64_t inv = den;
+    for (int i = 0; i < 6; i++) inv *= 2 - den * inv;
+    int v = __builtin_popcountll(n + 1) - 1;
+    return (num * inv) << v;
+}

@@ -30,7 +30,10 @@ struct Lib {
   RootsC roots;
   uint2* tws = nullptr;
   uint2* itws = nullptr;
-  std::map<int, std::pair<uint2*, uint2*>> twn;
+  uint2* tw2lo = nullptr;
+  uint32_t* tw2hi = nullptr;
+  uint2* itw2lo = nullptr;
+  uint32_t* itw2hi = nullptr;
   void* pin = nullptr;          // pinned host staging for small D2H
   int last_err = 0;
   std::recursive_mutex mu;
@@ -190,6 +193,12 @@ cat_status init_locked(int device) {
   HIPCHK(hipMalloc(&g.itws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
   hipLaunchKernelGGL(k_build_tws, dim3(32, CAT_NPRIMES), dim3(256), 0, 0, g.tws, g.itws);
   LAUNCHCHK();
+  HIPCHK(hipMalloc(&g.tw2lo, sizeof(uint2) * TW2_LO * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&g.itw2lo, sizeof(uint2) * TW2_LO * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&g.tw2hi, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&g.itw2hi, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
+  hipLaunchKernelGGL(k_build_tw2, dim3(64, CAT_NPRIMES), dim3(256), 0, 0, g.tw2lo, g.tw2hi, g.itw2lo, g.itw2hi);
+  LAUNCHCHK();
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipHostMalloc(&g.pin, 1 << 16, hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
@@ -197,33 +206,36 @@ cat_status init_locked(int device) {
   return CAT_OK;
 }
 
-cat_status ensure_twn(int logN) {
-  if (logN <= CAT_LDS_LOGT) return CAT_OK;
-  if (g.twn.count(logN)) return CAT_OK;
-  const size_t N = 1ull << logN;
-  uint2 *t = nullptr, *it = nullptr;
-  HIPCHK(hipMalloc(&t, sizeof(uint2) * N * CAT_NPRIMES));
-  HIPCHK(hipMalloc(&it, sizeof(uint2) * N * CAT_NPRIMES));
-  const uint32_t blocks = (uint32_t)std::min<size_t>(N / 256 + 1, 8192);
-  hipLaunchKernelGGL(k_build_twn, dim3(blocks, CAT_NPRIMES), dim3(256), 0, 0, logN, t, it);
-  LAUNCHCHK();
-  HIPCHK(hipDeviceSynchronize());
-  g.twn[logN] = {t, it};
-  return CAT_OK;
-}
-
 NttTables tables_for(int logN) {
+  (void)logN;
   NttTables tb;
   tb.tws = g.tws;
   tb.itws = g.itws;
-  tb.twn = nullptr;
-  tb.itwn = nullptr;
-  auto it = g.twn.find(logN);
-  if (it != g.twn.end()) {
-    tb.twn = it->second.first;
-    tb.itwn = it->second.second;
-  }
+  tb.tw2lo = g.tw2lo;
+  tb.tw2hi = g.tw2hi;
+  tb.itw2lo = g.itw2lo;
+  tb.itw2hi = g.itw2hi;
   return tb;
+}
+
+// Pass decomposition of a large transform: N = L_0 ... L_{P-1} * 2^12 with
+// every L_p <= 2^10 (so a tile of L_p x C words with C >= 16 fits 64 KB).
+struct PassPlan {
+  int P = 0;
+  int logL[4] = {}, logS[4] = {}, logC[4] = {};
+};
+PassPlan pass_plan(int logN) {
+  PassPlan pp;
+  const int rest = logN - CAT_LDS_LOGT;
+  pp.P = (rest + 9) / 10;
+  int ls = logN;
+  for (int k = 0; k < pp.P; k++) {
+    pp.logL[k] = rest / pp.P + (k < rest % pp.P ? 1 : 0);
+    pp.logS[k] = ls;
+    pp.logC[k] = std::min(14 - pp.logL[k], ls - pp.logL[k]);
+    ls -= pp.logL[k];
+  }
+  return pp;
 }
 
 // scale constant 2^32 * N^-1 (Montgomery pair): the pointwise product
@@ -693,9 +705,6 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
     free_plan(P);
     return CAT_EINTERNAL;
   }
-  // twiddle tables needed by the large classes
-  for (Stage* s : all)
-    if (s->cls == CLS_LARGE) STCHK(ensure_twn(s->logN));
   cat_status st = upload_tables(all, &P->dev);
   if (st != CAT_OK) {
     free_plan(P);
@@ -771,34 +780,35 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
     X.launches++;
     return CAT_OK;
   }
-  if (!tb.twn) return CAT_EINTERNAL;
+  const PassPlan pp = pass_plan(s.logN);
   const int logM = CAT_LDS_LOGT, logR1 = s.logN - logM;
-  int logC = 14 - logR1;
-  if (logC > logM) logC = logM;
-  if (logC < 0) return CAT_EINVAL;
-  const uint64_t tiles = 1ull << (logM - logC);
-  const double rows = (double)cnt * (1ull << logR1), cols = (double)cnt * (1ull << logM);
-  {
-    // column DFTs of both operands, 3 primes
-    KTime kt("k_col_fwd", X.st, bfly(6.0 * cols, logR1));
-    hipLaunchKernelGGL(k_col_fwd, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                       s.logN, logC, ain, bin, X.F, tb);
+  const double N = (double)(1ull << s.logN);
+  for (int k = 0; k < pp.P; k++) {
+    PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
+    const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
+    // L-point DFTs of both operands, 3 primes: (N/2) log2 L butterflies each
+    KTime kt("k_pass_fwd", X.st, 6.0 * cnt * N / 2 * pp.logL[k]);
+    hipLaunchKernelGGL(k_pass_fwd, dim3((uint32_t)gx, CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st, dv, pg,
+                       k == 0 ? 1 : 0, ain, bin, X.F, tb);
+    LAUNCHCHK();
   }
-  LAUNCHCHK();
   {
     // row DFTs: two forward and one inverse per row, 3 primes
+    const double rows = (double)cnt * (1ull << logR1);
     KTime kt("k_row", X.st, bfly(9.0 * rows, logM));
     hipLaunchKernelGGL(k_row, dim3((uint32_t)(cnt << logR1), CAT_NPRIMES), dim3(NTT_ROW_THREADS), 0, X.st, s.logN,
                        X.F, tb, s0, s1, s2);
   }
   LAUNCHCHK();
-  {
-    KTime kt("k_col_inv", X.st, bfly(3.0 * cols, logR1));
-    hipLaunchKernelGGL(k_col_inv, dim3((uint32_t)(cnt * tiles), CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                       s.logN, logC, X.F, X.res, X.res_stride, tb);
+  for (int k = pp.P - 1; k >= 0; k--) {
+    PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
+    const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
+    KTime kt("k_pass_inv", X.st, 3.0 * cnt * N / 2 * pp.logL[k]);
+    hipLaunchKernelGGL(k_pass_inv, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv, pg,
+                       k == 0 ? 1 : 0, X.F, X.res, X.res_stride, tb);
+    LAUNCHCHK();
   }
-  LAUNCHCHK();
-  X.launches += 3;
+  X.launches += 2 * pp.P + 1;
   return CAT_OK;
 }
 
@@ -1052,11 +1062,6 @@ cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t
   M->total = off;
   std::vector<Stage*> all;
   for (auto& st : M->stages) all.push_back(&st);
-  for (Stage* st : all)
-    if (st->cls == CLS_LARGE) {
-      cat_status e = ensure_twn(st->logN);
-      if (e != CAT_OK) { delete M; return e; }
-    }
   cat_status e = upload_tables(all, &M->dev);
   if (e != CAT_OK) { delete M; return e; }
   *out = M;

@@ -12,13 +12,15 @@
 //    product does not care about; the inverse runs the passes backwards with
 //    inverse roots (decimation-in-time networks), which undoes the order.
 //  * N <= 2^12 products run entirely in one workgroup (k_ntt_lds).
-//  * Larger N = R1 * M with M = 2^12 use the four-step split (Bailey 1990):
-//    k_col_fwd transforms the R1-point columns (packing limbs on the fly) and
-//    applies omega_N^{col*k1}; k_row transforms each M-point row of both
+//  * Larger N = L_0 ... L_{P-1} * M with M = 2^12 use Bailey's four-step
+//    split (1990) applied recursively: k_pass_fwd transforms the strided
+//    columns of one level of the split (packing limbs on the fly in the first)
+//    and applies its twiddles; k_row transforms each M-point row of both
 //    operands, multiplies them pointwise and inverse-transforms the row;
-//    k_col_inv undoes the column step and writes exact residues.
-//  * Twiddles are (w, wq) Montgomery pairs in tables laid out so that
-//    neighbouring lanes read neighbouring entries.
+//    k_pass_inv undoes the column levels, the outermost writing exact residues.
+//  * In-pass twiddles are (w, wq) Montgomery pairs in tables laid out so that
+//    neighbouring lanes read neighbouring entries; the column-level twiddles
+//    omega_S^{j*f} come from two small tables of omega_{2^27} powers.
 // The residues of the three primes are then recombined by k_crt (Garner's
 // method) into 96-bit coefficient values, summed into limbs and carried with
 // a wave64 ballot carry-lookahead; blocks of one product are joined by
@@ -202,11 +204,28 @@ __device__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t l
   }
 }
 
+// frequency held at output position q of the pass-structured transform of size 2^logS
+__device__ __forceinline__ uint32_t out_freq(uint32_t q, int logS) {
+  uint32_t f = 0, mult = 1;
+  while (logS > 0) {
+    const int r = pass_logr(logS);
+    const int rest = logS - r;
+    const uint32_t k1 = q >> rest;
+    f += k1 * mult;
+    mult <<= r;
+    q &= (1u << rest) - 1;
+    logS = rest;
+  }
+  return f;
+}
+
 struct NttTables {
-  const uint2* tws;    // [prime][TWS_ENTRIES] forward pass tables
-  const uint2* itws;   // [prime][TWS_ENTRIES] inverse
-  const uint2* twn;    // [prime][N]   four-step twiddles (large N only)
-  const uint2* itwn;
+  const uint2* tws;       // [prime][TWS_ENTRIES] forward pass tables
+  const uint2* itws;      // [prime][TWS_ENTRIES] inverse
+  const uint2* tw2lo;     // [prime][2^14] omega_{2^27}^i, Montgomery pairs
+  const uint32_t* tw2hi;  // [prime][2^13] omega_{2^27}^{i*2^14}, Montgomery form
+  const uint2* itw2lo;    // inverse roots
+  const uint32_t* itw2hi;
 };
 
 // ---------------------------------------------------------------------------
@@ -267,44 +286,126 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
 }
 
 // ---------------------------------------------------------------------------
-// Four-step path, N = R1 * M, M = 2^12, R1 = 2^logR1.
+// Large N: N = L_0 * L_1 * ... * L_{P-1} * M, M = 2^12 (Bailey's four-step,
+// applied recursively).  Pass p works on contiguous sub-problems of size S_p
+// (S_0 = N, S_{p+1} = S_p / L_p): the L_p-point DFT along the outermost
+// dimension (stride sigma = S_p / L_p) of each sub-problem, then the twiddle
+// omega_{S_p}^{j * f(q)} (j < sigma the inner index, f(q) the frequency at
+// output position q).  The last M-point transforms (k_row) run on rows.
+// A workgroup holds an L x C tile (C consecutive inner indices) in LDS.
 // Scratch F: per product, per prime, per operand N words:
-//   F[((m*3 + prime)*2 + op)*N + q*M + col]
+//   F[((m*3 + prime)*2 + op)*N + position]
 #define NTT_COL_THREADS 256
 #define NTT_COL_TILE 16384u     // LDS words of a column tile
+#define TW2_LO_BITS 14u
+#define TW2_LO (1u << TW2_LO_BITS)
+#define TW2_HI (1u << (CAT_MAX_LOGN - TW2_LO_BITS))
+
+// omega_{2^27}^y (or its inverse) as a Montgomery pair from the two-level
+// tables lo[y mod 2^14] (pairs) and hi[y >> 14] (Montgomery form).
+__device__ __forceinline__ uint2 tw2(const uint2* __restrict__ lo, const uint32_t* __restrict__ hi, uint32_t y,
+                                     const PrimeC& pc) {
+  const uint2 l = lo[y & (TW2_LO - 1)];
+  const uint32_t w = mul_tw(hi[y >> TW2_LO_BITS], l.x, l.y, pc.p);
+  return make_uint2(w, w * pc.pinv);
+}
+
+struct PassGeom {
+  int logN, logS, logL, logC;
+  __device__ __forceinline__ void locate(uint64_t bx, uint64_t* m, uint64_t* base, uint32_t* j0) const {
+    const int logSig = logS - logL;
+    const uint64_t tiles = 1ull << (logSig - logC);          // tiles per sub-problem
+    const uint64_t blocks = 1ull << (logN - logS);           // sub-problems per product
+    *m = bx / (blocks * tiles);
+    const uint64_t r = bx - *m * blocks * tiles;
+    const uint64_t blk = r / tiles;
+    *base = blk << logS;
+    *j0 = (uint32_t)((r - blk * tiles) << logC);
+  }
+};
 
 __global__ void __launch_bounds__(NTT_COL_THREADS)
-k_col_fwd(DescView dv, int logN, int logC, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
-          uint32_t* __restrict__ F, NttTables tb) {
+k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
+           uint32_t* __restrict__ F, NttTables tb) {
   __shared__ uint32_t lds[NTT_COL_TILE];
   const uint32_t prime = blockIdx.y, op = blockIdx.z;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
-  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
-  const uint32_t M = 1u << logM, C = 1u << logC;
-  const uint32_t tiles = M >> logC;
-  const uint64_t m = blockIdx.x / tiles;
-  const uint32_t col0 = (blockIdx.x % tiles) << logC;
-  const MulDesc d = dv.get(m);
-  const uint32_t* src = op ? bin + d.b_off : ain + d.a_off;
-  const uint32_t len = op ? d.lb : d.la;
-  const uint32_t T = 1u << (logR1 + logC);
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t q = t >> logC, c = t & (C - 1);
-    const uint32_t idx = (q << logM) + col0 + c;
-    lds[t] = idx < len ? reduce_limb(src[idx], p) : 0u;
+  uint64_t m, base;
+  uint32_t j0;
+  pg.locate(blockIdx.x, &m, &base, &j0);
+  const int logSig = pg.logS - pg.logL;
+  const uint32_t C = 1u << pg.logC;
+  const uint64_t N = 1ull << pg.logN;
+  const uint32_t T = 1u << (pg.logL + pg.logC);
+  uint32_t* f = F + ((m * 3 + prime) * 2 + op) * N;
+  if (first) {
+    const MulDesc d = dv.get(m);
+    const uint32_t* src = op ? bin + d.b_off : ain + d.a_off;
+    const uint64_t len = op ? d.lb : d.la;
+    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+      const uint64_t idx = base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1));
+      lds[t] = idx < len ? reduce_limb(src[idx], p) : 0u;
+    }
+  } else {
+    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
+      lds[t] = f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))];
   }
   __syncthreads();
-  ntt_fwd_tile<false>(lds, logR1, T, (uint32_t)logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
-  const uint64_t N = 1ull << logN;
-  const uint2* twn = tb.twn + (size_t)prime * N;
-  uint32_t* dst = F + ((m * 3 + prime) * 2 + op) * N;
+  ntt_fwd_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
+  const uint2* lo = tb.tw2lo + (size_t)prime * TW2_LO;
+  const uint32_t* hi = tb.tw2hi + (size_t)prime * TW2_HI;
+  const uint64_t smask = (1ull << pg.logS) - 1;
   for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t q = t >> logC, c = t & (C - 1);
-    const uint64_t at = ((uint64_t)q << logM) + col0 + c;
-    const uint2 w = twn[at];
-    dst[at] = mul_tw(lds[t], w.x, w.y, p);
+    const uint32_t q = t >> pg.logC, j = j0 + (t & (C - 1));
+    const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
+    const uint2 w = tw2(lo, hi, (uint32_t)(e << (CAT_MAX_LOGN - pg.logS)), pc);
+    f[base + ((uint64_t)q << logSig) + j] = mul_tw(lds[t], w.x, w.y, p);
   }
+}
+
+__global__ void __launch_bounds__(NTT_COL_THREADS)
+k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_t* __restrict__ res,
+           uint64_t res_stride, NttTables tb) {
+  __shared__ uint32_t lds[NTT_COL_TILE];
+  const uint32_t prime = blockIdx.y;
+  const PrimeC& pc = c_primes[prime];
+  const uint32_t p = pc.p;
+  uint64_t m, base;
+  uint32_t j0;
+  pg.locate(blockIdx.x, &m, &base, &j0);
+  const int logSig = pg.logS - pg.logL;
+  const uint32_t C = 1u << pg.logC;
+  const uint64_t N = 1ull << pg.logN;
+  const uint32_t T = 1u << (pg.logL + pg.logC);
+  uint32_t* f = F + ((m * 3 + prime) * 2 + 0) * N;
+  const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
+  const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
+  const uint64_t smask = (1ull << pg.logS) - 1;
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t q = t >> pg.logC, j = j0 + (t & (C - 1));
+    const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
+    const uint2 w = tw2(lo, hi, (uint32_t)(e << (CAT_MAX_LOGN - pg.logS)), pc);
+    lds[t] = mul_tw(f[base + ((uint64_t)q << logSig) + j], w.x, w.y, p);
+  }
+  __syncthreads();
+  ntt_inv_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  if (!last) {
+    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
+      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+    return;
+  }
+  // the outermost pass: positions are coefficient indices; write exact residues
+  const MulDesc d = dv.get(m);
+  uint32_t* out = res + (size_t)prime * res_stride + d.r_off;
+  const uint64_t L = (uint64_t)d.la + d.lb;
+  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint64_t j = base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1));
+    if (j < L) out[j] = lds[t];
+  }
+  // coefficient positions in [N, L) (only when L = N + 1) are zero
+  if (base == 0 && j0 == 0)
+    for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
 }
 
 #define NTT_ROW_THREADS 256
@@ -336,43 +437,6 @@ k_row(int logN, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scal
   __syncthreads();
   ntt_inv_tile<true>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) fa[t] = lds[lds_pad(t)];
-}
-
-__global__ void __launch_bounds__(NTT_COL_THREADS)
-k_col_inv(DescView dv, int logN, int logC, const uint32_t* __restrict__ F, uint32_t* __restrict__ res,
-          uint64_t res_stride, NttTables tb) {
-  __shared__ uint32_t lds[NTT_COL_TILE];
-  const uint32_t prime = blockIdx.y;
-  const PrimeC& pc = c_primes[prime];
-  const uint32_t p = pc.p;
-  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
-  const uint32_t M = 1u << logM, C = 1u << logC;
-  const uint32_t tiles = M >> logC;
-  const uint64_t m = blockIdx.x / tiles;
-  const uint32_t col0 = (blockIdx.x % tiles) << logC;
-  const MulDesc d = dv.get(m);
-  const uint64_t N = 1ull << logN;
-  const uint32_t* src = F + ((m * 3 + prime) * 2 + 0) * N;
-  const uint2* itwn = tb.itwn + (size_t)prime * N;
-  const uint32_t T = 1u << (logR1 + logC);
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t q = t >> logC, c = t & (C - 1);
-    const uint64_t at = ((uint64_t)q << logM) + col0 + c;
-    const uint2 w = itwn[at];
-    lds[t] = mul_tw(src[at], w.x, w.y, p);
-  }
-  __syncthreads();
-  ntt_inv_tile<false>(lds, logR1, T, (uint32_t)logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
-  uint32_t* out = res + (size_t)prime * res_stride + d.r_off;
-  const uint64_t L = (uint64_t)d.la + d.lb;
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t q = t >> logC, c = t & (C - 1);
-    const uint64_t j = ((uint64_t)q << logM) + col0 + c;
-    if (j < L) out[j] = lds[t];
-  }
-  // coefficient positions in [N, L) (only when L = N + 1) are zero
-  if (blockIdx.x % tiles == 0)
-    for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
 }
 
 // ---------------------------------------------------------------------------

@@ -222,33 +222,20 @@ __global__ void k_build_tws(uint2* __restrict__ tws, uint2* __restrict__ itws) {
   }
 }
 
-// frequency held at output position q of the pass-structured transform of size 2^logS
-__device__ __forceinline__ uint32_t out_freq(uint32_t q, int logS) {
-  uint32_t f = 0, mult = 1;
-  while (logS > 0) {
-    const int r = pass_logr(logS);
-    const int rest = logS - r;
-    const uint32_t k1 = q >> rest;
-    f += k1 * mult;
-    mult <<= r;
-    q &= (1u << rest) - 1;
-    logS = rest;
-  }
-  return f;
-}
-
-// Four-step tables for N = 2^logN = R1 * M: entry q*M + col = omega_N^{+-col*freq(q)}.
-__global__ void k_build_twn(int logN, uint2* __restrict__ twn, uint2* __restrict__ itwn) {
+// Two-level tables of omega_{2^27}: lo[i] = omega^i (i < 2^14, Montgomery
+// pairs), hi[i] = omega^{i*2^14} (i < 2^13, Montgomery form); and the inverse.
+__global__ void k_build_tw2(uint2* __restrict__ lo, uint32_t* __restrict__ hi, uint2* __restrict__ ilo,
+                            uint32_t* __restrict__ ihi) {
   const uint32_t prime = blockIdx.y;
   const uint32_t p = c_primes[prime].p, pinv = c_primes[prime].pinv;
-  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
-  const uint64_t N = 1ull << logN;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t q = (uint32_t)(i >> logM), col = (uint32_t)(i & ((1u << logM) - 1));
-    const uint64_t e = ((uint64_t)col * out_freq(q, logR1)) & (N - 1);
-    const uint32_t w = mont_pow(c_roots.r[prime][logN], e, c_roots.one[prime], p, pinv);
-    const uint32_t iw = mont_pow(c_roots.ir[prime][logN], e, c_roots.one[prime], p, pinv);
-    twn[(size_t)prime * N + i] = tw_pair(w, pinv);
-    itwn[(size_t)prime * N + i] = tw_pair(iw, pinv);
+  const uint32_t one = c_roots.one[prime];
+  const uint32_t r = c_roots.r[prime][CAT_MAX_LOGN], ir = c_roots.ir[prime][CAT_MAX_LOGN];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < TW2_LO; i += gridDim.x * blockDim.x) {
+    lo[(size_t)prime * TW2_LO + i] = tw_pair(mont_pow(r, i, one, p, pinv), pinv);
+    ilo[(size_t)prime * TW2_LO + i] = tw_pair(mont_pow(ir, i, one, p, pinv), pinv);
+    if (i < TW2_HI) {
+      hi[(size_t)prime * TW2_HI + i] = mont_pow(r, (uint64_t)i << TW2_LO_BITS, one, p, pinv);
+      ihi[(size_t)prime * TW2_HI + i] = mont_pow(ir, (uint64_t)i << TW2_LO_BITS, one, p, pinv);
+    }
   }
 }

@@ -185,5 +185,27 @@ def limbs_mod(limbs, q: int) -> int:
     return r
 
 
+def limbs_mod_small(limbs, q: int, chunk: int = 1 << 20) -> int:
+    """Value of LE uint32 limbs modulo a small q (q < 2^20), vectorised:
+    per chunk sum(limb_i * B^i) mod q with B = 2^32 mod q, chunks joined by
+    Horner steps with B^chunk."""
+    assert q < (1 << 20)
+    x = np.ascontiguousarray(limbs, dtype=np.uint64) % q
+    base = (1 << 32) % q
+    pw = np.empty(chunk, dtype=np.uint64)
+    v = 1
+    for i in range(chunk):
+        pw[i] = v
+        v = v * base % q
+    step = pow(base, chunk, q)
+    acc = 0
+    nch = (len(x) + chunk - 1) // chunk
+    for c in range(nch - 1, -1, -1):
+        part = x[c * chunk:(c + 1) * chunk]
+        r = int(np.sum((part * pw[: len(part)]) % q) % q)
+        acc = (acc * step + r) % q
+    return acc
+
+
 def catalan_comb(n: int) -> int:
     return math.comb(2 * n, n) // (n + 1)

@@ -242,3 +242,18 @@ def test_pins_reject_planted_mistakes(fault):
         assert bad
     finally:
         oracle.set_fault(0)
+
+
+# ------------------------------------------------------------------ large-n residue routines
+def test_residue_routines_match_python_definitions():
+    """The O(n) C routines used to check the largest n agree with the Python
+    forms and with exact integers."""
+    for n in [0, 1, 2, 3, 10, 77, 1000, 12345]:
+        c = pins.catalan_comb(n)
+        for q in [2**32 - 5, 4294967311, 2**61 - 1]:
+            if q > 2 * n:
+                assert oracle.catalan_mod_prime(n, q) == c % q
+        assert oracle.catalan_low64(n) == c % (1 << 64)
+    n = 10**5
+    assert oracle.catalan_mod_prime(n, 2**32 - 5) == pins.catalan_mod_prime_product(n, 2**32 - 5)
+    assert oracle.catalan_low64(n) == pins.catalan_low64(n)
