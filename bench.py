@@ -164,6 +164,55 @@ def batch_bench(cat, steps):
             "inputs": "numpy default_rng(0): la, lb = rint(2**U(6,16)) x 4096 each, limbs U[0,2^32)"}
 
 
+def serving_bench(cat, count=1100, warm=100, slots=8, budget=16 << 30, frac=0.7):
+    """Request stream of catalan_exact(n), n = floor(10^(3 + 4u)) from
+    default_rng(11621): closed-loop saturation first, then Poisson arrivals at
+    `frac` of that rate; p50/p99 latency (arrival -> result on the device) and
+    requests/s over the requests after the first `warm`; every output compared
+    bit for bit with the same n computed alone."""
+    import numpy as np
+
+    from paper_2601_11621_amd.serve import DONE, GpuExecutor, Server
+    from tests import batch_inputs
+
+    ns, gaps = batch_inputs.serving_requests(seed=11621, count=count)
+    ns = [int(x) for x in ns]
+    ex = GpuExecutor(max_slots=slots)
+    # closed loop: everything queued at once
+    srv = Server(ex, budget_bytes=budget, max_slots=slots)
+    for n in ns:
+        srv.submit(n, arrival=0.0)
+    t0 = time.perf_counter()
+    srv.run()
+    sat = len(ns) / (time.perf_counter() - t0)
+    # open loop at frac * saturation
+    lam = frac * sat
+    srv = Server(ex, budget_bytes=budget, max_slots=slots)
+    start = time.perf_counter() + 0.05
+    arr = start + np.cumsum(gaps) / lam
+    reqs = [srv.submit(n, arrival=float(a)) for n, a in zip(ns, arr)]
+    srv.run()
+    st = srv.stats(skip=warm)
+    bad = 0
+    solo = {}
+    for r in reqs:
+        if r.state != DONE:
+            bad += 1
+            continue
+        if r.n not in solo:
+            solo[r.n] = cat.to_numpy(cat.exact(r.n, mode="batched"))
+        if not np.array_equal(cat.to_numpy(r.result), solo[r.n]):
+            bad += 1
+    if bad:
+        raise SystemExit("bench: %d serving outputs differ from the same n alone" % bad)
+    return {"requests": count, "warmup_requests": warm, "slots": slots, "budget_bytes": budget,
+            "saturated_req_per_s": round(sat, 1), "offered_req_per_s": round(lam, 1),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
+            "req_per_s": round(st["req_per_s"], 1), "peak_active": st["peak_active"],
+            "all_outputs_equal_solo": True,
+            "inputs": "n = floor(10^(3+4u)), Poisson arrivals, numpy default_rng(11621)"}
+
+
 def cpu_baseline(n, product_limbs):
     import oracle
 
@@ -194,6 +243,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-product level-batch measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--only-kernel", default="", help="profiling aid: run graph steps only")
@@ -291,6 +341,10 @@ def main():
     batch = None if args.no_batch else batch_bench(cat, max(3, args.steps // 4))
     if batch:
         log("bench: level-batch 4096: graph %.2f ms, plain %.1f ms" % (batch["batched_graph_ms"], batch["plain_ms"]))
+    serving = None if args.no_serving else serving_bench(cat)
+    if serving:
+        log("bench: serving p50 %.2f ms p99 %.2f ms %.0f req/s" % (serving["p50_ms"], serving["p99_ms"],
+                                                                  serving["req_per_s"]))
     cpu = None if args.no_cpu else cpu_baseline(n, product_limbs)
 
     line = {
@@ -316,6 +370,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "level_batch_4096": batch,
+        "serving": serving,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()} if kt else None,
         "paper_context": {"wall_s_n1e7": 6.817, "hardware": "AMD Ryzen 9 4900HS laptop, Python 3.11 + gmpy2 "
                                                             "(Table 2, proposed algorithm)"},

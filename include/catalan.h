@@ -41,7 +41,8 @@ enum {
   CAT_ERANGE = -2,     /* a caller capacity is too small; the *needed output is set */
   CAT_ENOMEM = -3,     /* workspace too small, or a library allocation failed */
   CAT_EDEVICE = -4,    /* HIP runtime error; see cat_last_device_error() */
-  CAT_EINTERNAL = -5   /* a device-side invariant failed (negative exponent, carry out of a product) */
+  CAT_EINTERNAL = -5,  /* a device-side invariant failed (negative exponent, carry out of a product) */
+  CAT_EAGAIN = -6      /* cat_ticket_query: the queued work has not finished yet */
 };
 
 #define CAT_N_MAX 2147483647ull   /* 2n < 2^32, so primes fit in uint32 */
@@ -109,6 +110,29 @@ cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_li
                          size_t work_bytes, void* stream);
 cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
                             size_t work_bytes, void* stream, uint32_t flags);
+
+/* Asynchronous C(n), for request loops that keep many computations in
+ * flight on several streams (every call returns without waiting for the GPU):
+ *  catalan_begin    queues Phase 1 of n on `stream` in d_work (sized by
+ *                   catalan_sizes) and returns a ticket;
+ *  cat_ticket_query CAT_OK once the ticket's queued work has finished,
+ *                   CAT_EAGAIN before;
+ *  catalan_continue after Phase 1 finished: plans Phase 2 from the group
+ *                   counts (host only, no device allocation) and queues it with
+ *                   the normalisation and the copy of up to `cap` limbs of C(n)
+ *                   into d_limbs (limbs past *n_limbs are zero);
+ *  catalan_end      after Phase 2 finished: returns the limb count, checks the
+ *                   device error word and releases the ticket (CAT_ERANGE if
+ *                   cap was too small);
+ *  cat_ticket_release drops a ticket at any point (waits for its work).
+ * d_work and d_limbs must stay untouched until catalan_end.  The same results
+ * as catalan_exact, bit for bit. */
+typedef struct cat_ticket_s* cat_ticket;
+cat_status catalan_begin(uint64_t n, void* d_work, size_t work_bytes, void* stream, cat_ticket* ticket);
+cat_status cat_ticket_query(cat_ticket ticket);
+cat_status catalan_continue(cat_ticket ticket, uint32_t* d_limbs, size_t cap);
+cat_status catalan_end(cat_ticket ticket, size_t* n_limbs);
+cat_status cat_ticket_release(cat_ticket ticket);
 
 /* Reusable plans for repeated batches of the same shape (the batched form
  * of a tree level).  cat_mul_plan_create buckets the products by transform

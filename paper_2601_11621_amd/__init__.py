@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcatalan.so")
 
-CAT_OK, CAT_EINVAL, CAT_ERANGE, CAT_ENOMEM, CAT_EDEVICE, CAT_EINTERNAL = 0, -1, -2, -3, -4, -5
+CAT_OK, CAT_EINVAL, CAT_ERANGE, CAT_ENOMEM, CAT_EDEVICE, CAT_EINTERNAL, CAT_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 MODE_BATCHED, MODE_PLAIN, MODE_GRAPH = 0, 1, 2
 _MODES = {"batched": MODE_BATCHED, "plain": MODE_PLAIN, "graph": MODE_BATCHED | MODE_GRAPH}
 MAX_GROUPS = 32
@@ -29,6 +29,7 @@ EXPORTS = [
     "catalan_factor", "bigint_mul_workspace", "bigint_mul_batched", "bigint_mul_batched_ex",
     "catalan_exact", "catalan_exact_ex", "cat_mul_plan_create", "cat_mul_plan_exec",
     "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues", "cat_timer_set", "cat_timer_get",
+    "catalan_begin", "cat_ticket_query", "catalan_continue", "catalan_end", "cat_ticket_release",
 ]
 
 
@@ -93,6 +94,11 @@ def load(path: str = LIB_PATH):
         "bigint_residues": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
         "cat_timer_set": ([ctypes.c_char_p], st),
         "cat_timer_get": ([ctypes.POINTER(ctypes.c_double), u64p, ctypes.POINTER(ctypes.c_double)], st),
+        "catalan_begin": ([ctypes.c_uint64, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+        "cat_ticket_query": ([vp], st),
+        "catalan_continue": ([vp, vp, ctypes.c_size_t], st),
+        "catalan_end": ([vp, szp], st),
+        "cat_ticket_release": ([vp], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -97,11 +97,16 @@ struct TreeLevel {
   uint64_t mpref[CAT_MAX_GROUPS + 1];   // prefix count of products per group
 };
 
+#define CAT_INLINE_DESC 16
+
 struct DescView {
-  const MulDesc* table;  // nullptr => tree mode
-  TreeLevel tree;
+  const MulDesc* table;  // device table (large explicit batches), or
+  uint32_t ninl;         // > 0: explicit descriptors carried in the kernel arguments, or
+  MulDesc inl[CAT_INLINE_DESC];
+  TreeLevel tree;        // tree mode
   __device__ __forceinline__ MulDesc get(uint64_t i) const {
     if (table) return table[i];
+    if (ninl) return inl[i];
     uint32_t g = 0;
     while (g + 1 < tree.ngroups && i >= tree.mpref[g + 1]) g++;
     uint64_t il = i - tree.mpref[g];

@@ -276,8 +276,7 @@ struct Stage {
   // CRT (NTT classes)
   std::vector<CrtSeg> host_segs;
   std::vector<uint32_t> host_pref;
-  const CrtSeg* segs = nullptr;
-  const uint32_t* blk_pref = nullptr;
+  SegView sv{};            // CRT segments (inline or device tables), set by upload_tables
   uint32_t nseg = 0, nblk = 0;
   bool need_fix = false;
   // carried-up nodes
@@ -524,12 +523,28 @@ void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vecto
   }
   for (auto& kv : by) {
     Stage& s = kv.second;
-    s.nmul = s.host_desc.size();
-    s.a_base = s.b_base = s.c_base = 0;
-    build_crt_segs(s);
-    P.products += s.nmul;
-    P.product_limbs += s.limbs;
-    P.post.push_back(s);
+    // split into stages of at most CAT_INLINE_DESC products (kernel-argument tables)
+    for (size_t k0 = 0; k0 < s.host_desc.size(); k0 += CAT_INLINE_DESC) {
+      Stage t;
+      t.cls = s.cls;
+      t.logN = s.logN;
+      const size_t k1 = std::min(s.host_desc.size(), k0 + CAT_INLINE_DESC);
+      uint64_t r = 0;
+      for (size_t k = k0; k < k1; k++) {
+        MulDesc d = s.host_desc[k];
+        d.r_off = r;
+        r += (uint64_t)d.la + d.lb;
+        t.host_desc.push_back(d);
+        t.host_segs.push_back(CrtSeg{d.c_off, d.r_off, (uint64_t)d.la + d.lb});
+        t.limbs += (uint64_t)d.la + d.lb;
+      }
+      t.nmul = t.host_desc.size();
+      t.a_base = t.b_base = t.c_base = 0;
+      build_crt_segs(t);
+      P.products += t.nmul;
+      P.product_limbs += t.limbs;
+      P.post.push_back(t);
+    }
   }
 }
 
@@ -624,36 +639,53 @@ void plan_post(const Layout& Ly, Plan& P, uint64_t root_pos) {
   P.post_end = bump;
 }
 
-// Upload the device tables of every stage of the plan into one buffer.
+// Descriptor and segment tables: carried inline in the kernel arguments when
+// small (every catalan plan), otherwise uploaded to one device buffer (large
+// generic batches).  *dev stays nullptr when nothing needs device memory.
 cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
   size_t bytes = 0;
   for (Stage* s : all) {
-    bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
-    bytes = align_up(bytes, 16) + s->host_segs.size() * sizeof(CrtSeg);
-    bytes = align_up(bytes, 16) + s->host_pref.size() * sizeof(uint32_t);
+    if (s->host_desc.size() > CAT_INLINE_DESC) bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
+    if (s->host_segs.size() > CAT_INLINE_SEG) {
+      bytes = align_up(bytes, 16) + s->host_segs.size() * sizeof(CrtSeg);
+      bytes = align_up(bytes, 16) + s->host_pref.size() * sizeof(uint32_t);
+    }
   }
-  bytes = std::max<size_t>(bytes, 64);
-  std::vector<char> h(bytes, 0);
   char* d = nullptr;
-  HIPCHK(hipMalloc(&d, bytes));
+  std::vector<char> h(std::max<size_t>(bytes, 16), 0);
+  if (bytes) HIPCHK(hipMalloc(&d, bytes));
   size_t o = 0;
   for (Stage* s : all) {
-    o = align_up(o, 16);
+    s->dv.ninl = 0;
     if (!s->host_desc.empty()) {
-      memcpy(&h[o], s->host_desc.data(), s->host_desc.size() * sizeof(MulDesc));
-      s->dv.table = (const MulDesc*)(d + o);
+      if (s->host_desc.size() > CAT_INLINE_DESC) {
+        o = align_up(o, 16);
+        memcpy(&h[o], s->host_desc.data(), s->host_desc.size() * sizeof(MulDesc));
+        s->dv.table = (const MulDesc*)(d + o);
+        o += s->host_desc.size() * sizeof(MulDesc);
+      } else {
+        s->dv.table = nullptr;
+        s->dv.ninl = (uint32_t)s->host_desc.size();
+        for (size_t k = 0; k < s->host_desc.size(); k++) s->dv.inl[k] = s->host_desc[k];
+      }
     }
-    o += s->host_desc.size() * sizeof(MulDesc);
-    o = align_up(o, 16);
-    if (!s->host_segs.empty()) memcpy(&h[o], s->host_segs.data(), s->host_segs.size() * sizeof(CrtSeg));
-    s->segs = (const CrtSeg*)(d + o);
-    o += s->host_segs.size() * sizeof(CrtSeg);
-    o = align_up(o, 16);
-    if (!s->host_pref.empty()) memcpy(&h[o], s->host_pref.data(), s->host_pref.size() * sizeof(uint32_t));
-    s->blk_pref = (const uint32_t*)(d + o);
-    o += s->host_pref.size() * sizeof(uint32_t);
+    s->sv = SegView{};
+    s->sv.nseg = (uint32_t)s->host_segs.size();
+    if (s->host_segs.size() > CAT_INLINE_SEG) {
+      o = align_up(o, 16);
+      memcpy(&h[o], s->host_segs.data(), s->host_segs.size() * sizeof(CrtSeg));
+      s->sv.segs = (const CrtSeg*)(d + o);
+      o += s->host_segs.size() * sizeof(CrtSeg);
+      o = align_up(o, 16);
+      memcpy(&h[o], s->host_pref.data(), s->host_pref.size() * sizeof(uint32_t));
+      s->sv.pref = (const uint32_t*)(d + o);
+      o += s->host_pref.size() * sizeof(uint32_t);
+    } else {
+      for (size_t k = 0; k < s->host_segs.size(); k++) s->sv.iseg[k] = s->host_segs[k];
+      for (size_t k = 0; k < s->host_pref.size(); k++) s->sv.ipref[k] = s->host_pref[k];
+    }
   }
-  HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+  if (bytes) HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
   *dev = d;
   return CAT_OK;
 }
@@ -824,13 +856,7 @@ cat_status copy_tails(Exec& X, const Stage& s) {
   return CAT_OK;
 }
 
-SegView stage_segs(const Stage& s) {
-  SegView sv{};
-  sv.segs = s.segs;
-  sv.pref = s.blk_pref;
-  sv.nseg = s.nseg;
-  return sv;
-}
+SegView stage_segs(const Stage& s) { return s.sv; }
 
 cat_status run_stage_batched(Exec& X, const Stage& s) {
   if (s.is_leaf) {
@@ -855,10 +881,13 @@ cat_status run_stage_batched(Exec& X, const Stage& s) {
 cat_status run_stage_plain(Exec& X, const Stage& s) {
   if (s.is_leaf) return CAT_EINTERNAL;
   for (uint64_t i = 0; i < s.nmul; i++) {
-    const MulDesc d = s.dv.table ? s.host_desc[i] : tree_desc(s.dv.tree, i);
+    const bool expl = !s.host_desc.empty();
+    const MulDesc d = expl ? s.host_desc[i] : tree_desc(s.dv.tree, i);
     DescView one{};
-    if (s.dv.table) {
-      one.table = s.dv.table + i;
+    if (expl) {
+      one.table = nullptr;
+      one.ninl = 1;
+      one.inl[0] = d;
     } else {
       // a one-group, two-node tree whose only product is d
       one.table = nullptr;
@@ -873,8 +902,11 @@ cat_status run_stage_plain(Exec& X, const Stage& s) {
     if (s.cls != CLS_SCHOOL) {
       SegView sv{};
       sv.segs = nullptr;
-      sv.one = CrtSeg{d.c_off, d.r_off, (uint64_t)d.la + d.lb};
-      const uint32_t nb = (uint32_t)((sv.one.len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
+      sv.nseg = 1;
+      sv.iseg[0] = CrtSeg{d.c_off, d.r_off, (uint64_t)d.la + d.lb};
+      const uint32_t nb = (uint32_t)((sv.iseg[0].len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
+      sv.ipref[0] = 0;
+      sv.ipref[1] = nb;
       STCHK(launch_crt(X, out_base(X, s), sv, nb, nb > 1));
     }
   }
@@ -1146,6 +1178,63 @@ cat_status mul_plan_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_
   return CAT_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Asynchronous C(n): tickets.  Each ticket owns a 1 KB slice of pinned host
+// memory (group table, top index, error word) and an event; slices and events
+// are pooled so the serving loop never allocates.
+// ----------------------------------------------------------------------------
+struct Ticket {
+  uint64_t n = 0;
+  Layout Ly;
+  char* wb = nullptr;
+  hipStream_t st = nullptr;
+  int state = 0;              // 1: Phase 1 queued, 2: Phase 2 queued
+  hipEvent_t ev = nullptr;
+  char* pin = nullptr;
+  bool one = false;           // C(n) = 1
+  uint64_t cap = 0;
+};
+
+struct TicketPool {
+  char* pinned = nullptr;
+  std::vector<char*> free_slices;
+  std::vector<hipEvent_t> free_events;
+};
+TicketPool tp;
+#define TICKET_SLICE 1024
+#define TICKET_SLICES 4096
+
+cat_status ticket_alloc(Ticket** out) {
+  if (!tp.pinned) {
+    HIPCHK(hipHostMalloc((void**)&tp.pinned, (size_t)TICKET_SLICE * TICKET_SLICES, hipHostMallocDefault));
+    for (int k = TICKET_SLICES - 1; k >= 0; k--) tp.free_slices.push_back(tp.pinned + (size_t)k * TICKET_SLICE);
+  }
+  if (tp.free_slices.empty()) return CAT_ENOMEM;
+  Ticket* t = new Ticket();
+  t->pin = tp.free_slices.back();
+  tp.free_slices.pop_back();
+  if (!tp.free_events.empty()) {
+    t->ev = tp.free_events.back();
+    tp.free_events.pop_back();
+  } else {
+    hipError_t e = hipEventCreateWithFlags(&t->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      tp.free_slices.push_back(t->pin);
+      delete t;
+      g.last_err = (int)e;
+      return CAT_EDEVICE;
+    }
+  }
+  *out = t;
+  return CAT_OK;
+}
+
+void ticket_free(Ticket* t) {
+  tp.free_slices.push_back(t->pin);
+  tp.free_events.push_back(t->ev);
+  delete t;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1166,6 +1255,7 @@ const char* cat_strerror(cat_status s) {
     case CAT_ENOMEM: return "workspace too small or allocation failed";
     case CAT_EDEVICE: return "HIP runtime error";
     case CAT_EINTERNAL: return "device invariant violated";
+    case CAT_EAGAIN: return "not finished yet";
     default: return "unknown status";
   }
 }
@@ -1554,6 +1644,125 @@ cat_status bigint_residues(const uint32_t* d_x, size_t n, uint64_t* h_res, void*
     for (uint64_t c = nch; c > 0; c--) acc = (acc * pw + h[(c - 1) * 3 + m]) % q;
     h_res[m] = (uint64_t)acc;
   }
+  return CAT_OK;
+}
+
+cat_status catalan_begin(uint64_t n, void* d_work, size_t work_bytes, void* stream, cat_ticket* ticket) {
+  if (n > CAT_N_MAX || !d_work || !ticket) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  Ticket* t = nullptr;
+  STCHK(ticket_alloc(&t));
+  t->n = n;
+  t->Ly = make_layout(n);
+  if (work_bytes < t->Ly.total) {
+    ticket_free(t);
+    return CAT_ENOMEM;
+  }
+  t->wb = (char*)d_work;
+  t->st = (hipStream_t)stream;
+  uint64_t launches = 0;
+  cat_status s = run_phase1(t->Ly, t->wb, (uint32_t*)t->wb + t->Ly.primes, t->Ly.Kmax, t->st, &launches);
+  if (s == CAT_OK) {
+    hipError_t e = hipMemcpyAsync(t->pin, t->wb + t->Ly.gtab, sizeof(GroupTable), hipMemcpyDeviceToHost, t->st);
+    if (e == hipSuccess) e = hipEventRecord(t->ev, t->st);
+    if (e != hipSuccess) {
+      g.last_err = (int)e;
+      s = CAT_EDEVICE;
+    }
+  }
+  if (s != CAT_OK) {
+    (void)hipStreamSynchronize(t->st);
+    ticket_free(t);
+    return s;
+  }
+  t->state = 1;
+  *ticket = (cat_ticket)t;
+  return CAT_OK;
+}
+
+cat_status cat_ticket_query(cat_ticket ticket) {
+  if (!ticket) return CAT_EINVAL;
+  Ticket* t = (Ticket*)ticket;
+  hipError_t e = hipEventQuery(t->ev);
+  if (e == hipSuccess) return CAT_OK;
+  if (e == hipErrorNotReady) return CAT_EAGAIN;
+  g.last_err = (int)e;
+  return CAT_EDEVICE;
+}
+
+cat_status catalan_continue(cat_ticket ticket, uint32_t* d_limbs, size_t cap) {
+  if (!ticket || !d_limbs) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  Ticket* t = (Ticket*)ticket;
+  if (t->state != 1) return CAT_EINVAL;
+  HIPCHK(hipEventSynchronize(t->ev));
+  GroupTable gt;
+  memcpy(&gt, t->pin, sizeof(GroupTable));
+  if (gt.err || gt.ngroups > CAT_MAX_GROUPS) return CAT_EINTERNAL;
+  Plan* P = find_plan(t->n, gt);
+  if (!P) {
+    STCHK(make_plan(t->Ly, gt, &P));
+    remember_plan(P);
+  }
+  t->cap = cap;
+  Exec X = make_exec(t->Ly, t->wb, t->st);
+  unsigned long long* top = (unsigned long long*)(t->wb + t->Ly.top);
+  if (P->result_is_one) {
+    t->one = true;
+    if (cap < 1) return CAT_ERANGE;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, t->st, d_limbs, (uint64_t)1, 1u);
+    LAUNCHCHK();
+  } else {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, t->st, X.err, (uint64_t)1, 0u);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, t->st, (uint32_t*)top, (uint64_t)2, 0u);
+    LAUNCHCHK();
+    STCHK(run_phase2(X, *P, false));
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, t->st, X.W + P->result_pos, P->result_cap, top);
+    LAUNCHCHK();
+    const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)std::min<uint64_t>((ncopy + 255) / 256, 2048)), dim3(256), 0, t->st,
+                       X.W + P->result_pos, d_limbs, ncopy);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(t->pin + 512, t->wb + t->Ly.top, 8, hipMemcpyDeviceToHost, t->st));
+    HIPCHK(hipMemcpyAsync(t->pin + 520, t->wb + t->Ly.err, 4, hipMemcpyDeviceToHost, t->st));
+  }
+  HIPCHK(hipEventRecord(t->ev, t->st));
+  t->state = 2;
+  return CAT_OK;
+}
+
+cat_status catalan_end(cat_ticket ticket, size_t* n_limbs) {
+  if (!ticket || !n_limbs) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  Ticket* t = (Ticket*)ticket;
+  if (t->state != 2) return CAT_EINVAL;
+  HIPCHK(hipEventSynchronize(t->ev));
+  cat_status s = CAT_OK;
+  if (t->one) {
+    *n_limbs = 1;
+  } else {
+    uint64_t L = 0;
+    uint32_t derr = 0;
+    memcpy(&L, t->pin + 512, 8);
+    memcpy(&derr, t->pin + 520, 4);
+    *n_limbs = (size_t)L;
+    if (derr || L == 0) s = CAT_EINTERNAL;
+    else if (L > t->cap) s = CAT_ERANGE;
+  }
+  ticket_free(t);
+  return s;
+}
+
+cat_status cat_ticket_release(cat_ticket ticket) {
+  if (!ticket) return CAT_OK;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  Ticket* t = (Ticket*)ticket;
+  (void)hipEventSynchronize(t->ev);
+  ticket_free(t);
   return CAT_OK;
 }
 

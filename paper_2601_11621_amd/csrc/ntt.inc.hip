@@ -508,26 +508,25 @@ __device__ __forceinline__ uint32_t block_carry(bool g, bool pr, uint32_t* tmp, 
 
 // Segments of a CRT launch: a device table with block prefix, or one segment
 // passed by value (single products launched on their own).
+// Segments of a CRT launch: device tables (many segments) or up to
+// CAT_INLINE_SEG segments carried in the kernel arguments.
+#define CAT_INLINE_SEG 32
 struct SegView {
-  const CrtSeg* segs;        // nullptr => `one`
+  const CrtSeg* segs;        // nullptr => inline tables
   const uint32_t* pref;      // pref[s] = first block of segment s (nseg+1 entries)
   uint32_t nseg;
-  CrtSeg one;
+  CrtSeg iseg[CAT_INLINE_SEG];
+  uint32_t ipref[CAT_INLINE_SEG + 1];
   __device__ __forceinline__ void find(uint32_t b, CrtSeg* sg, uint32_t* first, uint32_t* end) const {
-    if (!segs) {
-      *sg = one;
-      *first = 0;
-      *end = (uint32_t)((one.len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
-      return;
-    }
-    uint32_t lo = 0, hi = nseg;   // pref[lo] <= b < pref[lo+1]
+    const uint32_t* pr = segs ? pref : ipref;
+    uint32_t lo = 0, hi = nseg;   // pr[lo] <= b < pr[lo+1]
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (pref[mid] <= b) lo = mid; else hi = mid;
+      if (pr[mid] <= b) lo = mid; else hi = mid;
     }
-    *sg = segs[lo];
-    *first = pref[lo];
-    *end = pref[lo + 1];
+    *sg = segs ? segs[lo] : iseg[lo];
+    *first = pr[lo];
+    *end = pr[lo + 1];
   }
 };
 

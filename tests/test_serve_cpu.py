@@ -1,0 +1,81 @@
+"""Scheduler logic of the request loop on the CPU (fake executor, fake clock):
+admission by footprint, FIFO order, slot reuse, overlap, latency statistics."""
+from paper_2601_11621_amd.serve import DONE, FAILED, FakeExecutor, Server
+
+
+def _drive(srv, ex, dt=0.001, limit=100000):
+    k = 0
+    while not srv.idle() and k < limit:
+        if not srv.step():
+            if srv.active:
+                ex.tick(dt)
+            elif srv.queue:
+                ex.wait_until(srv.queue[0].arrival)
+        k += 1
+    assert srv.idle()
+
+
+def test_budget_limits_concurrency_and_keeps_fifo():
+    ex = FakeExecutor(lambda n: 0.01, lambda n: 0.02)
+    srv = Server(ex, budget_bytes=250, max_slots=8, clock=ex.clock)
+    reqs = [srv.submit(100, arrival=0.0) for _ in range(6)]
+    _drive(srv, ex)
+    assert all(r.state == DONE for r in reqs)
+    assert srv.peak_used <= 250 and srv.peak_active == 2        # two footprints of 100 fit
+    begins = [rid for (what, rid, t) in ex.log if what == "begin"]
+    assert begins == sorted(begins)                               # FIFO admission
+
+
+def test_slots_limit_and_reuse():
+    ex = FakeExecutor(lambda n: 0.005, lambda n: 0.005)
+    srv = Server(ex, budget_bytes=10**9, max_slots=3, clock=ex.clock)
+    reqs = [srv.submit(10, arrival=0.0) for _ in range(10)]
+    _drive(srv, ex)
+    assert srv.peak_active == 3
+    assert sorted({r.slot for r in reqs}) == [0, 1, 2]
+    assert all(r.state == DONE and r.n_limbs == 10 for r in reqs)
+
+
+def test_late_arrivals_are_admitted_while_others_run():
+    """Continuous admission: a request arriving while a long one runs starts
+    before the long one finishes."""
+    ex = FakeExecutor(lambda n: 0.001, lambda n: n * 0.001)
+    srv = Server(ex, budget_bytes=10**6, max_slots=4, clock=ex.clock)
+    long = srv.submit(1000, arrival=0.0)      # runs for ~1 s
+    short = srv.submit(5, arrival=0.1)
+    _drive(srv, ex)
+    assert short.admitted < long.finished
+    assert short.finished < long.finished
+    assert abs(short.admitted - 0.1) < 0.01
+
+
+def test_head_too_large_is_failed_not_blocking():
+    ex = FakeExecutor(lambda n: 0.001, lambda n: 0.001)
+    srv = Server(ex, budget_bytes=100, max_slots=2, clock=ex.clock)
+    big = srv.submit(1000, arrival=0.0)
+    small = srv.submit(10, arrival=0.0)
+    _drive(srv, ex)
+    assert big.state == FAILED and small.state == DONE
+
+
+def test_large_head_waits_for_memory():
+    ex = FakeExecutor(lambda n: 0.001, lambda n: 0.05)
+    srv = Server(ex, budget_bytes=100, max_slots=4, clock=ex.clock)
+    a = srv.submit(60, arrival=0.0)
+    b = srv.submit(60, arrival=0.0)      # must wait for a
+    c = srv.submit(10, arrival=0.0)      # behind b: FIFO, waits too
+    _drive(srv, ex)
+    assert b.admitted >= a.finished
+    assert c.admitted >= b.admitted
+
+
+def test_latency_percentiles():
+    ex = FakeExecutor(lambda n: 0.0, lambda n: n * 0.001)
+    srv = Server(ex, budget_bytes=10**9, max_slots=100, clock=ex.clock)
+    for k in range(1, 101):
+        srv.submit(k, arrival=0.0)
+    _drive(srv, ex, dt=0.0005)
+    st = srv.stats()
+    assert st["completed"] == 100
+    assert 45 <= st["p50_ms"] <= 56
+    assert 95 <= st["p99_ms"] <= 102
