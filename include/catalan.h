@@ -171,6 +171,23 @@ typedef struct {
 } cat_stats;
 cat_status cat_get_stats(cat_stats* out);
 
+/* Product schedule per transform-length bucket (the autotuner's output).
+ * Products with la, lb <= school_max use the schoolbook kernel; otherwise
+ * bucket k = ceil(log2(la + lb - 1)) (at least 6) selects cls[k]:
+ * 1 = one workgroup holds the whole transform (k <= 12), 2 = four-step
+ * transform with rows of 2^log_row[k] words (8..12, < k) and column passes of
+ * at most 2^log_pass[k] points (4..10).  Every schedule gives the same bits.
+ * cat_tune_set(NULL) restores the defaults; CAT_EINVAL for an invalid table.
+ * Setting a table drops the cached C(n) plans. */
+typedef struct {
+  uint32_t school_max;
+  uint8_t cls[28];
+  uint8_t log_row[28];
+  uint8_t log_pass[28];
+} cat_tuning;
+cat_status cat_tune_set(const cat_tuning* t);
+cat_status cat_tune_get(cat_tuning* t);
+
 /* Kernel timer (measurement only).  cat_timer_set(name) brackets every later
  * launch of the named kernel ("k_ntt_lds", "k_row", "k_pass_fwd", "k_pass_inv",
  * "k_crt", "k_school", "k_leaf") with HIP events on the stream it is launched

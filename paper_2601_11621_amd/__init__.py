@@ -30,6 +30,7 @@ EXPORTS = [
     "catalan_exact", "catalan_exact_ex", "cat_mul_plan_create", "cat_mul_plan_exec",
     "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues", "cat_timer_set", "cat_timer_get",
     "catalan_begin", "cat_ticket_query", "catalan_continue", "catalan_end", "cat_ticket_release",
+    "cat_tune_set", "cat_tune_get",
 ]
 
 
@@ -40,6 +41,11 @@ class CatalanError(RuntimeError):
         if status == CAT_EDEVICE and _lib is not None:
             msg += " [hip error %d]" % _lib.cat_last_device_error()
         super().__init__(msg)
+
+
+class cat_tuning(ctypes.Structure):
+    _fields_ = [("school_max", ctypes.c_uint32), ("cls", ctypes.c_uint8 * 28),
+                ("log_row", ctypes.c_uint8 * 28), ("log_pass", ctypes.c_uint8 * 28)]
 
 
 class cat_stats(ctypes.Structure):
@@ -99,6 +105,8 @@ def load(path: str = LIB_PATH):
         "catalan_continue": ([vp, vp, ctypes.c_size_t], st),
         "catalan_end": ([vp, szp], st),
         "cat_ticket_release": ([vp], st),
+        "cat_tune_set": ([ctypes.POINTER(cat_tuning)], st),
+        "cat_tune_get": ([ctypes.POINTER(cat_tuning)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -152,9 +160,52 @@ def workspace(nbytes: int, key: str = "default"):
     return buf
 
 
-def init(device: int = -1) -> None:
+TUNING_FILE = os.path.join(_HERE, "tuning", "gfx950.json")
+
+
+def get_tuning() -> dict:
+    t = cat_tuning()
+    _check(load().cat_tune_get(ctypes.byref(t)), "cat_tune_get")
+    return {"school_max": t.school_max, "cls": list(t.cls), "log_row": list(t.log_row),
+            "log_pass": list(t.log_pass)}
+
+
+def set_tuning(d: Optional[dict]) -> None:
+    """Install a schedule table (None: the library defaults)."""
+    if d is None:
+        _check(load().cat_tune_set(None), "cat_tune_set")
+        return
+    t = cat_tuning()
+    t.school_max = int(d["school_max"])
+    for k in range(28):
+        t.cls[k] = int(d["cls"][k])
+        t.log_row[k] = int(d["log_row"][k])
+        t.log_pass[k] = int(d["log_pass"][k])
+    _check(load().cat_tune_set(ctypes.byref(t)), "cat_tune_set")
+
+
+def load_tuning(path: str = TUNING_FILE) -> bool:
+    """Install the autotuner's table for this GPU if one was written."""
+    import json
+
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        d = json.load(f)
+    set_tuning(d["table"])
+    return True
+
+
+_inited = False
+
+
+def init(device: int = -1, tuned: bool = True) -> None:
+    global _inited
     _torch()
     _check(load().cat_init(device), "cat_init")
+    if tuned and not _inited:
+        load_tuning()
+    _inited = True
 
 
 def sizes(n: int):

@@ -218,16 +218,17 @@ NttTables tables_for(int logN) {
   return tb;
 }
 
-// Pass decomposition of a large transform: N = L_0 ... L_{P-1} * 2^12 with
-// every L_p <= 2^10 (so a tile of L_p x C words with C >= 16 fits 64 KB).
+// Pass decomposition of a large transform: N = L_0 ... L_{P-1} * M with
+// every L_p <= 2^maxL (maxL <= 10, so a tile of L_p x C words with C >= 16
+// fits 64 KB) and rows of M = 2^logM.
 struct PassPlan {
   int P = 0;
-  int logL[4] = {}, logS[4] = {}, logC[4] = {};
+  int logL[8] = {}, logS[8] = {}, logC[8] = {};
 };
-PassPlan pass_plan(int logN) {
+PassPlan pass_plan(int logN, int logM, int maxL) {
   PassPlan pp;
-  const int rest = logN - CAT_LDS_LOGT;
-  pp.P = (rest + 9) / 10;
+  const int rest = logN - logM;
+  pp.P = (rest + maxL - 1) / maxL;
   int ls = logN;
   for (int k = 0; k < pp.P; k++) {
     pp.logL[k] = rest / pp.P + (k < rest % pp.P ? 1 : 0);
@@ -253,21 +254,62 @@ uint2 scale_pair(int prime, int logN) {
 // ----------------------------------------------------------------------------
 enum { CLS_SCHOOL = 0, CLS_LDS = 1, CLS_LARGE = 2 };
 
-void classify(uint64_t la, uint64_t lb, int* cls, int* logN) {
-  if (la <= SCHOOL_MAX && lb <= SCHOOL_MAX) {
-    *cls = CLS_SCHOOL;
-    *logN = 0;
-    return;
+// Schedule per transform-length bucket 2^k (set by the autotuner, or defaults).
+cat_tuning default_tuning() {
+  cat_tuning t;
+  memset(&t, 0, sizeof(t));
+  t.school_max = SCHOOL_MAX;
+  for (int k = 0; k <= CAT_MAX_LOGN; k++) {
+    t.cls[k] = (k <= CAT_LDS_LOGT) ? CLS_LDS : CLS_LARGE;
+    t.log_row[k] = CAT_LDS_LOGT;
+    t.log_pass[k] = 10;
   }
+  return t;
+}
+cat_tuning g_tune = default_tuning();
+
+bool tuning_valid(const cat_tuning& t) {
+  if (t.school_max < 1 || t.school_max > SCHOOL_MAX) return false;
+  for (int k = 6; k <= CAT_MAX_LOGN; k++) {
+    if (t.cls[k] == CLS_LDS) {
+      if (k > CAT_LDS_LOGT) return false;
+    } else if (t.cls[k] == CLS_LARGE) {
+      if (t.log_row[k] < 8 || t.log_row[k] > CAT_LDS_LOGT || k <= t.log_row[k]) return false;
+      if (t.log_pass[k] < 4 || t.log_pass[k] > 10) return false;
+    } else {
+      return false;
+    }
+  }
+  return true;
+}
+
+struct Cls {
+  int cls, logN, logM, maxL;
+};
+
+Cls classify2(uint64_t la, uint64_t lb) {
+  Cls c{CLS_SCHOOL, 0, 0, 0};
+  if (la <= g_tune.school_max && lb <= g_tune.school_max) return c;
   int k = ceil_log2(la + lb - 1);
   if (k < 6) k = 6;
-  *logN = k;
-  *cls = (k <= CAT_LDS_LOGT) ? CLS_LDS : CLS_LARGE;
+  c.logN = k;
+  c.cls = g_tune.cls[k];
+  c.logM = g_tune.log_row[k];
+  c.maxL = g_tune.log_pass[k];
+  return c;
+}
+
+void classify(uint64_t la, uint64_t lb, int* cls, int* logN) {
+  const Cls c = classify2(la, lb);
+  *cls = c.cls;
+  *logN = c.logN;
 }
 
 struct Stage {
   int cls = CLS_SCHOOL;
   int logN = 0;
+  int logM = CAT_LDS_LOGT;   // four-step row length
+  int maxL = 10;             // four-step column-pass limit
   DescView dv{};           // dv.table is a device pointer (explicit) or nullptr (tree)
   std::vector<MulDesc> host_desc;   // explicit descriptors (host copy)
   uint64_t nmul = 0;
@@ -477,7 +519,13 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
     }
     s.limbs = 0;
     for (const CrtSeg& sg : s.host_segs) s.limbs += sg.len;
-    classify(1ull << j, 1ull << j, &s.cls, &s.logN);
+    {
+      const Cls c = classify2(1ull << j, 1ull << j);
+      s.cls = c.cls;
+      s.logN = c.logN;
+      s.logM = c.logM;
+      s.maxL = c.maxL;
+    }
     s.a_base = s.b_base = in_of(j);
     s.c_base = out_of(j);
     s.tail_in_base = in_of(j);
@@ -504,11 +552,12 @@ void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vecto
   uint64_t rpos = 0;
   for (size_t k = 0; k < pairs.size(); k++) {
     const Item a = pairs[k].first, b = pairs[k].second, c = outs[k];
-    int cls, logN;
-    classify(a.cap, b.cap, &cls, &logN);
-    Stage& s = by[{cls, logN}];
-    s.cls = cls;
-    s.logN = logN;
+    const Cls cc = classify2(a.cap, b.cap);
+    Stage& s = by[{cc.cls, cc.logN}];
+    s.cls = cc.cls;
+    s.logN = cc.logN;
+    s.logM = cc.logM;
+    s.maxL = cc.maxL;
     MulDesc d;
     d.a_off = a.pos;
     d.b_off = b.pos;
@@ -528,6 +577,8 @@ void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vecto
       Stage t;
       t.cls = s.cls;
       t.logN = s.logN;
+      t.logM = s.logM;
+      t.maxL = s.maxL;
       const size_t k1 = std::min(s.host_desc.size(), k0 + CAT_INLINE_DESC);
       uint64_t r = 0;
       for (size_t k = k0; k < k1; k++) {
@@ -812,8 +863,8 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
     X.launches++;
     return CAT_OK;
   }
-  const PassPlan pp = pass_plan(s.logN);
-  const int logM = CAT_LDS_LOGT, logR1 = s.logN - logM;
+  const PassPlan pp = pass_plan(s.logN, s.logM, s.maxL);
+  const int logM = s.logM, logR1 = s.logN - logM;
   const double N = (double)(1ull << s.logN);
   for (int k = 0; k < pp.P; k++) {
     PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
@@ -829,7 +880,7 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
     const double rows = (double)cnt * (1ull << logR1);
     KTime kt("k_row", X.st, bfly(9.0 * rows, logM));
     hipLaunchKernelGGL(k_row, dim3((uint32_t)(cnt << logR1), CAT_NPRIMES), dim3(NTT_ROW_THREADS), 0, X.st, s.logN,
-                       X.F, tb, s0, s1, s2);
+                       logM, X.F, tb, s0, s1, s2);
   }
   LAUNCHCHK();
   for (int k = pp.P - 1; k >= 0; k--) {
@@ -1051,11 +1102,12 @@ cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t
       delete M;
       return CAT_EINVAL;
     }
-    int cls, logN;
-    classify(la, lb, &cls, &logN);
-    Stage& st = by[{cls, logN}];
-    st.cls = cls;
-    st.logN = logN;
+    const Cls cc = classify2(la, lb);
+    Stage& st = by[{cc.cls, cc.logN}];
+    st.cls = cc.cls;
+    st.logN = cc.logN;
+    st.logM = cc.logM;
+    st.maxL = cc.maxL;
     MulDesc d;
     d.a_off = a_off[i];
     d.b_off = b_off[i];
@@ -1261,6 +1313,26 @@ const char* cat_strerror(cat_status s) {
 }
 
 int cat_last_device_error(void) { return g.last_err; }
+
+cat_status cat_tune_set(const cat_tuning* t) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  const cat_tuning v = t ? *t : default_tuning();
+  if (!tuning_valid(v)) return CAT_EINVAL;
+  g_tune = v;
+  // cached plans and graphs were made with the old schedule
+  if (!g.plans.empty()) HIPCHK(hipDeviceSynchronize());
+  for (auto& kv : g.plans) free_plan(kv.second);
+  g.plans.clear();
+  g.plan_order.clear();
+  return CAT_OK;
+}
+
+cat_status cat_tune_get(cat_tuning* t) {
+  if (!t) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  *t = g_tune;
+  return CAT_OK;
+}
 
 cat_status cat_timer_set(const char* kernel) {
   std::lock_guard<std::recursive_mutex> lk(g.mu);

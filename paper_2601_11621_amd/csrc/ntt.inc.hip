@@ -410,12 +410,12 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
 
 #define NTT_ROW_THREADS 256
 __global__ void __launch_bounds__(NTT_ROW_THREADS)
-k_row(int logN, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
+k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
   __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
   const uint32_t prime = blockIdx.y;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
-  const int logM = CAT_LDS_LOGT, logR1 = logN - logM;
+  const int logR1 = logN - logM;   // rows of M = 2^logM <= 2^12 elements
   const uint32_t M = 1u << logM;
   const uint64_t N = 1ull << logN;
   const uint64_t m = blockIdx.x >> logR1;

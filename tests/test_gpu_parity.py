@@ -195,3 +195,37 @@ def test_residues_kernel(cat):
         v = pins.limbs_int(x)
         r = cat.residues(cat.from_numpy(x))
         assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1))
+
+
+def test_schedules_change_speed_not_bits(cat):
+    """A non-default product schedule (small schoolbook threshold, four-step
+    transforms with short rows and short column passes from 2^11 up) gives the
+    same C(n) and the same products as the default one."""
+    import torch
+
+    base = cat.get_tuning()
+    ns = [5000, 100000, 10**6]
+    ref = {n: cat.to_numpy(cat.exact(n, mode="batched")) for n in ns}
+    rng = np.random.default_rng(4)
+    la = np.rint(2 ** rng.uniform(3, 15, 40)).astype(np.int64)
+    lb = np.rint(2 ** rng.uniform(3, 15, 40)).astype(np.int64)
+    a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
+    da = cat.from_numpy(_rand(rng, int(a_off[-1])))
+    db = cat.from_numpy(_rand(rng, int(b_off[-1])))
+    c0, _ = cat.mul_batched(da, a_off, db, b_off)
+    c0 = c0.clone()
+    t = cat.get_tuning()
+    t["school_max"] = 32
+    for k in range(11, 28):
+        t["cls"][k] = 2
+        t["log_row"][k] = 10
+        t["log_pass"][k] = 6
+    try:
+        cat.set_tuning(t)
+        for n in ns:
+            assert np.array_equal(cat.to_numpy(cat.exact(n, mode="batched")), ref[n]), n
+        c1, _ = cat.mul_batched(da, a_off, db, b_off)
+        assert torch.equal(c0, c1)
+    finally:
+        cat.set_tuning(base)
