@@ -17,7 +17,7 @@
 #define CAT_MAX_LOGN 27
 #define CAT_MAX_GROUPS 32       // e_p <= log2(2n) < 32
 #define CAT_LDS_LOGT 12         // row length of the LDS-resident transforms
-#define CAT_CRT_E 16            // limbs per thread in the CRT/carry kernel
+#define CAT_CRT_E 4             // limbs per thread in the CRT/carry kernel (>= 3)
 #define CAT_CRT_THREADS 256
 #define CAT_CRT_BLOCK (CAT_CRT_E * CAT_CRT_THREADS)
 
@@ -46,33 +46,31 @@ struct CrtC {
 // ----------------------------------------------------------------------------
 // Modular arithmetic, p odd, 2^31 < p < 2^32.  Inputs of add/sub reduced.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t p) {
-  uint32_t t = p - b;          // in (0, p]
-  uint32_t d = a - t;
-  return a >= t ? d : d + p;
-}
 __device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t p) {
-  uint32_t d = a - b;
-  return a >= b ? d : d + p;
+  uint32_t d;
+  const bool borrow = __builtin_usub_overflow(a, b, &d);   // one v_sub_co_u32
+  return borrow ? d + p : d;
 }
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t p) {
+  return sub_mod(a, p - b, p);   // p - b in (0, p]
+}
+
 // Montgomery multiplication with a precomputed companion (Montgomery 1985,
 // with the quotient digit precomputed as in Shoup's method): returns a*w/R
 // mod p in [0,p) for any 32-bit a and w < p.
 __device__ __forceinline__ uint32_t mul_tw(uint32_t a, uint32_t w, uint32_t wq, uint32_t p) {
-  uint32_t m = a * wq;
-  uint32_t hi = __umulhi(a, w);
-  uint32_t mh = __umulhi(m, p);
-  uint32_t r = hi - mh;
-  return hi >= mh ? r : r + p;
+  const uint32_t m = a * wq;
+  const uint32_t hi = __umulhi(a, w);
+  const uint32_t mh = __umulhi(m, p);
+  return sub_mod(hi, mh, p);   // hi, mh < p
 }
 // General Montgomery product a*b/R mod p, a,b < p.
 __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
   uint32_t lo = a * b;
   uint32_t hi = __umulhi(a, b);
-  uint32_t m = lo * pinv;
-  uint32_t mh = __umulhi(m, p);
-  uint32_t r = hi - mh;
-  return hi >= mh ? r : r + p;
+  const uint32_t m = lo * pinv;
+  const uint32_t mh = __umulhi(m, p);
+  return sub_mod(hi, mh, p);   // hi, mh < p
 }
 // limb (any 32-bit value) reduced mod p: 2^32 < 2p, so one subtraction suffices
 __device__ __forceinline__ uint32_t reduce_limb(uint32_t x, uint32_t p) { return x >= p ? x - p : x; }

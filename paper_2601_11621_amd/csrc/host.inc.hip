@@ -219,8 +219,8 @@ NttTables tables_for(int logN) {
 }
 
 // Pass decomposition of a large transform: N = L_0 ... L_{P-1} * M with
-// every L_p <= 2^maxL (maxL <= 10, so a tile of L_p x C words with C >= 16
-// fits 64 KB) and rows of M = 2^logM.
+// every L_p <= 2^maxL (maxL <= 10, so a tile of L_p x C words with C >= 8
+// fits 32 KB) and rows of M = 2^logM.
 struct PassPlan {
   int P = 0;
   int logL[8] = {}, logS[8] = {}, logC[8] = {};
@@ -233,7 +233,7 @@ PassPlan pass_plan(int logN, int logM, int maxL) {
   for (int k = 0; k < pp.P; k++) {
     pp.logL[k] = rest / pp.P + (k < rest % pp.P ? 1 : 0);
     pp.logS[k] = ls;
-    pp.logC[k] = std::min(14 - pp.logL[k], ls - pp.logL[k]);
+    pp.logC[k] = std::min(13 - pp.logL[k], ls - pp.logL[k]);   // tile L x C <= 2^13 words
     ls -= pp.logL[k];
   }
   return pp;

@@ -89,68 +89,106 @@ __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
 // as element e of column c at (e << logC) + c (logC = 0: a plain vector).
 // The elements form consecutive sub-problems of size S = R << logSR.
 // tw: table of this pass, tw[(k1 << logSR) + j2] = omega_S^{j2*k1}.
-template <int LOGR, bool PAD>
-__device__ __forceinline__ void pass_fwd(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
-                                         const uint2* __restrict__ tw, const PrimeC& pc) {
+// A thread handles U groups at once (g, g + blockDim, ...) so that the loads
+// of one overlap the arithmetic of the other.
+template <int LOGR, bool PAD, int U>
+__device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t logSR, uint32_t logC,
+                                           const uint2* __restrict__ tw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
-  for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
-    const uint32_t c = g & cmask, h = g >> logC;
-    const uint32_t j2 = h & smask, b = h >> logSR;
-    const uint32_t e0 = (b << (logSR + LOGR)) + j2;
-    uint32_t v[R];
+  uint32_t v[U][R];
+  uint32_t e0[U], cc[U], jj[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const uint32_t g = g0 + u * blockDim.x;
+    const uint32_t h = g >> logC;
+    cc[u] = g & cmask;
+    jj[u] = h & smask;
+    e0[u] = ((h >> logSR) << (logSR + LOGR)) + jj[u];
 #pragma unroll
     for (int j1 = 0; j1 < R; j1++) {
-      uint32_t a = ((e0 + ((uint32_t)j1 << logSR)) << logC) + c;
-      v[j1] = lds[PAD ? lds_pad(a) : a];
+      const uint32_t a = ((e0[u] + ((uint32_t)j1 << logSR)) << logC) + cc[u];
+      v[u][j1] = lds[PAD ? lds_pad(a) : a];
     }
-    dft_fwd<LOGR>(v, pc);
-    if (logSR > 0 && j2 != 0) {
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    dft_fwd<LOGR>(v[u], pc);
+    if (logSR > 0 && jj[u] != 0) {
 #pragma unroll
       for (int k1 = 1; k1 < R; k1++) {
-        uint2 t = tw[((uint32_t)k1 << logSR) + j2];
+        const uint2 t = tw[((uint32_t)k1 << logSR) + jj[u]];
         const int r = brev_c(k1, LOGR);
-        v[r] = mul_tw(v[r], t.x, t.y, pc.p);
+        v[u][r] = mul_tw(v[u][r], t.x, t.y, pc.p);
       }
     }
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
 #pragma unroll
     for (int k1 = 0; k1 < R; k1++) {
-      uint32_t a = ((e0 + ((uint32_t)k1 << logSR)) << logC) + c;
-      lds[PAD ? lds_pad(a) : a] = v[brev_c(k1, LOGR)];
+      const uint32_t a = ((e0[u] + ((uint32_t)k1 << logSR)) << logC) + cc[u];
+      lds[PAD ? lds_pad(a) : a] = v[u][brev_c(k1, LOGR)];
+    }
+  }
+}
+
+template <int LOGR, bool PAD, int U>
+__device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t logSR, uint32_t logC,
+                                           const uint2* __restrict__ itw, const PrimeC& pc) {
+  constexpr int R = 1 << LOGR;
+  const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
+  uint32_t v[U][R];
+  uint32_t e0[U], cc[U], jj[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const uint32_t g = g0 + u * blockDim.x;
+    const uint32_t h = g >> logC;
+    cc[u] = g & cmask;
+    jj[u] = h & smask;
+    e0[u] = ((h >> logSR) << (logSR + LOGR)) + jj[u];
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) {
+      const uint32_t a = ((e0[u] + ((uint32_t)k1 << logSR)) << logC) + cc[u];
+      v[u][brev_c(k1, LOGR)] = lds[PAD ? lds_pad(a) : a];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if (logSR > 0 && jj[u] != 0) {
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        const uint2 t = itw[((uint32_t)k1 << logSR) + jj[u]];
+        const int r = brev_c(k1, LOGR);
+        v[u][r] = mul_tw(v[u][r], t.x, t.y, pc.p);
+      }
+    }
+    dft_inv<LOGR>(v[u], pc);
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+#pragma unroll
+    for (int j1 = 0; j1 < R; j1++) {
+      const uint32_t a = ((e0[u] + ((uint32_t)j1 << logSR)) << logC) + cc[u];
+      lds[PAD ? lds_pad(a) : a] = v[u][j1];
     }
   }
 }
 
 template <int LOGR, bool PAD>
+__device__ __forceinline__ void pass_fwd(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
+                                         const uint2* __restrict__ tw, const PrimeC& pc) {
+  uint32_t g = threadIdx.x;
+  for (; g + blockDim.x < ngroups; g += 2 * blockDim.x) groups_fwd<LOGR, PAD, 2>(lds, g, logSR, logC, tw, pc);
+  for (; g < ngroups; g += blockDim.x) groups_fwd<LOGR, PAD, 1>(lds, g, logSR, logC, tw, pc);
+}
+
+template <int LOGR, bool PAD>
 __device__ __forceinline__ void pass_inv(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
                                          const uint2* __restrict__ itw, const PrimeC& pc) {
-  constexpr int R = 1 << LOGR;
-  const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
-  for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
-    const uint32_t c = g & cmask, h = g >> logC;
-    const uint32_t j2 = h & smask, b = h >> logSR;
-    const uint32_t e0 = (b << (logSR + LOGR)) + j2;
-    uint32_t v[R];
-#pragma unroll
-    for (int k1 = 0; k1 < R; k1++) {
-      uint32_t a = ((e0 + ((uint32_t)k1 << logSR)) << logC) + c;
-      v[brev_c(k1, LOGR)] = lds[PAD ? lds_pad(a) : a];
-    }
-    if (logSR > 0 && j2 != 0) {
-#pragma unroll
-      for (int k1 = 1; k1 < R; k1++) {
-        uint2 t = itw[((uint32_t)k1 << logSR) + j2];
-        const int r = brev_c(k1, LOGR);
-        v[r] = mul_tw(v[r], t.x, t.y, pc.p);
-      }
-    }
-    dft_inv<LOGR>(v, pc);
-#pragma unroll
-    for (int j1 = 0; j1 < R; j1++) {
-      uint32_t a = ((e0 + ((uint32_t)j1 << logSR)) << logC) + c;
-      lds[PAD ? lds_pad(a) : a] = v[j1];
-    }
-  }
+  uint32_t g = threadIdx.x;
+  for (; g + blockDim.x < ngroups; g += 2 * blockDim.x) groups_inv<LOGR, PAD, 2>(lds, g, logSR, logC, itw, pc);
+  for (; g < ngroups; g += blockDim.x) groups_inv<LOGR, PAD, 1>(lds, g, logSR, logC, itw, pc);
 }
 
 // radix of the pass at sub-problem size 2^logS
@@ -162,7 +200,7 @@ __host__ __device__ constexpr uint32_t tws_off(int s) { return (1u << s) - 2u; }
 // Full forward transform of size 2^logS on every sub-problem of an LDS tile
 // with `total` elements (all columns), passes from size 2^logS down.
 template <bool PAD>
-__device__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
+__device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ tws, const PrimeC& pc) {
   while (logS > 0) {
     const int lr = pass_logr(logS);
@@ -181,7 +219,7 @@ __device__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t l
 }
 
 template <bool PAD>
-__device__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
+__device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ itws, const PrimeC& pc) {
   // passes in the reverse order of ntt_fwd_tile: the radix-16 passes of sizes
   // 2^4, 2^8, ... first, the (possibly smaller-radix) pass of size 2^logS last
@@ -234,7 +272,7 @@ struct NttTables {
 // Writes res[prime][r_off + j] = (a*b)_j mod p for j < la+lb.
 #define NTT_LDS_T 4096u
 #define NTT_LDS_THREADS 256
-__global__ void __launch_bounds__(NTT_LDS_THREADS)
+__global__ void __launch_bounds__(NTT_LDS_THREADS, 4)
 k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
           uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
   __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
@@ -296,7 +334,7 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
 // Scratch F: per product, per prime, per operand N words:
 //   F[((m*3 + prime)*2 + op)*N + position]
 #define NTT_COL_THREADS 256
-#define NTT_COL_TILE 16384u     // LDS words of a column tile
+#define NTT_COL_TILE 8192u      // LDS words of a column tile (32 KB: 4 workgroups per CU)
 #define TW2_LO_BITS 14u
 #define TW2_LO (1u << TW2_LO_BITS)
 #define TW2_HI (1u << (CAT_MAX_LOGN - TW2_LO_BITS))
@@ -409,7 +447,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
 }
 
 #define NTT_ROW_THREADS 256
-__global__ void __launch_bounds__(NTT_ROW_THREADS)
+__global__ void __launch_bounds__(NTT_ROW_THREADS, 4)
 k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
   __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
   const uint32_t prime = blockIdx.y;
@@ -536,22 +574,48 @@ __global__ void __launch_bounds__(CAT_CRT_THREADS)
 k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out,
       uint8_t* __restrict__ bsum, uint32_t* __restrict__ err) {
   __shared__ uint32_t tmp[16];
-  const uint32_t b = blockIdx.x;
+  __shared__ uint32_t xv[CAT_CRT_THREADS + 1][9];   // last three V of each thread
+  const uint32_t b = blockIdx.x, tid = threadIdx.x;
   CrtSeg sg;
   uint32_t first, end;
   sv.find(b, &sg, &first, &end);
   const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
-  const uint64_t k0 = kb + (uint64_t)threadIdx.x * CAT_CRT_E;
+  const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
   const uint32_t* r0 = res + sg.res_pos;
   const uint32_t* r1 = r0 + res_stride;
   const uint32_t* r2 = r1 + res_stride;
-  // V for positions k0-3 .. k0+E-1
+  // V for positions k0-3 .. k0+E-1: the thread's own E, the 3 before it from
+  // its left neighbour (thread 0: recomputed from the residues)
   uint32_t v0[CAT_CRT_E + 3], v1[CAT_CRT_E + 3], v2[CAT_CRT_E + 3];
 #pragma unroll
-  for (int i = 0; i < CAT_CRT_E + 3; i++) {
-    const int64_t k = (int64_t)k0 + i - 3;
-    if (k >= 0 && (uint64_t)k < sg.len) garner3(r0[k], r1[k], r2[k], v0[i], v1[i], v2[i]);
+  for (int i = 3; i < CAT_CRT_E + 3; i++) {
+    const uint64_t k = k0 + i - 3;
+    if (k < sg.len) garner3(r0[k], r1[k], r2[k], v0[i], v1[i], v2[i]);
     else { v0[i] = 0; v1[i] = 0; v2[i] = 0; }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    xv[tid + 1][3 * i + 0] = v0[CAT_CRT_E + i];
+    xv[tid + 1][3 * i + 1] = v1[CAT_CRT_E + i];
+    xv[tid + 1][3 * i + 2] = v2[CAT_CRT_E + i];
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const int64_t k = (int64_t)kb + i - 3;
+      uint32_t a0 = 0, a1 = 0, a2 = 0;
+      if (k >= 0) garner3(r0[k], r1[k], r2[k], a0, a1, a2);
+      xv[0][3 * i + 0] = a0;
+      xv[0][3 * i + 1] = a1;
+      xv[0][3 * i + 2] = a2;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    v0[i] = xv[tid][3 * i + 0];
+    v1[i] = xv[tid][3 * i + 1];
+    v2[i] = xv[tid][3 * i + 2];
   }
   uint64_t u[CAT_CRT_E];
   uint32_t yprev = (uint32_t)(((uint64_t)v0[2] + v1[1] + v2[0]) >> 32);   // position k0-1
