@@ -174,8 +174,8 @@ cat_status cat_get_stats(cat_stats* out);
 /* Product schedule per transform-length bucket (the autotuner's output).
  * Products with la, lb <= school_max use the schoolbook kernel; otherwise
  * bucket k = ceil(log2(la + lb - 1)) (at least 6) selects cls[k]:
- * 1 = one workgroup holds the whole transform (k <= 12), 2 = four-step
- * transform with rows of 2^log_row[k] words (8..12, < k) and column passes of
+ * 1 = one workgroup holds the whole transform (k <= 14), 2 = four-step
+ * transform with rows of 2^log_row[k] words (8..14, < k) and column passes of
  * at most 2^log_pass[k] points (4..10).  Every schedule gives the same bits.
  * cat_tune_set(NULL) restores the defaults; CAT_EINVAL for an invalid table.
  * Setting a table drops the cached C(n) plans. */

@@ -272,9 +272,9 @@ bool tuning_valid(const cat_tuning& t) {
   if (t.school_max < 1 || t.school_max > SCHOOL_MAX) return false;
   for (int k = 6; k <= CAT_MAX_LOGN; k++) {
     if (t.cls[k] == CLS_LDS) {
-      if (k > CAT_LDS_LOGT) return false;
+      if (k > CAT_LDS_MAX_LOGT) return false;
     } else if (t.cls[k] == CLS_LARGE) {
-      if (t.log_row[k] < 8 || t.log_row[k] > CAT_LDS_LOGT || k <= t.log_row[k]) return false;
+      if (t.log_row[k] < 8 || t.log_row[k] > CAT_LDS_MAX_LOGT || k <= t.log_row[k]) return false;
       if (t.log_pass[k] < 4 || t.log_pass[k] > 10) return false;
     } else {
       return false;
@@ -852,13 +852,20 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
   const NttTables tb = tables_for(s.logN);
   const uint2 s0 = scale_pair(0, s.logN), s1 = scale_pair(1, s.logN), s2 = scale_pair(2, s.logN);
   if (s.cls == CLS_LDS) {
-    const uint64_t per = NTT_LDS_T >> s.logN;
+    const int lt = std::max(s.logN, CAT_LDS_LOGT);   // tile 2^lt, 2^lt/16 threads
+    const uint64_t per = (1ull << lt) >> s.logN;
     const uint64_t tiles = (cnt + per - 1) / per;
-    {
-      KTime kt("k_ntt_lds", X.st, bfly(9.0 * cnt, s.logN));
-      hipLaunchKernelGGL(k_ntt_lds, dim3((uint32_t)tiles, CAT_NPRIMES), dim3(NTT_LDS_THREADS), 0, X.st, dv, cnt,
-                         s.logN, ain, bin, X.res, X.res_stride, tb, s0, s1, s2);
-    }
+    const dim3 grid((uint32_t)tiles, CAT_NPRIMES), block((1u << lt) / 16);
+    KTime kt("k_ntt_lds", X.st, bfly(9.0 * cnt, s.logN));
+    if (lt == 12)
+      hipLaunchKernelGGL(k_ntt_lds<12>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
+                         s1, s2);
+    else if (lt == 13)
+      hipLaunchKernelGGL(k_ntt_lds<13>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
+                         s1, s2);
+    else
+      hipLaunchKernelGGL(k_ntt_lds<14>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
+                         s1, s2);
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;
@@ -878,9 +885,15 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
   {
     // row DFTs: two forward and one inverse per row, 3 primes
     const double rows = (double)cnt * (1ull << logR1);
+    const int lt = std::max(logM, CAT_LDS_LOGT);
+    const dim3 grid((uint32_t)(cnt << logR1), CAT_NPRIMES), block((1u << lt) / 16);
     KTime kt("k_row", X.st, bfly(9.0 * rows, logM));
-    hipLaunchKernelGGL(k_row, dim3((uint32_t)(cnt << logR1), CAT_NPRIMES), dim3(NTT_ROW_THREADS), 0, X.st, s.logN,
-                       logM, X.F, tb, s0, s1, s2);
+    if (lt == 12)
+      hipLaunchKernelGGL(k_row<12>, grid, block, 0, X.st, s.logN, logM, X.F, tb, s0, s1, s2);
+    else if (lt == 13)
+      hipLaunchKernelGGL(k_row<13>, grid, block, 0, X.st, s.logN, logM, X.F, tb, s0, s1, s2);
+    else
+      hipLaunchKernelGGL(k_row<14>, grid, block, 0, X.st, s.logN, logM, X.F, tb, s0, s1, s2);
   }
   LAUNCHCHK();
   for (int k = pp.P - 1; k >= 0; k--) {

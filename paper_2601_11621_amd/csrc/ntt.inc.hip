@@ -11,20 +11,24 @@
 //    Outputs come out in a fixed digit-reversed order, which the pointwise
 //    product does not care about; the inverse runs the passes backwards with
 //    inverse roots (decimation-in-time networks), which undoes the order.
-//  * N <= 2^12 products run entirely in one workgroup (k_ntt_lds).
-//  * Larger N = L_0 ... L_{P-1} * M with M = 2^12 use Bailey's four-step
+//  * Products with N up to 2^14 can run entirely in one workgroup
+//    (k_ntt_lds: tiles of 2^12, 2^13 or 2^14 slots per operand, one thread per
+//    16 slots; small products share a 2^12 tile).
+//  * Larger N = L_0 ... L_{P-1} * M with M = 2^8 .. 2^14 use Bailey's four-step
 //    split (1990) applied recursively: k_pass_fwd transforms the strided
 //    columns of one level of the split (packing limbs on the fly in the first)
 //    and applies its twiddles; k_row transforms each M-point row of both
 //    operands, multiplies them pointwise and inverse-transforms the row;
 //    k_pass_inv undoes the column levels, the outermost writing exact residues.
+//    Which form a length bucket takes, and its row and column-pass lengths,
+//    come from the per-bucket schedule (defaults, or the autotuner's table).
 //  * In-pass twiddles are (w, wq) Montgomery pairs in tables laid out so that
 //    neighbouring lanes read neighbouring entries; the column-level twiddles
 //    omega_S^{j*f} come from two small tables of omega_{2^27} powers.
 // The residues of the three primes are then recombined by k_crt (Garner's
 // method) into 96-bit coefficient values, summed into limbs and carried with
 // a wave64 ballot carry-lookahead; blocks of one product are joined by
-// k_carry_scan / k_carry_apply.
+// k_carry_fix.
 
 __constant__ PrimeC c_primes[CAT_NPRIMES];
 __constant__ CrtC c_crt;
@@ -195,7 +199,8 @@ __device__ __forceinline__ void pass_inv(uint32_t* lds, uint32_t ngroups, uint32
 __host__ __device__ constexpr int pass_logr(int logS) { return (logS % 4) ? (logS % 4) : 4; }
 // offset of the table of size 2^s inside a per-prime pass-table block
 __host__ __device__ constexpr uint32_t tws_off(int s) { return (1u << s) - 2u; }
-#define TWS_ENTRIES 8190u   // sum over s = 1..12 of 2^s
+#define CAT_LDS_MAX_LOGT 14  // largest transform held by one workgroup (both operands, 2^14 each)
+#define TWS_ENTRIES 32766u   // sum over s = 1..14 of 2^s
 
 // Full forward transform of size 2^logS on every sub-problem of an LDS tile
 // with `total` elements (all columns), passes from size 2^logS down.
@@ -270,18 +275,20 @@ struct NttTables {
 // Whole product in one workgroup, N = 2^logN <= 2^12.  The tile holds
 // T = 2^12 coefficient slots = T/N products; grid (tiles, prime).
 // Writes res[prime][r_off + j] = (a*b)_j mod p for j < la+lb.
-#define NTT_LDS_T 4096u
-#define NTT_LDS_THREADS 256
-__global__ void __launch_bounds__(NTT_LDS_THREADS, 4)
+// Tile of 2^LOGT coefficient slots (T/N products), 2^LOGT/16 threads, so every
+// radix-16 pass gives each thread two groups over the two operands.
+template <int LOGT>
+__global__ void __launch_bounds__((1 << LOGT) / 16)
 k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
           uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
-  __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
-  __shared__ MulDesc ds[NTT_LDS_T / 64];
+  constexpr uint32_t TT = 1u << LOGT;
+  __shared__ uint32_t lds[lds_pad(2 * TT)];
+  __shared__ MulDesc ds[64];
   const uint32_t prime = blockIdx.y;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
   const uint32_t N = 1u << logN;
-  const uint32_t per = NTT_LDS_T >> logN;          // products per tile
+  const uint32_t per = TT >> logN;                 // products per tile (<= 64)
   const uint64_t m0 = (uint64_t)blockIdx.x * per;
   const uint32_t cnt = (uint32_t)min((uint64_t)per, nmul - m0);
   for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ds[i] = dv.get(m0 + i);
@@ -293,23 +300,23 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
     uint32_t x = j < d.la ? reduce_limb(ain[d.a_off + j], p) : 0u;
     uint32_t y = j < d.lb ? reduce_limb(bin[d.b_off + j], p) : 0u;
     lds[lds_pad(t)] = x;
-    lds[lds_pad(NTT_LDS_T + t)] = y;
+    lds[lds_pad(TT + t)] = y;
   }
   // unused slots of a partial tile stay untouched: their sub-problems are
   // independent and never read back
   __syncthreads();
   const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
   const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
-  // A occupies [0, T), B [NTT_LDS_T, NTT_LDS_T + T); transform both as one tile
-  if (T == NTT_LDS_T) {
-    ntt_fwd_tile<true>(lds, logN, 2 * NTT_LDS_T, 0, tws, pc);
+  // A occupies [0, T), B [TT, TT + T); transform both as one tile
+  if (T == TT) {
+    ntt_fwd_tile<true>(lds, logN, 2 * TT, 0, tws, pc);
   } else {
     ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
-    ntt_fwd_tile<true>(lds + lds_pad(NTT_LDS_T), logN, T, 0, tws, pc);
+    ntt_fwd_tile<true>(lds + lds_pad(TT), logN, T, 0, tws, pc);
   }
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
   for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(NTT_LDS_T + t)];
+    uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(TT + t)];
     lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
   }
   __syncthreads();
@@ -446,14 +453,16 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
     for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
 }
 
-#define NTT_ROW_THREADS 256
-__global__ void __launch_bounds__(NTT_ROW_THREADS, 4)
+// Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
+template <int LOGT>
+__global__ void __launch_bounds__((1 << LOGT) / 16)
 k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
-  __shared__ uint32_t lds[lds_pad(2 * NTT_LDS_T)];
+  constexpr uint32_t TT = 1u << LOGT;
+  __shared__ uint32_t lds[lds_pad(2 * TT)];
   const uint32_t prime = blockIdx.y;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
-  const int logR1 = logN - logM;   // rows of M = 2^logM <= 2^12 elements
+  const int logR1 = logN - logM;
   const uint32_t M = 1u << logM;
   const uint64_t N = 1ull << logN;
   const uint64_t m = blockIdx.x >> logR1;

@@ -19,7 +19,7 @@
 // Every group ends up with its primes ascending; G_1 = {seeds with e = 1}
 // followed by the large primes with e = 1.
 
-#define SIEVE_SEG_LOG 15
+#define SIEVE_SEG_LOG 14
 #define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment
 #define SIEVE_WORDS (SIEVE_SEG / 32)
 #define SIEVE_THREADS 256
@@ -64,8 +64,9 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* t
   return r;
 }
 
-__device__ __forceinline__ uint64_t legendre_dev(uint64_t m, uint64_t p) {
-  uint64_t s = 0;
+// Legendre's sum v_p(m!) = sum_k floor(m / p^k) by repeated division; m < 2^32.
+__device__ __forceinline__ uint32_t legendre_dev(uint32_t m, uint32_t p) {
+  uint32_t s = 0;
   while (m) { m /= p; s += m; }
   return s;
 }
@@ -75,16 +76,24 @@ __global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t
                                                 GroupTable* gt) {
   __shared__ uint8_t comp[65536];
   __shared__ uint32_t tmp[40];
+  __shared__ uint32_t small[64];
+  __shared__ uint32_t nsmall;
   const uint32_t T = blockDim.x, tid = threadIdx.x;
   for (uint32_t i = tid; i <= s; i += T) comp[i] = (i < 2) ? 1 : 0;
-  __syncthreads();
+  // primes up to isqrt(s) <= 255 by trial division, one thread per candidate
   uint32_t r = 0;
   while ((r + 1) * (r + 1) <= s) r++;
-  for (uint32_t q = 2; q <= r; q++) {
+  if (tid == 0) nsmall = 0;
+  __syncthreads();
+  if (tid >= 2 && tid <= r) {
     bool isq = true;
-    for (uint32_t d = 2; d * d <= q; d++)
-      if (q % d == 0) { isq = false; break; }
-    if (!isq) continue;
+    for (uint32_t d = 2; d * d <= tid; d++)
+      if (tid % d == 0) { isq = false; break; }
+    if (isq) small[atomicAdd(&nsmall, 1u)] = tid;
+  }
+  __syncthreads();
+  for (uint32_t k = 0; k < nsmall; k++) {
+    const uint32_t q = small[k];
     for (uint32_t m = q * q + tid * q; m <= s; m += T * q) comp[m] = 1;
   }
   __syncthreads();
@@ -100,16 +109,18 @@ __global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t
   if (tid == 0) gt->nseeds = total;
   __syncthreads();
   __threadfence_block();
+  // exponents by Legendre's sums; 2n < 2^32 and n + 1 < 2^32
+  const uint32_t n2 = (uint32_t)(2 * n), n1 = (uint32_t)n, np1 = (uint32_t)(n + 1);
   for (uint32_t k = tid; k < total; k += T) {
-    uint64_t q = seeds[k];
-    int64_t a = (int64_t)legendre_dev(2 * n, q);
-    int64_t b = (int64_t)legendre_dev(n, q);
-    uint64_t m = n + 1;
-    int64_t c = 0;
+    const uint32_t q = seeds[k];
+    const int32_t a = (int32_t)legendre_dev(n2, q);
+    const int32_t b = (int32_t)legendre_dev(n1, q);
+    uint32_t m = np1;
+    int32_t c = 0;
     while (m % q == 0) { m /= q; c++; }
-    int64_t e = a - 2 * b - c;
+    const int32_t e = a - 2 * b - c;
     if (e < 0) atomicOr(&gt->err, CAT_DEVERR_NEG_EXP);
-    seed_e[k] = (int32_t)e;
+    seed_e[k] = e;
   }
 }
 

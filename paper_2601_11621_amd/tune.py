@@ -6,15 +6,17 @@ in a tree level) and keeps the fastest:
 
   * k <= 8:  schoolbook kernel vs the one-workgroup transform (this sets the
              schoolbook threshold on operand length);
-  * k <= 12: one-workgroup transform vs the four-step transform with rows of
+  * k <= 14: one-workgroup transform vs the four-step transform with rows of
              2^8 .. 2^(k-1);
-  * k > 12:  four-step transform, rows of 2^10 / 2^11 / 2^12, column passes of
-             at most 2^6 / 2^8 / 2^10 points.
+  * k > 14:  four-step transform, rows of 2^10 .. 2^14, column passes of at
+             most 2^6 / 2^8 / 2^10 points.
 
 Every candidate's output is compared bit for bit with the default schedule's;
 a candidate that differs is an error (schedules change speed, never bits).
 
     python -m paper_2601_11621_amd.tune --max-k 24 --out paper_2601_11621_amd/tuning/gfx950.json
+    python -m paper_2601_11621_amd.tune --min-k 25 --max-k 27 \
+        --merge paper_2601_11621_amd/tuning/gfx950.json --out paper_2601_11621_amd/tuning/gfx950.json
 """
 from __future__ import annotations
 
@@ -43,7 +45,11 @@ def _time_plan(cat, a_off, b_off, da, db, c, reps):
     return float(np.median(ts)) * 1e3
 
 
-def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool = True) -> dict:
+def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool = True, min_k: int = 7,
+             start: dict | None = None) -> dict:
+    """Tune buckets min_k..max_k.  `start` (a previous result) supplies the
+    table and measurements of the other buckets; the schoolbook threshold is
+    only re-decided when min_k <= 8."""
     import torch
 
     import paper_2601_11621_amd as cat
@@ -51,11 +57,11 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
     cat.init(0, tuned=False)
     cat.set_tuning(None)
     base = cat.get_tuning()
-    table = json.loads(json.dumps(base))
-    meas = {}
+    table = json.loads(json.dumps(start["table"] if start else base))
+    meas = {int(k): v for k, v in (start or {}).get("ms", {}).items()}
     rng = np.random.default_rng(2024)
-    school_max = 0
-    for k in range(7, max_k + 1):
+    school_max = 0 if min_k <= 8 else table["school_max"]
+    for k in range(min_k, max_k + 1):
         half = 1 << (k - 1)
         count = max(1, 1 << max(0, total_log2 - k))
         la = np.full(count, half, dtype=np.int64)
@@ -75,13 +81,13 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
         cands = []
         if half <= 128:
             cands.append(("school", {"school_max": 128}))
-        if k <= 12:
+        if k <= 14:
             cands.append(("lds", {"school_max": min(half - 1, 128) if half <= 128 else 128, "cls": 1}))
             for lr in range(8, k):
                 cands.append(("rows%d" % lr, {"school_max": min(half - 1, 128) if half <= 128 else 128, "cls": 2,
                                               "log_row": lr, "log_pass": 10}))
         else:
-            for lr in (10, 11, 12):
+            for lr in (10, 11, 12, 13, 14):
                 for lp in (6, 8, 10):
                     if k - lr > 0:
                         cands.append(("rows%d_pass%d" % (lr, lp),
@@ -114,6 +120,7 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
                     table["log_row"][k] = cfg["log_row"]
                     table["log_pass"][k] = cfg["log_pass"]
         meas[k] = {n: round(v[0], 4) for n, v in res.items()}
+        meas = dict(sorted(meas.items()))
         if verbose:
             print("bucket 2^%d (%d products of %d limbs): best %s  %s" % (k, count, half, best, meas[k]),
                   flush=True)
@@ -129,12 +136,19 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--min-k", type=int, default=7)
     ap.add_argument("--max-k", type=int, default=24)
+    ap.add_argument("--merge", default=None, help="previous result: keep its other buckets")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--total-log2", type=int, default=22, help="coefficient slots per bucket (log2)")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
                                                   "gfx950.json"))
     args = ap.parse_args()
-    res = autotune(args.max_k, args.reps)
+    start = None
+    if args.merge:
+        with open(args.merge) as f:
+            start = json.load(f)
+    res = autotune(args.max_k, args.reps, total_log2=args.total_log2, min_k=args.min_k, start=start)
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)

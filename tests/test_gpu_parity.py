@@ -112,6 +112,17 @@ def test_mul_random_batch_uneven(cat):
     _run_batch(cat, la, lb, ["rand"] * 300, "batched", seed=8)
 
 
+def test_mul_wide_tiles(cat):
+    """Products of 2^12 .. 2^14 coefficient slots, enough of them that the
+    one-workgroup transforms of 2^13 and 2^14 slots run (when the schedule
+    selects them) next to the 2^12 tiles and the four-step form."""
+    rng = np.random.default_rng(12)
+    la = np.rint(2 ** rng.uniform(11, 13, 240)).astype(np.int64).tolist()
+    lb = np.rint(2 ** rng.uniform(11, 13, 240)).astype(np.int64).tolist()
+    la[:3], lb[:3] = [8192, 4097, 1], [8192, 4096, 16383]
+    _run_batch(cat, la, lb, ["ones", "rand", "rand"] + ["rand"] * 237, "batched", seed=13)
+
+
 def test_mul_plan_graph_replays(cat):
     import torch
 
@@ -197,10 +208,30 @@ def test_residues_kernel(cat):
         assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1))
 
 
-def test_schedules_change_speed_not_bits(cat):
-    """A non-default product schedule (small schoolbook threshold, four-step
-    transforms with short rows and short column passes from 2^11 up) gives the
-    same C(n) and the same products as the default one."""
+def _schedule_short(t):
+    """small schoolbook threshold, four-step transforms with short rows and
+    short column passes from 2^11 up"""
+    t["school_max"] = 32
+    for k in range(11, 28):
+        t["cls"][k] = 2
+        t["log_row"][k] = 10
+        t["log_pass"][k] = 6
+
+
+def _schedule_wide(t):
+    """one-workgroup transforms of 2^13 and 2^14 slots (512 and 1024 threads),
+    four-step rows of 2^13 or 2^14 words above"""
+    t["cls"][13] = t["cls"][14] = 1
+    for k in range(15, 28):
+        t["cls"][k] = 2
+        t["log_row"][k] = 13 + (k & 1)
+        t["log_pass"][k] = 8
+
+
+@pytest.mark.parametrize("schedule", [_schedule_short, _schedule_wide], ids=["short", "wide"])
+def test_schedules_change_speed_not_bits(cat, schedule):
+    """A non-default product schedule gives the same C(n) and the same
+    products as the default one."""
     import torch
 
     base = cat.get_tuning()
@@ -216,11 +247,7 @@ def test_schedules_change_speed_not_bits(cat):
     c0, _ = cat.mul_batched(da, a_off, db, b_off)
     c0 = c0.clone()
     t = cat.get_tuning()
-    t["school_max"] = 32
-    for k in range(11, 28):
-        t["cls"][k] = 2
-        t["log_row"][k] = 10
-        t["log_pass"][k] = 6
+    schedule(t)
     try:
         cat.set_tuning(t)
         for n in ns:
