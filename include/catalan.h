@@ -188,6 +188,14 @@ typedef struct {
 cat_status cat_tune_set(const cat_tuning* t);
 cat_status cat_tune_get(cat_tuning* t);
 
+/* Carry look-back between CRT blocks (diagnostics and tests).  A block reads
+ * the generate / propagate pair of the block before it from a flag that block
+ * publishes, polling it at most `polls` times (default 16, at most 2^20), and
+ * otherwise recomputes the pair from that block's residues; the result is the
+ * same either way, and polls = 0 always recomputes.  Cached C(n) plans are
+ * dropped; existing product plans keep the value they were recorded with. */
+cat_status cat_lookback_polls_set(uint32_t polls);
+
 /* Kernel timer (measurement only).  cat_timer_set(name) brackets every later
  * launch of the named kernel ("k_ntt_lds", "k_row", "k_pass_fwd", "k_pass_inv",
  * "k_crt", "k_school", "k_leaf") with HIP events on the stream it is launched

@@ -30,7 +30,7 @@ EXPORTS = [
     "catalan_exact", "catalan_exact_ex", "cat_mul_plan_create", "cat_mul_plan_exec",
     "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues", "cat_timer_set", "cat_timer_get",
     "catalan_begin", "cat_ticket_query", "catalan_continue", "catalan_end", "cat_ticket_release",
-    "cat_tune_set", "cat_tune_get",
+    "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
 ]
 
 
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "catalan_end": ([vp, szp], st),
         "cat_ticket_release": ([vp], st),
         "cat_tune_set": ([ctypes.POINTER(cat_tuning)], st),
+        "cat_lookback_polls_set": ([ctypes.c_uint32], st),
         "cat_tune_get": ([ctypes.POINTER(cat_tuning)], st),
     }
     for name, (args, res) in sig.items():
@@ -168,6 +169,12 @@ def get_tuning() -> dict:
     _check(load().cat_tune_get(ctypes.byref(t)), "cat_tune_get")
     return {"school_max": t.school_max, "cls": list(t.cls), "log_row": list(t.log_row),
             "log_pass": list(t.log_pass)}
+
+
+def set_lookback_polls(polls: int) -> None:
+    """Polls of a predecessor's carry flag before a CRT block recomputes it
+    (0: always recompute).  Same results either way."""
+    _check(load().cat_lookback_polls_set(int(polls)), "cat_lookback_polls_set")
 
 
 def set_tuning(d: Optional[dict]) -> None:

@@ -130,3 +130,32 @@ struct CrtSeg {
 #define CAT_DEVERR_CARRY_OUT 1u     // a product overflowed its la+lb limbs
 #define CAT_DEVERR_NEG_EXP 2u       // negative exponent (C(n) not integral)
 #define CAT_DEVERR_BOUNDS 4u        // a prime count exceeded its buffer
+#define CAT_DEVERR_SCAN 8u          // a carry look-back gave up waiting (never expected)
+
+// Ranges copied unchanged from one arena to the other (the last node of a
+// group with an odd node count is carried up a level).  Kernels that take a
+// CopyList run extra workgroups for it: workgroup cb (counted from the first
+// copy workgroup) copies chunk cb of TAIL_CHUNK words, ranges in order.
+#define TAIL_CHUNK 4096u
+struct CopyList {
+  uint32_t n;
+  uint64_t off[CAT_MAX_GROUPS];
+  uint64_t len[CAT_MAX_GROUPS];
+};
+inline uint32_t tail_blocks(const CopyList& cl) {
+  uint64_t b = 0;
+  for (uint32_t r = 0; r < cl.n; r++) b += (cl.len[r] + TAIL_CHUNK - 1) / TAIL_CHUNK;
+  return (uint32_t)b;
+}
+__device__ __forceinline__ void copy_tail_block(const CopyList& cl, const uint32_t* __restrict__ in,
+                                                uint32_t* __restrict__ out, uint32_t cb) {
+  for (uint32_t r = 0; r < cl.n; r++) {
+    const uint64_t nb = (cl.len[r] + TAIL_CHUNK - 1) / TAIL_CHUNK;
+    if (cb < nb) {
+      const uint64_t k0 = (uint64_t)cb * TAIL_CHUNK, k1 = min(k0 + (uint64_t)TAIL_CHUNK, cl.len[r]);
+      for (uint64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) out[cl.off[r] + k] = in[cl.off[r] + k];
+      return;
+    }
+    cb -= (uint32_t)nb;
+  }
+}

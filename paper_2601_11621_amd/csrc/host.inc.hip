@@ -267,6 +267,7 @@ cat_tuning default_tuning() {
   return t;
 }
 cat_tuning g_tune = default_tuning();
+uint32_t g_crt_polls = CAT_SCAN_POLLS;
 
 bool tuning_valid(const cat_tuning& t) {
   if (t.school_max < 1 || t.school_max > SCHOOL_MAX) return false;
@@ -320,7 +321,6 @@ struct Stage {
   std::vector<uint32_t> host_pref;
   SegView sv{};            // CRT segments (inline or device tables), set by upload_tables
   uint32_t nseg = 0, nblk = 0;
-  bool need_fix = false;
   // carried-up nodes
   CopyList tails{};
   uint64_t tail_in_base = 0, tail_out_base = 0;
@@ -349,11 +349,9 @@ MulDesc tree_desc(const TreeLevel& t, uint64_t i) {
 void build_crt_segs(Stage& s) {
   s.host_pref.clear();
   uint32_t b = 0;
-  s.need_fix = false;
   for (const CrtSeg& sg : s.host_segs) {
     s.host_pref.push_back(b);
     const uint64_t nb = (sg.len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK;
-    if (nb > 1) s.need_fix = true;
     b += (uint32_t)nb;
   }
   s.host_pref.push_back(b);
@@ -369,11 +367,18 @@ struct Layout {
   uint64_t Kmax = 0, post_cap = 0, res_len = 0, F_words = 0, nblk_max = 0;
   size_t primes = 0, arenaA = 0, arenaB = 0, post = 0, res = 0, F = 0;       // in uint32 units
   size_t seeds = 0, seed_e = 0, seg_cnt = 0, seg_off = 0, bitmap = 0;        // in uint32 units
-  size_t gtab = 0, bsum = 0, cin = 0, err = 0, top = 0;                      // bytes
+  size_t gtab = 0, top = 0, err = 0, ctl_words = 0;                         // bytes (ctl_words: uint32)
   size_t total = 0;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// byte offsets inside the control block
+#define CTL_TOP 512
+#define CTL_ERR 520
+#define CTL_READ 528
+#define CTL_FLAGS 528
+static_assert(sizeof(GroupTable) <= CTL_TOP, "group table must fit the control block head");
 
 Layout make_layout(uint64_t n) {
   Layout L;
@@ -406,11 +411,13 @@ Layout make_layout(uint64_t n) {
   L.seg_cnt = take((L.nseg + 1) * 4) / 4;
   L.seg_off = take((L.nseg + 1) * 4) / 4;
   L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
-  L.gtab = take(sizeof(GroupTable));
-  L.bsum = take(L.nblk_max);
-  L.cin = take(L.nblk_max);
-  L.err = take(64);
-  L.top = take(64);
+  // control block, cleared by Phase 1 (k_seeds): group table | top | error
+  // word | CRT look-back flags; the first CTL_READ bytes go back to the host
+  // in one copy
+  L.gtab = take(CTL_FLAGS + 4 * L.nblk_max);
+  L.top = L.gtab + CTL_TOP;
+  L.err = L.gtab + CTL_ERR;
+  L.ctl_words = (CTL_FLAGS + 4 * L.nblk_max) / 4;
   L.total = off;
   return L;
 }
@@ -808,42 +815,46 @@ struct Exec {
   uint32_t* res = nullptr;
   uint64_t res_stride = 0;
   uint32_t* F = nullptr;
-  uint8_t* bsum = nullptr;
-  uint8_t* cin = nullptr;
+  uint32_t* flags = nullptr;   // CRT look-back flags (cleared when the call starts)
+  uint32_t crt_epoch = 0;      // CRT launches so far in this call
   uint32_t* err = nullptr;
   hipStream_t st = nullptr;
   uint64_t launches = 0;
 };
 
-cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, bool fix) {
+cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const CopyList* tails = nullptr,
+                      const uint32_t* tin = nullptr, uint32_t* tout = nullptr) {
+  static const CopyList none{};
+  const CopyList& cl = tails ? *tails : none;
+  const uint32_t grid = nblk + tail_blocks(cl);
+  if (grid == 0) return CAT_OK;
   {
     KTime kt("k_crt", X.st, (double)nblk * CAT_CRT_BLOCK);
-    hipLaunchKernelGGL(k_crt, dim3(nblk), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.bsum,
-                       X.err);
+    X.crt_epoch++;
+    hipLaunchKernelGGL(k_crt, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk, X.flags,
+                       X.crt_epoch, g_crt_polls, cl, tin, tout, X.err);
   }
   LAUNCHCHK();
   X.launches++;
-  if (fix) {
-    hipLaunchKernelGGL(k_carry_fix, dim3(1), dim3(1024), 0, X.st, sv, X.bsum, nblk, X.cin, out, X.err);
-    LAUNCHCHK();
-    X.launches += 1;
-  }
   return CAT_OK;
 }
 
 // Products of a stage given by `dv` (cnt of them): the NTT or schoolbook part.
 uint32_t* out_base(Exec& X, const Stage& s) { return X.C ? X.C : X.W + s.c_base; }
 
-cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt) {
+cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, bool with_tails = false) {
   const uint32_t* ain = X.A ? X.A : X.W + s.a_base;
   const uint32_t* bin = X.B ? X.B : X.W + s.b_base;
   uint32_t* out = out_base(X, s);
   if (s.cls == CLS_SCHOOL) {
+    static const CopyList none{};
+    const CopyList& cl = with_tails ? s.tails : none;
     const uint64_t blocks = (cnt + SCHOOL_WAVES - 1) / SCHOOL_WAVES;
     {
       KTime kt("k_school", X.st, (double)s.limbs);
-      hipLaunchKernelGGL(k_school, dim3((uint32_t)blocks), dim3(64 * SCHOOL_WAVES), 0, X.st, dv, cnt, ain, bin, out,
-                         X.err);
+      hipLaunchKernelGGL(k_school, dim3((uint32_t)blocks + tail_blocks(cl)), dim3(64 * SCHOOL_WAVES), 0, X.st, dv,
+                         cnt, ain, bin, out, X.err, (uint32_t)blocks, cl, X.W + s.tail_in_base,
+                         X.W + s.tail_out_base);
     }
     LAUNCHCHK();
     X.launches++;
@@ -935,8 +946,12 @@ cat_status run_stage_batched(Exec& X, const Stage& s) {
     return CAT_OK;
   }
   if (s.nmul > 0) {
-    STCHK(launch_products(X, s, s.dv, s.nmul));
-    if (s.cls != CLS_SCHOOL) STCHK(launch_crt(X, out_base(X, s), stage_segs(s), s.nblk, s.need_fix));
+    // the tail copies ride along with the last kernel of the level
+    STCHK(launch_products(X, s, s.dv, s.nmul, s.cls == CLS_SCHOOL));
+    if (s.cls != CLS_SCHOOL)
+      STCHK(launch_crt(X, out_base(X, s), stage_segs(s), s.nblk, &s.tails, X.W + s.tail_in_base,
+                       X.W + s.tail_out_base));
+    return CAT_OK;
   }
   return copy_tails(X, s);
 }
@@ -971,7 +986,7 @@ cat_status run_stage_plain(Exec& X, const Stage& s) {
       const uint32_t nb = (uint32_t)((sv.iseg[0].len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
       sv.ipref[0] = 0;
       sv.ipref[1] = nb;
-      STCHK(launch_crt(X, out_base(X, s), sv, nb, nb > 1));
+      STCHK(launch_crt(X, out_base(X, s), sv, nb));
     }
   }
   return copy_tails(X, s);
@@ -1013,10 +1028,8 @@ cat_status run_phase2(Exec& X, Plan& P, bool plain) {
 cat_status run_phase1(const Layout& Ly, char* wb, uint32_t* primes, uint64_t cap, hipStream_t st, uint64_t* launches) {
   uint32_t* W = (uint32_t*)wb;
   GroupTable* gt = (GroupTable*)(wb + Ly.gtab);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)gt, (uint64_t)(sizeof(GroupTable) / 4), 0u);
-  LAUNCHCHK();
   hipLaunchKernelGGL(k_seeds, dim3(1), dim3(1024), 0, st, Ly.n, (uint32_t)Ly.s, W + Ly.seeds, (int32_t*)(W + Ly.seed_e),
-                     gt);
+                     gt, (uint32_t*)gt, (uint64_t)Ly.ctl_words);
   LAUNCHCHK();
   if (Ly.nseg > 0) {
     hipLaunchKernelGGL(k_sieve, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0, Ly.i_end,
@@ -1032,7 +1045,7 @@ cat_status run_phase1(const Layout& Ly, char* wb, uint32_t* primes, uint64_t cap
                        primes, cap);
     LAUNCHCHK();
   }
-  *launches += Ly.nseg > 0 ? 5 : 3;
+  *launches += Ly.nseg > 0 ? 4 : 2;
   return CAT_OK;
 }
 
@@ -1078,9 +1091,8 @@ Exec make_exec(const Layout& Ly, char* wb, hipStream_t st) {
   X.res = X.W + Ly.res;
   X.res_stride = Ly.res_len;
   X.F = X.W + Ly.F;
-  X.bsum = (uint8_t*)(wb + Ly.bsum);
-  X.cin = (uint8_t*)(wb + Ly.cin);
   X.err = (uint32_t*)(wb + Ly.err);
+  X.flags = (uint32_t*)(wb + Ly.gtab + CTL_FLAGS);
   X.st = st;
   return X;
 }
@@ -1089,6 +1101,8 @@ Exec make_exec(const Layout& Ly, char* wb, hipStream_t st) {
 // Generic batches c_i = a_i * b_i: products bucketed by class and transform
 // length, one stage (launch sequence) per bucket.
 // ----------------------------------------------------------------------------
+// byte offsets inside a product plan's control block
+#define MUL_CTL_FLAGS 16
 struct MulPlanImpl {
   uint32_t batch = 0;
   uint32_t flags = 0;
@@ -1096,7 +1110,7 @@ struct MulPlanImpl {
   CopyList zeros{};                          // unused (zero-length products are rejected)
   void* dev = nullptr;
   uint64_t res_len = 0, F_words = 0, nblk_max = 0;
-  size_t off_res = 0, off_F = 0, off_bsum = 0, off_cin = 0, off_err = 0, total = 0;
+  size_t off_res = 0, off_F = 0, off_ctl = 0, total = 0;   // control block: error word | look-back flags
   uint64_t products = 0, product_limbs = 0;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
 };
@@ -1153,9 +1167,7 @@ cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t
   };
   M->off_res = take(3 * (M->res_len + 64) * 4);
   M->off_F = take(M->F_words * 4);
-  M->off_bsum = take(M->nblk_max);
-  M->off_cin = take(M->nblk_max);
-  M->off_err = take(64);
+  M->off_ctl = take(MUL_CTL_FLAGS + 4 * M->nblk_max);
   M->total = off;
   std::vector<Stage*> all;
   for (auto& st : M->stages) all.push_back(&st);
@@ -1180,15 +1192,16 @@ Exec mul_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_b, uint32_t
   X.res = (uint32_t*)(wb + M->off_res);
   X.res_stride = M->res_len + 64;
   X.F = (uint32_t*)(wb + M->off_F);
-  X.bsum = (uint8_t*)(wb + M->off_bsum);
-  X.cin = (uint8_t*)(wb + M->off_cin);
-  X.err = (uint32_t*)(wb + M->off_err);
+  X.err = (uint32_t*)(wb + M->off_ctl);
+  X.flags = (uint32_t*)(wb + M->off_ctl + MUL_CTL_FLAGS);
   X.st = st;
   return X;
 }
 
 cat_status mul_plan_record(MulPlanImpl* M, Exec& X, bool plain) {
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, X.st, X.err, (uint64_t)1, 0u);
+  const uint64_t words = (MUL_CTL_FLAGS + 4 * M->nblk_max) / 4;
+  hipLaunchKernelGGL(k_fill, dim3((uint32_t)std::min<uint64_t>((words + 255) / 256, 256)), dim3(256), 0, X.st, X.err,
+                     words, 0u);
   LAUNCHCHK();
   X.launches++;
   for (const Stage& s : M->stages) STCHK(plain ? run_stage_plain(X, s) : run_stage_batched(X, s));
@@ -1340,6 +1353,18 @@ cat_status cat_tune_set(const cat_tuning* t) {
   return CAT_OK;
 }
 
+cat_status cat_lookback_polls_set(uint32_t polls) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  if (polls > (1u << 20)) return CAT_EINVAL;
+  g_crt_polls = polls;
+  // cached graphs of C(n) carry the old value
+  if (!g.plans.empty()) HIPCHK(hipDeviceSynchronize());
+  for (auto& kv : g.plans) free_plan(kv.second);
+  g.plans.clear();
+  g.plan_order.clear();
+  return CAT_OK;
+}
+
 cat_status cat_tune_get(cat_tuning* t) {
   if (!t) return CAT_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(g.mu);
@@ -1451,20 +1476,13 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
           [&](hipStream_t cs) -> cat_status {
             STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, cs, &nl));
             Exec E = make_exec(Ly, wb, cs);
-            hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, cs, E.err, (uint64_t)1, 0u);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, cs, (uint32_t*)top, (uint64_t)2, 0u);
-            LAUNCHCHK();
             STCHK(run_phase2(E, *P, false));
             const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
-            hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, cs, E.W + P->result_pos, P->result_cap,
-                               top);
-            LAUNCHCHK();
             const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
-            hipLaunchKernelGGL(k_copy, dim3((uint32_t)std::min<uint64_t>((ncopy + 255) / 256, 2048)), dim3(256), 0,
-                               cs, E.W + P->result_pos, d_limbs, ncopy);
+            hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, cs, E.W + P->result_pos, P->result_cap,
+                               top, d_limbs, ncopy);
             LAUNCHCHK();
-            nl += E.launches + 4;
+            nl += E.launches + 1;
             return CAT_OK;
           },
           &ge));
@@ -1472,17 +1490,16 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
       launches = nl;
     }
     HIPCHK(hipGraphLaunch(ge, st));
+    // group table, top and error word in one copy
     char* pin = (char*)g.pin;
-    HIPCHK(hipMemcpyAsync(pin, wb + Ly.gtab, sizeof(GroupTable), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(pin + 1024, wb + Ly.top, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(pin + 1032, wb + Ly.err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin, wb + Ly.gtab, CTL_READ, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     GroupTable gt;
     memcpy(&gt, pin, sizeof(GroupTable));
     uint64_t L = 0;
     uint32_t derr = 0;
-    memcpy(&L, pin + 1024, 8);
-    memcpy(&derr, pin + 1032, 4);
+    memcpy(&L, pin + CTL_TOP, 8);
+    memcpy(&derr, pin + CTL_ERR, 4);
     if (gt.err || find_plan(n, gt) != P) return CAT_EINTERNAL;
     if (derr || L == 0) return CAT_EINTERNAL;
     *n_limbs = (size_t)L;
@@ -1520,14 +1537,10 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
     return CAT_OK;
   }
   auto record = [&](Exec& E) -> cat_status {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, E.st, E.err, (uint64_t)1, 0u);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, E.st, (uint32_t*)top, (uint64_t)2, 0u);
-    LAUNCHCHK();
-    E.launches += 2;
     STCHK(run_phase2(E, *P, plain));
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
-    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top,
+                       (uint32_t*)nullptr, (uint64_t)0);
     LAUNCHCHK();
     E.launches++;
     return CAT_OK;
@@ -1569,9 +1582,8 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
     STCHK(record(X));
     launches += X.launches;
   }
-  // top limb index and error word
-  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.top, 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync((char*)g.pin + 8, X.err, 4, hipMemcpyDeviceToHost, st));
+  // top limb index and error word (adjacent in the control block)
+  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.top, 12, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   uint64_t L = 0;
   uint32_t derr = 0;
@@ -1630,7 +1642,7 @@ cat_status cat_mul_plan_check(cat_mul_plan plan, void* d_work, void* stream) {
   std::lock_guard<std::recursive_mutex> lk(g.mu);
   MulPlanImpl* M = (MulPlanImpl*)plan;
   hipStream_t st = (hipStream_t)stream;
-  HIPCHK(hipMemcpyAsync(g.pin, (char*)d_work + M->off_err, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(g.pin, (char*)d_work + M->off_ctl, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   uint32_t e = 0;
   memcpy(&e, g.pin, 4);
@@ -1677,7 +1689,7 @@ cat_status bigint_mul_batched_ex(uint32_t batch, const uint32_t* d_a, const uint
   }
   if (s == CAT_OK && batch > 0) {
     uint32_t derr = 0;
-    if (hipMemcpy(&derr, (char*)d_work + M->off_err, 4, hipMemcpyDeviceToHost) != hipSuccess) s = CAT_EDEVICE;
+    if (hipMemcpy(&derr, (char*)d_work + M->off_ctl, 4, hipMemcpyDeviceToHost) != hipSuccess) s = CAT_EDEVICE;
     else if (derr) s = CAT_EINTERNAL;
   }
   cat_stats stt{};
@@ -1800,20 +1812,14 @@ cat_status catalan_continue(cat_ticket ticket, uint32_t* d_limbs, size_t cap) {
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, t->st, d_limbs, (uint64_t)1, 1u);
     LAUNCHCHK();
   } else {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, t->st, X.err, (uint64_t)1, 0u);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, t->st, (uint32_t*)top, (uint64_t)2, 0u);
-    LAUNCHCHK();
     STCHK(run_phase2(X, *P, false));
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
-    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, t->st, X.W + P->result_pos, P->result_cap, top);
-    LAUNCHCHK();
     const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
-    hipLaunchKernelGGL(k_copy, dim3((uint32_t)std::min<uint64_t>((ncopy + 255) / 256, 2048)), dim3(256), 0, t->st,
-                       X.W + P->result_pos, d_limbs, ncopy);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, t->st, X.W + P->result_pos, P->result_cap, top,
+                       d_limbs, ncopy);
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(t->pin + 512, t->wb + t->Ly.top, 8, hipMemcpyDeviceToHost, t->st));
-    HIPCHK(hipMemcpyAsync(t->pin + 520, t->wb + t->Ly.err, 4, hipMemcpyDeviceToHost, t->st));
+    // top and error word, adjacent in the control block
+    HIPCHK(hipMemcpyAsync(t->pin + CTL_TOP, t->wb + t->Ly.top, 12, hipMemcpyDeviceToHost, t->st));
   }
   HIPCHK(hipEventRecord(t->ev, t->st));
   t->state = 2;
@@ -1832,8 +1838,8 @@ cat_status catalan_end(cat_ticket ticket, size_t* n_limbs) {
   } else {
     uint64_t L = 0;
     uint32_t derr = 0;
-    memcpy(&L, t->pin + 512, 8);
-    memcpy(&derr, t->pin + 520, 4);
+    memcpy(&L, t->pin + CTL_TOP, 8);
+    memcpy(&derr, t->pin + CTL_ERR, 4);
     *n_limbs = (size_t)L;
     if (derr || L == 0) s = CAT_EINTERNAL;
     else if (L > t->cap) s = CAT_ERANGE;

@@ -27,8 +27,8 @@
 //    omega_S^{j*f} come from two small tables of omega_{2^27} powers.
 // The residues of the three primes are then recombined by k_crt (Garner's
 // method) into 96-bit coefficient values, summed into limbs and carried with
-// a wave64 ballot carry-lookahead; blocks of one product are joined by
-// k_carry_fix.
+// a wave64 ballot carry-lookahead; blocks of one product are joined by a
+// look-back over the preceding blocks inside the same launch.
 
 __constant__ PrimeC c_primes[CAT_NPRIMES];
 __constant__ CrtC c_crt;
@@ -527,34 +527,6 @@ __device__ __forceinline__ uint32_t wave_carry(bool g, bool pr, uint32_t cin, ui
   return (uint32_t)((cm >> (threadIdx.x & 63)) & 1ull);
 }
 
-// Block-level (blockDim = 64*W): returns the thread's carry-in given block
-// carry-in 0; *bG, *bP: block generate / propagate.  tmp >= 2*W words.
-__device__ __forceinline__ uint32_t block_carry(bool g, bool pr, uint32_t* tmp, uint32_t* bG, uint32_t* bP) {
-  const uint32_t wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint32_t cout;
-  bool ap;
-  wave_carry(g, pr, 0, &cout, &ap);
-  if ((threadIdx.x & 63) == 0) tmp[wid] = cout | (ap ? 2u : 0u);
-  __syncthreads();
-  uint32_t cin = 0;
-  for (uint32_t w = 0; w < wid; w++) {
-    const uint32_t x = tmp[w];
-    cin = (x & 1u) | ((x >> 1) & cin);
-  }
-  uint32_t G = 0, P = 1;
-  for (uint32_t w = 0; w < nw; w++) {
-    const uint32_t x = tmp[w];
-    G = (x & 1u) | ((x >> 1) & G);
-    P = P & (x >> 1);
-  }
-  __syncthreads();
-  *bG = G;
-  *bP = P;
-  return wave_carry(g, pr, cin, &cout, &ap);
-}
-
-// Segments of a CRT launch: a device table with block prefix, or one segment
-// passed by value (single products launched on their own).
 // Segments of a CRT launch: device tables (many segments) or up to
 // CAT_INLINE_SEG segments carried in the kernel arguments.
 #define CAT_INLINE_SEG 32
@@ -577,22 +549,25 @@ struct SegView {
   }
 };
 
-// CRT + carry.  Block b covers CAT_CRT_BLOCK limbs of one segment.
-// bsum[b]: bit0 = block generate, bit1 = block propagate (carry-in 0).
-__global__ void __launch_bounds__(CAT_CRT_THREADS)
-k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out,
-      uint8_t* __restrict__ bsum, uint32_t* __restrict__ err) {
-  __shared__ uint32_t tmp[16];
-  __shared__ uint32_t xv[CAT_CRT_THREADS + 1][9];   // last three V of each thread
-  const uint32_t b = blockIdx.x, tid = threadIdx.x;
-  CrtSeg sg;
-  uint32_t first, end;
-  sv.find(b, &sg, &first, &end);
-  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
+// CRT + carry.  Workgroup b < nblk covers CAT_CRT_BLOCK limbs of one segment;
+// workgroups from nblk on copy tail ranges.  The carry into a block follows
+// from the generate / all-propagate pair (G, P) of the blocks before it in the
+// segment (with carry-in 0).  Each block publishes its pair as
+// flags[b] = epoch << 3 | P << 2 | G << 1 | 1 (epoch: this launch's number in
+// the call; the flags are cleared when the call starts) and reads its
+// predecessor's; a pair that has not appeared after a few polls is recomputed
+// from that block's residues instead, so no block ever waits on another
+// (nothing is assumed about which workgroups run at the same time).
+#define CAT_SCAN_POLLS 16   // default number of polls of a predecessor's flag
+
+// Garner values of this thread's CAT_CRT_E positions of the block starting at
+// kb, their sums u and the thread's (G, P); wave pairs go to tmp[wave].
+__device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __restrict__ r0,
+                                          const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
+                                          uint64_t kb, uint32_t (*xv)[9], uint32_t* tmp, uint64_t* u, bool* Gt,
+                                          bool* Pt) {
+  const uint32_t tid = threadIdx.x;
   const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
-  const uint32_t* r0 = res + sg.res_pos;
-  const uint32_t* r1 = r0 + res_stride;
-  const uint32_t* r2 = r1 + res_stride;
   // V for positions k0-3 .. k0+E-1: the thread's own E, the 3 before it from
   // its left neighbour (thread 0: recomputed from the residues)
   uint32_t v0[CAT_CRT_E + 3], v1[CAT_CRT_E + 3], v2[CAT_CRT_E + 3];
@@ -602,6 +577,7 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
     if (k < sg.len) garner3(r0[k], r1[k], r2[k], v0[i], v1[i], v2[i]);
     else { v0[i] = 0; v1[i] = 0; v2[i] = 0; }
   }
+  __syncthreads();   // xv may still be read by a previous call
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     xv[tid + 1][3 * i + 0] = v0[CAT_CRT_E + i];
@@ -626,7 +602,6 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
     v1[i] = xv[tid][3 * i + 1];
     v2[i] = xv[tid][3 * i + 2];
   }
-  uint64_t u[CAT_CRT_E];
   uint32_t yprev = (uint32_t)(((uint64_t)v0[2] + v1[1] + v2[0]) >> 32);   // position k0-1
   bool G = false, P = true;
 #pragma unroll
@@ -638,97 +613,99 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
     G = g || (pr && G);
     P = P && pr;
   }
-  uint32_t bG, bP;
-  uint32_t c = block_carry(G, P, tmp, &bG, &bP);
-  uint32_t* o = out + sg.out_pos;
-#pragma unroll
-  for (int i = 0; i < CAT_CRT_E; i++) {
-    const uint64_t k = k0 + i;
-    const uint64_t t = u[i] + c;
-    c = (uint32_t)(t >> 32);
-    if (k < sg.len) o[k] = (uint32_t)t;
-  }
-  if (threadIdx.x == 0) {
-    bsum[b] = (uint8_t)(bG | (bP << 1));
-    if (b + 1 == end && bG) atomicOr(err, CAT_DEVERR_CARRY_OUT);
-  }
+  *Gt = G;
+  *Pt = P;
+  uint32_t cout;
+  bool ap;
+  wave_carry(G, P, 0, &cout, &ap);
+  if ((tid & 63) == 0) tmp[tid >> 6] = cout | (ap ? 2u : 0u);
+  __syncthreads();
 }
 
-// Carry fix-up of a CRT launch in one workgroup: the carry into every block is
-// cin[b+1] = G_b | (P_b & cin[b]) (nothing crosses a segment end), found with
-// the wave carry-lookahead 1024 blocks at a time; then each wave adds the
-// carry-in of its blocks: the low limbs equal to 2^32-1 become 0 and the first
-// other limb is incremented (every walk stops at its block end).
-__global__ void __launch_bounds__(1024)
-k_carry_fix(SegView sv, const uint8_t* __restrict__ bsum, uint32_t nblk, uint8_t* __restrict__ cin,
-            uint32_t* __restrict__ out, uint32_t* __restrict__ err) {
-  __shared__ uint32_t tmp[32];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (uint32_t base = 0; base < nblk; base += blockDim.x) {
-    const uint32_t b = base + threadIdx.x;
-    bool g = false, pr = false, seg_last = false;
-    if (b < nblk) {
-      CrtSeg sg;
-      uint32_t first, end;
-      sv.find(b, &sg, &first, &end);
-      seg_last = (b + 1 == end);
-      const uint8_t x = bsum[b];
-      g = (x & 1) != 0;
-      pr = (x & 2) != 0;
-    }
-    const bool gg = g && !seg_last, pp = pr && !seg_last;
-    uint32_t cout;
-    bool ap;
-    wave_carry(gg, pp, 0, &cout, &ap);
-    if (lane == 0) tmp[wid] = cout | (ap ? 2u : 0u);
-    __syncthreads();
-    uint32_t wc = carry;
-    for (uint32_t w = 0; w < wid; w++) {
-      const uint32_t x = tmp[w];
-      wc = (x & 1u) | ((x >> 1) & wc);
-    }
-    const uint32_t c = wave_carry(gg, pp, wc, &cout, &ap);   // carry into b
-    if (b < nblk) {
-      if (b + 1 < nblk) cin[b + 1] = (uint8_t)(gg | (pp & c));
-      if (b == 0) cin[0] = 0;
-      if (seg_last && (g || (pr && c))) atomicOr(err, CAT_DEVERR_CARRY_OUT);
-    }
-    __syncthreads();
-    if (threadIdx.x == blockDim.x - 1) {
-      uint32_t cc = carry;
-      for (uint32_t w = 0; w < nw; w++) {
-        const uint32_t x = tmp[w];
-        cc = (x & 1u) | ((x >> 1) & cc);
-      }
-      carry = cc;
-    }
-    __syncthreads();
+// block pair from the wave pairs: bit 0 = G, bit 1 = P
+__device__ __forceinline__ uint32_t crt_block_pair(const uint32_t* tmp) {
+  uint32_t bG = 0, bP = 1;
+  for (uint32_t w = 0; w < (blockDim.x >> 6); w++) {
+    const uint32_t x = tmp[w];
+    bG = (x & 1u) | ((x >> 1) & bG);
+    bP = bP & (x >> 1);
   }
-  __threadfence_block();
-  __syncthreads();
-  for (uint32_t b = wid; b < nblk; b += nw) {
-    if (!cin[b]) continue;
-    CrtSeg sg;
-    uint32_t first, end;
-    sv.find(b, &sg, &first, &end);
-    const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
-    const uint64_t ke = min(kb + (uint64_t)CAT_CRT_BLOCK, sg.len);
-    uint32_t* o = out + sg.out_pos;
-    for (uint64_t k = kb; k < ke; k += 64) {
-      const uint64_t kk = k + lane;
-      const bool in = kk < ke;
-      const uint32_t x = in ? o[kk] : 0u;
-      const uint64_t nz = __ballot(in && x != 0xFFFFFFFFu);
-      if (nz) {
-        const uint32_t f = (uint32_t)__ffsll((unsigned long long)nz) - 1;
-        if (lane < f) o[kk] = 0u;
-        else if (lane == f) o[kk] = x + 1u;
-        break;
+  return bG | (bP << 1);
+}
+
+__global__ void __launch_bounds__(CAT_CRT_THREADS)
+k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out, uint32_t nblk,
+      uint32_t* __restrict__ flags, uint32_t epoch, uint32_t polls, CopyList tails, const uint32_t* __restrict__ tin,
+      uint32_t* __restrict__ tout, uint32_t* __restrict__ err) {
+  __shared__ uint32_t tmp[16], tmp2[16];
+  __shared__ uint32_t xv[CAT_CRT_THREADS + 1][9];   // last three V of each thread
+  __shared__ uint32_t s_state, s_pair;
+  const uint32_t b = blockIdx.x, tid = threadIdx.x;
+  if (b >= nblk) {
+    copy_tail_block(tails, tin, tout, b - nblk);
+    return;
+  }
+  CrtSeg sg;
+  uint32_t first, end;
+  sv.find(b, &sg, &first, &end);
+  const uint32_t* r0 = res + sg.res_pos;
+  const uint32_t* r1 = r0 + res_stride;
+  const uint32_t* r2 = r1 + res_stride;
+  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
+  uint64_t u[CAT_CRT_E];
+  bool G, P;
+  crt_local(sg, r0, r1, r2, kb, xv, tmp, u, &G, &P);
+  const uint32_t own = crt_block_pair(tmp);
+  if (tid == 0)
+    __hip_atomic_store(flags + b, (epoch << 3) | (own << 1) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // look back over the predecessors k = b-1, b-2, ... >= first (block-uniform)
+  uint32_t cin = 0, k = b;
+  bool done = (b == first);
+  while (!done) {
+    k--;
+    if (tid == 0) {
+      uint32_t f = 0;
+      for (uint32_t i = 0; i < polls; i++) {
+        f = __hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((f & 1u) && (f >> 3) == epoch) break;
+        f = 0;
+        __builtin_amdgcn_s_sleep(2);
       }
-      if (in) o[kk] = 0u;
+      s_state = f ? 1u : 2u;
+      s_pair = (f >> 1) & 3u;
     }
+    __syncthreads();
+    const uint32_t state = s_state;
+    uint32_t pair = s_pair;
+    __syncthreads();
+    if (state == 2u) {
+      // not published yet: recompute block k's pair from its residues
+      uint64_t u2[CAT_CRT_E];
+      bool G2, P2;
+      crt_local(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      pair = crt_block_pair(tmp2);
+    }
+    if (pair & 1u) { cin = 1; done = true; }           // block k generates a carry
+    else if (!(pair & 2u)) done = true;                 // block k absorbs any carry-in
+    else if (k == first) done = true;                   // all-propagate back to the start
+  }
+  if (tid == 0 && b + 1 == end && ((own & 1u) | ((own >> 1) & cin))) atomicOr(err, CAT_DEVERR_CARRY_OUT);
+  const uint32_t wid = tid >> 6;
+  uint32_t wc = cin;
+  for (uint32_t w = 0; w < wid; w++) {
+    const uint32_t x = tmp[w];
+    wc = (x & 1u) | ((x >> 1) & wc);
+  }
+  uint32_t cout;
+  bool ap;
+  uint32_t c = wave_carry(G, P, wc, &cout, &ap);
+  uint32_t* o = out + sg.out_pos;
+  const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E; i++) {
+    const uint64_t kk = k0 + i;
+    const uint64_t t = u[i] + c;
+    c = (uint32_t)(t >> 32);
+    if (kk < sg.len) o[kk] = (uint32_t)t;
   }
 }

@@ -72,13 +72,17 @@ __device__ __forceinline__ uint32_t legendre_dev(uint32_t m, uint32_t p) {
 }
 
 // ---------------------------------------------------------------------------
+// ctl: the call's control block (group table first), ctl_words words, cleared
+// here before anything else of the call writes to it.
 __global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t* seeds, int32_t* seed_e,
-                                                GroupTable* gt) {
+                                                GroupTable* gt, uint32_t* __restrict__ ctl, uint64_t ctl_words) {
   __shared__ uint8_t comp[65536];
   __shared__ uint32_t tmp[40];
   __shared__ uint32_t small[64];
   __shared__ uint32_t nsmall;
   const uint32_t T = blockDim.x, tid = threadIdx.x;
+  for (uint64_t k = tid; k < ctl_words; k += T) ctl[k] = 0u;
+  __threadfence_block();
   for (uint32_t i = tid; i <= s; i += T) comp[i] = (i < 2) ? 1 : 0;
   // primes up to isqrt(s) <= 255 by trial division, one thread per candidate
   uint32_t r = 0;

@@ -47,15 +47,21 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
 }
 
 // ---------------------------------------------------------------------------
-// Schoolbook products, la, lb <= 128.  4 waves per block, one product each.
+// Schoolbook products, la, lb <= 128.  4 waves per block, one product each;
+// blocks from ceil(nmul / 4) on copy the tail ranges.
 #define SCHOOL_MAX 128
 #define SCHOOL_WAVES 4
 __global__ void __launch_bounds__(64 * SCHOOL_WAVES)
 k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
-         uint32_t* __restrict__ out, uint32_t* __restrict__ err) {
+         uint32_t* __restrict__ out, uint32_t* __restrict__ err, uint32_t prod_blocks, CopyList tails,
+         const uint32_t* __restrict__ tin, uint32_t* __restrict__ tout) {
   __shared__ uint32_t sa[SCHOOL_WAVES][SCHOOL_MAX];
   __shared__ uint32_t sb[SCHOOL_WAVES][SCHOOL_MAX];
   __shared__ uint32_t sv[SCHOOL_WAVES][3][2 * SCHOOL_MAX + 4];
+  if (blockIdx.x >= prod_blocks) {
+    copy_tail_block(tails, tin, tout, blockIdx.x - prod_blocks);
+    return;
+  }
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t mi = (uint64_t)blockIdx.x * SCHOOL_WAVES + w;
   if (mi >= nmul) return;   // whole wave leaves together; no block barrier below
@@ -117,11 +123,6 @@ k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uin
 
 // ---------------------------------------------------------------------------
 // Copy of up to CAT_MAX_GROUPS ranges (the odd nodes carried up a level).
-struct CopyList {
-  uint32_t n;
-  uint64_t off[CAT_MAX_GROUPS];
-  uint64_t len[CAT_MAX_GROUPS];
-};
 __global__ void k_copy_ranges(CopyList cl, const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
   const uint32_t r = blockIdx.y;
   if (r >= cl.n) return;
@@ -135,19 +136,19 @@ __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     p[k] = v;
 }
 
-__global__ void k_copy(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint64_t n) {
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
-    out[k] = in[k];
-}
-
-// Highest index with a nonzero limb, +1 (0 if all zero) -> *top.  Each block
-// reduces in LDS and issues one atomicMax.
+// Highest index with a nonzero limb, +1 (0 if all zero) -> *top; limbs below
+// ncopy are also copied to dst (the caller's output).  Each block reduces in
+// LDS and issues one atomicMax.
 __global__ void __launch_bounds__(256) k_top_nonzero(const uint32_t* __restrict__ x, uint64_t n,
-                                                     unsigned long long* top) {
+                                                     unsigned long long* top, uint32_t* __restrict__ dst,
+                                                     uint64_t ncopy) {
   __shared__ unsigned long long part[4];
   unsigned long long best = 0;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
-    if (x[k]) best = k + 1;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = x[k];
+    if (v) best = k + 1;
+    if (k < ncopy) dst[k] = v;
+  }
   for (int d = 32; d >= 1; d >>= 1) {
     unsigned long long o = __shfl_xor(best, d, 64);
     best = o > best ? o : best;

@@ -208,6 +208,23 @@ def test_residues_kernel(cat):
         assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1))
 
 
+@pytest.mark.parametrize("polls", [0, 1])
+def test_carry_lookback_recompute(cat, polls):
+    """With no (or one) poll of the predecessor's published carry pair, CRT
+    blocks recompute it from the residues: same products, same C(n).  All-ones
+    operands give blocks that propagate a carry across their whole length."""
+    try:
+        cat.set_lookback_polls(polls)
+        la = [5000, 70000, 9000, 4096, 131072, 3000]
+        lb = [5000, 70000, 2, 4096, 131071, 12000]
+        kinds = ["ones", "ones", "rand", "ones", "ones", "rand"]
+        _run_batch(cat, la, lb, kinds, "batched", seed=21)
+        for n in (13337, 250000):
+            assert np.array_equal(cat.to_numpy(cat.exact(n, mode="graph")), oracle.catalan(n)), n
+    finally:
+        cat.set_lookback_polls(16)
+
+
 def _schedule_short(t):
     """small schoolbook threshold, four-step transforms with short rows and
     short column passes from 2^11 up"""
