@@ -41,6 +41,8 @@ struct Lib {
   std::map<uint64_t, Plan*> plans;
   std::vector<uint64_t> plan_order;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side_stream = nullptr;            // second branch of captured calls
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // kernel timer: events around every launch of one named kernel
   std::string timer_name;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_ev;
@@ -202,6 +204,9 @@ cat_status init_locked(int device) {
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipHostMalloc(&g.pin, 1 << 16, hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&g.side_stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
   g.inited = true;
   return CAT_OK;
 }
@@ -365,7 +370,9 @@ void build_crt_segs(Stage& s) {
 struct Layout {
   uint64_t n = 0, s = 0, i0 = 0, i_end = 0, nseg = 0;
   uint64_t Kmax = 0, post_cap = 0, res_len = 0, F_words = 0, nblk_max = 0;
+  uint64_t res2_len = 0, F2_words = 0, nblk2_max = 0;   // scratch of the side branch
   size_t primes = 0, arenaA = 0, arenaB = 0, post = 0, res = 0, F = 0;       // in uint32 units
+  size_t res2 = 0, F2 = 0;                                                    // in uint32 units
   size_t seeds = 0, seed_e = 0, seg_cnt = 0, seg_off = 0, bitmap = 0;        // in uint32 units
   size_t gtab = 0, top = 0, err = 0, ctl_words = 0;                         // bytes (ctl_words: uint32)
   size_t total = 0;
@@ -394,6 +401,12 @@ Layout make_layout(uint64_t n) {
   const uint64_t big = 1ull << ceil_log2(std::max(L.Kmax, L.post_cap));
   L.F_words = (big > (1ull << CAT_LDS_LOGT)) ? 12 * big + (1ull << 20) : (1ull << 20);
   L.nblk_max = L.res_len / CAT_CRT_BLOCK + 4096;
+  // The powers P_e (e >= 2) and their product R involve only primes below
+  // sqrt(2n), each prime power below 2^32: every step of them fits 64 limbs
+  // per seed prime.
+  L.res2_len = 64 * sb + 4096;
+  L.F2_words = 12 * (1ull << ceil_log2(L.res2_len)) + (1ull << 16);
+  L.nblk2_max = L.res2_len / CAT_CRT_BLOCK + 64;
   size_t off = 0;  // bytes
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -406,18 +419,20 @@ Layout make_layout(uint64_t n) {
   L.post = take(L.post_cap * 4) / 4;
   L.res = take(3 * L.res_len * 4) / 4;
   L.F = take(L.F_words * 4) / 4;
+  L.res2 = take(3 * L.res2_len * 4) / 4;
+  L.F2 = take(L.F2_words * 4) / 4;
   L.seeds = take(SEED_MAX * 4) / 4;
   L.seed_e = take(SEED_MAX * 4) / 4;
   L.seg_cnt = take((L.nseg + 1) * 4) / 4;
   L.seg_off = take((L.nseg + 1) * 4) / 4;
   L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
   // control block, cleared by Phase 1 (k_seeds): group table | top | error
-  // word | CRT look-back flags; the first CTL_READ bytes go back to the host
-  // in one copy
-  L.gtab = take(CTL_FLAGS + 4 * L.nblk_max);
+  // word | CRT look-back flags of the main and the side branch; the first
+  // CTL_READ bytes go back to the host in one copy
+  L.gtab = take(CTL_FLAGS + 4 * (L.nblk_max + L.nblk2_max));
   L.top = L.gtab + CTL_TOP;
   L.err = L.gtab + CTL_ERR;
-  L.ctl_words = (CTL_FLAGS + 4 * L.nblk_max) / 4;
+  L.ctl_words = (CTL_FLAGS + 4 * (L.nblk_max + L.nblk2_max)) / 4;
   L.total = off;
   return L;
 }
@@ -436,6 +451,13 @@ struct Plan {
   uint64_t result_pos = 0, result_cap = 0;   // uint32 offset from workspace base
   bool result_is_one = false;
   uint64_t post_end = 0;        // end of the post-tree arena used
+  uint64_t root[CAT_MAX_GROUPS] = {};   // Q_e of group g (uint32 offset), the same in both forms
+  // Side branch (captured calls): after fork_count batched stages every group
+  // with e >= 2 is complete, and post[0, post_final) (powers and R) may run
+  // beside the remaining levels of Q_1; post[post_final..] (C = Q_1 R) waits
+  // for both.  fork_count < 0: no side branch.
+  int fork_count = -1;
+  size_t post_final = 0;
   void* dev = nullptr;          // device tables (segments, prefixes, descriptors)
   uint64_t products = 0, product_limbs = 0;
   uint32_t levels = 0;
@@ -447,16 +469,25 @@ struct Plan {
 
 // Forest levels of the product trees over the groups (one tree per group).
 // out(j) = A for even j, B for odd j; in(0) = primes.
-void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
+void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   std::vector<Stage>& st = batched ? P.batched : P.plain;
   const uint32_t ng = P.ng;
   auto out_of = [&](int j) -> uint64_t { return (j % 2 == 0) ? Ly.arenaA : Ly.arenaB; };
   auto in_of = [&](int j) -> uint64_t { return j == 0 ? Ly.primes : out_of(j - 1); };
   uint64_t Kmax_g = 0;
   for (uint32_t gi = 0; gi < ng; gi++) Kmax_g = std::max(Kmax_g, P.off[gi + 1] - P.off[gi]);
-  int jstart = 0;
   const int LF = 5;
   const int J = ceil_log2(std::max<uint64_t>(Kmax_g, 1));   // levels until one node per group
+  // levels folded into the leaf kernel of the batched form
+  const int jleaf = Kmax_g > 1 ? std::min(J, LF) : 0;
+  // Q_e is complete after level jdone - 1 (at least the leaf levels), in
+  // in_of(jdone); the plain form carries early roots up to the same place
+  int jdone[CAT_MAX_GROUPS];
+  for (uint32_t gi = 0; gi < ng; gi++) {
+    jdone[gi] = std::max(ceil_log2(P.off[gi + 1] - P.off[gi]), jleaf);
+    P.root[gi] = in_of(jdone[gi]) + P.off[gi];
+  }
+  int jstart = 0;
   if (batched && Kmax_g > 1) {
     // leaf packing covers levels 0..LF-1
     Stage s;
@@ -474,26 +505,17 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
     s.leaf_nodes = nodes;
     s.a_base = Ly.primes;
     // the buffer the pairwise levels would have written last
-    s.c_base = out_of(std::min(J, LF) - 1);
+    s.c_base = out_of(jleaf - 1);
     for (uint32_t gi = 0; gi < ng; gi++) {
       const uint64_t K = P.off[gi + 1] - P.off[gi];
-      const uint64_t cnt = std::min<uint64_t>(K, 1ull << LF);
       // products inside the packed levels: K - nodes
       P.products += K - ((K + (1ull << LF) - 1) >> LF);
-      (void)cnt;
     }
     st.push_back(s);
-    jstart = std::min(J, LF);
+    jstart = jleaf;
   }
-  uint64_t where = (jstart == 0) ? Ly.primes : out_of(jstart - 1);
   int j = jstart;
-  for (;; j++) {
-    bool any = false;
-    for (uint32_t gi = 0; gi < ng; gi++) {
-      const uint64_t K = P.off[gi + 1] - P.off[gi];
-      if (((K + (1ull << j) - 1) >> j) > 1) any = true;
-    }
-    if (!any) break;
+  for (; j < J; j++) {
     Stage s;
     s.dv.table = nullptr;
     TreeLevel& t = s.dv.tree;
@@ -508,7 +530,8 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
       t.K[gi] = K;
       t.mpref[gi] = m;
       m += nodes / 2;
-      if (nodes & 1) {
+      // the odd last node moves up; a finished root moves until jdone
+      if ((nodes & 1) && (nodes > 1 || j < jdone[gi])) {
         const uint64_t o = P.off[gi] + (nodes - 1) * (1ull << j);
         s.tails.off[s.tails.n] = o;
         s.tails.len[s.tails.n] = P.off[gi + 1] - o;
@@ -520,10 +543,6 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
     }
     t.mpref[ng] = m;
     s.nmul = m;
-    for (uint64_t i = 0; i < m; i++) {
-      // sum of la+lb (cheap closed form would do; m is at most K/2)
-      (void)i;
-    }
     s.limbs = 0;
     for (const CrtSeg& sg : s.host_segs) s.limbs += sg.len;
     {
@@ -541,10 +560,15 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched, uint64_t* root_pos) {
     P.products += m;
     P.product_limbs += s.limbs;
     st.push_back(s);
-    where = out_of(j);
   }
   P.levels = (uint32_t)j;
-  *root_pos = where;
+  if (batched) {
+    // stages after which every group with e >= 2 is complete
+    int jf = -1;
+    for (uint32_t gi = 0; gi < ng; gi++)
+      if (P.exps[gi] >= 2) jf = std::max(jf, jdone[gi]);
+    P.fork_count = jf < 0 ? -1 : (jstart > 0 ? 1 : 0) + std::max(0, jf - jstart);
+  }
 }
 
 // Explicit products after the forest: P_e = Q_e^e (left-to-right binary
@@ -606,7 +630,7 @@ void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vecto
   }
 }
 
-void plan_post(const Layout& Ly, Plan& P, uint64_t root_pos) {
+void plan_post(const Layout& Ly, Plan& P) {
   uint64_t bump = Ly.post;
   auto alloc = [&](uint64_t cap) {
     Item it{bump, cap};
@@ -625,7 +649,7 @@ void plan_post(const Layout& Ly, Plan& P, uint64_t root_pos) {
   };
   std::vector<Chain> ch;
   for (uint32_t gi = 0; gi < P.ng; gi++) {
-    Item q{root_pos + P.off[gi], P.off[gi + 1] - P.off[gi]};
+    Item q{P.root[gi], P.off[gi + 1] - P.off[gi]};
     if (P.exps[gi] == 1) {
       q1 = q;
       has_q1 = true;
@@ -679,6 +703,8 @@ void plan_post(const Layout& Ly, Plan& P, uint64_t root_pos) {
     add_products(P, pairs, outs);
     pe = next;
   }
+  P.post_final = P.post.size();
+  if (!has_q1 || pe.empty()) P.fork_count = -1;   // nothing runs beside the Q_1 tree
   if (has_q1 && !pe.empty()) {
     std::vector<std::pair<Item, Item>> pairs{{q1, pe[0]}};
     std::vector<Item> outs{alloc(q1.cap + pe[0].cap)};
@@ -761,21 +787,13 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
   P->ng = gt.ngroups;
   for (uint32_t gi = 0; gi < gt.ngroups; gi++) P->exps[gi] = gt.exps[gi];
   for (uint32_t gi = 0; gi <= gt.ngroups; gi++) P->off[gi] = gt.off[gi];
-  uint64_t root_b = 0, root_p = 0;
-  plan_tree(Ly, *P, true, &root_b);
-  const uint64_t prod_b = P->products, limbs_b = P->product_limbs;
-  P->products = 0;
-  P->product_limbs = 0;
-  plan_tree(Ly, *P, false, &root_p);
-  if (root_b != root_p) {
-    free_plan(P);
-    return CAT_EINTERNAL;
-  }
+  plan_tree(Ly, *P, true);
   // products and their limbs are counted from the pairwise levels of the plain
   // form (the leaf kernel of the batched form folds the lowest levels)
-  (void)prod_b;
-  (void)limbs_b;
-  plan_post(Ly, *P, root_b);
+  P->products = 0;
+  P->product_limbs = 0;
+  plan_tree(Ly, *P, false);
+  plan_post(Ly, *P);
   std::vector<Stage*> all;
   for (auto& s : P->batched) all.push_back(&s);
   for (auto& s : P->plain) all.push_back(&s);
@@ -790,6 +808,15 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
       free_plan(P);
       return CAT_EINTERNAL;
     }
+  }
+  // the side branch runs with its own scratch; without room there the powers
+  // run in line
+  for (size_t k = 0; k < P->post_final && P->fork_count >= 0; k++) {
+    const Stage& s = P->post[k];
+    uint64_t rmax = 0;
+    for (const CrtSeg& sg : s.host_segs) rmax = std::max(rmax, sg.res_pos + sg.len);
+    const uint64_t fneed = (s.cls == CLS_LARGE) ? s.nmul * 6ull << s.logN : 0;
+    if (rmax > Ly.res2_len || fneed > Ly.F2_words || s.nblk > Ly.nblk2_max) P->fork_count = -1;
   }
   if (P->post_end > Ly.post + Ly.post_cap) {
     free_plan(P);
@@ -817,6 +844,12 @@ struct Exec {
   uint32_t* F = nullptr;
   uint32_t* flags = nullptr;   // CRT look-back flags (cleared when the call starts)
   uint32_t crt_epoch = 0;      // CRT launches so far in this call
+  // side branch: stream (nullptr: everything runs in order on st) and its scratch
+  hipStream_t side = nullptr;
+  uint32_t* res2 = nullptr;
+  uint64_t res2_stride = 0;
+  uint32_t* F2 = nullptr;
+  uint32_t* flags2 = nullptr;
   uint32_t* err = nullptr;
   hipStream_t st = nullptr;
   uint64_t launches = 0;
@@ -1017,6 +1050,29 @@ cat_status capture_graph(F&& rec, hipGraphExec_t* out) {
 
 cat_status run_phase2(Exec& X, Plan& P, bool plain) {
   std::vector<Stage>& st = plain ? P.plain : P.batched;
+  if (!plain && X.side && P.fork_count >= 0) {
+    // Q_1's upper levels on st; the powers and R on the side stream with
+    // their own scratch; C = Q_1 R once both are done
+    const size_t nf = std::min<size_t>((size_t)P.fork_count, st.size());
+    for (size_t k = 0; k < nf; k++) STCHK(run_stage_batched(X, st[k]));
+    HIPCHK(hipEventRecord(g.ev_fork, X.st));
+    HIPCHK(hipStreamWaitEvent(X.side, g.ev_fork, 0));
+    Exec S = X;
+    S.st = X.side;
+    S.res = X.res2;
+    S.res_stride = X.res2_stride;
+    S.F = X.F2;
+    S.flags = X.flags2;
+    S.crt_epoch = 0;
+    S.launches = 0;
+    for (size_t k = 0; k < P.post_final; k++) STCHK(run_stage_batched(S, P.post[k]));
+    HIPCHK(hipEventRecord(g.ev_join, S.st));
+    for (size_t k = nf; k < st.size(); k++) STCHK(run_stage_batched(X, st[k]));
+    HIPCHK(hipStreamWaitEvent(X.st, g.ev_join, 0));
+    for (size_t k = P.post_final; k < P.post.size(); k++) STCHK(run_stage_batched(X, P.post[k]));
+    X.launches += S.launches;
+    return CAT_OK;
+  }
   for (const Stage& s : st) STCHK(plain ? run_stage_plain(X, s) : run_stage_batched(X, s));
   for (const Stage& s : P.post) STCHK(plain ? run_stage_plain(X, s) : run_stage_batched(X, s));
   return CAT_OK;
@@ -1093,6 +1149,10 @@ Exec make_exec(const Layout& Ly, char* wb, hipStream_t st) {
   X.F = X.W + Ly.F;
   X.err = (uint32_t*)(wb + Ly.err);
   X.flags = (uint32_t*)(wb + Ly.gtab + CTL_FLAGS);
+  X.res2 = X.W + Ly.res2;
+  X.res2_stride = Ly.res2_len;
+  X.F2 = X.W + Ly.F2;
+  X.flags2 = X.flags + Ly.nblk_max;
   X.st = st;
   return X;
 }
@@ -1476,6 +1536,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
           [&](hipStream_t cs) -> cat_status {
             STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, cs, &nl));
             Exec E = make_exec(Ly, wb, cs);
+            E.side = g.side_stream;
             STCHK(run_phase2(E, *P, false));
             const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
             const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
@@ -1555,6 +1616,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
     } else {
       Exec C = X;
       C.st = g.cap_stream;
+      C.side = g.side_stream;
       HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
       cat_status s = record(C);
       hipGraph_t graph = nullptr;
