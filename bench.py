@@ -251,7 +251,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py: this build is single-GPU (one MI355X); --gpus %d is not supported" % max(args.gpus, world),
+        print("bench.py measures one GPU (one MI355X); --gpus %d is not supported" % max(args.gpus, world),
               file=sys.stderr)
         sys.exit(2)
 

@@ -202,8 +202,27 @@ __host__ __device__ constexpr uint32_t tws_off(int s) { return (1u << s) - 2u; }
 #define CAT_LDS_MAX_LOGT 14  // largest transform held by one workgroup (both operands, 2^14 each)
 #define TWS_ENTRIES 32766u   // sum over s = 1..14 of 2^s
 
+// Synchronisation between two radix-16 passes.  Both have total/16 groups,
+// and the 2^logSmall elements of a sub-problem of the smaller size are written
+// and read by the same 2^logSmall consecutive groups, i.e. consecutive
+// threads; in a plain vector (logC = 0) with 2^logSmall <= 64 those sit in one
+// wave, which orders its own LDS traffic, so no workgroup barrier is needed.
+// (Next to a pass of smaller radix the group counts differ: full barrier.)
+__device__ __forceinline__ void pass_sync(int logSmall, uint32_t logC) {
+  if (logC == 0 && logSmall <= 6) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Full forward transform of size 2^logS on every sub-problem of an LDS tile
-// with `total` elements (all columns), passes from size 2^logS down.
+// with `total` elements (all columns), passes from size 2^logS down.  On
+// return (logC = 0) thread g of the last pass holds the outputs at
+// [16 g, 16 g + 16) of its groups; the caller synchronises before other
+// threads read them.
 template <bool PAD>
 __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ tws, const PrimeC& pc) {
@@ -218,11 +237,17 @@ __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t t
       case 3: pass_fwd<3, PAD>(lds, ng, logSR, logC, tw, pc); break;
       default: pass_fwd<4, PAD>(lds, ng, logSR, logC, tw, pc); break;
     }
-    __syncthreads();
     logS -= lr;
+    if (logS > 0) {
+      if (lr == 4) pass_sync(logS, logC);   // every later pass has radix 16
+      else __syncthreads();
+    }
   }
 }
 
+// Inverse; the caller synchronises before the first pass as needed (with
+// logC = 0 the first pass reads [16 g, 16 g + 16) in thread g) and the
+// transform ends with a workgroup barrier.
 template <bool PAD>
 __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ itws, const PrimeC& pc) {
@@ -231,7 +256,8 @@ __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t t
   const int lr0 = pass_logr(logS);
   for (int ls = 4; ls <= logS - lr0; ls += 4) {
     pass_inv<4, PAD>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc);
-    __syncthreads();
+    if (ls + 4 <= logS - lr0 || lr0 == 4) pass_sync(ls, logC);   // the next pass has radix 16
+    else __syncthreads();
   }
   if (logS > 0) {
     const uint32_t ng = total >> lr0;
@@ -243,8 +269,8 @@ __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t t
       case 3: pass_inv<3, PAD>(lds, ng, logSR, logC, tw, pc); break;
       default: pass_inv<4, PAD>(lds, ng, logSR, logC, tw, pc); break;
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // frequency held at output position q of the pass-structured transform of size 2^logS
@@ -294,16 +320,30 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ds[i] = dv.get(m0 + i);
   __syncthreads();
   const uint32_t T = cnt << logN;                  // live slots
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t m = t >> logN, j = t & (N - 1);
-    const MulDesc d = ds[m];
-    uint32_t x = j < d.la ? reduce_limb(ain[d.a_off + j], p) : 0u;
-    uint32_t y = j < d.lb ? reduce_limb(bin[d.b_off + j], p) : 0u;
-    lds[lds_pad(t)] = x;
-    lds[lds_pad(TT + t)] = y;
+  {
+    // every load of the thread is issued before the first is used: clamped,
+    // in-bounds addresses and masks instead of branches around the loads
+    constexpr uint32_t NT = TT / 16;               // blockDim.x
+    uint32_t xa[16], xb[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t t = threadIdx.x + i * NT;
+      const uint32_t tc = t < T ? t : T - 1;
+      const uint32_t m = tc >> logN, j = tc & (N - 1);
+      const MulDesc d = ds[m];
+      const uint32_t ka = j < d.la ? 0xFFFFFFFFu : 0u, kb = j < d.lb ? 0xFFFFFFFFu : 0u;
+      xa[i] = ain[d.a_off + (j & ka)] & ka;
+      xb[i] = bin[d.b_off + (j & kb)] & kb;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t t = threadIdx.x + i * NT;
+      lds[lds_pad(t)] = reduce_limb(xa[i], p);
+      lds[lds_pad(TT + t)] = reduce_limb(xb[i], p);
+    }
   }
-  // unused slots of a partial tile stay untouched: their sub-problems are
-  // independent and never read back
+  // slots past T of a partial tile repeat the last live slot; their
+  // sub-problems are independent and never read back
   __syncthreads();
   const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
   const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
@@ -314,12 +354,18 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
     ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
     ntt_fwd_tile<true>(lds + lds_pad(TT), logN, T, 0, tws, pc);
   }
+  // pointwise product on the 16 positions whose forward outputs this thread
+  // wrote last (A and B alike), which the first inverse pass reads back in the
+  // same thread: no barrier on either side
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(TT + t)];
-    lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+  if (16 * threadIdx.x < T) {
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const uint32_t t = 16 * threadIdx.x + k;
+      const uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(TT + t)];
+      lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+    }
   }
-  __syncthreads();
   ntt_inv_tile<true>(lds, logN, T, 0, itws, pc);
   uint32_t* out = res + (size_t)prime * res_stride;
   for (uint32_t m = 0; m < cnt; m++) {
@@ -342,6 +388,7 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
 //   F[((m*3 + prime)*2 + op)*N + position]
 #define NTT_COL_THREADS 256
 #define NTT_COL_TILE 8192u      // LDS words of a column tile (32 KB: 4 workgroups per CU)
+#define COL_BATCH 16            // global loads a thread keeps in flight in the column kernels
 #define TW2_LO_BITS 14u
 #define TW2_LO (1u << TW2_LO_BITS)
 #define TW2_HI (1u << (CAT_MAX_LOGN - TW2_LO_BITS))
@@ -384,28 +431,71 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
   const uint64_t N = 1ull << pg.logN;
   const uint32_t T = 1u << (pg.logL + pg.logC);
   uint32_t* f = F + ((m * 3 + prime) * 2 + op) * N;
+  // loads in batches of COL_BATCH per thread, all issued before the first use
   if (first) {
     const MulDesc d = dv.get(m);
     const uint32_t* src = op ? bin + d.b_off : ain + d.a_off;
     const uint64_t len = op ? d.lb : d.la;
-    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-      const uint64_t idx = base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1));
-      lds[t] = idx < len ? reduce_limb(src[idx], p) : 0u;
+    for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+      uint32_t v[COL_BATCH];
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        const uint32_t tc = t < T ? t : T - 1;
+        const uint64_t idx = base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1));
+        const uint32_t k = idx < len ? 0xFFFFFFFFu : 0u;
+        v[i] = src[idx < len ? idx : 0] & k;
+      }
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        if (t < T) lds[t] = reduce_limb(v[i], p);
+      }
     }
   } else {
-    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
-      lds[t] = f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))];
+    for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+      uint32_t v[COL_BATCH];
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        const uint32_t tc = t < T ? t : T - 1;
+        v[i] = f[base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1))];
+      }
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        if (t < T) lds[t] = v[i];
+      }
+    }
   }
   __syncthreads();
   ntt_fwd_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
+  __syncthreads();
   const uint2* lo = tb.tw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.tw2hi + (size_t)prime * TW2_HI;
   const uint64_t smask = (1ull << pg.logS) - 1;
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t q = t >> pg.logC, j = j0 + (t & (C - 1));
-    const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
-    const uint2 w = tw2(lo, hi, (uint32_t)(e << (CAT_MAX_LOGN - pg.logS)), pc);
-    f[base + ((uint64_t)q << logSig) + j] = mul_tw(lds[t], w.x, w.y, p);
+  for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+    uint2 l[COL_BATCH];
+    uint32_t h[COL_BATCH];
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; i++) {
+      const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+      const uint32_t tc = t < T ? t : T - 1;
+      const uint32_t q = tc >> pg.logC, j = j0 + (tc & (C - 1));
+      const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
+      const uint32_t y = (uint32_t)(e << (CAT_MAX_LOGN - pg.logS));
+      l[i] = lo[y & (TW2_LO - 1)];
+      h[i] = hi[y >> TW2_LO_BITS];
+    }
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; i++) {
+      const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+      if (t < T) {
+        const uint32_t q = t >> pg.logC, j = j0 + (t & (C - 1));
+        const uint32_t w = mul_tw(h[i], l[i].x, l[i].y, p);
+        f[base + ((uint64_t)q << logSig) + j] = mul_tw(lds[t], w, w * pc.pinv, p);
+      }
+    }
   }
 }
 
@@ -427,11 +517,28 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
   const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
   const uint64_t smask = (1ull << pg.logS) - 1;
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t q = t >> pg.logC, j = j0 + (t & (C - 1));
-    const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
-    const uint2 w = tw2(lo, hi, (uint32_t)(e << (CAT_MAX_LOGN - pg.logS)), pc);
-    lds[t] = mul_tw(f[base + ((uint64_t)q << logSig) + j], w.x, w.y, p);
+  for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+    uint2 l[COL_BATCH];
+    uint32_t h[COL_BATCH], v[COL_BATCH];
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; i++) {
+      const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+      const uint32_t tc = t < T ? t : T - 1;
+      const uint32_t q = tc >> pg.logC, j = j0 + (tc & (C - 1));
+      const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
+      const uint32_t y = (uint32_t)(e << (CAT_MAX_LOGN - pg.logS));
+      l[i] = lo[y & (TW2_LO - 1)];
+      h[i] = hi[y >> TW2_LO_BITS];
+      v[i] = f[base + ((uint64_t)q << logSig) + j];
+    }
+#pragma unroll
+    for (int i = 0; i < COL_BATCH; i++) {
+      const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+      if (t < T) {
+        const uint32_t w = mul_tw(h[i], l[i].x, l[i].y, p);
+        lds[t] = mul_tw(v[i], w, w * pc.pinv, p);
+      }
+    }
   }
   __syncthreads();
   ntt_inv_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
@@ -469,21 +576,49 @@ k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, 
   const uint32_t q = blockIdx.x & ((1u << logR1) - 1);
   uint32_t* fa = F + ((m * 3 + prime) * 2 + 0) * N + ((uint64_t)q << logM);
   uint32_t* fb = F + ((m * 3 + prime) * 2 + 1) * N + ((uint64_t)q << logM);
-  for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
-    lds[lds_pad(t)] = fa[t];
-    lds[lds_pad(M + t)] = fb[t];
+  constexpr uint32_t NT = TT / 16;                 // blockDim.x
+  if (M == TT) {
+    // full rows: all 32 loads of the thread in flight before the first use
+    uint32_t va[16], vb[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      va[i] = fa[threadIdx.x + i * NT];
+      vb[i] = fb[threadIdx.x + i * NT];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      lds[lds_pad(threadIdx.x + i * NT)] = va[i];
+      lds[lds_pad(TT + threadIdx.x + i * NT)] = vb[i];
+    }
+  } else {
+    for (uint32_t t = threadIdx.x; t < M; t += NT) {
+      lds[lds_pad(t)] = fa[t];
+      lds[lds_pad(M + t)] = fb[t];
+    }
   }
   __syncthreads();
   const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
   ntt_fwd_tile<true>(lds, logM, 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
-  for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
-    uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
-    lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+  if (M == TT) {
+    // thread g wrote A and B at [16 g, 16 g + 16): pointwise in place, and the
+    // first inverse pass reads the same positions in the same thread
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const uint32_t t = 16 * threadIdx.x + k;
+      const uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
+      lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+    }
+  } else {
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
+      uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
+      lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   ntt_inv_tile<true>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
-  for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) fa[t] = lds[lds_pad(t)];
+  for (uint32_t t = threadIdx.x; t < M; t += NT) fa[t] = lds[lds_pad(t)];
 }
 
 // ---------------------------------------------------------------------------
