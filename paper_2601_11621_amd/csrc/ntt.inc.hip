@@ -706,11 +706,23 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
   // V for positions k0-3 .. k0+E-1: the thread's own E, the 3 before it from
   // its left neighbour (thread 0: recomputed from the residues)
   uint32_t v0[CAT_CRT_E + 3], v1[CAT_CRT_E + 3], v2[CAT_CRT_E + 3];
+  {
+    // the thread's 3*E residue loads in flight together (clamped addresses;
+    // positions past the segment count as zero)
+    uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E];
 #pragma unroll
-  for (int i = 3; i < CAT_CRT_E + 3; i++) {
-    const uint64_t k = k0 + i - 3;
-    if (k < sg.len) garner3(r0[k], r1[k], r2[k], v0[i], v1[i], v2[i]);
-    else { v0[i] = 0; v1[i] = 0; v2[i] = 0; }
+    for (int i = 0; i < CAT_CRT_E; i++) {
+      const uint64_t k = k0 + i;
+      const uint64_t kc = k < sg.len ? k : 0;
+      x0[i] = r0[kc];
+      x1[i] = r1[kc];
+      x2[i] = r2[kc];
+    }
+#pragma unroll
+    for (int i = 0; i < CAT_CRT_E; i++) {
+      if (k0 + i < sg.len) garner3(x0[i], x1[i], x2[i], v0[i + 3], v1[i + 3], v2[i + 3]);
+      else { v0[i + 3] = 0; v1[i + 3] = 0; v2[i + 3] = 0; }
+    }
   }
   __syncthreads();   // xv may still be read by a previous call
 #pragma unroll

@@ -23,14 +23,19 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
   const uint64_t off = tl.base[g] + il * W;
   const uint64_t rem = tl.K[g] - il * W;
   const uint32_t cnt = (uint32_t)(rem < (uint64_t)W ? rem : (uint64_t)W);
+  // all 2^LF loads first (clamped to the node's last leaf; leaves past cnt are
+  // never multiplied in)
+  uint32_t qv[W];
+#pragma unroll
+  for (int k = 0; k < W; k++) qv[k] = primes[off + ((uint32_t)k < cnt ? (uint32_t)k : cnt - 1)];
   uint32_t acc[W];
-  acc[0] = primes[off];
+  acc[0] = qv[0];
 #pragma unroll
   for (int k = 1; k < W; k++) acc[k] = 0;
 #pragma unroll
   for (int k = 1; k < W; k++) {
     if ((uint32_t)k < cnt) {
-      const uint32_t q = primes[off + k];
+      const uint32_t q = qv[k];
       uint32_t carry = 0;
 #pragma unroll
       for (int l = 0; l < k; l++) {
@@ -67,8 +72,16 @@ k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uin
   if (mi >= nmul) return;   // whole wave leaves together; no block barrier below
   const MulDesc d = dv.get(mi);
   const uint32_t la = d.la, lb = d.lb, L = la + lb;
-  for (uint32_t k = lane; k < la; k += 64) sa[w][k] = ain[d.a_off + k];
-  for (uint32_t k = lane; k < lb; k += 64) sb[w][k] = bin[d.b_off + k];
+  {
+    // the (at most 2 + 2) loads of a lane in flight together
+    const uint32_t k0 = lane, k1 = lane + 64;
+    const uint32_t a0 = ain[d.a_off + (k0 < la ? k0 : 0u)], a1 = ain[d.a_off + (k1 < la ? k1 : 0u)];
+    const uint32_t b0 = bin[d.b_off + (k0 < lb ? k0 : 0u)], b1 = bin[d.b_off + (k1 < lb ? k1 : 0u)];
+    if (k0 < la) sa[w][k0] = a0;
+    if (k1 < la) sa[w][k1] = a1;
+    if (k0 < lb) sb[w][k0] = b0;
+    if (k1 < lb) sb[w][k1] = b1;
+  }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   // column k = sum_{i} a_i b_{k-i}; lanes take k = lane + 64*c
