@@ -300,7 +300,7 @@ def main():
     # batched without graph (launch overhead visible) and the plain form
     ms_batched = time_steps(cat, n, "batched", max(1, args.steps // 4), out)
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and args.plain_steps > 0:
         cat.exact(n, mode="plain", out=out)   # plan + warm
         ms_plain = time_steps(cat, n, "plain", args.plain_steps, out)
         t = cat.exact(n, mode="plain", out=out)
