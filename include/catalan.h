@@ -111,6 +111,36 @@ cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_li
 cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
                             size_t work_bytes, void* stream, uint32_t flags);
 
+/* Factorial ratios N = a_1! ... a_k! / (b_1! ... b_m!) (Sec. 6.3: the exponent
+ * of p is sum_i v_p(a_i!) - sum_j v_p(b_j!), and the reconstruction is the
+ * Phase 2 of C(n) unchanged): binomial and multinomial coefficients,
+ * factorials, super-factorials of up to 32 terms.  a[0..k), b[0..m) are host
+ * arrays, k, m <= CAT_RATIO_MAX_TERMS, every argument < 2^32.
+ *
+ * factorial_ratio_sizes: host only; upper bounds on the grouped prime entries,
+ *   on the limbs of N, and the workspace bytes.
+ * factorial_ratio_factor: Phase 1.  The primes with v_p(N) > 0 are grouped by
+ *   the bits of their exponents: group g holds, ascending, the primes whose
+ *   exponent has bit b set, and h_exps[g] = 2^b (bits ascending, at most 32
+ *   groups), so that N = prod_g (prod of group g)^(h_exps[g]).  Otherwise as
+ *   catalan_factor.
+ * factorial_ratio_exact: N as normalised limbs (N = 1 gives {1}); flags
+ *   CAT_MODE_BATCHED or CAT_MODE_PLAIN; d_limbs == NULL is a size query.
+ *   Synchronises `stream`.
+ * Errors: CAT_EINVAL for bad arguments and for a ratio that is not an integer
+ * (some exponent negative, found by Phase 1); CAT_ERANGE when an exponent
+ * reaches 2^32, a product would exceed the 2^27-coefficient transform, or a
+ * capacity is too small. */
+#define CAT_RATIO_MAX_TERMS 32
+cat_status factorial_ratio_sizes(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, size_t* max_primes,
+                                 size_t* max_limbs, size_t* workspace_bytes);
+cat_status factorial_ratio_factor(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, uint32_t* d_primes,
+                                  size_t primes_cap, uint32_t* h_exps, uint64_t* h_off, uint32_t* n_groups,
+                                  size_t* n_primes, void* d_work, size_t work_bytes, void* stream);
+cat_status factorial_ratio_exact(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, uint32_t* d_limbs,
+                                 size_t cap, size_t* n_limbs, void* d_work, size_t work_bytes, void* stream,
+                                 uint32_t flags);
+
 /* Asynchronous C(n), for request loops that keep many computations in
  * flight on several streams (every call returns without waiting for the GPU):
  *  catalan_begin    queues Phase 1 of n on `stream` in d_work (sized by

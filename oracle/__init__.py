@@ -78,6 +78,10 @@ def _load():
     lib.orc_catalan_mod_prime.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.orc_catalan_mod_prime.restype = ctypes.c_uint64
     lib.orc_catalan_low64.argtypes = [ctypes.c_uint64]
+    lib.orc_ratio_factor.argtypes = [u64p, ctypes.c_size_t, u64p, ctypes.c_size_t, u32p, u64p, ctypes.c_size_t, szp]
+    lib.orc_ratio_factor.restype = ctypes.c_int
+    lib.orc_ratio.argtypes = [u64p, ctypes.c_size_t, u64p, ctypes.c_size_t, u32p, ctypes.c_size_t, szp]
+    lib.orc_ratio.restype = ctypes.c_int
     lib.orc_catalan_low64.restype = ctypes.c_uint64
     _lib = lib
     return lib
@@ -221,3 +225,47 @@ def int_to_limbs(x: int, length: int | None = None) -> np.ndarray:
     if length is not None:
         nb = max(nb, length)
     return np.frombuffer(x.to_bytes(4 * nb, "little"), dtype="<u4").astype(np.uint32)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _args(xs):
+    return np.ascontiguousarray(np.asarray([int(x) for x in xs], dtype=np.uint64).reshape(-1))
+
+
+def ratio_factor(num, den=()):
+    """(primes uint32[], exponents uint64[]) of prod(num!) / prod(den!), p ascending,
+    exponent > 0 (Sec. 6.3, extended Legendre formula)."""
+    lib = _load()
+    a, b = _args(num), _args(den)
+    cnt = ctypes.c_size_t()
+    st = lib.orc_ratio_factor(_p(a, ctypes.c_uint64), len(a), _p(b, ctypes.c_uint64), len(b), None, None, 0,
+                              ctypes.byref(cnt))
+    if st:
+        raise OracleError("orc_ratio_factor: %d" % st)
+    pr = np.zeros(max(cnt.value, 1), dtype=np.uint32)
+    ex = np.zeros(max(cnt.value, 1), dtype=np.uint64)
+    st = lib.orc_ratio_factor(_p(a, ctypes.c_uint64), len(a), _p(b, ctypes.c_uint64), len(b),
+                              _p(pr, ctypes.c_uint32), _p(ex, ctypes.c_uint64), len(pr), ctypes.byref(cnt))
+    if st:
+        raise OracleError("orc_ratio_factor: %d" % st)
+    return pr[: cnt.value], ex[: cnt.value]
+
+
+def ratio(num, den=()) -> np.ndarray:
+    """prod(num!) / prod(den!) as normalised uint32 limbs; raises OracleError when
+    the ratio is not an integer."""
+    lib = _load()
+    a, b = _args(num), _args(den)
+    n = ctypes.c_size_t()
+    st = lib.orc_ratio(_p(a, ctypes.c_uint64), len(a), _p(b, ctypes.c_uint64), len(b), None, 0, ctypes.byref(n))
+    if st:
+        raise OracleError("orc_ratio: %d" % st)
+    out = np.zeros(max(n.value, 1), dtype=np.uint32)
+    st = lib.orc_ratio(_p(a, ctypes.c_uint64), len(a), _p(b, ctypes.c_uint64), len(b), _p(out, ctypes.c_uint32),
+                       len(out), ctypes.byref(n))
+    if st:
+        raise OracleError("orc_ratio: %d" % st)
+    return out[: n.value]

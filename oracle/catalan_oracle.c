@@ -384,6 +384,95 @@ int orc_catalan(uint64_t n, uint32_t *out, size_t cap, size_t *len)
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * Factorial ratios N = prod_i a_i! / prod_j b_j! (Sec. 6.3).  The exponent of
+ * p is sum_i v_p(a_i!) - sum_j v_p(b_j!) with Legendre's sums; N is the product
+ * over the primes p <= max(a_i, b_j) of p^{v_p(N)}, rebuilt as in Alg. 2:
+ * groups of equal exponent, Q_e by the balanced tree, P_e = Q_e^e, and the
+ * balanced tree over the P_e in exponent order.
+ * ------------------------------------------------------------------------- */
+
+/* (p, v_p(N)) for every prime with v_p(N) > 0, p ascending.  ORC_EINVAL for a
+ * negative exponent (N not an integer), ORC_ERANGE for an exponent >= 2^32 or
+ * more than cap primes.  primes_out == NULL: count only. */
+int orc_ratio_factor(const uint64_t *a, size_t k, const uint64_t *b, size_t m,
+                     uint32_t *primes_out, uint64_t *exp_out, size_t cap, size_t *np_out)
+{
+    uint64_t A = 0;
+    for (size_t i = 0; i < k; i++) { if (a[i] > 0xFFFFFFFFull) return ORC_EINVAL; if (a[i] > A) A = a[i]; }
+    for (size_t j = 0; j < m; j++) { if (b[j] > 0xFFFFFFFFull) return ORC_EINVAL; if (b[j] > A) A = b[j]; }
+    size_t bound = orc_pi_bound(A);
+    uint32_t *pr = (uint32_t *)malloc(sizeof(uint32_t) * (bound ? bound : 1));
+    if (!pr) return ORC_ENOMEM;
+    size_t np = A >= 2 ? orc_primes(A, pr, bound) : 0;
+    if (np == (size_t)-1) { free(pr); return ORC_EINTERNAL; }
+    size_t cnt = 0;
+    int st = ORC_OK;
+    for (size_t i = 0; i < np; i++) {
+        int64_t e = 0;
+        for (size_t t = 0; t < k; t++) e += (int64_t)orc_legendre(a[t], pr[i]);
+        for (size_t t = 0; t < m; t++) e -= (int64_t)orc_legendre(b[t], pr[i]);
+        if (e < 0) { st = ORC_EINVAL; break; }
+        if (e >= ((int64_t)1 << 32)) { st = ORC_ERANGE; break; }
+        if (e == 0) continue;
+        if (primes_out) {
+            if (cnt >= cap) { st = ORC_ERANGE; break; }
+            primes_out[cnt] = pr[i];
+            exp_out[cnt] = (uint64_t)e;
+        }
+        cnt++;
+    }
+    free(pr);
+    *np_out = cnt;
+    return st;
+}
+
+static int cmp_pe(const void *x, const void *y)
+{
+    const uint64_t *u = (const uint64_t *)x, *v = (const uint64_t *)y;   /* (e, p) pairs */
+    if (u[0] != v[0]) return u[0] < v[0] ? -1 : 1;
+    if (u[1] != v[1]) return u[1] < v[1] ? -1 : 1;
+    return 0;
+}
+
+/* N as normalised limbs; out == NULL is a size query. */
+int orc_ratio(const uint64_t *a, size_t k, const uint64_t *b, size_t m, uint32_t *out, size_t cap, size_t *len)
+{
+    size_t np = 0;
+    int st = orc_ratio_factor(a, k, b, m, NULL, NULL, 0, &np);
+    if (st) return st;
+    uint32_t *pr = (uint32_t *)malloc(sizeof(uint32_t) * (np ? np : 1));
+    uint64_t *ex = (uint64_t *)malloc(sizeof(uint64_t) * (np ? np : 1));
+    uint64_t *pe = (uint64_t *)malloc(2 * sizeof(uint64_t) * (np ? np : 1));
+    if (!pr || !ex || !pe) { free(pr); free(ex); free(pe); return ORC_ENOMEM; }
+    st = orc_ratio_factor(a, k, b, m, pr, ex, np, &np);
+    if (st) { free(pr); free(ex); free(pe); return st; }
+    /* groups G_e: exponent ascending, primes ascending inside a group */
+    for (size_t i = 0; i < np; i++) { pe[2 * i] = ex[i]; pe[2 * i + 1] = pr[i]; }
+    qsort(pe, np, 2 * sizeof(uint64_t), cmp_pe);
+    uint32_t *gp = (uint32_t *)malloc(sizeof(uint32_t) * (np ? np : 1));
+    uint32_t *gexp = (uint32_t *)malloc(sizeof(uint32_t) * (np ? np : 1));
+    uint64_t *goff = (uint64_t *)malloc(sizeof(uint64_t) * (np + 1));
+    uint32_t ng = 0;
+    goff[0] = 0;
+    for (size_t i = 0; i < np; i++) {
+        gp[i] = (uint32_t)pe[2 * i + 1];
+        if (i == 0 || pe[2 * i] != pe[2 * (i - 1)]) { gexp[ng] = (uint32_t)pe[2 * i]; ng++; }
+        goff[ng] = i + 1;
+    }
+    big_t c;
+    st = reconstruct(gp, gexp, goff, ng, &c);
+    free(pr); free(ex); free(pe); free(gp); free(gexp); free(goff);
+    if (st) return st;
+    *len = c.n;
+    if (out) {
+        if (cap < c.n) { free(c.d); return ORC_ERANGE; }
+        memcpy(out, c.d, c.n * 4);
+    }
+    free(c.d);
+    return ORC_OK;
+}
+
 /* Product of an arbitrary list of big integers by the same balanced tree;
  * items are given as one flat limb array with offsets (n_items+1 entries).
  * Result normalised; out == NULL is a size query. */

@@ -31,6 +31,7 @@ EXPORTS = [
     "cat_mul_plan_check", "cat_mul_plan_destroy", "bigint_residues", "cat_timer_set", "cat_timer_get",
     "catalan_begin", "cat_ticket_query", "catalan_continue", "catalan_end", "cat_ticket_release",
     "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
+    "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
 ]
 
 
@@ -107,6 +108,11 @@ def load(path: str = LIB_PATH):
         "cat_ticket_release": ([vp], st),
         "cat_tune_set": ([ctypes.POINTER(cat_tuning)], st),
         "cat_lookback_polls_set": ([ctypes.c_uint32], st),
+        "factorial_ratio_sizes": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, szp, szp, szp], st),
+        "factorial_ratio_factor": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, vp, ctypes.c_size_t, u32p, u64p,
+                                    u32p, szp, vp, ctypes.c_size_t, vp], st),
+        "factorial_ratio_exact": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, vp, ctypes.c_size_t, szp, vp,
+                                   ctypes.c_size_t, vp, ctypes.c_uint32], st),
         "cat_tune_get": ([ctypes.POINTER(cat_tuning)], st),
     }
     for name, (args, res) in sig.items():
@@ -259,6 +265,61 @@ def exact(n: int, mode: str = "graph", stream=None, out=None):
     st = lib.catalan_exact_ex(n, _ptr(out), out.numel(), ctypes.byref(nl), _ptr(w), w.numel(), _stream(stream),
                               _MODES[mode])
     _check(st, "catalan_exact")
+    return out[: nl.value]
+
+
+def _terms(xs):
+    arr = np.ascontiguousarray(np.asarray([int(x) for x in xs], dtype=np.uint64))
+    return arr, len(arr)
+
+
+def ratio_sizes(num, den=()):
+    """(max_primes, max_limbs, workspace_bytes) for prod(num!) / prod(den!) (host-only)."""
+    lib = load()
+    a, k = _terms(num)
+    b, m = _terms(den)
+    x, y, z = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.factorial_ratio_sizes(_p64(a), k, _p64(b), m, ctypes.byref(x), ctypes.byref(y), ctypes.byref(z)),
+           "factorial_ratio_sizes")
+    return x.value, y.value, z.value
+
+
+def ratio_factor(num, den=(), stream=None):
+    """Phase 1 of prod(num!) / prod(den!) on the GPU: (exps uint32[g] = 2^bit,
+    off uint64[g+1], grouped primes int32 device tensor)."""
+    torch = _torch()
+    lib = load()
+    a, k = _terms(num)
+    b, m = _terms(den)
+    max_primes, _, wbytes = ratio_sizes(num, den)
+    primes = torch.empty(max(max_primes, 1), dtype=torch.int32, device="cuda")
+    w = workspace(wbytes)
+    exps = np.zeros(MAX_GROUPS, dtype=np.uint32)
+    off = np.zeros(MAX_GROUPS + 1, dtype=np.uint64)
+    ng = ctypes.c_uint32()
+    npr = ctypes.c_size_t()
+    st = lib.factorial_ratio_factor(_p64(a), k, _p64(b), m, _ptr(primes), primes.numel(),
+                                    exps.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _p64(off), ctypes.byref(ng),
+                                    ctypes.byref(npr), _ptr(w), w.numel(), _stream(stream))
+    _check(st, "factorial_ratio_factor")
+    g = ng.value
+    return exps[:g].copy(), off[: g + 1].copy(), primes[: npr.value]
+
+
+def ratio_exact(num, den=(), mode: str = "batched", stream=None, out=None):
+    """prod(num!) / prod(den!) as normalised limbs in an int32 device tensor."""
+    torch = _torch()
+    lib = load()
+    a, k = _terms(num)
+    b, m = _terms(den)
+    _, max_limbs, wbytes = ratio_sizes(num, den)
+    w = workspace(wbytes)
+    if out is None:
+        out = torch.empty(max(max_limbs, 1), dtype=torch.int32, device="cuda")
+    nl = ctypes.c_size_t()
+    st = lib.factorial_ratio_exact(_p64(a), k, _p64(b), m, _ptr(out), out.numel(), ctypes.byref(nl), _ptr(w),
+                                   w.numel(), _stream(stream), _MODES[mode] & ~MODE_GRAPH)
+    _check(st, "factorial_ratio_exact")
     return out[: nl.value]
 
 

@@ -4,4 +4,5 @@
 #include "ntt.inc.hip"
 #include "small.inc.hip"
 #include "sieve.inc.hip"
+#include "ratio.inc.hip"
 #include "host.inc.hip"

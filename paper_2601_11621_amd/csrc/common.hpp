@@ -131,6 +131,7 @@ struct CrtSeg {
 #define CAT_DEVERR_NEG_EXP 2u       // negative exponent (C(n) not integral)
 #define CAT_DEVERR_BOUNDS 4u        // a prime count exceeded its buffer
 #define CAT_DEVERR_SCAN 8u          // a carry look-back gave up waiting (never expected)
+#define CAT_DEVERR_RANGE 16u        // an exponent reached 2^32
 
 // Ranges copied unchanged from one arena to the other (the last node of a
 // group with an odd node count is carried up a level).  Kernels that take a

@@ -299,6 +299,10 @@ Cls classify2(uint64_t la, uint64_t lb) {
   int k = ceil_log2(la + lb - 1);
   if (k < 6) k = 6;
   c.logN = k;
+  if (k > CAT_MAX_LOGN) {   // beyond the transform length: the plan is rejected
+    c.cls = CLS_LARGE;
+    return c;
+  }
   c.cls = g_tune.cls[k];
   c.logM = g_tune.log_row[k];
   c.maxL = g_tune.log_pass[k];
@@ -369,6 +373,10 @@ void build_crt_segs(Stage& s) {
 // ----------------------------------------------------------------------------
 struct Layout {
   uint64_t n = 0, s = 0, i0 = 0, i_end = 0, nseg = 0;
+  // factorial ratios: all primes with v_p(N) > 0 (capacity np_cap) before grouping
+  uint64_t np_cap = 0, nchunks = 0;
+  size_t P = 0, E = 0, chunk_cnt = 0, chunk_off = 0;      // in uint32 units
+  size_t rcounts = 0;                                      // bytes
   uint64_t Kmax = 0, post_cap = 0, res_len = 0, F_words = 0, nblk_max = 0;
   uint64_t res2_len = 0, F2_words = 0, nblk2_max = 0;   // scratch of the side branch
   size_t primes = 0, arenaA = 0, arenaB = 0, post = 0, res = 0, F = 0;       // in uint32 units
@@ -381,30 +389,20 @@ struct Layout {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // byte offsets inside the control block
-#define CTL_TOP 512
-#define CTL_ERR 520
-#define CTL_READ 528
-#define CTL_FLAGS 528
+#define CTL_TOP 1024
+#define CTL_ERR 1032
+#define CTL_READ 1040
+#define CTL_FLAGS 1040
 static_assert(sizeof(GroupTable) <= CTL_TOP, "group table must fit the control block head");
 
-Layout make_layout(uint64_t n) {
-  Layout L;
-  L.n = n;
-  L.s = isqrt64(2 * n);
-  L.i0 = (L.s + 1) / 2;
-  L.i_end = n;
+// Offsets of every buffer, given the sizes set in L (sieve range, Kmax,
+// post_cap, res2_len, and np_cap / nchunks for ratios).
+Layout layout_finish(Layout L) {
   L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + SIEVE_SEG - 1) / SIEVE_SEG : 0;
-  L.Kmax = std::max<uint64_t>(pi_bound(2 * n), 16);
-  const uint64_t sb = std::min<uint64_t>(pi_bound(L.s + 1), SEED_MAX);
-  L.post_cap = L.Kmax + 256 * sb + 4096;
   L.res_len = std::max(L.Kmax, L.post_cap) + 64;
   const uint64_t big = 1ull << ceil_log2(std::max(L.Kmax, L.post_cap));
   L.F_words = (big > (1ull << CAT_LDS_LOGT)) ? 12 * big + (1ull << 20) : (1ull << 20);
   L.nblk_max = L.res_len / CAT_CRT_BLOCK + 4096;
-  // The powers P_e (e >= 2) and their product R involve only primes below
-  // sqrt(2n), each prime power below 2^32: every step of them fits 64 limbs
-  // per seed prime.
-  L.res2_len = 64 * sb + 4096;
   L.F2_words = 12 * (1ull << ceil_log2(L.res2_len)) + (1ull << 16);
   L.nblk2_max = L.res2_len / CAT_CRT_BLOCK + 64;
   size_t off = 0;  // bytes
@@ -426,15 +424,38 @@ Layout make_layout(uint64_t n) {
   L.seg_cnt = take((L.nseg + 1) * 4) / 4;
   L.seg_off = take((L.nseg + 1) * 4) / 4;
   L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
-  // control block, cleared by Phase 1 (k_seeds): group table | top | error
-  // word | CRT look-back flags of the main and the side branch; the first
-  // CTL_READ bytes go back to the host in one copy
+  if (L.np_cap) {
+    L.P = take(L.np_cap * 4) / 4;
+    L.E = take(L.np_cap * 4) / 4;
+    L.chunk_cnt = take(L.nchunks * 32 * 4) / 4;
+    L.chunk_off = take(L.nchunks * 32 * 4) / 4;
+    L.rcounts = take(sizeof(RatioCounts));
+  }
+  // control block, cleared by Phase 1 (k_seeds / k_rseeds): group table | top
+  // | error word | CRT look-back flags of the main and the side branch; the
+  // first CTL_READ bytes go back to the host in one copy
   L.gtab = take(CTL_FLAGS + 4 * (L.nblk_max + L.nblk2_max));
   L.top = L.gtab + CTL_TOP;
   L.err = L.gtab + CTL_ERR;
   L.ctl_words = (CTL_FLAGS + 4 * (L.nblk_max + L.nblk2_max)) / 4;
   L.total = off;
   return L;
+}
+
+Layout make_layout(uint64_t n) {
+  Layout L;
+  L.n = n;
+  L.s = isqrt64(2 * n);
+  L.i0 = (L.s + 1) / 2;
+  L.i_end = n;
+  L.Kmax = std::max<uint64_t>(pi_bound(2 * n), 16);
+  const uint64_t sb = std::min<uint64_t>(pi_bound(L.s + 1), SEED_MAX);
+  L.post_cap = L.Kmax + 256 * sb + 4096;
+  // The powers P_e (e >= 2) and their product R involve only primes below
+  // sqrt(2n), each prime power below 2^32: every step of them fits 64 limbs
+  // per seed prime.
+  L.res2_len = 64 * sb + 4096;
+  return layout_finish(L);
 }
 
 // ----------------------------------------------------------------------------
@@ -452,6 +473,7 @@ struct Plan {
   bool result_is_one = false;
   uint64_t post_end = 0;        // end of the post-tree arena used
   uint64_t root[CAT_MAX_GROUPS] = {};   // Q_e of group g (uint32 offset), the same in both forms
+  uint64_t gbits[CAT_MAX_GROUPS] = {};  // bit-length bound of Q_e (group table)
   // Side branch (captured calls): after fork_count batched stages every group
   // with e >= 2 is complete, and post[0, post_final) (powers and R) may run
   // beside the remaining levels of Q_1; post[post_final..] (C = Q_1 R) waits
@@ -574,8 +596,13 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
 // Explicit products after the forest: P_e = Q_e^e (left-to-right binary
 // powering), R = prod_{e>=2} P_e (balanced, adjacent pairs), C = Q_1 * R.
 struct Item {
-  uint64_t pos, cap;   // absolute uint32 offset from the workspace base, capacity in limbs
+  uint64_t pos, cap;   // absolute uint32 offset from the workspace base, limbs read as the operand
+  uint64_t bits;       // upper bound on the bit length of the value
 };
+// the limbs an operand of `bits` bits needs, within the `alloc` limbs written
+inline uint64_t cap_of(uint64_t alloc, uint64_t bits) {
+  return std::max<uint64_t>(1, std::min<uint64_t>(alloc, (bits + 31) / 32));
+}
 
 void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vector<Item>& outs) {
   // group the products of one step by class; positions already assigned
@@ -632,13 +659,14 @@ void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vecto
 
 void plan_post(const Layout& Ly, Plan& P) {
   uint64_t bump = Ly.post;
-  auto alloc = [&](uint64_t cap) {
-    Item it{bump, cap};
-    bump += cap;
+  // a product's output: la + lb limbs written, read back as cap_of(...) limbs
+  auto alloc = [&](uint64_t limbs, uint64_t bits) {
+    Item it{bump, cap_of(limbs, bits), bits};
+    bump += limbs;
     return it;
   };
   std::vector<Item> pe;     // P_e for e >= 2, exponent ascending
-  Item q1{0, 0};
+  Item q1{0, 0, 0};
   bool has_q1 = false;
   // powers: all chains advance one step per stage
   struct Chain {
@@ -649,7 +677,9 @@ void plan_post(const Layout& Ly, Plan& P) {
   };
   std::vector<Chain> ch;
   for (uint32_t gi = 0; gi < P.ng; gi++) {
-    Item q{P.root[gi], P.off[gi + 1] - P.off[gi]};
+    // Q_e occupies K limbs of its node; its value fits ceil(gbits / 32) of them
+    const uint64_t K = P.off[gi + 1] - P.off[gi];
+    Item q{P.root[gi], cap_of(K, P.gbits[gi]), std::min<uint64_t>(P.gbits[gi], 32 * K)};
     if (P.exps[gi] == 1) {
       q1 = q;
       has_q1 = true;
@@ -668,10 +698,10 @@ void plan_post(const Layout& Ly, Plan& P) {
       if (c.bit < 0) continue;
       if (!c.sq_done) {
         pairs.push_back({c.r, c.r});
-        outs.push_back(alloc(2 * c.r.cap));
+        outs.push_back(alloc(2 * c.r.cap, 2 * c.r.bits));
       } else {
         pairs.push_back({c.r, c.q});
-        outs.push_back(alloc(c.r.cap + c.q.cap));
+        outs.push_back(alloc(c.r.cap + c.q.cap, c.r.bits + c.q.bits));
       }
       who.push_back(k);
     }
@@ -696,7 +726,7 @@ void plan_post(const Layout& Ly, Plan& P) {
     std::vector<Item> outs, next;
     for (size_t k = 0; k + 1 < pe.size(); k += 2) {
       pairs.push_back({pe[k], pe[k + 1]});
-      outs.push_back(alloc(pe[k].cap + pe[k + 1].cap));
+      outs.push_back(alloc(pe[k].cap + pe[k + 1].cap, pe[k].bits + pe[k + 1].bits));
       next.push_back(outs.back());
     }
     if (pe.size() & 1) next.push_back(pe.back());
@@ -707,7 +737,7 @@ void plan_post(const Layout& Ly, Plan& P) {
   if (!has_q1 || pe.empty()) P.fork_count = -1;   // nothing runs beside the Q_1 tree
   if (has_q1 && !pe.empty()) {
     std::vector<std::pair<Item, Item>> pairs{{q1, pe[0]}};
-    std::vector<Item> outs{alloc(q1.cap + pe[0].cap)};
+    std::vector<Item> outs{alloc(q1.cap + pe[0].cap, q1.bits + pe[0].bits)};
     add_products(P, pairs, outs);
     P.result_pos = outs[0].pos;
     P.result_cap = outs[0].cap;
@@ -785,7 +815,10 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
   Plan* P = new Plan();
   P->n = Ly.n;
   P->ng = gt.ngroups;
-  for (uint32_t gi = 0; gi < gt.ngroups; gi++) P->exps[gi] = gt.exps[gi];
+  for (uint32_t gi = 0; gi < gt.ngroups; gi++) {
+    P->exps[gi] = gt.exps[gi];
+    P->gbits[gi] = gt.gbits[gi];
+  }
   for (uint32_t gi = 0; gi <= gt.ngroups; gi++) P->off[gi] = gt.off[gi];
   plan_tree(Ly, *P, true);
   // products and their limbs are counted from the pairwise levels of the plain
@@ -801,6 +834,10 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
   // the plan must fit the workspace layout sized from n alone
   for (Stage* s : all) {
     if (s->is_leaf) continue;
+    if (s->logN > CAT_MAX_LOGN) {   // a product longer than the longest exact transform
+      free_plan(P);
+      return CAT_ERANGE;
+    }
     uint64_t rmax = 0;
     for (const CrtSeg& sg : s->host_segs) rmax = std::max(rmax, sg.res_pos + sg.len);
     const uint64_t fneed = (s->cls == CLS_LARGE) ? s->nmul * 6ull << s->logN : 0;
@@ -1120,7 +1157,7 @@ Plan* find_plan(uint64_t n, const GroupTable& gt) {
   Plan* P = it->second;
   if (P->ng != gt.ngroups) return nullptr;
   for (uint32_t k = 0; k < gt.ngroups; k++)
-    if (P->exps[k] != gt.exps[k] || P->off[k + 1] != gt.off[k + 1]) return nullptr;
+    if (P->exps[k] != gt.exps[k] || P->off[k + 1] != gt.off[k + 1] || P->gbits[k] != gt.gbits[k]) return nullptr;
   return P;
 }
 
@@ -1317,7 +1354,7 @@ cat_status mul_plan_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_
 }
 
 // ----------------------------------------------------------------------------
-// Asynchronous C(n): tickets.  Each ticket owns a 1 KB slice of pinned host
+// Asynchronous C(n): tickets.  Each ticket owns a 2 KB slice of pinned host
 // memory (group table, top index, error word) and an event; slices and events
 // are pooled so the serving loop never allocates.
 // ----------------------------------------------------------------------------
@@ -1339,7 +1376,7 @@ struct TicketPool {
   std::vector<hipEvent_t> free_events;
 };
 TicketPool tp;
-#define TICKET_SLICE 1024
+#define TICKET_SLICE 2048
 #define TICKET_SLICES 4096
 
 cat_status ticket_alloc(Ticket** out) {
@@ -1378,6 +1415,118 @@ void ticket_free(Ticket* t) {
 // ============================================================================
 // C ABI
 // ============================================================================
+// ----------------------------------------------------------------------------
+// Factorial ratios N = prod_i a_i! / prod_j b_j! (Sec. 6.3)
+// ----------------------------------------------------------------------------
+struct RatioSpec {
+  RatioTerms rt{};
+  uint64_t A = 0;        // largest argument
+  uint64_t S = 0;        // sum of the numerator arguments
+  double log2N = 0;      // log2 of N (from log-gamma), 0 when N = 1
+};
+
+cat_status ratio_spec(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, RatioSpec* out) {
+  if (k > RATIO_MAX_TERMS || m > RATIO_MAX_TERMS || (k && !a) || (m && !b)) return CAT_EINVAL;
+  RatioSpec r;
+  r.rt.k = k;
+  r.rt.m = m;
+  double lg = 0;
+  for (uint32_t i = 0; i < k; i++) {
+    if (a[i] > 0xFFFFFFFFull) return CAT_EINVAL;
+    r.rt.a[i] = (uint32_t)a[i];
+    r.A = std::max(r.A, a[i]);
+    r.S += a[i];
+    lg += std::lgamma((double)a[i] + 1.0);
+  }
+  for (uint32_t j = 0; j < m; j++) {
+    if (b[j] > 0xFFFFFFFFull) return CAT_EINVAL;
+    r.rt.b[j] = (uint32_t)b[j];
+    r.A = std::max(r.A, b[j]);
+    lg -= std::lgamma((double)b[j] + 1.0);
+  }
+  r.log2N = std::max(0.0, lg / std::log(2.0));
+  *out = r;
+  // N itself must fit the longest exact product (2^27 coefficients)
+  if (r.log2N > 32.0 * (double)((1ull << CAT_MAX_LOGN) - 64)) return CAT_ERANGE;
+  return CAT_OK;
+}
+
+// upper bound on the limbs of N (a non-integral ratio is rejected later)
+uint64_t ratio_limbs_bound(const RatioSpec& r) {
+  return (uint64_t)((r.log2N * (1.0 + 1e-12) + 64.0) / 32.0) + 2;
+}
+
+Layout make_layout_ratio(const RatioSpec& r) {
+  Layout L;
+  L.n = 0;
+  L.s = isqrt64(r.A);
+  L.i0 = (L.s + 1) / 2;
+  L.i_end = (r.A + 1) / 2;   // odd m = 2i + 1 <= A
+  L.np_cap = pi_bound(r.A) + 64;
+  L.nchunks = (L.np_cap + RATIO_CHUNK - 1) / RATIO_CHUNK;
+  // grouped entries: p enters once per set bit of v_p(N) <= S / (p - 1), so a
+  // bit t needs p <= S / 2^t + 1
+  uint64_t ent = 0;
+  for (uint64_t x = r.S; x >= 1; x >>= 1) ent += pi_bound(std::min<uint64_t>(r.A, x + 1));
+  L.Kmax = std::max<uint64_t>(ent, 16);
+  // post-tree allocations: the power chains, the outer tree and the final
+  // product together stay below 16 log2(N) / 32 limbs plus the operands' slack
+  L.post_cap = (uint64_t)(16.0 * (r.log2N + 64.0) / 32.0) + L.Kmax + 8192;
+  L.res2_len = 4096;
+  return layout_finish(L);
+}
+
+cat_status run_phase1_ratio(const Layout& Ly, const RatioSpec& r, char* wb, uint32_t* primes, uint64_t cap,
+                            hipStream_t st, uint64_t* launches) {
+  uint32_t* W = (uint32_t*)wb;
+  GroupTable* gt = (GroupTable*)(wb + Ly.gtab);
+  RatioCounts* rc = (RatioCounts*)(wb + Ly.rcounts);
+  hipLaunchKernelGGL(k_rseeds, dim3(1), dim3(1024), 0, st, r.rt, (uint32_t)Ly.s, W + Ly.seeds, W + Ly.seed_e, gt,
+                     (uint32_t*)gt, (uint64_t)Ly.ctl_words, rc);
+  LAUNCHCHK();
+  if (Ly.nseg > 0) {
+    hipLaunchKernelGGL(k_rsieve, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, r.rt, Ly.i0, Ly.i_end,
+                       (const uint32_t*)(W + Ly.seeds), gt, W + Ly.bitmap, W + Ly.seg_cnt);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_rscan, dim3(1), dim3(1024), 0, st, (uint32_t)Ly.nseg, (const uint32_t*)(W + Ly.seg_cnt),
+                     W + Ly.seg_off, (const uint32_t*)(W + Ly.seeds), (const uint32_t*)(W + Ly.seed_e), gt, W + Ly.P,
+                     W + Ly.E, (uint64_t)Ly.np_cap, rc);
+  LAUNCHCHK();
+  if (Ly.nseg > 0) {
+    hipLaunchKernelGGL(k_rscatter, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, r.rt, Ly.i0,
+                       (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
+                       W + Ly.P, W + Ly.E, (uint64_t)Ly.np_cap);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_rbits, dim3((uint32_t)Ly.nchunks), dim3(256), 0, st, (const uint32_t*)(W + Ly.P),
+                     (const uint32_t*)(W + Ly.E), (const RatioCounts*)rc, W + Ly.chunk_cnt, rc);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_rbitscan, dim3(32), dim3(1024), 0, st, (uint32_t)Ly.nchunks, (const uint32_t*)(W + Ly.chunk_cnt),
+                     W + Ly.chunk_off);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_rtable, dim3(1), dim3(64), 0, st, (const RatioCounts*)rc, gt, cap);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_rbitscatter, dim3((uint32_t)Ly.nchunks), dim3(256), 0, st, (const uint32_t*)(W + Ly.P),
+                     (const uint32_t*)(W + Ly.E), (const RatioCounts*)rc, (const uint32_t*)(W + Ly.chunk_off),
+                     (const GroupTable*)gt, primes, cap);
+  LAUNCHCHK();
+  *launches += Ly.nseg > 0 ? 8 : 6;
+  return CAT_OK;
+}
+
+// the group table of a ratio's Phase 1, with its error word mapped
+cat_status read_groups_ratio(const Layout& Ly, char* wb, hipStream_t st, GroupTable* out) {
+  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.gtab, sizeof(GroupTable), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  memcpy(out, g.pin, sizeof(GroupTable));
+  if (out->err & CAT_DEVERR_NEG_EXP) return CAT_EINVAL;    // N is not an integer
+  if (out->err & CAT_DEVERR_RANGE) return CAT_ERANGE;      // an exponent reaches 2^32
+  if (out->err & CAT_DEVERR_BOUNDS) return CAT_EINTERNAL;
+  if (out->ngroups > CAT_MAX_GROUPS) return CAT_EINTERNAL;
+  return CAT_OK;
+}
+
 extern "C" {
 
 cat_status cat_init(int device) {
@@ -1922,6 +2071,126 @@ cat_status cat_ticket_release(cat_ticket ticket) {
 cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work, size_t work_bytes,
                          void* stream) {
   return catalan_exact_ex(n, d_limbs, cap, n_limbs, d_work, work_bytes, stream, CAT_MODE_BATCHED | CAT_MODE_GRAPH);
+}
+
+cat_status factorial_ratio_sizes(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, size_t* max_primes,
+                                 size_t* max_limbs, size_t* workspace_bytes) {
+  RatioSpec r;
+  STCHK(ratio_spec(a, k, b, m, &r));
+  const Layout Ly = make_layout_ratio(r);
+  if (max_primes) *max_primes = (size_t)Ly.Kmax;
+  if (max_limbs) *max_limbs = (size_t)ratio_limbs_bound(r);
+  if (workspace_bytes) *workspace_bytes = Ly.total;
+  return CAT_OK;
+}
+
+cat_status factorial_ratio_factor(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, uint32_t* d_primes,
+                                  size_t primes_cap, uint32_t* h_exps, uint64_t* h_off, uint32_t* n_groups,
+                                  size_t* n_primes, void* d_work, size_t work_bytes, void* stream) {
+  if (!h_exps || !h_off || !n_groups || !n_primes || !d_work) return CAT_EINVAL;
+  if (!d_primes && primes_cap > 0) return CAT_EINVAL;
+  RatioSpec r;
+  STCHK(ratio_spec(a, k, b, m, &r));
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  const Layout Ly = make_layout_ratio(r);
+  if (work_bytes < Ly.total) return CAT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t launches = 0;
+  uint32_t dummy = 0;
+  STCHK(run_phase1_ratio(Ly, r, (char*)d_work, d_primes ? d_primes : &dummy, d_primes ? primes_cap : 0, st,
+                         &launches));
+  GroupTable gt;
+  const cat_status e = read_groups_ratio(Ly, (char*)d_work, st, &gt);
+  if (e != CAT_OK && !(e == CAT_EINTERNAL && (gt.err & CAT_DEVERR_BOUNDS))) return e;
+  *n_groups = gt.ngroups;
+  for (uint32_t q = 0; q < gt.ngroups; q++) h_exps[q] = gt.exps[q];
+  for (uint32_t q = 0; q <= gt.ngroups; q++) h_off[q] = gt.off[q];
+  *n_primes = (size_t)gt.off[gt.ngroups];
+  g.stats = cat_stats{};
+  g.stats.launches = launches;
+  g.stats.n_primes = *n_primes;
+  if (*n_primes > primes_cap) return CAT_ERANGE;
+  return CAT_OK;
+}
+
+cat_status factorial_ratio_exact(const uint64_t* a, uint32_t k, const uint64_t* b, uint32_t m, uint32_t* d_limbs,
+                                 size_t cap, size_t* n_limbs, void* d_work, size_t work_bytes, void* stream,
+                                 uint32_t flags) {
+  if (!n_limbs) return CAT_EINVAL;
+  RatioSpec r;
+  STCHK(ratio_spec(a, k, b, m, &r));
+  if (!d_limbs) {
+    *n_limbs = (size_t)ratio_limbs_bound(r);
+    return CAT_OK;
+  }
+  if (!d_work) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  const Layout Ly = make_layout_ratio(r);
+  if (work_bytes < Ly.total) return CAT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)d_work;
+  const bool plain = (flags & CAT_MODE_PLAIN) != 0;
+  uint64_t launches = 0;
+  STCHK(run_phase1_ratio(Ly, r, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, st, &launches));
+  GroupTable gt;
+  STCHK(read_groups_ratio(Ly, wb, st, &gt));
+  Plan* P = nullptr;
+  STCHK(make_plan(Ly, gt, &P));
+  cat_status res = CAT_OK;
+  if (P->result_is_one) {
+    if (cap < 1) {
+      *n_limbs = 1;
+      res = CAT_ERANGE;
+    } else {
+      hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, d_limbs, (uint64_t)1, 1u);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        g.last_err = (int)e;
+        res = CAT_EDEVICE;
+      }
+      *n_limbs = 1;
+    }
+    free_plan(P);
+    return res;
+  }
+  Exec X = make_exec(Ly, wb, st);
+  unsigned long long* top = (unsigned long long*)(wb + Ly.top);
+  res = run_phase2(X, *P, plain);
+  if (res == CAT_OK) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, st, X.W + P->result_pos, P->result_cap, top, d_limbs,
+                       ncopy);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(g.pin, wb + Ly.top, 12, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      g.last_err = (int)e;
+      res = CAT_EDEVICE;
+    }
+  }
+  cat_stats stats{};
+  stats.products = P->products;
+  stats.product_limbs = P->product_limbs;
+  stats.launches = launches + X.launches + 1;
+  stats.n_primes = gt.off[gt.ngroups];
+  stats.levels = P->levels;
+  free_plan(P);
+  g.stats = stats;
+  if (res != CAT_OK) return res;
+  uint64_t L = 0;
+  uint32_t derr = 0;
+  memcpy(&L, g.pin, 8);
+  memcpy(&derr, (char*)g.pin + 8, 4);
+  if (derr || L == 0) return CAT_EINTERNAL;
+  *n_limbs = (size_t)L;
+  if (cap < L) return CAT_ERANGE;
+  return CAT_OK;
 }
 
 }  // extern "C"

@@ -32,6 +32,9 @@ struct GroupTable {
   uint32_t err;
   uint32_t exps[CAT_MAX_GROUPS];
   uint64_t off[CAT_MAX_GROUPS + 1];
+  // upper bound on the bit length of Q_g (sum of the bit lengths of its
+  // primes; 32 per prime where not summed), which bounds the power chains
+  uint64_t gbits[CAT_MAX_GROUPS];
 };
 
 // Exclusive scan over a block of up to 16 wave64s.  tmp: >= 40 words.
@@ -72,31 +75,25 @@ __device__ __forceinline__ uint32_t legendre_dev(uint32_t m, uint32_t p) {
 }
 
 // ---------------------------------------------------------------------------
-// ctl: the call's control block (group table first), ctl_words words, cleared
-// here before anything else of the call writes to it.
-__global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t* seeds, int32_t* seed_e,
-                                                GroupTable* gt, uint32_t* __restrict__ ctl, uint64_t ctl_words) {
-  __shared__ uint8_t comp[65536];
-  __shared__ uint32_t tmp[40];
-  __shared__ uint32_t small[64];
-  __shared__ uint32_t nsmall;
+// The primes q <= s (s < 2^16) in ascending order, by a workgroup of up to 1024
+// threads sieving a byte map in LDS (comp: s+1 bytes); returns their count.
+__device__ uint32_t build_seeds(uint32_t s, uint8_t* comp, uint32_t* tmp, uint32_t* small, uint32_t* nsmall,
+                                uint32_t* seeds) {
   const uint32_t T = blockDim.x, tid = threadIdx.x;
-  for (uint64_t k = tid; k < ctl_words; k += T) ctl[k] = 0u;
-  __threadfence_block();
   for (uint32_t i = tid; i <= s; i += T) comp[i] = (i < 2) ? 1 : 0;
   // primes up to isqrt(s) <= 255 by trial division, one thread per candidate
   uint32_t r = 0;
   while ((r + 1) * (r + 1) <= s) r++;
-  if (tid == 0) nsmall = 0;
+  if (tid == 0) *nsmall = 0;
   __syncthreads();
   if (tid >= 2 && tid <= r) {
     bool isq = true;
     for (uint32_t d = 2; d * d <= tid; d++)
       if (tid % d == 0) { isq = false; break; }
-    if (isq) small[atomicAdd(&nsmall, 1u)] = tid;
+    if (isq) small[atomicAdd(nsmall, 1u)] = tid;
   }
   __syncthreads();
-  for (uint32_t k = 0; k < nsmall; k++) {
+  for (uint32_t k = 0; k < *nsmall; k++) {
     const uint32_t q = small[k];
     for (uint32_t m = q * q + tid * q; m <= s; m += T * q) comp[m] = 1;
   }
@@ -110,6 +107,61 @@ __global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t
   uint32_t pos = block_excl_scan_1024(cnt, tmp, &total);
   for (uint32_t i = lo; i < hi; i++)
     if (!comp[i]) seeds[pos++] = i;
+  return total;
+}
+
+// Bit map of the odd numbers 2i+1, i in [i_lo, i_lo + len), that no odd seed
+// divides (seeds[0] = 2 is skipped; every seed q has q*q above the segment's
+// composites it must strike, so what stays is prime).  bits: SIEVE_WORDS words.
+__device__ void mark_segment(uint32_t* bits, uint64_t i_lo, uint32_t len, const uint32_t* seeds, uint32_t nseeds) {
+  const uint32_t T = blockDim.x, tid = threadIdx.x;
+  for (uint32_t w = tid; w < SIEVE_WORDS; w += T) {
+    uint32_t b0 = w * 32;
+    uint32_t v = 0;
+    if (b0 + 32 <= len) v = 0xFFFFFFFFu;
+    else if (b0 < len) v = (1u << (len - b0)) - 1u;
+    bits[w] = v;
+  }
+  __syncthreads();
+  const uint64_t m_lo = 2 * i_lo + 1;
+  // small odd seeds: every thread marks a share of the multiples of q
+  uint32_t k = 1;
+  for (; k < nseeds; k++) {
+    uint64_t q = seeds[k];
+    if (q * SIEVE_THREADS > 2 * SIEVE_SEG) break;   // fewer multiples than 2 per thread
+    uint64_t t = (m_lo + q - 1) / q;
+    if (t < q) t = q;
+    if (!(t & 1)) t++;
+    uint64_t idx = (q * t - 1) / 2 - i_lo;
+    for (uint64_t x = idx + (uint64_t)tid * q; x < len; x += (uint64_t)T * q)
+      atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
+  }
+  // large seeds: one thread per prime
+  for (uint32_t kk = k + tid; kk < nseeds; kk += T) {
+    uint64_t q = seeds[kk];
+    uint64_t t = (m_lo + q - 1) / q;
+    if (t < q) t = q;
+    if (!(t & 1)) t++;
+    uint64_t idx = (q * t - 1) / 2 - i_lo;
+    for (uint64_t x = idx; x < len; x += q)
+      atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// ctl: the call's control block (group table first), ctl_words words, cleared
+// here before anything else of the call writes to it.
+__global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t* seeds, int32_t* seed_e,
+                                                GroupTable* gt, uint32_t* __restrict__ ctl, uint64_t ctl_words) {
+  __shared__ uint8_t comp[65536];
+  __shared__ uint32_t tmp[40];
+  __shared__ uint32_t small[64];
+  __shared__ uint32_t nsmall;
+  const uint32_t T = blockDim.x, tid = threadIdx.x;
+  for (uint64_t k = tid; k < ctl_words; k += T) ctl[k] = 0u;
+  __threadfence_block();
+  const uint32_t total = build_seeds(s, comp, tmp, small, &nsmall, seeds);
   if (tid == 0) gt->nseeds = total;
   __syncthreads();
   __threadfence_block();
@@ -140,39 +192,7 @@ __global__ void __launch_bounds__(SIEVE_THREADS) k_sieve(uint64_t n, uint64_t i0
   const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SIEVE_SEG;
   const uint64_t i_hi = min(i_lo + SIEVE_SEG, i_end);
   const uint32_t len = (uint32_t)(i_hi - i_lo);
-  for (uint32_t w = tid; w < SIEVE_WORDS; w += T) {
-    uint32_t b0 = w * 32;
-    uint32_t v = 0;
-    if (b0 + 32 <= len) v = 0xFFFFFFFFu;
-    else if (b0 < len) v = (1u << (len - b0)) - 1u;
-    bits[w] = v;
-  }
-  __syncthreads();
-  const uint32_t nseeds = gt->nseeds;
-  const uint64_t m_lo = 2 * i_lo + 1;
-  // small odd seeds: every thread marks a share of the multiples of q
-  uint32_t k = 1;
-  for (; k < nseeds; k++) {
-    uint64_t q = seeds[k];
-    if (q * SIEVE_THREADS > 2 * SIEVE_SEG) break;   // fewer multiples than 2 per thread
-    uint64_t t = (m_lo + q - 1) / q;
-    if (t < q) t = q;
-    if (!(t & 1)) t++;
-    uint64_t idx = (q * t - 1) / 2 - i_lo;
-    for (uint64_t x = idx + (uint64_t)tid * q; x < len; x += (uint64_t)T * q)
-      atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
-  }
-  // large seeds: one thread per prime
-  for (uint32_t kk = k + tid; kk < nseeds; kk += T) {
-    uint64_t q = seeds[kk];
-    uint64_t t = (m_lo + q - 1) / q;
-    if (t < q) t = q;
-    if (!(t & 1)) t++;
-    uint64_t idx = (q * t - 1) / 2 - i_lo;
-    for (uint64_t x = idx; x < len; x += q)
-      atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
-  }
-  __syncthreads();
+  mark_segment(bits, i_lo, len, seeds, gt->nseeds);
   // keep primes with e_p = 1, count them
   uint32_t cnt = 0;
   const uint32_t n32 = (uint32_t)n;   // n < 2^31
@@ -200,6 +220,7 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
                                                  uint32_t* primes, uint64_t cap, GroupTable* gt) {
   __shared__ uint32_t tmp[40];
   __shared__ uint32_t cnt_e[CAT_MAX_GROUPS + 1];
+  __shared__ unsigned long long bits_e[CAT_MAX_GROUPS + 1];
   __shared__ uint64_t goff[CAT_MAX_GROUPS + 2];
   const uint32_t T = blockDim.x, tid = threadIdx.x;
   // 1. exclusive scan of the segment counts
@@ -211,12 +232,18 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
   uint32_t pos = block_excl_scan_1024(c, tmp, &total_large);
   for (uint32_t i = lo; i < hi; i++) { seg_off[i] = pos; pos += seg_cnt[i]; }
   // 2. seed counts per exponent
-  if (tid <= CAT_MAX_GROUPS) cnt_e[tid] = 0;
+  if (tid <= CAT_MAX_GROUPS) {
+    cnt_e[tid] = 0;
+    bits_e[tid] = 0;
+  }
   __syncthreads();
   const uint32_t ns = gt->nseeds;
   for (uint32_t k = tid; k < ns; k += T) {
     int32_t e = seed_e[k];
-    if (e > 0 && e <= CAT_MAX_GROUPS) atomicAdd(&cnt_e[e], 1u);
+    if (e > 0 && e <= CAT_MAX_GROUPS) {
+      atomicAdd(&cnt_e[e], 1u);
+      atomicAdd(&bits_e[e], (unsigned long long)(32 - __clz(seeds[k])));
+    }
   }
   __syncthreads();
   // 3. group table (exponent ascending, empty groups dropped)
@@ -229,6 +256,8 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
       if (cnt == 0) continue;
       gt->exps[g] = e;
       gt->off[g] = o;
+      // G_1 holds the large primes: no tighter bound is needed for it
+      gt->gbits[g] = e == 1 ? 32 * cnt : (uint64_t)bits_e[e];
       o += cnt;
       g++;
     }

@@ -209,3 +209,35 @@ def limbs_mod_small(limbs, q: int, chunk: int = 1 << 20) -> int:
 
 def catalan_comb(n: int) -> int:
     return math.comb(2 * n, n) // (n + 1)
+
+
+# ---------------------------------------------------------------- factorial ratios
+def legendre_digits(n: int, p: int) -> int:
+    """v_p(n!) = (n - s_p(n)) / (p - 1), s_p the base-p digit sum (Legendre's
+    digit-sum form; independent of the repeated-division sums)."""
+    s, m = 0, n
+    while m:
+        s += m % p
+        m //= p
+    return (n - s) // (p - 1)
+
+
+def ratio_exponents(num, den, primes_list):
+    """v_p(prod num! / prod den!) for every p in primes_list, by digit sums."""
+    return [sum(legendre_digits(a, p) for a in num) - sum(legendre_digits(b, p) for b in den) for p in primes_list]
+
+
+def ratio_value(num, den=()):
+    """prod num! / prod den! with Python integers (exact division checked)."""
+    import math
+
+    top = 1
+    for a in num:
+        top *= math.factorial(a)
+    bot = 1
+    for b in den:
+        bot *= math.factorial(b)
+    q, r = divmod(top, bot)
+    if r:
+        raise ValueError("not an integer")
+    return q

@@ -85,3 +85,24 @@ def test_binding_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         cat.exact(10)
+
+
+def test_ratio_sizes_host_only():
+    """factorial_ratio_sizes needs no GPU: bounds grow with the arguments; bad
+    arguments and results beyond the longest transform are refused."""
+    import paper_2601_11621_amd as cat
+
+    p1, l1, w1 = cat.ratio_sizes([1000], [400, 600])
+    p2, l2, w2 = cat.ratio_sizes([10**6], [400000, 600000])
+    assert 0 < p1 < p2 and 0 < l1 < l2 and 0 < w1 < w2
+    # C(1000, 400) has 992 bits: 31 limbs, the bound is a little above
+    assert 31 <= l1 <= 40
+    with pytest.raises(cat.CatalanError) as e:
+        cat.ratio_sizes([2**28])             # 2^28! needs more than 2^27 limbs
+    assert e.value.status == cat.CAT_ERANGE
+    with pytest.raises(cat.CatalanError) as e:
+        cat.ratio_sizes([2**32])
+    assert e.value.status == cat.CAT_EINVAL
+    with pytest.raises(cat.CatalanError) as e:
+        cat.ratio_sizes(list(range(33)))
+    assert e.value.status == cat.CAT_EINVAL

@@ -257,3 +257,64 @@ def test_residue_routines_match_python_definitions():
     n = 10**5
     assert oracle.catalan_mod_prime(n, 2**32 - 5) == pins.catalan_mod_prime_product(n, 2**32 - 5)
     assert oracle.catalan_low64(n) == pins.catalan_low64(n)
+
+
+# ------------------------------------------------------------ factorial ratios (Sec. 6.3)
+RATIOS = [
+    ([10], [3, 7]), ([100], [37, 63]), ([1000], [1, 999]), ([5000], [1234, 3766]),
+    ([30], [10, 10, 10]), ([25], [4, 5, 6, 10]),                  # multinomials
+    ([400], []), ([1], []), ([0], []), ([], []),                  # factorials, empty product
+    ([1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12], []),                # super-factorial sf(12)
+    ([10], [4, 4]), ([2 * 777], [777, 778]),                      # an integral non-binomial; C(777)
+    ([3000, 17], [2999, 5, 12]),
+]
+
+
+@pytest.mark.parametrize("num,den", RATIOS)
+def test_ratio_exponents_match_digit_sum_formula(num, den):
+    """Every exponent of the oracle's ratio factorisation against Legendre's
+    digit-sum form; primes absent from the list have exponent 0."""
+    import sympy
+
+    A = max(list(num) + list(den) + [1])
+    plist = list(sympy.primerange(2, A + 1))
+    want = pins.ratio_exponents(num, den, plist)
+    pr, ex = oracle.ratio_factor(num, den)
+    got = dict(zip(pr.tolist(), ex.tolist()))
+    for p, e in zip(plist, want):
+        assert got.get(p, 0) == e, (p, e)
+    assert all(e > 0 for e in ex.tolist())
+
+
+@pytest.mark.parametrize("num,den", RATIOS)
+def test_ratio_values_match_python_integers(num, den):
+    assert oracle.limbs_to_int(oracle.ratio(num, den)) == pins.ratio_value(num, den)
+
+
+def test_ratio_binomials_all_small():
+    import math
+
+    for n in range(0, 90):
+        for k in range(0, n + 1):
+            assert oracle.limbs_to_int(oracle.ratio([n], [k, n - k])) == math.comb(n, k), (n, k)
+
+
+def test_ratio_large_binomial_and_factorial():
+    import math
+
+    assert oracle.limbs_to_int(oracle.ratio([100000], [31415, 68585])) == math.comb(100000, 31415)
+    assert oracle.limbs_to_int(oracle.ratio([20000])) == math.factorial(20000)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 13, 1000, 100000])
+def test_ratio_reproduces_catalan(n):
+    """C(n) = (2n)! / (n! (n+1)!) through the ratio route equals the Catalan oracle."""
+    assert np.array_equal(oracle.ratio([2 * n], [n, n + 1]), oracle.catalan(n))
+
+
+@pytest.mark.parametrize("num,den", [([3], [4]), ([4], [3, 3]), ([6], [4, 4])])
+def test_ratio_not_integral_rejected(num, den):
+    with pytest.raises(oracle.OracleError):
+        oracle.ratio(num, den)
+    with pytest.raises(ValueError):
+        pins.ratio_value(num, den)
