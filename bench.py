@@ -164,6 +164,49 @@ def batch_bench(cat, steps):
             "inputs": "numpy default_rng(0): la, lb = rint(2**U(6,16)) x 4096 each, limbs U[0,2^32)"}
 
 
+def _prod_mod(lo: int, hi: int, q: int) -> int:
+    """prod_{k=lo}^{hi} k mod q (q < 2^32), by a vectorised pairwise reduction."""
+    import numpy as np
+
+    if hi < lo:
+        return 1 % q
+    v = (np.arange(lo, hi + 1, dtype=np.uint64) % np.uint64(q))
+    while len(v) > 1:
+        if len(v) & 1:
+            v = np.append(v, np.uint64(1))
+        v = (v[0::2] * v[1::2]) % np.uint64(q)
+    return int(v[0])
+
+
+def ratio_bench(cat, reps=5):
+    """Factorial ratios (the reconstruction engine on other exponent sources):
+    the central binomial C(2*10^7, 10^7) and 10^6!, batched, checked by their
+    residue mod the prime 2^32 - 5 from the product formula."""
+    import numpy as np
+    import torch
+
+    q = 2**32 - 5
+    out = {}
+    for name, num, den in [("binomial_2e7_1e7", [2 * 10**7], [10**7, 10**7]), ("factorial_1e6", [10**6], [])]:
+        want = _prod_mod(1, num[0], q)
+        for d in den:
+            want = want * pow(_prod_mod(1, d, q), q - 2, q) % q
+        t = cat.ratio_exact(num, den)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            t = cat.ratio_exact(num, den)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        st = cat.stats()
+        ms = float(np.median(ts)) * 1e3
+        out[name] = {"num": num, "den": den, "ms": round(ms, 3), "result_limbs": int(t.numel()),
+                     "product_limbs": st["product_limbs"], "limbs_per_s": st["product_limbs"] / (ms / 1e3),
+                     "verified_mod_2p32_minus_5": cat.residues(t)[0] == want}
+    return out
+
+
 def serving_bench(cat, count=1100, warm=100, slots=8, budget=16 << 30, frac=0.7):
     """Request stream of catalan_exact(n), n = floor(10^(3 + 4u)) from
     default_rng(11621): closed-loop saturation first, then Poisson arrivals at
@@ -244,6 +287,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-product level-batch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
+    ap.add_argument("--no-ratio", action="store_true", help="skip the factorial-ratio measurement")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--only-kernel", default="", help="profiling aid: run graph steps only")
@@ -345,6 +389,9 @@ def main():
     if serving:
         log("bench: serving p50 %.2f ms p99 %.2f ms %.0f req/s" % (serving["p50_ms"], serving["p99_ms"],
                                                                   serving["req_per_s"]))
+    ratios = None if args.no_ratio else ratio_bench(cat)
+    if ratios:
+        log("bench: ratios %s" % {k: v["ms"] for k, v in ratios.items()})
     cpu = None if args.no_cpu else cpu_baseline(n, product_limbs)
 
     line = {
@@ -371,6 +418,7 @@ def main():
         "cpu_baseline": cpu,
         "level_batch_4096": batch,
         "serving": serving,
+        "factorial_ratios": ratios,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()} if kt else None,
         "paper_context": {"wall_s_n1e7": 6.817, "hardware": "AMD Ryzen 9 4900HS laptop, Python 3.11 + gmpy2 "
                                                             "(Table 2, proposed algorithm)"},
