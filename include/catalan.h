@@ -111,6 +111,24 @@ cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_li
 cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
                             size_t work_bytes, void* stream, uint32_t flags);
 
+/* Phase 2 on a caller's factorisation (Alg. 2, the reconstruction engine):
+ * N = prod_g (prod of the entries of group g)^(h_exps[g]).  Group g is
+ * d_entries[h_off[g] .. h_off[g+1]) (device, uint32, nonzero, e.g. the primes of
+ * one exponent read from a factorisation file); h_exps strictly ascending, at
+ * most CAT_MAX_GROUPS nonempty groups (empty ones are skipped), h_off[0] = 0.
+ * max_entry_bits (1..32) bounds the bit length of every entry and sizes the
+ * workspace (CAT_EINVAL if an entry is longer).
+ * prime_power_product_sizes: host only, bounds on the result limbs and the
+ *   workspace bytes.
+ * prime_power_product: N as normalised limbs into d_limbs (cap limbs);
+ *   flags CAT_MODE_BATCHED or CAT_MODE_PLAIN; synchronises `stream`.
+ *   CAT_ERANGE if N could exceed the 2^27-coefficient transform or cap. */
+cat_status prime_power_product_sizes(const uint32_t* h_exps, const uint64_t* h_off, uint32_t ngroups,
+                                     uint32_t max_entry_bits, size_t* max_limbs, size_t* workspace_bytes);
+cat_status prime_power_product(const uint32_t* d_entries, const uint32_t* h_exps, const uint64_t* h_off,
+                               uint32_t ngroups, uint32_t max_entry_bits, uint32_t* d_limbs, size_t cap,
+                               size_t* n_limbs, void* d_work, size_t work_bytes, void* stream, uint32_t flags);
+
 /* Factorial ratios N = a_1! ... a_k! / (b_1! ... b_m!) (Sec. 6.3: the exponent
  * of p is sum_i v_p(a_i!) - sum_j v_p(b_j!), and the reconstruction is the
  * Phase 2 of C(n) unchanged): binomial and multinomial coefficients,

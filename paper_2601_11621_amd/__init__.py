@@ -32,6 +32,7 @@ EXPORTS = [
     "catalan_begin", "cat_ticket_query", "catalan_continue", "catalan_end", "cat_ticket_release",
     "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
+    "prime_power_product_sizes", "prime_power_product",
 ]
 
 
@@ -109,6 +110,9 @@ def load(path: str = LIB_PATH):
         "cat_tune_set": ([ctypes.POINTER(cat_tuning)], st),
         "cat_lookback_polls_set": ([ctypes.c_uint32], st),
         "factorial_ratio_sizes": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, szp, szp, szp], st),
+        "prime_power_product_sizes": ([u32p, u64p, ctypes.c_uint32, ctypes.c_uint32, szp, szp], st),
+        "prime_power_product": ([vp, u32p, u64p, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_size_t, szp, vp,
+                                 ctypes.c_size_t, vp, ctypes.c_uint32], st),
         "factorial_ratio_factor": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, vp, ctypes.c_size_t, u32p, u64p,
                                     u32p, szp, vp, ctypes.c_size_t, vp], st),
         "factorial_ratio_exact": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, vp, ctypes.c_size_t, szp, vp,
@@ -320,6 +324,38 @@ def ratio_exact(num, den=(), mode: str = "batched", stream=None, out=None):
     st = lib.factorial_ratio_exact(_p64(a), k, _p64(b), m, _ptr(out), out.numel(), ctypes.byref(nl), _ptr(w),
                                    w.numel(), _stream(stream), _MODES[mode] & ~MODE_GRAPH)
     _check(st, "factorial_ratio_exact")
+    return out[: nl.value]
+
+
+def product_sizes(exps, off, max_entry_bits: int = 32):
+    """(max_limbs, workspace_bytes) of prod_g (entries of g)^exps[g] (host-only)."""
+    lib = load()
+    e = np.ascontiguousarray(np.asarray(exps, dtype=np.uint32))
+    o = _u64(off)
+    x, y = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.prime_power_product_sizes(e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _p64(o), len(e),
+                                         max_entry_bits, ctypes.byref(x), ctypes.byref(y)), "prime_power_product_sizes")
+    return x.value, y.value
+
+
+def product(exps, off, entries, max_entry_bits: int = 32, mode: str = "batched", stream=None, out=None):
+    """Phase 2 alone: prod_g (prod entries[off[g]:off[g+1]])^exps[g] as normalised
+    limbs; `entries` is a device tensor (int32 bits) or a host array."""
+    torch = _torch()
+    lib = load()
+    e = np.ascontiguousarray(np.asarray(exps, dtype=np.uint32))
+    o = _u64(off)
+    if not isinstance(entries, torch.Tensor):
+        entries = from_numpy(np.ascontiguousarray(np.asarray(entries, dtype=np.uint32)))
+    max_limbs, wbytes = product_sizes(e, o, max_entry_bits)
+    w = workspace(wbytes)
+    if out is None:
+        out = torch.empty(max(max_limbs, 1), dtype=torch.int32, device="cuda")
+    nl = ctypes.c_size_t()
+    st = lib.prime_power_product(_ptr(entries), e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _p64(o), len(e),
+                                 max_entry_bits, _ptr(out), out.numel(), ctypes.byref(nl), _ptr(w), w.numel(),
+                                 _stream(stream), _MODES[mode] & ~MODE_GRAPH)
+    _check(st, "prime_power_product")
     return out[: nl.value]
 
 

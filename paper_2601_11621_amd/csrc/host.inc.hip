@@ -1416,6 +1416,51 @@ void ticket_free(Ticket* t) {
 // C ABI
 // ============================================================================
 // ----------------------------------------------------------------------------
+// Products of prime powers from a caller's grouped factorisation (Alg. 2 on
+// groups read from a factorisation file, or any other exponent source)
+// ----------------------------------------------------------------------------
+struct GroupsIn {
+  uint32_t ng = 0;
+  uint32_t exps[CAT_MAX_GROUPS];
+  uint64_t off[CAT_MAX_GROUPS + 1];
+  uint64_t total = 0;
+  double lbits = 0;   // bound on log2 of the product from max_entry_bits
+};
+
+cat_status groups_in(const uint32_t* h_exps, const uint64_t* h_off, uint32_t ngroups, uint32_t max_entry_bits,
+                     GroupsIn* out) {
+  if (ngroups > CAT_MAX_GROUPS || (ngroups && (!h_exps || !h_off))) return CAT_EINVAL;
+  if (max_entry_bits < 1 || max_entry_bits > 32) return CAT_EINVAL;
+  if (ngroups && h_off[0] != 0) return CAT_EINVAL;
+  GroupsIn G;
+  G.off[0] = 0;
+  uint32_t last = 0;
+  for (uint32_t g = 0; g < ngroups; g++) {
+    if (h_off[g + 1] < h_off[g] || h_exps[g] == 0) return CAT_EINVAL;
+    if (h_off[g + 1] == h_off[g]) continue;          // empty groups are dropped
+    if (h_exps[g] <= last) return CAT_EINVAL;         // one group per exponent, ascending
+    last = h_exps[g];
+    G.exps[G.ng] = h_exps[g];
+    G.off[G.ng + 1] = G.off[G.ng] + (h_off[g + 1] - h_off[g]);
+    G.lbits += (double)h_exps[g] * (double)(h_off[g + 1] - h_off[g]) * max_entry_bits;
+    G.ng++;
+  }
+  G.total = G.off[G.ng];
+  if (G.total >= (1ull << 32)) return CAT_ERANGE;
+  *out = G;
+  return CAT_OK;
+}
+
+Layout make_layout_groups(const GroupsIn& G) {
+  Layout L;
+  L.n = 0;
+  L.Kmax = std::max<uint64_t>(G.total, 16);
+  L.post_cap = (uint64_t)(16.0 * (G.lbits + 64.0) / 32.0) + L.Kmax + 8192;
+  L.res2_len = 4096;
+  return layout_finish(L);
+}
+
+// ----------------------------------------------------------------------------
 // Factorial ratios N = prod_i a_i! / prod_j b_j! (Sec. 6.3)
 // ----------------------------------------------------------------------------
 struct RatioSpec {
@@ -2179,6 +2224,115 @@ cat_status factorial_ratio_exact(const uint64_t* a, uint32_t k, const uint64_t* 
   stats.product_limbs = P->product_limbs;
   stats.launches = launches + X.launches + 1;
   stats.n_primes = gt.off[gt.ngroups];
+  stats.levels = P->levels;
+  free_plan(P);
+  g.stats = stats;
+  if (res != CAT_OK) return res;
+  uint64_t L = 0;
+  uint32_t derr = 0;
+  memcpy(&L, g.pin, 8);
+  memcpy(&derr, (char*)g.pin + 8, 4);
+  if (derr || L == 0) return CAT_EINTERNAL;
+  *n_limbs = (size_t)L;
+  if (cap < L) return CAT_ERANGE;
+  return CAT_OK;
+}
+
+cat_status prime_power_product_sizes(const uint32_t* h_exps, const uint64_t* h_off, uint32_t ngroups,
+                                     uint32_t max_entry_bits, size_t* max_limbs, size_t* workspace_bytes) {
+  GroupsIn G;
+  STCHK(groups_in(h_exps, h_off, ngroups, max_entry_bits, &G));
+  if (G.lbits > 32.0 * (double)((1ull << CAT_MAX_LOGN) - 64)) return CAT_ERANGE;
+  const Layout Ly = make_layout_groups(G);
+  if (max_limbs) *max_limbs = (size_t)(G.lbits / 32.0) + 2;
+  if (workspace_bytes) *workspace_bytes = Ly.total;
+  return CAT_OK;
+}
+
+cat_status prime_power_product(const uint32_t* d_entries, const uint32_t* h_exps, const uint64_t* h_off,
+                               uint32_t ngroups, uint32_t max_entry_bits, uint32_t* d_limbs, size_t cap,
+                               size_t* n_limbs, void* d_work, size_t work_bytes, void* stream, uint32_t flags) {
+  if (!n_limbs || !d_limbs || !d_work) return CAT_EINVAL;
+  GroupsIn G;
+  STCHK(groups_in(h_exps, h_off, ngroups, max_entry_bits, &G));
+  if (G.lbits > 32.0 * (double)((1ull << CAT_MAX_LOGN) - 64)) return CAT_ERANGE;
+  if (G.total && !d_entries) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  const Layout Ly = make_layout_groups(G);
+  if (work_bytes < Ly.total) return CAT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)d_work;
+  uint32_t* W = (uint32_t*)wb;
+  // control block cleared; entries into the tree's leaf buffer, group offsets
+  // and the bit sums in the seed buffer (unused here)
+  hipLaunchKernelGGL(k_fill, dim3((uint32_t)std::min<uint64_t>((Ly.ctl_words + 255) / 256, 1024)), dim3(256), 0, st,
+                     (uint32_t*)(wb + Ly.gtab), (uint64_t)Ly.ctl_words, 0u);
+  LAUNCHCHK();
+  if (G.total) HIPCHK(hipMemcpyAsync(W + Ly.primes, d_entries, G.total * 4, hipMemcpyDeviceToDevice, st));
+  uint64_t* d_off = (uint64_t*)(W + Ly.seeds);
+  unsigned long long* d_bits = (unsigned long long*)(d_off + CAT_MAX_GROUPS + 2);
+  memcpy(g.pin, G.off, sizeof(uint64_t) * (G.ng + 1));
+  HIPCHK(hipMemcpyAsync(d_off, g.pin, sizeof(uint64_t) * (G.ng + 1), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)d_bits, (uint64_t)(2 * CAT_MAX_GROUPS), 0u);
+  LAUNCHCHK();
+  if (G.ng) {
+    hipLaunchKernelGGL(k_group_bits, dim3(256, G.ng), dim3(256), 0, st, (const uint32_t*)(W + Ly.primes),
+                       (const uint64_t*)d_off, G.ng, d_bits);
+    LAUNCHCHK();
+  }
+  HIPCHK(hipMemcpyAsync((char*)g.pin + 1024, d_bits, sizeof(uint64_t) * CAT_MAX_GROUPS, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  GroupTable gt;
+  memset(&gt, 0, sizeof(gt));
+  gt.ngroups = G.ng;
+  double lb = 0;
+  for (uint32_t q = 0; q < G.ng; q++) {
+    gt.exps[q] = G.exps[q];
+    gt.off[q] = G.off[q];
+    memcpy(&gt.gbits[q], (char*)g.pin + 1024 + 8 * q, 8);
+    if (gt.gbits[q] > (G.off[q + 1] - G.off[q]) * (uint64_t)max_entry_bits) return CAT_EINVAL;
+    lb += (double)G.exps[q] * (double)gt.gbits[q];
+  }
+  gt.off[G.ng] = G.off[G.ng];
+  if (lb > 32.0 * (double)((1ull << CAT_MAX_LOGN) - 64)) return CAT_ERANGE;
+  Plan* P = nullptr;
+  STCHK(make_plan(Ly, gt, &P));
+  cat_status res = CAT_OK;
+  if (P->result_is_one) {
+    free_plan(P);
+    if (cap < 1) {
+      *n_limbs = 1;
+      return CAT_ERANGE;
+    }
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, d_limbs, (uint64_t)1, 1u);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+    *n_limbs = 1;
+    return CAT_OK;
+  }
+  Exec X = make_exec(Ly, wb, st);
+  unsigned long long* top = (unsigned long long*)(wb + Ly.top);
+  res = run_phase2(X, *P, (flags & CAT_MODE_PLAIN) != 0);
+  if (res == CAT_OK) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, st, X.W + P->result_pos, P->result_cap, top, d_limbs,
+                       ncopy);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(g.pin, wb + Ly.top, 12, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      g.last_err = (int)e;
+      res = CAT_EDEVICE;
+    }
+  }
+  cat_stats stats{};
+  stats.products = P->products;
+  stats.product_limbs = P->product_limbs;
+  stats.launches = X.launches + 4;
+  stats.n_primes = G.total;
   stats.levels = P->levels;
   free_plan(P);
   g.stats = stats;

@@ -174,6 +174,19 @@ __global__ void __launch_bounds__(256) k_top_nonzero(const uint32_t* __restrict_
   }
 }
 
+// Sum of the bit lengths of the entries of each group (bounds on log2 Q_g).
+__global__ void __launch_bounds__(256) k_group_bits(const uint32_t* __restrict__ x, const uint64_t* __restrict__ off,
+                                                    uint32_t ngroups, unsigned long long* __restrict__ gbits) {
+  const uint32_t g = blockIdx.y;
+  if (g >= ngroups) return;
+  unsigned long long s = 0;
+  for (uint64_t k = off[g] + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < off[g + 1];
+       k += (uint64_t)gridDim.x * blockDim.x)
+    s += (unsigned long long)(32 - __clz(x[k]));
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&gbits[g], s);
+}
+
 // Fingerprints of a limb vector: x mod (2^32 - 5), x mod (2^32 + 1), x mod (2^32 - 1).
 // Each block reduces a contiguous chunk with Horner steps, partial results
 // are combined by weights (2^32)^{offset} on the host side of the library.

@@ -1,0 +1,68 @@
+"""Phase 2 as a reusable engine on the GPU: rebuilding from a factorisation
+file (the paper's text format) equals catalan_exact, and products of powers
+of arbitrary 32-bit entries equal Python integers."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_11621_amd import factorfile
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cat():
+    import torch
+
+    import paper_2601_11621_amd as c
+
+    torch.cuda.set_device(0)
+    c.init(0)
+    return c
+
+
+@pytest.mark.parametrize("n", [2, 1000, 100000, 10**6, 10**7])
+def test_file_round_trip_equals_catalan_exact(cat, tmp_path, n):
+    print("factorisation file", n, flush=True)
+    path = str(tmp_path / ("catalan_%d_factorization.txt" % n))
+    factorfile.factorize_to_file(cat, n, path)
+    for mode in (["batched", "plain"] if n <= 1000 else ["batched"]):
+        got = cat.to_numpy(factorfile.reconstruct_from_file(cat, path, mode=mode))
+        assert np.array_equal(got, cat.to_numpy(cat.exact(n, mode="batched"))), mode
+    if n <= 10**6:
+        assert np.array_equal(got, oracle.catalan(n))
+
+
+def test_oracle_factorisation_file(cat, tmp_path):
+    n = 13337
+    exps, off, primes = oracle.factor(n)
+    path = str(tmp_path / "o.txt")
+    factorfile.write_factorization(path, exps, off, primes, "Catalan(%d)" % n)
+    assert np.array_equal(cat.to_numpy(factorfile.reconstruct_from_file(cat, path)), oracle.catalan(n))
+
+
+def test_product_of_powers_of_arbitrary_entries(cat):
+    rng = np.random.default_rng(31)
+    sizes = [5000, 300, 17, 1]
+    exps = [1, 3, 7, 40]
+    ent = rng.integers(1, 2**32, size=sum(sizes), dtype=np.uint64).astype(np.uint32)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    want = 1
+    for g, e in enumerate(exps):
+        q = 1
+        for v in ent[int(off[g]):int(off[g + 1])].tolist():
+            q *= v
+        want *= q ** e
+    got = cat.product(exps, off, ent)
+    assert oracle.limbs_to_int(cat.to_numpy(got)) == want
+
+
+def test_product_argument_checks(cat):
+    ent = np.array([3, 5, 7], dtype=np.uint32)
+    with pytest.raises(cat.CatalanError) as e:
+        cat.product([2, 1], [0, 1, 3], ent)                 # exponents must ascend
+    assert e.value.status == cat.CAT_EINVAL
+    with pytest.raises(cat.CatalanError) as e:
+        cat.product([1], [0, 3], ent, max_entry_bits=2)     # 5 and 7 need 3 bits
+    assert e.value.status == cat.CAT_EINVAL
+    assert oracle.limbs_to_int(cat.to_numpy(cat.product([], [0], np.zeros(0, np.uint32)))) == 1
