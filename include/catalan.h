@@ -111,6 +111,14 @@ cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_li
 cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
                             size_t work_bytes, void* stream, uint32_t flags);
 
+/* sign(floor(x / 2^shift_bits) - y) in *sign (-1, 0, 1) for little-endian limb
+ * vectors x[0..lx), y[0..ly) (leading zero limbs allowed).  d_work: at least
+ * 16 bytes of device scratch.  Synchronises `stream`.  With x = C(n) and
+ * y = 5^k this checks x >= 10^k as floor(x / 2^k) >= 5^k, which settles a
+ * decimal digit count exactly (Table 1). */
+cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, const uint32_t* d_y, size_t ly,
+                          int32_t* sign, void* d_work, size_t work_bytes, void* stream);
+
 /* Phase 2 on a caller's factorisation (Alg. 2, the reconstruction engine):
  * N = prod_g (prod of the entries of group g)^(h_exps[g]).  Group g is
  * d_entries[h_off[g] .. h_off[g+1]) (device, uint32, nonzero, e.g. the primes of

@@ -32,7 +32,7 @@ EXPORTS = [
     "catalan_begin", "cat_ticket_query", "catalan_continue", "catalan_end", "cat_ticket_release",
     "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
-    "prime_power_product_sizes", "prime_power_product",
+    "prime_power_product_sizes", "prime_power_product", "bigint_compare",
 ]
 
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
         "cat_lookback_polls_set": ([ctypes.c_uint32], st),
         "factorial_ratio_sizes": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, szp, szp, szp], st),
         "prime_power_product_sizes": ([u32p, u64p, ctypes.c_uint32, ctypes.c_uint32, szp, szp], st),
+        "bigint_compare": ([vp, ctypes.c_size_t, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
+                            vp, ctypes.c_size_t, vp], st),
         "prime_power_product": ([vp, u32p, u64p, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_size_t, szp, vp,
                                  ctypes.c_size_t, vp, ctypes.c_uint32], st),
         "factorial_ratio_factor": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, vp, ctypes.c_size_t, u32p, u64p,
@@ -357,6 +359,55 @@ def product(exps, off, entries, max_entry_bits: int = 32, mode: str = "batched",
                                  _stream(stream), _MODES[mode] & ~MODE_GRAPH)
     _check(st, "prime_power_product")
     return out[: nl.value]
+
+
+def compare(x, y, shift_bits: int = 0, stream=None) -> int:
+    """sign(floor(x / 2^shift_bits) - y) of two limb tensors, on the GPU."""
+    lib = load()
+    w = workspace(256, key="cmp")
+    sgn = ctypes.c_int32()
+    _check(lib.bigint_compare(_ptr(x), x.numel(), int(shift_bits), _ptr(y), y.numel(), ctypes.byref(sgn), _ptr(w),
+                              w.numel(), _stream(stream)), "bigint_compare")
+    return sgn.value
+
+
+def pow5(k: int):
+    """5^k as a limb tensor, by the product engine (groups of 5^13 and 5^(k mod 13))."""
+    q, r = divmod(int(k), 13)
+    if q == 0:
+        return from_numpy(np.array([5**r], dtype=np.uint32))
+    if q == 1:
+        return product([1], [0, 2], [5**r, 5**13])
+    if r == 0:
+        return product([q], [0, 1], [5**13])
+    return product([1, q], [0, 1, 2], [5**r, 5**13])
+
+
+def decimal_digits(x, stream=None) -> int:
+    """The number of decimal digits d of a limb tensor x > 0, settled exactly on
+    the GPU: 10^(d-1) <= x < 10^d checked as floor(x / 2^(d-1)) >= 5^(d-1) and
+    floor(x / 2^d) < 5^d (the powers of five by the product engine); the first
+    guess comes from the top limbs in floating point."""
+    import math
+
+    xs = to_numpy(x)
+    n = len(xs)
+    while n > 1 and xs[n - 1] == 0:
+        n -= 1
+    k0 = max(0, n - 3)
+    top = sum(float(xs[k]) * 2.0 ** (32 * (k - k0)) for k in range(k0, n))
+    d = int(math.floor(math.log10(top) + 32 * k0 * math.log10(2.0))) + 1
+    for _ in range(4):
+        lo = pow5(d - 1)
+        if compare(x, lo, d - 1, stream) < 0:
+            d -= 1
+            continue
+        hi, _ = mul_batched(lo, [0, lo.numel()], from_numpy(np.array([5], dtype=np.uint32)), [0, 1])
+        if compare(x, hi, d, stream) >= 0:
+            d += 1
+            continue
+        return d
+    raise RuntimeError("decimal digit count did not settle")
 
 
 def mul_batched(a_flat, a_off, b_flat, b_off, mode: str = "batched", stream=None):

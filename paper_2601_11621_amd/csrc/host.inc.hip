@@ -399,8 +399,10 @@ static_assert(sizeof(GroupTable) <= CTL_TOP, "group table must fit the control b
 // post_cap, res2_len, and np_cap / nchunks for ratios).
 Layout layout_finish(Layout L) {
   L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + SIEVE_SEG - 1) / SIEVE_SEG : 0;
-  L.res_len = std::max(L.Kmax, L.post_cap) + 64;
-  const uint64_t big = 1ull << ceil_log2(std::max(L.Kmax, L.post_cap));
+  // residues of one stage: by default bounded by everything the tree and the
+  // post area can hold; callers with long power chains set a tighter bound
+  if (L.res_len == 0) L.res_len = std::max(L.Kmax, L.post_cap) + 64;
+  const uint64_t big = 1ull << ceil_log2(L.res_len);
   L.F_words = (big > (1ull << CAT_LDS_LOGT)) ? 12 * big + (1ull << 20) : (1ull << 20);
   L.nblk_max = L.res_len / CAT_CRT_BLOCK + 4096;
   L.F2_words = 12 * (1ull << ceil_log2(L.res2_len)) + (1ull << 16);
@@ -1455,7 +1457,15 @@ Layout make_layout_groups(const GroupsIn& G) {
   Layout L;
   L.n = 0;
   L.Kmax = std::max<uint64_t>(G.total, 16);
-  L.post_cap = (uint64_t)(16.0 * (G.lbits + 64.0) / 32.0) + L.Kmax + 8192;
+  // the power chains (about twice their results), the outer tree (one pass
+  // over the powers per level) and the final product
+  uint32_t nchain = 0;
+  for (uint32_t q = 0; q < G.ng; q++) nchain += G.exps[q] >= 2;
+  const double levels = nchain > 1 ? std::ceil(std::log2((double)nchain)) : 0.0;
+  L.post_cap = (uint64_t)((5.0 + levels) * (G.lbits + 64.0) / 32.0) + L.Kmax + 256ull * G.ng + 8192;
+  // one stage's products (a step of every chain, a level of the outer tree,
+  // or the final product) add up to at most the result's bound
+  L.res_len = std::max<uint64_t>(L.Kmax, (uint64_t)((G.lbits + 64.0) / 32.0) + 64ull * G.ng + 4096) + 64;
   L.res2_len = 4096;
   return layout_finish(L);
 }
@@ -1517,6 +1527,9 @@ Layout make_layout_ratio(const RatioSpec& r) {
   // post-tree allocations: the power chains, the outer tree and the final
   // product together stay below 16 log2(N) / 32 limbs plus the operands' slack
   L.post_cap = (uint64_t)(16.0 * (r.log2N + 64.0) / 32.0) + L.Kmax + 8192;
+  // one stage's products add up to at most sum_p v_p(N) bitlen(p) <= 2 log2 N
+  // bits (plus a few limbs per group)
+  L.res_len = std::max<uint64_t>(L.Kmax, (uint64_t)(2.0 * (r.log2N + 64.0) / 32.0) + 4096) + 64;
   L.res2_len = 4096;
   return layout_finish(L);
 }
@@ -2344,6 +2357,48 @@ cat_status prime_power_product(const uint32_t* d_entries, const uint32_t* h_exps
   if (derr || L == 0) return CAT_EINTERNAL;
   *n_limbs = (size_t)L;
   if (cap < L) return CAT_ERANGE;
+  return CAT_OK;
+}
+
+cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, const uint32_t* d_y, size_t ly,
+                          int32_t* sign, void* d_work, size_t work_bytes, void* stream) {
+  if (!sign || !d_work || work_bytes < 16 || (lx && !d_x) || (ly && !d_y)) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* top = (unsigned long long*)d_work;
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)top, (uint64_t)2, 0u);
+  LAUNCHCHK();
+  const uint64_t lxs = (uint64_t)lx > (shift_bits >> 5) ? (uint64_t)lx - (shift_bits >> 5) : 0;   // limbs of x >> s
+  const uint64_t n = std::max<uint64_t>(lxs, ly);
+  if (n) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_diff_top, dim3(blocks), dim3(256), 0, st, d_x, (uint64_t)lx, shift_bits, d_y, (uint64_t)ly, n,
+                       top);
+    LAUNCHCHK();
+  }
+  HIPCHK(hipMemcpyAsync(g.pin, top, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint64_t t = 0;
+  memcpy(&t, g.pin, 8);
+  if (t == 0) {
+    *sign = 0;
+    return CAT_OK;
+  }
+  // the differing limb of x >> s (one or two source limbs) and of y
+  const uint64_t k = t - 1, w = k + (shift_bits >> 5);
+  const uint32_t r = (uint32_t)(shift_bits & 31);
+  uint32_t x2[2] = {0, 0}, b = 0;
+  if (w < lx) HIPCHK(hipMemcpyAsync((char*)g.pin + 16, d_x + w, 4, hipMemcpyDeviceToHost, st));
+  if (w + 1 < lx) HIPCHK(hipMemcpyAsync((char*)g.pin + 20, d_x + w + 1, 4, hipMemcpyDeviceToHost, st));
+  if (k < ly) HIPCHK(hipMemcpyAsync((char*)g.pin + 24, d_y + k, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (w < lx) memcpy(&x2[0], (char*)g.pin + 16, 4);
+  if (w + 1 < lx) memcpy(&x2[1], (char*)g.pin + 20, 4);
+  if (k < ly) memcpy(&b, (char*)g.pin + 24, 4);
+  const uint32_t a = r ? ((x2[0] >> r) | (x2[1] << (32 - r))) : x2[0];
+  *sign = a > b ? 1 : -1;
   return CAT_OK;
 }
 

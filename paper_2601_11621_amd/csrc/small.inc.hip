@@ -174,6 +174,40 @@ __global__ void __launch_bounds__(256) k_top_nonzero(const uint32_t* __restrict_
   }
 }
 
+// Limb k of floor(x / 2^s) for x[0..lx) (zero past the top).
+__device__ __forceinline__ uint32_t shifted_limb(const uint32_t* __restrict__ x, uint64_t lx, uint64_t s, uint64_t k) {
+  const uint64_t w = k + (s >> 5);
+  const uint32_t r = (uint32_t)(s & 31);
+  const uint32_t lo = w < lx ? x[w] : 0u;
+  if (r == 0) return lo;
+  const uint32_t hi = w + 1 < lx ? x[w + 1] : 0u;
+  return (lo >> r) | (hi << (32 - r));
+}
+
+// 1 + the highest index where X = floor(x / 2^s) and Y = y differ (0 if X = Y),
+// limbs past the ends being zero -> *top (atomicMax; zero it before).  n: the
+// limbs to scan (at least the longer of X and Y).
+__global__ void __launch_bounds__(256) k_diff_top(const uint32_t* __restrict__ x, uint64_t lx, uint64_t s,
+                                                  const uint32_t* __restrict__ y, uint64_t ly, uint64_t n,
+                                                  unsigned long long* top) {
+  __shared__ unsigned long long part[4];
+  unsigned long long best = 0;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t a = shifted_limb(x, lx, s, k), b = k < ly ? y[k] : 0u;
+    if (a != b) best = k + 1;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    unsigned long long o = __shfl_xor(best, d, 64);
+    best = o > best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++) best = part[w] > best ? part[w] : best;
+    if (best) atomicMax(top, best);
+  }
+}
+
 // Sum of the bit lengths of the entries of each group (bounds on log2 Q_g).
 __global__ void __launch_bounds__(256) k_group_bits(const uint32_t* __restrict__ x, const uint64_t* __restrict__ off,
                                                     uint32_t ngroups, unsigned long long* __restrict__ gbits) {

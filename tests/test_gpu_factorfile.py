@@ -66,3 +66,30 @@ def test_product_argument_checks(cat):
         cat.product([1], [0, 3], ent, max_entry_bits=2)     # 5 and 7 need 3 bits
     assert e.value.status == cat.CAT_EINVAL
     assert oracle.limbs_to_int(cat.to_numpy(cat.product([], [0], np.zeros(0, np.uint32)))) == 1
+
+
+def test_compare_with_shift_against_python(cat):
+    rng = np.random.default_rng(5)
+    for trial in range(30):
+        lx, ly = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        x = rng.integers(0, 2**32, size=lx, dtype=np.uint64).astype(np.uint32)
+        y = rng.integers(0, 2**32, size=ly, dtype=np.uint64).astype(np.uint32)
+        s = int(rng.integers(0, 40 * 32))
+        if trial % 3 == 0:                     # equal values: y = x >> s
+            xi = oracle.limbs_to_int(x) >> s
+            y = oracle.int_to_limbs(xi, max(1, (xi.bit_length() + 31) // 32))
+        X, Y = oracle.limbs_to_int(x) >> s, oracle.limbs_to_int(y)
+        want = (X > Y) - (X < Y)
+        assert cat.compare(cat.from_numpy(x), cat.from_numpy(y), s) == want, trial
+
+
+@pytest.mark.parametrize("n", [1, 2, 13, 1000, 100000, 10**7])
+def test_decimal_digits_of_catalan(cat, n):
+    from tests import pins
+
+    t = cat.exact(n, mode="batched")
+    d = cat.decimal_digits(t)
+    if n <= 1000:
+        assert d == len(str(oracle.limbs_to_int(cat.to_numpy(t))))
+    else:
+        assert d == pins.log_pins(n)[1]

@@ -109,5 +109,8 @@ def test_catalan_2050572903_table1(cat):
     h_le = hashlib.sha256(le).hexdigest()
     h_be = hashlib.sha256(le[::-1]).hexdigest()
     _say("sha256 LE %s BE %s (paper %s)" % (h_le, h_be, t1["sha256_of_output_file"]))
-    with open(os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out", "largest_sha.txt"), "w") as f:
-        f.write("LE %s\nBE %s\npaper %s\n" % (h_le, h_be, t1["sha256_of_output_file"]))
+    # the decimal digit count of Table 1, settled exactly on the GPU:
+    # 10^(d-1) <= C(n) < 10^d as floor(C / 2^(d-1)) >= 5^(d-1), floor(C / 2^d) < 5^d
+    t0 = time.time()
+    assert cat.decimal_digits(t) == t1["decimal_digits"]
+    _say("digit count settled in %.3f s" % (time.time() - t0))
