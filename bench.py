@@ -256,6 +256,35 @@ def serving_bench(cat, count=1100, warm=100, slots=8, budget=16 << 30, frac=0.7)
             "inputs": "n = floor(10^(3+4u)), Poisson arrivals, numpy default_rng(11621)"}
 
 
+def steady_state(cat, kernel="k_ntt_lds", half=2048, count=1024, reps=10):
+    """The transform kernel fed enough work to fill the GPU: one launch over
+    `count` products of half x half limbs (N = 2 * half), timed per launch with
+    the library's event timer; butterflies per second against the VALU peak."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(1)
+    off = np.arange(count + 1, dtype=np.uint64) * np.uint64(half)
+    a = cat.from_numpy(rng.integers(0, 2**32, size=count * half, dtype=np.uint64).astype(np.uint32))
+    plan = cat.MulPlan(off, off, mode="batched")
+    c = torch.empty(2 * count * half, dtype=torch.int32, device="cuda")
+    plan(a, a, c)
+    plan.check()
+    cat.timer_set(kernel)
+    for _ in range(reps):
+        plan(a, a, c)
+    torch.cuda.synchronize()
+    kms, launches, work = cat.timer_get()
+    cat.timer_set(None)
+    plan.check()
+    plan.close()
+    achieved = work / (kms / 1e3)
+    return {"kernel": kernel, "workload": "%d products of %d x %d limbs (N = %d), one launch" % (count, half, half,
+                                                                                              2 * half),
+            "avg_launch_ms": round(kms / launches, 5), "achieved": round(achieved / 1e12, 4),
+            "frac": round(achieved / PEAK_BFLY, 4)}
+
+
 def cpu_baseline(n, product_limbs):
     import oracle
 
@@ -380,6 +409,8 @@ def main():
                     "avg_launch_ms": round(avg_ms, 5), "launches": klaunch}
         tr = load_traffic(dom, n)
         roof["traffic"] = tr.get("bytes_per_launch") if tr else None
+        if dom == "k_ntt_lds":
+            roof["steady_state"] = steady_state(cat)
         log("bench: dominant kernel %s: %.4f ms avg over %d launches" % (dom, avg_ms, klaunch))
 
     batch = None if args.no_batch else batch_bench(cat, max(3, args.steps // 4))
