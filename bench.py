@@ -207,6 +207,35 @@ def ratio_bench(cat, reps=5):
     return out
 
 
+def decimal_bench(cat, reps=5):
+    """Decimal text of C(10^7) and C(10^8) (radix-10^9 conversion on the GPU),
+    checked by its nine-digit groups against the limbs modulo 10^9 +- 1."""
+    import numpy as np
+    import torch
+
+    from tests import pins
+
+    out = {}
+    for n in (10**7, 10**8):
+        t = cat.exact(n)
+        text = cat.to_decimal_device(t)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            text = cat.to_decimal_device(t)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        st = cat.stats()
+        s1, s2, _ = pins.decimal_group_residues(text)
+        ok = s1 == pins.limbs_mod_torch(t, 10**9 - 1) and s2 == pins.limbs_mod_torch(t, 10**9 + 1)
+        ms = float(np.median(ts)) * 1e3
+        out["catalan_%s" % ("1e7" if n == 10**7 else "1e8")] = {
+            "digits": int(text.numel()), "ms": round(ms, 3), "digits_per_s": text.numel() / (ms / 1e3),
+            "levels": st["levels"], "products": st["products"], "verified_mod_1e9_pm_1": bool(ok)}
+    return out
+
+
 def serving_bench(cat, count=1100, warm=100, slots=8, budget=16 << 30, frac=0.7):
     """Request stream of catalan_exact(n), n = floor(10^(3 + 4u)) from
     default_rng(11621): closed-loop saturation first, then Poisson arrivals at
@@ -317,6 +346,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-product level-batch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--no-ratio", action="store_true", help="skip the factorial-ratio measurement")
+    ap.add_argument("--no-decimal", action="store_true", help="skip the decimal-text measurement")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--only-kernel", default="", help="profiling aid: run graph steps only")
@@ -423,6 +453,9 @@ def main():
     ratios = None if args.no_ratio else ratio_bench(cat)
     if ratios:
         log("bench: ratios %s" % {k: v["ms"] for k, v in ratios.items()})
+    decimal = None if args.no_decimal else decimal_bench(cat)
+    if decimal:
+        log("bench: decimal %s" % {k: v["ms"] for k, v in decimal.items()})
     cpu = None if args.no_cpu else cpu_baseline(n, product_limbs)
 
     line = {
@@ -450,6 +483,7 @@ def main():
         "level_batch_4096": batch,
         "serving": serving,
         "factorial_ratios": ratios,
+        "decimal_text": decimal,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()} if kt else None,
         "paper_context": {"wall_s_n1e7": 6.817, "hardware": "AMD Ryzen 9 4900HS laptop, Python 3.11 + gmpy2 "
                                                             "(Table 2, proposed algorithm)"},

@@ -119,6 +119,20 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
 cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, const uint32_t* d_y, size_t ly,
                           int32_t* sign, void* d_work, size_t work_bytes, void* stream);
 
+/* Decimal text of x (the optional decimal output of Sec. 3.2): the digits of
+ * the little-endian limb vector d_x[0 .. n_limbs) (device; leading zero limbs
+ * allowed; n_limbs = 0 means 0), most significant first, no leading zeros
+ * ("0" for zero), no terminator, as ASCII into d_out (device, cap bytes).
+ * *n_chars is set to the digit count D whenever the conversion ran; CAT_ERANGE
+ * if d_out is NULL or cap < D (nothing written), or if n_limbs > 2^27.
+ * decimal_sizes: host only; an upper bound on D and the workspace bytes.
+ * bigint_to_decimal: d_work of at least that many bytes (device, caller-owned,
+ * contents undefined afterwards); synchronises `stream`; CAT_EINTERNAL if a
+ * device check failed. */
+cat_status decimal_sizes(size_t n_limbs, size_t* max_chars, size_t* workspace_bytes);
+cat_status bigint_to_decimal(const uint32_t* d_x, size_t n_limbs, char* d_out, size_t cap, size_t* n_chars,
+                             void* d_work, size_t work_bytes, void* stream);
+
 /* Phase 2 on a caller's factorisation (Alg. 2, the reconstruction engine):
  * N = prod_g (prod of the entries of group g)^(h_exps[g]).  Group g is
  * d_entries[h_off[g] .. h_off[g+1]) (device, uint32, nonzero, e.g. the primes of

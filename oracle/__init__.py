@@ -83,6 +83,8 @@ def _load():
     lib.orc_ratio.argtypes = [u64p, ctypes.c_size_t, u64p, ctypes.c_size_t, u32p, ctypes.c_size_t, szp]
     lib.orc_ratio.restype = ctypes.c_int
     lib.orc_catalan_low64.restype = ctypes.c_uint64
+    lib.orc_to_decimal.argtypes = [u32p, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_size_t]
+    lib.orc_to_decimal.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -269,3 +271,20 @@ def ratio(num, den=()) -> np.ndarray:
     if st:
         raise OracleError("orc_ratio: %d" % st)
     return out[: n.value]
+
+
+def to_decimal(limbs) -> str:
+    """Decimal text of LE uint32 limbs by repeated schoolbook division by 10^9
+    (Sec. 3.2, optional decimal output), O(L^2)."""
+    lib = _load()
+    x = np.ascontiguousarray(np.asarray(limbs, dtype=np.uint32).reshape(-1))
+    if x.size == 0:
+        x = np.zeros(1, dtype=np.uint32)
+    n = lib.orc_to_decimal(_p(x, ctypes.c_uint32), x.size, None, 0)
+    if n == 0:
+        raise OracleError("orc_to_decimal: out of memory")
+    buf = ctypes.create_string_buffer(n)
+    m = lib.orc_to_decimal(_p(x, ctypes.c_uint32), x.size, buf, n)
+    if m != n:
+        raise OracleError("orc_to_decimal: %d != %d" % (m, n))
+    return buf.raw[:n].decode("ascii")

@@ -37,7 +37,8 @@
 
 /* Planted-mistake switch, used only by the test that shows the pins catch a
  * wrong oracle: 0 = correct; 1 = drop the v_p(n+1) term; 2 = drop the carry
- * out of each schoolbook row; 3 = use v_p(n!) once instead of twice. */
+ * out of each schoolbook row; 3 = use v_p(n!) once instead of twice; 4 = drop
+ * the leading zeros of the inner nine-digit groups of the decimal text. */
 static int g_fault = 0;
 void orc_set_fault(int f) { g_fault = f; }
 
@@ -558,4 +559,60 @@ uint64_t orc_catalan_low64(uint64_t n)
     for (int i = 0; i < 6; i++) inv *= 2 - den * inv;
     int v = __builtin_popcountll(n + 1) - 1;
     return (num * inv) << v;
+}
+
+/* ---------------------------------------------------------------------------
+ * Decimal text of a limb vector (the optional decimal output of Sec. 3.2), by
+ * the textbook route: divide the whole number by 10^9 again and again
+ * (schoolbook long division, most significant limb first), each remainder
+ * giving the next nine digits from the bottom; O(L^2).  Writes the digits
+ * most significant first, no leading zeros ("0" for zero), no terminator, and
+ * returns their count; returns it without writing when cap is too small.
+ * ------------------------------------------------------------------------- */
+size_t orc_to_decimal(const uint32_t *x, size_t L, char *out, size_t cap)
+{
+    size_t n = L;
+    while (n > 0 && x[n - 1] == 0) n--;
+    if (n == 0) {
+        if (out && cap >= 1) out[0] = '0';
+        return 1;
+    }
+    uint32_t *q = (uint32_t *)malloc(n * sizeof(uint32_t));
+    uint32_t *grp = (uint32_t *)malloc((n * 32 / 29 + 2) * sizeof(uint32_t));   /* 10^9 > 2^29 */
+    if (!q || !grp) { free(q); free(grp); return 0; }
+    memcpy(q, x, n * sizeof(uint32_t));
+    size_t ng = 0;
+    while (n > 0) {
+        uint64_t r = 0;
+        for (size_t i = n; i-- > 0;) {
+            uint64_t cur = (r << 32) | q[i];
+            q[i] = (uint32_t)(cur / 1000000000u);
+            r = cur % 1000000000u;
+        }
+        grp[ng++] = (uint32_t)r;
+        while (n > 0 && q[n - 1] == 0) n--;
+    }
+    /* groups least significant first; the top one without leading zeros */
+    char buf[16];
+    size_t top = 0;
+    for (uint32_t v = grp[ng - 1]; ; v /= 10) { buf[top++] = (char)('0' + v % 10); if (v < 10) break; }
+    size_t len = top;
+    for (size_t k = 0; k + 1 < ng; k++) {
+        if (g_fault == 4) { uint32_t v = grp[k]; do { len++; v /= 10; } while (v); }
+        else len += 9;
+    }
+    if (out && cap >= len) {
+        size_t o = 0;
+        while (top > 0) out[o++] = buf[--top];
+        for (size_t k = ng - 1; k-- > 0;) {
+            uint32_t v = grp[k];
+            int w = 9;
+            if (g_fault == 4) { w = 0; uint32_t t = v; do { w++; t /= 10; } while (t); }
+            for (int i = w - 1; i >= 0; i--) { out[o + i] = (char)('0' + v % 10); v /= 10; }
+            o += (size_t)w;
+        }
+    }
+    free(q);
+    free(grp);
+    return len;
 }

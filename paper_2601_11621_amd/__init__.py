@@ -33,6 +33,7 @@ EXPORTS = [
     "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
+    "decimal_sizes", "bigint_to_decimal",
 ]
 
 
@@ -120,6 +121,8 @@ def load(path: str = LIB_PATH):
         "factorial_ratio_exact": ([u64p, ctypes.c_uint32, u64p, ctypes.c_uint32, vp, ctypes.c_size_t, szp, vp,
                                    ctypes.c_size_t, vp, ctypes.c_uint32], st),
         "cat_tune_get": ([ctypes.POINTER(cat_tuning)], st),
+        "decimal_sizes": ([ctypes.c_size_t, szp, szp], st),
+        "bigint_to_decimal": ([vp, ctypes.c_size_t, vp, ctypes.c_size_t, szp, vp, ctypes.c_size_t, vp], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -408,6 +411,34 @@ def decimal_digits(x, stream=None) -> int:
             continue
         return d
     raise RuntimeError("decimal digit count did not settle")
+
+
+def decimal_sizes(n_limbs: int):
+    """(upper bound on the decimal digits, workspace bytes) for n_limbs limbs; host only."""
+    lib = load()
+    mc, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.decimal_sizes(int(n_limbs), ctypes.byref(mc), ctypes.byref(wb)), "decimal_sizes")
+    return mc.value, wb.value
+
+
+def to_decimal_device(x, stream=None):
+    """Decimal digits of the limb tensor x as a uint8 device tensor of ASCII
+    characters, most significant first (the radix conversion runs on the GPU)."""
+    torch = _torch()
+    lib = load()
+    n = int(x.numel())
+    mc, wb = decimal_sizes(n)
+    w = workspace(wb, key="dec")
+    out = torch.empty(max(mc, 1), dtype=torch.uint8, device="cuda")
+    nc = ctypes.c_size_t()
+    _check(lib.bigint_to_decimal(_ptr(x) if n else None, n, _ptr(out), out.numel(), ctypes.byref(nc), _ptr(w),
+                                 w.numel(), _stream(stream)), "bigint_to_decimal")
+    return out[: nc.value]
+
+
+def to_decimal(x, stream=None) -> str:
+    """Decimal text of the limb tensor x (converted on the GPU, copied to the host)."""
+    return to_decimal_device(x, stream).cpu().numpy().tobytes().decode("ascii")
 
 
 def mul_batched(a_flat, a_off, b_flat, b_off, mode: str = "batched", stream=None):

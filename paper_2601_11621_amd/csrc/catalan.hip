@@ -5,4 +5,6 @@
 #include "small.inc.hip"
 #include "sieve.inc.hip"
 #include "ratio.inc.hip"
+#include "decimal.inc.hip"
 #include "host.inc.hip"
+#include "decimal_host.inc.hip"

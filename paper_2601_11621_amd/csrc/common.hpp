@@ -97,14 +97,33 @@ struct TreeLevel {
 
 #define CAT_INLINE_DESC 16
 
+// Uniform batch: product i reads a at a0 + i*sa and b at b0 + i*sb (la, lb
+// limbs each) and writes c at c0 + i*sc; residues at i*(la+lb).
+struct UniDesc {
+  uint64_t a0, sa, b0, sb, c0, sc;
+  uint32_t la, lb;
+};
+
 struct DescView {
   const MulDesc* table;  // device table (large explicit batches), or
   uint32_t ninl;         // > 0: explicit descriptors carried in the kernel arguments, or
+  uint32_t uni;          // > 0: uniform batch, or
   MulDesc inl[CAT_INLINE_DESC];
+  UniDesc u;
   TreeLevel tree;        // tree mode
   __device__ __forceinline__ MulDesc get(uint64_t i) const {
     if (table) return table[i];
     if (ninl) return inl[i];
+    if (uni) {
+      MulDesc d;
+      d.a_off = u.a0 + i * u.sa;
+      d.b_off = u.b0 + i * u.sb;
+      d.c_off = u.c0 + i * u.sc;
+      d.r_off = i * ((uint64_t)u.la + u.lb);
+      d.la = u.la;
+      d.lb = u.lb;
+      return d;
+    }
     uint32_t g = 0;
     while (g + 1 < tree.ngroups && i >= tree.mpref[g + 1]) g++;
     uint64_t il = i - tree.mpref[g];
@@ -121,9 +140,11 @@ struct DescView {
   }
 };
 
-// CRT/carry segments: out[out_pos + k] for k < len from residues at res_pos + k.
+// CRT/carry segments: out[out_pos + k] for k < len from residues at res_pos + k
+// (radix-10^9 products also add the digits add[add_pos + k] for k < add_len).
 struct CrtSeg {
   uint64_t out_pos, res_pos, len;
+  uint64_t add_pos, add_len;
 };
 
 // Bits of the device error word

@@ -1,0 +1,282 @@
+// Radix conversion to decimal (the optional decimal text output of Sec. 3.2):
+// device kernels.  The integer is converted bottom-up in radix B = 10^9:
+// leaves of four 32-bit limbs become five radix-B digits, and each level joins
+// two neighbours as hi * 2^(128 * 2^j) + lo, where the power of two is itself
+// held in radix B.  The product is the NTT product of the library with a
+// radix-B carry step that also adds lo.
+#define DEC_B 1000000000u
+#define DEC_LEAF_LIMBS 4
+#define DEC_LEAF_DIGITS 5          // 2^128 < 10^45
+
+// floor((r * 2^32 + w) / 10^9) and its remainder, for r < 10^9 (so the
+// quotient fits 32 bits): two-by-one division with a precomputed reciprocal
+// of the normalised divisor d = 4 * 10^9 (Moller and Granlund, "Improved
+// division by invariant integers", IEEE TC 2011, Algorithm 4).
+#define DEC_D 4000000000u
+#define DEC_V ((uint32_t)(0xFFFFFFFFFFFFFFFFull / DEC_D - (1ull << 32)))
+__device__ __forceinline__ uint32_t div_b(uint32_t r, uint32_t w, uint32_t* rem) {
+  const uint32_t u1 = (r << 2) | (w >> 30), u0 = w << 2;
+  const uint64_t q = (uint64_t)DEC_V * u1 + ((((uint64_t)u1 + 1) << 32) | u0);
+  uint32_t q1 = (uint32_t)(q >> 32);
+  const uint32_t q0 = (uint32_t)q;
+  uint32_t rr = u0 - q1 * DEC_D;
+  if (rr > q0) {
+    q1--;
+    rr += DEC_D;
+  }
+  if (rr >= DEC_D) {
+    q1++;
+    rr -= DEC_D;
+  }
+  *rem = rr >> 2;
+  return q1;
+}
+
+// Column value V = conv + addend (< 2^96) split into radix-B components
+// V = c0 + c1 B + c2 B^2 + c3 B^3 (c3 < 80).
+__device__ __forceinline__ void dec_split(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t add, uint32_t* c) {
+  uint32_t v0, v1, v2;
+  garner3(r0, r1, r2, v0, v1, v2);
+  const uint64_t lo = ((uint64_t)v1 << 32 | v0) + add;
+  if (lo < add) v2++;
+  v0 = (uint32_t)lo;
+  v1 = (uint32_t)(lo >> 32);
+  uint32_t r;
+  const uint32_t q2 = div_b(0, v2, &r);
+  const uint32_t q1 = div_b(r, v1, &r);
+  const uint32_t q0 = div_b(r, v0, &r);
+  c[0] = r;
+  // (q2, q1, q0) / B: q2 <= 4, and the quotient is below 2^37
+  const uint32_t p2 = div_b(0, q2, &r);
+  const uint32_t p1 = div_b(r, q1, &r);
+  const uint32_t p0 = div_b(r, q0, &r);
+  c[1] = r;
+  (void)p2;   // zero
+  const uint32_t s1 = div_b(0, p1, &r);
+  const uint32_t s0 = div_b(r, p0, &r);
+  (void)s1;   // zero
+  c[2] = r;
+  c[3] = s0;
+}
+
+// Radix-B digit k of a segment: s_k = c0(k) + c1(k-1) + c2(k-2) + c3(k-3) <
+// 3B + 80, so s_k = x_k + B y_k with y_k <= 3, u_k = x_k + y_{k-1} <= B + 2 and
+// the carries left are binary: generate u_k >= B, propagate u_k = B - 1.
+// Thread positions k0 .. k0+E-1; the four components of the positions
+// k0-4 .. k0-1 that enter these sums (10 words) come from the left neighbour
+// (thread 0: recomputed from the residues).
+#define DEC_XV 10
+__device__ __forceinline__ void dec_load(const CrtSeg& sg, const uint32_t* __restrict__ r0,
+                                         const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
+                                         const uint32_t* __restrict__ add, int64_t k, uint32_t* c) {
+  c[0] = c[1] = c[2] = c[3] = 0;
+  if (k < 0 || (uint64_t)k >= sg.len) return;
+  dec_split(r0[k], r1[k], r2[k], (uint64_t)k < sg.add_len ? add[sg.add_pos + k] : 0u, c);
+}
+
+__device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __restrict__ r0,
+                                            const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
+                                            const uint32_t* __restrict__ add, uint64_t kb, uint32_t (*xv)[DEC_XV],
+                                            uint32_t* tmp, uint64_t* u, bool* Gt, bool* Pt) {
+  const uint32_t tid = threadIdx.x;
+  const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
+  // c[i][.] for positions k0-4+i (i < 4 from the neighbour, own from i = 4)
+  uint32_t c[CAT_CRT_E + 4][4];
+  {
+    uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E], xa[CAT_CRT_E];
+#pragma unroll
+    for (int i = 0; i < CAT_CRT_E; i++) {
+      const uint64_t k = k0 + i;
+      const uint64_t kc = k < sg.len ? k : 0;
+      x0[i] = r0[kc];
+      x1[i] = r1[kc];
+      x2[i] = r2[kc];
+      xa[i] = add[sg.add_pos + (k < sg.add_len ? k : 0)];
+    }
+#pragma unroll
+    for (int i = 0; i < CAT_CRT_E; i++) {
+      const uint64_t k = k0 + i;
+      if (k < sg.len) {
+        dec_split(x0[i], x1[i], x2[i], k < sg.add_len ? xa[i] : 0u, c[i + 4]);
+      } else {
+        c[i + 4][0] = c[i + 4][1] = c[i + 4][2] = c[i + 4][3] = 0;
+      }
+    }
+  }
+  __syncthreads();   // xv may still be read by a previous call
+  {
+    uint32_t* o = xv[tid + 1];
+    const int e = CAT_CRT_E;
+    o[0] = c[e + 3][0]; o[1] = c[e + 3][1]; o[2] = c[e + 3][2]; o[3] = c[e + 3][3];
+    o[4] = c[e + 2][1]; o[5] = c[e + 2][2]; o[6] = c[e + 2][3];
+    o[7] = c[e + 1][2]; o[8] = c[e + 1][3];
+    o[9] = c[e][3];
+  }
+  if (tid == 0) {
+    uint32_t q[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) dec_load(sg, r0, r1, r2, add, (int64_t)kb - 4 + i, q[i]);
+    uint32_t* o = xv[0];
+    o[0] = q[3][0]; o[1] = q[3][1]; o[2] = q[3][2]; o[3] = q[3][3];
+    o[4] = q[2][1]; o[5] = q[2][2]; o[6] = q[2][3];
+    o[7] = q[1][2]; o[8] = q[1][3];
+    o[9] = q[0][3];
+  }
+  __syncthreads();
+  {
+    const uint32_t* o = xv[tid];
+    c[3][0] = o[0]; c[3][1] = o[1]; c[3][2] = o[2]; c[3][3] = o[3];
+    c[2][0] = 0;    c[2][1] = o[4]; c[2][2] = o[5]; c[2][3] = o[6];
+    c[1][0] = 0;    c[1][1] = 0;    c[1][2] = o[7]; c[1][3] = o[8];
+    c[0][0] = 0;    c[0][1] = 0;    c[0][2] = 0;    c[0][3] = o[9];
+  }
+  // position k0 - 1 gives y_{k0-1}
+  uint32_t s = c[3][0] + c[2][1] + c[1][2] + c[0][3];
+  uint32_t yprev = (s >= DEC_B) + (s >= 2 * DEC_B) + (s >= 3 * DEC_B);
+  bool G = false, P = true;
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E; i++) {
+    s = c[i + 4][0] + c[i + 3][1] + c[i + 2][2] + c[i + 1][3];
+    const uint32_t y = (s >= DEC_B) + (s >= 2 * DEC_B) + (s >= 3 * DEC_B);
+    u[i] = (uint64_t)(s - y * DEC_B) + yprev;
+    yprev = y;
+    const bool g = u[i] >= DEC_B, pr = u[i] == DEC_B - 1;
+    G = g || (pr && G);
+    P = P && pr;
+  }
+  *Gt = G;
+  *Pt = P;
+  uint32_t cout;
+  bool ap;
+  wave_carry(G, P, 0, &cout, &ap);
+  if ((tid & 63) == 0) tmp[tid >> 6] = cout | (ap ? 2u : 0u);
+  __syncthreads();
+}
+
+// CRT + radix-B carry + addend, with the look-back of k_crt (same flags,
+// epochs and recompute fallback); the blocks from nblk on copy tail ranges.
+__global__ void __launch_bounds__(CAT_CRT_THREADS)
+k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out,
+        const uint32_t* __restrict__ add, uint32_t nblk, uint32_t* __restrict__ flags, uint32_t epoch,
+        uint32_t polls, CopyList tails, const uint32_t* __restrict__ tin, uint32_t* __restrict__ tout,
+        uint32_t* __restrict__ err) {
+  __shared__ uint32_t tmp[16], tmp2[16];
+  __shared__ uint32_t xv[CAT_CRT_THREADS + 1][DEC_XV];
+  __shared__ uint32_t s_state, s_pair;
+  const uint32_t b = blockIdx.x, tid = threadIdx.x;
+  if (b >= nblk) {
+    copy_tail_block(tails, tin, tout, b - nblk);
+    return;
+  }
+  CrtSeg sg;
+  uint32_t first, end;
+  sv.find(b, &sg, &first, &end);
+  const uint32_t* r0 = res + sg.res_pos;
+  const uint32_t* r1 = r0 + res_stride;
+  const uint32_t* r2 = r1 + res_stride;
+  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
+  uint64_t u[CAT_CRT_E];
+  bool G, P;
+  crt_local10(sg, r0, r1, r2, add, kb, xv, tmp, u, &G, &P);
+  const uint32_t own = crt_block_pair(tmp);
+  if (tid == 0)
+    __hip_atomic_store(flags + b, (epoch << 3) | (own << 1) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t cin = 0, k = b;
+  bool done = (b == first);
+  while (!done) {
+    k--;
+    if (tid == 0) {
+      uint32_t f = 0;
+      for (uint32_t i = 0; i < polls; i++) {
+        f = __hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((f & 1u) && (f >> 3) == epoch) break;
+        f = 0;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      s_state = f ? 1u : 2u;
+      s_pair = (f >> 1) & 3u;
+    }
+    __syncthreads();
+    const uint32_t state = s_state;
+    uint32_t pair = s_pair;
+    __syncthreads();
+    if (state == 2u) {
+      uint64_t u2[CAT_CRT_E];
+      bool G2, P2;
+      crt_local10(sg, r0, r1, r2, add, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      pair = crt_block_pair(tmp2);
+    }
+    if (pair & 1u) { cin = 1; done = true; }
+    else if (!(pair & 2u)) done = true;
+    else if (k == first) done = true;
+  }
+  if (tid == 0 && b + 1 == end && ((own & 1u) | ((own >> 1) & cin))) atomicOr(err, CAT_DEVERR_CARRY_OUT);
+  const uint32_t wid = tid >> 6;
+  uint32_t wc = cin;
+  for (uint32_t w = 0; w < wid; w++) {
+    const uint32_t x = tmp[w];
+    wc = (x & 1u) | ((x >> 1) & wc);
+  }
+  uint32_t cout;
+  bool ap;
+  uint32_t c = wave_carry(G, P, wc, &cout, &ap);
+  uint32_t* o = out + sg.out_pos;
+  const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E; i++) {
+    const uint64_t kk = k0 + i;
+    const uint32_t t = (uint32_t)u[i] + c;
+    c = t >= DEC_B;
+    if (kk < sg.len) o[kk] = c ? t - DEC_B : t;
+  }
+}
+
+// Leaves: limbs [4i, 4i+4) of x (zero past L) as five radix-B digits at
+// out[5i .. 5i+5), least significant first.
+__global__ void __launch_bounds__(256) k_dec_leaf(const uint32_t* __restrict__ x, uint64_t L,
+                                                  uint32_t* __restrict__ out, uint64_t nleaves) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaves) return;
+  uint32_t w[DEC_LEAF_LIMBS];
+#pragma unroll
+  for (int k = 0; k < DEC_LEAF_LIMBS; k++) {
+    const uint64_t at = i * DEC_LEAF_LIMBS + k;
+    w[k] = at < L ? x[at] : 0u;
+  }
+#pragma unroll
+  for (int d = 0; d < DEC_LEAF_DIGITS; d++) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = DEC_LEAF_LIMBS - 1; k >= 0; k--) w[k] = div_b(r, w[k], &r);
+    out[i * DEC_LEAF_DIGITS + d] = r;
+  }
+}
+
+// out[k] = k < nin ? in[k] : 0 for k < nout (a node carried up a level).
+__global__ void k_copy_pad(const uint32_t* __restrict__ in, uint64_t nin, uint32_t* __restrict__ out,
+                           uint64_t nout) {
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nout; k += (uint64_t)gridDim.x * blockDim.x)
+    out[k] = k < nin ? in[k] : 0u;
+}
+
+// Text: radix-B digits dig[0 .. top] (dig[top] != 0, or top = 0) as
+// D = width(dig[top]) + 9 top characters, most significant first.
+__global__ void __launch_bounds__(256) k_dec_ascii(const uint32_t* __restrict__ dig, uint64_t top, uint32_t width,
+                                                   char* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > top) return;
+  uint32_t v = dig[i];
+  if (i == top) {
+    for (int k = (int)width - 1; k >= 0; k--) {
+      out[k] = (char)('0' + v % 10u);
+      v /= 10u;
+    }
+    return;
+  }
+  char* o = out + width + 9 * (top - 1 - i);
+#pragma unroll
+  for (int k = 8; k >= 0; k--) {
+    o[k] = (char)('0' + v % 10u);
+    v /= 10u;
+  }
+}

@@ -336,6 +336,7 @@ struct Stage {
   bool is_leaf = false;    // k_leaf<5>
   TreeLevel leaf{};
   uint64_t leaf_nodes = 0;
+  bool dec = false;        // radix-10^9 products (k_crt10; addends in the segments)
 };
 
 // host mirror of DescView::get in tree mode
@@ -911,6 +912,22 @@ cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const C
   return CAT_OK;
 }
 
+// Radix-10^9 CRT + carry + addend (addends are read relative to the workspace).
+cat_status launch_crt10(Exec& X, uint32_t* out, const SegView& sv, uint32_t nblk, const CopyList* tails,
+                        const uint32_t* tin, uint32_t* tout) {
+  const uint32_t grid = nblk + tail_blocks(*tails);
+  if (grid == 0) return CAT_OK;
+  {
+    KTime kt("k_crt10", X.st, (double)nblk * CAT_CRT_BLOCK);
+    X.crt_epoch++;
+    hipLaunchKernelGGL(k_crt10, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.W, nblk,
+                       X.flags, X.crt_epoch, g_crt_polls, *tails, tin, tout, X.err);
+  }
+  LAUNCHCHK();
+  X.launches++;
+  return CAT_OK;
+}
+
 // Products of a stage given by `dv` (cnt of them): the NTT or schoolbook part.
 uint32_t* out_base(Exec& X, const Stage& s) { return X.C ? X.C : X.W + s.c_base; }
 
@@ -1016,6 +1033,11 @@ cat_status run_stage_batched(Exec& X, const Stage& s) {
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;
+  }
+  if (s.nmul > 0 && s.dec) {
+    if (s.cls == CLS_SCHOOL) return CAT_EINTERNAL;
+    STCHK(launch_products(X, s, s.dv, s.nmul));
+    return launch_crt10(X, out_base(X, s), s.sv, s.nblk, &s.tails, X.W + s.tail_in_base, X.W + s.tail_out_base);
   }
   if (s.nmul > 0) {
     // the tail copies ride along with the last kernel of the level

@@ -669,9 +669,23 @@ struct SegView {
   const CrtSeg* segs;        // nullptr => inline tables
   const uint32_t* pref;      // pref[s] = first block of segment s (nseg+1 entries)
   uint32_t nseg;
+  uint32_t ubl;              // > 0: uniform segments of ubl blocks each (below)
   CrtSeg iseg[CAT_INLINE_SEG];
   uint32_t ipref[CAT_INLINE_SEG + 1];
+  // uniform: segment s is iseg[0] with out_pos, res_pos and add_pos advanced
+  // by s * ustep[0], s * iseg[0].len and s * ustep[1]
+  uint64_t ustep[2];
   __device__ __forceinline__ void find(uint32_t b, CrtSeg* sg, uint32_t* first, uint32_t* end) const {
+    if (ubl) {
+      const uint32_t q = b / ubl;
+      *sg = iseg[0];
+      sg->out_pos += q * ustep[0];
+      sg->res_pos += q * iseg[0].len;
+      sg->add_pos += q * ustep[1];
+      *first = q * ubl;
+      *end = *first + ubl;
+      return;
+    }
     const uint32_t* pr = segs ? pref : ipref;
     uint32_t lo = 0, hi = nseg;   // pr[lo] <= b < pr[lo+1]
     while (hi - lo > 1) {

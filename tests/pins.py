@@ -241,3 +241,71 @@ def ratio_value(num, den=()):
     if r:
         raise ValueError("not an integer")
     return q
+
+
+def limbs_mod_vec(limbs, m: int, chunk: int = 4096) -> int:
+    """Value of LE uint32 limbs modulo m < 2^31: per chunk sum((limb_i mod m) *
+    (2^32i mod m) mod m), chunks joined by Horner steps with 2^(32 chunk)."""
+    assert 1 < m < (1 << 31)
+    x = np.ascontiguousarray(limbs, dtype=np.uint64) % m
+    base = (1 << 32) % m
+    pw = np.empty(chunk, dtype=np.uint64)
+    v = 1
+    for i in range(chunk):
+        pw[i] = v
+        v = v * base % m
+    step = pow(base, chunk, m)
+    pad = (-len(x)) % chunk
+    xs = np.concatenate([x, np.zeros(pad, dtype=np.uint64)]).reshape(-1, chunk)
+    part = ((xs * pw[None, :]) % m).sum(axis=1) % m
+    acc = 0
+    for c in range(len(part) - 1, -1, -1):
+        acc = (acc * step + int(part[c])) % m
+    return acc
+
+
+def decimal_group_residues(text, rows: int = 1 << 22) -> tuple:
+    """From decimal text (a torch uint8 tensor of ASCII digits, any device):
+    the nine-digit groups g_i (least significant first) reduced as
+    (sum g_i mod 10^9-1, sum (-1)^i g_i mod 10^9+1, g_0), i.e. the number
+    modulo 10^9-1, 10^9+1 and 10^9.  Works through the groups in slices."""
+    import torch
+
+    pad = (-text.numel()) % 9
+    t = torch.cat([torch.full((pad,), 48, dtype=torch.uint8, device=text.device), text]).reshape(-1, 9)
+    ng = t.shape[0]
+    w = torch.tensor([10**k for k in range(8, -1, -1)], dtype=torch.int64, device=text.device)
+    m1, m2 = 10**9 - 1, 10**9 + 1
+    s1 = s2 = 0
+    for r0 in range(0, ng, rows):
+        d = t[r0:r0 + rows].to(torch.int64) - 48
+        assert bool(((d >= 0) & (d <= 9)).all())
+        g = (d * w).sum(dim=1)                 # most significant first
+        idx = ng - 1 - (r0 + torch.arange(g.numel(), device=g.device))   # group index from the bottom
+        s1 = (s1 + int(g.sum().item())) % m1
+        sign = 1 - 2 * (idx & 1)
+        s2 = (s2 + int((g * sign).sum().item())) % m2
+    g0 = int(((t[-1].to(torch.int64) - 48) * w).sum().item())
+    return s1, s2, g0
+
+
+def limbs_mod_torch(t, m: int, chunk: int = 4096) -> int:
+    """limbs_mod_vec for a torch int32 limb tensor (on its own device)."""
+    import torch
+
+    assert 1 < m < (1 << 31)
+    x = t.to(torch.int64) & 0xFFFFFFFF
+    pad = (-x.numel()) % chunk
+    x = torch.cat([x, torch.zeros(pad, dtype=torch.int64, device=x.device)]).reshape(-1, chunk) % m
+    base = (1 << 32) % m
+    pw, v = [], 1
+    for _ in range(chunk):
+        pw.append(v)
+        v = v * base % m
+    pwt = torch.tensor(pw, dtype=torch.int64, device=x.device)
+    part = ((x * pwt[None, :]) % m).sum(dim=1).remainder(m).cpu().tolist()
+    step = pow(base, chunk, m)
+    acc = 0
+    for c in range(len(part) - 1, -1, -1):
+        acc = (acc * step + part[c]) % m
+    return acc

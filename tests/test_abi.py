@@ -106,3 +106,23 @@ def test_ratio_sizes_host_only():
     with pytest.raises(cat.CatalanError) as e:
         cat.ratio_sizes(list(range(33)))
     assert e.value.status == cat.CAT_EINVAL
+
+
+def test_decimal_sizes_host_only():
+    """decimal_sizes needs no GPU: the digit bound covers 2^(32 L) - 1, the
+    workspace grows with L, and inputs beyond the longest transform are refused."""
+    import math
+
+    import paper_2601_11621_amd as cat
+
+    prev = 0
+    for L in [0, 1, 4, 5, 1000, 624999, 6249999]:
+        mc, wb = cat.decimal_sizes(L)
+        assert mc >= math.floor(32 * L * math.log10(2)) + 1
+        assert wb >= prev
+        prev = wb
+    mc, wb = cat.decimal_sizes(128160805)         # C(2,050,572,903): 1,234,567,890 digits
+    assert mc >= 1234567890 and wb < 64 * 2**30
+    with pytest.raises(cat.CatalanError) as e:
+        cat.decimal_sizes(2**27 + 1)
+    assert e.value.status == cat.CAT_ERANGE

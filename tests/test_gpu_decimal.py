@@ -1,0 +1,114 @@
+"""Decimal text on the GPU (the optional decimal output of Sec. 3.2): the
+radix-10^9 conversion against the oracle's schoolbook division, character for
+character, on ragged random sizes, closed forms and C(n); at sizes beyond the
+oracle by residues of the text against residues of the limbs, and by the
+digit count settled independently with powers of five."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cat():
+    import torch
+
+    import paper_2601_11621_amd as c
+
+    torch.cuda.set_device(0)
+    c.init(0)
+    return c
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _random_limbs(L, seed):
+    return np.random.default_rng(seed).integers(0, 2**32, size=L, dtype=np.uint64).astype(np.uint32)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 7, 8, 9, 16, 31, 33, 64, 100, 257, 1000, 1023, 1025, 4096, 4097,
+                               10000, 20001])
+def test_random_vs_oracle(cat, L):
+    _say("decimal random", L)
+    x = _random_limbs(L, L)
+    assert cat.to_decimal(cat.from_numpy(x)) == oracle.to_decimal(x)
+
+
+@pytest.mark.parametrize("L", [1, 4, 5, 8, 100, 1000, 4097])
+def test_all_ones_vs_oracle(cat, L):
+    """2^(32L) - 1: every radix-10^9 column near its maximum."""
+    _say("decimal all ones", L)
+    x = np.full(L, 0xFFFFFFFF, dtype=np.uint32)
+    assert cat.to_decimal(cat.from_numpy(x)) == oracle.to_decimal(x)
+
+
+@pytest.mark.parametrize("k", [0, 1, 9, 18, 27, 100, 1000, 9999, 100001])
+def test_powers_of_ten(cat, k):
+    """10^k and 10^k - 1: long runs of zeros and nines (carry chains)."""
+    _say("decimal 10^k", k)
+    for x, want in [(10**k, "1" + "0" * k), (10**k - 1, "9" * k if k else "0")]:
+        assert cat.to_decimal(cat.from_numpy(oracle.int_to_limbs(x))) == want
+
+
+def test_zero_and_leading_zero_limbs(cat):
+    import torch
+
+    assert cat.to_decimal(torch.zeros(0, dtype=torch.int32, device="cuda")) == "0"
+    assert cat.to_decimal(torch.zeros(9, dtype=torch.int32, device="cuda")) == "0"
+    x = oracle.int_to_limbs(123456789123456789, length=50)
+    assert cat.to_decimal(cat.from_numpy(x)) == "123456789123456789"
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 10, 1000, 10**5])
+def test_catalan_vs_oracle(cat, n):
+    _say("decimal C(%d)" % n)
+    t = cat.exact(n)
+    assert cat.to_decimal(t) == oracle.to_decimal(oracle.catalan(n))
+
+
+def test_repeat_calls_identical(cat):
+    """Same text on back-to-back calls of different sizes (scratch reuse)."""
+    a = cat.from_numpy(_random_limbs(5000, 1))
+    b = cat.from_numpy(_random_limbs(300, 2))
+    sa = cat.to_decimal(a)
+    sb = cat.to_decimal(b)
+    assert cat.to_decimal(a) == sa and cat.to_decimal(b) == sb
+
+
+@pytest.mark.parametrize("n", [10**6, 10**7, 10**8])
+def test_catalan_residues_and_digit_count(cat, n):
+    """The text's nine-digit groups modulo 10^9-1, 10^9+1 and 10^9 agree with
+    the limbs modulo the same numbers, and its length is the digit count found
+    by the shifted comparisons against powers of five."""
+    import time
+
+    import torch
+
+    t = cat.exact(n)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    text = cat.to_decimal_device(t)
+    torch.cuda.synchronize()
+    _say("decimal C(%d): %d digits in %.4f s" % (n, text.numel(), time.time() - t0))
+    limbs = cat.to_numpy(t)
+    s1, s2, g0 = pins.decimal_group_residues(text)
+    assert s1 == pins.limbs_mod_vec(limbs, 10**9 - 1)
+    assert s2 == pins.limbs_mod_vec(limbs, 10**9 + 1)
+    assert g0 == pins.limbs_mod_vec(limbs, 10**9)
+    assert int(text[0].item()) != 48
+    assert text.numel() == cat.decimal_digits(t)
+
+
+def test_random_large_residues(cat):
+    """A random 3,000,000-limb integer (about 28.9 M digits)."""
+    x = _random_limbs(3_000_000, 7)
+    text = cat.to_decimal_device(cat.from_numpy(x))
+    s1, s2, g0 = pins.decimal_group_residues(text)
+    assert s1 == pins.limbs_mod_vec(x, 10**9 - 1)
+    assert s2 == pins.limbs_mod_vec(x, 10**9 + 1)
+    assert g0 == pins.limbs_mod_vec(x, 10**9)

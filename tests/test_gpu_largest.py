@@ -114,3 +114,17 @@ def test_catalan_2050572903_table1(cat):
     t0 = time.time()
     assert cat.decimal_digits(t) == t1["decimal_digits"]
     _say("digit count settled in %.3f s" % (time.time() - t0))
+    # the decimal text itself (the optional output of Sec. 3.2), converted on
+    # the GPU: 1,234,567,890 characters whose nine-digit groups agree with the
+    # limbs modulo 10^9 - 1, 10^9 + 1 and 10^9
+    t0 = time.time()
+    text = cat.to_decimal_device(t)
+    torch.cuda.synchronize()
+    _say("decimal text in %.3f s" % (time.time() - t0))
+    assert text.numel() == t1["decimal_digits"]
+    s1, s2, g0 = pins.decimal_group_residues(text)
+    assert s1 == pins.limbs_mod_torch(t, 10**9 - 1)
+    assert s2 == pins.limbs_mod_torch(t, 10**9 + 1)
+    assert g0 == pins.limbs_mod_torch(t, 10**9)
+    del text
+    torch.cuda.empty_cache()

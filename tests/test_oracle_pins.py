@@ -318,3 +318,48 @@ def test_ratio_not_integral_rejected(num, den):
         oracle.ratio(num, den)
     with pytest.raises(ValueError):
         pins.ratio_value(num, den)
+
+
+# ------------------------------------------------------------------ decimal text (Sec. 3.2, optional output)
+def _dec_cases():
+    import random
+
+    rng = random.Random(11621)
+    xs = [0, 1, 9, 10, 99, 100, 2**32 - 1, 2**32, 10**9 - 1, 10**9, 10**9 + 1, 10**18, 2**64 - 1, 2**64]
+    xs += [10**k for k in (17, 18, 19, 26, 27, 28, 100, 333)] + [10**k - 1 for k in (9, 18, 27, 100, 333)]
+    xs += [rng.getrandbits(rng.randint(1, 4000)) for _ in range(120)]
+    return xs
+
+
+def test_decimal_oracle_closed_forms():
+    """10^k is a one and k zeros, 10^k - 1 is k nines, zero is "0", and leading
+    zero limbs change nothing."""
+    for k in [0, 1, 8, 9, 10, 17, 18, 19, 45, 200, 1001]:
+        assert oracle.to_decimal(oracle.int_to_limbs(10**k)) == "1" + "0" * k
+        if k:
+            assert oracle.to_decimal(oracle.int_to_limbs(10**k - 1)) == "9" * k
+    assert oracle.to_decimal(np.zeros(0, dtype=np.uint32)) == "0"
+    assert oracle.to_decimal(np.zeros(7, dtype=np.uint32)) == "0"
+    assert oracle.to_decimal(oracle.int_to_limbs(12345, length=9)) == "12345"
+
+
+def test_decimal_oracle_against_python_conversion():
+    """Against CPython's own integer-to-text conversion and parsed back by int()."""
+    import sys
+
+    if hasattr(sys, "set_int_max_str_digits"):
+        sys.set_int_max_str_digits(0)
+    for x in _dec_cases():
+        s = oracle.to_decimal(oracle.int_to_limbs(x))
+        assert s == str(x)
+        assert int(s) == x and (s == "0" or s[0] != "0")
+
+
+def test_decimal_pins_reject_planted_mistake():
+    """Dropping the zero padding of inner nine-digit groups fails the parse-back."""
+    try:
+        oracle.set_fault(4)
+        bad = any(int(oracle.to_decimal(oracle.int_to_limbs(x))) != x for x in [10**9, 10**20 + 7, 2**200])
+        assert bad
+    finally:
+        oracle.set_fault(0)
