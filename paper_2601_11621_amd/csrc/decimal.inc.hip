@@ -1,12 +1,12 @@
 // Radix conversion to decimal (the optional decimal text output of Sec. 3.2):
 // device kernels.  The integer is converted bottom-up in radix B = 10^9:
-// leaves of four 32-bit limbs become five radix-B digits, and each level joins
-// two neighbours as hi * 2^(128 * 2^j) + lo, where the power of two is itself
-// held in radix B.  The product is the NTT product of the library with a
+// leaves of sixteen 32-bit limbs become eighteen radix-B digits, and each level
+// joins two neighbours as hi * 2^(512 * 2^j) + lo, where the power of two is
+// itself held in radix B.  The product is the NTT product of the library with a
 // radix-B carry step that also adds lo.
 #define DEC_B 1000000000u
-#define DEC_LEAF_LIMBS 4
-#define DEC_LEAF_DIGITS 5          // 2^128 < 10^45
+#define DEC_LEAF_LIMBS 16
+#define DEC_LEAF_DIGITS 18         // 2^512 < 10^162
 
 // floor((r * 2^32 + w) / 10^9) and its remainder, for r < 10^9 (so the
 // quotient fits 32 bits): two-by-one division with a precomputed reciprocal
@@ -112,15 +112,15 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
     o[7] = c[e + 1][2]; o[8] = c[e + 1][3];
     o[9] = c[e][3];
   }
-  if (tid == 0) {
-    uint32_t q[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) dec_load(sg, r0, r1, r2, add, (int64_t)kb - 4 + i, q[i]);
+  if (tid < 4) {
+    // threads 0..3 recompute positions kb-4 .. kb-1, one each
+    uint32_t q[4];
+    dec_load(sg, r0, r1, r2, add, (int64_t)kb - 4 + tid, q);
     uint32_t* o = xv[0];
-    o[0] = q[3][0]; o[1] = q[3][1]; o[2] = q[3][2]; o[3] = q[3][3];
-    o[4] = q[2][1]; o[5] = q[2][2]; o[6] = q[2][3];
-    o[7] = q[1][2]; o[8] = q[1][3];
-    o[9] = q[0][3];
+    if (tid == 3) { o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; }
+    if (tid == 2) { o[4] = q[1]; o[5] = q[2]; o[6] = q[3]; }
+    if (tid == 1) { o[7] = q[2]; o[8] = q[3]; }
+    if (tid == 0) o[9] = q[3];
   }
   __syncthreads();
   {
@@ -231,8 +231,8 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
   }
 }
 
-// Leaves: limbs [4i, 4i+4) of x (zero past L) as five radix-B digits at
-// out[5i .. 5i+5), least significant first.
+// Leaves: limbs [16i, 16i+16) of x (zero past L) as eighteen radix-B digits
+// at out[18i .. 18i+18), least significant first (schoolbook division).
 __global__ void __launch_bounds__(256) k_dec_leaf(const uint32_t* __restrict__ x, uint64_t L,
                                                   uint32_t* __restrict__ out, uint64_t nleaves) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

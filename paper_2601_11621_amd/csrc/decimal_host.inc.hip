@@ -1,13 +1,14 @@
 // Radix conversion to decimal text (the optional decimal output of Sec. 3.2):
 // plan and C ABI.
 //
-// x (L limbs) is cut into n_0 = ceil(L/4) leaves of four limbs, each turned
-// into len_0 = 5 radix-10^9 digits.  Level j holds n_j nodes of len_j digits;
-// node i is the value of limbs [i 4 2^j, (i+1) 4 2^j).  Two neighbours join as
-// hi * P_j + lo with P_j = 2^(128 2^j) in radix 10^9 (t_j digits; P_{j+1} =
+// x (L limbs) is cut into n_0 = ceil(L/16) leaves of sixteen limbs, each turned
+// into len_0 = 18 radix-10^9 digits.  Level j holds n_j nodes of len_j digits;
+// node i is the value of limbs [i 16 2^j, (i+1) 16 2^j).  Two neighbours join as
+// hi * P_j + lo with P_j = 2^(512 2^j) in radix 10^9 (t_j digits; P_{j+1} =
 // P_j^2), giving len_{j+1} = len_j + t_j digits; a last node without a
 // partner is carried up (copied and zero-padded).  All products of a level are
-// one uniform batch.  A product too long for one transform (only the top one,
+// one uniform batch.  The squarings that make the powers run on a second
+// stream with their own scratch, level j waiting only for P_j.  A product too long for one transform (only the top one,
 // beyond about 1.2e9 decimal digits) is cut in two along hi:
 // T = hi_lo * P + lo, then c = hi_hi * P + T / B^m above the copied T mod B^m.
 
@@ -23,8 +24,9 @@ struct DecPlan {
   std::vector<Stage> pw;         // P_j = P_{j-1}^2, j = 1 .. h-1
   std::vector<std::vector<Stage>> join;   // stages of level j -> j+1
   uint64_t x[2] = {0, 0}, xsize = 0, pbase = 0, psize = 0, tbase = 0, tsize = 0;   // uint32 offsets
-  uint64_t res_len = 0, F_words = 0, nblk_max = 0;
-  size_t off_res = 0, off_F = 0, off_ctl = 0, ctl_words = 0, total = 0;          // bytes (ctl_words: uint32)
+  uint64_t res_len = 0, F_words = 0, nblk_max = 0;      // joins
+  uint64_t res2_len = 0, F2_words = 0, nblk2_max = 0;   // squarings (second stream)
+  size_t off_res = 0, off_F = 0, off_res2 = 0, off_F2 = 0, off_ctl = 0, ctl_words = 0, total = 0;   // bytes
   uint64_t products = 0, product_digits = 0;
 };
 
@@ -76,7 +78,8 @@ cat_status make_dec_plan(uint64_t L, DecPlan* D) {
   for (int j = 0; P.lv[j].nodes > 1; j++) {
     DecLevel& c = P.lv[j];
     c.poff = poff;
-    c.t = j == 0 ? (uint64_t)DEC_LEAF_DIGITS : std::min<uint64_t>(pcap, dec_digits_pow2(128ull << j));
+    c.t = j == 0 ? (uint64_t)DEC_LEAF_DIGITS
+                 : std::min<uint64_t>(pcap, dec_digits_pow2((32ull * DEC_LEAF_LIMBS) << j));
     poff += pcap;
     pcap = 2 * c.t;   // P_{j+1} = P_j^2 as a product of 2 t_j digits
     DecLevel nx;
@@ -151,16 +154,16 @@ cat_status make_dec_plan(uint64_t L, DecPlan* D) {
     v[1].tail_in_base = P.tbase;
   }
   // scratch of the products
-  auto scratch = [&](const Stage& s) {
-    P.res_len = std::max<uint64_t>(P.res_len, s.limbs);
-    if (s.cls == CLS_LARGE) P.F_words = std::max<uint64_t>(P.F_words, s.nmul * 6ull << s.logN);
-    P.nblk_max = std::max<uint64_t>(P.nblk_max, s.nblk);
+  auto scratch = [&](const Stage& s, uint64_t* res_len, uint64_t* F_words, uint64_t* nblk_max) {
+    *res_len = std::max<uint64_t>(*res_len, s.limbs);
+    if (s.cls == CLS_LARGE) *F_words = std::max<uint64_t>(*F_words, s.nmul * 6ull << s.logN);
+    *nblk_max = std::max<uint64_t>(*nblk_max, s.nblk);
     P.products += s.nmul;
     P.product_digits += s.limbs;
   };
-  for (const Stage& s : P.pw) scratch(s);
+  for (const Stage& s : P.pw) scratch(s, &P.res2_len, &P.F2_words, &P.nblk2_max);
   for (const auto& v : P.join)
-    for (const Stage& s : v) scratch(s);
+    for (const Stage& s : v) scratch(s, &P.res_len, &P.F_words, &P.nblk_max);
   size_t off = o * 4;
   auto takeb = [&](size_t bytes) {
     const size_t r = off;
@@ -169,19 +172,23 @@ cat_status make_dec_plan(uint64_t L, DecPlan* D) {
   };
   P.off_res = takeb(3 * (P.res_len + 64) * 4);
   P.off_F = takeb(P.F_words * 4);
-  // control block: error word | top index (8 bytes) | look-back flags
-  P.ctl_words = 4 + P.nblk_max + 1;
+  P.off_res2 = takeb(3 * (P.res2_len + 64) * 4);
+  P.off_F2 = takeb(P.F2_words * 4);
+  // control block: error word | top index (8 bytes) | look-back flags of the
+  // joins | those of the squarings
+  P.ctl_words = 4 + (P.nblk_max + 1) + (P.nblk2_max + 1);
   P.off_ctl = takeb(P.ctl_words * 4);
   P.total = off;
   return CAT_OK;
 }
 
-// P_0 = 2^128 in radix 10^9, least significant digit first
+// P_0 = 2^(32 DEC_LEAF_LIMBS) in radix 10^9, least significant digit first
 void dec_p0(uint32_t* d) {
-  uint32_t w[5] = {0, 0, 0, 0, 1};   // 2^128 as 32-bit limbs, by long division
+  uint32_t w[DEC_LEAF_LIMBS + 1] = {0};   // as 32-bit limbs, by long division
+  w[DEC_LEAF_LIMBS] = 1;
   for (int k = 0; k < DEC_LEAF_DIGITS; k++) {
     uint64_t r = 0;
-    for (int i = 4; i >= 0; i--) {
+    for (int i = DEC_LEAF_LIMBS; i >= 0; i--) {
       const uint64_t cur = (r << 32) | w[i];
       w[i] = (uint32_t)(cur / DEC_B);
       r = cur % DEC_B;
@@ -225,17 +232,38 @@ cat_status bigint_to_decimal(const uint32_t* d_x, size_t n_limbs, char* d_out, s
   hipLaunchKernelGGL(k_fill, dim3((uint32_t)std::min<uint64_t>((P.ctl_words + 255) / 256, 1024)), dim3(256), 0, st,
                      X.err, (uint64_t)P.ctl_words, 0u);
   LAUNCHCHK();
-  const uint64_t n0 = P.lv[0].nodes;
-  hipLaunchKernelGGL(k_dec_leaf, dim3((uint32_t)((n0 + 255) / 256)), dim3(256), 0, st, d_x, (uint64_t)n_limbs,
-                     X.W + P.x[0], n0);
-  LAUNCHCHK();
   const int h = (int)P.lv.size() - 1;
+  while (g.dec_ev.size() < (size_t)std::max(h, 1)) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    g.dec_ev.push_back(e);
+  }
   if (h > 0) {
     dec_p0((uint32_t*)g.pin);
     HIPCHK(hipMemcpyAsync(X.W + P.pbase, g.pin, 4 * DEC_LEAF_DIGITS, hipMemcpyHostToDevice, st));
   }
-  for (Stage& s : P.pw) STCHK(run_stage_batched(X, s));
+  if (!P.pw.empty()) {
+    // P_1 .. P_{h-1} on the second stream (after the fill and P_0); event j-1 marks P_j
+    Exec S = X;
+    S.st = g.side_stream;
+    S.res = (uint32_t*)(wb + P.off_res2);
+    S.res_stride = P.res2_len + 64;
+    S.F = (uint32_t*)(wb + P.off_F2);
+    S.flags = X.flags + P.nblk_max + 1;
+    S.crt_epoch = 0;
+    HIPCHK(hipEventRecord(g.dec_ev[0], st));
+    HIPCHK(hipStreamWaitEvent(S.st, g.dec_ev[0], 0));
+    for (size_t k = 0; k < P.pw.size(); k++) {
+      STCHK(run_stage_batched(S, P.pw[k]));
+      HIPCHK(hipEventRecord(g.dec_ev[k], S.st));
+    }
+  }
+  const uint64_t n0 = P.lv[0].nodes;
+  hipLaunchKernelGGL(k_dec_leaf, dim3((uint32_t)((n0 + 255) / 256)), dim3(256), 0, st, d_x, (uint64_t)n_limbs,
+                     X.W + P.x[0], n0);
+  LAUNCHCHK();
   for (int j = 0; j < h; j++) {
+    if (j >= 1) HIPCHK(hipStreamWaitEvent(st, g.dec_ev[j - 1], 0));
     for (Stage& s : P.join[j]) STCHK(run_stage_batched(X, s));
     const DecLevel& c = P.lv[j];
     if (c.nodes & 1) {

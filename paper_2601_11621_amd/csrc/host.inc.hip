@@ -43,6 +43,7 @@ struct Lib {
   hipStream_t cap_stream = nullptr;
   hipStream_t side_stream = nullptr;            // second branch of captured calls
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<hipEvent_t> dec_ev;               // decimal conversion: P_j ready
   // kernel timer: events around every launch of one named kernel
   std::string timer_name;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_ev;
