@@ -119,3 +119,14 @@ def reconstruct_from_file(cat, path: str, mode: str = "batched"):
     _, exps, off, primes = read_factorization(path)
     bits = int(primes.max()).bit_length() if primes.size else 1
     return cat.product(exps, off, primes, max_entry_bits=max(1, bits), mode=mode)
+
+
+def write_decimal(cat, x, path: str, chunk: int = 1 << 28) -> int:
+    """The decimal text of the limb tensor x (converted on the GPU) written to
+    `path` without a line break (the optional decimal output of Sec. 3.2);
+    returns the digit count."""
+    text = cat.to_decimal_device(x)
+    with open(path, "wb") as f:
+        for s in range(0, text.numel(), chunk):
+            f.write(text[s:s + chunk].cpu().numpy().tobytes())
+    return int(text.numel())

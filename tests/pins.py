@@ -309,3 +309,33 @@ def limbs_mod_torch(t, m: int, chunk: int = 4096) -> int:
     for c in range(len(part) - 1, -1, -1):
         acc = (acc * step + part[c]) % m
     return acc
+
+
+def leading_decimal(n: int, k: int = 30, dps: int = 80):
+    """The first k decimal digits of C(n) from log-gamma at `dps` digits, and
+    the distance of 10^(frac(log10 C) + k - 1) from the nearest integer (a
+    safe floor needs a margin well above 10^(k - dps + 12))."""
+    import mpmath
+
+    mpmath.mp.dps = dps
+    lnC = mpmath.loggamma(2 * n + 1) - mpmath.loggamma(n + 1) - mpmath.loggamma(n + 2)
+    log10C = lnC / mpmath.log(10)
+    f = log10C - mpmath.floor(log10C)
+    v = mpmath.power(10, f + k - 1)
+    lead = int(mpmath.floor(v))
+    return str(lead), float(min(v - lead, lead + 1 - v))
+
+
+def catalan_valuation(n: int, p: int) -> int:
+    """v_p(C(n)) = v_p((2n)!) - 2 v_p(n!) - v_p(n+1) (Legendre)."""
+    def vf(m):
+        s, q = 0, m
+        while q:
+            q //= p
+            s += q
+        return s
+    m, vn1 = n + 1, 0
+    while m % p == 0:
+        m //= p
+        vn1 += 1
+    return vf(2 * n) - 2 * vf(n) - vn1

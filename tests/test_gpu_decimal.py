@@ -102,6 +102,17 @@ def test_catalan_residues_and_digit_count(cat, n):
     assert g0 == pins.limbs_mod_vec(limbs, 10**9)
     assert int(text[0].item()) != 48
     assert text.numel() == cat.decimal_digits(t)
+    _check_ends(text, n)
+
+
+def _check_ends(text, n, k=30):
+    """First k digits against log-gamma, trailing zeros against min(v_2, v_5)."""
+    lead, margin = pins.leading_decimal(n, k)
+    assert margin > 1e-30
+    assert text[:k].cpu().numpy().tobytes().decode() == lead
+    z = min(pins.catalan_valuation(n, 2), pins.catalan_valuation(n, 5))
+    tail = text[-(z + 1):].cpu().numpy().tobytes().decode()
+    assert tail == tail[0] + "0" * z and tail[0] != "0"
 
 
 def test_random_large_residues(cat):

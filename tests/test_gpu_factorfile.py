@@ -93,3 +93,13 @@ def test_decimal_digits_of_catalan(cat, n):
         assert d == len(str(oracle.limbs_to_int(cat.to_numpy(t))))
     else:
         assert d == pins.log_pins(n)[1]
+
+
+def test_decimal_text_file(cat, tmp_path):
+    """The decimal text file of C(10^5) equals the oracle's text."""
+    path = str(tmp_path / "catalan_100000.txt")
+    d = factorfile.write_decimal(cat, cat.exact(10**5), path, chunk=4096)
+    with open(path, "rb") as f:
+        s = f.read().decode("ascii")
+    assert d == len(s) == 60199
+    assert s == oracle.to_decimal(oracle.catalan(10**5))

@@ -126,5 +126,13 @@ def test_catalan_2050572903_table1(cat):
     assert s1 == pins.limbs_mod_torch(t, 10**9 - 1)
     assert s2 == pins.limbs_mod_torch(t, 10**9 + 1)
     assert g0 == pins.limbs_mod_torch(t, 10**9)
+    lead, margin = pins.leading_decimal(n, 30)
+    assert margin > 1e-30 and text[:30].cpu().numpy().tobytes().decode() == lead
+    z = min(pins.catalan_valuation(n, 2), pins.catalan_valuation(n, 5))
+    tail = text[-(z + 1):].cpu().numpy().tobytes().decode()
+    assert tail == tail[0] + "0" * z and tail[0] != "0"
+    # the SHA-256 of Table 1 does not cover the bare text either (reading in
+    # the design notes); printed for the record
+    _say("sha256 of the decimal text %s" % hashlib.sha256(text.cpu().numpy().tobytes()).hexdigest())
     del text
     torch.cuda.empty_cache()

@@ -363,3 +363,18 @@ def test_decimal_pins_reject_planted_mistake():
         assert bad
     finally:
         oracle.set_fault(0)
+
+
+def test_leading_digits_and_trailing_zeros_pins():
+    """The log-gamma leading digits and the Legendre count of trailing zeros
+    (min(v_2, v_5)) agree with the exact decimal text for moderate n."""
+    import sys
+
+    if hasattr(sys, "set_int_max_str_digits"):
+        sys.set_int_max_str_digits(0)
+    for n in [50, 777, 5000, 30011]:
+        s = str(pins.catalan_comb(n))
+        lead, margin = pins.leading_decimal(n, 25)
+        assert margin > 1e-30 and s[:25] == lead
+        z = min(pins.catalan_valuation(n, 2), pins.catalan_valuation(n, 5))
+        assert len(s) - len(s.rstrip("0")) == z
