@@ -402,6 +402,18 @@ __device__ __forceinline__ uint2 tw2(const uint2* __restrict__ lo, const uint32_
   return make_uint2(w, w * pc.pinv);
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2) in
+// the order of their linear index.  Neighbouring column tiles share cache
+// lines (a tile row is C words), so block b of a grid of G is renumbered to
+// put consecutive tiles on one XCD: XCD x gets the tiles
+// [x ceil(G/8), ...) in order (a bijection of [0, G) for any G).
+#define CAT_XCDS 8
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+  const uint32_t q = G / CAT_XCDS, r = G % CAT_XCDS;
+  const uint32_t x = b % CAT_XCDS, k = b / CAT_XCDS;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 struct PassGeom {
   int logN, logS, logL, logC;
   __device__ __forceinline__ void locate(uint64_t bx, uint64_t* m, uint64_t* base, uint32_t* j0) const {
@@ -425,7 +437,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
   const uint32_t p = pc.p;
   uint64_t m, base;
   uint32_t j0;
-  pg.locate(blockIdx.x, &m, &base, &j0);
+  pg.locate(xcd_remap(blockIdx.x, gridDim.x), &m, &base, &j0);
   const int logSig = pg.logS - pg.logL;
   const uint32_t C = 1u << pg.logC;
   const uint64_t N = 1ull << pg.logN;
@@ -508,7 +520,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
   const uint32_t p = pc.p;
   uint64_t m, base;
   uint32_t j0;
-  pg.locate(blockIdx.x, &m, &base, &j0);
+  pg.locate(xcd_remap(blockIdx.x, gridDim.x), &m, &base, &j0);
   const int logSig = pg.logS - pg.logL;
   const uint32_t C = 1u << pg.logC;
   const uint64_t N = 1ull << pg.logN;
