@@ -388,6 +388,7 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
 //   F[((m*3 + prime)*2 + op)*N + position]
 #define NTT_COL_THREADS 256
 #define NTT_COL_TILE 8192u      // LDS words of a column tile (32 KB: 4 workgroups per CU)
+#define NTT_COL_MAXL 10         // longest column DFT: 2^10 points
 #define COL_BATCH 16            // global loads a thread keeps in flight in the column kernels
 #define TW2_LO_BITS 14u
 #define TW2_LO (1u << TW2_LO_BITS)
@@ -485,7 +486,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
   __syncthreads();
   const uint2* lo = tb.tw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.tw2hi + (size_t)prime * TW2_HI;
-  const uint64_t smask = (1ull << pg.logS) - 1;
+  const uint32_t ysh = CAT_MAX_LOGN - pg.logS;
   for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
     uint2 l[COL_BATCH];
     uint32_t h[COL_BATCH];
@@ -494,8 +495,9 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
       const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
       const uint32_t tc = t < T ? t : T - 1;
       const uint32_t q = tc >> pg.logC, j = j0 + (tc & (C - 1));
-      const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
-      const uint32_t y = (uint32_t)(e << (CAT_MAX_LOGN - pg.logS));
+      // omega_S^(j f(q)) = omega_{2^27}^y, y = (j f(q) 2^(27 - logS)) mod 2^27:
+      // the bits of j f(q) above 2^32 do not reach y
+      const uint32_t y = ((j * out_freq(q, pg.logL)) << ysh) & ((1u << CAT_MAX_LOGN) - 1);
       l[i] = lo[y & (TW2_LO - 1)];
       h[i] = hi[y >> TW2_LO_BITS];
     }
@@ -515,6 +517,7 @@ __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_t* __restrict__ res,
            uint64_t res_stride, NttTables tb) {
   __shared__ uint32_t lds[NTT_COL_TILE];
+  __shared__ uint32_t fq[1u << NTT_COL_MAXL];   // frequency at each output row
   const uint32_t prime = blockIdx.y;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
@@ -528,7 +531,9 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
   uint32_t* f = F + ((m * 3 + prime) * 2 + 0) * N;
   const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
-  const uint64_t smask = (1ull << pg.logS) - 1;
+  const uint32_t ysh = CAT_MAX_LOGN - pg.logS;
+  for (uint32_t q = threadIdx.x; q < (1u << pg.logL); q += blockDim.x) fq[q] = out_freq(q, pg.logL);
+  __syncthreads();
   for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
     uint2 l[COL_BATCH];
     uint32_t h[COL_BATCH], v[COL_BATCH];
@@ -537,8 +542,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
       const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
       const uint32_t tc = t < T ? t : T - 1;
       const uint32_t q = tc >> pg.logC, j = j0 + (tc & (C - 1));
-      const uint64_t e = ((uint64_t)j * out_freq(q, pg.logL)) & smask;
-      const uint32_t y = (uint32_t)(e << (CAT_MAX_LOGN - pg.logS));
+      const uint32_t y = ((j * fq[q]) << ysh) & ((1u << CAT_MAX_LOGN) - 1);
       l[i] = lo[y & (TW2_LO - 1)];
       h[i] = hi[y >> TW2_LO_BITS];
       v[i] = f[base + ((uint64_t)q << logSig) + j];
