@@ -123,3 +123,30 @@ def test_random_large_residues(cat):
     assert s1 == pins.limbs_mod_vec(x, 10**9 - 1)
     assert s2 == pins.limbs_mod_vec(x, 10**9 + 1)
     assert g0 == pins.limbs_mod_vec(x, 10**9)
+
+
+def test_abi_capacity_and_size_query(cat):
+    """Through the C ABI: a short output buffer gives CAT_ERANGE with the digit
+    count set and nothing written; a large enough one gives the text."""
+    import ctypes
+
+    import torch
+
+    lib = cat.load()
+    x = cat.from_numpy(oracle.int_to_limbs(10**40 + 12345))
+    mc, wb = cat.decimal_sizes(x.numel())
+    w = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    out = torch.full((64,), 35, dtype=torch.uint8, device="cuda")
+    nc = ctypes.c_size_t()
+    st = lib.bigint_to_decimal(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(out.data_ptr()), 10,
+                               ctypes.byref(nc), ctypes.c_void_p(w.data_ptr()), wb, None)
+    assert st == cat.CAT_ERANGE and nc.value == 41
+    assert bool((out == 35).all())
+    st = lib.bigint_to_decimal(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(out.data_ptr()), 64,
+                               ctypes.byref(nc), ctypes.c_void_p(w.data_ptr()), wb, None)
+    assert st == cat.CAT_OK and nc.value == 41
+    assert out[:41].cpu().numpy().tobytes().decode() == str(10**40 + 12345)
+    assert int(out[41].item()) == 35
+    st = lib.bigint_to_decimal(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(out.data_ptr()), 64,
+                               ctypes.byref(nc), ctypes.c_void_p(w.data_ptr()), 16, None)
+    assert st == cat.CAT_ENOMEM
