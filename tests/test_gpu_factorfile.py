@@ -103,3 +103,25 @@ def test_decimal_text_file(cat, tmp_path):
         s = f.read().decode("ascii")
     assert d == len(s) == 60199
     assert s == oracle.to_decimal(oracle.catalan(10**5))
+
+
+def test_command_line_two_phases(cat, tmp_path, capsys):
+    """factor -> rebuild through the command line: the binary file, its
+    SHA-256 and the decimal text equal the oracle's C(10^5)."""
+    import hashlib
+    import json
+
+    from paper_2601_11621_amd import cli
+
+    f, b, t = str(tmp_path / "f.txt"), str(tmp_path / "c.bin"), str(tmp_path / "c.txt")
+    assert cli.main(["factor", "100000", "--out", f]) == 0
+    capsys.readouterr()
+    assert cli.main(["rebuild", f, "--bin", b, "--txt", t]) == 0
+    info = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    want = oracle.catalan(100000)
+    assert np.array_equal(factorfile.read_bin(b), want)
+    with open(b, "rb") as fh:
+        assert hashlib.sha256(fh.read()).hexdigest() == info["sha256"]
+    with open(t) as fh:
+        assert fh.read() == oracle.to_decimal(want)
+    assert info["digits"] == 60199 and info["bits"] == 199975
