@@ -225,13 +225,13 @@ NttTables tables_for(int logN) {
 }
 
 // Pass decomposition of a large transform: N = L_0 ... L_{P-1} * M with
-// every L_p <= 2^maxL (maxL <= 10, so a tile of L_p x C words with C >= 8
+// every L_p <= 2^maxL (maxL <= 10, so a tile of L_p x C words with C >= 4
 // fits 32 KB) and rows of M = 2^logM.
 struct PassPlan {
   int P = 0;
   int logL[8] = {}, logS[8] = {}, logC[8] = {};
 };
-PassPlan pass_plan(int logN, int logM, int maxL) {
+PassPlan pass_plan(int logN, int logM, int maxL, int logT = NTT_COL_LOGT) {
   PassPlan pp;
   const int rest = logN - logM;
   pp.P = (rest + maxL - 1) / maxL;
@@ -239,7 +239,7 @@ PassPlan pass_plan(int logN, int logM, int maxL) {
   for (int k = 0; k < pp.P; k++) {
     pp.logL[k] = rest / pp.P + (k < rest % pp.P ? 1 : 0);
     pp.logS[k] = ls;
-    pp.logC[k] = std::min(13 - pp.logL[k], ls - pp.logL[k]);   // tile L x C <= 2^13 words
+    pp.logC[k] = std::min(logT - pp.logL[k], ls - pp.logL[k]);   // tile L x C <= 2^logT words
     ls -= pp.logL[k];
   }
   return pp;
@@ -971,7 +971,9 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     X.launches++;
     return CAT_OK;
   }
-  const PassPlan pp = pass_plan(s.logN, s.logM, s.maxL);
+  // column tiles: the smaller size when the stage cannot fill the GPU
+  const int logT = ((double)cnt * (double)(1ull << s.logN) < 4194304.0) ? NTT_COL_LOGT_SMALL : NTT_COL_LOGT;
+  const PassPlan pp = pass_plan(s.logN, s.logM, s.maxL, logT);
   const int logM = s.logM, logR1 = s.logN - logM;
   const double N = (double)(1ull << s.logN);
   for (int k = 0; k < pp.P; k++) {
@@ -979,8 +981,12 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
     // L-point DFTs of both operands, 3 primes: (N/2) log2 L butterflies each
     KTime kt("k_pass_fwd", X.st, 6.0 * cnt * N / 2 * pp.logL[k]);
-    hipLaunchKernelGGL(k_pass_fwd, dim3((uint32_t)gx, CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st, dv, pg,
-                       k == 0 ? 1 : 0, ain, bin, X.F, tb);
+    if (logT == NTT_COL_LOGT_SMALL)
+      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, dim3((uint32_t)gx, CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0,
+                         X.st, dv, pg, k == 0 ? 1 : 0, ain, bin, X.F, tb);
+    else
+      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, dim3((uint32_t)gx, CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st,
+                         dv, pg, k == 0 ? 1 : 0, ain, bin, X.F, tb);
     LAUNCHCHK();
   }
   {
@@ -1001,8 +1007,12 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
     const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
     KTime kt("k_pass_inv", X.st, 3.0 * cnt * N / 2 * pp.logL[k]);
-    hipLaunchKernelGGL(k_pass_inv, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv, pg,
-                       k == 0 ? 1 : 0, X.F, X.res, X.res_stride, tb);
+    if (logT == NTT_COL_LOGT_SMALL)
+      hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT_SMALL>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st,
+                         dv, pg, k == 0 ? 1 : 0, X.F, X.res, X.res_stride, tb);
+    else
+      hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
+                         pg, k == 0 ? 1 : 0, X.F, X.res, X.res_stride, tb);
     LAUNCHCHK();
   }
   X.launches += 2 * pp.P + 1;

@@ -387,7 +387,11 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
 // Scratch F: per product, per prime, per operand N words:
 //   F[((m*3 + prime)*2 + op)*N + position]
 #define NTT_COL_THREADS 256
-#define NTT_COL_TILE 8192u      // LDS words of a column tile (32 KB: 4 workgroups per CU)
+// Column tiles hold 2^NTT_COL_LOGT words (32 KB, 4 workgroups per CU) on large
+// stages and 2^NTT_COL_LOGT_SMALL on stages too small to fill the GPU (twice
+// the workgroups, twice as many resident).
+#define NTT_COL_LOGT 13
+#define NTT_COL_LOGT_SMALL 12
 #define NTT_COL_MAXL 10         // longest column DFT: 2^10 points
 #define COL_BATCH 16            // global loads a thread keeps in flight in the column kernels
 #define TW2_LO_BITS 14u
@@ -429,10 +433,11 @@ struct PassGeom {
   }
 };
 
+template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
            uint32_t* __restrict__ F, NttTables tb) {
-  __shared__ uint32_t lds[NTT_COL_TILE];
+  __shared__ uint32_t lds[1u << LOGT];
   const uint32_t prime = blockIdx.y, op = blockIdx.z;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
@@ -513,11 +518,13 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
   }
 }
 
+template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_t* __restrict__ res,
            uint64_t res_stride, NttTables tb) {
-  __shared__ uint32_t lds[NTT_COL_TILE];
-  __shared__ uint32_t fq[1u << NTT_COL_MAXL];   // frequency at each output row
+  __shared__ uint32_t lds[1u << LOGT];
+  __shared__ uint32_t fq[1u << NTT_COL_MAXL];    // frequency at each output row
+  const uint32_t T = 1u << (pg.logL + pg.logC);
   const uint32_t prime = blockIdx.y;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
@@ -527,7 +534,6 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
   const int logSig = pg.logS - pg.logL;
   const uint32_t C = 1u << pg.logC;
   const uint64_t N = 1ull << pg.logN;
-  const uint32_t T = 1u << (pg.logL + pg.logC);
   uint32_t* f = F + ((m * 3 + prime) * 2 + 0) * N;
   const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
