@@ -7,6 +7,10 @@
 #define DEC_B 1000000000u
 #define DEC_LEAF_LIMBS 16
 #define DEC_LEAF_DIGITS 18         // 2^512 < 10^162
+// digits per thread of the radix-B carry step (>= 4: a thread's first sum
+// reaches four positions back) and per workgroup
+#define DEC_CRT_E 4
+#define DEC_CRT_BLOCK (DEC_CRT_E * CAT_CRT_THREADS)
 
 // floor((r * 2^32 + w) / 10^9) and its remainder, for r < 10^9 (so the
 // quotient fits 32 bits): two-by-one division with a precomputed reciprocal
@@ -79,13 +83,13 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
                                             const uint32_t* __restrict__ add, uint64_t kb, uint32_t (*xv)[DEC_XV],
                                             uint32_t* tmp, uint64_t* u, bool* Gt, bool* Pt) {
   const uint32_t tid = threadIdx.x;
-  const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
+  const uint64_t k0 = kb + (uint64_t)tid * DEC_CRT_E;
   // c[i][.] for positions k0-4+i (i < 4 from the neighbour, own from i = 4)
-  uint32_t c[CAT_CRT_E + 4][4];
+  uint32_t c[DEC_CRT_E + 4][4];
   {
-    uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E], xa[CAT_CRT_E];
+    uint32_t x0[DEC_CRT_E], x1[DEC_CRT_E], x2[DEC_CRT_E], xa[DEC_CRT_E];
 #pragma unroll
-    for (int i = 0; i < CAT_CRT_E; i++) {
+    for (int i = 0; i < DEC_CRT_E; i++) {
       const uint64_t k = k0 + i;
       const uint64_t kc = k < sg.len ? k : 0;
       x0[i] = r0[kc];
@@ -94,7 +98,7 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
       xa[i] = add[sg.add_pos + (k < sg.add_len ? k : 0)];
     }
 #pragma unroll
-    for (int i = 0; i < CAT_CRT_E; i++) {
+    for (int i = 0; i < DEC_CRT_E; i++) {
       const uint64_t k = k0 + i;
       if (k < sg.len) {
         dec_split(x0[i], x1[i], x2[i], k < sg.add_len ? xa[i] : 0u, c[i + 4]);
@@ -106,7 +110,7 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
   __syncthreads();   // xv may still be read by a previous call
   {
     uint32_t* o = xv[tid + 1];
-    const int e = CAT_CRT_E;
+    const int e = DEC_CRT_E;
     o[0] = c[e + 3][0]; o[1] = c[e + 3][1]; o[2] = c[e + 3][2]; o[3] = c[e + 3][3];
     o[4] = c[e + 2][1]; o[5] = c[e + 2][2]; o[6] = c[e + 2][3];
     o[7] = c[e + 1][2]; o[8] = c[e + 1][3];
@@ -135,7 +139,7 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
   uint32_t yprev = (s >= DEC_B) + (s >= 2 * DEC_B) + (s >= 3 * DEC_B);
   bool G = false, P = true;
 #pragma unroll
-  for (int i = 0; i < CAT_CRT_E; i++) {
+  for (int i = 0; i < DEC_CRT_E; i++) {
     s = c[i + 4][0] + c[i + 3][1] + c[i + 2][2] + c[i + 1][3];
     const uint32_t y = (s >= DEC_B) + (s >= 2 * DEC_B) + (s >= 3 * DEC_B);
     u[i] = (uint64_t)(s - y * DEC_B) + yprev;
@@ -174,8 +178,8 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
   const uint32_t* r0 = res + sg.res_pos;
   const uint32_t* r1 = r0 + res_stride;
   const uint32_t* r2 = r1 + res_stride;
-  const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
-  uint64_t u[CAT_CRT_E];
+  const uint64_t kb = (uint64_t)(b - first) * DEC_CRT_BLOCK;
+  uint64_t u[DEC_CRT_E];
   bool G, P;
   crt_local10(sg, r0, r1, r2, add, kb, xv, tmp, u, &G, &P);
   const uint32_t own = crt_block_pair(tmp);
@@ -201,9 +205,9 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
     uint32_t pair = s_pair;
     __syncthreads();
     if (state == 2u) {
-      uint64_t u2[CAT_CRT_E];
+      uint64_t u2[DEC_CRT_E];
       bool G2, P2;
-      crt_local10(sg, r0, r1, r2, add, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      crt_local10(sg, r0, r1, r2, add, (uint64_t)(k - first) * DEC_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
       pair = crt_block_pair(tmp2);
     }
     if (pair & 1u) { cin = 1; done = true; }
@@ -221,9 +225,9 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
   bool ap;
   uint32_t c = wave_carry(G, P, wc, &cout, &ap);
   uint32_t* o = out + sg.out_pos;
-  const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
+  const uint64_t k0 = kb + (uint64_t)tid * DEC_CRT_E;
 #pragma unroll
-  for (int i = 0; i < CAT_CRT_E; i++) {
+  for (int i = 0; i < DEC_CRT_E; i++) {
     const uint64_t kk = k0 + i;
     const uint32_t t = (uint32_t)u[i] + c;
     c = t >= DEC_B;

@@ -51,7 +51,7 @@ Stage dec_stage(uint64_t nmul, const UniDesc& u, uint64_t d0, uint64_t sd, uint6
   s.dv.uni = 1;
   s.dv.u = u;
   s.sv = SegView{};
-  s.sv.ubl = (uint32_t)((len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
+  s.sv.ubl = (uint32_t)((len + DEC_CRT_BLOCK - 1) / DEC_CRT_BLOCK);
   s.sv.nseg = (uint32_t)nmul;
   s.sv.iseg[0] = CrtSeg{u.c0, 0, len, d0, ld};
   s.sv.ustep[0] = u.sc;

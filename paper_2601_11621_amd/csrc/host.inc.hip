@@ -919,7 +919,7 @@ cat_status launch_crt10(Exec& X, uint32_t* out, const SegView& sv, uint32_t nblk
   const uint32_t grid = nblk + tail_blocks(*tails);
   if (grid == 0) return CAT_OK;
   {
-    KTime kt("k_crt10", X.st, (double)nblk * CAT_CRT_BLOCK);
+    KTime kt("k_crt10", X.st, (double)nblk * DEC_CRT_BLOCK);
     X.crt_epoch++;
     hipLaunchKernelGGL(k_crt10, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.W, nblk,
                        X.flags, X.crt_epoch, g_crt_polls, *tails, tin, tout, X.err);
