@@ -127,8 +127,9 @@ cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, c
  * if d_out is NULL or cap < D (nothing written), or if n_limbs > 2^27.
  * decimal_sizes: host only; an upper bound on D and the workspace bytes.
  * bigint_to_decimal: d_work of at least that many bytes (device, caller-owned,
- * contents undefined afterwards); synchronises `stream`; CAT_EINTERNAL if a
- * device check failed. */
+ * contents undefined afterwards; CAT_ENOMEM if smaller); d_x, d_out and d_work
+ * must not overlap; synchronises `stream`; CAT_EINTERNAL if a device check
+ * failed. */
 cat_status decimal_sizes(size_t n_limbs, size_t* max_chars, size_t* workspace_bytes);
 cat_status bigint_to_decimal(const uint32_t* d_x, size_t n_limbs, char* d_out, size_t cap, size_t* n_chars,
                              void* d_work, size_t work_bytes, void* stream);
