@@ -258,7 +258,9 @@ uint2 scale_pair(int prime, int logN) {
 // ----------------------------------------------------------------------------
 // Stages: one batch of products of one class.
 // ----------------------------------------------------------------------------
-enum { CLS_SCHOOL = 0, CLS_LDS = 1, CLS_LARGE = 2 };
+// CLS_COLSUM: a long operand times a short one by exact column sums (only
+// chosen by the planner of the outer products, never by the tuning table).
+enum { CLS_SCHOOL = 0, CLS_LDS = 1, CLS_LARGE = 2, CLS_COLSUM = 3 };
 
 // Schedule per transform-length bucket 2^k (set by the autotuner, or defaults).
 cat_tuning default_tuning() {
@@ -608,13 +610,28 @@ inline uint64_t cap_of(uint64_t alloc, uint64_t bits) {
   return std::max<uint64_t>(1, std::min<uint64_t>(alloc, (bits + 31) / 32));
 }
 
+// A long times a short operand whose transform would take the four-step
+// path: column sums cost la lb 32x32 products (about six VALU instructions
+// each) in one pass; the transform costs 9 (N/2) log2 N butterflies (about 14
+// each) in four launches of a lone product.  Column sums when they need no
+// more instructions than the transform.
+bool colsum_wins(uint64_t la, uint64_t lb, const Cls& c) {
+  if (c.cls != CLS_LARGE || lb > COLSUM_MAX_LB || la < 8 * lb) return false;
+  const double cs = 6.0 * (double)la * (double)lb;
+  const double ntt = 14.0 * 9.0 * 0.5 * (double)(1ull << c.logN) * c.logN;
+  return cs <= ntt;
+}
+
 void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vector<Item>& outs) {
   // group the products of one step by class; positions already assigned
   std::map<std::pair<int, int>, Stage> by;
   uint64_t rpos = 0;
   for (size_t k = 0; k < pairs.size(); k++) {
-    const Item a = pairs[k].first, b = pairs[k].second, c = outs[k];
-    const Cls cc = classify2(a.cap, b.cap);
+    Item a = pairs[k].first, b = pairs[k].second;
+    const Item c = outs[k];
+    Cls cc = classify2(a.cap, b.cap);
+    if (a.cap < b.cap) std::swap(a, b);   // a: the longer operand
+    if (colsum_wins(a.cap, b.cap, cc)) cc = Cls{CLS_COLSUM, 0, 0, 0};
     Stage& s = by[{cc.cls, cc.logN}];
     s.cls = cc.cls;
     s.logN = cc.logN;
@@ -897,7 +914,7 @@ struct Exec {
 };
 
 cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const CopyList* tails = nullptr,
-                      const uint32_t* tin = nullptr, uint32_t* tout = nullptr) {
+                      const uint32_t* tin = nullptr, uint32_t* tout = nullptr, bool raw = false) {
   static const CopyList none{};
   const CopyList& cl = tails ? *tails : none;
   const uint32_t grid = nblk + tail_blocks(cl);
@@ -905,8 +922,12 @@ cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const C
   {
     KTime kt("k_crt", X.st, (double)nblk * CAT_CRT_BLOCK);
     X.crt_epoch++;
-    hipLaunchKernelGGL(k_crt, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk, X.flags,
-                       X.crt_epoch, g_crt_polls, cl, tin, tout, X.err);
+    if (raw)
+      hipLaunchKernelGGL(k_crt<true>, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk,
+                         X.flags, X.crt_epoch, g_crt_polls, cl, tin, tout, X.err);
+    else
+      hipLaunchKernelGGL(k_crt<false>, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk,
+                         X.flags, X.crt_epoch, g_crt_polls, cl, tin, tout, X.err);
   }
   LAUNCHCHK();
   X.launches++;
@@ -948,6 +969,19 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     }
     LAUNCHCHK();
     X.launches++;
+    return CAT_OK;
+  }
+  if (s.cls == CLS_COLSUM) {
+    // one launch per product (the stage holds its descriptors on the host)
+    for (uint64_t i = 0; i < cnt; i++) {
+      const MulDesc d = dv.ninl ? dv.inl[i] : s.host_desc[i];
+      const uint32_t L = d.la + d.lb;
+      KTime kt("k_colsum", X.st, (double)d.la * d.lb);
+      hipLaunchKernelGGL(k_colsum, dim3((L + COLSUM_COLS - 1) / COLSUM_COLS), dim3(256), 0, X.st, ain + d.a_off, d.la,
+                         bin + d.b_off, d.lb, X.res + d.r_off, X.res_stride, L);
+      LAUNCHCHK();
+      X.launches++;
+    }
     return CAT_OK;
   }
   const NttTables tb = tables_for(s.logN);
@@ -1055,7 +1089,7 @@ cat_status run_stage_batched(Exec& X, const Stage& s) {
     STCHK(launch_products(X, s, s.dv, s.nmul, s.cls == CLS_SCHOOL));
     if (s.cls != CLS_SCHOOL)
       STCHK(launch_crt(X, out_base(X, s), stage_segs(s), s.nblk, &s.tails, X.W + s.tail_in_base,
-                       X.W + s.tail_out_base));
+                       X.W + s.tail_out_base, s.cls == CLS_COLSUM));
     return CAT_OK;
   }
   return copy_tails(X, s);
@@ -1091,7 +1125,7 @@ cat_status run_stage_plain(Exec& X, const Stage& s) {
       const uint32_t nb = (uint32_t)((sv.iseg[0].len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
       sv.ipref[0] = 0;
       sv.ipref[1] = nb;
-      STCHK(launch_crt(X, out_base(X, s), sv, nb));
+      STCHK(launch_crt(X, out_base(X, s), sv, nb, nullptr, nullptr, nullptr, s.cls == CLS_COLSUM));
     }
   }
   return copy_tails(X, s);

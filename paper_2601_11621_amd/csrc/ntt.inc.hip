@@ -731,8 +731,12 @@ struct SegView {
 // (nothing is assumed about which workgroups run at the same time).
 #define CAT_SCAN_POLLS 16   // default number of polls of a predecessor's flag
 
-// Garner values of this thread's CAT_CRT_E positions of the block starting at
-// kb, their sums u and the thread's (G, P); wave pairs go to tmp[wave].
+// Values V of this thread's CAT_CRT_E positions of the block starting at kb,
+// their sums u and the thread's (G, P); wave pairs go to tmp[wave].  V is
+// Garner's recombination of the three residues, or (RAW) the three words
+// themselves when they already hold V = v0 + v1 2^32 + v2 2^64 (exact column
+// sums of a schoolbook product).
+template <bool RAW>
 __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __restrict__ r0,
                                           const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
                                           uint64_t kb, uint32_t (*xv)[9], uint32_t* tmp, uint64_t* u, bool* Gt,
@@ -756,7 +760,15 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
     }
 #pragma unroll
     for (int i = 0; i < CAT_CRT_E; i++) {
-      if (k0 + i < sg.len) garner3(x0[i], x1[i], x2[i], v0[i + 3], v1[i + 3], v2[i + 3]);
+      if (k0 + i < sg.len) {
+        if constexpr (RAW) {
+          v0[i + 3] = x0[i];
+          v1[i + 3] = x1[i];
+          v2[i + 3] = x2[i];
+        } else {
+          garner3(x0[i], x1[i], x2[i], v0[i + 3], v1[i + 3], v2[i + 3]);
+        }
+      }
       else { v0[i + 3] = 0; v1[i + 3] = 0; v2[i + 3] = 0; }
     }
   }
@@ -772,7 +784,15 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
     for (int i = 0; i < 3; i++) {
       const int64_t k = (int64_t)kb + i - 3;
       uint32_t a0 = 0, a1 = 0, a2 = 0;
-      if (k >= 0) garner3(r0[k], r1[k], r2[k], a0, a1, a2);
+      if (k >= 0) {
+        if constexpr (RAW) {
+          a0 = r0[k];
+          a1 = r1[k];
+          a2 = r2[k];
+        } else {
+          garner3(r0[k], r1[k], r2[k], a0, a1, a2);
+        }
+      }
       xv[0][3 * i + 0] = a0;
       xv[0][3 * i + 1] = a1;
       xv[0][3 * i + 2] = a2;
@@ -816,6 +836,7 @@ __device__ __forceinline__ uint32_t crt_block_pair(const uint32_t* tmp) {
   return bG | (bP << 1);
 }
 
+template <bool RAW>
 __global__ void __launch_bounds__(CAT_CRT_THREADS)
 k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out, uint32_t nblk,
       uint32_t* __restrict__ flags, uint32_t epoch, uint32_t polls, CopyList tails, const uint32_t* __restrict__ tin,
@@ -837,7 +858,7 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
   const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
   uint64_t u[CAT_CRT_E];
   bool G, P;
-  crt_local(sg, r0, r1, r2, kb, xv, tmp, u, &G, &P);
+  crt_local<RAW>(sg, r0, r1, r2, kb, xv, tmp, u, &G, &P);
   const uint32_t own = crt_block_pair(tmp);
   if (tid == 0)
     __hip_atomic_store(flags + b, (epoch << 3) | (own << 1) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -865,7 +886,7 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
       // not published yet: recompute block k's pair from its residues
       uint64_t u2[CAT_CRT_E];
       bool G2, P2;
-      crt_local(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      crt_local<RAW>(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
       pair = crt_block_pair(tmp2);
     }
     if (pair & 1u) { cin = 1; done = true; }           // block k generates a carry

@@ -55,6 +55,62 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
 // Schoolbook products, la, lb <= 128.  4 waves per block, one product each;
 // blocks from ceil(nmul / 4) on copy the tail ranges.
 #define SCHOOL_MAX 128
+// ---------------------------------------------------------------------------
+// Long times short (lb <= COLSUM_MAX_LB limbs, la >> lb): the exact column sums
+// V(k) = sum_j a[k-j] b[j] (< lb 2^64 < 2^96) for k < la + lb, written as three
+// words to the residue rows (v0, v1, v2 at r[0], r[stride], r[2 stride]); the
+// raw mode of the CRT kernel then propagates the carries.  A block of 256
+// threads covers COLSUM_E * 256 consecutive columns; it stages the operand
+// window a[k0 - lb + 1, k0 + COLSUM_E * 256) and b in LDS, and each thread slides
+// a window of COLSUM_E values of a down j.
+#define COLSUM_MAX_LB 1024
+#define COLSUM_E 4
+#define COLSUM_COLS (COLSUM_E * 256)
+__global__ void __launch_bounds__(256) k_colsum(const uint32_t* __restrict__ a, uint32_t la, const uint32_t* __restrict__ b,
+                                                uint32_t lb, uint32_t* __restrict__ r, uint64_t stride, uint32_t L) {
+  __shared__ uint32_t sw[COLSUM_COLS + COLSUM_MAX_LB];   // a[kb - lb + 1 + i]
+  __shared__ uint32_t sbv[COLSUM_MAX_LB];
+  const uint32_t kb = blockIdx.x * COLSUM_COLS, tid = threadIdx.x;
+  const uint32_t wn = COLSUM_COLS + lb - 1;
+  for (uint32_t i = tid; i < wn; i += 256) {
+    const int64_t idx = (int64_t)kb - (int64_t)lb + 1 + i;
+    sw[i] = (idx >= 0 && idx < (int64_t)la) ? a[idx] : 0u;
+  }
+  for (uint32_t i = tid; i < lb; i += 256) sbv[i] = b[i];
+  __syncthreads();
+  // column k = kb + COLSUM_E tid + e takes a[k - j] = sw[k - j - kb + lb - 1]
+  const uint32_t c0 = COLSUM_E * tid + lb - 1;   // sw index of a[k0], k0 = kb + COLSUM_E tid
+  uint32_t w[COLSUM_E];
+#pragma unroll
+  for (int e = 0; e < COLSUM_E; e++) w[e] = sw[c0 + e];
+  uint64_t lo[COLSUM_E], hi[COLSUM_E];
+#pragma unroll
+  for (int e = 0; e < COLSUM_E; e++) lo[e] = hi[e] = 0;
+  for (uint32_t j = 0; j < lb; j++) {
+    const uint32_t bj = sbv[j];
+#pragma unroll
+    for (int e = 0; e < COLSUM_E; e++) {
+      const uint64_t pr = (uint64_t)w[e] * bj;
+      lo[e] += (uint32_t)pr;
+      hi[e] += (uint32_t)(pr >> 32);
+    }
+    // next j: every column moves one position down a
+#pragma unroll
+    for (int e = COLSUM_E - 1; e > 0; e--) w[e] = w[e - 1];
+    w[0] = j + 1 < lb ? sw[c0 - j - 1] : 0u;
+  }
+  const uint32_t k0 = kb + COLSUM_E * tid;
+#pragma unroll
+  for (int e = 0; e < COLSUM_E; e++) {
+    if (k0 + e >= L) break;
+    // V = lo + hi 2^32 with lo, hi < 2^42
+    const uint64_t m = (lo[e] >> 32) + (hi[e] & 0xFFFFFFFFull);
+    r[k0 + e] = (uint32_t)lo[e];
+    r[stride + k0 + e] = (uint32_t)m;
+    r[2 * stride + k0 + e] = (uint32_t)((m >> 32) + (hi[e] >> 32));
+  }
+}
+
 #define SCHOOL_WAVES 4
 __global__ void __launch_bounds__(64 * SCHOOL_WAVES)
 k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
