@@ -164,6 +164,17 @@ def test_exact_vs_oracle(cat, n):
         assert np.array_equal(got, exp), mode
 
 
+def test_exact_random_n_vs_oracle(cat):
+    """Seeded random n spread over the sizes where the schedule changes
+    (schoolbook, LDS tiles, four-step levels, small and large column tiles,
+    the column-sum product by R)."""
+    rng = np.random.default_rng(20260)
+    ns = sorted(set(int(x) for x in np.exp(rng.uniform(np.log(300), np.log(400000), 24)).astype(np.int64)))
+    for n in ns:
+        _say("exact random", n)
+        assert np.array_equal(cat.to_numpy(cat.exact(n, mode="graph")), oracle.catalan(n)), n
+
+
 def test_exact_1e6_vs_oracle(cat):
     exp = oracle.catalan(10**6)
     got = cat.to_numpy(cat.exact(10**6, mode="graph"))
