@@ -697,7 +697,8 @@ struct SegView {
   // uniform: segment s is iseg[0] with out_pos, res_pos and add_pos advanced
   // by s * ustep[0], s * iseg[0].len and s * ustep[1]
   uint64_t ustep[2];
-  __device__ __forceinline__ void find(uint32_t b, CrtSeg* sg, uint32_t* first, uint32_t* end) const {
+  __device__ __forceinline__ void find(uint32_t b, CrtSeg* sg, uint32_t* first, uint32_t* end,
+                                       uint32_t* segi = nullptr) const {
     if (ubl) {
       const uint32_t q = b / ubl;
       *sg = iseg[0];
@@ -706,6 +707,7 @@ struct SegView {
       sg->add_pos += q * ustep[1];
       *first = q * ubl;
       *end = *first + ubl;
+      if (segi) *segi = q;
       return;
     }
     const uint32_t* pr = segs ? pref : ipref;
@@ -717,6 +719,7 @@ struct SegView {
     *sg = segs ? segs[lo] : iseg[lo];
     *first = pr[lo];
     *end = pr[lo + 1];
+    if (segi) *segi = lo;
   }
 };
 

@@ -56,21 +56,39 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
 // blocks from ceil(nmul / 4) on copy the tail ranges.
 #define SCHOOL_MAX 128
 // ---------------------------------------------------------------------------
-// Long times short (lb <= COLSUM_MAX_LB limbs, la >> lb): the exact column sums
-// V(k) = sum_j a[k-j] b[j] (< lb 2^64 < 2^96) for k < la + lb, written as three
-// words to the residue rows (v0, v1, v2 at r[0], r[stride], r[2 stride]); the
-// raw mode of the CRT kernel then propagates the carries.  A block of 256
-// threads covers COLSUM_E * 256 consecutive columns; it stages the operand
-// window a[k0 - lb + 1, k0 + COLSUM_E * 256) and b in LDS, and each thread slides
-// a window of COLSUM_E values of a down j.
+// Long times short (the shorter operand <= COLSUM_MAX_LB limbs): the exact
+// column sums V(k) = sum_j a[k-j] b[j] (< 2^74) for k < la + lb, written as
+// three words to the residue rows (v0, v1, v2 at r[k], r[stride + k],
+// r[2 stride + k]); the raw mode of the CRT kernel then propagates the carries.
+// Workgroup b covers the CRT block b (COLSUM_COLS = CAT_CRT_BLOCK columns of
+// one product, found with the stage's segment map); it stages the window
+// a[k0 - lb + 1, k0 + COLSUM_COLS) and b in LDS, and each thread slides a
+// window of COLSUM_E values of a down j.
 #define COLSUM_MAX_LB 1024
-#define COLSUM_E 4
+#define COLSUM_E CAT_CRT_E
 #define COLSUM_COLS (COLSUM_E * 256)
-__global__ void __launch_bounds__(256) k_colsum(const uint32_t* __restrict__ a, uint32_t la, const uint32_t* __restrict__ b,
-                                                uint32_t lb, uint32_t* __restrict__ r, uint64_t stride, uint32_t L) {
+static_assert(COLSUM_COLS == CAT_CRT_BLOCK, "column-sum blocks are the CRT blocks");
+__global__ void __launch_bounds__(256) k_colsum(DescView dv, SegView sv, const uint32_t* __restrict__ ain,
+                                                const uint32_t* __restrict__ bin, uint32_t* __restrict__ res,
+                                                uint64_t stride, uint32_t* __restrict__ err) {
   __shared__ uint32_t sw[COLSUM_COLS + COLSUM_MAX_LB];   // a[kb - lb + 1 + i]
   __shared__ uint32_t sbv[COLSUM_MAX_LB];
-  const uint32_t kb = blockIdx.x * COLSUM_COLS, tid = threadIdx.x;
+  CrtSeg sg;
+  uint32_t first, end, si;
+  sv.find(blockIdx.x, &sg, &first, &end, &si);
+  const MulDesc d = dv.get(si);
+  // the longer operand slides, the shorter one is the kernel of the sums
+  const bool sw_ab = d.la < d.lb;
+  const uint32_t* a = sw_ab ? bin + d.b_off : ain + d.a_off;
+  const uint32_t* b = sw_ab ? ain + d.a_off : bin + d.b_off;
+  const uint32_t la = sw_ab ? d.lb : d.la, lb = sw_ab ? d.la : d.lb;
+  const uint32_t tid = threadIdx.x;
+  if (lb > COLSUM_MAX_LB) {
+    if (tid == 0) atomicOr(err, CAT_DEVERR_BOUNDS);
+    return;
+  }
+  const uint32_t L = la + lb;
+  const uint32_t kb = (blockIdx.x - first) * COLSUM_COLS;
   const uint32_t wn = COLSUM_COLS + lb - 1;
   for (uint32_t i = tid; i < wn; i += 256) {
     const int64_t idx = (int64_t)kb - (int64_t)lb + 1 + i;
@@ -78,8 +96,8 @@ __global__ void __launch_bounds__(256) k_colsum(const uint32_t* __restrict__ a, 
   }
   for (uint32_t i = tid; i < lb; i += 256) sbv[i] = b[i];
   __syncthreads();
-  // column k = kb + COLSUM_E tid + e takes a[k - j] = sw[k - j - kb + lb - 1]
-  const uint32_t c0 = COLSUM_E * tid + lb - 1;   // sw index of a[k0], k0 = kb + COLSUM_E tid
+  // column k = kb + COLSUM_E tid + e takes a[k - j] = sw[c0 + e - j]
+  const uint32_t c0 = COLSUM_E * tid + lb - 1;
   uint32_t w[COLSUM_E];
 #pragma unroll
   for (int e = 0; e < COLSUM_E; e++) w[e] = sw[c0 + e];
@@ -99,6 +117,7 @@ __global__ void __launch_bounds__(256) k_colsum(const uint32_t* __restrict__ a, 
     for (int e = COLSUM_E - 1; e > 0; e--) w[e] = w[e - 1];
     w[0] = j + 1 < lb ? sw[c0 - j - 1] : 0u;
   }
+  uint32_t* r = res + sg.res_pos;
   const uint32_t k0 = kb + COLSUM_E * tid;
 #pragma unroll
   for (int e = 0; e < COLSUM_E; e++) {

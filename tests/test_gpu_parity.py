@@ -105,6 +105,32 @@ def test_mul_large_fourstep(cat):
     _run_batch(cat, la, lb, kinds, "batched", seed=5)
 
 
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_mul_long_by_short(cat, mode):
+    """Long-by-short products (the shorter operand up to 1,024 limbs) that the
+    schedule may take by exact column sums: the all-ones worst case for the
+    column sums (1,024 full products of (2^32 - 1)^2 per column), both operand
+    orders, ragged ends of the 768-column blocks, and a random mix beside
+    products of other classes in the same batch."""
+    rng = np.random.default_rng(21)
+    la = [65536, 1024, 8199, 50000, 9000, 1, 30000, 12345, 769, 40000]
+    lb = [1024, 65536, 1024, 513, 1, 9001, 1000, 1000, 20000, 40]
+    kinds = ["ones", "ones", "rand", "rand", "ones", "rand", "ones", "rand", "rand", "zero"]
+    for _ in range(24):
+        x = int(np.rint(2 ** rng.uniform(13, 16)))
+        y = int(np.rint(2 ** rng.uniform(0, 10)))
+        if rng.random() < 0.5:
+            x, y = y, x
+        la.append(x)
+        lb.append(y)
+        kinds.append("rand")
+    # neighbours of other classes (schoolbook, one-workgroup, four-step)
+    la += [100, 3000, 70000]
+    lb += [90, 2500, 60000]
+    kinds += ["rand", "rand", "rand"]
+    _run_batch(cat, la, lb, kinds, mode, seed=22)
+
+
 def test_mul_random_batch_uneven(cat):
     rng = np.random.default_rng(7)
     la = np.rint(2 ** rng.uniform(0, 13, 300)).astype(np.int64).tolist()
