@@ -611,17 +611,18 @@ inline uint64_t cap_of(uint64_t alloc, uint64_t bits) {
 }
 
 // A long times a short operand whose transform would take the four-step
-// path: column sums cost la lb 32x32 products (about six VALU instructions
-// each) in one pass; the transform costs 9 (N/2) log2 N butterflies (about 14
-// each) in four launches of a lone product.  Measured, the column sums issue
-// at about twice the rate of a lone four-step product (C(10^8): 0.56 against
-// 0.75 ms for 1.6 times the instructions), so they are chosen up to 1.8 times
-// the transform's instruction count.
+// path: column sums cost la lb 32x32 multiply-adds (two VALU instructions
+// each, about 2.5 with the window's shifts and LDS reads) in one pass; the
+// transform costs 9 (N/2) log2 N butterflies (about 14 each) in four launches
+// per product.  The column sums are chosen up to 1.25 times the transform's
+// instruction count: on a batch of 4,096 uneven products the time is 4.64,
+// 4.54, 4.55 and 4.56 ms at 0.75, 1.25, 1.9 and 2.9; C(10^7) and C(10^8) are
+// flat over that range.
 bool colsum_wins(uint64_t la, uint64_t lb, const Cls& c) {
   if (c.cls != CLS_LARGE || lb > COLSUM_MAX_LB || la < 8 * lb) return false;
-  const double cs = 6.0 * (double)la * (double)lb;
+  const double cs = 2.5 * (double)la * (double)lb;
   const double ntt = 14.0 * 9.0 * 0.5 * (double)(1ull << c.logN) * c.logN;
-  return cs <= 1.8 * ntt;
+  return cs <= 1.25 * ntt;
 }
 
 void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vector<Item>& outs) {
@@ -1307,8 +1308,6 @@ cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t
       return CAT_EINVAL;
     }
     Cls cc = classify2(la, lb);
-    // in a batch of uneven products the optimum is flat between factors 1 and
-    // 2 (a 4,096-product batch: 4.95 ms at 1.0, 4.90 ms at 2.0, 5.10 at 4.0)
     if (colsum_wins(std::max(la, lb), std::min(la, lb), cc)) cc = Cls{CLS_COLSUM, 0, 0, 0};
     Stage& st = by[{cc.cls, cc.logN}];
     st.cls = cc.cls;

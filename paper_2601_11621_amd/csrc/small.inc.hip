@@ -62,71 +62,97 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
 // r[2 stride + k]); the raw mode of the CRT kernel then propagates the carries.
 // Workgroup b covers the CRT block b (COLSUM_COLS = CAT_CRT_BLOCK columns of
 // one product, found with the stage's segment map); it stages the window
-// a[k0 - lb + 1, k0 + COLSUM_COLS) and b in LDS, and each thread slides a
-// window of COLSUM_E values of a down j.
+// a[kb - lb, kb + COLSUM_COLS) and b in LDS, and each thread slides a window of
+// COLSUM_E values of a down j.  Each column keeps a 64-bit sum and a count of
+// its carries out of bit 64 (at most lb), one multiply-add and one add-carry
+// per 32x32 product.
 #define COLSUM_MAX_LB 1024
 #define COLSUM_E CAT_CRT_E
 #define COLSUM_COLS (COLSUM_E * 256)
 static_assert(COLSUM_COLS == CAT_CRT_BLOCK, "column-sum blocks are the CRT blocks");
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+// acc_e += w_e * bj (64-bit, carry out of bit 64 counted in top_e) for three
+// columns: the carry of each multiply-add goes to a mask of its own and is
+// added two instructions after it was written
+__device__ __forceinline__ void colsum_mac3(uint64_t& a0, uint64_t& a1, uint64_t& a2, uint32_t& t0, uint32_t& t1,
+                                            uint32_t& t2, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t bj) {
+  uint64_t c0, c1, c2;
+  asm("v_mad_u64_u32 %0, %6, %9, %12, %0\n\t"
+      "v_mad_u64_u32 %1, %7, %10, %12, %1\n\t"
+      "v_mad_u64_u32 %2, %8, %11, %12, %2\n\t"
+      "v_addc_co_u32_e64 %3, %6, 0, %3, %6\n\t"
+      "v_addc_co_u32_e64 %4, %7, 0, %4, %7\n\t"
+      "v_addc_co_u32_e64 %5, %8, 0, %5, %8"
+      : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(t0), "+v"(t1), "+v"(t2), "=&s"(c0), "=&s"(c1), "=&s"(c2)
+      : "v"(w0), "v"(w1), "v"(w2), "v"(bj));
+}
+static_assert(COLSUM_E == 3, "colsum_mac3 covers three columns");
 __global__ void __launch_bounds__(256) k_colsum(DescView dv, SegView sv, const uint32_t* __restrict__ ain,
                                                 const uint32_t* __restrict__ bin, uint32_t* __restrict__ res,
                                                 uint64_t stride, uint32_t* __restrict__ err) {
-  __shared__ uint32_t sw[COLSUM_COLS + COLSUM_MAX_LB];   // a[kb - lb + 1 + i]
-  __shared__ uint32_t sbv[COLSUM_MAX_LB];
+  // lb rounded up to even (b padded with a zero limb); sw[t] = a[kb - lbe + t]
+  __shared__ uint32_t sw[COLSUM_COLS + COLSUM_MAX_LB];
+  __shared__ __align__(8) uint32_t sbv[COLSUM_MAX_LB];
   CrtSeg sg;
   uint32_t first, end, si;
   sv.find(blockIdx.x, &sg, &first, &end, &si);
-  const MulDesc d = dv.get(si);
+  const MulDesc d = dv.get(uni32(si));
   // the longer operand slides, the shorter one is the kernel of the sums
-  const bool sw_ab = d.la < d.lb;
-  const uint32_t* a = sw_ab ? bin + d.b_off : ain + d.a_off;
-  const uint32_t* b = sw_ab ? ain + d.a_off : bin + d.b_off;
-  const uint32_t la = sw_ab ? d.lb : d.la, lb = sw_ab ? d.la : d.lb;
+  const uint32_t da = uni32(d.la), db = uni32(d.lb);
+  const bool sw_ab = da < db;
+  const uint32_t* a = sw_ab ? bin + uni64(d.b_off) : ain + uni64(d.a_off);
+  const uint32_t* b = sw_ab ? ain + uni64(d.a_off) : bin + uni64(d.b_off);
+  const uint32_t la = sw_ab ? db : da, lb = sw_ab ? da : db;
   const uint32_t tid = threadIdx.x;
   if (lb > COLSUM_MAX_LB) {
     if (tid == 0) atomicOr(err, CAT_DEVERR_BOUNDS);
     return;
   }
   const uint32_t L = la + lb;
-  const uint32_t kb = (blockIdx.x - first) * COLSUM_COLS;
-  const uint32_t wn = COLSUM_COLS + lb - 1;
+  const uint32_t kb = (uni32(blockIdx.x) - uni32(first)) * COLSUM_COLS;
+  const uint32_t lbe = (lb + 1) & ~1u;
+  const uint32_t wn = COLSUM_COLS + lbe;
   for (uint32_t i = tid; i < wn; i += 256) {
-    const int64_t idx = (int64_t)kb - (int64_t)lb + 1 + i;
+    const int64_t idx = (int64_t)kb - (int64_t)lbe + i;
     sw[i] = (idx >= 0 && idx < (int64_t)la) ? a[idx] : 0u;
   }
-  for (uint32_t i = tid; i < lb; i += 256) sbv[i] = b[i];
+  for (uint32_t i = tid; i < lbe; i += 256) sbv[i] = i < lb ? b[i] : 0u;
   __syncthreads();
-  // column k = kb + COLSUM_E tid + e takes a[k - j] = sw[c0 + e - j]
-  const uint32_t c0 = COLSUM_E * tid + lb - 1;
+  // column k = kb + COLSUM_E tid + e takes a[k - j] = sw[c0 + e - j]; the
+  // reads for j + 1 and j + 2 at the last pair (down to sw[COLSUM_E tid])
+  // stay in the window
+  const uint32_t c0 = COLSUM_E * tid + lbe;
   uint32_t w[COLSUM_E];
 #pragma unroll
   for (int e = 0; e < COLSUM_E; e++) w[e] = sw[c0 + e];
-  uint64_t lo[COLSUM_E], hi[COLSUM_E];
+  uint64_t acc[COLSUM_E];
+  uint32_t top[COLSUM_E];
 #pragma unroll
-  for (int e = 0; e < COLSUM_E; e++) lo[e] = hi[e] = 0;
-  for (uint32_t j = 0; j < lb; j++) {
-    const uint32_t bj = sbv[j];
-#pragma unroll
-    for (int e = 0; e < COLSUM_E; e++) {
-      const uint64_t pr = (uint64_t)w[e] * bj;
-      lo[e] += (uint32_t)pr;
-      hi[e] += (uint32_t)(pr >> 32);
-    }
-    // next j: every column moves one position down a
-#pragma unroll
-    for (int e = COLSUM_E - 1; e > 0; e--) w[e] = w[e - 1];
-    w[0] = j + 1 < lb ? sw[c0 - j - 1] : 0u;
+  for (int e = 0; e < COLSUM_E; e++) {
+    acc[e] = 0;
+    top[e] = 0;
+  }
+  for (uint32_t j = 0; j < lbe; j += 2) {
+    const uint2 bj = *(const uint2*)&sbv[j];
+    const uint32_t wn1 = sw[c0 - j - 1], wn2 = sw[c0 - j - 2];
+    colsum_mac3(acc[0], acc[1], acc[2], top[0], top[1], top[2], w[0], w[1], w[2], bj.x);
+    // j + 1: every column moves one position down a
+    colsum_mac3(acc[0], acc[1], acc[2], top[0], top[1], top[2], wn1, w[0], w[1], bj.y);
+    w[2] = w[0];
+    w[1] = wn1;
+    w[0] = wn2;
   }
   uint32_t* r = res + sg.res_pos;
   const uint32_t k0 = kb + COLSUM_E * tid;
 #pragma unroll
   for (int e = 0; e < COLSUM_E; e++) {
     if (k0 + e >= L) break;
-    // V = lo + hi 2^32 with lo, hi < 2^42
-    const uint64_t m = (lo[e] >> 32) + (hi[e] & 0xFFFFFFFFull);
-    r[k0 + e] = (uint32_t)lo[e];
-    r[stride + k0 + e] = (uint32_t)m;
-    r[2 * stride + k0 + e] = (uint32_t)((m >> 32) + (hi[e] >> 32));
+    r[k0 + e] = (uint32_t)acc[e];
+    r[stride + k0 + e] = (uint32_t)(acc[e] >> 32);
+    r[2 * stride + k0 + e] = top[e];
   }
 }
 
