@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -120,9 +122,53 @@ def load_traffic(kernel, n):
     return t
 
 
+def _time_plan(plan, da, db, c, reps):
+    import torch
+
+    plan(da, db, c)
+    plan.check()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        plan(da, db, c)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    plan.check()
+    return sorted(ts)[len(ts) // 2] * 1e3
+
+
+def batch_buckets(cat, a, a_off, b, b_off, reps=5):
+    """The batch split by transform size (N = 2^ceil(log2(la + lb - 1)), at
+    least 2^6): each bucket alone as one graph replay, median of `reps`."""
+    import torch
+
+    la = (a_off[1:] - a_off[:-1]).astype(np.int64)
+    lb = (b_off[1:] - b_off[:-1]).astype(np.int64)
+    logn = np.maximum(6, np.ceil(np.log2(np.maximum(la + lb - 1, 1))).astype(np.int64))
+    out = {}
+    for k in sorted(set(logn.tolist())):
+        idx = np.nonzero(logn == k)[0]
+        sa = np.concatenate([a[int(a_off[i]):int(a_off[i + 1])] for i in idx])
+        sb = np.concatenate([b[int(b_off[i]):int(b_off[i + 1])] for i in idx])
+        oa = np.concatenate([[0], np.cumsum(la[idx])]).astype(np.uint64)
+        ob = np.concatenate([[0], np.cumsum(lb[idx])]).astype(np.uint64)
+        limbs = int((la[idx] + lb[idx]).sum())
+        da, db = cat.from_numpy(sa), cat.from_numpy(sb)
+        c = torch.empty(limbs, dtype=torch.int32, device="cuda")
+        g = cat.MulPlan(oa, ob, mode="graph")
+        ms = _time_plan(g, da, db, c, reps)
+        g.close()
+        out["2^%d" % k] = {"products": int(len(idx)), "product_limbs": limbs, "ms": round(ms, 4),
+                           "limbs_per_s": limbs / (ms / 1e3)}
+    return out
+
+
 def batch_bench(cat, steps):
     """The synthetic level-batch: 4,096 products, operand lengths log-uniform in
-    [64, 65536] limbs (uneven), one graph replay vs one product per launch."""
+    [64, 65536] limbs (uneven), one graph replay vs one product per launch;
+    then the same lengths with lb = la (balanced), and the uneven batch split
+    by transform size."""
     import torch
 
     from tests import batch_inputs
@@ -157,11 +203,58 @@ def batch_bench(cat, steps):
         raise SystemExit("bench: batched and plain level-batch products differ")
     g.close()
     p.close()
+    buckets = batch_buckets(cat, a, a_off, b, b_off)
+    # balanced variant: lb = la
+    a2, a2_off, b2, b2_off = batch_inputs.level_batch(seed=0, balanced=True)
+    limbs2 = int((a2_off[1:] - a2_off[:-1]).sum() * 2)
+    da2, db2 = cat.from_numpy(a2), cat.from_numpy(b2)
+    c3 = torch.empty(limbs2, dtype=torch.int32, device="cuda")
+    c4 = torch.empty_like(c3)
+    g2 = cat.MulPlan(a2_off, b2_off, mode="graph")
+    ms_b = _time_plan(g2, da2, db2, c3, steps)
+    p2 = cat.MulPlan(a2_off, b2_off, mode="plain")
+    p2(da2, db2, c4)
+    p2.check()
+    torch.cuda.synchronize()
+    if not torch.equal(c3, c4):
+        raise SystemExit("bench: batched and plain balanced products differ")
+    g2.close()
+    p2.close()
+    balanced = {"products": 4096, "product_limbs": limbs2, "batched_graph_ms": round(ms_b, 3),
+                "batched_limbs_per_s": limbs2 / (ms_b / 1e3), "batched_equals_plain": True,
+                "inputs": "numpy default_rng(0): la = rint(2**U(6,16)) x 4096, lb = la, limbs U[0,2^32)"}
     return {"products": 4096, "product_limbs": limbs, "batched_graph_ms": round(ms_g, 3),
             "batched_limbs_per_s": limbs / (ms_g / 1e3), "plain_ms": round(ms_p, 3),
             "plain_limbs_per_s": limbs / (ms_p / 1e3), "speedup": round(ms_p / ms_g, 2),
             "batched_equals_plain": same,
-            "inputs": "numpy default_rng(0): la, lb = rint(2**U(6,16)) x 4096 each, limbs U[0,2^32)"}
+            "inputs": "numpy default_rng(0): la, lb = rint(2**U(6,16)) x 4096 each, limbs U[0,2^32)",
+            "by_transform_size": buckets, "balanced": balanced}
+
+
+def phase_times(cat, n, reps=9):
+    """Phase 1 (catalan_factor: sieve, exponents, groups, back to the host) and
+    Phase 2 from that factorisation (prime_power_product, batched launches)
+    as separate calls, medians of wall time around each synchronised call.
+    The fused catalan_exact call avoids the host round trip between them."""
+    import torch
+
+    exps, off, primes = cat.factor(n)
+    t = cat.product(exps, off, primes)
+    torch.cuda.synchronize()
+    t1, t2 = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        exps, off, primes = cat.factor(n)
+        torch.cuda.synchronize()
+        t1.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        t = cat.product(exps, off, primes)
+        torch.cuda.synchronize()
+        t2.append(time.perf_counter() - t0)
+    return t, {"phase1_ms": round(sorted(t1)[reps // 2] * 1e3, 4), "phase2_ms": round(sorted(t2)[reps // 2] * 1e3, 4),
+               "note": "separate synchronised calls (factorisation to the host, then its product); "
+                       "the headline value is the fused call"}
 
 
 def _prod_mod(lo: int, hi: int, q: int) -> int:
@@ -402,6 +495,9 @@ def main():
 
     # batched without graph (launch overhead visible) and the plain form
     ms_batched = time_steps(cat, n, "batched", max(1, args.steps // 4), out)
+    t2, phases = phase_times(cat, n)
+    phases["phase2_output_verified"] = bool(check_output(cat, t2, n, gold))
+    log("bench: phase 1 %.3f ms, phase 2 %.3f ms (separate calls)" % (phases["phase1_ms"], phases["phase2_ms"]))
     plain = None
     if not args.no_plain and args.plain_steps > 0:
         cat.exact(n, mode="plain", out=out)   # plan + warm
@@ -477,6 +573,7 @@ def main():
                    "primes": st["n_primes"], "tree_levels": st["levels"], "verified_bit_exact": bool(verified)},
         "reconstruction_s": round(ms / 1e3, 6),
         "batched_no_graph_ms_per_step": round(ms_batched, 3),
+        "phases": phases,
         "plain": plain,
         "roofline": roof,
         "cpu_baseline": cpu,
