@@ -610,19 +610,24 @@ inline uint64_t cap_of(uint64_t alloc, uint64_t bits) {
   return std::max<uint64_t>(1, std::min<uint64_t>(alloc, (bits + 31) / 32));
 }
 
-// A long times a short operand whose transform would take the four-step
-// path: column sums cost la lb 32x32 multiply-adds (two VALU instructions
-// each, about 2.5 with the window's shifts and LDS reads) in one pass; the
-// transform costs 9 (N/2) log2 N butterflies (about 14 each) in four launches
-// per product.  The column sums are chosen up to 1.25 times the transform's
-// instruction count: on a batch of 4,096 uneven products the time is 4.64,
-// 4.54, 4.55 and 4.56 ms at 0.75, 1.25, 1.9 and 2.9; C(10^7) and C(10^8) are
-// flat over that range.
+// A long times a short operand (la >= 8 lb) beyond the schoolbook bound:
+// column sums cost la lb 32x32 multiply-adds (two VALU instructions each,
+// about 2.5 with the window's shifts and LDS reads) in one pass; the transform
+// costs 9 (N/2) log2 N butterflies (about 14 each).  Against the four-step
+// path (four launches per product) the column sums are chosen up to 1.25
+// times the transform's instruction count: on a batch of 4,096 uneven
+// products the time is 4.64, 4.54, 4.55 and 4.56 ms at 0.75, 1.25, 1.9 and
+// 2.9; C(10^7) and C(10^8) are flat over that range.  Against the
+// one-workgroup transform (one launch, no HBM round trip) they are chosen up
+// to its instruction count (the same batch: 4.58, 4.53, 4.48 and 4.46 ms at
+// 0, 0.25, 0.5 and 1; in C(10^7) the short products of the side branch,
+// about 150 x 6 limbs, leave the transform: 0.325 -> 0.266 ms of k_ntt_lds
+// per call, hidden before beside the Q_1 tree).
 bool colsum_wins(uint64_t la, uint64_t lb, const Cls& c) {
-  if (c.cls != CLS_LARGE || lb > COLSUM_MAX_LB || la < 8 * lb) return false;
+  if (c.cls == CLS_SCHOOL || c.cls == CLS_COLSUM || lb > COLSUM_MAX_LB || la < 8 * lb) return false;
   const double cs = 2.5 * (double)la * (double)lb;
   const double ntt = 14.0 * 9.0 * 0.5 * (double)(1ull << c.logN) * c.logN;
-  return cs <= 1.25 * ntt;
+  return cs <= (c.cls == CLS_LARGE ? 1.25 : 1.0) * ntt;
 }
 
 void add_products(Plan& P, std::vector<std::pair<Item, Item>>& pairs, std::vector<Item>& outs) {
@@ -1002,7 +1007,7 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     const int lt = std::max(s.logN, CAT_LDS_LOGT);   // tile 2^lt, 2^lt/16 threads
     const uint64_t per = (1ull << lt) >> s.logN;
     const uint64_t tiles = (cnt + per - 1) / per;
-    const dim3 grid((uint32_t)tiles, CAT_NPRIMES), block((1u << lt) / 16);
+    const dim3 grid((uint32_t)(tiles * CAT_NPRIMES)), block((1u << lt) / 16);
     KTime kt("k_ntt_lds", X.st, bfly(9.0 * cnt, s.logN));
     if (lt == 12)
       hipLaunchKernelGGL(k_ntt_lds<12>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
@@ -1028,10 +1033,10 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     // L-point DFTs of both operands, 3 primes: (N/2) log2 L butterflies each
     KTime kt("k_pass_fwd", X.st, 6.0 * cnt * N / 2 * pp.logL[k]);
     if (logT == NTT_COL_LOGT_SMALL)
-      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, dim3((uint32_t)gx, CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0,
+      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0,
                          X.st, dv, pg, k == 0 ? 1 : 0, ain, bin, X.F, tb);
     else
-      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, dim3((uint32_t)gx, CAT_NPRIMES, 2), dim3(NTT_COL_THREADS), 0, X.st,
+      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0, X.st,
                          dv, pg, k == 0 ? 1 : 0, ain, bin, X.F, tb);
     LAUNCHCHK();
   }

@@ -288,6 +288,18 @@ __device__ __forceinline__ uint32_t out_freq(uint32_t q, int logS) {
   return f;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2) in
+// the order of their linear index.  Neighbouring column tiles share cache
+// lines (a tile row is C words), so block b of a grid of G is renumbered to
+// put consecutive tiles on one XCD: XCD x gets the tiles
+// [x ceil(G/8), ...) in order (a bijection of [0, G) for any G).
+#define CAT_XCDS 8
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+  const uint32_t q = G / CAT_XCDS, r = G % CAT_XCDS;
+  const uint32_t x = b % CAT_XCDS, k = b / CAT_XCDS;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 struct NttTables {
   const uint2* tws;       // [prime][TWS_ENTRIES] forward pass tables
   const uint2* itws;      // [prime][TWS_ENTRIES] inverse
@@ -302,7 +314,10 @@ struct NttTables {
 // T = 2^12 coefficient slots = T/N products; grid (tiles, prime).
 // Writes res[prime][r_off + j] = (a*b)_j mod p for j < la+lb.
 // Tile of 2^LOGT coefficient slots (T/N products), 2^LOGT/16 threads, so every
-// radix-16 pass gives each thread two groups over the two operands.
+// radix-16 pass gives each thread two groups over the two operands.  The grid
+// is 3 x tiles workgroups; workgroup ids are renumbered so that each XCD takes
+// a contiguous run of (tile, prime) pairs: the three primes of a tile run one
+// after another on one XCD and read the operands once from HBM into its L2.
 template <int LOGT>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
 k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
@@ -310,12 +325,13 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   constexpr uint32_t TT = 1u << LOGT;
   __shared__ uint32_t lds[lds_pad(2 * TT)];
   __shared__ MulDesc ds[64];
-  const uint32_t prime = blockIdx.y;
+  const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t prime = wid % CAT_NPRIMES;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
   const uint32_t N = 1u << logN;
   const uint32_t per = TT >> logN;                 // products per tile (<= 64)
-  const uint64_t m0 = (uint64_t)blockIdx.x * per;
+  const uint64_t m0 = (uint64_t)(wid / CAT_NPRIMES) * per;
   const uint32_t cnt = (uint32_t)min((uint64_t)per, nmul - m0);
   for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ds[i] = dv.get(m0 + i);
   __syncthreads();
@@ -407,17 +423,6 @@ __device__ __forceinline__ uint2 tw2(const uint2* __restrict__ lo, const uint32_
   return make_uint2(w, w * pc.pinv);
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2) in
-// the order of their linear index.  Neighbouring column tiles share cache
-// lines (a tile row is C words), so block b of a grid of G is renumbered to
-// put consecutive tiles on one XCD: XCD x gets the tiles
-// [x ceil(G/8), ...) in order (a bijection of [0, G) for any G).
-#define CAT_XCDS 8
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
-  const uint32_t q = G / CAT_XCDS, r = G % CAT_XCDS;
-  const uint32_t x = b % CAT_XCDS, k = b / CAT_XCDS;
-  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
 
 struct PassGeom {
   int logN, logS, logL, logC;
@@ -438,12 +443,15 @@ __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
            uint32_t* __restrict__ F, NttTables tb) {
   __shared__ uint32_t lds[1u << LOGT];
-  const uint32_t prime = blockIdx.y, op = blockIdx.z;
+  // x: (tile, prime) pairs, XCD-contiguous; the three primes of a tile of the
+  // first pass read the same operand words
+  const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t prime = wid % CAT_NPRIMES, op = blockIdx.z;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
   uint64_t m, base;
   uint32_t j0;
-  pg.locate(xcd_remap(blockIdx.x, gridDim.x), &m, &base, &j0);
+  pg.locate(wid / CAT_NPRIMES, &m, &base, &j0);
   const int logSig = pg.logS - pg.logL;
   const uint32_t C = 1u << pg.logC;
   const uint64_t N = 1ull << pg.logN;
