@@ -5,8 +5,9 @@
 //    (up to) 2^LF consecutive primes, by multiplying a register accumulator by
 //    one 32-bit prime at a time.  The node is the same integer the pairwise
 //    tree gives (a product of the same leaves), in the same 2^LF-limb slot.
-//  * k_school: one wave per product of la, lb <= 128 limbs: column sums in
-//    96-bit accumulators (Comba order), then the ballot carry-lookahead.
+//  * k_school: one wave per product of la, lb <= 128 limbs: column sums (a
+//    lane holds up to four consecutive columns, a 64-bit sum and a carry
+//    count each), then the ballot carry-lookahead.
 
 // ---------------------------------------------------------------------------
 // Leaf packing.  Tree view: level LF, node i of group g is written at
@@ -90,6 +91,51 @@ __device__ __forceinline__ void colsum_mac3(uint64_t& a0, uint64_t& a1, uint64_t
       : "v"(w0), "v"(w1), "v"(w2), "v"(bj));
 }
 static_assert(COLSUM_E == 3, "colsum_mac3 covers three columns");
+// the same for one, two and four columns (one and two with wait states
+// between a carry's write and its read)
+__device__ __forceinline__ void colsum_mac1(uint64_t& a0, uint32_t& t0, uint32_t w0, uint32_t bj) {
+  uint64_t c0;
+  asm("v_mad_u64_u32 %0, %2, %3, %4, %0\n\t"
+      "s_nop 1\n\t"
+      "v_addc_co_u32_e64 %1, %2, 0, %1, %2"
+      : "+v"(a0), "+v"(t0), "=&s"(c0)
+      : "v"(w0), "v"(bj));
+}
+__device__ __forceinline__ void colsum_mac2(uint64_t& a0, uint64_t& a1, uint32_t& t0, uint32_t& t1, uint32_t w0,
+                                            uint32_t w1, uint32_t bj) {
+  uint64_t c0, c1;
+  asm("v_mad_u64_u32 %0, %4, %6, %8, %0\n\t"
+      "v_mad_u64_u32 %1, %5, %7, %8, %1\n\t"
+      "s_nop 0\n\t"
+      "v_addc_co_u32_e64 %2, %4, 0, %2, %4\n\t"
+      "v_addc_co_u32_e64 %3, %5, 0, %3, %5"
+      : "+v"(a0), "+v"(a1), "+v"(t0), "+v"(t1), "=&s"(c0), "=&s"(c1)
+      : "v"(w0), "v"(w1), "v"(bj));
+}
+__device__ __forceinline__ void colsum_mac4(uint64_t& a0, uint64_t& a1, uint64_t& a2, uint64_t& a3, uint32_t& t0,
+                                            uint32_t& t1, uint32_t& t2, uint32_t& t3, uint32_t w0, uint32_t w1,
+                                            uint32_t w2, uint32_t w3, uint32_t bj) {
+  uint64_t c0, c1, c2, c3;
+  asm("v_mad_u64_u32 %0, %8, %12, %16, %0\n\t"
+      "v_mad_u64_u32 %1, %9, %13, %16, %1\n\t"
+      "v_mad_u64_u32 %2, %10, %14, %16, %2\n\t"
+      "v_mad_u64_u32 %3, %11, %15, %16, %3\n\t"
+      "v_addc_co_u32_e64 %4, %8, 0, %4, %8\n\t"
+      "v_addc_co_u32_e64 %5, %9, 0, %5, %9\n\t"
+      "v_addc_co_u32_e64 %6, %10, 0, %6, %10\n\t"
+      "v_addc_co_u32_e64 %7, %11, 0, %7, %11"
+      : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(t0), "+v"(t1), "+v"(t2), "+v"(t3), "=&s"(c0), "=&s"(c1),
+        "=&s"(c2), "=&s"(c3)
+      : "v"(w0), "v"(w1), "v"(w2), "v"(w3), "v"(bj));
+}
+template <int E>
+__device__ __forceinline__ void mac_cols(uint64_t* acc, uint32_t* top, const uint32_t* w, uint32_t bj) {
+  if constexpr (E == 1) colsum_mac1(acc[0], top[0], w[0], bj);
+  if constexpr (E == 2) colsum_mac2(acc[0], acc[1], top[0], top[1], w[0], w[1], bj);
+  if constexpr (E == 3) colsum_mac3(acc[0], acc[1], acc[2], top[0], top[1], top[2], w[0], w[1], w[2], bj);
+  if constexpr (E == 4)
+    colsum_mac4(acc[0], acc[1], acc[2], acc[3], top[0], top[1], top[2], top[3], w[0], w[1], w[2], w[3], bj);
+}
 __global__ void __launch_bounds__(256) k_colsum(DescView dv, SegView sv, const uint32_t* __restrict__ ain,
                                                 const uint32_t* __restrict__ bin, uint32_t* __restrict__ res,
                                                 uint64_t stride, uint32_t* __restrict__ err) {
@@ -157,12 +203,62 @@ __global__ void __launch_bounds__(256) k_colsum(DescView dv, SegView sv, const u
 }
 
 #define SCHOOL_WAVES 4
+#define SCHOOL_WIN (3 * SCHOOL_MAX)
+// Column sums of one product in one wave: lane owns the E consecutive columns
+// k = E lane + e (64 E >= la + lb - 1) and runs over j < lbe (the shorter
+// operand rounded up to even, padded with a zero limb): V(k) = sum_j
+// a[k - j] b[j], with sa[t] = a[t - lbe] (zero outside [0, la)).  Each column
+// keeps a 64-bit sum and its count of carries out of bit 64; the three words
+// go to sv[.][k + 3].
+template <int E>
+__device__ __forceinline__ void school_cols(const uint32_t* sa, const uint32_t* sbv, uint32_t lbe, uint32_t lane,
+                                            uint32_t (*sv)[2 * SCHOOL_MAX + 4]) {
+  const uint32_t c0 = E * lane + lbe;
+  uint32_t w[E];
+#pragma unroll
+  for (int e = 0; e < E; e++) w[e] = sa[c0 + e];
+  uint64_t acc[E];
+  uint32_t top[E];
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    acc[e] = 0;
+    top[e] = 0;
+  }
+  for (uint32_t j = 0; j < lbe; j += 2) {
+    const uint2 bj = *(const uint2*)&sbv[j];
+    const uint32_t wn1 = sa[c0 - j - 1], wn2 = sa[c0 - j - 2];
+    mac_cols<E>(acc, top, w, bj.x);
+    // j + 1: every column one position further down a
+    uint32_t w1[E];
+    w1[0] = wn1;
+#pragma unroll
+    for (int e = 1; e < E; e++) w1[e] = w[e - 1];
+    mac_cols<E>(acc, top, w1, bj.y);
+#pragma unroll
+    for (int e = E - 1; e >= 2; e--) w[e] = w[e - 2];
+    if constexpr (E >= 2) w[1] = wn1;
+    w[0] = wn2;
+  }
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const uint32_t k = E * lane + e;
+    sv[0][k + 3] = (uint32_t)acc[e];
+    sv[1][k + 3] = (uint32_t)(acc[e] >> 32);
+    sv[2][k + 3] = top[e];
+  }
+  for (uint32_t k = 64 * E + lane; k < 2 * SCHOOL_MAX; k += 64) {
+    sv[0][k + 3] = 0;
+    sv[1][k + 3] = 0;
+    sv[2][k + 3] = 0;
+  }
+}
+
 __global__ void __launch_bounds__(64 * SCHOOL_WAVES)
 k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
          uint32_t* __restrict__ out, uint32_t* __restrict__ err, uint32_t prod_blocks, CopyList tails,
          const uint32_t* __restrict__ tin, uint32_t* __restrict__ tout) {
-  __shared__ uint32_t sa[SCHOOL_WAVES][SCHOOL_MAX];
-  __shared__ uint32_t sb[SCHOOL_WAVES][SCHOOL_MAX];
+  __shared__ uint32_t sa[SCHOOL_WAVES][SCHOOL_WIN];
+  __shared__ __align__(8) uint32_t sb[SCHOOL_WAVES][SCHOOL_MAX];
   __shared__ uint32_t sv[SCHOOL_WAVES][3][2 * SCHOOL_MAX + 4];
   if (blockIdx.x >= prod_blocks) {
     copy_tail_block(tails, tin, tout, blockIdx.x - prod_blocks);
@@ -171,37 +267,43 @@ k_school(DescView dv, uint64_t nmul, const uint32_t* __restrict__ ain, const uin
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t mi = (uint64_t)blockIdx.x * SCHOOL_WAVES + w;
   if (mi >= nmul) return;   // whole wave leaves together; no block barrier below
-  const MulDesc d = dv.get(mi);
-  const uint32_t la = d.la, lb = d.lb, L = la + lb;
+  const MulDesc d = dv.get(uni64(mi));
+  // the longer operand slides (la), the shorter one is summed over (lb)
+  const uint32_t da = uni32(d.la), db = uni32(d.lb);
+  const bool swp = da < db;
+  const uint32_t* a = swp ? bin + uni64(d.b_off) : ain + uni64(d.a_off);
+  const uint32_t* b = swp ? ain + uni64(d.a_off) : bin + uni64(d.b_off);
+  const uint32_t la = swp ? db : da, lb = swp ? da : db, L = la + lb;
+  const uint32_t lbe = (lb + 1) & ~1u;
   {
-    // the (at most 2 + 2) loads of a lane in flight together
-    const uint32_t k0 = lane, k1 = lane + 64;
-    const uint32_t a0 = ain[d.a_off + (k0 < la ? k0 : 0u)], a1 = ain[d.a_off + (k1 < la ? k1 : 0u)];
-    const uint32_t b0 = bin[d.b_off + (k0 < lb ? k0 : 0u)], b1 = bin[d.b_off + (k1 < lb ? k1 : 0u)];
-    if (k0 < la) sa[w][k0] = a0;
-    if (k1 < la) sa[w][k1] = a1;
-    if (k0 < lb) sb[w][k0] = b0;
-    if (k1 < lb) sb[w][k1] = b1;
+    // every load of the lane in flight together: clamped addresses, masks
+    uint32_t xa[SCHOOL_WIN / 64], xb[2];
+#pragma unroll
+    for (int i = 0; i < SCHOOL_WIN / 64; i++) {
+      const uint32_t idx = lane + 64 * i - lbe;    // wraps when t < lbe
+      xa[i] = idx < la ? a[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const uint32_t t = lane + 64 * i;
+      xb[i] = t < lb ? b[t] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < SCHOOL_WIN / 64; i++) sa[w][lane + 64 * i] = xa[i];
+#pragma unroll
+    for (int i = 0; i < 2; i++) sb[w][lane + 64 * i] = xb[i];
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  // column k = sum_{i} a_i b_{k-i}; lanes take k = lane + 64*c
-  for (uint32_t k = lane; k < 2 * SCHOOL_MAX; k += 64) {
-    uint64_t lo = 0;
-    uint32_t hi = 0;
-    if (k + 1 < L) {
-      const uint32_t i0 = k + 1 > lb ? k + 1 - lb : 0;
-      const uint32_t i1 = k < la - 1 ? k : la - 1;
-      for (uint32_t i = i0; i <= i1; i++) {
-        const uint64_t t = (uint64_t)sa[w][i] * sb[w][k - i];
-        lo += t;
-        hi += (lo < t);
-      }
-    }
-    sv[w][0][k + 3] = (uint32_t)lo;
-    sv[w][1][k + 3] = (uint32_t)(lo >> 32);
-    sv[w][2][k + 3] = hi;
-  }
+  const uint32_t ncol = (L - 1 + 63) / 64;   // columns per lane; k < L - 1 carry the sums
+  if (ncol <= 1)
+    school_cols<1>(sa[w], sb[w], lbe, lane, sv[w]);
+  else if (ncol == 2)
+    school_cols<2>(sa[w], sb[w], lbe, lane, sv[w]);
+  else if (ncol == 3)
+    school_cols<3>(sa[w], sb[w], lbe, lane, sv[w]);
+  else
+    school_cols<4>(sa[w], sb[w], lbe, lane, sv[w]);
   if (lane < 3) { sv[w][0][lane] = 0; sv[w][1][lane] = 0; sv[w][2][lane] = 0; }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
