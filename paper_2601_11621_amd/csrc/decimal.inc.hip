@@ -63,6 +63,7 @@ __device__ __forceinline__ void dec_split(uint32_t r0, uint32_t r1, uint32_t r2,
   c[3] = s0;
 }
 
+
 // Radix-B digit k of a segment: s_k = c0(k) + c1(k-1) + c2(k-2) + c3(k-3) <
 // 3B + 80, so s_k = x_k + B y_k with y_k <= 3, u_k = x_k + y_{k-1} <= B + 2 and
 // the carries left are binary: generate u_k >= B, propagate u_k = B - 1.
@@ -70,14 +71,6 @@ __device__ __forceinline__ void dec_split(uint32_t r0, uint32_t r1, uint32_t r2,
 // k0-4 .. k0-1 that enter these sums (10 words) come from the left neighbour
 // (thread 0: recomputed from the residues).
 #define DEC_XV 10
-__device__ __forceinline__ void dec_load(const CrtSeg& sg, const uint32_t* __restrict__ r0,
-                                         const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
-                                         const uint32_t* __restrict__ add, int64_t k, uint32_t* c) {
-  c[0] = c[1] = c[2] = c[3] = 0;
-  if (k < 0 || (uint64_t)k >= sg.len) return;
-  dec_split(r0[k], r1[k], r2[k], (uint64_t)k < sg.add_len ? add[sg.add_pos + k] : 0u, c);
-}
-
 __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __restrict__ r0,
                                             const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
                                             const uint32_t* __restrict__ add, uint64_t kb, uint32_t (*xv)[DEC_XV],
@@ -86,6 +79,11 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
   const uint64_t k0 = kb + (uint64_t)tid * DEC_CRT_E;
   // c[i][.] for positions k0-4+i (i < 4 from the neighbour, own from i = 4)
   uint32_t c[DEC_CRT_E + 4][4];
+  // threads 0..3 also fetch the block's left context kb-4 .. kb-1, one
+  // position each, with their own loads
+  const int64_t kl = (int64_t)kb - 4 + (int64_t)tid;
+  const bool lctx = tid < 4 && kl >= 0 && (uint64_t)kl < sg.len;
+  uint32_t y0 = 0, y1 = 0, y2 = 0, ya = 0;
   {
     uint32_t x0[DEC_CRT_E], x1[DEC_CRT_E], x2[DEC_CRT_E], xa[DEC_CRT_E];
 #pragma unroll
@@ -96,6 +94,13 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
       x1[i] = r1[kc];
       x2[i] = r2[kc];
       xa[i] = add[sg.add_pos + (k < sg.add_len ? k : 0)];
+    }
+    if (tid < 4) {
+      const uint64_t kc = lctx ? (uint64_t)kl : 0;
+      y0 = r0[kc];
+      y1 = r1[kc];
+      y2 = r2[kc];
+      ya = add[sg.add_pos + (kc < sg.add_len ? kc : 0)];
     }
 #pragma unroll
     for (int i = 0; i < DEC_CRT_E; i++) {
@@ -118,8 +123,8 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
   }
   if (tid < 4) {
     // threads 0..3 recompute positions kb-4 .. kb-1, one each
-    uint32_t q[4];
-    dec_load(sg, r0, r1, r2, add, (int64_t)kb - 4 + tid, q);
+    uint32_t q[4] = {0, 0, 0, 0};
+    if (lctx) dec_split(y0, y1, y2, (uint64_t)kl < sg.add_len ? ya : 0u, q);
     uint32_t* o = xv[0];
     if (tid == 3) { o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; }
     if (tid == 2) { o[4] = q[1]; o[5] = q[2]; o[6] = q[3]; }

@@ -755,11 +755,15 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
   const uint32_t tid = threadIdx.x;
   const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
   // V for positions k0-3 .. k0+E-1: the thread's own E, the 3 before it from
-  // its left neighbour (thread 0: recomputed from the residues)
+  // its left neighbour (for thread 0 the block's left context kb-3 .. kb-1,
+  // recomputed from the residues by threads 0, 1 and 2, one position each)
   uint32_t v0[CAT_CRT_E + 3], v1[CAT_CRT_E + 3], v2[CAT_CRT_E + 3];
+  const bool lctx = tid < 3 && kb + tid >= 3;
+  uint32_t y0 = 0, y1 = 0, y2 = 0;
   {
-    // the thread's 3*E residue loads in flight together (clamped addresses;
-    // positions past the segment count as zero)
+    // the thread's 3*E residue loads, and its left-context position, in
+    // flight together (clamped addresses; positions past the segment count
+    // as zero)
     uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E];
 #pragma unroll
     for (int i = 0; i < CAT_CRT_E; i++) {
@@ -768,6 +772,12 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
       x0[i] = r0[kc];
       x1[i] = r1[kc];
       x2[i] = r2[kc];
+    }
+    if (tid < 3) {
+      const uint64_t kl = lctx ? kb + tid - 3 : 0;
+      y0 = r0[kl];
+      y1 = r1[kl];
+      y2 = r2[kl];
     }
 #pragma unroll
     for (int i = 0; i < CAT_CRT_E; i++) {
@@ -790,24 +800,20 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
     xv[tid + 1][3 * i + 1] = v1[CAT_CRT_E + i];
     xv[tid + 1][3 * i + 2] = v2[CAT_CRT_E + i];
   }
-  if (tid == 0) {
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-      const int64_t k = (int64_t)kb + i - 3;
-      uint32_t a0 = 0, a1 = 0, a2 = 0;
-      if (k >= 0) {
-        if constexpr (RAW) {
-          a0 = r0[k];
-          a1 = r1[k];
-          a2 = r2[k];
-        } else {
-          garner3(r0[k], r1[k], r2[k], a0, a1, a2);
-        }
+  if (tid < 3) {
+    uint32_t a0 = 0, a1 = 0, a2 = 0;
+    if (lctx) {
+      if constexpr (RAW) {
+        a0 = y0;
+        a1 = y1;
+        a2 = y2;
+      } else {
+        garner3(y0, y1, y2, a0, a1, a2);
       }
-      xv[0][3 * i + 0] = a0;
-      xv[0][3 * i + 1] = a1;
-      xv[0][3 * i + 2] = a2;
     }
+    xv[0][3 * tid + 0] = a0;
+    xv[0][3 * tid + 1] = a1;
+    xv[0][3 * tid + 2] = a2;
   }
   __syncthreads();
 #pragma unroll
