@@ -223,6 +223,20 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
   __shared__ unsigned long long bits_e[CAT_MAX_GROUPS + 1];
   __shared__ uint64_t goff[CAT_MAX_GROUPS + 2];
   const uint32_t T = blockDim.x, tid = threadIdx.x;
+  // the thread's seeds (a contiguous chunk, ascending) and their exponents,
+  // loaded once, with the segment counts below, all in flight
+  constexpr int SCH = (SEED_MAX + 1023) / 1024;
+  const uint32_t ns = gt->nseeds;
+  const uint32_t sch = (ns + T - 1) / T;   // <= SCH
+  const uint32_t slo = min(tid * sch, ns), shi = min(slo + sch, ns);
+  uint32_t sd[SCH];
+  int32_t se[SCH];
+#pragma unroll
+  for (int i = 0; i < SCH; i++) {
+    const uint32_t k = slo + i < shi ? slo + i : 0;
+    sd[i] = seeds[k];
+    se[i] = slo + i < shi ? seed_e[k] : 0;
+  }
   // 1. exclusive scan of the segment counts
   const uint32_t chunk = (nseg + T - 1) / T;
   uint32_t lo = min(tid * chunk, nseg), hi = min(lo + chunk, nseg);
@@ -237,12 +251,12 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
     bits_e[tid] = 0;
   }
   __syncthreads();
-  const uint32_t ns = gt->nseeds;
-  for (uint32_t k = tid; k < ns; k += T) {
-    int32_t e = seed_e[k];
+#pragma unroll
+  for (int i = 0; i < SCH; i++) {
+    const int32_t e = se[i];
     if (e > 0 && e <= CAT_MAX_GROUPS) {
       atomicAdd(&cnt_e[e], 1u);
-      atomicAdd(&bits_e[e], (unsigned long long)(32 - __clz(seeds[k])));
+      atomicAdd(&bits_e[e], (unsigned long long)(32 - __clz(sd[i])));
     }
   }
   __syncthreads();
@@ -269,18 +283,18 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
   }
   __syncthreads();
   // 4. seeds into their groups, stable (seeds ascending)
-  const uint32_t sch = (ns + T - 1) / T;
-  const uint32_t slo = min(tid * sch, ns), shi = min(slo + sch, ns);
   for (uint32_t e = 1; e <= CAT_MAX_GROUPS; e++) {
     if (cnt_e[e] == 0) continue;   // uniform
     uint32_t cc = 0;
-    for (uint32_t k = slo; k < shi; k++) cc += (seed_e[k] == (int32_t)e);
+#pragma unroll
+    for (int i = 0; i < SCH; i++) cc += (se[i] == (int32_t)e);
     uint32_t r = block_excl_scan_1024(cc, tmp, nullptr);
-    uint64_t base = goff[e];
-    for (uint32_t k = slo; k < shi; k++)
-      if (seed_e[k] == (int32_t)e) {
-        uint64_t at = base + r++;
-        if (at < cap) primes[at] = seeds[k];
+    const uint64_t base = goff[e];
+#pragma unroll
+    for (int i = 0; i < SCH; i++)
+      if (se[i] == (int32_t)e) {
+        const uint64_t at = base + r++;
+        if (at < cap) primes[at] = sd[i];
       }
   }
 }
