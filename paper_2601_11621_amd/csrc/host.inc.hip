@@ -792,6 +792,7 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
     if (s->host_segs.size() > CAT_INLINE_SEG) {
       bytes = align_up(bytes, 16) + s->host_segs.size() * sizeof(CrtSeg);
       bytes = align_up(bytes, 16) + s->host_pref.size() * sizeof(uint32_t);
+      bytes = align_up(bytes, 16) + (size_t)s->nblk * sizeof(uint32_t);
     }
   }
   char* d = nullptr;
@@ -823,6 +824,14 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
       memcpy(&h[o], s->host_pref.data(), s->host_pref.size() * sizeof(uint32_t));
       s->sv.pref = (const uint32_t*)(d + o);
       o += s->host_pref.size() * sizeof(uint32_t);
+      // block -> segment, so that a block of a large batch finds its product
+      // with one load instead of a binary search over the prefix table
+      o = align_up(o, 16);
+      uint32_t* b2s = (uint32_t*)&h[o];
+      for (size_t k = 0; k + 1 < s->host_pref.size(); k++)
+        for (uint32_t b = s->host_pref[k]; b < s->host_pref[k + 1]; b++) b2s[b] = (uint32_t)k;
+      s->sv.b2s = (const uint32_t*)(d + o);
+      o += (size_t)s->nblk * sizeof(uint32_t);
     } else {
       for (size_t k = 0; k < s->host_segs.size(); k++) s->sv.iseg[k] = s->host_segs[k];
       for (size_t k = 0; k < s->host_pref.size(); k++) s->sv.ipref[k] = s->host_pref[k];

@@ -698,6 +698,7 @@ __device__ __forceinline__ uint32_t wave_carry(bool g, bool pr, uint32_t cin, ui
 struct SegView {
   const CrtSeg* segs;        // nullptr => inline tables
   const uint32_t* pref;      // pref[s] = first block of segment s (nseg+1 entries)
+  const uint32_t* b2s;       // with segs: the segment of every block (one load, no search)
   uint32_t nseg;
   uint32_t ubl;              // > 0: uniform segments of ubl blocks each (below)
   CrtSeg iseg[CAT_INLINE_SEG];
@@ -720,9 +721,13 @@ struct SegView {
     }
     const uint32_t* pr = segs ? pref : ipref;
     uint32_t lo = 0, hi = nseg;   // pr[lo] <= b < pr[lo+1]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (pr[mid] <= b) lo = mid; else hi = mid;
+    if (segs && b2s) {
+      lo = b2s[b];
+    } else {
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pr[mid] <= b) lo = mid; else hi = mid;
+      }
     }
     *sg = segs ? segs[lo] : iseg[lo];
     *first = pr[lo];
