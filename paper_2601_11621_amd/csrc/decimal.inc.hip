@@ -270,22 +270,44 @@ __global__ void k_copy_pad(const uint32_t* __restrict__ in, uint64_t nin, uint32
 
 // Text: radix-B digits dig[0 .. top] (dig[top] != 0, or top = 0) as
 // D = width(dig[top]) + 9 top characters, most significant first.
-__global__ void __launch_bounds__(256) k_dec_ascii(const uint32_t* __restrict__ dig, uint64_t top, uint32_t width,
-                                                   char* __restrict__ out) {
+// ASCII text, most significant digit first.  top (device) is one past the
+// highest nonzero radix-10^9 group (0 for x = 0); the leading group takes
+// `width` characters, every other group nine.  The character count goes to
+// *nc; nothing is written when it exceeds cap.  Grid: one thread per group
+// that can exist.
+__global__ void __launch_bounds__(256) k_dec_ascii(const uint32_t* __restrict__ dig,
+                                                   const unsigned long long* __restrict__ top, uint64_t cap,
+                                                   char* __restrict__ out, unsigned long long* __restrict__ nc) {
+  const unsigned long long t = *top;
+  const uint64_t ti = t ? t - 1 : 0;
+  const uint32_t vt = dig[ti];
+  uint32_t width = 1;
+  for (uint32_t q = vt; q >= 10u; q /= 10u) width++;
+  const uint64_t n = width + 9 * ti;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > top) return;
+  if (i == 0) *nc = n;
+  if (n > cap || i > ti) return;
   uint32_t v = dig[i];
-  if (i == top) {
+  if (i == ti) {
     for (int k = (int)width - 1; k >= 0; k--) {
       out[k] = (char)('0' + v % 10u);
       v /= 10u;
     }
     return;
   }
-  char* o = out + width + 9 * (top - 1 - i);
+  char* o = out + width + 9 * (ti - 1 - i);
 #pragma unroll
   for (int k = 8; k >= 0; k--) {
     o[k] = (char)('0' + v % 10u);
     v /= 10u;
   }
+}
+
+// P_0 (the leaf power in radix 10^9), written by a kernel so that a captured
+// conversion carries it as an argument
+struct DecWords {
+  uint32_t w[DEC_LEAF_DIGITS];
+};
+__global__ void k_dec_p0(DecWords p0, uint32_t* __restrict__ out) {
+  if (threadIdx.x < DEC_LEAF_DIGITS) out[threadIdx.x] = p0.w[threadIdx.x];
 }
