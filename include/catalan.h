@@ -129,7 +129,9 @@ cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, c
  * bigint_to_decimal: d_work of at least that many bytes (device, caller-owned,
  * contents undefined afterwards; CAT_ENOMEM if smaller); d_x, d_out and d_work
  * must not overlap; synchronises `stream`; CAT_EINTERNAL if a device check
- * failed. */
+ * failed.  The first call for a given (n_limbs, d_x, d_out, cap, d_work)
+ * captures the conversion as a HIP graph that later calls with the same
+ * arguments replay (the library keeps up to 32 such graphs). */
 cat_status decimal_sizes(size_t n_limbs, size_t* max_chars, size_t* workspace_bytes);
 cat_status bigint_to_decimal(const uint32_t* d_x, size_t n_limbs, char* d_out, size_t cap, size_t* n_chars,
                              void* d_work, size_t work_bytes, void* stream);
