@@ -150,3 +150,46 @@ def test_abi_capacity_and_size_query(cat):
     st = lib.bigint_to_decimal(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(out.data_ptr()), 64,
                                ctypes.byref(nc), ctypes.c_void_p(w.data_ptr()), 16, None)
     assert st == cat.CAT_ENOMEM
+
+
+def test_replay_reads_current_input(cat):
+    """Calls with the same buffers replay one captured conversion: new values
+    written into the same input buffer (same length, then with leading zero
+    limbs) give their own text, a short capacity on a replay writes nothing,
+    and the first value converts again afterwards."""
+    import ctypes
+
+    import torch
+
+    lib = cat.load()
+    L = 3000
+    vals = [_random_limbs(L, 41), _random_limbs(L, 42)]
+    c = _random_limbs(L, 43)
+    c[L // 2:] = 0                       # same length, half of it leading zeros
+    vals.append(c)
+    x = torch.empty(L, dtype=torch.int32, device="cuda")
+    mc, wb = cat.decimal_sizes(L)
+    w = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    out = torch.empty(mc, dtype=torch.uint8, device="cuda")
+    nc = ctypes.c_size_t()
+
+    def conv(v, cap):
+        x.copy_(cat.from_numpy(v))
+        out.fill_(35)
+        torch.cuda.synchronize()
+        st = lib.bigint_to_decimal(ctypes.c_void_p(x.data_ptr()), L, ctypes.c_void_p(out.data_ptr()), cap,
+                                   ctypes.byref(nc), ctypes.c_void_p(w.data_ptr()), wb, None)
+        return st, nc.value
+
+    for rep in range(2):
+        for i, v in enumerate(vals + [vals[0]]):
+            want = oracle.to_decimal(v)
+            st, n = conv(v, mc)
+            _say("replay", rep, i, n)
+            assert st == cat.CAT_OK and n == len(want), (rep, i)
+            assert out[:n].cpu().numpy().tobytes().decode() == want, (rep, i)
+            assert bool((out[n:] == 35).all()), (rep, i)
+        want = oracle.to_decimal(vals[2])
+        st, n = conv(vals[2], len(want) - 1)
+        assert st == cat.CAT_ERANGE and n == len(want)
+        assert bool((out == 35).all())
