@@ -747,6 +747,12 @@ struct SegView {
 // (nothing is assumed about which workgroups run at the same time).
 #define CAT_SCAN_POLLS 16   // default number of polls of a predecessor's flag
 
+// A thread's CAT_CRT_E consecutive words: one vector access in a block that
+// lies inside its segment
+struct CrtWords {
+  uint32_t w[CAT_CRT_E];
+};
+
 // Values V of this thread's CAT_CRT_E positions of the block starting at kb,
 // their sums u and the thread's (G, P); wave pairs go to tmp[wave].  V is
 // Garner's recombination of the three residues, or (RAW) the three words
@@ -770,13 +776,24 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
     // flight together (clamped addresses; positions past the segment count
     // as zero)
     uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E];
+    if (kb + CAT_CRT_BLOCK <= sg.len) {
+      const CrtWords a0 = *(const CrtWords*)(r0 + k0), a1 = *(const CrtWords*)(r1 + k0),
+                     a2 = *(const CrtWords*)(r2 + k0);
 #pragma unroll
-    for (int i = 0; i < CAT_CRT_E; i++) {
-      const uint64_t k = k0 + i;
-      const uint64_t kc = k < sg.len ? k : 0;
-      x0[i] = r0[kc];
-      x1[i] = r1[kc];
-      x2[i] = r2[kc];
+      for (int i = 0; i < CAT_CRT_E; i++) {
+        x0[i] = a0.w[i];
+        x1[i] = a1.w[i];
+        x2[i] = a2.w[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < CAT_CRT_E; i++) {
+        const uint64_t k = k0 + i;
+        const uint64_t kc = k < sg.len ? k : 0;
+        x0[i] = r0[kc];
+        x1[i] = r1[kc];
+        x2[i] = r2[kc];
+      }
     }
     if (tid < 3) {
       const uint64_t kl = lctx ? kb + tid - 3 : 0;
@@ -927,11 +944,18 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
   uint32_t c = wave_carry(G, P, wc, &cout, &ap);
   uint32_t* o = out + sg.out_pos;
   const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
+  CrtWords r;
 #pragma unroll
   for (int i = 0; i < CAT_CRT_E; i++) {
-    const uint64_t kk = k0 + i;
     const uint64_t t = u[i] + c;
     c = (uint32_t)(t >> 32);
-    if (kk < sg.len) o[kk] = (uint32_t)t;
+    r.w[i] = (uint32_t)t;
+  }
+  if (kb + CAT_CRT_BLOCK <= sg.len) {
+    *(CrtWords*)(o + k0) = r;
+  } else {
+#pragma unroll
+    for (int i = 0; i < CAT_CRT_E; i++)
+      if (k0 + i < sg.len) o[k0 + i] = r.w[i];
   }
 }
