@@ -263,10 +263,13 @@ cat_status cat_tune_get(cat_tuning* t);
 
 /* Carry look-back between CRT blocks (diagnostics and tests).  A block reads
  * the generate / propagate pair of the block before it from a flag that block
- * publishes, polling it at most `polls` times (default 16, at most 2^20), and
- * otherwise recomputes the pair from that block's residues; the result is the
- * same either way, and polls = 0 always recomputes.  Cached C(n) plans are
- * dropped; existing product plans keep the value they were recorded with. */
+ * publishes, polling it at most `polls` times (at most 2^20), and otherwise
+ * recomputes the pair from that block's residues; the result is the same
+ * either way, and polls = 0 always recomputes.  CAT_POLLS_AUTO (the default)
+ * recomputes at once in launches of at most 2^15 blocks and polls up to 16
+ * times in larger ones.  Cached C(n) plans are dropped; existing product
+ * plans keep the value they were recorded with. */
+#define CAT_POLLS_AUTO 0xFFFFFFFFu
 cat_status cat_lookback_polls_set(uint32_t polls);
 
 /* Kernel timer (measurement only).  cat_timer_set(name) brackets every later

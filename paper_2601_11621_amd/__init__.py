@@ -186,10 +186,14 @@ def get_tuning() -> dict:
             "log_pass": list(t.log_pass)}
 
 
-def set_lookback_polls(polls: int) -> None:
+POLLS_AUTO = 0xFFFFFFFF
+
+
+def set_lookback_polls(polls: Optional[int]) -> None:
     """Polls of a predecessor's carry flag before a CRT block recomputes it
-    (0: always recompute).  Same results either way."""
-    _check(load().cat_lookback_polls_set(int(polls)), "cat_lookback_polls_set")
+    (0: always recompute; None: the library's per-launch choice).  Same
+    results either way."""
+    _check(load().cat_lookback_polls_set(POLLS_AUTO if polls is None else int(polls)), "cat_lookback_polls_set")
 
 
 def set_tuning(d: Optional[dict]) -> None:

@@ -275,7 +275,17 @@ cat_tuning default_tuning() {
   return t;
 }
 cat_tuning g_tune = default_tuning();
-uint32_t g_crt_polls = CAT_SCAN_POLLS;
+// polls of a predecessor's carry pair; CAT_POLLS_AUTO chooses per launch:
+// launches of at most CRT_RECOMPUTE_BLOCKS blocks (one or a few rounds of
+// workgroups, latency-bound) recompute the pair at once, which measured 4-5 %
+// faster for k_crt at 10^7 and 10^8; larger ones poll (recomputing costs HBM
+// bandwidth there: 3 % slower at 2,050,572,903)
+uint32_t g_crt_polls = CAT_POLLS_AUTO;
+#define CRT_RECOMPUTE_BLOCKS (1u << 15)
+inline uint32_t crt_polls(uint32_t nblk) {
+  if (g_crt_polls != CAT_POLLS_AUTO) return g_crt_polls;
+  return nblk <= CRT_RECOMPUTE_BLOCKS ? 0u : CAT_SCAN_POLLS;
+}
 
 bool tuning_valid(const cat_tuning& t) {
   if (t.school_max < 1 || t.school_max > SCHOOL_MAX) return false;
@@ -941,10 +951,10 @@ cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const C
     X.crt_epoch++;
     if (raw)
       hipLaunchKernelGGL(k_crt<true>, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk,
-                         X.flags, X.crt_epoch, g_crt_polls, cl, tin, tout, X.err);
+                         X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
     else
       hipLaunchKernelGGL(k_crt<false>, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk,
-                         X.flags, X.crt_epoch, g_crt_polls, cl, tin, tout, X.err);
+                         X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
   }
   LAUNCHCHK();
   X.launches++;
@@ -960,7 +970,7 @@ cat_status launch_crt10(Exec& X, uint32_t* out, const SegView& sv, uint32_t nblk
     KTime kt("k_crt10", X.st, (double)nblk * DEC_CRT_BLOCK);
     X.crt_epoch++;
     hipLaunchKernelGGL(k_crt10, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.W, nblk,
-                       X.flags, X.crt_epoch, g_crt_polls, *tails, tin, tout, X.err);
+                       X.flags, X.crt_epoch, crt_polls(nblk), *tails, tin, tout, X.err);
   }
   LAUNCHCHK();
   X.launches++;
@@ -1716,7 +1726,7 @@ cat_status cat_tune_set(const cat_tuning* t) {
 
 cat_status cat_lookback_polls_set(uint32_t polls) {
   std::lock_guard<std::recursive_mutex> lk(g.mu);
-  if (polls > (1u << 20)) return CAT_EINVAL;
+  if (polls > (1u << 20) && polls != CAT_POLLS_AUTO) return CAT_EINVAL;
   g_crt_polls = polls;
   // cached graphs of C(n) carry the old value
   if (!g.plans.empty()) HIPCHK(hipDeviceSynchronize());

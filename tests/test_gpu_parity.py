@@ -245,7 +245,7 @@ def test_residues_kernel(cat):
         assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1))
 
 
-@pytest.mark.parametrize("polls", [0, 1])
+@pytest.mark.parametrize("polls", [0, 1, 16])
 def test_carry_lookback_recompute(cat, polls):
     """With no (or one) poll of the predecessor's published carry pair, CRT
     blocks recompute it from the residues: same products, same C(n).  All-ones
@@ -259,7 +259,7 @@ def test_carry_lookback_recompute(cat, polls):
         for n in (13337, 250000):
             assert np.array_equal(cat.to_numpy(cat.exact(n, mode="graph")), oracle.catalan(n)), n
     finally:
-        cat.set_lookback_polls(16)
+        cat.set_lookback_polls(None)
 
 
 def _schedule_short(t):
