@@ -1053,10 +1053,10 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     KTime kt("k_pass_fwd", X.st, 6.0 * cnt * N / 2 * pp.logL[k]);
     if (logT == NTT_COL_LOGT_SMALL)
       hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0,
-                         X.st, dv, pg, k == 0 ? 1 : 0, ain, bin, X.F, tb);
+                         X.st, dv, pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, ain, bin, X.F, tb);
     else
       hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0, X.st,
-                         dv, pg, k == 0 ? 1 : 0, ain, bin, X.F, tb);
+                         dv, pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, ain, bin, X.F, tb);
     LAUNCHCHK();
   }
   {
@@ -1066,11 +1066,14 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     const dim3 grid((uint32_t)(cnt << logR1), CAT_NPRIMES), block((1u << lt) / 16);
     KTime kt("k_row", X.st, bfly(9.0 * rows, logM));
     if (lt == 12)
-      hipLaunchKernelGGL(k_row<12>, grid, block, 0, X.st, s.logN, logM, X.F, tb, s0, s1, s2);
+      hipLaunchKernelGGL(k_row<12>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], X.F,
+                         tb, s0, s1, s2);
     else if (lt == 13)
-      hipLaunchKernelGGL(k_row<13>, grid, block, 0, X.st, s.logN, logM, X.F, tb, s0, s1, s2);
+      hipLaunchKernelGGL(k_row<13>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], X.F,
+                         tb, s0, s1, s2);
     else
-      hipLaunchKernelGGL(k_row<14>, grid, block, 0, X.st, s.logN, logM, X.F, tb, s0, s1, s2);
+      hipLaunchKernelGGL(k_row<14>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], X.F,
+                         tb, s0, s1, s2);
   }
   LAUNCHCHK();
   for (int k = pp.P - 1; k >= 0; k--) {
@@ -1079,10 +1082,10 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     KTime kt("k_pass_inv", X.st, 3.0 * cnt * N / 2 * pp.logL[k]);
     if (logT == NTT_COL_LOGT_SMALL)
       hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT_SMALL>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st,
-                         dv, pg, k == 0 ? 1 : 0, X.F, X.res, X.res_stride, tb);
+                         dv, pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, X.F, X.res, X.res_stride, tb);
     else
       hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                         pg, k == 0 ? 1 : 0, X.F, X.res, X.res_stride, tb);
+                         pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, X.F, X.res, X.res_stride, tb);
     LAUNCHCHK();
   }
   X.launches += 2 * pp.P + 1;

@@ -440,8 +440,8 @@ struct PassGeom {
 
 template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
-k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
-           uint32_t* __restrict__ F, NttTables tb) {
+k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, const uint32_t* __restrict__ ain,
+           const uint32_t* __restrict__ bin, uint32_t* __restrict__ F, NttTables tb) {
   __shared__ uint32_t lds[1u << LOGT];
   // x: (tile, prime) pairs, XCD-contiguous; the three primes of a tile of the
   // first pass read the same operand words
@@ -497,6 +497,12 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
   __syncthreads();
   ntt_fwd_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
   __syncthreads();
+  if (!tw) {
+    // the pass next to the rows: k_row applies this pass's twiddles
+    for (uint32_t t = threadIdx.x; t < T; t += NTT_COL_THREADS)
+      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+    return;
+  }
   const uint2* lo = tb.tw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.tw2hi + (size_t)prime * TW2_HI;
   const uint32_t ysh = CAT_MAX_LOGN - pg.logS;
@@ -528,7 +534,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, const uint32_t* __restrict__ ain
 
 template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
-k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_t* __restrict__ res,
+k_pass_inv(DescView dv, PassGeom pg, int last, int tw, uint32_t* __restrict__ F, uint32_t* __restrict__ res,
            uint64_t res_stride, NttTables tb) {
   __shared__ uint32_t lds[1u << LOGT];
   __shared__ uint32_t fq[1u << NTT_COL_MAXL];    // frequency at each output row
@@ -546,6 +552,23 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
   const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
   const uint32_t ysh = CAT_MAX_LOGN - pg.logS;
+  if (!tw) {
+    // the pass next to the rows: k_row applied this pass's twiddles
+    for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+      uint32_t v[COL_BATCH];
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        const uint32_t tc = t < T ? t : T - 1;
+        v[i] = f[base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1))];
+      }
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        if (t < T) lds[t] = v[i];
+      }
+    }
+  } else {
   for (uint32_t q = threadIdx.x; q < (1u << pg.logL); q += blockDim.x) fq[q] = out_freq(q, pg.logL);
   __syncthreads();
   for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
@@ -570,6 +593,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
       }
     }
   }
+  }
   __syncthreads();
   ntt_inv_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   if (!last) {
@@ -593,7 +617,8 @@ k_pass_inv(DescView dv, PassGeom pg, int last, uint32_t* __restrict__ F, uint32_
 // Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
 template <int LOGT>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
-k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
+k_row(int logN, int logM, int logSl, int logLl, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1,
+      uint2 scale2) {
   constexpr uint32_t TT = 1u << LOGT;
   __shared__ uint32_t lds[lds_pad(2 * TT)];
   const uint32_t prime = blockIdx.y;
@@ -607,6 +632,17 @@ k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, 
   uint32_t* fa = F + ((m * 3 + prime) * 2 + 0) * N + ((uint64_t)q << logM);
   uint32_t* fb = F + ((m * 3 + prime) * 2 + 1) * N + ((uint64_t)q << logM);
   constexpr uint32_t NT = TT / 16;                 // blockDim.x
+  // The twiddles of the column pass next to the rows (sub-problems of
+  // S = 2^logSl, rows of L = 2^logLl): position j of row q takes
+  // omega_S^(j f) with f the frequency of q within its sub-problem, and the
+  // inverse on the way back.  A thread's positions j = tid + i NT form a
+  // geometric sequence: w_i = w_0 R^i, R = omega_S^(NT f).
+  const uint32_t fr = out_freq(q & ((1u << logLl) - 1), logLl);
+  const uint32_t ysh = CAT_MAX_LOGN - logSl, ymask = (1u << CAT_MAX_LOGN) - 1;
+  const uint2* flo = tb.tw2lo + (size_t)prime * TW2_LO;
+  const uint32_t* fhi = tb.tw2hi + (size_t)prime * TW2_HI;
+  uint2 w = tw2(flo, fhi, ((threadIdx.x * fr) << ysh) & ymask, pc);
+  const uint2 R = tw2(flo, fhi, ((NT * fr) << ysh) & ymask, pc);
   if (M == TT) {
     // full rows: all 32 loads of the thread in flight before the first use
     uint32_t va[16], vb[16];
@@ -617,13 +653,17 @@ k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, 
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-      lds[lds_pad(threadIdx.x + i * NT)] = va[i];
-      lds[lds_pad(TT + threadIdx.x + i * NT)] = vb[i];
+      lds[lds_pad(threadIdx.x + i * NT)] = mul_tw(va[i], w.x, w.y, p);
+      lds[lds_pad(TT + threadIdx.x + i * NT)] = mul_tw(vb[i], w.x, w.y, p);
+      w.x = mul_tw(w.x, R.x, R.y, p);
+      w.y = w.x * pc.pinv;
     }
   } else {
     for (uint32_t t = threadIdx.x; t < M; t += NT) {
-      lds[lds_pad(t)] = fa[t];
-      lds[lds_pad(M + t)] = fb[t];
+      lds[lds_pad(t)] = mul_tw(fa[t], w.x, w.y, p);
+      lds[lds_pad(M + t)] = mul_tw(fb[t], w.x, w.y, p);
+      w.x = mul_tw(w.x, R.x, R.y, p);
+      w.y = w.x * pc.pinv;
     }
   }
   __syncthreads();
@@ -648,7 +688,15 @@ k_row(int logN, int logM, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, 
     __syncthreads();
   }
   ntt_inv_tile<true>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
-  for (uint32_t t = threadIdx.x; t < M; t += NT) fa[t] = lds[lds_pad(t)];
+  const uint2* ilo = tb.itw2lo + (size_t)prime * TW2_LO;
+  const uint32_t* ihi = tb.itw2hi + (size_t)prime * TW2_HI;
+  uint2 wi = tw2(ilo, ihi, ((threadIdx.x * fr) << ysh) & ymask, pc);
+  const uint2 Ri = tw2(ilo, ihi, ((NT * fr) << ysh) & ymask, pc);
+  for (uint32_t t = threadIdx.x; t < M; t += NT) {
+    fa[t] = mul_tw(lds[lds_pad(t)], wi.x, wi.y, p);
+    wi.x = mul_tw(wi.x, Ri.x, Ri.y, p);
+    wi.y = wi.x * pc.pinv;
+  }
 }
 
 // ---------------------------------------------------------------------------
