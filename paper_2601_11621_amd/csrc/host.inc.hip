@@ -1046,17 +1046,27 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
   const PassPlan pp = pass_plan(s.logN, s.logM, s.maxL, logT);
   const int logM = s.logM, logR1 = s.logN - logM;
   const double N = (double)(1ull << s.logN);
+  // The twiddles of pass k are applied by pass k itself (forward: at its
+  // store; inverse: at its load), or, when the next pass's tiles have at most
+  // 256 columns (a thread's positions then advance by a constant step), by
+  // pass k + 1 (forward: at its load; inverse: at its store); those of the
+  // last pass by k_row.
+  bool defer[8] = {};
+  for (int k = 0; k + 1 < pp.P; k++) defer[k] = pp.logC[k + 1] <= 8;
+  auto self_tw = [&](int k) { return (k + 1 < pp.P && !defer[k]) ? 1 : 0; };
+  auto pre_tw = [&](int k) { return (k >= 1 && defer[k - 1]) ? 1 : 0; };
   for (int k = 0; k < pp.P; k++) {
     PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
+    const int plS = k >= 1 ? pp.logS[k - 1] : 0, plL = k >= 1 ? pp.logL[k - 1] : 0;
     const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
     // L-point DFTs of both operands, 3 primes: (N/2) log2 L butterflies each
     KTime kt("k_pass_fwd", X.st, 6.0 * cnt * N / 2 * pp.logL[k]);
     if (logT == NTT_COL_LOGT_SMALL)
       hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0,
-                         X.st, dv, pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, ain, bin, X.F, tb);
+                         X.st, dv, pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, ain, bin, X.F, tb);
     else
       hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0, X.st,
-                         dv, pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, ain, bin, X.F, tb);
+                         dv, pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, ain, bin, X.F, tb);
     LAUNCHCHK();
   }
   {
@@ -1078,14 +1088,15 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
   LAUNCHCHK();
   for (int k = pp.P - 1; k >= 0; k--) {
     PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
+    const int plS = k >= 1 ? pp.logS[k - 1] : 0, plL = k >= 1 ? pp.logL[k - 1] : 0;
     const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
     KTime kt("k_pass_inv", X.st, 3.0 * cnt * N / 2 * pp.logL[k]);
     if (logT == NTT_COL_LOGT_SMALL)
       hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT_SMALL>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st,
-                         dv, pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, X.F, X.res, X.res_stride, tb);
+                         dv, pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, X.F, X.res, X.res_stride, tb);
     else
       hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                         pg, k == 0 ? 1 : 0, k + 1 < pp.P ? 1 : 0, X.F, X.res, X.res_stride, tb);
+                         pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, X.F, X.res, X.res_stride, tb);
     LAUNCHCHK();
   }
   X.launches += 2 * pp.P + 1;

@@ -440,8 +440,9 @@ struct PassGeom {
 
 template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
-k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, const uint32_t* __restrict__ ain,
-           const uint32_t* __restrict__ bin, uint32_t* __restrict__ F, NttTables tb) {
+k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int plogL,
+           const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin, uint32_t* __restrict__ F,
+           NttTables tb) {
   __shared__ uint32_t lds[1u << LOGT];
   // x: (tile, prime) pairs, XCD-contiguous; the three primes of a tile of the
   // first pass read the same operand words
@@ -479,6 +480,19 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, const uint32_t* __restri
       }
     }
   } else {
+    // pre: this sub-problem is row q' of the previous pass's sub-problem, which
+    // left its twiddles omega_{S'}^(j f(q')) to this load; with C <= 256 a
+    // thread's positions j advance by a constant step, so the twiddle does too
+    uint2 w = make_uint2(0, 0), R = make_uint2(0, 0);
+    if (pre) {
+      const uint32_t fr = out_freq((uint32_t)(base >> pg.logS) & ((1u << plogL) - 1), plogL);
+      const uint32_t ysh = CAT_MAX_LOGN - plogS, ymask = (1u << CAT_MAX_LOGN) - 1;
+      const uint2* plo = tb.tw2lo + (size_t)prime * TW2_LO;
+      const uint32_t* phi = tb.tw2hi + (size_t)prime * TW2_HI;
+      const uint32_t jt = ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1));
+      w = tw2(plo, phi, ((jt * fr) << ysh) & ymask, pc);
+      R = tw2(plo, phi, ((((NTT_COL_THREADS >> pg.logC) << logSig) * fr) << ysh) & ymask, pc);
+    }
     for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
       uint32_t v[COL_BATCH];
 #pragma unroll
@@ -490,6 +504,11 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, const uint32_t* __restri
 #pragma unroll
       for (int i = 0; i < COL_BATCH; i++) {
         const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        if (pre) {
+          v[i] = mul_tw(v[i], w.x, w.y, p);
+          w.x = mul_tw(w.x, R.x, R.y, p);
+          w.y = w.x * pc.pinv;
+        }
         if (t < T) lds[t] = v[i];
       }
     }
@@ -534,8 +553,8 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, const uint32_t* __restri
 
 template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
-k_pass_inv(DescView dv, PassGeom pg, int last, int tw, uint32_t* __restrict__ F, uint32_t* __restrict__ res,
-           uint64_t res_stride, NttTables tb) {
+k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int plogL, uint32_t* __restrict__ F,
+           uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb) {
   __shared__ uint32_t lds[1u << LOGT];
   __shared__ uint32_t fq[1u << NTT_COL_MAXL];    // frequency at each output row
   const uint32_t T = 1u << (pg.logL + pg.logC);
@@ -597,8 +616,25 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, uint32_t* __restrict__ F,
   __syncthreads();
   ntt_inv_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   if (!last) {
-    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
-      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+    if (!post) {
+      for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
+        f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+      return;
+    }
+    // post: the inverse twiddles of the previous (outer) pass, at the same
+    // positions the forward load of this pass took them, by the same steps
+    const uint32_t fr = out_freq((uint32_t)(base >> pg.logS) & ((1u << plogL) - 1), plogL);
+    const uint32_t ysh2 = CAT_MAX_LOGN - plogS, ymask = (1u << CAT_MAX_LOGN) - 1;
+    const uint2* plo = tb.itw2lo + (size_t)prime * TW2_LO;
+    const uint32_t* phi = tb.itw2hi + (size_t)prime * TW2_HI;
+    const uint32_t jt = ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1));
+    uint2 w = tw2(plo, phi, ((jt * fr) << ysh2) & ymask, pc);
+    const uint2 R = tw2(plo, phi, ((((NTT_COL_THREADS >> pg.logC) << logSig) * fr) << ysh2) & ymask, pc);
+    for (uint32_t t = threadIdx.x; t < T; t += NTT_COL_THREADS) {
+      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = mul_tw(lds[t], w.x, w.y, p);
+      w.x = mul_tw(w.x, R.x, R.y, p);
+      w.y = w.x * pc.pinv;
+    }
     return;
   }
   // the outermost pass: positions are coefficient indices; write exact residues
