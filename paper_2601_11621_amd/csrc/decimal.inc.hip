@@ -50,15 +50,15 @@ __device__ __forceinline__ void dec_split(uint32_t r0, uint32_t r1, uint32_t r2,
   const uint32_t q1 = div_b(r, v1, &r);
   const uint32_t q0 = div_b(r, v0, &r);
   c[0] = r;
-  // (q2, q1, q0) / B: q2 <= 4, and the quotient is below 2^37
-  const uint32_t p2 = div_b(0, q2, &r);
+  // (q2, q1, q0) = floor(V / B) < 2^96 / B < 2^67, so q2 < 8 < B: the
+  // division of the top word is q2 = 0 B + q2
+  r = q2;
   const uint32_t p1 = div_b(r, q1, &r);
   const uint32_t p0 = div_b(r, q0, &r);
   c[1] = r;
-  (void)p2;   // zero
-  const uint32_t s1 = div_b(0, p1, &r);
+  // (p1, p0) < 2^67 / B < 2^38, so p1 < 2^6 < B likewise
+  r = p1;
   const uint32_t s0 = div_b(r, p0, &r);
-  (void)s1;   // zero
   c[2] = r;
   c[3] = s0;
 }
