@@ -1055,35 +1055,62 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
   for (int k = 0; k + 1 < pp.P; k++) defer[k] = pp.logC[k + 1] <= 8;
   auto self_tw = [&](int k) { return (k + 1 < pp.P && !defer[k]) ? 1 : 0; };
   auto pre_tw = [&](int k) { return (k >= 1 && defer[k - 1]) ? 1 : 0; };
+  // A second operand that is the same for every product (the power P_j of a
+  // decimal join) is transformed once: its column passes for product 0 only,
+  // its row transforms once (k_row mode 1), reused by every product (mode 2).
+  const bool constb = dv.uni && dv.u.sb == 0 && cnt > 1;
+  auto pass_fwd = [&](const PassGeom& pg, int k, int plS, int plL, uint64_t gx, uint32_t nop, int op_base) {
+    const dim3 grid((uint32_t)(gx * CAT_NPRIMES), 1, nop);
+    if (logT == NTT_COL_LOGT_SMALL)
+      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, grid, dim3(NTT_COL_THREADS), 0, X.st, dv, pg, k == 0 ? 1 : 0,
+                         self_tw(k), pre_tw(k), plS, plL, op_base, ain, bin, X.F, tb);
+    else
+      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, grid, dim3(NTT_COL_THREADS), 0, X.st, dv, pg, k == 0 ? 1 : 0,
+                         self_tw(k), pre_tw(k), plS, plL, op_base, ain, bin, X.F, tb);
+  };
   for (int k = 0; k < pp.P; k++) {
     PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
     const int plS = k >= 1 ? pp.logS[k - 1] : 0, plL = k >= 1 ? pp.logL[k - 1] : 0;
-    const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
+    const uint64_t gx1 = 1ull << (s.logN - pp.logL[k] - pp.logC[k]);   // tiles of one product
+    const uint64_t gx = cnt * gx1;
     // L-point DFTs of both operands, 3 primes: (N/2) log2 L butterflies each
-    KTime kt("k_pass_fwd", X.st, 6.0 * cnt * N / 2 * pp.logL[k]);
-    if (logT == NTT_COL_LOGT_SMALL)
-      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0,
-                         X.st, dv, pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, ain, bin, X.F, tb);
-    else
-      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, dim3((uint32_t)(gx * CAT_NPRIMES), 1, 2), dim3(NTT_COL_THREADS), 0, X.st,
-                         dv, pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, ain, bin, X.F, tb);
+    KTime kt("k_pass_fwd", X.st, (constb ? 3.0 * (cnt + 1) : 6.0 * cnt) * N / 2 * pp.logL[k]);
+    if (constb) {
+      pass_fwd(pg, k, plS, plL, gx, 1, 0);
+      LAUNCHCHK();
+      pass_fwd(pg, k, plS, plL, gx1, 1, 1);
+    } else {
+      pass_fwd(pg, k, plS, plL, gx, 2, 0);
+    }
     LAUNCHCHK();
+    if (constb) X.launches++;
   }
   {
     // row DFTs: two forward and one inverse per row, 3 primes
     const double rows = (double)cnt * (1ull << logR1);
     const int lt = std::max(logM, CAT_LDS_LOGT);
-    const dim3 grid((uint32_t)(cnt << logR1), CAT_NPRIMES), block((1u << lt) / 16);
-    KTime kt("k_row", X.st, bfly(9.0 * rows, logM));
-    if (lt == 12)
-      hipLaunchKernelGGL(k_row<12>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], X.F,
-                         tb, s0, s1, s2);
-    else if (lt == 13)
-      hipLaunchKernelGGL(k_row<13>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], X.F,
-                         tb, s0, s1, s2);
-    else
-      hipLaunchKernelGGL(k_row<14>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], X.F,
-                         tb, s0, s1, s2);
+    const dim3 block((1u << lt) / 16);
+    auto row = [&](uint64_t nprod, int bmode) {
+      const dim3 grid((uint32_t)(nprod << logR1), CAT_NPRIMES);
+      if (lt == 12)
+        hipLaunchKernelGGL(k_row<12>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], bmode,
+                           X.F, tb, s0, s1, s2);
+      else if (lt == 13)
+        hipLaunchKernelGGL(k_row<13>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], bmode,
+                           X.F, tb, s0, s1, s2);
+      else
+        hipLaunchKernelGGL(k_row<14>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], bmode,
+                           X.F, tb, s0, s1, s2);
+    };
+    KTime kt("k_row", X.st, constb ? bfly(6.0 * rows + 3.0 * (1ull << logR1), logM) : bfly(9.0 * rows, logM));
+    if (constb) {
+      row(1, 1);
+      LAUNCHCHK();
+      X.launches++;
+      row(cnt, 2);
+    } else {
+      row(cnt, 0);
+    }
   }
   LAUNCHCHK();
   for (int k = pp.P - 1; k >= 0; k--) {

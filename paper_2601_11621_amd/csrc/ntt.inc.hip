@@ -440,14 +440,14 @@ struct PassGeom {
 
 template <int LOGT>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
-k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int plogL,
+k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int plogL, int op_base,
            const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin, uint32_t* __restrict__ F,
            NttTables tb) {
   __shared__ uint32_t lds[1u << LOGT];
   // x: (tile, prime) pairs, XCD-contiguous; the three primes of a tile of the
   // first pass read the same operand words
   const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t prime = wid % CAT_NPRIMES, op = blockIdx.z;
+  const uint32_t prime = wid % CAT_NPRIMES, op = op_base + blockIdx.z;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
   uint64_t m, base;
@@ -653,8 +653,13 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
 // Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
 template <int LOGT>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
-k_row(int logN, int logM, int logSl, int logLl, uint32_t* __restrict__ F, NttTables tb, uint2 scale0, uint2 scale1,
-      uint2 scale2) {
+// bmode 0: both operands per product.  A stage whose second operand is the
+// same for every product computes that operand's row transforms once:
+// bmode 1 (rows of product 0 only) transforms them and stores the tile as it
+// stands in LDS; bmode 2 then loads it into the second half for every
+// product and transforms only the first operand.
+k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict__ F, NttTables tb, uint2 scale0,
+      uint2 scale1, uint2 scale2) {
   constexpr uint32_t TT = 1u << LOGT;
   __shared__ uint32_t lds[lds_pad(2 * TT)];
   const uint32_t prime = blockIdx.y;
@@ -666,7 +671,7 @@ k_row(int logN, int logM, int logSl, int logLl, uint32_t* __restrict__ F, NttTab
   const uint64_t m = blockIdx.x >> logR1;
   const uint32_t q = blockIdx.x & ((1u << logR1) - 1);
   uint32_t* fa = F + ((m * 3 + prime) * 2 + 0) * N + ((uint64_t)q << logM);
-  uint32_t* fb = F + ((m * 3 + prime) * 2 + 1) * N + ((uint64_t)q << logM);
+  uint32_t* fb = F + (((bmode ? 0 : m) * 3 + prime) * 2 + 1) * N + ((uint64_t)q << logM);
   constexpr uint32_t NT = TT / 16;                 // blockDim.x
   // The twiddles of the column pass next to the rows (sub-problems of
   // S = 2^logSl, rows of L = 2^logLl): position j of row q takes
@@ -679,7 +684,27 @@ k_row(int logN, int logM, int logSl, int logLl, uint32_t* __restrict__ F, NttTab
   const uint32_t* fhi = tb.tw2hi + (size_t)prime * TW2_HI;
   uint2 w = tw2(flo, fhi, ((threadIdx.x * fr) << ysh) & ymask, pc);
   const uint2 R = tw2(flo, fhi, ((NT * fr) << ysh) & ymask, pc);
-  if (M == TT) {
+  const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
+  if (bmode == 1) {
+    for (uint32_t t = threadIdx.x; t < M; t += NT) {
+      lds[lds_pad(t)] = mul_tw(fb[t], w.x, w.y, p);
+      w.x = mul_tw(w.x, R.x, R.y, p);
+      w.y = w.x * pc.pinv;
+    }
+    __syncthreads();
+    ntt_fwd_tile<true>(lds, logM, M, 0, tws, pc);
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < M; t += NT) fb[t] = lds[lds_pad(t)];
+    return;
+  }
+  if (bmode == 2) {
+    for (uint32_t t = threadIdx.x; t < M; t += NT) {
+      lds[lds_pad(t)] = mul_tw(fa[t], w.x, w.y, p);
+      lds[lds_pad(M + t)] = fb[t];
+      w.x = mul_tw(w.x, R.x, R.y, p);
+      w.y = w.x * pc.pinv;
+    }
+  } else if (M == TT) {
     // full rows: all 32 loads of the thread in flight before the first use
     uint32_t va[16], vb[16];
 #pragma unroll
@@ -703,8 +728,7 @@ k_row(int logN, int logM, int logSl, int logLl, uint32_t* __restrict__ F, NttTab
     }
   }
   __syncthreads();
-  const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
-  ntt_fwd_tile<true>(lds, logM, 2 * M, 0, tws, pc);
+  ntt_fwd_tile<true>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
   if (M == TT) {
     // thread g wrote A and B at [16 g, 16 g + 16): pointwise in place, and the
