@@ -157,6 +157,8 @@ cat_status make_dec_plan(uint64_t L, DecPlan* D) {
   auto scratch = [&](const Stage& s, uint64_t* res_len, uint64_t* F_words, uint64_t* nblk_max) {
     *res_len = std::max<uint64_t>(*res_len, s.limbs);
     if (s.cls == CLS_LARGE) *F_words = std::max<uint64_t>(*F_words, s.nmul * 6ull << s.logN);
+    // a join's common second operand, transformed once per prime
+    if (s.cls == CLS_LDS && s.nmul > 1) *F_words = std::max<uint64_t>(*F_words, 3ull << s.logN);
     *nblk_max = std::max<uint64_t>(*nblk_max, s.nblk);
     P.products += s.nmul;
     P.product_digits += s.limbs;
@@ -174,8 +176,8 @@ cat_status make_dec_plan(uint64_t L, DecPlan* D) {
   P.off_F = takeb(P.F_words * 4);
   P.off_res2 = takeb(3 * (P.res2_len + 64) * 4);
   P.off_F2 = takeb(P.F2_words * 4);
-  // control block: error word | top index (8 bytes) | look-back flags of the
-  // joins | those of the squarings
+  // control block: error word | top index (8 bytes) | character count (8
+  // bytes) | look-back flags of the joins | those of the squarings
   P.ctl_words = 6 + (P.nblk_max + 1) + (P.nblk2_max + 1);
   P.off_ctl = takeb(P.ctl_words * 4);
   P.total = off;

@@ -1027,16 +1027,29 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     const uint64_t per = (1ull << lt) >> s.logN;
     const uint64_t tiles = (cnt + per - 1) / per;
     const dim3 grid((uint32_t)(tiles * CAT_NPRIMES)), block((1u << lt) / 16);
-    KTime kt("k_ntt_lds", X.st, bfly(9.0 * cnt, s.logN));
-    if (lt == 12)
-      hipLaunchKernelGGL(k_ntt_lds<12>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
-                         s1, s2);
-    else if (lt == 13)
-      hipLaunchKernelGGL(k_ntt_lds<13>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
-                         s1, s2);
-    else
-      hipLaunchKernelGGL(k_ntt_lds<14>, grid, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0,
-                         s1, s2);
+    // a second operand common to all products (decimal joins): transformed
+    // once per prime into the stage scratch, then reused, where the stage is
+    // large enough for the saved transforms to outweigh the extra launch
+    const bool constb = dv.uni && dv.u.sb == 0 && cnt > 1 && (cnt << s.logN) >= (1ull << 21);
+    KTime kt("k_ntt_lds", X.st, constb ? bfly(6.0 * cnt + 3.0, s.logN) : bfly(9.0 * cnt, s.logN));
+#define LDS_LAUNCH(LT, BM, G)                                                                                      \
+  hipLaunchKernelGGL((k_ntt_lds<LT, BM>), G, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0, \
+                     s1, s2, X.F)
+    if (constb) {
+      if (lt == 12) LDS_LAUNCH(12, 1, dim3(CAT_NPRIMES));
+      else if (lt == 13) LDS_LAUNCH(13, 1, dim3(CAT_NPRIMES));
+      else LDS_LAUNCH(14, 1, dim3(CAT_NPRIMES));
+      LAUNCHCHK();
+      X.launches++;
+      if (lt == 12) LDS_LAUNCH(12, 2, grid);
+      else if (lt == 13) LDS_LAUNCH(13, 2, grid);
+      else LDS_LAUNCH(14, 2, grid);
+    } else {
+      if (lt == 12) LDS_LAUNCH(12, 0, grid);
+      else if (lt == 13) LDS_LAUNCH(13, 0, grid);
+      else LDS_LAUNCH(14, 0, grid);
+    }
+#undef LDS_LAUNCH
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;

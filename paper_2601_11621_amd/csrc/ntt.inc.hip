@@ -318,10 +318,11 @@ struct NttTables {
 // is 3 x tiles workgroups; workgroup ids are renumbered so that each XCD takes
 // a contiguous run of (tile, prime) pairs: the three primes of a tile run one
 // after another on one XCD and read the operands once from HBM into its L2.
-template <int LOGT>
+template <int LOGT, int BMODE>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
 k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
-          uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2) {
+          uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2,
+          uint32_t* __restrict__ fb) {
   constexpr uint32_t TT = 1u << LOGT;
   __shared__ uint32_t lds[lds_pad(2 * TT)];
   __shared__ MulDesc ds[64];
@@ -336,6 +337,22 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ds[i] = dv.get(m0 + i);
   __syncthreads();
   const uint32_t T = cnt << logN;                  // live slots
+  const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
+  const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
+  // A second operand that is the same for every product (the power P_j of a
+  // decimal join): BMODE 1 (one workgroup per prime) transforms it once and
+  // stores the N words as they stand in LDS to fb[prime][.]; BMODE 2 loads
+  // them into every product's slot and transforms only the first operands.
+  if constexpr (BMODE == 1) {
+    const MulDesc d = ds[0];
+    for (uint32_t t = threadIdx.x; t < N; t += blockDim.x)
+      lds[lds_pad(t)] = reduce_limb(t < d.lb ? bin[d.b_off + t] : 0u, p);
+    __syncthreads();
+    ntt_fwd_tile<true>(lds, logN, N, 0, tws, pc);
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < N; t += blockDim.x) fb[(size_t)prime * N + t] = lds[lds_pad(t)];
+    return;
+  }
   {
     // every load of the thread is issued before the first is used: clamped,
     // in-bounds addresses and masks instead of branches around the loads
@@ -349,22 +366,25 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
       const MulDesc d = ds[m];
       const uint32_t ka = j < d.la ? 0xFFFFFFFFu : 0u, kb = j < d.lb ? 0xFFFFFFFFu : 0u;
       xa[i] = ain[d.a_off + (j & ka)] & ka;
-      xb[i] = bin[d.b_off + (j & kb)] & kb;
+      if constexpr (BMODE == 2)
+        xb[i] = fb[(size_t)prime * N + j];
+      else
+        xb[i] = bin[d.b_off + (j & kb)] & kb;
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
       const uint32_t t = threadIdx.x + i * NT;
       lds[lds_pad(t)] = reduce_limb(xa[i], p);
-      lds[lds_pad(TT + t)] = reduce_limb(xb[i], p);
+      lds[lds_pad(TT + t)] = BMODE == 2 ? xb[i] : reduce_limb(xb[i], p);
     }
   }
   // slots past T of a partial tile repeat the last live slot; their
   // sub-problems are independent and never read back
   __syncthreads();
-  const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
-  const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
   // A occupies [0, T), B [TT, TT + T); transform both as one tile
-  if (T == TT) {
+  if (BMODE == 2) {
+    ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
+  } else if (T == TT) {
     ntt_fwd_tile<true>(lds, logN, 2 * TT, 0, tws, pc);
   } else {
     ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
