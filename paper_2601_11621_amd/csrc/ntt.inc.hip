@@ -310,11 +310,15 @@ struct NttTables {
 };
 
 // ---------------------------------------------------------------------------
-// Whole product in one workgroup, N = 2^logN <= 2^12.  The tile holds
-// T = 2^12 coefficient slots = T/N products; grid (tiles, prime).
+// Whole product in one workgroup, N = 2^logN <= 2^LOGT <= 2^14.
 // Writes res[prime][r_off + j] = (a*b)_j mod p for j < la+lb.
 // Tile of 2^LOGT coefficient slots (T/N products), 2^LOGT/16 threads, so every
-// radix-16 pass gives each thread two groups over the two operands.  The grid
+// radix-16 pass gives each thread two groups over the two operands.
+// BMODE 0: both operands per product.  BMODE 1 and 2 serve a stage whose
+// second operand is one array for every product: mode 1, launched with one
+// workgroup per prime, leaves its transform in fb[prime][0 .. N); mode 2
+// loads that beside each first operand and transforms only the latter.  The
+// grid
 // is 3 x tiles workgroups; workgroup ids are renumbered so that each XCD takes
 // a contiguous run of (tile, prime) pairs: the three primes of a tile run one
 // after another on one XCD and read the operands once from HBM into its L2.
@@ -382,7 +386,7 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   // sub-problems are independent and never read back
   __syncthreads();
   // A occupies [0, T), B [TT, TT + T); transform both as one tile
-  if (BMODE == 2) {
+  if constexpr (BMODE == 2) {
     ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
   } else if (T == TT) {
     ntt_fwd_tile<true>(lds, logN, 2 * TT, 0, tws, pc);
