@@ -969,7 +969,7 @@ cat_status launch_crt10(Exec& X, uint32_t* out, const SegView& sv, uint32_t nblk
   {
     KTime kt("k_crt10", X.st, (double)nblk * DEC_CRT_BLOCK);
     X.crt_epoch++;
-    hipLaunchKernelGGL(k_crt10, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.W, nblk,
+    hipLaunchKernelGGL(k_crt10, dim3(grid), dim3(DEC_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, X.W, nblk,
                        X.flags, X.crt_epoch, crt_polls(nblk), *tails, tin, tout, X.err);
   }
   LAUNCHCHK();
@@ -1015,7 +1015,7 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     }
     if (nblk == 0) return CAT_OK;
     KTime kt("k_colsum", X.st, (double)nblk * COLSUM_COLS);
-    hipLaunchKernelGGL(k_colsum, dim3(nblk), dim3(256), 0, X.st, dv, sv, ain, bin, X.res, X.res_stride, X.err);
+    hipLaunchKernelGGL(k_colsum, dim3(nblk), dim3(COLSUM_T), 0, X.st, dv, sv, ain, bin, X.res, X.res_stride, X.err);
     LAUNCHCHK();
     X.launches++;
     return CAT_OK;

@@ -69,7 +69,8 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
 // per 32x32 product.
 #define COLSUM_MAX_LB 1024
 #define COLSUM_E CAT_CRT_E
-#define COLSUM_COLS (COLSUM_E * 256)
+#define COLSUM_T CAT_CRT_THREADS
+#define COLSUM_COLS (COLSUM_E * COLSUM_T)
 static_assert(COLSUM_COLS == CAT_CRT_BLOCK, "column-sum blocks are the CRT blocks");
 __device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
@@ -136,7 +137,7 @@ __device__ __forceinline__ void mac_cols(uint64_t* acc, uint32_t* top, const uin
   if constexpr (E == 4)
     colsum_mac4(acc[0], acc[1], acc[2], acc[3], top[0], top[1], top[2], top[3], w[0], w[1], w[2], w[3], bj);
 }
-__global__ void __launch_bounds__(256) k_colsum(DescView dv, SegView sv, const uint32_t* __restrict__ ain,
+__global__ void __launch_bounds__(COLSUM_T) k_colsum(DescView dv, SegView sv, const uint32_t* __restrict__ ain,
                                                 const uint32_t* __restrict__ bin, uint32_t* __restrict__ res,
                                                 uint64_t stride, uint32_t* __restrict__ err) {
   // lb rounded up to even (b padded with a zero limb); sw[t] = a[kb - lbe + t]
@@ -161,11 +162,11 @@ __global__ void __launch_bounds__(256) k_colsum(DescView dv, SegView sv, const u
   const uint32_t kb = (uni32(blockIdx.x) - uni32(first)) * COLSUM_COLS;
   const uint32_t lbe = (lb + 1) & ~1u;
   const uint32_t wn = COLSUM_COLS + lbe;
-  for (uint32_t i = tid; i < wn; i += 256) {
+  for (uint32_t i = tid; i < wn; i += COLSUM_T) {
     const int64_t idx = (int64_t)kb - (int64_t)lbe + i;
     sw[i] = (idx >= 0 && idx < (int64_t)la) ? a[idx] : 0u;
   }
-  for (uint32_t i = tid; i < lbe; i += 256) sbv[i] = i < lb ? b[i] : 0u;
+  for (uint32_t i = tid; i < lbe; i += COLSUM_T) sbv[i] = i < lb ? b[i] : 0u;
   __syncthreads();
   // column k = kb + COLSUM_E tid + e takes a[k - j] = sw[c0 + e - j]; the
   // reads for j + 1 and j + 2 at the last pair (down to sw[COLSUM_E tid])
