@@ -1248,11 +1248,15 @@ cat_status run_phase2(Exec& X, Plan& P, bool plain) {
   std::vector<Stage>& st = plain ? P.plain : P.batched;
   if (!plain && X.side && P.fork_count >= 0) {
     // Q_1's upper levels on st; the powers and R on the side stream with
-    // their own scratch; C = Q_1 R once both are done
+    // their own scratch; C = Q_1 R once both are done.  Q_1's levels are
+    // issued first: a graph submits its nodes in the order they were
+    // captured, and the short power steps issued first held the long levels
+    // back until the whole chain had run.
     const size_t nf = std::min<size_t>((size_t)P.fork_count, st.size());
     for (size_t k = 0; k < nf; k++) STCHK(run_stage_batched(X, st[k]));
     HIPCHK(hipEventRecord(g.ev_fork, X.st));
     HIPCHK(hipStreamWaitEvent(X.side, g.ev_fork, 0));
+    for (size_t k = nf; k < st.size(); k++) STCHK(run_stage_batched(X, st[k]));
     Exec S = X;
     S.st = X.side;
     S.res = X.res2;
@@ -1263,7 +1267,6 @@ cat_status run_phase2(Exec& X, Plan& P, bool plain) {
     S.launches = 0;
     for (size_t k = 0; k < P.post_final; k++) STCHK(run_stage_batched(S, P.post[k]));
     HIPCHK(hipEventRecord(g.ev_join, S.st));
-    for (size_t k = nf; k < st.size(); k++) STCHK(run_stage_batched(X, st[k]));
     HIPCHK(hipStreamWaitEvent(X.st, g.ev_join, 0));
     for (size_t k = P.post_final; k < P.post.size(); k++) STCHK(run_stage_batched(X, P.post[k]));
     X.launches += S.launches;
