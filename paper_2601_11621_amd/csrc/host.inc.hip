@@ -121,6 +121,14 @@ uint2 h_pair2(uint32_t W, const PrimeC& pc) {
   return r;
 }
 
+// Workgroups of the result length scan (k_top_nonzero, 256 threads, one
+// atomic each): 512 up to 2^24 limbs, then one per 2^15 limbs up to 4,096, so
+// that a long result is read by enough waves to reach HBM bandwidth.
+uint32_t top_scan_blocks(uint64_t cap) {
+  const uint64_t want = std::min<uint64_t>(std::max<uint64_t>(cap >> 15, 512), 4096);
+  return (uint32_t)std::max<uint64_t>(std::min<uint64_t>((cap + 255) / 256, want), 1);
+}
+
 uint64_t isqrt64(uint64_t x) {
   uint64_t r = (uint64_t)std::sqrt((double)x);
   while (r * r > x) r--;
@@ -1906,7 +1914,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
             Exec E = make_exec(Ly, wb, cs);
             E.side = g.side_stream;
             STCHK(run_phase2(E, *P, false));
-            const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+            const uint32_t blocks = top_scan_blocks(P->result_cap);
             const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
             hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, cs, E.W + P->result_pos, P->result_cap,
                                top, d_limbs, ncopy);
@@ -1967,7 +1975,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
   }
   auto record = [&](Exec& E) -> cat_status {
     STCHK(run_phase2(E, *P, plain));
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    const uint32_t blocks = top_scan_blocks(P->result_cap);
     hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top,
                        (uint32_t*)nullptr, (uint64_t)0);
     LAUNCHCHK();
@@ -2243,7 +2251,7 @@ cat_status catalan_continue(cat_ticket ticket, uint32_t* d_limbs, size_t cap) {
     LAUNCHCHK();
   } else {
     STCHK(run_phase2(X, *P, false));
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    const uint32_t blocks = top_scan_blocks(P->result_cap);
     const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
     hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, t->st, X.W + P->result_pos, P->result_cap, top,
                        d_limbs, ncopy);
@@ -2381,7 +2389,7 @@ cat_status factorial_ratio_exact(const uint64_t* a, uint32_t k, const uint64_t* 
   unsigned long long* top = (unsigned long long*)(wb + Ly.top);
   res = run_phase2(X, *P, plain);
   if (res == CAT_OK) {
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    const uint32_t blocks = top_scan_blocks(P->result_cap);
     const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
     hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, st, X.W + P->result_pos, P->result_cap, top, d_limbs,
                        ncopy);
@@ -2490,7 +2498,7 @@ cat_status prime_power_product(const uint32_t* d_entries, const uint32_t* h_exps
   unsigned long long* top = (unsigned long long*)(wb + Ly.top);
   res = run_phase2(X, *P, (flags & CAT_MODE_PLAIN) != 0);
   if (res == CAT_OK) {
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((P->result_cap + 255) / 256, 512);
+    const uint32_t blocks = top_scan_blocks(P->result_cap);
     const uint64_t ncopy = std::min<uint64_t>(P->result_cap, cap);
     hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, st, X.W + P->result_pos, P->result_cap, top, d_limbs,
                        ncopy);
