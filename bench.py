@@ -1,16 +1,21 @@
-"""Benchmark: exact C(n) on one MI355X (default n = 10,000,000).
+"""Benchmark: exact C(n) on one MI355X (default n = 2,050,572,903, the paper's
+Table 1 run).
 
 One step = one whole pass of the hot path: catalan_exact(n) — the device
 sieve with Legendre exponents (Phase 1) and the batched product tree with
-multi-prime NTT products (Phase 2) — launched as cached HIP graphs, with the
-result verified bit-exact against the oracle's digest before a time is kept.
+multi-prime NTT products (Phase 2) — launched as one cached HIP graph.  The
+result is verified before and after the timed steps: at n = 2,050,572,903
+against Table 1 (bit length, file size, digit count) and residue pins (the
+2-adic low limbs and C mod 2^32 - 5 from the oracle's definition-based
+routines, C mod 2^32 + 1 by Lucas' theorem, the top 64 bits from log-gamma);
+at smaller n bit for bit against the oracle's digest.
 
 Prints ONE JSON line.  `value` is the whole-step throughput in product limbs
 per second: the sum over every product of the tree (Q_e trees, powers, outer
-product) of la + lb, divided by the step time.  The unbatched form (one
-product per launch) is timed on the same GPU for the "vs plain" comparison,
-the dominant kernel is timed live with HIP events for the roofline, and the
-CPU oracle is timed on the host for the baseline.
+product) of la + lb, divided by the step time.  The same line carries the
+batched-vs-plain comparisons (C(10^7), C(10^8), the 4,096-product level
+batch), serving, the dominant kernel's roofline (timed live with HIP events)
+and the CPU oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -18,6 +23,8 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -29,13 +36,20 @@ sys.path.insert(0, ROOT)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_catalan.json")
 PROFILES = os.path.join(ROOT, "profiles")
 METRIC = "C(n) exact-reconstruction time; batched bigint-mul limbs/s vs plain, bit-exact"
+HEADLINE_N = 2050572903
 
-# MI355X figures: 256 CUs x 64 lanes x 2.4 GHz of 32-bit VALU issue; one modular
-# radix-2 butterfly of this library issues 14 VALU instructions (Montgomery
-# twiddle product: 3 multiplies + 4 other; modular add: 4; modular subtract: 3).
+# MI355X figures: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T 32-bit VALU lane
+# operations per second.  A radix-2 NTT butterfly with a precomputed-quotient
+# twiddle costs about 9 lane operations as an algorithm (3 multiplies plus
+# about 6 additions, subtractions and selects): that prices the butterfly
+# peak.  This library's own butterfly issues 14 instructions (the primes
+# exceed 2^31, which leaves no room for lazy reduction); the fraction against
+# that count is reported as a labelled secondary figure.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-BFLY_OPS = 14.0
+BFLY_OPS = 9.0
+BFLY_OPS_CODE = 14.0
 PEAK_BFLY = VALU_LANE_OPS / BFLY_OPS
+PEAK_BFLY_CODE = VALU_LANE_OPS / BFLY_OPS_CODE
 HBM_PEAK_GBS = 8000.0
 
 CANDIDATES = ["k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds", "k_crt", "k_school", "k_leaf"]
@@ -46,34 +60,63 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+_PINS = {}
+
+
+def largest_pins(n):
+    """Pins of C(n) where the oracle cannot multiply it out: Table 1 and the
+    stored residues (the oracle's definition-based routines), plus C mod
+    2^32 + 1 by Lucas' theorem and the bit length, digit count and top 64 bits
+    from log-gamma (computed here, once)."""
+    if n in _PINS:
+        return _PINS[n]
+    pz = os.path.join(ROOT, "tests", "golden", "pins_n%d.json" % n)
+    t1 = os.path.join(ROOT, "tests", "golden", "table1_n%d.json" % n)
+    if not (os.path.exists(pz) and os.path.exists(t1)):
+        _PINS[n] = None
+        return None
+    from tests import pins
+
+    with open(pz) as f:
+        pz = json.load(f)
+    with open(t1) as f:
+        t1 = json.load(f)
+    b2, digits, top64, _ = pins.log_pins(n, dps=80)
+    if b2 != t1["bit_length"] or digits != t1["decimal_digits"]:
+        raise SystemExit("bench: log-gamma pins disagree with Table 1")
+    _PINS[n] = {"bits": t1["bit_length"], "bytes": t1["result_file_bytes"], "digits": t1["decimal_digits"],
+                "limb0": pz["limb0"], "limb1": pz["limb1"], "mod_2p32_minus_5": pz["mod_2p32_minus_5"],
+                "mod_2p32_plus_1": pins.catalan_mod_composite(n, [641, 6700417]), "top64": top64}
+    return _PINS[n]
+
+
 def check_output(cat, t, n, gold):
     """Bit-exact check of a device result against the oracle digest, or, for
-    n = 2,050,572,903 (no oracle product), against Table 1's bit length and the
-    oracle's definition-based residues."""
+    the largest n (no oracle product), against Table 1 and the residue pins.
+    Returns the list of what was checked; raises SystemExit on a mismatch."""
     if gold is None:
-        pz = os.path.join(ROOT, "tests", "golden", "pins_n%d.json" % n)
-        t1 = os.path.join(ROOT, "tests", "golden", "table1_n%d.json" % n)
-        if not (os.path.exists(pz) and os.path.exists(t1)):
+        pz = largest_pins(n)
+        if pz is None:
             return None
-        with open(pz) as f:
-            pz = json.load(f)
-        with open(t1) as f:
-            t1 = json.load(f)
+        L = t.numel()
         top = int(t[-1].item()) & 0xFFFFFFFF
-        bits = 32 * (t.numel() - 1) + top.bit_length()
+        bits = 32 * (L - 1) + top.bit_length()
         low = cat.to_numpy(t[:2])
+        hi = cat.to_numpy(t[L - 2:])
         r = cat.residues(t)
-        ok = (bits == t1["bit_length"] and int(low[0]) == pz["limb0"] and int(low[1]) == pz["limb1"]
-              and r[0] == pz["mod_2p32_minus_5"])
+        ok = (bits == pz["bits"] and (bits + 7) // 8 == pz["bytes"] and int(low[0]) == pz["limb0"]
+              and int(low[1]) == pz["limb1"] and r[0] == pz["mod_2p32_minus_5"] and r[1] == pz["mod_2p32_plus_1"]
+              and (int(hi[1]) << 32 | int(hi[0])) == pz["top64"])
         if not ok:
             raise SystemExit("bench: C(%d) does NOT match Table 1 / residue pins" % n)
-        return True
+        return ["table1_bit_length", "table1_file_bytes", "limb0", "limb1", "mod_2^32-5", "mod_2^32+1",
+                "top64_log_gamma"]
     got = cat.to_numpy(t)
     h = hashlib.sha256(got.astype("<u4").tobytes()).hexdigest()
     ok = (len(got) == gold["n_limbs"] and h == gold["sha256_le_limbs"])
     if not ok:
         raise SystemExit("bench: C(%d) does NOT match the oracle digest" % n)
-    return True
+    return ["oracle_sha256_all_limbs"]
 
 
 def time_steps(cat, n, mode, steps, out):
@@ -381,8 +424,7 @@ def serving_bench(cat, count=1100, warm=100, slots=8, budget=16 << 30, frac=0.7)
 def steady_state(cat, kernel="k_ntt_lds", half=2048, count=1024, reps=10):
     """The transform kernel fed enough work to fill the GPU: one launch over
     `count` products of half x half limbs (N = 2 * half), timed per launch with
-    the library's event timer; butterflies per second against the VALU peak."""
-    import numpy as np
+    the library's event timer; butterflies per second against the peak."""
     import torch
 
     rng = np.random.default_rng(1)
@@ -403,27 +445,140 @@ def steady_state(cat, kernel="k_ntt_lds", half=2048, count=1024, reps=10):
     achieved = work / (kms / 1e3)
     return {"kernel": kernel, "workload": "%d products of %d x %d limbs (N = %d), one launch" % (count, half, half,
                                                                                               2 * half),
-            "avg_launch_ms": round(kms / launches, 5), "achieved": round(achieved / 1e12, 4),
-            "frac": round(achieved / PEAK_BFLY, 4)}
+            "avg_launch_ms": round(kms / launches, 5), "achieved_Tbfly_s": round(achieved / 1e12, 4),
+            "frac": round(achieved / PEAK_BFLY, 4), "frac_code_14_ops": round(achieved / PEAK_BFLY_CODE, 4)}
 
 
-def cpu_baseline(n, product_limbs):
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n_sample, limbs, gpu_limbs_per_s):
+    """The CPU oracle on a bounded sample of the workload: one full C(n_sample)
+    with every host thread and again with one thread.  `value` is product
+    limbs per second: `limbs` is the sum of la + lb over the product tree of
+    C(n_sample) (the GPU's count at that n; the oracle multiplies the same
+    factors in a tree of the same shape)."""
     import oracle
 
-    t0 = time.perf_counter()
-    c = oracle.catalan(n)
-    dt = time.perf_counter() - t0
+    res = {}
+    for threads in (oracle.num_threads(), 1):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        c = oracle.catalan(n_sample)
+        dt = time.perf_counter() - t0
+        res[threads] = (dt, len(c))
+    oracle.set_threads(0)
+    nt = max(res)
+    dt_all, L = res[nt]
     return {
-        "value": product_limbs / dt,
+        "value": limbs / dt_all,
         "unit": "limbs/s",
-        "cores": oracle.num_threads(),
+        "cores": nt,
         "kind": "oracle",
-        "sample": "one full C(%d) by the CPU oracle (trial-division primes, Legendre exponents, "
-                  "Karatsuba product tree, OpenMP over tree nodes): %.2f s; value = the GPU step's "
-                  "product limbs / that time" % (n, dt),
-        "seconds": round(dt, 3),
-        "limbs": int(len(c)),
+        "sample": "one full C(%d) by the CPU oracle (trial-division primes, Legendre exponents, Karatsuba product "
+                  "tree, OpenMP over the nodes of a level) on %d threads: %.2f s for %d product limbs (%d result "
+                  "limbs); one thread: %.2f s.  The oracle's cost per limb grows with n (Karatsuba), so its rate "
+                  "at n = 2,050,572,903 is lower than this sample's" % (n_sample, nt, dt_all, limbs, L, res[1][0]),
+        "n": n_sample,
+        "seconds_all_threads": round(dt_all, 3),
+        "seconds_one_thread": round(res[1][0], 3),
+        "one_thread_limbs_per_s": limbs / res[1][0],
+        "cpu_model": cpu_model(),
+        "gpu_over_cpu": round(gpu_limbs_per_s / (limbs / dt_all), 1),
     }
+
+
+def catalan_mode_times(cat, n, steps, plain_steps, out_bytes_limit=None):
+    """C(n) batched (one graph replay per call, and plain launches without a
+    graph) against the plain form (one product per launch), on the same GPU,
+    every output checked against the oracle's digest."""
+    import torch
+
+    with open(GOLDEN) as f:
+        gold = json.load(f).get(str(n))
+    _, max_limbs, _ = cat.sizes(n)
+    out = torch.empty(max_limbs, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        t = cat.exact(n, mode="graph", out=out)
+    checks = check_output(cat, t, n, gold)
+    st = cat.stats()
+    ms_g = time_steps(cat, n, "graph", steps, out)
+    t = cat.exact(n, mode="graph", out=out)
+    check_output(cat, t, n, gold)
+    ms_b = time_steps(cat, n, "batched", max(1, steps // 2), out)
+    r = {"n": n, "graph_ms": round(ms_g, 4), "batched_no_graph_ms": round(ms_b, 4),
+         "products": st["products"], "product_limbs": st["product_limbs"],
+         "graph_limbs_per_s": st["product_limbs"] / (ms_g / 1e3), "verified": checks}
+    if plain_steps > 0:
+        cat.exact(n, mode="plain", out=out)
+        ms_p = time_steps(cat, n, "plain", plain_steps, out)
+        t = cat.exact(n, mode="plain", out=out)
+        check_output(cat, t, n, gold)
+        sp = cat.stats()
+        r.update({"plain_ms": round(ms_p, 3), "plain_launches": sp["launches"],
+                  "plain_limbs_per_s": st["product_limbs"] / (ms_p / 1e3),
+                  "speedup_graph_vs_plain": round(ms_p / ms_g, 1)})
+    del out
+    torch.cuda.empty_cache()
+    return r
+
+
+def roofline(cat, n, out, steps, st, ms):
+    """The dominant kernel of a step (most summed time, library event timer on
+    batched launches), timed live over `steps` further steps: algorithmic
+    butterflies per second against the 9-lane-op butterfly peak; the HBM
+    counters of that kernel from the committed rocprofv3 summary when it was
+    taken on the current sources; and the step's algorithmic HBM traffic
+    (8 bytes per product limb) and overall butterfly rate."""
+    kt = kernel_times(cat, n, out)
+    dom = max(kt, key=lambda k: kt[k][0])
+    cat.timer_set(dom)
+    for _ in range(steps):
+        cat.exact(n, mode="batched", out=out)
+    kms, klaunch, kwork = cat.timer_get()
+    cat.timer_set(None)
+    avg_ms = kms / max(klaunch, 1)
+    tr = load_traffic(dom, n)
+    if dom in NTT_KERNELS:
+        achieved = kwork / (kms / 1e3)
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 4),
+                "peak": round(PEAK_BFLY / 1e12, 4), "unit": "Tbfly/s", "frac": round(achieved / PEAK_BFLY, 4),
+                "basis": "radix-2 butterflies: 3 primes x (2 forward + 1 inverse) x (M/2) log2 M per row of M "
+                         "points (the row stages of each product's 9 (N/2) log2 N); peak = 256 CU x 64 lanes x "
+                         "2.4 GHz / 9 lane-ops per butterfly",
+                "frac_code_14_ops": round(achieved / PEAK_BFLY_CODE, 4)}
+    else:
+        per_limb = 16.0 if dom == "k_crt" else 8.0
+        achieved = kwork * per_limb / (kms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof["avg_launch_ms"] = round(avg_ms, 5)
+    roof["launches"] = klaunch
+    roof["work_per_launch"] = kwork / max(klaunch, 1)
+    roof["traffic"] = tr.get("bytes_per_launch") if tr else None
+    if tr:
+        roof["traffic_GBps"] = round(tr["bytes_per_launch"] / (avg_ms / 1e3) / 1e9, 1)
+        roof["traffic_hbm_frac"] = round(tr["bytes_per_launch"] / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    # the whole step: every NTT product's butterflies (the four transform
+    # kernels' algorithmic counts) and the operands-in + product-out bytes
+    bfly = sum(kt[k][2] for k in NTT_KERNELS if k in kt)
+    step_s = ms / 1e3
+    step = {"butterflies_per_step": bfly, "achieved_Tbfly_s": round(bfly / step_s / 1e12, 4),
+            "frac": round(bfly / step_s / PEAK_BFLY, 4),
+            "algorithmic_bytes_per_step": 8 * st["product_limbs"],
+            "algorithmic_GBps": round(8 * st["product_limbs"] / step_s / 1e9, 1),
+            "hbm_frac": round(8 * st["product_limbs"] / step_s / 1e9 / HBM_PEAK_GBS, 4)}
+    kms_step = {k: round(v[0], 4) for k, v in kt.items()}
+    return roof, step, kms_step, dom
 
 
 def main():
@@ -431,11 +586,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--n", type=int, default=HEADLINE_N)
+    ap.add_argument("--plain-steps", type=int, default=1, help="plain-form steps of C(10^7) and C(10^8)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=10_000_000, help="n of the CPU oracle's sample")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the C(10^7) and C(10^8) comparisons")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-product level-batch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--no-ratio", action="store_true", help="skip the factorial-ratio measurement")
@@ -475,11 +632,14 @@ def main():
     if os.path.exists(GOLDEN):
         with open(GOLDEN) as f:
             gold = json.load(f).get(str(n))
-    _, max_limbs, _ = cat.sizes(n)
+    _, max_limbs, wbytes = cat.sizes(n)
     out = torch.empty(max_limbs, dtype=torch.int32, device="cuda")
 
-    log("bench: n=%d warmup=%d steps=%d" % (n, args.warmup, args.steps))
-    for _ in range(max(args.warmup, 1)):
+    log("bench: n=%d warmup=%d steps=%d workspace %.2f GB" % (n, args.warmup, args.steps, wbytes / 1e9))
+    t0 = time.perf_counter()
+    t = cat.exact(n, mode="graph", out=out)
+    first_s = time.perf_counter() - t0
+    for _ in range(max(args.warmup - 1, 0)):
         t = cat.exact(n, mode="graph", out=out)
     verified = check_output(cat, t, n, gold)
     st = cat.stats()
@@ -493,51 +653,32 @@ def main():
     value = product_limbs / (ms / 1e3)
     log("bench: graph %.3f ms/step, %d products, %d product limbs" % (ms, st["products"], product_limbs))
 
-    # batched without graph (launch overhead visible) and the plain form
     ms_batched = time_steps(cat, n, "batched", max(1, args.steps // 4), out)
-    t2, phases = phase_times(cat, n)
+    t2, phases = phase_times(cat, n, reps=5)
     phases["phase2_output_verified"] = bool(check_output(cat, t2, n, gold))
+    del t2
     log("bench: phase 1 %.3f ms, phase 2 %.3f ms (separate calls)" % (phases["phase1_ms"], phases["phase2_ms"]))
-    plain = None
-    if not args.no_plain and args.plain_steps > 0:
-        cat.exact(n, mode="plain", out=out)   # plan + warm
-        ms_plain = time_steps(cat, n, "plain", args.plain_steps, out)
-        t = cat.exact(n, mode="plain", out=out)
-        check_output(cat, t, n, gold)
-        sp = cat.stats()
-        plain = {"ms_per_step": round(ms_plain, 3), "limbs_per_s": product_limbs / (ms_plain / 1e3),
-                 "launches_per_step": sp["launches"], "speedup_batched_graph_vs_plain": round(ms_plain / ms, 2)}
-        log("bench: plain %.1f ms/step (%d launches)" % (ms_plain, sp["launches"]))
 
-    roof = None
-    kt = None
+    roof = step_roof = kms_step = None
     if not args.no_roofline:
-        kt = kernel_times(cat, n, out)
-        dom = max(kt, key=lambda k: kt[k][0])
-        # live measurement of the dominant kernel over the timed steps (batched launches)
-        cat.timer_set(dom)
-        for _ in range(args.steps):
-            cat.exact(n, mode="batched", out=out)
-        kms, klaunch, kwork = cat.timer_get()
-        cat.timer_set(None)
-        avg_ms = kms / max(klaunch, 1)
-        if dom in NTT_KERNELS:
-            achieved = kwork / (kms / 1e3) / 1e12
-            roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 4), "peak": round(PEAK_BFLY / 1e12, 4),
-                    "unit": "Tbfly/s", "frac": round(achieved * 1e12 / PEAK_BFLY, 4),
-                    "avg_launch_ms": round(avg_ms, 5), "launches": klaunch}
-        else:
-            # HBM-bound kernels: algorithmic bytes (12 B per limb read as residues + 4 B written for k_crt)
-            per_limb = 16.0 if dom == "k_crt" else 8.0
-            achieved = kwork * per_limb / (kms / 1e3) / 1e9
-            roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "avg_launch_ms": round(avg_ms, 5), "launches": klaunch}
-        tr = load_traffic(dom, n)
-        roof["traffic"] = tr.get("bytes_per_launch") if tr else None
+        roof, step_roof, kms_step, dom = roofline(cat, n, out, args.steps, st, ms)
         if dom == "k_ntt_lds":
             roof["steady_state"] = steady_state(cat)
-        log("bench: dominant kernel %s: %.4f ms avg over %d launches" % (dom, avg_ms, klaunch))
+        log("bench: dominant kernel %s: %.4f ms avg over %d launches, frac %.3f" % (
+            dom, roof["avg_launch_ms"], roof["launches"], roof["frac"]))
+    del out
+    cat.release_workspaces()
+    torch.cuda.empty_cache()
+
+    secondary = None
+    if not args.no_secondary:
+        secondary = {}
+        for n2 in (10**7, 10**8):
+            if n2 == n:
+                continue
+            secondary["catalan_%s" % ("1e7" if n2 == 10**7 else "1e8")] = catalan_mode_times(
+                cat, n2, max(3, args.steps // 2), 0 if args.no_plain else args.plain_steps)
+            log("bench: C(%d) %s" % (n2, secondary["catalan_%s" % ("1e7" if n2 == 10**7 else "1e8")]))
 
     batch = None if args.no_batch else batch_bench(cat, max(3, args.steps // 4))
     if batch:
@@ -552,7 +693,14 @@ def main():
     decimal = None if args.no_decimal else decimal_bench(cat)
     if decimal:
         log("bench: decimal %s" % {k: v["ms"] for k, v in decimal.items()})
-    cpu = None if args.no_cpu else cpu_baseline(n, product_limbs)
+    cpu = None
+    if not args.no_cpu:
+        if secondary and "catalan_1e7" in secondary and args.cpu_n == 10**7:
+            cpu_limbs = secondary["catalan_1e7"]["product_limbs"]
+        else:
+            cat.exact(args.cpu_n, mode="batched")
+            cpu_limbs = cat.stats()["product_limbs"]
+        cpu = cpu_baseline(args.cpu_n, cpu_limbs, value)
 
     line = {
         "metric": METRIC,
@@ -567,23 +715,30 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "catalan_exact n=%d (Phase 1 sieve + Phase 2 product tree)" % n, "n": n,
-                   "mode": "batched, one HIP graph per call", "products_per_step": st["products"],
+        "config": {"workload": "catalan_exact n=%d (Phase 1 device sieve + Phase 2 batched product tree; "
+                               "the paper's Table 1 run)" % n if n == HEADLINE_N else
+                               "catalan_exact n=%d (Phase 1 device sieve + Phase 2 batched product tree)" % n,
+                   "n": n, "mode": "batched, one HIP graph per call", "products_per_step": st["products"],
                    "product_limbs_per_step": product_limbs, "result_limbs": int(t.numel()),
-                   "primes": st["n_primes"], "tree_levels": st["levels"], "verified_bit_exact": bool(verified)},
+                   "primes": st["n_primes"], "tree_levels": st["levels"], "verified_bit_exact": bool(verified),
+                   "checks": verified},
         "reconstruction_s": round(ms / 1e3, 6),
+        "first_call_s": round(first_s, 3),
         "batched_no_graph_ms_per_step": round(ms_batched, 3),
         "phases": phases,
-        "plain": plain,
         "roofline": roof,
+        "phase2_roofline": step_roof,
         "cpu_baseline": cpu,
+        "batched_vs_plain": secondary,
         "level_batch_4096": batch,
         "serving": serving,
         "factorial_ratios": ratios,
         "decimal_text": decimal,
-        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()} if kt else None,
-        "paper_context": {"wall_s_n1e7": 6.817, "hardware": "AMD Ryzen 9 4900HS laptop, Python 3.11 + gmpy2 "
-                                                            "(Table 2, proposed algorithm)"},
+        "kernel_ms_per_step": kms_step,
+        "paper_context": {"phase2_s": 1369.77, "total_s": 1549.14, "phase1_s": 179.37,
+                          "n": 2050572903, "hardware": "AMD Ryzen 9 4900HS laptop, 16 GB, Python 3.11 + gmpy2 "
+                                                      "(Sec. 5, Table 1)",
+                          "table2_proposed_s": {"1e6": 2.923, "1e7": 6.817, "1e8": 62.835}},
     }
     print(json.dumps(line))
 

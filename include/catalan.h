@@ -194,10 +194,17 @@ cat_status factorial_ratio_exact(const uint64_t* a, uint32_t k, const uint64_t* 
  *                   counts (host only, no device allocation) and queues it with
  *                   the normalisation and the copy of up to `cap` limbs of C(n)
  *                   into d_limbs (limbs past *n_limbs are zero);
- *  catalan_end      after Phase 2 finished: returns the limb count, checks the
- *                   device error word and releases the ticket (CAT_ERANGE if
- *                   cap was too small);
- *  cat_ticket_release drops a ticket at any point (waits for its work).
+ *  catalan_end      after Phase 2 was queued: waits for it, returns the limb
+ *                   count and checks the device error word (CAT_ERANGE if
+ *                   cap was too small).  It releases the ticket on every
+ *                   path, errors included (CAT_EINVAL when called before
+ *                   catalan_continue succeeded: then it first waits for the
+ *                   ticket's stream); the ticket must not be used again;
+ *  cat_ticket_release drops a ticket that catalan_end has not released, at
+ *                   any point: it waits until everything queued on the
+ *                   ticket's stream has finished (also the part of Phase 2 a
+ *                   failed catalan_continue may have queued), so d_work and
+ *                   d_limbs are free to reuse when it returns.
  * d_work and d_limbs must stay untouched until catalan_end.  The same results
  * as catalan_exact, bit for bit. */
 typedef struct cat_ticket_s* cat_ticket;

@@ -73,6 +73,8 @@ def _load():
     lib.orc_product.restype = ctypes.c_int
     lib.orc_set_fault.argtypes = [ctypes.c_int]
     lib.orc_set_fault.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_catalan_mod_prime.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -101,6 +103,11 @@ def set_fault(code: int) -> None:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads of the oracle's parallel loops (t <= 0: the runtime's default)."""
+    _load().orc_set_threads(int(t))
 
 
 def primes(limit: int) -> np.ndarray:

@@ -512,6 +512,19 @@ void orc_mul_batched(size_t batch, const uint32_t *a, const uint64_t *a_off,
     }
 }
 
+/* Threads of the parallel loops: t >= 1 sets them, t <= 0 restores the
+ * count the OpenMP runtime chose at start-up. */
+static int g_default_threads = 0;
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (g_default_threads == 0) g_default_threads = omp_get_max_threads();
+    omp_set_num_threads(t >= 1 ? t : g_default_threads);
+#else
+    (void)t;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -176,6 +176,11 @@ def workspace(nbytes: int, key: str = "default"):
     return buf
 
 
+def release_workspaces() -> None:
+    """Drop the cached scratch buffers (the next call allocates afresh)."""
+    _work.clear()
+
+
 TUNING_FILE = os.path.join(_HERE, "tuning", "gfx950.json")
 
 

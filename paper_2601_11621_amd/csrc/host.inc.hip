@@ -511,7 +511,27 @@ struct Plan {
   // capacity) -> exec of the whole call (Phase 1 + Phase 2 + copy)
   std::map<uintptr_t, hipGraphExec_t> graphs;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> full_graphs;
+  std::vector<uintptr_t> graphs_order;
+  std::vector<std::vector<uintptr_t>> full_graphs_order;
 };
+
+// Graph caches keep at most PLAN_GRAPHS_MAX executables each (one per set of
+// buffers a caller used); the oldest is destroyed once the device is idle.
+#define PLAN_GRAPHS_MAX 8
+template <class K>
+void cache_graph(std::map<K, hipGraphExec_t>& m, std::vector<K>& order, const K& key, hipGraphExec_t ge) {
+  m[key] = ge;
+  order.push_back(key);
+  while (order.size() > PLAN_GRAPHS_MAX) {
+    (void)hipDeviceSynchronize();
+    auto it = m.find(order.front());
+    if (it != m.end()) {
+      (void)hipGraphExecDestroy(it->second);
+      m.erase(it);
+    }
+    order.erase(order.begin());
+  }
+}
 
 // Forest levels of the product trees over the groups (one tree per group).
 // out(j) = A for even j, B for odd j; in(0) = primes.
@@ -1380,6 +1400,7 @@ struct MulPlanImpl {
   size_t off_res = 0, off_F = 0, off_ctl = 0, total = 0;   // control block: error word | look-back flags
   uint64_t products = 0, product_limbs = 0;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  std::vector<std::vector<uintptr_t>> graphs_order;
 };
 
 cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t* b_off, const uint64_t* c_off,
@@ -1517,7 +1538,7 @@ cat_status mul_plan_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_
       g.last_err = (int)e;
       return CAT_EDEVICE;
     }
-    M->graphs[key] = ge;
+    cache_graph(M->graphs, M->graphs_order, key, ge);
     *launches = C.launches;
   }
   HIPCHK(hipGraphLaunch(ge, st));
@@ -1923,7 +1944,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
             return CAT_OK;
           },
           &ge));
-      P->full_graphs[key] = ge;
+      cache_graph(P->full_graphs, P->full_graphs_order, key, ge);
       launches = nl;
     }
     HIPCHK(hipGraphLaunch(ge, st));
@@ -2011,7 +2032,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
         g.last_err = (int)e;
         return CAT_EDEVICE;
       }
-      P->graphs[(uintptr_t)wb] = ge;
+      cache_graph(P->graphs, P->graphs_order, (uintptr_t)wb, ge);
       launches += C.launches;
     }
     HIPCHK(hipGraphLaunch(ge, st));
@@ -2149,7 +2170,7 @@ cat_status bigint_mul_batched(uint32_t batch, const uint32_t* d_a, const uint64_
 cat_status bigint_residues(const uint32_t* d_x, size_t n, uint64_t* h_res, void* d_work, size_t work_bytes,
                            void* stream) {
   if (!h_res || (!d_x && n > 0)) return CAT_EINVAL;
-  const uint64_t chunk = 4096;
+  const uint64_t chunk = RES_BLOCK;
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (n == 0) {
     h_res[0] = h_res[1] = h_res[2] = 0;
@@ -2161,7 +2182,12 @@ cat_status bigint_residues(const uint32_t* d_x, size_t n, uint64_t* h_res, void*
   STCHK(set_device());
   hipStream_t st = (hipStream_t)stream;
   uint64_t* part = (uint64_t*)d_work;
-  hipLaunchKernelGGL(k_residues, dim3((uint32_t)((nch + 255) / 256)), dim3(256), 0, st, d_x, (uint64_t)n, chunk, part);
+  // 5^256 mod (2^32 - 5): the weight of one step of a thread's Horner pass
+  const uint32_t w256 = (uint32_t)h_powmod(5u, RES_T, (uint32_t)RES_Q0);
+  {
+    KTime kt("k_residues", st, (double)n);
+    hipLaunchKernelGGL(k_residues, dim3((uint32_t)nch), dim3(RES_T), 0, st, d_x, (uint64_t)n, w256, part);
+  }
   LAUNCHCHK();
   std::vector<uint64_t> h(nch * 3);
   HIPCHK(hipMemcpyAsync(h.data(), part, nch * 24, hipMemcpyDeviceToHost, st));
@@ -2265,11 +2291,22 @@ cat_status catalan_continue(cat_ticket ticket, uint32_t* d_limbs, size_t cap) {
 }
 
 cat_status catalan_end(cat_ticket ticket, size_t* n_limbs) {
-  if (!ticket || !n_limbs) return CAT_EINVAL;
+  if (!ticket) return CAT_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(g.mu);
   Ticket* t = (Ticket*)ticket;
-  if (t->state != 2) return CAT_EINVAL;
-  HIPCHK(hipEventSynchronize(t->ev));
+  // the ticket is released on every path below: the caller never uses it again
+  if (!n_limbs || t->state != 2) {
+    (void)hipStreamSynchronize(t->st);
+    ticket_free(t);
+    return CAT_EINVAL;
+  }
+  hipError_t e = hipEventSynchronize(t->ev);
+  if (e != hipSuccess) {
+    g.last_err = (int)e;
+    (void)hipStreamSynchronize(t->st);
+    ticket_free(t);
+    return CAT_EDEVICE;
+  }
   cat_status s = CAT_OK;
   if (t->one) {
     *n_limbs = 1;
@@ -2290,7 +2327,10 @@ cat_status cat_ticket_release(cat_ticket ticket) {
   if (!ticket) return CAT_OK;
   std::lock_guard<std::recursive_mutex> lk(g.mu);
   Ticket* t = (Ticket*)ticket;
-  (void)hipEventSynchronize(t->ev);
+  // everything the ticket queued (a failed catalan_continue may have queued
+  // part of Phase 2 after the last event) has finished before d_work and
+  // d_limbs go back to the caller
+  (void)hipStreamSynchronize(t->st);
   ticket_free(t);
   return CAT_OK;
 }

@@ -425,26 +425,74 @@ __global__ void __launch_bounds__(256) k_group_bits(const uint32_t* __restrict__
   if ((threadIdx.x & 63) == 0 && s) atomicAdd(&gbits[g], s);
 }
 
-// Fingerprints of a limb vector: x mod (2^32 - 5), x mod (2^32 + 1), x mod (2^32 - 1).
-// Each block reduces a contiguous chunk with Horner steps, partial results
-// are combined by weights (2^32)^{offset} on the host side of the library.
-__device__ __forceinline__ uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) {
-  // a, b < m <= 2^33: exact via 128-bit product
-  unsigned __int128 t = (unsigned __int128)a * b;
-  return (uint64_t)(t % m);
+// Fingerprints of a limb vector: x mod (2^32 - 5), x mod (2^32 + 1), x mod
+// (2^32 - 1).  Workgroup b reduces the 4096 limbs [4096 b, 4096 b + 4096):
+// thread t holds the RES_C limbs at 4096 b + 256 i + t (coalesced loads) and
+// the block's partial is sum_k x_k (2^32)^(k - 4096 b) mod q; the library
+// combines the partials with the weights (2^32)^(4096 b) on the host.  With
+// 2^32 = 5, -1 and 1 modulo the three moduli, the weight of limb 256 i + t
+// is 5^(256 i + t), (-1)^t and 1: a Horner pass over i with the constant
+// 5^256 (two folds of 2^32 = 5 per step) for the first, plain 64-bit sums
+// for the others.
+#define RES_T 256
+#define RES_C 16
+#define RES_BLOCK (RES_T * RES_C)
+#define RES_Q0 4294967291ull   // 2^32 - 5
+#define RES_Q1 4294967297ull   // 2^32 + 1
+#define RES_Q2 4294967295ull   // 2^32 - 1
+// y mod (2^32 - 5) for any 64-bit y: fold 2^32 = 5 twice, then one subtraction
+__device__ __forceinline__ uint32_t mod_q0(uint64_t y) {
+  const uint64_t r = (y >> 32) * 5ull + (y & 0xFFFFFFFFull);   // < 6 * 2^32
+  const uint64_t r2 = (r >> 32) * 5ull + (r & 0xFFFFFFFFull);  // < 2^32 + 30
+  return (uint32_t)(r2 >= RES_Q0 ? r2 - RES_Q0 : r2);
 }
-__global__ void k_residues(const uint32_t* __restrict__ x, uint64_t n, uint64_t chunk, uint64_t* __restrict__ part) {
-  const uint64_t mods[3] = {4294967291ull, 4294967297ull, 4294967295ull};
-  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t lo = c * chunk;
-  if (lo >= n) return;
-  const uint64_t hi = min(lo + chunk, n);
-  for (int m = 0; m < 3; m++) {
-    const uint64_t q = mods[m];
-    const uint64_t base = (1ull << 32) % q;
-    uint64_t r = 0;
-    for (uint64_t k = hi; k > lo; k--) r = (mulmod64(r, base, q) + x[k - 1]) % q;
-    part[c * 3 + m] = r;
+__global__ void __launch_bounds__(RES_T) k_residues(const uint32_t* __restrict__ x, uint64_t n, uint32_t w256,
+                                                    uint64_t* __restrict__ part) {
+  __shared__ uint64_t red[3][RES_T / 64];
+  const uint32_t t = threadIdx.x;
+  const uint64_t base = (uint64_t)blockIdx.x * RES_BLOCK;
+  uint32_t v[RES_C];
+#pragma unroll
+  for (int i = 0; i < RES_C; i++) {
+    const uint64_t k = base + (uint64_t)i * RES_T + t;
+    v[i] = k < n ? x[k] : 0u;
+  }
+  uint32_t h = 0;
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = RES_C - 1; i >= 0; i--) {
+    h = mod_q0((uint64_t)h * w256 + v[i]);
+    s += v[i];
+  }
+  // lane weight 5^t mod q0 by square-and-multiply over the bits of t < 256
+  uint32_t w = 1, b5 = 5;
+  for (uint32_t e = t; e; e >>= 1) {
+    if (e & 1) w = mod_q0((uint64_t)w * b5);
+    b5 = mod_q0((uint64_t)b5 * b5);
+  }
+  uint64_t a0 = mod_q0((uint64_t)h * w);      // < 2^32: 256 of them sum below 2^40
+  uint64_t ap = (t & 1) ? 0 : s, am = (t & 1) ? s : 0;   // s < 2^36
+  for (int d = 32; d >= 1; d >>= 1) {
+    a0 += __shfl_xor(a0, d, 64);
+    ap += __shfl_xor(ap, d, 64);
+    am += __shfl_xor(am, d, 64);
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = a0;
+    red[1][t >> 6] = ap;
+    red[2][t >> 6] = am;
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint64_t s0 = 0, sp = 0, sm = 0;
+    for (int k = 0; k < RES_T / 64; k++) {
+      s0 += red[0][k];
+      sp += red[1][k];
+      sm += red[2][k];
+    }
+    part[3 * (uint64_t)blockIdx.x + 0] = s0 % RES_Q0;
+    part[3 * (uint64_t)blockIdx.x + 1] = (sp % RES_Q1 + RES_Q1 - sm % RES_Q1) % RES_Q1;
+    part[3 * (uint64_t)blockIdx.x + 2] = (sp + sm) % RES_Q2;
   }
 }
 

@@ -9,7 +9,9 @@ library tickets on its slot's stream — Phase 1 queued at admission, Phase 2
 queued once Phase 1 has finished — so the work of all admitted requests
 overlaps on the device, and everything a request builds (primes, groups,
 partial product trees) stays resident in its workspace until it finishes.
-The host loop only polls events; it never waits on the GPU.
+The host loop only polls events; it never waits on the GPU.  A request can be
+cancelled at any point: a queued one leaves the queue, a running one has its
+device work drained and its slot and memory freed.
 
 `Server` is independent of the device: it drives an executor with
 `footprint / begin / ready / advance / finish`.  `GpuExecutor` binds that to
@@ -24,7 +26,7 @@ from dataclasses import dataclass, field
 from typing import Callable, Deque, List, Optional
 
 
-QUEUED, PHASE1, PHASE2, DONE, FAILED = "queued", "phase1", "phase2", "done", "failed"
+QUEUED, PHASE1, PHASE2, DONE, FAILED, CANCELLED = "queued", "phase1", "phase2", "done", "failed", "cancelled"
 
 
 @dataclass
@@ -48,10 +50,18 @@ class Request:
 
 
 class Server:
+    """`on_done(request)`, if given, is called once per request as it leaves
+    the server (done, failed or cancelled), e.g. to consume and drop results."""
+
     def __init__(self, executor, budget_bytes: int, max_slots: int = 8,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, on_done: Optional[Callable] = None):
         self.ex = executor
         self.budget = int(budget_bytes)
+        self.on_done = on_done
+        # the executor keeps freed workspaces for reuse only within the budget
+        attach = getattr(executor, "attach", None)
+        if attach is not None:
+            attach(self.budget)
         self.max_slots = int(max_slots)
         self.clock = clock
         self.queue: Deque[Request] = collections.deque()
@@ -79,7 +89,7 @@ class Server:
             if r.footprint > self.budget:
                 self.queue.popleft()
                 r.state, r.error, r.finished = FAILED, "footprint exceeds the budget", now
-                self.done.append(r)
+                self._finished(r)
                 moved = True
                 continue
             if self.used + r.footprint > self.budget:
@@ -93,6 +103,7 @@ class Server:
                 self.ex.begin(r)
                 r.state = PHASE1
             except Exception as e:  # noqa: BLE001 - reported on the request
+                self.ex.abort(r)
                 self._retire(r, now, str(e))
             else:
                 self.active.append(r)
@@ -100,13 +111,38 @@ class Server:
             moved = True
         return moved
 
-    def _retire(self, r: Request, now: float, error: Optional[str] = None):
+    def _finished(self, r: Request):
+        self.done.append(r)
+        if self.on_done is not None:
+            self.on_done(r)
+
+    def _retire(self, r: Request, now: float, error: Optional[str] = None, state: Optional[str] = None):
         r.finished = now
-        r.state = FAILED if error else DONE
+        r.state = state or (FAILED if error else DONE)
         r.error = error
         self.used -= r.footprint
         self.free_slots.append(r.slot)
-        self.done.append(r)
+        self._finished(r)
+
+    def cancel(self, r: Request) -> bool:
+        """Withdraw a request.  A queued one leaves the queue; a running one has
+        its queued device work drained by the executor, then its slot and its
+        memory are freed.  False if it had already left the server."""
+        now = self.clock()
+        if r.state == QUEUED:
+            try:
+                self.queue.remove(r)
+            except ValueError:
+                return False
+            r.state, r.error, r.finished = CANCELLED, "cancelled", now
+            self._finished(r)
+            return True
+        if r in self.active:
+            self.active.remove(r)
+            self.ex.abort(r)
+            self._retire(r, now, "cancelled", CANCELLED)
+            return True
+        return False
 
     def step(self) -> bool:
         """One pass: poll running requests, then admit.  True if anything moved."""
@@ -160,6 +196,7 @@ class Server:
         t0 = min(r.arrival for r in rs)
         t1 = max(r.finished for r in rs)
         return {"completed": len(rs), "failed": sum(1 for r in self.done if r.state == FAILED),
+                "cancelled": sum(1 for r in self.done if r.state == CANCELLED),
                 "p50_ms": pct(0.5) * 1e3, "p99_ms": pct(0.99) * 1e3, "mean_ms": sum(lat) / len(lat) * 1e3,
                 "req_per_s": len(rs) / (t1 - t0) if t1 > t0 else float("inf"),
                 "peak_active": self.peak_active, "peak_bytes": self.peak_used}
@@ -167,9 +204,15 @@ class Server:
 
 # ---------------------------------------------------------------------------
 class GpuExecutor:
-    """Executor on the library's ticket API; one HIP stream per slot."""
+    """Executor on the library's ticket API.
 
-    def __init__(self, max_slots: int, device: int = 0):
+    Slots share at most `max_streams` HIP streams (default 4: the hardware
+    queues a process gets by default; more streams would only be multiplexed
+    onto them).  Workspaces of finished requests are kept for reuse by size
+    class, but only while the active requests plus the kept buffers stay
+    within the budget the server attaches; beyond it they are released."""
+
+    def __init__(self, max_slots: int, device: int = 0, max_streams: int = 4):
         import torch
 
         from . import _check, _ptr, init, load, sizes
@@ -178,9 +221,16 @@ class GpuExecutor:
         self._check, self._ptr, self._sizes = _check, _ptr, sizes
         init(device)
         self.lib = load()
-        # default-priority streams, one per slot
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(max_slots)]
+        # default-priority streams shared round-robin by the slots
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, min(max_slots, max_streams)))]
         self._pool = collections.defaultdict(list)     # size class -> free workspace tensors
+        self.pooled = 0                                 # bytes held by the pool
+        self.active_bytes = 0                           # bytes held by running requests
+        self.budget: Optional[int] = None
+
+    def attach(self, budget_bytes: int):
+        self.budget = int(budget_bytes)
+        self._trim(0)
 
     @staticmethod
     def _cls(nbytes: int) -> int:
@@ -188,6 +238,22 @@ class GpuExecutor:
         while c < nbytes:
             c <<= 1
         return c
+
+    def _trim(self, need: int):
+        """Release pooled workspaces (largest first) until active + pooled +
+        need fits the budget."""
+        if self.budget is None:
+            return
+        for cls in sorted(self._pool, reverse=True):
+            free = self._pool[cls]
+            while free and self.active_bytes + self.pooled + need > self.budget:
+                free.pop()
+                self.pooled -= cls
+
+    def _release(self, cls: int, w):
+        self._pool[cls].append(w)
+        self.pooled += cls
+        self._trim(0)
 
     def footprint(self, n: int) -> int:
         _, max_limbs, wbytes = self._sizes(n)
@@ -198,13 +264,21 @@ class GpuExecutor:
         _, max_limbs, wbytes = self._sizes(r.n)
         cls = self._cls(wbytes)
         free = self._pool[cls]
-        w = free.pop() if free else torch.empty(cls, dtype=torch.uint8, device="cuda")
+        if free:
+            w = free.pop()
+            self.pooled -= cls
+        else:
+            self._trim(cls + 4 * max_limbs)
+            w = torch.empty(cls, dtype=torch.uint8, device="cuda")
+        held = cls + 4 * max_limbs
+        self.active_bytes += held
         out = torch.empty(max_limbs, dtype=torch.int32, device="cuda")
-        st = self.streams[r.slot]
+        st = self.streams[r.slot % len(self.streams)]
         t = ctypes.c_void_p()
+        r.handle = (None, w, out, cls, held)
         self._check(self.lib.catalan_begin(r.n, self._ptr(w), w.numel(), ctypes.c_void_p(st.cuda_stream),
                                            ctypes.byref(t)), "catalan_begin")
-        r.handle = (t, w, out, cls)
+        r.handle = (t, w, out, cls, held)
 
     def ready(self, r: Request) -> bool:
         s = self.lib.cat_ticket_query(r.handle[0])
@@ -214,24 +288,35 @@ class GpuExecutor:
         return True
 
     def advance(self, r: Request):
-        t, w, out, cls = r.handle
+        t, w, out = r.handle[:3]
         self._check(self.lib.catalan_continue(t, self._ptr(out), out.numel()), "catalan_continue")
 
-    def finish(self, r: Request) -> int:
-        t, w, out, cls = r.handle
-        nl = ctypes.c_size_t()
-        self._check(self.lib.catalan_end(t, ctypes.byref(nl)), "catalan_end")
-        r.result = out[: nl.value]
-        self._pool[cls].append(w)
+    def _done_with(self, r: Request):
+        t, w, out, cls, held = r.handle
         r.handle = None
+        self.active_bytes -= held
+        self._release(cls, w)
+        return out
+
+    def finish(self, r: Request) -> int:
+        t = r.handle[0]
+        nl = ctypes.c_size_t()
+        # catalan_end waits for the ticket's work and releases the ticket on
+        # every path, so the handle is dropped before its status is checked
+        st = self.lib.catalan_end(t, ctypes.byref(nl))
+        out = self._done_with(r)
+        self._check(st, "catalan_end")
+        r.result = out[: nl.value]
         return nl.value
 
     def abort(self, r: Request):
-        if r.handle is not None:
-            t, w, out, cls = r.handle
+        if r.handle is None:
+            return
+        t = r.handle[0]
+        if t is not None and t.value:
+            # waits until everything queued on the ticket's stream has finished
             self.lib.cat_ticket_release(t)
-            self._pool[cls].append(w)
-            r.handle = None
+        self._done_with(r)
 
     def wait_until(self, t: float):
         while time.perf_counter() < t:
@@ -242,10 +327,13 @@ class FakeExecutor:
     """Simulated executor for CPU tests: Phase 1 and Phase 2 take given times on
     a fake clock; footprints are n bytes."""
 
-    def __init__(self, phase1: Callable[[int], float], phase2: Callable[[int], float]):
+    def __init__(self, phase1: Callable[[int], float], phase2: Callable[[int], float],
+                 fail_finish: Callable[[int], bool] = lambda n: False):
         self.now = 0.0
         self.p1, self.p2 = phase1, phase2
+        self.fail_finish = fail_finish
         self.log = []
+        self.open = set()     # requests with device work the executor holds
 
     def clock(self) -> float:
         return self.now
@@ -255,6 +343,7 @@ class FakeExecutor:
 
     def begin(self, r: Request):
         r.handle = self.now + self.p1(r.n)
+        self.open.add(r.rid)
         self.log.append(("begin", r.rid, self.now))
 
     def ready(self, r: Request) -> bool:
@@ -266,10 +355,17 @@ class FakeExecutor:
 
     def finish(self, r: Request) -> int:
         self.log.append(("finish", r.rid, self.now))
+        self.open.discard(r.rid)
+        r.handle = None
+        if self.fail_finish(r.n):
+            raise RuntimeError("finish failed")
         return r.n
 
     def abort(self, r: Request):
-        pass
+        self.log.append(("abort", r.rid, self.now))
+        if r.handle is not None:
+            self.open.discard(r.rid)
+            r.handle = None
 
     def wait_until(self, t: float):
         self.now = max(self.now, t)

@@ -238,11 +238,16 @@ def test_exact_graph_replays_are_identical(cat):
 
 def test_residues_kernel(cat):
     rng = np.random.default_rng(3)
-    for n in [1, 5, 4096, 4097, 100000]:
+    for n in [1, 5, 255, 256, 257, 4095, 4096, 4097, 8192 + 300, 100000, 1 << 20]:
         x = _rand(rng, n)
         v = pins.limbs_int(x)
         r = cat.residues(cat.from_numpy(x))
-        assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1))
+        assert r == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1)), n
+    # all-ones limbs: the largest partial sums of every block
+    for n in [4096, 3 * 4096 + 17]:
+        x = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+        v = (1 << (32 * n)) - 1
+        assert cat.residues(cat.from_numpy(x)) == (v % (2**32 - 5), v % (2**32 + 1), v % (2**32 - 1)), n
 
 
 @pytest.mark.parametrize("polls", [0, 1, 16])

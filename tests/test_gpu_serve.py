@@ -75,3 +75,107 @@ def test_budget_smaller_than_one_request_fails_cleanly(cat):
     srv.run()
     assert a.state == FAILED and b.state == DONE
     assert np.array_equal(cat.to_numpy(b.result), oracle.catalan(10**5))
+
+
+def test_ticket_erange_then_requests_continue(cat):
+    """A ticket whose output capacity is too small ends with CAT_ERANGE (and
+    the needed length); the ticket is released exactly once, so requests
+    served afterwards through the same ticket pool stay bit-exact."""
+    import ctypes
+
+    import torch
+
+    from paper_2601_11621_amd.serve import DONE, FAILED, GpuExecutor, Server
+
+    lib = cat.load()
+    _, _, wbytes = cat.sizes(10**5)
+    w = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream()
+    t = ctypes.c_void_p()
+    cat._check(lib.catalan_begin(10**5, cat._ptr(w), w.numel(), ctypes.c_void_p(st.cuda_stream),
+                                 ctypes.byref(t)), "catalan_begin")
+    while lib.cat_ticket_query(t) == cat.CAT_EAGAIN:
+        pass
+    cat._check(lib.catalan_continue(t, cat._ptr(out), 1), "catalan_continue")
+    nl = ctypes.c_size_t()
+    assert lib.catalan_end(t, ctypes.byref(nl)) == cat.CAT_ERANGE and nl.value == 6250
+
+    class SmallOut(GpuExecutor):
+        """Hands the library a one-limb output for n = 5000: catalan_end then
+        reports CAT_ERANGE inside the server's finish step."""
+
+        def begin(self, r):
+            super().begin(r)
+            if r.n == 5000:
+                tk, ws, o, cls, held = r.handle
+                r.handle = (tk, ws, o[:1], cls, held)
+
+        def advance(self, r):
+            tk, ws, o = r.handle[:3]
+            self._check(self.lib.catalan_continue(tk, self._ptr(o), o.numel()), "catalan_continue")
+
+    ns = [5000, 1234, 5000, 20000, 777, 5000, 3000]
+    srv = Server(SmallOut(max_slots=3), budget_bytes=1 << 30, max_slots=3)
+    reqs = [srv.submit(n, arrival=0.0) for n in ns]
+    srv.run()
+    for r in reqs:
+        if r.n == 5000:
+            assert r.state == FAILED and "capacity" in r.error, r.error
+        else:
+            assert r.state == DONE, (r.n, r.error)
+            assert np.array_equal(cat.to_numpy(r.result), oracle.catalan(r.n)), r.n
+    # the same executor type without the small output: everything served
+    srv = Server(GpuExecutor(max_slots=3), budget_bytes=1 << 30, max_slots=3)
+    reqs = [srv.submit(n, arrival=0.0) for n in ns]
+    srv.run()
+    for r in reqs:
+        assert r.state == DONE and np.array_equal(cat.to_numpy(r.result), oracle.catalan(r.n)), r.n
+
+
+def test_cancel_running_request_on_gpu(cat):
+    """Cancelling a running request drains its queued work and frees its slot
+    and memory; the other requests finish bit-exact."""
+    from paper_2601_11621_amd.serve import CANCELLED, DONE, GpuExecutor, Server
+
+    srv = Server(GpuExecutor(max_slots=2), budget_bytes=4 << 30, max_slots=2)
+    big = srv.submit(10**7, arrival=0.0)
+    small = [srv.submit(n, arrival=0.0) for n in (10**4, 2 * 10**4, 3 * 10**4)]
+    srv.step()
+    assert big in srv.active
+    assert srv.cancel(big) and big.state == CANCELLED
+    srv.run()
+    assert srv.used == 0
+    for r in small:
+        assert r.state == DONE and np.array_equal(cat.to_numpy(r.result), oracle.catalan(r.n)), r.n
+
+
+def test_device_memory_stays_within_budget(cat):
+    """The executor's pool of freed workspaces is trimmed so that running
+    requests plus kept buffers never exceed the server's budget (results are
+    consumed and dropped as they finish)."""
+    import torch
+
+    from paper_2601_11621_amd.serve import DONE, GpuExecutor, Server
+
+    ns, _ = batch_inputs.serving_requests(seed=5, count=60, lo_exp=3.0, hi_exp=6.3)
+    budget = 256 << 20
+    bad = []
+
+    def consume(r):
+        if r.state == DONE:
+            if r.n <= 20000 and not np.array_equal(cat.to_numpy(r.result), oracle.catalan(r.n)):
+                bad.append(r.n)
+            r.result = None
+
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    ex = GpuExecutor(max_slots=4)
+    srv = Server(ex, budget_bytes=budget, max_slots=4, on_done=consume)
+    reqs = [srv.submit(int(n), arrival=0.0) for n in ns]
+    srv.run()
+    torch.cuda.synchronize()
+    assert all(r.state == DONE for r in reqs) and not bad
+    assert torch.cuda.max_memory_allocated() - base <= budget
+    assert ex.active_bytes == 0 and ex.pooled <= budget

@@ -79,3 +79,54 @@ def test_latency_percentiles():
     assert st["completed"] == 100
     assert 45 <= st["p50_ms"] <= 56
     assert 95 <= st["p99_ms"] <= 102
+
+
+def test_cancel_frees_slot_and_budget():
+    """A running request that is cancelled gives its slot and its memory back
+    at once (its device work drained by the executor's abort), so the request
+    waiting behind it is admitted; a queued one simply leaves the queue."""
+    from paper_2601_11621_amd.serve import CANCELLED
+
+    ex = FakeExecutor(lambda n: 0.001, lambda n: 1.0)
+    srv = Server(ex, budget_bytes=100, max_slots=1, clock=ex.clock)
+    a = srv.submit(80, arrival=0.0)
+    b = srv.submit(80, arrival=0.0)       # waits for a's slot and memory
+    c = srv.submit(10, arrival=0.0)
+    srv.step()
+    assert srv.active == [a] and srv.used == 80
+    assert srv.cancel(c) and c.state == CANCELLED and c not in srv.queue
+    assert srv.cancel(a)
+    assert a.state == CANCELLED and srv.used == 0 and srv.free_slots == [0]
+    assert ("abort", a.rid, ex.now) in ex.log and a.rid not in ex.open
+    _drive(srv, ex)
+    assert b.state == DONE and b.admitted <= a.finished + 1e-9
+    assert not srv.cancel(b)              # already finished
+    st = srv.stats()
+    assert st["completed"] == 1 and st["cancelled"] == 2
+
+
+def test_failed_finish_releases_once_and_server_continues():
+    """An executor whose finish raises (e.g. a capacity or device error from
+    the library) has its request failed exactly once: the executor drops the
+    handle before raising, the server's abort then finds nothing to release,
+    and later requests are served normally."""
+    ex = FakeExecutor(lambda n: 0.001, lambda n: 0.002, fail_finish=lambda n: n == 13)
+    srv = Server(ex, budget_bytes=1000, max_slots=2, clock=ex.clock)
+    bad = srv.submit(13, arrival=0.0)
+    good = [srv.submit(20 + k, arrival=0.0) for k in range(4)]
+    _drive(srv, ex)
+    assert bad.state == FAILED and "finish failed" in bad.error
+    assert all(r.state == DONE for r in good)
+    aborts = [rid for (what, rid, t) in ex.log if what == "abort"]
+    assert aborts == [bad.rid] and not ex.open
+    assert srv.used == 0 and sorted(srv.free_slots) == [0, 1]
+
+
+def test_on_done_sees_every_request_once():
+    seen = []
+    ex = FakeExecutor(lambda n: 0.001, lambda n: 0.001)
+    srv = Server(ex, budget_bytes=50, max_slots=2, clock=ex.clock, on_done=lambda r: seen.append(r.rid))
+    rs = [srv.submit(n, arrival=0.0) for n in (10, 100, 20)]   # 100 exceeds the budget
+    _drive(srv, ex)
+    assert sorted(seen) == [r.rid for r in rs]
+    assert rs[1].state == FAILED
