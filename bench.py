@@ -52,8 +52,8 @@ PEAK_BFLY = VALU_LANE_OPS / BFLY_OPS
 PEAK_BFLY_CODE = VALU_LANE_OPS / BFLY_OPS_CODE
 HBM_PEAK_GBS = 8000.0
 
-CANDIDATES = ["k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds", "k_crt", "k_school", "k_leaf"]
-NTT_KERNELS = {"k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds"}
+CANDIDATES = ["k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds", "k_tree_fused", "k_crt", "k_school", "k_leaf"]
+NTT_KERNELS = {"k_row", "k_pass_fwd", "k_pass_inv", "k_ntt_lds", "k_tree_fused"}
 
 
 def log(*a):
@@ -142,11 +142,15 @@ def kernel_times(cat, n, out):
     return res
 
 
-def source_sha1():
+def source_sha1(files=None):
+    """SHA-1 over the library sources `files` (names under csrc/; all of them
+    when None)."""
     import glob
 
     h = hashlib.sha1()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_11621_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_2601_11621_amd", "csrc")
+    paths = sorted(glob.glob(os.path.join(csrc, "*"))) if files is None else [os.path.join(csrc, f) for f in files]
+    for f in paths:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -154,13 +158,14 @@ def source_sha1():
 
 def load_traffic(kernel, n):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernels changed after the counters were taken."""
+    None when the sources that define the kernel changed after the counters
+    were taken."""
     path = os.path.join(PROFILES, "traffic_%s_n%d.json" % (kernel, n))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_sha1") != source_sha1():
+    if t.get("source_sha1") != source_sha1(t.get("sources")):
         return None
     return t
 
@@ -234,6 +239,17 @@ def batch_bench(cat, steps):
     torch.cuda.synchronize()
     ms_g = (time.perf_counter() - t0) * 1e3 / steps
     g.check()
+    oracle_ok = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch4096_digests.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            want = json.load(f)["uneven"]["sha256_128"]
+        got = cat.to_numpy(c)
+        d = [hashlib.sha256(got[int(g.c_off[i]):int(g.c_off[i + 1])].astype("<u4").tobytes()).hexdigest()[:32]
+             for i in range(len(want))]
+        oracle_ok = d == want
+        if not oracle_ok:
+            raise SystemExit("bench: level-batch products differ from the oracle's digests")
     p(da, db, c2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -269,7 +285,7 @@ def batch_bench(cat, steps):
     return {"products": 4096, "product_limbs": limbs, "batched_graph_ms": round(ms_g, 3),
             "batched_limbs_per_s": limbs / (ms_g / 1e3), "plain_ms": round(ms_p, 3),
             "plain_limbs_per_s": limbs / (ms_p / 1e3), "speedup": round(ms_p / ms_g, 2),
-            "batched_equals_plain": same,
+            "batched_equals_plain": same, "every_product_equals_oracle_digest": oracle_ok,
             "inputs": "numpy default_rng(0): la, lb = rint(2**U(6,16)) x 4096 each, limbs U[0,2^32)",
             "by_transform_size": buckets, "balanced": balanced}
 
@@ -403,21 +419,33 @@ def serving_bench(cat, count=1100, warm=100, slots=8, budget=16 << 30, frac=0.7)
     st = srv.stats(skip=warm)
     bad = 0
     solo = {}
+    gold = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "serving_digests.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            gold = json.load(f)["digests"]
+    checked = 0
     for r in reqs:
         if r.state != DONE:
             bad += 1
             continue
         if r.n not in solo:
             solo[r.n] = cat.to_numpy(cat.exact(r.n, mode="batched"))
-        if not np.array_equal(cat.to_numpy(r.result), solo[r.n]):
+        got = cat.to_numpy(r.result)
+        if not np.array_equal(got, solo[r.n]):
             bad += 1
+        if str(r.n) in gold:
+            L, h = gold[str(r.n)]
+            checked += 1
+            if len(got) != L or hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() != h:
+                bad += 1
     if bad:
-        raise SystemExit("bench: %d serving outputs differ from the same n alone" % bad)
+        raise SystemExit("bench: %d serving outputs differ from the same n alone or from the oracle" % bad)
     return {"requests": count, "warmup_requests": warm, "slots": slots, "budget_bytes": budget,
             "saturated_req_per_s": round(sat, 1), "offered_req_per_s": round(lam, 1),
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
             "req_per_s": round(st["req_per_s"], 1), "peak_active": st["peak_active"],
-            "all_outputs_equal_solo": True,
+            "all_outputs_equal_solo": True, "outputs_checked_against_oracle_digests": checked,
             "inputs": "n = floor(10^(3+4u)), Poisson arrivals, numpy default_rng(11621)"}
 
 

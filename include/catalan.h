@@ -119,6 +119,19 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
 cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, const uint32_t* d_y, size_t ly,
                           int32_t* sign, void* d_work, size_t work_bytes, void* stream);
 
+/* Exact decimal digit count D of the limb vector d_x[0 .. n_limbs) (device,
+ * leading zero limbs allowed; 0 counts as one digit), the count Table 1
+ * reports for C(2,050,572,903).  D is settled on the device: 10^(D-1) <= x <
+ * 10^D is checked as floor(x / 2^(D-1)) >= 5^(D-1) and floor(x / 2^D) < 5^D,
+ * with the powers of five from the Phase-2 engine; the first guess comes from
+ * the top limbs.  bigint_decimal_digits_workspace: host only, the d_work bytes
+ * for n_limbs.  d_work: device, caller-owned, at least that size (CAT_ENOMEM
+ * otherwise), must not overlap d_x.  Synchronises `stream`; CAT_EINVAL for
+ * n_limbs > 2^27. */
+cat_status bigint_decimal_digits_workspace(size_t n_limbs, size_t* workspace_bytes);
+cat_status bigint_decimal_digits(const uint32_t* d_x, size_t n_limbs, uint64_t* digits, void* d_work,
+                                 size_t work_bytes, void* stream);
+
 /* Decimal text of x (the optional decimal output of Sec. 3.2): the digits of
  * the little-endian limb vector d_x[0 .. n_limbs) (device; leading zero limbs
  * allowed; n_limbs = 0 means 0), most significant first, no leading zeros
@@ -268,6 +281,19 @@ typedef struct {
 cat_status cat_tune_set(const cat_tuning* t);
 cat_status cat_tune_get(cat_tuning* t);
 
+/* Lower tree levels fused into one launch (the batched form of C(n) and of
+ * the other Phase-2 entry points): the consecutive levels above the
+ * schoolbook levels whose products are one-workgroup transforms of at most
+ * 2^max_logn coefficients run in one kernel that keeps each 4,096-leaf tile
+ * of a group in LDS from the first of them to the last (three-prime
+ * transforms, Garner recombination and carries inside the workgroup), in
+ * trees of at most 2^22 leaves (larger levels fill the GPU, where the
+ * separate launches are faster).
+ * max_logn = 0 turns the fusion off (every level is then a transform launch
+ * and a carry launch); otherwise 4..12 (default 12).  The result is the same
+ * bit for bit either way.  Cached C(n) plans are dropped. */
+cat_status cat_fused_levels_set(uint32_t max_logn);
+
 /* Carry look-back between CRT blocks (diagnostics and tests).  A block reads
  * the generate / propagate pair of the block before it from a flag that block
  * publishes, polling it at most `polls` times (at most 2^20), and otherwise
@@ -281,12 +307,14 @@ cat_status cat_lookback_polls_set(uint32_t polls);
 
 /* Kernel timer (measurement only).  cat_timer_set(name) brackets every later
  * launch of the named kernel ("k_ntt_lds", "k_row", "k_pass_fwd", "k_pass_inv",
- * "k_crt", "k_school", "k_leaf") with HIP events on the stream it is launched
- * on, outside graph capture; NULL or "" stops it.  Each call resets the
+ * "k_tree_fused", "k_crt", "k_school", "k_leaf", "k_residues") with HIP
+ * events on the stream it is launched on, outside graph capture; NULL or ""
+ * stops it.  Each call resets the
  * counters.  cat_timer_get waits for the recorded events and returns the summed
  * kernel time, the launch count and the algorithmic work of those launches
- * (radix-2 butterflies for NTT kernels, limbs for k_crt and k_school, nodes for
- * k_leaf). */
+ * (radix-2 butterflies for NTT kernels, limbs for k_crt, k_school and
+ * k_residues, nodes for k_leaf).  Calls of catalan_exact_noalloc are not
+ * timed. */
 cat_status cat_timer_set(const char* kernel);
 cat_status cat_timer_get(double* ms, uint64_t* launches, double* work);
 

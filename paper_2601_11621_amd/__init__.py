@@ -33,7 +33,7 @@ EXPORTS = [
     "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
-    "decimal_sizes", "bigint_to_decimal",
+    "decimal_sizes", "bigint_to_decimal", "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits",
 ]
 
 
@@ -123,6 +123,9 @@ def load(path: str = LIB_PATH):
         "cat_tune_get": ([ctypes.POINTER(cat_tuning)], st),
         "decimal_sizes": ([ctypes.c_size_t, szp, szp], st),
         "bigint_to_decimal": ([vp, ctypes.c_size_t, vp, ctypes.c_size_t, szp, vp, ctypes.c_size_t, vp], st),
+        "cat_fused_levels_set": ([ctypes.c_uint32], st),
+        "bigint_decimal_digits_workspace": ([ctypes.c_size_t, szp], st),
+        "bigint_decimal_digits": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -199,6 +202,13 @@ def set_lookback_polls(polls: Optional[int]) -> None:
     (0: always recompute; None: the library's per-launch choice).  Same
     results either way."""
     _check(load().cat_lookback_polls_set(POLLS_AUTO if polls is None else int(polls)), "cat_lookback_polls_set")
+
+
+def set_fused_levels(max_logn: int = 12) -> None:
+    """Fuse the tree levels with transforms of up to 2^max_logn coefficients
+    into one launch (0: every level is a transform and a carry launch).  Same
+    results either way."""
+    _check(load().cat_fused_levels_set(int(max_logn)), "cat_fused_levels_set")
 
 
 def set_tuning(d: Optional[dict]) -> None:
@@ -383,43 +393,18 @@ def compare(x, y, shift_bits: int = 0, stream=None) -> int:
     return sgn.value
 
 
-def pow5(k: int):
-    """5^k as a limb tensor, by the product engine (groups of 5^13 and 5^(k mod 13))."""
-    q, r = divmod(int(k), 13)
-    if q == 0:
-        return from_numpy(np.array([5**r], dtype=np.uint32))
-    if q == 1:
-        return product([1], [0, 2], [5**r, 5**13])
-    if r == 0:
-        return product([q], [0, 1], [5**13])
-    return product([1, q], [0, 1, 2], [5**r, 5**13])
-
-
 def decimal_digits(x, stream=None) -> int:
-    """The number of decimal digits d of a limb tensor x > 0, settled exactly on
-    the GPU: 10^(d-1) <= x < 10^d checked as floor(x / 2^(d-1)) >= 5^(d-1) and
-    floor(x / 2^d) < 5^d (the powers of five by the product engine); the first
-    guess comes from the top limbs in floating point."""
-    import math
-
-    xs = to_numpy(x)
-    n = len(xs)
-    while n > 1 and xs[n - 1] == 0:
-        n -= 1
-    k0 = max(0, n - 3)
-    top = sum(float(xs[k]) * 2.0 ** (32 * (k - k0)) for k in range(k0, n))
-    d = int(math.floor(math.log10(top) + 32 * k0 * math.log10(2.0))) + 1
-    for _ in range(4):
-        lo = pow5(d - 1)
-        if compare(x, lo, d - 1, stream) < 0:
-            d -= 1
-            continue
-        hi, _ = mul_batched(lo, [0, lo.numel()], from_numpy(np.array([5], dtype=np.uint32)), [0, 1])
-        if compare(x, hi, d, stream) >= 0:
-            d += 1
-            continue
-        return d
-    raise RuntimeError("decimal digit count did not settle")
+    """The exact number of decimal digits of a limb tensor x, settled on the
+    GPU by the library (bigint_decimal_digits)."""
+    lib = load()
+    n = int(x.numel())
+    wb = ctypes.c_size_t()
+    _check(lib.bigint_decimal_digits_workspace(n, ctypes.byref(wb)), "bigint_decimal_digits_workspace")
+    w = workspace(wb.value, key="digits")
+    d = ctypes.c_uint64()
+    _check(lib.bigint_decimal_digits(_ptr(x) if n else None, n, ctypes.byref(d), _ptr(w), w.numel(),
+                                     _stream(stream)), "bigint_decimal_digits")
+    return d.value
 
 
 def decimal_sizes(n_limbs: int):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcatalan.so")
 SOURCES = ["catalan.hip"]
-DEPS = ["catalan.hip", "common.hpp", "ntt.inc.hip", "small.inc.hip", "sieve.inc.hip", "ratio.inc.hip",
+DEPS = ["catalan.hip", "common.hpp", "ntt.inc.hip", "small.inc.hip", "fused.inc.hip", "sieve.inc.hip", "ratio.inc.hip",
         "decimal.inc.hip", "host.inc.hip", "decimal_host.inc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

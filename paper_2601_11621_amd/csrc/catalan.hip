@@ -3,6 +3,7 @@
 #include "common.hpp"
 #include "ntt.inc.hip"
 #include "small.inc.hip"
+#include "fused.inc.hip"
 #include "sieve.inc.hip"
 #include "ratio.inc.hip"
 #include "decimal.inc.hip"

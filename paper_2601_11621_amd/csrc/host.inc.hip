@@ -40,6 +40,9 @@ struct Lib {
   cat_stats stats{};
   std::map<uint64_t, Plan*> plans;
   std::vector<uint64_t> plan_order;
+  std::map<uint64_t, Plan*> noalloc_plans;      // plans of catalan_exact_noalloc
+  std::vector<uint64_t> noalloc_order;
+  bool in_noalloc = false;                      // a catalan_exact_noalloc call is running
   hipStream_t cap_stream = nullptr;
   hipStream_t side_stream = nullptr;            // second branch of captured calls
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -52,13 +55,14 @@ struct Lib {
 };
 Lib g;
 
+
 // Brackets a launch of kernel `name` with events when the timer watches it.
 struct KTime {
   bool on = false;
   hipStream_t st;
   size_t idx = 0;
   KTime(const char* name, hipStream_t s, double work) : st(s) {
-    if (g.timer_name.empty() || g.timer_name != name) return;
+    if (g.in_noalloc || g.timer_name.empty() || g.timer_name != name) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (g.timer_used == g.timer_ev.size()) {
@@ -358,7 +362,25 @@ struct Stage {
   TreeLevel leaf{};
   uint64_t leaf_nodes = 0;
   bool dec = false;        // radix-10^9 products (k_crt10; addends in the segments)
+  bool is_fused = false;   // k_tree_fused over the levels fused.j0 .. fused.j1
+  FusedTree fused{};
+  uint32_t fused_tiles = 0;
+  double fused_bfly = 0;   // algorithmic butterflies of the fused levels
+  int jfirst = 0;          // first tree level this stage computes (tree stages)
 };
+
+// Tree levels fused into one launch: consecutive one-workgroup levels with
+// transforms of up to 2^g_fuse_logn coefficients (0: none, each level then
+// is a transform launch plus a carry launch), for trees of at most
+// FUSE_MAX_LEAVES leaves in the groups concerned.  A fused workgroup holds
+// the tiles of all three primes (121 KB of LDS, one workgroup and 12 waves per
+// CU) and pays a barrier per transform pass across them; the separate
+// launches run four 4-wave workgroups per CU.  Below about 2^22 leaves a
+// level cannot fill the GPU and the saved launches and carry round trips
+// win (C(10^7): 0.96 -> 0.92 ms); above it the separate launches are faster
+// (C(10^8): 5.91 vs 6.05 ms; C(2,050,572,903): 136.5 vs 137.9 ms).
+uint32_t g_fuse_logn = FT_LOGT;
+#define FUSE_MAX_LEAVES (1ull << 22)
 
 // host mirror of DescView::get in tree mode
 MulDesc tree_desc(const TreeLevel& t, uint64_t i) {
@@ -546,11 +568,28 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   const int J = ceil_log2(std::max<uint64_t>(Kmax_g, 1));   // levels until one node per group
   // levels folded into the leaf kernel of the batched form
   const int jleaf = Kmax_g > 1 ? std::min(J, LF) : 0;
+  // levels jf0..jf1 of the batched form run as one fused launch: the
+  // consecutive levels above the leaf and schoolbook levels whose products
+  // are one-workgroup transforms of at most 2^g_fuse_logn coefficients
+  int jf0 = -1, jf1 = -2;
+  uint64_t leaves = 0;
+  for (uint32_t gi = 0; gi < ng; gi++) leaves += P.off[gi + 1] - P.off[gi];
+  for (int j = std::max(jleaf, 3); j < J && j + 1 <= (int)g_fuse_logn && leaves <= FUSE_MAX_LEAVES; j++) {
+    if (classify2(1ull << j, 1ull << j).cls == CLS_LDS) {
+      if (jf0 < 0) jf0 = j;
+      jf1 = j;
+    } else if (jf0 >= 0) {
+      break;
+    }
+  }
   // Q_e is complete after level jdone - 1 (at least the leaf levels), in
-  // in_of(jdone); the plain form carries early roots up to the same place
+  // in_of(jdone); the plain form carries early roots up to the same place.
+  // A root completed inside the fused levels is where the fused launch
+  // leaves it, in in_of(jf1 + 1), in both forms.
   int jdone[CAT_MAX_GROUPS];
   for (uint32_t gi = 0; gi < ng; gi++) {
     jdone[gi] = std::max(ceil_log2(P.off[gi + 1] - P.off[gi]), jleaf);
+    if (jf0 >= 0 && jdone[gi] > jf0 && jdone[gi] <= jf1 + 1) jdone[gi] = jf1 + 1;
     P.root[gi] = in_of(jdone[gi]) + P.off[gi];
   }
   int jstart = 0;
@@ -582,7 +621,39 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   }
   int j = jstart;
   for (; j < J; j++) {
+    if (batched && j == jf0) {
+      // the fused levels: one workgroup per 2^FT_LOGT leaves of every group
+      // that still has products there
+      Stage s;
+      s.is_fused = true;
+      s.jfirst = jf0;
+      FusedTree& f = s.fused;
+      f.j0 = (uint32_t)jf0;
+      f.j1 = (uint32_t)jf1;
+      uint32_t tiles = 0;
+      for (uint32_t gi = 0; gi < ng; gi++) {
+        if (jdone[gi] <= jf0) continue;
+        const uint64_t K = P.off[gi + 1] - P.off[gi];
+        f.base[f.ngroups] = P.off[gi];
+        f.K[f.ngroups] = K;
+        f.tpref[f.ngroups] = tiles;
+        tiles += (uint32_t)((K + FT_SLOTS - 1) / FT_SLOTS);
+        f.ngroups++;
+      }
+      f.tpref[f.ngroups] = tiles;
+      s.fused_tiles = tiles;
+      for (int jj = jf0; jj <= jf1; jj++) {
+        for (int q = 0; q < CAT_NPRIMES; q++) f.scale[jj - jf0][q] = scale_pair(q, jj + 1);
+        s.fused_bfly += bfly(9.0 * tiles * (FT_SLOTS >> (jj + 1)), jj + 1);
+      }
+      s.a_base = in_of(jf0);
+      s.c_base = out_of(jf1);
+      st.push_back(s);
+      j = jf1;
+      continue;
+    }
     Stage s;
+    s.jfirst = j;
     s.dv.table = nullptr;
     TreeLevel& t = s.dv.tree;
     t.ngroups = ng;
@@ -629,11 +700,19 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   }
   P.levels = (uint32_t)j;
   if (batched) {
-    // stages after which every group with e >= 2 is complete
+    // stages after which every group with e >= 2 is complete: those that
+    // begin at a level below jdone (the leaf stage begins at level 0)
     int jf = -1;
     for (uint32_t gi = 0; gi < ng; gi++)
       if (P.exps[gi] >= 2) jf = std::max(jf, jdone[gi]);
-    P.fork_count = jf < 0 ? -1 : (jstart > 0 ? 1 : 0) + std::max(0, jf - jstart);
+    if (jf < 0) {
+      P.fork_count = -1;
+    } else {
+      int fc = 0;
+      for (const Stage& s : st)
+        if ((s.is_leaf ? 0 : s.jfirst) <= jf - 1) fc++;
+      P.fork_count = fc;
+    }
   }
 }
 
@@ -823,7 +902,7 @@ void plan_post(const Layout& Ly, Plan& P) {
 // Descriptor and segment tables: carried inline in the kernel arguments when
 // small (every catalan plan), otherwise uploaded to one device buffer (large
 // generic batches).  *dev stays nullptr when nothing needs device memory.
-cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
+cat_status upload_tables(std::vector<Stage*>& all, void** dev, bool device_tables = true) {
   size_t bytes = 0;
   for (Stage* s : all) {
     if (s->host_desc.size() > CAT_INLINE_DESC) bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
@@ -833,6 +912,9 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev) {
       bytes = align_up(bytes, 16) + (size_t)s->nblk * sizeof(uint32_t);
     }
   }
+  // callers that must not allocate get CAT_EINTERNAL instead (C(n) plans
+  // always fit the kernel arguments)
+  if (bytes && !device_tables) return CAT_EINTERNAL;
   char* d = nullptr;
   std::vector<char> h(std::max<size_t>(bytes, 16), 0);
   if (bytes) HIPCHK(hipMalloc(&d, bytes));
@@ -887,7 +969,7 @@ void free_plan(Plan* P) {
   delete P;
 }
 
-cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
+cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out, bool device_tables = true) {
   Plan* P = new Plan();
   P->n = Ly.n;
   P->ng = gt.ngroups;
@@ -935,7 +1017,7 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out) {
     free_plan(P);
     return CAT_EINTERNAL;
   }
-  cat_status st = upload_tables(all, &P->dev);
+  cat_status st = upload_tables(all, &P->dev, device_tables);
   if (st != CAT_OK) {
     free_plan(P);
     return st;
@@ -1186,6 +1268,17 @@ cat_status copy_tails(Exec& X, const Stage& s) {
 SegView stage_segs(const Stage& s) { return s.sv; }
 
 cat_status run_stage_batched(Exec& X, const Stage& s) {
+  if (s.is_fused) {
+    if (s.fused_tiles == 0) return CAT_OK;
+    {
+      KTime kt("k_tree_fused", X.st, s.fused_bfly);
+      hipLaunchKernelGGL(k_tree_fused, dim3(s.fused_tiles), dim3(FT_THREADS), 0, X.st, s.fused, X.W + s.a_base,
+                         X.W + s.c_base, tables_for(0), X.err);
+    }
+    LAUNCHCHK();
+    X.launches++;
+    return CAT_OK;
+  }
   if (s.is_leaf) {
     const uint32_t blocks = (uint32_t)((s.leaf_nodes + 255) / 256);
     {
@@ -1341,14 +1434,37 @@ cat_status read_groups(const Layout& Ly, char* wb, hipStream_t st, GroupTable* o
   return CAT_OK;
 }
 
-Plan* find_plan(uint64_t n, const GroupTable& gt) {
-  auto it = g.plans.find(n);
-  if (it == g.plans.end()) return nullptr;
+Plan* find_plan_in(std::map<uint64_t, Plan*>& plans, uint64_t n, const GroupTable& gt) {
+  auto it = plans.find(n);
+  if (it == plans.end()) return nullptr;
   Plan* P = it->second;
   if (P->ng != gt.ngroups) return nullptr;
   for (uint32_t k = 0; k < gt.ngroups; k++)
     if (P->exps[k] != gt.exps[k] || P->off[k + 1] != gt.off[k + 1] || P->gbits[k] != gt.gbits[k]) return nullptr;
   return P;
+}
+
+Plan* find_plan(uint64_t n, const GroupTable& gt) { return find_plan_in(g.plans, n, gt); }
+
+// Plans of the allocation-free entry point: kept apart from the main cache
+// (whose eviction destroys graphs); they hold no device memory, so dropping
+// one frees host memory only.
+#define NOALLOC_PLANS_MAX 64
+void remember_noalloc_plan(Plan* P) {
+  auto it = g.noalloc_plans.find(P->n);
+  if (it != g.noalloc_plans.end()) {
+    free_plan(it->second);
+    g.noalloc_plans.erase(it);
+    g.noalloc_order.erase(std::find(g.noalloc_order.begin(), g.noalloc_order.end(), P->n));
+  }
+  g.noalloc_plans[P->n] = P;
+  g.noalloc_order.push_back(P->n);
+  while (g.noalloc_order.size() > NOALLOC_PLANS_MAX) {
+    const uint64_t old = g.noalloc_order.front();
+    g.noalloc_order.erase(g.noalloc_order.begin());
+    free_plan(g.noalloc_plans[old]);
+    g.noalloc_plans.erase(old);
+  }
 }
 
 void remember_plan(Plan* P) {
@@ -1775,6 +1891,110 @@ cat_status read_groups_ratio(const Layout& Ly, char* wb, hipStream_t st, GroupTa
   return CAT_OK;
 }
 
+// The general form of a C(n) call in a given workspace: Phase 1, the group
+// table to the host, the plan of n (cached by n), Phase 2 as launches or as
+// one captured graph, the normalisation and the copy of the result to
+// d_limbs.  With `noalloc` nothing is allocated on the device: the plan comes
+// from a cache of its own whose plans carry no device tables and no graphs.
+static cat_status exact_in_workspace(uint64_t n, const Layout& Ly, char* wb, uint32_t* d_limbs, size_t cap,
+                              size_t* n_limbs, hipStream_t st, bool plain, bool use_graph, bool noalloc,
+                              uint64_t launches) {
+  cat_stats stats{};
+  unsigned long long* top = (unsigned long long*)(wb + Ly.top);
+  STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, st, &launches));
+  GroupTable gt;
+  STCHK(read_groups(Ly, wb, st, &gt));
+  if (gt.err & CAT_DEVERR_BOUNDS) return CAT_EINTERNAL;
+  Plan* P = noalloc ? find_plan_in(g.noalloc_plans, n, gt) : find_plan(n, gt);
+  if (!P) {
+    STCHK(make_plan(Ly, gt, &P, !noalloc));
+    if (noalloc) remember_noalloc_plan(P);
+    else remember_plan(P);
+  }
+  Exec X = make_exec(Ly, wb, st);
+  uint32_t* W = X.W;
+  if (P->result_is_one) {
+    if (cap < 1) {
+      *n_limbs = 1;
+      return CAT_ERANGE;
+    }
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, d_limbs, (uint64_t)1, 1u);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+    *n_limbs = 1;
+    g.stats = stats;
+    return CAT_OK;
+  }
+  auto record = [&](Exec& E) -> cat_status {
+    STCHK(run_phase2(E, *P, plain));
+    const uint32_t blocks = top_scan_blocks(P->result_cap);
+    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top,
+                       (uint32_t*)nullptr, (uint64_t)0);
+    LAUNCHCHK();
+    E.launches++;
+    return CAT_OK;
+  };
+  bool replayed = false;
+  if (use_graph) {
+    hipGraphExec_t ge = nullptr;
+    auto it = P->graphs.find((uintptr_t)wb);
+    if (it != P->graphs.end()) {
+      ge = it->second;
+      replayed = true;
+    } else {
+      Exec C = X;
+      C.st = g.cap_stream;
+      C.side = g.side_stream;
+      HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+      cat_status s = record(C);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
+      if (s != CAT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (e != hipSuccess) {
+        g.last_err = (int)e;
+        return CAT_EDEVICE;
+      }
+      e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        g.last_err = (int)e;
+        return CAT_EDEVICE;
+      }
+      cache_graph(P->graphs, P->graphs_order, (uintptr_t)wb, ge);
+      launches += C.launches;
+    }
+    HIPCHK(hipGraphLaunch(ge, st));
+    if (replayed) launches += 1;
+  } else {
+    STCHK(record(X));
+    launches += X.launches;
+  }
+  // top limb index and error word (adjacent in the control block)
+  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.top, 12, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint64_t L = 0;
+  uint32_t derr = 0;
+  memcpy(&L, g.pin, 8);
+  memcpy(&derr, (char*)g.pin + 8, 4);
+  if (derr) return CAT_EINTERNAL;
+  if (L == 0) return CAT_EINTERNAL;   // C(n) >= 1
+  *n_limbs = (size_t)L;
+  stats.products = P->products;
+  stats.product_limbs = P->product_limbs;
+  stats.launches = launches;
+  stats.n_primes = gt.off[gt.ngroups];
+  stats.levels = P->levels;
+  stats.graph_replayed = replayed ? 1 : 0;
+  g.stats = stats;
+  if (cap < L) return CAT_ERANGE;
+  HIPCHK(hipMemcpyAsync(d_limbs, W + P->result_pos, L * 4, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CAT_OK;
+}
+
 extern "C" {
 
 cat_status cat_init(int device) {
@@ -1807,6 +2027,21 @@ cat_status cat_tune_set(const cat_tuning* t) {
   for (auto& kv : g.plans) free_plan(kv.second);
   g.plans.clear();
   g.plan_order.clear();
+  return CAT_OK;
+}
+
+cat_status cat_fused_levels_set(uint32_t max_logn) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  if (max_logn != 0 && (max_logn < 4 || max_logn > FT_LOGT)) return CAT_EINVAL;
+  g_fuse_logn = max_logn;
+  // cached plans were made with the old setting
+  if (!g.plans.empty() || !g.noalloc_plans.empty()) HIPCHK(hipDeviceSynchronize());
+  for (auto& kv : g.plans) free_plan(kv.second);
+  g.plans.clear();
+  g.plan_order.clear();
+  for (auto& kv : g.noalloc_plans) free_plan(kv.second);
+  g.noalloc_plans.clear();
+  g.noalloc_order.clear();
   return CAT_OK;
 }
 
@@ -1971,97 +2206,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
     if (cap < L) return CAT_ERANGE;
     return CAT_OK;
   }
-  STCHK(run_phase1(Ly, wb, (uint32_t*)wb + Ly.primes, Ly.Kmax, st, &launches));
-  GroupTable gt;
-  STCHK(read_groups(Ly, wb, st, &gt));
-  if (gt.err & CAT_DEVERR_BOUNDS) return CAT_EINTERNAL;
-  Plan* P = find_plan(n, gt);
-  if (!P) {
-    STCHK(make_plan(Ly, gt, &P));
-    remember_plan(P);
-  }
-  Exec X = make_exec(Ly, wb, st);
-  uint32_t* W = X.W;
-  if (P->result_is_one) {
-    if (cap < 1) {
-      *n_limbs = 1;
-      return CAT_ERANGE;
-    }
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, d_limbs, (uint64_t)1, 1u);
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(st));
-    *n_limbs = 1;
-    g.stats = stats;
-    return CAT_OK;
-  }
-  auto record = [&](Exec& E) -> cat_status {
-    STCHK(run_phase2(E, *P, plain));
-    const uint32_t blocks = top_scan_blocks(P->result_cap);
-    hipLaunchKernelGGL(k_top_nonzero, dim3(blocks), dim3(256), 0, E.st, W + P->result_pos, P->result_cap, top,
-                       (uint32_t*)nullptr, (uint64_t)0);
-    LAUNCHCHK();
-    E.launches++;
-    return CAT_OK;
-  };
-  bool replayed = false;
-  if (use_graph) {
-    hipGraphExec_t ge = nullptr;
-    auto it = P->graphs.find((uintptr_t)wb);
-    if (it != P->graphs.end()) {
-      ge = it->second;
-      replayed = true;
-    } else {
-      Exec C = X;
-      C.st = g.cap_stream;
-      C.side = g.side_stream;
-      HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
-      cat_status s = record(C);
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
-      if (s != CAT_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return s;
-      }
-      if (e != hipSuccess) {
-        g.last_err = (int)e;
-        return CAT_EDEVICE;
-      }
-      e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) {
-        g.last_err = (int)e;
-        return CAT_EDEVICE;
-      }
-      cache_graph(P->graphs, P->graphs_order, (uintptr_t)wb, ge);
-      launches += C.launches;
-    }
-    HIPCHK(hipGraphLaunch(ge, st));
-    if (replayed) launches += 1;
-  } else {
-    STCHK(record(X));
-    launches += X.launches;
-  }
-  // top limb index and error word (adjacent in the control block)
-  HIPCHK(hipMemcpyAsync(g.pin, wb + Ly.top, 12, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  uint64_t L = 0;
-  uint32_t derr = 0;
-  memcpy(&L, g.pin, 8);
-  memcpy(&derr, (char*)g.pin + 8, 4);
-  if (derr) return CAT_EINTERNAL;
-  if (L == 0) return CAT_EINTERNAL;   // C(n) >= 1
-  *n_limbs = (size_t)L;
-  stats.products = P->products;
-  stats.product_limbs = P->product_limbs;
-  stats.launches = launches;
-  stats.n_primes = gt.off[gt.ngroups];
-  stats.levels = P->levels;
-  stats.graph_replayed = replayed ? 1 : 0;
-  g.stats = stats;
-  if (cap < L) return CAT_ERANGE;
-  HIPCHK(hipMemcpyAsync(d_limbs, W + P->result_pos, L * 4, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return CAT_OK;
+  return exact_in_workspace(n, Ly, wb, d_limbs, cap, n_limbs, st, plain, use_graph, false, launches);
 }
 
 
@@ -2609,6 +2754,134 @@ cat_status bigint_compare(const uint32_t* d_x, size_t lx, uint64_t shift_bits, c
   const uint32_t a = r ? ((x2[0] >> r) | (x2[1] << (32 - r))) : x2[0];
   *sign = a > b ? 1 : -1;
   return CAT_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Exact decimal digit count (Table 1's 1,234,567,890 digits): d is the count
+// of x > 0 exactly when 10^(d-1) <= x < 10^d, checked on the device as
+// floor(x / 2^(d-1)) >= 5^(d-1) and floor(x / 2^d) < 5^d; the powers of five
+// come from the Phase-2 engine ((5^13)^q * 5^r), the first guess of d from
+// the top limbs in double precision, corrected by at most a few steps.
+// ----------------------------------------------------------------------------
+#define DD_HEAD 512   // entries (two words) and the comparison scratch
+static const uint32_t kPow5_13 = 1220703125u;   // 5^13 < 2^31
+
+// groups of 5^k for the product engine: exponent 1 on [5^r] and q on [5^13]
+static uint32_t pow5_groups(uint64_t k, uint32_t* exps, uint64_t* off, uint32_t* ent) {
+  const uint64_t q = k / 13, r = k % 13;
+  uint32_t p5r = 1;
+  for (uint64_t i = 0; i < r; i++) p5r *= 5u;
+  if (q <= 1) {
+    exps[0] = 1;
+    off[0] = 0;
+    off[1] = q ? 2 : 1;
+    ent[0] = p5r;
+    ent[1] = kPow5_13;
+    return 1;
+  }
+  exps[0] = 1;
+  exps[1] = (uint32_t)q;
+  off[0] = 0;
+  off[1] = 1;
+  off[2] = 2;
+  ent[0] = p5r;
+  ent[1] = kPow5_13;
+  return 2;
+}
+
+static uint64_t dd_max_digits(size_t n_limbs) { return (uint64_t)(32.0 * (double)n_limbs * 0.30102999566398120) + 2; }
+
+// limbs and product-engine workspace for 5^k, k <= kmax
+static cat_status dd_sizes(uint64_t kmax, size_t* p5_limbs, size_t* ppp_bytes) {
+  uint32_t exps[2], ent[2];
+  uint64_t off[3];
+  const uint32_t ng = pow5_groups(kmax, exps, off, ent);
+  size_t ml = 0, wb = 0;
+  STCHK(prime_power_product_sizes(exps, off, ng, 31, &ml, &wb));
+  *p5_limbs = std::max<size_t>(ml, 2);
+  *ppp_bytes = wb;
+  return CAT_OK;
+}
+
+cat_status bigint_decimal_digits_workspace(size_t n_limbs, size_t* workspace_bytes) {
+  if (!workspace_bytes) return CAT_EINVAL;
+  if (n_limbs > (1ull << CAT_MAX_LOGN)) return CAT_EINVAL;
+  size_t pl = 0, pw = 0;
+  STCHK(dd_sizes(dd_max_digits(n_limbs), &pl, &pw));
+  *workspace_bytes = DD_HEAD + align_up(pl * 4, 256) + pw;
+  return CAT_OK;
+}
+
+cat_status bigint_decimal_digits(const uint32_t* d_x, size_t n_limbs, uint64_t* digits, void* d_work,
+                                 size_t work_bytes, void* stream) {
+  if (!digits || !d_work || (n_limbs && !d_x) || n_limbs > (1ull << CAT_MAX_LOGN)) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  size_t need = 0;
+  STCHK(bigint_decimal_digits_workspace(n_limbs, &need));
+  if (work_bytes < need) return CAT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)d_work;
+  unsigned long long* top = (unsigned long long*)(wb + 256);
+  // the highest nonzero limb
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)top, (uint64_t)2, 0u);
+  LAUNCHCHK();
+  if (n_limbs) {
+    hipLaunchKernelGGL(k_top_nonzero, dim3(top_scan_blocks(n_limbs)), dim3(256), 0, st, d_x, (uint64_t)n_limbs, top,
+                       (uint32_t*)nullptr, (uint64_t)0);
+    LAUNCHCHK();
+  }
+  HIPCHK(hipMemcpyAsync(g.pin, top, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint64_t L = 0;
+  memcpy(&L, g.pin, 8);
+  if (L == 0) {   // x = 0 has one digit
+    *digits = 1;
+    return CAT_OK;
+  }
+  const uint64_t k0 = L > 3 ? L - 3 : 0;
+  HIPCHK(hipMemcpyAsync(g.pin, d_x + k0, (L - k0) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint32_t tl[3] = {0, 0, 0};
+  memcpy(tl, g.pin, (L - k0) * 4);
+  double topv = 0;
+  for (uint64_t k = L; k > k0; k--) topv = topv * 4294967296.0 + (double)tl[k - 1 - k0];
+  int64_t d = (int64_t)std::floor(std::log10(topv) + 32.0 * (double)k0 * 0.30102999566398120) + 1;
+  size_t pl = 0, pw = 0;
+  STCHK(dd_sizes(dd_max_digits(n_limbs), &pl, &pw));
+  uint32_t* d_ent = (uint32_t*)wb;
+  uint32_t* d_y = (uint32_t*)(wb + DD_HEAD);
+  void* ppp = wb + DD_HEAD + align_up(pl * 4, 256);
+  // sign(floor(x / 2^k) - 5^k)
+  auto cmp_pow5 = [&](uint64_t k, int32_t* sgn) -> cat_status {
+    uint32_t exps[2], ent[2];
+    uint64_t off[3];
+    const uint32_t ng = pow5_groups(k, exps, off, ent);
+    memcpy((char*)g.pin + 2048, ent, 8);
+    HIPCHK(hipMemcpyAsync(d_ent, (char*)g.pin + 2048, 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    size_t ly = 0;
+    STCHK(prime_power_product(d_ent, exps, off, ng, 31, d_y, pl, &ly, ppp, pw, stream, CAT_MODE_BATCHED));
+    return bigint_compare(d_x, L, k, d_y, ly, sgn, wb + 256, 256, stream);
+  };
+  for (int it = 0; it < 6; it++) {
+    if (d < 1) d = 1;
+    int32_t s1 = 0, s2 = 0;
+    STCHK(cmp_pow5((uint64_t)(d - 1), &s1));
+    if (s1 < 0) {   // x < 10^(d-1)
+      d--;
+      continue;
+    }
+    STCHK(cmp_pow5((uint64_t)d, &s2));
+    if (s2 >= 0) {  // x >= 10^d
+      d++;
+      continue;
+    }
+    *digits = (uint64_t)d;
+    return CAT_OK;
+  }
+  return CAT_EINTERNAL;
 }
 
 }  // extern "C"

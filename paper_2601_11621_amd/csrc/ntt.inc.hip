@@ -96,7 +96,7 @@ __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
 // A thread handles U groups at once (g, g + blockDim, ...) so that the loads
 // of one overlap the arithmetic of the other.
 template <int LOGR, bool PAD, int U>
-__device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t logSR, uint32_t logC,
+__device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ tw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
@@ -104,7 +104,7 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
   uint32_t e0[U], cc[U], jj[U];
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const uint32_t g = g0 + u * blockDim.x;
+    const uint32_t g = g0 + u * nthr;
     const uint32_t h = g >> logC;
     cc[u] = g & cmask;
     jj[u] = h & smask;
@@ -138,7 +138,7 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
 }
 
 template <int LOGR, bool PAD, int U>
-__device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t logSR, uint32_t logC,
+__device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ itw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
   uint32_t e0[U], cc[U], jj[U];
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const uint32_t g = g0 + u * blockDim.x;
+    const uint32_t g = g0 + u * nthr;
     const uint32_t h = g >> logC;
     cc[u] = g & cmask;
     jj[u] = h & smask;
@@ -179,20 +179,24 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
   }
 }
 
+// Thread `tid` of the `nthr` threads that share the tile (the workgroup, or
+// one prime's part of a workgroup that holds several tiles).
 template <int LOGR, bool PAD>
 __device__ __forceinline__ void pass_fwd(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
-                                         const uint2* __restrict__ tw, const PrimeC& pc) {
-  uint32_t g = threadIdx.x;
-  for (; g + blockDim.x < ngroups; g += 2 * blockDim.x) groups_fwd<LOGR, PAD, 2>(lds, g, logSR, logC, tw, pc);
-  for (; g < ngroups; g += blockDim.x) groups_fwd<LOGR, PAD, 1>(lds, g, logSR, logC, tw, pc);
+                                         const uint2* __restrict__ tw, const PrimeC& pc, uint32_t tid,
+                                         uint32_t nthr) {
+  uint32_t g = tid;
+  for (; g + nthr < ngroups; g += 2 * nthr) groups_fwd<LOGR, PAD, 2>(lds, g, nthr, logSR, logC, tw, pc);
+  for (; g < ngroups; g += nthr) groups_fwd<LOGR, PAD, 1>(lds, g, nthr, logSR, logC, tw, pc);
 }
 
 template <int LOGR, bool PAD>
 __device__ __forceinline__ void pass_inv(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
-                                         const uint2* __restrict__ itw, const PrimeC& pc) {
-  uint32_t g = threadIdx.x;
-  for (; g + blockDim.x < ngroups; g += 2 * blockDim.x) groups_inv<LOGR, PAD, 2>(lds, g, logSR, logC, itw, pc);
-  for (; g < ngroups; g += blockDim.x) groups_inv<LOGR, PAD, 1>(lds, g, logSR, logC, itw, pc);
+                                         const uint2* __restrict__ itw, const PrimeC& pc, uint32_t tid,
+                                         uint32_t nthr) {
+  uint32_t g = tid;
+  for (; g + nthr < ngroups; g += 2 * nthr) groups_inv<LOGR, PAD, 2>(lds, g, nthr, logSR, logC, itw, pc);
+  for (; g < ngroups; g += nthr) groups_inv<LOGR, PAD, 1>(lds, g, nthr, logSR, logC, itw, pc);
 }
 
 // radix of the pass at sub-problem size 2^logS
@@ -225,17 +229,18 @@ __device__ __forceinline__ void pass_sync(int logSmall, uint32_t logC) {
 // threads read them.
 template <bool PAD>
 __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
-                             const uint2* __restrict__ tws, const PrimeC& pc) {
+                             const uint2* __restrict__ tws, const PrimeC& pc, uint32_t tid = threadIdx.x,
+                             uint32_t nthr = blockDim.x) {
   while (logS > 0) {
     const int lr = pass_logr(logS);
     const uint32_t ng = total >> lr;
     const uint32_t logSR = (uint32_t)(logS - lr);
     const uint2* tw = tws + tws_off(logS);
     switch (lr) {
-      case 1: pass_fwd<1, PAD>(lds, ng, logSR, logC, tw, pc); break;
-      case 2: pass_fwd<2, PAD>(lds, ng, logSR, logC, tw, pc); break;
-      case 3: pass_fwd<3, PAD>(lds, ng, logSR, logC, tw, pc); break;
-      default: pass_fwd<4, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      case 1: pass_fwd<1, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 2: pass_fwd<2, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 3: pass_fwd<3, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      default: pass_fwd<4, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
     }
     logS -= lr;
     if (logS > 0) {
@@ -250,12 +255,13 @@ __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t t
 // transform ends with a workgroup barrier.
 template <bool PAD>
 __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
-                             const uint2* __restrict__ itws, const PrimeC& pc) {
+                             const uint2* __restrict__ itws, const PrimeC& pc, uint32_t tid = threadIdx.x,
+                             uint32_t nthr = blockDim.x) {
   // passes in the reverse order of ntt_fwd_tile: the radix-16 passes of sizes
   // 2^4, 2^8, ... first, the (possibly smaller-radix) pass of size 2^logS last
   const int lr0 = pass_logr(logS);
   for (int ls = 4; ls <= logS - lr0; ls += 4) {
-    pass_inv<4, PAD>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc);
+    pass_inv<4, PAD>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc, tid, nthr);
     if (ls + 4 <= logS - lr0 || lr0 == 4) pass_sync(ls, logC);   // the next pass has radix 16
     else __syncthreads();
   }
@@ -264,10 +270,10 @@ __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t t
     const uint32_t logSR = (uint32_t)(logS - lr0);
     const uint2* tw = itws + tws_off(logS);
     switch (lr0) {
-      case 1: pass_inv<1, PAD>(lds, ng, logSR, logC, tw, pc); break;
-      case 2: pass_inv<2, PAD>(lds, ng, logSR, logC, tw, pc); break;
-      case 3: pass_inv<3, PAD>(lds, ng, logSR, logC, tw, pc); break;
-      default: pass_inv<4, PAD>(lds, ng, logSR, logC, tw, pc); break;
+      case 1: pass_inv<1, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 2: pass_inv<2, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 3: pass_inv<3, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      default: pass_inv<4, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
     }
   }
   __syncthreads();

@@ -193,3 +193,32 @@ def test_replay_reads_current_input(cat):
         st, n = conv(vals[2], len(want) - 1)
         assert st == cat.CAT_ERANGE and n == len(want)
         assert bool((out == 35).all())
+
+
+def test_decimal_digit_count_entry(cat):
+    """bigint_decimal_digits (the exact digit count in the library) against
+    the length of Python's own decimal text: powers of ten and their
+    neighbours (where a first guess from the top limbs is most fragile),
+    zero, leading zero limbs, and random values."""
+    rng = np.random.default_rng(77)
+    vals = [0, 1, 9, 10, 99, 100, 2**32 - 1, 2**32, 2**64 - 1]
+    for k in (9, 10, 19, 20, 38, 39, 200, 1000, 4000, 20001):
+        vals += [10**k - 1, 10**k, 10**k + 1]
+    vals += [int.from_bytes(rng.bytes(int(nb)), "little") for nb in (3, 40, 401, 4000, 40001)]
+    for v in vals:
+        L = max(1, (v.bit_length() + 31) // 32)
+        limbs = oracle.int_to_limbs(v, L + 2)        # two leading zero limbs
+        got = cat.decimal_digits(cat.from_numpy(limbs))
+        assert got == _ndigits(v), (v.bit_length(), got)
+
+
+def _ndigits(v: int) -> int:
+    """Decimal digits of v >= 0 by exact comparison with powers of ten."""
+    if v == 0:
+        return 1
+    d = max(1, int(v.bit_length() * 0.30102999566398120))
+    while 10 ** (d - 1) > v:
+        d -= 1
+    while 10**d <= v:
+        d += 1
+    return d

@@ -315,3 +315,25 @@ def test_schedules_change_speed_not_bits(cat, schedule):
         assert torch.equal(c0, c1)
     finally:
         cat.set_tuning(base)
+
+
+@pytest.mark.parametrize("logn", [0, 9, 10, 12])
+def test_fused_levels_same_bits(cat, logn):
+    """The lower tree levels fused into one launch (tiles of 4,096 leaves kept
+    in LDS across levels, carries inside the workgroup) give the same C(n) as
+    one transform launch and one carry launch per level: ragged last tiles,
+    groups whose tree ends inside the fused levels, and sizes where the fused
+    range is cut short by the tree height."""
+    try:
+        cat.set_fused_levels(logn)
+        for n in (300, 2500, 5000, 13337, 65536, 100000, 262147, 1000003):
+            _say("fused", logn, n)
+            got = cat.to_numpy(cat.exact(n, mode="graph"))
+            assert np.array_equal(got, oracle.catalan(n)), (logn, n)
+            assert np.array_equal(cat.to_numpy(cat.exact(n, mode="batched")), got), (logn, n)
+        with open(os.path.join(GOLDEN, "oracle_catalan.json")) as f:
+            gold = json.load(f)["10000000"]
+        got = cat.to_numpy(cat.exact(10**7, mode="graph"))
+        assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
+    finally:
+        cat.set_fused_levels(12)

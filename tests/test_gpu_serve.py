@@ -1,6 +1,12 @@
 """Serving on the GPU: requests of mixed n admitted while others run, their
 work overlapping on several streams; every result must equal the same n
-computed alone (bit for bit) and, where cheap, the CPU oracle."""
+computed alone (bit for bit) and the CPU oracle's C(n) (through the digests
+in tests/golden/serving_digests.json, written by a script that calls only the
+oracle, for every distinct n of these streams)."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -8,6 +14,13 @@ import oracle
 from tests import batch_inputs
 
 pytestmark = pytest.mark.gpu
+with open(os.path.join(os.path.dirname(__file__), "golden", "serving_digests.json")) as _f:
+    ORACLE = json.load(_f)["digests"]
+
+
+def _oracle_match(limbs: np.ndarray, n: int) -> bool:
+    L, h = ORACLE[str(n)]
+    return len(limbs) == L and hashlib.sha256(limbs.astype("<u4").tobytes()).hexdigest() == h
 
 
 @pytest.fixture(scope="module")
@@ -42,8 +55,7 @@ def test_mix_equals_solo_closed_loop(cat):
         assert r.state == DONE, (r.n, r.error)
         got = cat.to_numpy(r.result)
         assert np.array_equal(got, solo[r.n]), r.n
-        if r.n <= 20000:
-            assert np.array_equal(got, oracle.catalan(r.n)), r.n
+        assert _oracle_match(got, r.n), r.n
 
 
 def test_mix_equals_solo_poisson_arrivals(cat):
@@ -60,7 +72,8 @@ def test_mix_equals_solo_poisson_arrivals(cat):
     solo = _solo(cat, [int(n) for n in ns])
     for r in reqs:
         assert r.state == DONE, (r.n, r.error)
-        assert np.array_equal(cat.to_numpy(r.result), solo[r.n]), r.n
+        got = cat.to_numpy(r.result)
+        assert np.array_equal(got, solo[r.n]) and _oracle_match(got, r.n), r.n
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
 
@@ -164,7 +177,7 @@ def test_device_memory_stays_within_budget(cat):
 
     def consume(r):
         if r.state == DONE:
-            if r.n <= 20000 and not np.array_equal(cat.to_numpy(r.result), oracle.catalan(r.n)):
+            if not _oracle_match(cat.to_numpy(r.result), r.n):
                 bad.append(r.n)
             r.result = None
 
