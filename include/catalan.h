@@ -111,6 +111,25 @@ cat_status catalan_exact(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_li
 cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* d_work,
                             size_t work_bytes, void* stream, uint32_t flags);
 
+/* Allocation-free C(n), for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same result as catalan_exact, bit for bit, computed with
+ * batched launches (no graph) in a static device scratch array of the
+ * library instead of a caller workspace; the call allocates nothing on the
+ * device and synchronises `stream` before returning.
+ *  n:       as catalan_exact; CAT_ENOMEM when the workspace of n (see
+ *           catalan_sizes) exceeds the scratch (every n <= 10^7 fits);
+ *  d_limbs: device output of cap limbs, caller-owned, not NULL; C(n) as
+ *           normalised limbs d_limbs[0 .. *n_limbs); CAT_ERANGE if
+ *           cap < *n_limbs (then *n_limbs holds the length).
+ * The scratch is one per GPU, shared by every call on that GPU, and keeps the
+ * last call's contents (each call clears what it needs).  Calls in one
+ * process are serialised by the library lock and end with a stream
+ * synchronisation, so they never overlap; overlapping calls would race.
+ * catalan_noalloc_max_bytes: the scratch size in bytes (host only). */
+cat_status catalan_exact_noalloc(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* stream);
+cat_status catalan_noalloc_max_bytes(size_t* bytes);
+
 /* sign(floor(x / 2^shift_bits) - y) in *sign (-1, 0, 1) for little-endian limb
  * vectors x[0..lx), y[0..ly) (leading zero limbs allowed).  d_work: at least
  * 16 bytes of device scratch.  Synchronises `stream`.  With x = C(n) and

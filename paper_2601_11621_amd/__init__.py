@@ -33,7 +33,8 @@ EXPORTS = [
     "cat_tune_set", "cat_tune_get", "cat_lookback_polls_set",
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
-    "decimal_sizes", "bigint_to_decimal", "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits",
+    "decimal_sizes", "bigint_to_decimal", "catalan_exact_noalloc", "catalan_noalloc_max_bytes",
+    "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits",
 ]
 
 
@@ -123,6 +124,8 @@ def load(path: str = LIB_PATH):
         "cat_tune_get": ([ctypes.POINTER(cat_tuning)], st),
         "decimal_sizes": ([ctypes.c_size_t, szp, szp], st),
         "bigint_to_decimal": ([vp, ctypes.c_size_t, vp, ctypes.c_size_t, szp, vp, ctypes.c_size_t, vp], st),
+        "catalan_exact_noalloc": ([ctypes.c_uint64, vp, ctypes.c_size_t, szp, vp], st),
+        "catalan_noalloc_max_bytes": ([szp], st),
         "cat_fused_levels_set": ([ctypes.c_uint32], st),
         "bigint_decimal_digits_workspace": ([ctypes.c_size_t, szp], st),
         "bigint_decimal_digits": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
@@ -294,6 +297,23 @@ def exact(n: int, mode: str = "graph", stream=None, out=None):
                               _MODES[mode])
     _check(st, "catalan_exact")
     return out[: nl.value]
+
+
+def exact_noalloc(n: int, out, stream=None):
+    """C(n) into the caller's int32 device tensor `out` by the allocation-free
+    entry point (the library's static device scratch); returns out[:limbs]."""
+    lib = load()
+    nl = ctypes.c_size_t()
+    _check(lib.catalan_exact_noalloc(n, _ptr(out), out.numel(), ctypes.byref(nl), _stream(stream)),
+           "catalan_exact_noalloc")
+    return out[: nl.value]
+
+
+def noalloc_max_bytes() -> int:
+    """Size of the static scratch behind exact_noalloc (host only)."""
+    b = ctypes.c_size_t()
+    _check(load().catalan_noalloc_max_bytes(ctypes.byref(b)), "catalan_noalloc_max_bytes")
+    return b.value
 
 
 def _terms(xs):

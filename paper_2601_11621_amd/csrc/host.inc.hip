@@ -42,6 +42,7 @@ struct Lib {
   std::vector<uint64_t> plan_order;
   std::map<uint64_t, Plan*> noalloc_plans;      // plans of catalan_exact_noalloc
   std::vector<uint64_t> noalloc_order;
+  void* scratch_ptr = nullptr;                  // device address of `scratch` on g.device
   bool in_noalloc = false;                      // a catalan_exact_noalloc call is running
   hipStream_t cap_stream = nullptr;
   hipStream_t side_stream = nullptr;            // second branch of captured calls
@@ -55,6 +56,16 @@ struct Lib {
 };
 Lib g;
 
+// Device scratch of the allocation-free entry point catalan_exact_noalloc,
+// for callers that cannot allocate device memory.  It holds the workspace
+// layout of one C(n) call (primes, tree arenas, residues, transform scratch,
+// control block) for every n whose workspace fits (n <= 10^7 does).  Each GPU
+// that loads the library holds its own copy until the process ends.  In host
+// code `scratch` only stands in for the symbol: its device address comes from
+// hipGetSymbolAddress at initialisation (g.scratch_ptr), and that address is
+// what the kernels receive.
+#define CAT_NOALLOC_BYTES ((size_t)144 << 20)
+static __device__ __align__(256) unsigned char scratch[CAT_NOALLOC_BYTES];
 
 // Brackets a launch of kernel `name` with events when the timer watches it.
 struct KTime {
@@ -216,6 +227,9 @@ cat_status init_locked(int device) {
   LAUNCHCHK();
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipHostMalloc(&g.pin, 1 << 16, hipHostMallocDefault));
+  // the device's own copy of the static scratch (the device is current here)
+  HIPCHK(hipGetSymbolAddress(&g.scratch_ptr, HIP_SYMBOL(scratch)));
+  if (!g.scratch_ptr) return CAT_EDEVICE;
   HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&g.side_stream, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
@@ -2477,6 +2491,27 @@ cat_status cat_ticket_release(cat_ticket ticket) {
   // d_limbs go back to the caller
   (void)hipStreamSynchronize(t->st);
   ticket_free(t);
+  return CAT_OK;
+}
+
+cat_status catalan_exact_noalloc(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* stream) {
+  if (n > CAT_N_MAX || !n_limbs || !d_limbs) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  const Layout Ly = make_layout(n);
+  if (Ly.total > CAT_NOALLOC_BYTES) return CAT_ENOMEM;   // beyond the static scratch
+  if (!g.scratch_ptr) return CAT_EINTERNAL;
+  g.in_noalloc = true;
+  const cat_status s = exact_in_workspace(n, Ly, (char*)g.scratch_ptr, d_limbs, cap, n_limbs, (hipStream_t)stream,
+                                          false, false, true, 0);
+  g.in_noalloc = false;
+  return s;
+}
+
+cat_status catalan_noalloc_max_bytes(size_t* bytes) {
+  if (!bytes) return CAT_EINVAL;
+  *bytes = CAT_NOALLOC_BYTES;
   return CAT_OK;
 }
 
