@@ -91,8 +91,18 @@ cat_status bigint_mul_workspace(uint32_t batch, const uint64_t* h_a_off, const u
  * d_c[h_c_off[i] .. h_c_off[i] + la_i + lb_i), not normalised (leading zero
  * limbs kept).  Offsets are host arrays of batch+1 entries (h_c_off: batch).
  * Requirements: 1 <= la_i, lb_i and la_i + lb_i - 1 <= 2^27; the c ranges must
- * not overlap each other nor any operand.  Synchronises `stream`; CAT_EINTERNAL
- * if a device check failed.  flags: CAT_MODE_BATCHED or CAT_MODE_PLAIN. */
+ * not overlap each other nor any operand.  flags: CAT_MODE_BATCHED or
+ * CAT_MODE_PLAIN.
+ * Asynchronous on `stream`: the call returns once the products are queued
+ * (CAT_EINVAL / CAT_ENOMEM / CAT_EDEVICE for what the host can see); d_a, d_b,
+ * d_c and d_work must stay untouched until that work has finished.  The
+ * device-side check (a product needing more than la_i + lb_i limbs, which
+ * exact arithmetic rules out) is read by bigint_mul_check.  The library
+ * keeps the plans of the last 16 batch shapes (lengths and output offsets),
+ * so a repeated shape costs no planning and no table upload; a new shape's
+ * descriptor tables are uploaded on `stream`.
+ * bigint_mul_check: synchronises `stream` and returns CAT_EINTERNAL if the
+ * last product batch run in d_work failed its device check, else CAT_OK. */
 cat_status bigint_mul_batched(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off,
                               const uint32_t* d_b, const uint64_t* h_b_off, uint32_t* d_c,
                               const uint64_t* h_c_off, void* d_work, size_t work_bytes, void* stream);
@@ -100,6 +110,7 @@ cat_status bigint_mul_batched_ex(uint32_t batch, const uint32_t* d_a, const uint
                                  const uint32_t* d_b, const uint64_t* h_b_off, uint32_t* d_c,
                                  const uint64_t* h_c_off, void* d_work, size_t work_bytes, void* stream,
                                  uint32_t flags);
+cat_status bigint_mul_check(void* d_work, void* stream);
 
 /* C(n) (Sec. 1) by Phase 1 + Phase 2 (Alg. 1, Alg. 2) as normalised limbs:
  * d_limbs[0 .. *n_limbs), top limb nonzero, C(0) = C(1) = {1}.
@@ -286,7 +297,9 @@ cat_status cat_get_stats(cat_stats* out);
 /* Product schedule per transform-length bucket (the autotuner's output).
  * Products with la, lb <= school_max use the schoolbook kernel; otherwise
  * bucket k = ceil(log2(la + lb - 1)) (at least 6) selects cls[k]:
- * 1 = one workgroup holds the whole transform (k <= 14), 2 = four-step
+ * 1 = one workgroup holds the whole transform (k <= 14) in a tile of
+ * 2^max(k, log_row[k]) slots per operand (log_row 12..14: 2^(log_row - k)
+ * products and 2^log_row / 16 threads per workgroup), 2 = four-step
  * transform with rows of 2^log_row[k] words (8..14, < k) and column passes of
  * at most 2^log_pass[k] points (4..10).  Every schedule gives the same bits.
  * cat_tune_set(NULL) restores the defaults; CAT_EINVAL for an invalid table.

@@ -34,7 +34,7 @@ EXPORTS = [
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
     "decimal_sizes", "bigint_to_decimal", "catalan_exact_noalloc", "catalan_noalloc_max_bytes",
-    "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits",
+    "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
 ]
 
 
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
         "cat_fused_levels_set": ([ctypes.c_uint32], st),
         "bigint_decimal_digits_workspace": ([ctypes.c_size_t, szp], st),
         "bigint_decimal_digits": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
+        "bigint_mul_check": ([vp, vp], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -472,6 +473,9 @@ def mul_batched(a_flat, a_off, b_flat, b_off, mode: str = "batched", stream=None
     st = lib.bigint_mul_batched_ex(batch, _ptr(a_flat), _p64(a_off), _ptr(b_flat), _p64(b_off), _ptr(c),
                                    _p64(c_off), _ptr(w), w.numel(), _stream(stream), _MODES[mode] & ~MODE_GRAPH)
     _check(st, "bigint_mul_batched")
+    if batch:
+        # the call only queued the products; wait for them and read the device check
+        _check(lib.bigint_mul_check(_ptr(w), _stream(stream)), "bigint_mul_check")
     return c[: int(c_off[-1])], c_off
 
 

@@ -317,7 +317,8 @@ bool tuning_valid(const cat_tuning& t) {
   if (t.school_max < 1 || t.school_max > SCHOOL_MAX) return false;
   for (int k = 6; k <= CAT_MAX_LOGN; k++) {
     if (t.cls[k] == CLS_LDS) {
-      if (k > CAT_LDS_MAX_LOGT) return false;
+      // log_row: the tile of 2^log_row slots (12..14; at least the transform)
+      if (k > CAT_LDS_MAX_LOGT || t.log_row[k] < CAT_LDS_LOGT || t.log_row[k] > CAT_LDS_MAX_LOGT) return false;
     } else if (t.cls[k] == CLS_LARGE) {
       if (t.log_row[k] < 8 || t.log_row[k] > CAT_LDS_MAX_LOGT || k <= t.log_row[k]) return false;
       if (t.log_pass[k] < 4 || t.log_pass[k] > 10) return false;
@@ -916,7 +917,8 @@ void plan_post(const Layout& Ly, Plan& P) {
 // Descriptor and segment tables: carried inline in the kernel arguments when
 // small (every catalan plan), otherwise uploaded to one device buffer (large
 // generic batches).  *dev stays nullptr when nothing needs device memory.
-cat_status upload_tables(std::vector<Stage*>& all, void** dev, bool device_tables = true) {
+cat_status upload_tables(std::vector<Stage*>& all, void** dev, bool device_tables = true,
+                         std::vector<char>* keep = nullptr, hipStream_t st = nullptr) {
   size_t bytes = 0;
   for (Stage* s : all) {
     if (s->host_desc.size() > CAT_INLINE_DESC) bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
@@ -971,7 +973,13 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev, bool device_table
       for (size_t k = 0; k < s->host_pref.size(); k++) s->sv.ipref[k] = s->host_pref[k];
     }
   }
-  if (bytes) HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+  if (bytes && keep) {
+    // stream-ordered upload; the host image lives as long as the plan
+    keep->swap(h);
+    HIPCHK(hipMemcpyAsync(d, keep->data(), bytes, hipMemcpyHostToDevice, st));
+  } else if (bytes) {
+    HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+  }
   *dev = d;
   return CAT_OK;
 }
@@ -1147,7 +1155,10 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
   const NttTables tb = tables_for(s.logN);
   const uint2 s0 = scale_pair(0, s.logN), s1 = scale_pair(1, s.logN), s2 = scale_pair(2, s.logN);
   if (s.cls == CLS_LDS) {
-    const int lt = std::max(s.logN, CAT_LDS_LOGT);   // tile 2^lt, 2^lt/16 threads
+    // tile 2^lt (2^lt / 16 threads, 2^(lt - logN) products per workgroup): the
+    // schedule's tile for the bucket (log_row of a one-workgroup bucket)
+    // (at most 64 products per tile: the kernel's descriptor array)
+    const int lt = std::max(s.logN, std::min({std::max(s.logM, CAT_LDS_LOGT), CAT_LDS_MAX_LOGT, s.logN + 6}));
     const uint64_t per = (1ull << lt) >> s.logN;
     const uint64_t tiles = (cnt + per - 1) / per;
     const dim3 grid((uint32_t)(tiles * CAT_NPRIMES)), block((1u << lt) / 16);
@@ -1531,10 +1542,13 @@ struct MulPlanImpl {
   uint64_t products = 0, product_limbs = 0;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
   std::vector<std::vector<uintptr_t>> graphs_order;
+  std::vector<char> host_tables;             // source of an asynchronous table upload
 };
 
+// async_upload: the device tables are copied on `st` (ordered before the
+// plan's launches there) instead of by a synchronous copy.
 cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t* b_off, const uint64_t* c_off,
-                           uint32_t flags, MulPlanImpl** out) {
+                           uint32_t flags, MulPlanImpl** out, bool async_upload = false, hipStream_t upload_st = nullptr) {
   if (!a_off || !b_off || (!c_off && batch > 0)) return CAT_EINVAL;
   MulPlanImpl* M = new MulPlanImpl();
   M->batch = batch;
@@ -1584,13 +1598,15 @@ cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t
     off = align_up(off + bytes, 256);
     return o;
   };
+  // the control block first: the error word of every product plan is the
+  // first word of its workspace (bigint_mul_check reads it there)
+  M->off_ctl = take(MUL_CTL_FLAGS + 4 * M->nblk_max);
   M->off_res = take(3 * (M->res_len + 64) * 4);
   M->off_F = take(M->F_words * 4);
-  M->off_ctl = take(MUL_CTL_FLAGS + 4 * M->nblk_max);
   M->total = off;
   std::vector<Stage*> all;
   for (auto& st : M->stages) all.push_back(&st);
-  cat_status e = upload_tables(all, &M->dev);
+  cat_status e = upload_tables(all, &M->dev, true, async_upload ? &M->host_tables : nullptr, upload_st);
   if (e != CAT_OK) { delete M; return e; }
   *out = M;
   return CAT_OK;
@@ -1600,6 +1616,32 @@ void mul_plan_free(MulPlanImpl* M) {
   for (auto& kv : M->graphs) (void)hipGraphExecDestroy(kv.second);
   if (M->dev) (void)hipFree(M->dev);
   delete M;
+}
+
+// Plans of bigint_mul_batched, cached by shape (batch, mode and the three
+// offset arrays), so that a call only queues work.  A plan is destroyed only
+// once the event recorded after its last queued use has completed.
+struct MulCacheEntry {
+  std::vector<uint64_t> key;
+  MulPlanImpl* M = nullptr;
+  hipEvent_t ev = nullptr;   // after the last queued use
+  hipEvent_t up = nullptr;   // after the table upload (a later call may come on another stream)
+};
+std::vector<MulCacheEntry> g_mul_cache;   // least recently used first
+#define MUL_CACHE_MAX 16
+
+void mul_cache_drop(MulCacheEntry& e) {
+  if (e.ev) {
+    (void)hipEventSynchronize(e.ev);
+    (void)hipEventDestroy(e.ev);
+  }
+  if (e.up) (void)hipEventDestroy(e.up);
+  mul_plan_free(e.M);
+}
+
+void mul_cache_clear() {
+  for (auto& e : g_mul_cache) mul_cache_drop(e);
+  g_mul_cache.clear();
 }
 
 Exec mul_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c, char* wb, hipStream_t st) {
@@ -2037,6 +2079,7 @@ cat_status cat_tune_set(const cat_tuning* t) {
   if (!tuning_valid(v)) return CAT_EINVAL;
   g_tune = v;
   // cached plans and graphs were made with the old schedule
+  mul_cache_clear();
   if (!g.plans.empty()) HIPCHK(hipDeviceSynchronize());
   for (auto& kv : g.plans) free_plan(kv.second);
   g.plans.clear();
@@ -2292,31 +2335,73 @@ cat_status bigint_mul_workspace(uint32_t batch, const uint64_t* h_a_off, const u
 cat_status bigint_mul_batched_ex(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off, const uint32_t* d_b,
                                  const uint64_t* h_b_off, uint32_t* d_c, const uint64_t* h_c_off, void* d_work,
                                  size_t work_bytes, void* stream, uint32_t flags) {
+  if (!h_a_off || !h_b_off || (batch > 0 && !h_c_off)) return CAT_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(g.mu);
   STCHK(init_locked(-1));
   STCHK(set_device());
-  MulPlanImpl* M = nullptr;
-  STCHK(mul_plan_create(batch, h_a_off, h_b_off, h_c_off, flags & ~CAT_MODE_GRAPH, &M));
-  uint64_t launches = 0;
   hipStream_t st = (hipStream_t)stream;
-  cat_status s = mul_plan_exec(M, d_a, d_b, d_c, d_work, work_bytes, st, &launches);
-  hipError_t e = hipStreamSynchronize(st);
-  if (s == CAT_OK && e != hipSuccess) {
-    g.last_err = (int)e;
+  const uint32_t mode = flags & CAT_MODE_PLAIN;
+  std::vector<uint64_t> key;
+  key.reserve(3 * (size_t)batch + 4);
+  key.push_back(batch);
+  key.push_back(mode);
+  key.insert(key.end(), h_a_off, h_a_off + batch + 1);
+  key.insert(key.end(), h_b_off, h_b_off + batch + 1);
+  if (batch) key.insert(key.end(), h_c_off, h_c_off + batch);
+  size_t k = 0;
+  while (k < g_mul_cache.size() && g_mul_cache[k].key != key) k++;
+  if (k < g_mul_cache.size()) {
+    MulCacheEntry e = g_mul_cache[k];
+    g_mul_cache.erase(g_mul_cache.begin() + k);
+    g_mul_cache.push_back(e);
+    HIPCHK(hipStreamWaitEvent(st, e.up, 0));
+  } else {
+    MulCacheEntry e;
+    STCHK(mul_plan_create(batch, h_a_off, h_b_off, h_c_off, mode, &e.M, true, st));
+    hipError_t he = hipEventCreateWithFlags(&e.ev, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&e.up, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventRecord(e.up, st);
+    if (he != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      if (e.ev) (void)hipEventDestroy(e.ev);
+      if (e.up) (void)hipEventDestroy(e.up);
+      mul_plan_free(e.M);
+      g.last_err = (int)he;
+      return CAT_EDEVICE;
+    }
+    e.key.swap(key);
+    if (g_mul_cache.size() >= MUL_CACHE_MAX) {
+      mul_cache_drop(g_mul_cache.front());
+      g_mul_cache.erase(g_mul_cache.begin());
+    }
+    g_mul_cache.push_back(e);
+  }
+  MulCacheEntry& e = g_mul_cache.back();
+  uint64_t launches = 0;
+  cat_status s = mul_plan_exec(e.M, d_a, d_b, d_c, d_work, work_bytes, st, &launches);
+  const hipError_t he = hipEventRecord(e.ev, st);
+  if (s == CAT_OK && he != hipSuccess) {
+    g.last_err = (int)he;
     s = CAT_EDEVICE;
   }
-  if (s == CAT_OK && batch > 0) {
-    uint32_t derr = 0;
-    if (hipMemcpy(&derr, (char*)d_work + M->off_ctl, 4, hipMemcpyDeviceToHost) != hipSuccess) s = CAT_EDEVICE;
-    else if (derr) s = CAT_EINTERNAL;
-  }
   cat_stats stt{};
-  stt.products = M->products;
-  stt.product_limbs = M->product_limbs;
+  stt.products = e.M->products;
+  stt.product_limbs = e.M->product_limbs;
   stt.launches = launches;
   g.stats = stt;
-  mul_plan_free(M);
   return s;
+}
+
+cat_status bigint_mul_check(void* d_work, void* stream) {
+  if (!d_work) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(set_device());
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(g.pin, d_work, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint32_t e = 0;
+  memcpy(&e, g.pin, 4);
+  return e ? CAT_EINTERNAL : CAT_OK;
 }
 
 cat_status bigint_mul_batched(uint32_t batch, const uint32_t* d_a, const uint64_t* h_a_off, const uint32_t* d_b,

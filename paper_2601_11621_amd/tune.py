@@ -6,8 +6,9 @@ in a tree level) and keeps the fastest:
 
   * k <= 8:  schoolbook kernel vs the one-workgroup transform (this sets the
              schoolbook threshold on operand length);
-  * k <= 14: one-workgroup transform vs the four-step transform with rows of
-             2^8 .. 2^(k-1);
+  * k <= 14: one-workgroup transform with tiles of 2^12, 2^13 or 2^14 slots
+             (products per workgroup and workgroup size: 2^(t-k) and 2^t / 16
+             threads) vs the four-step transform with rows of 2^8 .. 2^(k-1);
   * k > 14:  four-step transform, rows of 2^10 .. 2^14, column passes of at
              most 2^6 / 2^8 / 2^10 points.
 
@@ -82,7 +83,15 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
         if half <= 128:
             cands.append(("school", {"school_max": 128}))
         if k <= 14:
-            cands.append(("lds", {"school_max": min(half - 1, 128) if half <= 128 else 128, "cls": 1}))
+            seen = set()
+            for lt in (12, 13, 14):
+                # the tile the library uses: at least the transform, at most 64 products
+                eff = max(k, min(lt, k + 6, 14))
+                if eff in seen:
+                    continue
+                seen.add(eff)
+                cands.append(("lds_t%d" % eff, {"school_max": min(half - 1, 128) if half <= 128 else 128, "cls": 1,
+                                                "log_row": lt}))
             for lr in range(8, k):
                 cands.append(("rows%d" % lr, {"school_max": min(half - 1, 128) if half <= 128 else 128, "cls": 2,
                                               "log_row": lr, "log_pass": 10}))
@@ -98,8 +107,8 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
             t["school_max"] = cfg["school_max"]
             if "cls" in cfg:
                 t["cls"][k] = cfg["cls"]
+                t["log_row"][k] = cfg["log_row"]
                 if cfg["cls"] == 2:
-                    t["log_row"][k] = cfg["log_row"]
                     t["log_pass"][k] = cfg["log_pass"]
             try:
                 cat.set_tuning(t)
@@ -116,8 +125,8 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
         else:
             if "cls" in cfg:
                 table["cls"][k] = cfg["cls"]
+                table["log_row"][k] = cfg["log_row"]
                 if cfg["cls"] == 2:
-                    table["log_row"][k] = cfg["log_row"]
                     table["log_pass"][k] = cfg["log_pass"]
         meas[k] = {n: round(v[0], 4) for n, v in res.items()}
         meas = dict(sorted(meas.items()))
@@ -129,7 +138,8 @@ def autotune(max_k: int = 24, reps: int = 5, total_log2: int = 22, verbose: bool
     table["school_max"] = max(school_max, 1)
     cat.set_tuning(table)
     props = torch.cuda.get_device_properties(0)
-    return {"arch": getattr(props, "gcnArchName", "gfx950"), "device": props.name, "reps": reps,
+    return {"arch": getattr(props, "gcnArchName", "gfx950"),
+            "device": "%s, %d compute units" % (props.name, props.multi_processor_count), "reps": reps,
             "workload": "per bucket 2^k: 2^max(0,%d-k) products of 2^(k-1) x 2^(k-1) limbs" % total_log2,
             "table": table, "ms": meas}
 

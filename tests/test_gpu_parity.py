@@ -337,3 +337,43 @@ def test_fused_levels_same_bits(cat, logn):
         assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
     finally:
         cat.set_fused_levels(12)
+
+
+def test_mul_batched_is_asynchronous(cat):
+    """bigint_mul_batched returns once the products are queued; the device
+    check comes from bigint_mul_check.  The same shape again (plan from the
+    library's cache) on a second stream, and a new shape, give the oracle's
+    products bit for bit."""
+    import ctypes
+
+    import torch
+
+    lib = cat.load()
+    rng = np.random.default_rng(41)
+    la = np.rint(2 ** rng.uniform(0, 13, 40)).astype(np.int64)
+    lb = np.rint(2 ** rng.uniform(0, 13, 40)).astype(np.int64)
+    a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
+    c_off = np.concatenate([[0], np.cumsum(la + lb)]).astype(np.uint64)
+    af, bf = _rand(rng, int(a_off[-1])), _rand(rng, int(b_off[-1]))
+    oc, _ = oracle.mul_batched(af, a_off, bf, b_off)
+    wb = ctypes.c_size_t()
+    cat._check(lib.bigint_mul_workspace(40, cat._p64(a_off), cat._p64(b_off), ctypes.byref(wb)), "workspace")
+    da, db = cat.from_numpy(af), cat.from_numpy(bf)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for s in streams + streams[:1]:
+        c = torch.full((int(c_off[-1]),), -1, dtype=torch.int32, device="cuda")
+        w = torch.empty(wb.value, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        vs = ctypes.c_void_p(s.cuda_stream)
+        st = lib.bigint_mul_batched(40, cat._ptr(da), cat._p64(a_off), cat._ptr(db), cat._p64(b_off), cat._ptr(c),
+                                    cat._p64(c_off), cat._ptr(w), w.numel(), vs)
+        assert st == cat.CAT_OK
+        outs.append((c, w, vs))
+    for c, w, vs in outs:
+        assert lib.bigint_mul_check(cat._ptr(w), vs) == cat.CAT_OK
+        assert np.array_equal(cat.to_numpy(c), oc)
+    # a different shape (one product more) is planned afresh
+    c2, c2_off = cat.mul_batched(da, a_off[:31], db, b_off[:31])
+    assert np.array_equal(cat.to_numpy(c2), oc[: int(c2_off[-1])])
