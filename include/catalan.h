@@ -257,6 +257,35 @@ cat_status catalan_continue(cat_ticket ticket, uint32_t* d_limbs, size_t cap);
 cat_status catalan_end(cat_ticket ticket, size_t* n_limbs);
 cat_status cat_ticket_release(cat_ticket ticket);
 
+/* Batches of C(n) requests (continuous batching in a request loop): the
+ * requests' Phase 1 runs request by request, then Phase 2 of all of them is
+ * planned together, so that each tree level of every request, and each step
+ * of their powers and outer products, is one launch per kernel stage (at most
+ * CAT_MAX_GROUPS exponent groups per plan; a batch with more runs as several
+ * plans one after another on the stream).  Results are bit-identical to
+ * catalan_exact for every n.
+ *  catalan_batch_sizes:    host only; d_work bytes for the k <= CAT_BATCH_MAX
+ *                          values ns[0..k);
+ *  catalan_batch_begin:    queues Phase 1 of every request on `stream` in
+ *                          d_work and returns a ticket (cat_ticket_query and
+ *                          cat_ticket_release work on it);
+ *  catalan_batch_continue: after Phase 1 finished: plans and queues Phase 2
+ *                          and the copy of up to caps[r] limbs of C(ns[r]) to
+ *                          d_limbs[r] (device, k pointers in a host array);
+ *  catalan_batch_end:      after Phase 2 was queued: waits for it and sets
+ *                          n_limbs[r] and, if req_status is not NULL, the
+ *                          status of each request (CAT_ERANGE if caps[r] was
+ *                          too small, CAT_EINTERNAL if a device check failed);
+ *                          returns the first request's error or CAT_OK, and
+ *                          releases the ticket on every path.
+ * d_work and the outputs must stay untouched until catalan_batch_end. */
+#define CAT_BATCH_MAX 32
+cat_status catalan_batch_sizes(uint32_t k, const uint64_t* ns, size_t* workspace_bytes);
+cat_status catalan_batch_begin(uint32_t k, const uint64_t* ns, void* d_work, size_t work_bytes, void* stream,
+                               cat_ticket* ticket);
+cat_status catalan_batch_continue(cat_ticket ticket, uint32_t* const* d_limbs, const size_t* caps);
+cat_status catalan_batch_end(cat_ticket ticket, size_t* n_limbs, cat_status* req_status);
+
 /* Reusable plans for repeated batches of the same shape (the batched form
  * of a tree level).  cat_mul_plan_create buckets the products by transform
  * length (schoolbook for la, lb <= 128; LDS-resident NTT up to 2^12

@@ -35,6 +35,7 @@ EXPORTS = [
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
     "decimal_sizes", "bigint_to_decimal", "catalan_exact_noalloc", "catalan_noalloc_max_bytes",
     "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
+    "catalan_batch_sizes", "catalan_batch_begin", "catalan_batch_continue", "catalan_batch_end",
 ]
 
 
@@ -130,6 +131,10 @@ def load(path: str = LIB_PATH):
         "bigint_decimal_digits_workspace": ([ctypes.c_size_t, szp], st),
         "bigint_decimal_digits": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
         "bigint_mul_check": ([vp, vp], st),
+        "catalan_batch_sizes": ([ctypes.c_uint32, u64p, szp], st),
+        "catalan_batch_begin": ([ctypes.c_uint32, u64p, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+        "catalan_batch_continue": ([vp, ctypes.POINTER(vp), szp], st),
+        "catalan_batch_end": ([vp, szp, ctypes.POINTER(ctypes.c_int32)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -315,6 +320,42 @@ def noalloc_max_bytes() -> int:
     b = ctypes.c_size_t()
     _check(load().catalan_noalloc_max_bytes(ctypes.byref(b)), "catalan_noalloc_max_bytes")
     return b.value
+
+
+BATCH_MAX = 32
+
+
+def batch_sizes(ns) -> int:
+    """Workspace bytes of one batch of C(n) requests (host only)."""
+    a = _u64(ns)
+    wb = ctypes.c_size_t()
+    _check(load().catalan_batch_sizes(len(a), _p64(a), ctypes.byref(wb)), "catalan_batch_sizes")
+    return wb.value
+
+
+def exact_batch(ns, stream=None):
+    """C(n) for every n of ns (at most BATCH_MAX) as one batch: Phase 1 per
+    request, Phase 2 of all of them planned and launched together.  Returns
+    a list of limb tensors (bit-identical to exact(n))."""
+    torch = _torch()
+    lib = load()
+    a = _u64(ns)
+    k = len(a)
+    w = workspace(batch_sizes(a), key="batch")
+    outs = [torch.empty(max(sizes(int(n))[1], 1), dtype=torch.int32, device="cuda") for n in a]
+    t = ctypes.c_void_p()
+    _check(lib.catalan_batch_begin(k, _p64(a), _ptr(w), w.numel(), _stream(stream), ctypes.byref(t)),
+           "catalan_batch_begin")
+    ptrs = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+    caps = (ctypes.c_size_t * k)(*[o.numel() for o in outs])
+    st = lib.catalan_batch_continue(t, ptrs, caps)
+    if st != CAT_OK:
+        lib.cat_ticket_release(t)
+        _check(st, "catalan_batch_continue")
+    nl = (ctypes.c_size_t * k)()
+    rs = (ctypes.c_int32 * k)()
+    _check(lib.catalan_batch_end(t, nl, rs), "catalan_batch_end")
+    return [o[: nl[i]] for i, o in enumerate(outs)]
 
 
 def _terms(xs):

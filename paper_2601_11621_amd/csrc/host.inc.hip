@@ -532,6 +532,14 @@ struct Plan {
   std::vector<Stage> post;      // powers, outer tree, final product (shared by both modes)
   uint64_t result_pos = 0, result_cap = 0;   // uint32 offset from workspace base
   bool result_is_one = false;
+  // several requests in one plan (batched serving): group g belongs to
+  // request req[g]; the powers, the outer product and the final product are
+  // formed per request, with results rpos / rcap / rone (request 0 also in
+  // the fields above)
+  uint32_t nreq = 1;
+  uint32_t req[CAT_MAX_GROUPS] = {};
+  uint64_t rpos[CAT_MAX_GROUPS] = {}, rcap[CAT_MAX_GROUPS] = {};
+  bool rone[CAT_MAX_GROUPS] = {};
   uint64_t post_end = 0;        // end of the post-tree arena used
   uint64_t root[CAT_MAX_GROUPS] = {};   // Q_e of group g (uint32 offset), the same in both forms
   uint64_t gbits[CAT_MAX_GROUPS] = {};  // bit-length bound of Q_e (group table)
@@ -826,29 +834,32 @@ void plan_post(const Layout& Ly, Plan& P) {
     bump += limbs;
     return it;
   };
-  std::vector<Item> pe;     // P_e for e >= 2, exponent ascending
-  Item q1{0, 0, 0};
-  bool has_q1 = false;
+  const uint32_t nr = std::max<uint32_t>(P.nreq, 1);
+  std::vector<std::vector<Item>> pe(nr);   // P_e for e >= 2 of each request, exponent ascending
+  std::vector<Item> q1(nr, Item{0, 0, 0});
+  std::vector<bool> has_q1(nr, false);
   // powers: all chains advance one step per stage
   struct Chain {
     Item q, r;
     uint32_t e;
     int bit;
     bool sq_done;
+    uint32_t req;
   };
   std::vector<Chain> ch;
   for (uint32_t gi = 0; gi < P.ng; gi++) {
     // Q_e occupies K limbs of its node; its value fits ceil(gbits / 32) of them
     const uint64_t K = P.off[gi + 1] - P.off[gi];
     Item q{P.root[gi], cap_of(K, P.gbits[gi]), std::min<uint64_t>(P.gbits[gi], 32 * K)};
+    const uint32_t r = P.nreq > 1 ? P.req[gi] : 0;
     if (P.exps[gi] == 1) {
-      q1 = q;
-      has_q1 = true;
+      q1[r] = q;
+      has_q1[r] = true;
       continue;
     }
     int top = 31;
     while (!((P.exps[gi] >> top) & 1)) top--;
-    ch.push_back(Chain{q, q, P.exps[gi], top - 1, false});
+    ch.push_back(Chain{q, q, P.exps[gi], top - 1, false, r});
   }
   for (;;) {
     std::vector<std::pair<Item, Item>> pairs;
@@ -880,37 +891,61 @@ void plan_post(const Layout& Ly, Plan& P) {
       }
     }
   }
-  for (auto& c : ch) pe.push_back(c.r);
-  // outer product of the P_e, e >= 2
-  while (pe.size() > 1) {
+  for (auto& c : ch) pe[c.req].push_back(c.r);
+  // outer product of the P_e, e >= 2, of each request; one round of pairs
+  // of every request per step
+  for (;;) {
     std::vector<std::pair<Item, Item>> pairs;
-    std::vector<Item> outs, next;
-    for (size_t k = 0; k + 1 < pe.size(); k += 2) {
-      pairs.push_back({pe[k], pe[k + 1]});
-      outs.push_back(alloc(pe[k].cap + pe[k + 1].cap, pe[k].bits + pe[k + 1].bits));
-      next.push_back(outs.back());
+    std::vector<Item> outs;
+    std::vector<std::vector<Item>> next(nr);
+    for (uint32_t r = 0; r < nr; r++) {
+      if (pe[r].size() <= 1) {
+        next[r] = pe[r];
+        continue;
+      }
+      for (size_t k = 0; k + 1 < pe[r].size(); k += 2) {
+        pairs.push_back({pe[r][k], pe[r][k + 1]});
+        outs.push_back(alloc(pe[r][k].cap + pe[r][k + 1].cap, pe[r][k].bits + pe[r][k + 1].bits));
+        next[r].push_back(outs.back());
+      }
+      if (pe[r].size() & 1) next[r].push_back(pe[r].back());
     }
-    if (pe.size() & 1) next.push_back(pe.back());
+    if (pairs.empty()) break;
     add_products(P, pairs, outs);
     pe = next;
   }
   P.post_final = P.post.size();
-  if (!has_q1 || pe.empty()) P.fork_count = -1;   // nothing runs beside the Q_1 tree
-  if (has_q1 && !pe.empty()) {
-    std::vector<std::pair<Item, Item>> pairs{{q1, pe[0]}};
-    std::vector<Item> outs{alloc(q1.cap + pe[0].cap, q1.bits + pe[0].bits)};
-    add_products(P, pairs, outs);
-    P.result_pos = outs[0].pos;
-    P.result_cap = outs[0].cap;
-  } else if (has_q1) {
-    P.result_pos = q1.pos;
-    P.result_cap = q1.cap;
-  } else if (!pe.empty()) {
-    P.result_pos = pe[0].pos;
-    P.result_cap = pe[0].cap;
-  } else {
-    P.result_is_one = true;
+  bool any_final = false;
+  for (uint32_t r = 0; r < nr; r++) any_final = any_final || (has_q1[r] && !pe[r].empty());
+  // nothing runs beside the Q_1 tree (one request only: batches run in line)
+  if (!any_final || nr > 1) P.fork_count = -1;
+  std::vector<std::pair<Item, Item>> pairs;
+  std::vector<Item> outs;
+  std::vector<uint32_t> who;
+  for (uint32_t r = 0; r < nr; r++) {
+    P.rone[r] = false;
+    if (has_q1[r] && !pe[r].empty()) {
+      pairs.push_back({q1[r], pe[r][0]});
+      outs.push_back(alloc(q1[r].cap + pe[r][0].cap, q1[r].bits + pe[r][0].bits));
+      who.push_back(r);
+    } else if (has_q1[r]) {
+      P.rpos[r] = q1[r].pos;
+      P.rcap[r] = q1[r].cap;
+    } else if (!pe[r].empty()) {
+      P.rpos[r] = pe[r][0].pos;
+      P.rcap[r] = pe[r][0].cap;
+    } else {
+      P.rone[r] = true;
+    }
   }
+  if (!pairs.empty()) add_products(P, pairs, outs);
+  for (size_t t = 0; t < who.size(); t++) {
+    P.rpos[who[t]] = outs[t].pos;
+    P.rcap[who[t]] = outs[t].cap;
+  }
+  P.result_pos = P.rpos[0];
+  P.result_cap = P.rcap[0];
+  P.result_is_one = P.rone[0];
   P.post_end = bump;
 }
 
@@ -991,10 +1026,14 @@ void free_plan(Plan* P) {
   delete P;
 }
 
-cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out, bool device_tables = true) {
+cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out, bool device_tables = true,
+                     const uint32_t* req = nullptr, uint32_t nreq = 1) {
   Plan* P = new Plan();
   P->n = Ly.n;
   P->ng = gt.ngroups;
+  P->nreq = req ? nreq : 1;
+  if (req)
+    for (uint32_t gi = 0; gi < gt.ngroups; gi++) P->req[gi] = req[gi];
   for (uint32_t gi = 0; gi < gt.ngroups; gi++) {
     P->exps[gi] = gt.exps[gi];
     P->gbits[gi] = gt.gbits[gi];
@@ -1722,6 +1761,7 @@ cat_status mul_plan_exec(MulPlanImpl* M, const uint32_t* d_a, const uint32_t* d_
 // memory (group table, top index, error word) and an event; slices and events
 // are pooled so the serving loop never allocates.
 // ----------------------------------------------------------------------------
+struct BatchState;
 struct Ticket {
   uint64_t n = 0;
   Layout Ly;
@@ -1732,6 +1772,7 @@ struct Ticket {
   char* pin = nullptr;
   bool one = false;           // C(n) = 1
   uint64_t cap = 0;
+  BatchState* batch = nullptr;   // a batch of requests (catalan_batch_*)
 };
 
 struct TicketPool {
@@ -1768,11 +1809,117 @@ cat_status ticket_alloc(Ticket** out) {
   return CAT_OK;
 }
 
+void batch_free(BatchState* b);
 void ticket_free(Ticket* t) {
   tp.free_slices.push_back(t->pin);
   tp.free_events.push_back(t->ev);
+  if (t->batch) batch_free(t->batch);
   delete t;
 }
+
+// ----------------------------------------------------------------------------
+// Batches of C(n) requests (continuous batching in a request loop): every
+// request's Phase 1 runs in a small region of its own, its primes land in a
+// staging array, and the primes of all requests are compacted into one array
+// so that their groups sit side by side.  Phase 2 is planned once for all of
+// them (at most CAT_MAX_GROUPS groups per plan; a larger batch is cut into
+// chunks run one after another): each tree level of every request is one
+// launch per kernel stage, and the powers, outer products and final products
+// of all requests share the launches of their steps.
+// ----------------------------------------------------------------------------
+#define CAT_BATCH_MAX 32
+#define BATCH_PIN (64 << 10)
+
+// Phase 1 of one request of a batch: the sieve's scratch and a control block
+Layout layout_phase1(uint64_t n) {
+  Layout L;
+  L.n = n;
+  L.s = isqrt64(2 * n);
+  L.i0 = (L.s + 1) / 2;
+  L.i_end = n;
+  L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + SIEVE_SEG - 1) / SIEVE_SEG : 0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  L.seeds = take(SEED_MAX * 4) / 4;
+  L.seed_e = take(SEED_MAX * 4) / 4;
+  L.seg_cnt = take((L.nseg + 1) * 4) / 4;
+  L.seg_off = take((L.nseg + 1) * 4) / 4;
+  L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
+  L.gtab = take(CTL_READ);
+  L.top = L.gtab + CTL_TOP;
+  L.err = L.gtab + CTL_ERR;
+  L.ctl_words = CTL_READ / 4;
+  L.total = off;
+  return L;
+}
+
+struct BatchLayout {
+  uint32_t k = 0;
+  std::vector<uint64_t> n;
+  std::vector<Layout> p1;
+  std::vector<size_t> p1_off;      // bytes
+  std::vector<uint64_t> kmax;      // prime capacity of each request
+  std::vector<uint64_t> stage;     // request's primes in the staging array (uint32 units)
+  Layout c;                        // Phase 2 of all requests
+  size_t c_off = 0, tops_off = 0, total = 0;
+};
+
+BatchLayout make_batch_layout(uint32_t k, const uint64_t* ns) {
+  BatchLayout B;
+  B.k = k;
+  size_t off = 0;
+  uint64_t ksum = 0, post = 0;
+  for (uint32_t r = 0; r < k; r++) {
+    const Layout full = make_layout(ns[r]);
+    B.n.push_back(ns[r]);
+    B.p1.push_back(layout_phase1(ns[r]));
+    B.p1_off.push_back(off);
+    off = align_up(off + B.p1.back().total, 256);
+    B.kmax.push_back(full.Kmax);
+    B.stage.push_back(ksum);
+    ksum += full.Kmax;
+    post += full.post_cap;
+  }
+  Layout L;
+  L.n = 0;
+  L.Kmax = std::max<uint64_t>(ksum, 16);
+  L.post_cap = post + 4096;
+  L.res2_len = 4096;
+  B.c = layout_finish(L);
+  B.c_off = off;
+  off = align_up(off + B.c.total, 256);
+  B.tops_off = off;
+  off = align_up(off + 8 * (size_t)k, 256);
+  B.total = off;
+  return B;
+}
+
+struct BatchState {
+  BatchLayout B;
+  char* pin = nullptr;                     // group tables | tops | error word (pinned)
+  std::vector<cat_status> status;          // per request
+  std::vector<size_t> cap;
+};
+
+struct BigPinPool {
+  std::vector<char*> free_bufs;
+};
+BigPinPool bpp;
+
+void batch_free(BatchState* b) {
+  if (b->pin) bpp.free_bufs.push_back(b->pin);
+  delete b;
+}
+
+// byte offsets inside a batch's pinned buffer
+inline size_t bpin_gt(uint32_t r) { return (size_t)r * sizeof(GroupTable); }
+inline size_t bpin_tops() { return (size_t)CAT_BATCH_MAX * sizeof(GroupTable); }
+inline size_t bpin_err() { return bpin_tops() + 8 * CAT_BATCH_MAX; }
+static_assert(CAT_BATCH_MAX * sizeof(GroupTable) + 8 * CAT_BATCH_MAX + 16 <= BATCH_PIN, "batch pinned buffer");
 
 }  // namespace
 
@@ -2577,6 +2724,228 @@ cat_status cat_ticket_release(cat_ticket ticket) {
   (void)hipStreamSynchronize(t->st);
   ticket_free(t);
   return CAT_OK;
+}
+
+cat_status catalan_batch_sizes(uint32_t k, const uint64_t* ns, size_t* workspace_bytes) {
+  if (!workspace_bytes || !ns || k == 0 || k > CAT_BATCH_MAX) return CAT_EINVAL;
+  for (uint32_t r = 0; r < k; r++)
+    if (ns[r] > CAT_N_MAX) return CAT_EINVAL;
+  *workspace_bytes = make_batch_layout(k, ns).total;
+  return CAT_OK;
+}
+
+cat_status catalan_batch_begin(uint32_t k, const uint64_t* ns, void* d_work, size_t work_bytes, void* stream,
+                               cat_ticket* ticket) {
+  if (!ns || !d_work || !ticket || k == 0 || k > CAT_BATCH_MAX) return CAT_EINVAL;
+  for (uint32_t r = 0; r < k; r++)
+    if (ns[r] > CAT_N_MAX) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  STCHK(init_locked(-1));
+  STCHK(set_device());
+  BatchLayout B = make_batch_layout(k, ns);
+  if (work_bytes < B.total) return CAT_ENOMEM;
+  char* pin = nullptr;
+  if (!bpp.free_bufs.empty()) {
+    pin = bpp.free_bufs.back();
+    bpp.free_bufs.pop_back();
+  } else {
+    HIPCHK(hipHostMalloc((void**)&pin, BATCH_PIN, hipHostMallocDefault));
+  }
+  Ticket* t = nullptr;
+  const cat_status ta = ticket_alloc(&t);
+  if (ta != CAT_OK) {
+    bpp.free_bufs.push_back(pin);
+    return ta;
+  }
+  BatchState* b = new BatchState();
+  b->B = B;
+  b->pin = pin;
+  b->status.assign(k, CAT_OK);
+  t->batch = b;
+  t->wb = (char*)d_work;
+  t->st = (hipStream_t)stream;
+  char* wb = t->wb;
+  uint32_t* stage = (uint32_t*)(wb + B.c_off) + B.c.arenaA;
+  uint64_t launches = 0;
+  cat_status s = CAT_OK;
+  for (uint32_t r = 0; r < k && s == CAT_OK; r++) {
+    s = run_phase1(B.p1[r], wb + B.p1_off[r], stage + B.stage[r], B.kmax[r], t->st, &launches);
+    if (s == CAT_OK) {
+      const hipError_t e = hipMemcpyAsync(pin + bpin_gt(r), wb + B.p1_off[r] + B.p1[r].gtab, sizeof(GroupTable),
+                                          hipMemcpyDeviceToHost, t->st);
+      if (e != hipSuccess) {
+        g.last_err = (int)e;
+        s = CAT_EDEVICE;
+      }
+    }
+  }
+  if (s == CAT_OK) {
+    const hipError_t e = hipEventRecord(t->ev, t->st);
+    if (e != hipSuccess) {
+      g.last_err = (int)e;
+      s = CAT_EDEVICE;
+    }
+  }
+  if (s != CAT_OK) {
+    (void)hipStreamSynchronize(t->st);
+    ticket_free(t);
+    return s;
+  }
+  t->state = 1;
+  *ticket = (cat_ticket)t;
+  return CAT_OK;
+}
+
+cat_status catalan_batch_continue(cat_ticket ticket, uint32_t* const* d_limbs, const size_t* caps) {
+  if (!ticket || !d_limbs || !caps) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  Ticket* t = (Ticket*)ticket;
+  BatchState* b = t->batch;
+  if (!b || t->state != 1) return CAT_EINVAL;
+  const BatchLayout& B = b->B;
+  const uint32_t k = B.k;
+  for (uint32_t r = 0; r < k; r++)
+    if (!d_limbs[r]) return CAT_EINVAL;
+  HIPCHK(hipEventSynchronize(t->ev));
+  std::vector<GroupTable> gts(k);
+  for (uint32_t r = 0; r < k; r++) {
+    memcpy(&gts[r], b->pin + bpin_gt(r), sizeof(GroupTable));
+    if (gts[r].err || gts[r].ngroups > CAT_MAX_GROUPS) b->status[r] = CAT_EINTERNAL;
+  }
+  hipStream_t st = t->st;
+  char* wb = t->wb;
+  char* cw = wb + B.c_off;
+  uint32_t* W = (uint32_t*)cw;
+  // the primes of all requests side by side (request order)
+  std::vector<uint64_t> q(k, 0);
+  MoveList ml{};
+  uint64_t qn = 0, lmax = 0;
+  for (uint32_t r = 0; r < k; r++) {
+    if (b->status[r] != CAT_OK) continue;
+    const uint64_t np = gts[r].off[gts[r].ngroups];
+    q[r] = qn;
+    if (np) {
+      ml.src[ml.n] = B.stage[r];
+      ml.dst[ml.n] = qn;
+      ml.len[ml.n] = np;
+      ml.n++;
+      lmax = std::max(lmax, np);
+    }
+    qn += np;
+  }
+  if (ml.n) {
+    hipLaunchKernelGGL(k_move_ranges, dim3((uint32_t)std::min<uint64_t>((lmax + 255) / 256, 1024), ml.n), dim3(256),
+                       0, st, ml, (const uint32_t*)(W + B.c.arenaA), W + B.c.primes);
+    LAUNCHCHK();
+  }
+  // control block (look-back flags, error word) and the top indices cleared
+  unsigned long long* tops = (unsigned long long*)(wb + B.tops_off);
+  hipLaunchKernelGGL(k_fill, dim3((uint32_t)std::min<uint64_t>((B.c.ctl_words + 255) / 256, 1024)), dim3(256), 0, st,
+                     (uint32_t*)(cw + B.c.gtab), (uint64_t)B.c.ctl_words, 0u);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)tops, (uint64_t)(2 * k), 0u);
+  LAUNCHCHK();
+  // chunks of whole requests with at most CAT_MAX_GROUPS groups each
+  uint32_t epoch = 0;
+  uint32_t r0 = 0;
+  while (r0 < k) {
+    uint32_t r1 = r0, ng = 0;
+    while (r1 < k && (b->status[r1] != CAT_OK || ng + gts[r1].ngroups <= CAT_MAX_GROUPS)) {
+      if (b->status[r1] == CAT_OK) ng += gts[r1].ngroups;
+      r1++;
+    }
+    GroupTable gtc{};
+    uint32_t req[CAT_MAX_GROUPS] = {};
+    std::vector<uint32_t> members;
+    for (uint32_t r = r0; r < r1; r++) {
+      if (b->status[r] != CAT_OK) continue;
+      const uint32_t i = (uint32_t)members.size();
+      members.push_back(r);
+      for (uint32_t gg = 0; gg < gts[r].ngroups; gg++) {
+        gtc.exps[gtc.ngroups] = gts[r].exps[gg];
+        gtc.off[gtc.ngroups] = q[r] + gts[r].off[gg];
+        gtc.gbits[gtc.ngroups] = gts[r].gbits[gg];
+        req[gtc.ngroups] = i;
+        gtc.ngroups++;
+      }
+      gtc.off[gtc.ngroups] = q[r] + gts[r].off[gts[r].ngroups];
+    }
+    Plan* P = nullptr;
+    if (gtc.ngroups) {
+      // no device tables: the plan is freed as soon as its launches are queued
+      STCHK(make_plan(B.c, gtc, &P, false, req, (uint32_t)members.size()));
+      Exec X = make_exec(B.c, cw, st);
+      X.crt_epoch = epoch;
+      const cat_status rs = run_phase2(X, *P, false);
+      epoch = X.crt_epoch;
+      if (rs != CAT_OK) {
+        free_plan(P);
+        return rs;
+      }
+    }
+    for (uint32_t i = 0; i < (uint32_t)members.size(); i++) {
+      const uint32_t r = members[i];
+      if (!P || P->rone[i]) {
+        // C(n) = 1
+        if (caps[r] >= 1) hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, d_limbs[r], (uint64_t)1, 1u);
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)(tops + r), (uint64_t)1, 1u);
+      } else {
+        hipLaunchKernelGGL(k_top_nonzero, dim3(top_scan_blocks(P->rcap[i])), dim3(256), 0, st, W + P->rpos[i],
+                           P->rcap[i], tops + r, d_limbs[r], std::min<uint64_t>(P->rcap[i], caps[r]));
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        if (P) free_plan(P);
+        g.last_err = (int)e;
+        return CAT_EDEVICE;
+      }
+    }
+    if (P) free_plan(P);
+    r0 = r1;
+  }
+  HIPCHK(hipMemcpyAsync(b->pin + bpin_tops(), tops, 8 * (size_t)k, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(b->pin + bpin_err(), cw + B.c.err, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(t->ev, st));
+  b->cap.assign(caps, caps + k);
+  t->state = 2;
+  return CAT_OK;
+}
+
+cat_status catalan_batch_end(cat_ticket ticket, size_t* n_limbs, cat_status* req_status) {
+  if (!ticket) return CAT_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  Ticket* t = (Ticket*)ticket;
+  BatchState* b = t->batch;
+  // the ticket is released on every path below
+  if (!b || !n_limbs || t->state != 2) {
+    (void)hipStreamSynchronize(t->st);
+    ticket_free(t);
+    return CAT_EINVAL;
+  }
+  hipError_t e = hipEventSynchronize(t->ev);
+  if (e != hipSuccess) {
+    g.last_err = (int)e;
+    (void)hipStreamSynchronize(t->st);
+    ticket_free(t);
+    return CAT_EDEVICE;
+  }
+  uint32_t derr = 0;
+  memcpy(&derr, b->pin + bpin_err(), 4);
+  cat_status first = CAT_OK;
+  for (uint32_t r = 0; r < b->B.k; r++) {
+    uint64_t L = 0;
+    memcpy(&L, b->pin + bpin_tops() + 8 * (size_t)r, 8);
+    cat_status s = b->status[r];
+    n_limbs[r] = s == CAT_OK ? (size_t)L : 0;
+    if (s == CAT_OK) {
+      if (derr || L == 0) s = CAT_EINTERNAL;
+      else if (L > b->cap[r]) s = CAT_ERANGE;
+    }
+    if (req_status) req_status[r] = s;
+    if (first == CAT_OK) first = s;
+  }
+  ticket_free(t);
+  return first;
 }
 
 cat_status catalan_exact_noalloc(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n_limbs, void* stream) {

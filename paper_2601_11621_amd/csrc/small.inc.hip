@@ -348,6 +348,20 @@ __global__ void k_copy_ranges(CopyList cl, const uint32_t* __restrict__ in, uint
     out[cl.off[r] + k] = in[cl.off[r] + k];
 }
 
+// Copies of up to CAT_MAX_GROUPS ranges from one array to another, each to
+// an offset of its own (the primes of the requests of a batch, compacted).
+struct MoveList {
+  uint32_t n;
+  uint64_t src[CAT_MAX_GROUPS], dst[CAT_MAX_GROUPS], len[CAT_MAX_GROUPS];
+};
+__global__ void k_move_ranges(MoveList ml, const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
+  const uint32_t r = blockIdx.y;
+  if (r >= ml.n) return;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ml.len[r];
+       k += (uint64_t)gridDim.x * blockDim.x)
+    out[ml.dst[r] + k] = in[ml.src[r] + k];
+}
+
 __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
     p[k] = v;

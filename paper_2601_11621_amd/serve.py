@@ -14,8 +14,13 @@ cancelled at any point: a queued one leaves the queue, a running one has its
 device work drained and its slot and memory freed.
 
 `Server` is independent of the device: it drives an executor with
-`footprint / begin / ready / advance / finish`.  `GpuExecutor` binds that to
-the C ABI; `FakeExecutor` (used by the CPU tests) simulates durations.
+`footprint / begin / ready / advance / finish` (and `flush` after each
+admission step, for executors that batch).  `GpuExecutor` binds that to the
+C ABI with one ticket per request; `BatchExecutor` runs the requests admitted
+in one step as one library batch (continuous batching: each tree level of all
+of them, and each step of their powers and outer products, is one launch per
+kernel stage, while the requests of earlier steps keep running on other
+streams); `FakeExecutor` (used by the CPU tests) simulates durations.
 """
 from __future__ import annotations
 
@@ -109,6 +114,14 @@ class Server:
                 self.active.append(r)
                 self.peak_active = max(self.peak_active, len(self.active))
             moved = True
+        # a batching executor launches what this step admitted as one batch
+        flush = getattr(self.ex, "flush", None)
+        if moved and flush is not None:
+            for r, err in flush() or []:
+                if r in self.active:
+                    self.active.remove(r)
+                    self.ex.abort(r)
+                    self._retire(r, now, err)
         return moved
 
     def _finished(self, r: Request):
@@ -317,6 +330,168 @@ class GpuExecutor:
             # waits until everything queued on the ticket's stream has finished
             self.lib.cat_ticket_release(t)
         self._done_with(r)
+
+    def wait_until(self, t: float):
+        while time.perf_counter() < t:
+            pass
+
+
+class BatchExecutor:
+    """Executor on the library's batch API (catalan_batch_*): the requests the
+    server admits in one step (at most `max_batch`) share one batch ticket,
+    one workspace and one set of Phase-2 launches; successive batches run on
+    up to `max_streams` streams, so a new batch's Phase 1 overlaps the running
+    ones.  A request's footprint counts twice its own workspace (the batch's
+    combined scratch rounds up over the requests) plus its output."""
+
+    def __init__(self, max_slots: int, device: int = 0, max_streams: int = 4, max_batch: int = 16):
+        import torch
+
+        from . import BATCH_MAX, _check, _ptr, init, load, sizes
+
+        self._torch = torch
+        self._check, self._ptr, self._sizes = _check, _ptr, sizes
+        init(device)
+        self.lib = load()
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, max_streams))]
+        self._next_stream = 0
+        self.max_batch = max(1, min(int(max_batch), BATCH_MAX))
+        self.forming: List[Request] = []
+        self._pool = collections.defaultdict(list)
+        self.pooled = 0
+        self.active_bytes = 0
+        self.budget: Optional[int] = None
+        self.batches = 0
+        self.batched_requests = 0
+
+    attach = GpuExecutor.attach
+    _cls = staticmethod(GpuExecutor._cls)
+    _trim = GpuExecutor._trim
+    _release = GpuExecutor._release
+
+    def footprint(self, n: int) -> int:
+        _, max_limbs, wbytes = self._sizes(n)
+        return 2 * self._cls(wbytes) + 4 * max_limbs
+
+    def begin(self, r: Request):
+        _, max_limbs, _ = self._sizes(r.n)
+        r.handle = None
+        out = self._torch.empty(max_limbs, dtype=self._torch.int32, device="cuda")
+        r.handle = {"batch": None, "out": out}
+        self.forming.append(r)
+
+    def flush(self):
+        """Launch the forming requests as batches of at most max_batch;
+        returns the (request, error) pairs of batches that failed to start."""
+        import ctypes
+
+        failed = []
+        while self.forming:
+            reqs, self.forming = self.forming[: self.max_batch], self.forming[self.max_batch:]
+            torch = self._torch
+            import numpy as np
+
+            ns = np.ascontiguousarray(np.array([r.n for r in reqs], dtype=np.uint64))
+            p64 = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+            wb = ctypes.c_size_t()
+            st = self.lib.catalan_batch_sizes(len(reqs), p64, ctypes.byref(wb))
+            if st != 0:
+                failed += [(r, "catalan_batch_sizes failed (%d)" % st) for r in reqs]
+                continue
+            cls = self._cls(wb.value)
+            free = self._pool[cls]
+            if free:
+                w = free.pop()
+                self.pooled -= cls
+            else:
+                self._trim(cls)
+                w = torch.empty(cls, dtype=torch.uint8, device="cuda")
+            self.active_bytes += cls
+            stream = self.streams[self._next_stream % len(self.streams)]
+            self._next_stream += 1
+            t = ctypes.c_void_p()
+            st = self.lib.catalan_batch_begin(len(reqs), p64, self._ptr(w), w.numel(),
+                                              ctypes.c_void_p(stream.cuda_stream), ctypes.byref(t))
+            if st != 0:
+                self.active_bytes -= cls
+                self._release(cls, w)
+                failed += [(r, "catalan_batch_begin failed (%d)" % st) for r in reqs]
+                continue
+            b = {"ticket": t, "reqs": reqs, "w": w, "cls": cls, "state": 1, "left": len(reqs),
+                 "n_limbs": None, "status": None}
+            for r in reqs:
+                r.handle["batch"] = b
+            self.batches += 1
+            self.batched_requests += len(reqs)
+        return failed
+
+    def ready(self, r: Request) -> bool:
+        b = r.handle["batch"]
+        if b["state"] == 3:
+            return True
+        s = self.lib.cat_ticket_query(b["ticket"])
+        if s == -6:
+            return False
+        self._check(s, "cat_ticket_query")
+        return True
+
+    def advance(self, r: Request):
+        import ctypes
+
+        b = r.handle["batch"]
+        if b["state"] != 1:
+            return
+        reqs = b["reqs"]
+        k = len(reqs)
+        outs = [q.handle["out"] for q in reqs]
+        ptrs = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+        caps = (ctypes.c_size_t * k)(*[o.numel() for o in outs])
+        b["keep"] = (ptrs, caps)
+        self._check(self.lib.catalan_batch_continue(b["ticket"], ptrs, caps), "catalan_batch_continue")
+        b["state"] = 2
+
+    def _end(self, b):
+        import ctypes
+
+        k = len(b["reqs"])
+        nl = (ctypes.c_size_t * k)()
+        rs = (ctypes.c_int32 * k)()
+        self.lib.catalan_batch_end(b["ticket"], nl, rs)     # releases the ticket; statuses per request
+        b["n_limbs"], b["status"] = list(nl), list(rs)
+        b["state"] = 3
+        self.active_bytes -= b["cls"]
+        self._release(b["cls"], b["w"])
+        b["w"] = None
+
+    def finish(self, r: Request) -> int:
+        b = r.handle["batch"]
+        if b["state"] == 2:
+            self._end(b)
+        b["left"] -= 1
+        i = b["reqs"].index(r)
+        out = r.handle["out"]
+        r.handle = None
+        self._check(b["status"][i], "catalan_batch_end")
+        r.result = out[: b["n_limbs"][i]]
+        return b["n_limbs"][i]
+
+    def abort(self, r: Request):
+        if r.handle is None:
+            return
+        b = r.handle["batch"]
+        r.handle = None
+        if b is None:
+            if r in self.forming:
+                self.forming.remove(r)
+            return
+        b["left"] -= 1
+        if b["left"] == 0 and b["state"] in (1, 2):
+            # nobody waits for this batch any more: drain it and free its workspace
+            self.lib.cat_ticket_release(b["ticket"])
+            b["state"] = 3
+            self.active_bytes -= b["cls"]
+            self._release(b["cls"], b["w"])
+            b["w"] = None
 
     def wait_until(self, t: float):
         while time.perf_counter() < t:

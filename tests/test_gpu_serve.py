@@ -192,3 +192,78 @@ def test_device_memory_stays_within_budget(cat):
     assert all(r.state == DONE for r in reqs) and not bad
     assert torch.cuda.max_memory_allocated() - base <= budget
     assert ex.active_bytes == 0 and ex.pooled <= budget
+
+
+def test_exact_batch_equals_solo_and_oracle(cat):
+    """One library batch of mixed n (Phase 2 planned and launched for all of
+    them together): every result equals catalan_exact alone and the oracle,
+    including C(0), C(1), and a batch with more exponent groups than one plan
+    holds (run as several plans)."""
+    ns = [0, 1, 13, 1000, 5000, 20000, 10**4, 2 * 10**4]
+    got = cat.exact_batch(ns)
+    for n, t in zip(ns, got):
+        assert _oracle_match(cat.to_numpy(t), n), n
+    big, _ = batch_inputs.serving_requests(seed=11621, count=60)
+    big = [int(x) for x in big[:24]]                 # about 4-7 groups each: several plans
+    got = cat.exact_batch(big)
+    for n, t in zip(big, got):
+        assert _oracle_match(cat.to_numpy(t), n), n
+        assert np.array_equal(cat.to_numpy(t), cat.to_numpy(cat.exact(n, mode="batched"))), n
+
+
+def test_batch_executor_mix_equals_solo(cat):
+    """Serving with cross-request batching: the requests admitted in one step
+    share launches; every result equals the oracle's, and the stream really
+    ran as several multi-request batches."""
+    import time
+
+    from paper_2601_11621_amd.serve import DONE, BatchExecutor, Server
+
+    ns, gaps = batch_inputs.serving_requests(seed=11621, count=60)
+    ex = BatchExecutor(max_slots=16)
+    srv = Server(ex, budget_bytes=8 << 30, max_slots=16)
+    reqs = [srv.submit(int(n), arrival=0.0) for n in ns]
+    srv.run()
+    for r in reqs:
+        assert r.state == DONE, (r.n, r.error)
+        assert _oracle_match(cat.to_numpy(r.result), r.n), r.n
+    assert ex.batches < len(reqs) and ex.batched_requests == len(reqs)
+    # Poisson arrivals: later requests join later batches
+    ns, gaps = batch_inputs.serving_requests(seed=7, count=80, lo_exp=3.0, hi_exp=6.0)
+    srv = Server(ex, budget_bytes=2 << 30, max_slots=12)
+    t0 = time.perf_counter() + 0.01
+    arr = t0 + np.cumsum(gaps) * 0.0005
+    reqs = [srv.submit(int(n), arrival=float(a)) for n, a in zip(ns, arr)]
+    srv.run()
+    for r in reqs:
+        assert r.state == DONE, (r.n, r.error)
+        assert _oracle_match(cat.to_numpy(r.result), r.n), r.n
+
+
+def test_batch_capacity_error_is_per_request(cat):
+    """A batch in which one request's output is too small: that request gets
+    CAT_ERANGE with its length, the others their exact results."""
+    import ctypes
+
+    import torch
+
+    lib = cat.load()
+    ns = np.array([1000, 5000, 777], dtype=np.uint64)
+    k = len(ns)
+    w = torch.empty(cat.batch_sizes(ns), dtype=torch.uint8, device="cuda")
+    outs = [torch.empty(cat.sizes(int(n))[1] if i != 1 else 3, dtype=torch.int32, device="cuda")
+            for i, n in enumerate(ns)]
+    t = ctypes.c_void_p()
+    st = torch.cuda.current_stream()
+    cat._check(lib.catalan_batch_begin(k, cat._p64(ns), cat._ptr(w), w.numel(), ctypes.c_void_p(st.cuda_stream),
+                                       ctypes.byref(t)), "begin")
+    ptrs = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+    caps = (ctypes.c_size_t * k)(*[o.numel() for o in outs])
+    cat._check(lib.catalan_batch_continue(t, ptrs, caps), "continue")
+    nl = (ctypes.c_size_t * k)()
+    rs = (ctypes.c_int32 * k)()
+    assert lib.catalan_batch_end(t, nl, rs) == cat.CAT_ERANGE
+    assert list(rs) == [cat.CAT_OK, cat.CAT_ERANGE, cat.CAT_OK]
+    assert nl[1] == len(oracle.catalan(5000))
+    for i in (0, 2):
+        assert np.array_equal(cat.to_numpy(outs[i][: nl[i]]), oracle.catalan(int(ns[i]))), i

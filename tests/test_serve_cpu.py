@@ -130,3 +130,39 @@ def test_on_done_sees_every_request_once():
     _drive(srv, ex)
     assert sorted(seen) == [r.rid for r in rs]
     assert rs[1].state == FAILED
+
+
+class _FakeBatching(FakeExecutor):
+    """Fake executor that, like the batch executor, starts the requests of one
+    admission step together when the server flushes."""
+
+    def __init__(self, *a, **kw):
+        super().__init__(*a, **kw)
+        self.forming, self.batches = [], []
+
+    def begin(self, r):
+        r.handle = None
+        self.forming.append(r)
+        self.log.append(("begin", r.rid, self.now))
+
+    def flush(self):
+        if self.forming:
+            self.batches.append([r.rid for r in self.forming])
+            for r in self.forming:
+                r.handle = self.now + self.p1(r.n)
+            self.forming = []
+        return []
+
+
+def test_flush_batches_each_admission_step():
+    """Requests admitted in the same step are flushed as one batch; requests
+    arriving while that batch runs form the next one (continuous batching)."""
+    ex = _FakeBatching(lambda n: 0.001, lambda n: 0.01)
+    srv = Server(ex, budget_bytes=10**6, max_slots=8, clock=ex.clock)
+    first = [srv.submit(10, arrival=0.0) for _ in range(3)]
+    late = [srv.submit(20, arrival=0.005) for _ in range(2)]
+    _drive(srv, ex)
+    assert all(r.state == DONE for r in first + late)
+    assert ex.batches[0] == [r.rid for r in first]
+    assert ex.batches[1] == [r.rid for r in late]
+    assert late[0].admitted < first[0].finished          # admitted while the first batch ran
