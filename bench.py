@@ -447,26 +447,30 @@ def serving_bench(cat, count=1100, warm=100, slots=None, budget=16 << 30, frac=0
         sat = len(ns) / dt
         if lam is None:
             lam = frac * sat
+        def verify(reqs):
+            bad = checked = 0
+            for r in reqs:
+                if r.state != DONE:
+                    bad += 1
+                    continue
+                if r.n not in solo:
+                    solo[r.n] = cat.to_numpy(cat.exact(r.n, mode="batched"))
+                got = cat.to_numpy(r.result)
+                if not np.array_equal(got, solo[r.n]):
+                    bad += 1
+                if str(r.n) in gold:
+                    L, h = gold[str(r.n)]
+                    checked += 1
+                    if len(got) != L or hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() != h:
+                        bad += 1
+                r.result = None
+            if bad:
+                raise SystemExit("bench: %d %s serving outputs differ from the same n alone or the oracle" % (bad, kind))
+            return checked
+
         srv, reqs, _ = _serve_once(cat, kind, ns, gaps, lam, slots[kind], budget, warm)
         st = srv.stats(skip=warm)
-        bad = checked = 0
-        for r in reqs:
-            if r.state != DONE:
-                bad += 1
-                continue
-            if r.n not in solo:
-                solo[r.n] = cat.to_numpy(cat.exact(r.n, mode="batched"))
-            got = cat.to_numpy(r.result)
-            if not np.array_equal(got, solo[r.n]):
-                bad += 1
-            if str(r.n) in gold:
-                L, h = gold[str(r.n)]
-                checked += 1
-                if len(got) != L or hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() != h:
-                    bad += 1
-            r.result = None
-        if bad:
-            raise SystemExit("bench: %d %s serving outputs differ from the same n alone or the oracle" % (bad, kind))
+        checked = verify(reqs)
         ex = _serve_once.ex[kind]
         out[kind] = {"saturated_req_per_s": round(sat, 1), "offered_req_per_s": round(lam, 1),
                      "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
@@ -480,8 +484,7 @@ def serving_bench(cat, count=1100, warm=100, slots=None, budget=16 << 30, frac=0
             lam2 = frac * sat
             srv, reqs, _ = _serve_once(cat, kind, ns, gaps, lam2, slots[kind], budget, warm)
             st2 = srv.stats(skip=warm)
-            if any(r.state != DONE for r in reqs):
-                raise SystemExit("bench: batched serving failed requests at the higher load")
+            verify(reqs)
             out[kind]["at_own_saturation"] = {"offered_req_per_s": round(lam2, 1), "p50_ms": round(st2["p50_ms"], 3),
                                               "p99_ms": round(st2["p99_ms"], 3),
                                               "req_per_s": round(st2["req_per_s"], 1)}
