@@ -286,7 +286,7 @@ uint2 scale_pair(int prime, int logN) {
 // ----------------------------------------------------------------------------
 // CLS_COLSUM: a long operand times a short one by exact column sums (only
 // chosen by the planner of the outer products, never by the tuning table).
-enum { CLS_SCHOOL = 0, CLS_LDS = 1, CLS_LARGE = 2, CLS_COLSUM = 3 };
+enum { CLS_SCHOOL = 0, CLS_LDS = 1, CLS_LARGE = 2, CLS_COLSUM = 3, CLS_FUSED = 4 };
 
 // Schedule per transform-length bucket 2^k (set by the autotuner, or defaults).
 cat_tuning default_tuning() {
@@ -382,6 +382,10 @@ struct Stage {
   uint32_t fused_tiles = 0;
   double fused_bfly = 0;   // algorithmic butterflies of the fused levels
   int jfirst = 0;          // first tree level this stage computes (tree stages)
+  // CLS_FUSED (generic batches): the one-workgroup buckets of up to 2^12
+  // coefficients in one k_mul_fused launch over a tile table
+  FusedMul fm{};
+  std::vector<uint2> host_tiles;
 };
 
 // Tree levels fused into one launch: consecutive one-workgroup levels with
@@ -956,6 +960,11 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev, bool device_table
                          std::vector<char>* keep = nullptr, hipStream_t st = nullptr) {
   size_t bytes = 0;
   for (Stage* s : all) {
+    if (s->cls == CLS_FUSED) {
+      bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
+      bytes = align_up(bytes, 16) + s->host_tiles.size() * sizeof(uint2);
+      continue;
+    }
     if (s->host_desc.size() > CAT_INLINE_DESC) bytes = align_up(bytes, 16) + s->host_desc.size() * sizeof(MulDesc);
     if (s->host_segs.size() > CAT_INLINE_SEG) {
       bytes = align_up(bytes, 16) + s->host_segs.size() * sizeof(CrtSeg);
@@ -971,6 +980,17 @@ cat_status upload_tables(std::vector<Stage*>& all, void** dev, bool device_table
   if (bytes) HIPCHK(hipMalloc(&d, bytes));
   size_t o = 0;
   for (Stage* s : all) {
+    if (s->cls == CLS_FUSED) {
+      o = align_up(o, 16);
+      memcpy(&h[o], s->host_desc.data(), s->host_desc.size() * sizeof(MulDesc));
+      s->fm.desc = (const MulDesc*)(d + o);
+      o += s->host_desc.size() * sizeof(MulDesc);
+      o = align_up(o, 16);
+      memcpy(&h[o], s->host_tiles.data(), s->host_tiles.size() * sizeof(uint2));
+      s->fm.tiles = (const uint2*)(d + o);
+      o += s->host_tiles.size() * sizeof(uint2);
+      continue;
+    }
     s->dv.ninl = 0;
     if (!s->host_desc.empty()) {
       if (s->host_desc.size() > CAT_INLINE_DESC) {
@@ -1332,6 +1352,18 @@ cat_status copy_tails(Exec& X, const Stage& s) {
 SegView stage_segs(const Stage& s) { return s.sv; }
 
 cat_status run_stage_batched(Exec& X, const Stage& s) {
+  if (s.cls == CLS_FUSED) {
+    if (s.host_tiles.empty()) return CAT_OK;
+    {
+      KTime kt("k_mul_fused", X.st, s.fused_bfly);
+      hipLaunchKernelGGL(k_mul_fused, dim3((uint32_t)s.host_tiles.size()), dim3(FT_THREADS), 0, X.st, s.fm,
+                         X.A ? X.A : X.W + s.a_base, X.B ? X.B : X.W + s.b_base, out_base(X, s), tables_for(0),
+                         X.err);
+    }
+    LAUNCHCHK();
+    X.launches++;
+    return CAT_OK;
+  }
   if (s.is_fused) {
     if (s.fused_tiles == 0) return CAT_OK;
     {
@@ -1631,6 +1663,43 @@ cat_status mul_plan_create(uint32_t batch, const uint64_t* a_off, const uint64_t
     M->stages.push_back(st);
   }
   M->nblk_max = nblk + 1;
+  // the one-workgroup buckets of up to 2^g_fuse_logn coefficients in one
+  // fused launch (batched form, while they hold at most FUSE_MAX_LEAVES
+  // coefficient slots: beyond that the per-bucket launches run at higher
+  // occupancy)
+  if (!(flags & CAT_MODE_PLAIN) && g_fuse_logn) {
+    uint64_t slots = 0;
+    int nf = 0;
+    for (const Stage& st : M->stages)
+      if (st.cls == CLS_LDS && st.logN <= (int)g_fuse_logn) {
+        slots += st.nmul << st.logN;
+        nf++;
+      }
+    if (nf > 0 && slots <= FUSE_MAX_LEAVES) {
+      Stage f;
+      f.cls = CLS_FUSED;
+      std::vector<Stage> kept;
+      for (Stage& st : M->stages) {
+        if (!(st.cls == CLS_LDS && st.logN <= (int)g_fuse_logn)) {
+          kept.push_back(st);
+          continue;
+        }
+        const uint32_t per = FT_SLOTS >> st.logN;
+        for (size_t i0 = 0; i0 < st.host_desc.size(); i0 += per) {
+          const uint32_t cnt = (uint32_t)std::min<size_t>(per, st.host_desc.size() - i0);
+          f.host_tiles.push_back(make_uint2((uint32_t)(f.host_desc.size() + i0), (uint32_t)st.logN | (cnt << 8)));
+        }
+        f.host_desc.insert(f.host_desc.end(), st.host_desc.begin(), st.host_desc.end());
+        f.nmul += st.nmul;
+        f.limbs += st.limbs;
+        f.fused_bfly += bfly(9.0 * st.nmul, st.logN);
+      }
+      for (int k = 0; k <= FT_LOGT; k++)
+        for (int q = 0; q < CAT_NPRIMES; q++) f.fm.scale[k][q] = k >= 1 ? scale_pair(q, k) : make_uint2(0, 0);
+      M->stages = kept;
+      M->stages.insert(M->stages.begin(), f);
+    }
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;

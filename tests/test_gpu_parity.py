@@ -331,6 +331,13 @@ def test_fused_levels_same_bits(cat, logn):
             got = cat.to_numpy(cat.exact(n, mode="graph"))
             assert np.array_equal(got, oracle.catalan(n)), (logn, n)
             assert np.array_equal(cat.to_numpy(cat.exact(n, mode="batched")), got), (logn, n)
+        # a generic batch: the one-workgroup buckets in one fused launch (or
+        # one launch pair per bucket), products of N and N + 1 limbs included
+        rng = np.random.default_rng(logn + 100)
+        la = np.rint(2 ** rng.uniform(0, 12, 150)).astype(np.int64).tolist() + [64, 2049, 1024, 2048, 129]
+        lb = np.rint(2 ** rng.uniform(0, 12, 150)).astype(np.int64).tolist() + [65, 2048, 1025, 2048, 128]
+        kinds = ["rand"] * 150 + ["ones", "ones", "rand", "ones", "rand"]
+        _run_batch(cat, la, lb, kinds, "batched", seed=logn)
         with open(os.path.join(GOLDEN, "oracle_catalan.json")) as f:
             gold = json.load(f)["10000000"]
         got = cat.to_numpy(cat.exact(10**7, mode="graph"))
