@@ -739,6 +739,22 @@ def main():
             roof["steady_state"] = steady_state(cat)
         log("bench: dominant kernel %s: %.4f ms avg over %d launches, frac %.3f" % (
             dom, roof["avg_launch_ms"], roof["launches"], roof["frac"]))
+    # the fingerprint kernel on the result (the residues every check reads):
+    # 4 B per limb read, against 8 TB/s
+    fp = None
+    if t.numel() >= (1 << 20):
+        cat.residues(t)
+        cat.timer_set("k_residues")
+        for _ in range(5):
+            cat.residues(t)
+        rms, rl, rw = cat.timer_get()
+        cat.timer_set(None)
+        gbs = 4.0 * rw / (rms / 1e3) / 1e9
+        fp = {"kernel": "k_residues", "limbs": int(t.numel()), "avg_launch_ms": round(rms / max(rl, 1), 4),
+              "achieved_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        ftr = load_traffic("k_residues", args.n)
+        fp["traffic"] = ftr.get("bytes_per_launch") if ftr else None
+        log("bench: fingerprints %s" % fp)
     del out
     cat.release_workspaces()
     torch.cuda.empty_cache()
@@ -801,6 +817,7 @@ def main():
         "phases": phases,
         "roofline": roof,
         "phase2_roofline": step_roof,
+        "fingerprint_kernel": fp,
         "cpu_baseline": cpu,
         "batched_vs_plain": secondary,
         "level_batch_4096": batch,
