@@ -164,7 +164,8 @@ k_mul_fused(FusedMul fm, const uint32_t* __restrict__ ain, const uint32_t* __res
   const uint32_t cnt = tl.y >> 8, N = 1u << logN;
   for (uint32_t i = tid; i < cnt; i += FT_THREADS) ds[i] = fm.desc[tl.x + i];
   __syncthreads();
-  const uint32_t prime = tid / FT_PART, lt = tid % FT_PART;
+  // FT_PART is a multiple of the wave size: the prime is uniform per wave
+  const uint32_t prime = __builtin_amdgcn_readfirstlane(tid / FT_PART), lt = tid % FT_PART;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
   uint32_t* lds = buf[prime];
@@ -215,7 +216,8 @@ k_tree_fused(FusedTree ft, const uint32_t* __restrict__ in, uint32_t* __restrict
   for (uint32_t k = tid; k < Kt; k += FT_THREADS) X[k] = in[gofs + k];
   __syncthreads();
 
-  const uint32_t prime = tid / FT_PART, lt = tid % FT_PART;
+  // FT_PART is a multiple of the wave size: the prime is uniform per wave
+  const uint32_t prime = __builtin_amdgcn_readfirstlane(tid / FT_PART), lt = tid % FT_PART;
   const PrimeC& pc = c_primes[prime];
   const uint32_t p = pc.p;
   uint32_t* lds = buf[prime];

@@ -95,33 +95,66 @@ __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
 // tw: table of this pass, tw[(k1 << logSR) + j2] = omega_S^{j2*k1}.
 // A thread handles U groups at once (g, g + blockDim, ...) so that the loads
 // of one overlap the arithmetic of the other.
+//
+// Addressing: element j1 of a group sits at base + j1 * stride with a stride
+// that is the same for the whole pass.  Unpadded, stride = 2^(logSR + logC).
+// Padded (PAD, used with logC = 0 only), index i sits at i + i/16; every pass
+// has logSR = 0 or a multiple of 4 (the passes after the first have radix 16
+// and the first takes logS mod 4), so i/16 grows by 2^logSR/16 per step of j1
+// (or by 0 when logSR = 0 and the 16 elements are one aligned run) and the
+// padded index is linear in j1 as well.  The twiddle of (k1, j2) is read at a
+// per-pass base (k1 << logSR), uniform across the workgroup, plus the lane's
+// j2: one 32-bit offset per group serves all R - 1 reads.
+__device__ __forceinline__ uint32_t pass_stride(bool pad, uint32_t logSR, uint32_t logC) {
+  return pad ? (1u << logSR) + ((1u << logSR) >> 4) : (1u << (logSR + logC));
+}
+
+template <int LOGR, bool PAD>
+__device__ __forceinline__ uint32_t group_base(uint32_t g, uint32_t logSR, uint32_t logC, uint32_t* jj) {
+  const uint32_t h = g >> logC;
+  const uint32_t j = h & ((1u << logSR) - 1);
+  *jj = j;
+  const uint32_t e0 = ((h >> logSR) << (logSR + LOGR)) + j;
+  return PAD ? lds_pad(e0) : (e0 << logC) + (g & ((1u << logC) - 1));
+}
+
+// The twiddle reads go through a raw buffer resource over the pass table
+// (kept in scalar registers: the table pointer is the same for a whole wave),
+// with the uniform part (k1 << logSR) as the scalar offset and the lane's j2
+// as the vector offset, so no per-read 64-bit address arithmetic is spent.
+// Word 3 of the gfx9 descriptor: 32-bit data format, which untyped loads use
+// for nothing but the range check against the table size.
+#define CAT_BUF_DW3 0x00020000
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tw_rsrc(const uint2* tw, uint32_t entries) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)tw, (short)0, (int)(entries * (uint32_t)sizeof(uint2)), CAT_BUF_DW3);
+}
+__device__ __forceinline__ uint2 tw_at(__amdgpu_buffer_rsrc_t rs, uint32_t k1, uint32_t logSR, uint32_t jo) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, jo, (int)((k1 << logSR) * (uint32_t)sizeof(uint2)), 0);
+  return make_uint2(v[0], v[1]);
+}
+
 template <int LOGR, bool PAD, int U>
 __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ tw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
-  const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
+  const uint32_t stride = pass_stride(PAD, logSR, logC);
   uint32_t v[U][R];
-  uint32_t e0[U], cc[U], jj[U];
+  uint32_t b[U], jj[U];
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const uint32_t g = g0 + u * nthr;
-    const uint32_t h = g >> logC;
-    cc[u] = g & cmask;
-    jj[u] = h & smask;
-    e0[u] = ((h >> logSR) << (logSR + LOGR)) + jj[u];
+    b[u] = group_base<LOGR, PAD>(g0 + u * nthr, logSR, logC, &jj[u]);
 #pragma unroll
-    for (int j1 = 0; j1 < R; j1++) {
-      const uint32_t a = ((e0[u] + ((uint32_t)j1 << logSR)) << logC) + cc[u];
-      v[u][j1] = lds[PAD ? lds_pad(a) : a];
-    }
+    for (int j1 = 0; j1 < R; j1++) v[u][j1] = lds[b[u] + j1 * stride];
   }
 #pragma unroll
   for (int u = 0; u < U; u++) {
     dft_fwd<LOGR>(v[u], pc);
     if (logSR > 0 && jj[u] != 0) {
+      const uint32_t jo = jj[u] * (uint32_t)sizeof(uint2);
+      const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << logSR);
 #pragma unroll
       for (int k1 = 1; k1 < R; k1++) {
-        const uint2 t = tw[((uint32_t)k1 << logSR) + jj[u]];
+        const uint2 t = tw_at(rs, (uint32_t)k1, logSR, jo);
         const int r = brev_c(k1, LOGR);
         v[u][r] = mul_tw(v[u][r], t.x, t.y, pc.p);
       }
@@ -130,10 +163,7 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
 #pragma unroll
   for (int u = 0; u < U; u++) {
 #pragma unroll
-    for (int k1 = 0; k1 < R; k1++) {
-      const uint32_t a = ((e0[u] + ((uint32_t)k1 << logSR)) << logC) + cc[u];
-      lds[PAD ? lds_pad(a) : a] = v[u][brev_c(k1, LOGR)];
-    }
+    for (int k1 = 0; k1 < R; k1++) lds[b[u] + k1 * stride] = v[u][brev_c(k1, LOGR)];
   }
 }
 
@@ -141,28 +171,23 @@ template <int LOGR, bool PAD, int U>
 __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ itw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
-  const uint32_t cmask = (1u << logC) - 1, smask = (1u << logSR) - 1;
+  const uint32_t stride = pass_stride(PAD, logSR, logC);
   uint32_t v[U][R];
-  uint32_t e0[U], cc[U], jj[U];
+  uint32_t b[U], jj[U];
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const uint32_t g = g0 + u * nthr;
-    const uint32_t h = g >> logC;
-    cc[u] = g & cmask;
-    jj[u] = h & smask;
-    e0[u] = ((h >> logSR) << (logSR + LOGR)) + jj[u];
+    b[u] = group_base<LOGR, PAD>(g0 + u * nthr, logSR, logC, &jj[u]);
 #pragma unroll
-    for (int k1 = 0; k1 < R; k1++) {
-      const uint32_t a = ((e0[u] + ((uint32_t)k1 << logSR)) << logC) + cc[u];
-      v[u][brev_c(k1, LOGR)] = lds[PAD ? lds_pad(a) : a];
-    }
+    for (int k1 = 0; k1 < R; k1++) v[u][brev_c(k1, LOGR)] = lds[b[u] + k1 * stride];
   }
 #pragma unroll
   for (int u = 0; u < U; u++) {
     if (logSR > 0 && jj[u] != 0) {
+      const uint32_t jo = jj[u] * (uint32_t)sizeof(uint2);
+      const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, (uint32_t)R << logSR);
 #pragma unroll
       for (int k1 = 1; k1 < R; k1++) {
-        const uint2 t = itw[((uint32_t)k1 << logSR) + jj[u]];
+        const uint2 t = tw_at(rs, (uint32_t)k1, logSR, jo);
         const int r = brev_c(k1, LOGR);
         v[u][r] = mul_tw(v[u][r], t.x, t.y, pc.p);
       }
@@ -172,10 +197,7 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
 #pragma unroll
   for (int u = 0; u < U; u++) {
 #pragma unroll
-    for (int j1 = 0; j1 < R; j1++) {
-      const uint32_t a = ((e0[u] + ((uint32_t)j1 << logSR)) << logC) + cc[u];
-      lds[PAD ? lds_pad(a) : a] = v[u][j1];
-    }
+    for (int j1 = 0; j1 < R; j1++) lds[b[u] + j1 * stride] = v[u][j1];
   }
 }
 
@@ -767,20 +789,24 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     for (int k = 0; k < 16; k++) {
       const uint32_t t = 16 * threadIdx.x + k;
       const uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
-      lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+      lds[lds_pad(t)] = mont_mul(x, y, p, pc.pinv);
     }
   } else {
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
       uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
-      lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+      lds[lds_pad(t)] = mont_mul(x, y, p, pc.pinv);
     }
     __syncthreads();
   }
   ntt_inv_tile<true>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   const uint2* ilo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* ihi = tb.itw2hi + (size_t)prime * TW2_HI;
+  // the pointwise scale (2^32 / N) rides on the inverse twiddles: every step
+  // after the pointwise product is linear mod p
   uint2 wi = tw2(ilo, ihi, ((threadIdx.x * fr) << ysh) & ymask, pc);
+  wi.x = mul_tw(wi.x, sc.x, sc.y, p);
+  wi.y = wi.x * pc.pinv;
   const uint2 Ri = tw2(ilo, ihi, ((NT * fr) << ysh) & ymask, pc);
   for (uint32_t t = threadIdx.x; t < M; t += NT) {
     fa[t] = mul_tw(lds[lds_pad(t)], wi.x, wi.y, p);
