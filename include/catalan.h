@@ -355,6 +355,19 @@ cat_status cat_tune_get(cat_tuning* t);
  * bit for bit either way.  Cached C(n) plans are dropped. */
 cat_status cat_fused_levels_set(uint32_t max_logn);
 
+/* Prime set of the transform products (Sec. 3.2: every multiplication of
+ * the reconstruction phase).  Products whose transform has at most
+ * 2^max_logn points use three primes below 2^30 (105 2^23 + 1,
+ * 107 2^23 + 1, 119 2^23 + 1), whose 4q < 2^32 lets the butterflies leave
+ * their values unreduced between operations; larger ones use the three
+ * primes in (2^31, 2^32).  Both cover every coefficient in their range
+ * (products of min(la, lb) <= 2^22 limbs for the first, <= 2^26 for the
+ * second), so the result is the same bit for bit either way.
+ * max_logn = 0 uses the second set everywhere; otherwise at most 23
+ * (default 23).  Cached C(n) and batched-multiply plans are dropped.
+ * Returns CAT_EINVAL above 23. */
+cat_status cat_lazy_primes_set(uint32_t max_logn);
+
 /* Carry look-back between CRT blocks (diagnostics and tests).  A block reads
  * the generate / propagate pair of the block before it from a flag that block
  * publishes, polling it at most `polls` times (at most 2^20), and otherwise

@@ -34,7 +34,7 @@ EXPORTS = [
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
     "decimal_sizes", "bigint_to_decimal", "catalan_exact_noalloc", "catalan_noalloc_max_bytes",
-    "cat_fused_levels_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
+    "cat_fused_levels_set", "cat_lazy_primes_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
     "catalan_batch_sizes", "catalan_batch_begin", "catalan_batch_continue", "catalan_batch_end",
 ]
 
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
         "catalan_exact_noalloc": ([ctypes.c_uint64, vp, ctypes.c_size_t, szp, vp], st),
         "catalan_noalloc_max_bytes": ([szp], st),
         "cat_fused_levels_set": ([ctypes.c_uint32], st),
+        "cat_lazy_primes_set": ([ctypes.c_uint32], st),
         "bigint_decimal_digits_workspace": ([ctypes.c_size_t, szp], st),
         "bigint_decimal_digits": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
         "bigint_mul_check": ([vp, vp], st),
@@ -218,6 +219,13 @@ def set_fused_levels(max_logn: int = 12) -> None:
     into one launch (0: every level is a transform and a carry launch).  Same
     results either way."""
     _check(load().cat_fused_levels_set(int(max_logn)), "cat_fused_levels_set")
+
+
+def set_lazy_primes(max_logn: int = 23) -> None:
+    """Transforms of up to 2^max_logn points use the three primes below 2^30
+    with unreduced butterfly ranges (0: the primes above 2^31 everywhere).
+    The results are the same bit for bit either way."""
+    _check(load().cat_lazy_primes_set(int(max_logn)), "cat_lazy_primes_set")
 
 
 def set_tuning(d: Optional[dict]) -> None:

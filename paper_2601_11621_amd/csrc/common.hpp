@@ -76,6 +76,44 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p,
 __device__ __forceinline__ uint32_t reduce_limb(uint32_t x, uint32_t p) { return x >= p ? x - p : x; }
 
 // ----------------------------------------------------------------------------
+// The second prime set: q0 = 105*2^23+1, q1 = 107*2^23+1, q2 = 119*2^23+1, all
+// below 2^30 (product ~2^89.35, 2-adicity 23).  A coefficient of a product
+// with min(la, lb) <= 2^22 limbs is below 2^22 (2^32-1)^2 < 2^86, so
+// transforms of up to 2^23 points can use it.  With 4q < 2^32, residues may
+// stay unreduced between butterflies (Harvey 2014, "Faster arithmetic for
+// number-theoretic transforms"): forward passes keep values in [0, 2q),
+// inverse passes in [0, 4q), and only the outputs that leave the transform
+// are reduced to [0, q).  Twiddles from tables are Shoup pairs (w in normal
+// form, w' = floor(w 2^32 / q)); twiddles computed on the fly stay Montgomery
+// pairs as in the first set.
+// ----------------------------------------------------------------------------
+#define CAT_LAZY_MAX_LOGN 23
+
+// x < 2m -> x mod m (one subtraction, m = q or 2q)
+__device__ __forceinline__ uint32_t red2(uint32_t x, uint32_t m) {
+  uint32_t d;
+  return __builtin_usub_overflow(x, m, &d) ? x : d;
+}
+// a*w mod q in [0, 2q) for every 32-bit a (Shoup): w < q, ws = floor(w 2^32 / q)
+__device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
+  return a * w - __umulhi(a, ws) * q;
+}
+// a*w/2^32 mod q in (0, 2q) for every 32-bit a, w < q Montgomery form,
+// wq = w * q^-1 mod 2^32: hi(a w) - hi(m q) lies in (-q, q)
+__device__ __forceinline__ uint32_t mont_lazy(uint32_t a, uint32_t w, uint32_t wq, uint32_t q) {
+  return __umulhi(a, w) - __umulhi(a * wq, q) + q;
+}
+// x*y/2^32 mod q in (0, 2q) for x, y < 2q (x y < 4q^2, so hi(x y) < q)
+__device__ __forceinline__ uint32_t mont_mul_lazy(uint32_t x, uint32_t y, uint32_t q, uint32_t qinv) {
+  const uint32_t lo = x * y;
+  return __umulhi(x, y) - __umulhi(lo * qinv, q) + q;
+}
+// limb (any 32-bit value, < 8q) into [0, 2q)
+__device__ __forceinline__ uint32_t limb_lazy(uint32_t x, uint32_t q) { return red2(red2(x, 4 * q), 2 * q); }
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ uint32_t red4(uint32_t x, uint32_t q) { return red2(red2(x, 2 * q), q); }
+
+// ----------------------------------------------------------------------------
 // Descriptors of a batch of products c = a * b.
 // Explicit: a table in device memory.  Tree: computed from the level of a
 // forest of balanced product trees (one tree per exponent group): node i of

@@ -17,14 +17,17 @@ namespace {
 
 static const uint32_t kP[CAT_NPRIMES] = {3221225473u, 3489660929u, 3892314113u};
 static const uint32_t kGen[CAT_NPRIMES] = {5u, 3u, 3u};   // primitive roots
+// the second (lazy) set, ascending as Garner's method needs: 105 2^23 + 1,
+// 107 2^23 + 1, 119 2^23 + 1
+static const uint32_t kQ[CAT_NPRIMES] = {880803841u, 897581057u, 998244353u};
+static const uint32_t kQGen[CAT_NPRIMES] = {26u, 3u, 3u};
 
 struct Stage;
 struct Plan;
 struct MulPlanImpl;
 
-struct Lib {
-  bool inited = false;
-  int device = -1;
+// Constants and twiddle tables of one prime set.
+struct PrimeSet {
   PrimeC prc[CAT_NPRIMES];
   CrtC crt;
   RootsC roots;
@@ -34,6 +37,12 @@ struct Lib {
   uint32_t* tw2hi = nullptr;
   uint2* itw2lo = nullptr;
   uint32_t* itw2hi = nullptr;
+};
+
+struct Lib {
+  bool inited = false;
+  int device = -1;
+  PrimeSet set[2];   // 0: primes in (2^31, 2^32); 1: the lazy set below 2^30
   void* pin = nullptr;          // pinned host staging for small D2H
   int last_err = 0;
   std::recursive_mutex mu;
@@ -173,58 +182,91 @@ cat_status set_device() {
   return CAT_OK;
 }
 
-cat_status init_locked(int device) {
-  if (g.inited) return CAT_OK;
-  if (device < 0) HIPCHK(hipGetDevice(&device));
-  g.device = device;
-  HIPCHK(hipSetDevice(device));
-  memset(&g.roots, 0, sizeof(g.roots));
+// Constants and tables of prime set `as` (primes P ascending, primitive
+// roots G, transforms up to 2^maxlog).  Set 0 keeps Montgomery pairs
+// everywhere; set 1 takes Shoup pairs for the in-pass constants and tables.
+cat_status init_prime_set(int as, const uint32_t* P, const uint32_t* G, int maxlog) {
+  PrimeSet& S = g.set[as];
+  memset(&S.roots, 0, sizeof(S.roots));
   for (int i = 0; i < CAT_NPRIMES; i++) {
-    PrimeC& pc = g.prc[i];
+    PrimeC& pc = S.prc[i];
     memset(&pc, 0, sizeof(pc));
-    pc.p = kP[i];
-    pc.pinv = h_inv32(kP[i]);
+    pc.p = P[i];
+    pc.pinv = h_inv32(P[i]);
     const uint32_t p = pc.p;
-    const uint32_t w27 = h_powmod(kGen[i], (uint64_t)(p - 1) >> CAT_MAX_LOGN, p);
-    const uint32_t iw27 = h_inv(w27, p);
-    for (int s = 0; s <= CAT_MAX_LOGN; s++) {
-      const uint64_t ex = 1ull << (CAT_MAX_LOGN - s);
-      g.roots.r[i][s] = h_mont(h_powmod(w27, ex, p), p);
-      g.roots.ir[i][s] = h_mont(h_powmod(iw27, ex, p), p);
+    const uint32_t wmax = h_powmod(G[i], (uint64_t)(p - 1) >> maxlog, p);
+    // a primitive 2^maxlog-th root: its 2^(maxlog-1)-th power is -1
+    if (h_powmod(wmax, 1ull << (maxlog - 1), p) != p - 1) return CAT_EINTERNAL;
+    const uint32_t iwmax = h_inv(wmax, p);
+    for (int s = 0; s <= maxlog; s++) {
+      const uint64_t ex = 1ull << (maxlog - s);
+      S.roots.r[i][s] = h_mont(h_powmod(wmax, ex, p), p);
+      S.roots.ir[i][s] = h_mont(h_powmod(iwmax, ex, p), p);
     }
-    g.roots.one[i] = h_mont(1, p);
-    const uint32_t w16 = h_powmod(w27, 1ull << (CAT_MAX_LOGN - 4), p);
+    S.roots.one[i] = h_mont(1, p);
+    const uint32_t w16 = h_powmod(wmax, 1ull << (maxlog - 4), p);
     const uint32_t iw16 = h_inv(w16, p);
     for (int k = 0; k < 8; k++) {
-      h_pair(h_powmod(w16, k, p), pc, &pc.w16[k], &pc.w16q[k]);
-      h_pair(h_powmod(iw16, k, p), pc, &pc.iw16[k], &pc.iw16q[k]);
+      if (as == 0) {
+        h_pair(h_powmod(w16, k, p), pc, &pc.w16[k], &pc.w16q[k]);
+        h_pair(h_powmod(iw16, k, p), pc, &pc.iw16[k], &pc.iw16q[k]);
+      } else {
+        pc.w16[k] = h_powmod(w16, k, p);
+        pc.w16q[k] = (uint32_t)(((uint64_t)pc.w16[k] << 32) / p);
+        pc.iw16[k] = h_powmod(iw16, k, p);
+        pc.iw16q[k] = (uint32_t)(((uint64_t)pc.iw16[k] << 32) / p);
+      }
     }
   }
   {
-    CrtC& c = g.crt;
-    const uint32_t p0 = kP[0], p1 = kP[1], p2 = kP[2];
-    h_pair(h_inv(p0 % p1, p1), g.prc[1], &c.c01, &c.c01q);
-    h_pair(p0 % p2, g.prc[2], &c.p0m2, &c.p0m2q);
+    CrtC& c = S.crt;
+    const uint32_t p0 = P[0], p1 = P[1], p2 = P[2];
+    h_pair(h_inv(p0 % p1, p1), S.prc[1], &c.c01, &c.c01q);
+    h_pair(p0 % p2, S.prc[2], &c.p0m2, &c.p0m2q);
     const uint32_t p01m2 = h_mulmod(p0 % p2, p1 % p2, p2);
-    h_pair(h_inv(p01m2, p2), g.prc[2], &c.c012, &c.c012q);
+    h_pair(h_inv(p01m2, p2), S.prc[2], &c.c012, &c.c012q);
     c.p0 = p0;
     const uint64_t p01 = (uint64_t)p0 * p1;
     c.p01_lo = (uint32_t)p01;
     c.p01_hi = (uint32_t)(p01 >> 32);
   }
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_primes), g.prc, sizeof(g.prc)));
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_crt), &g.crt, sizeof(g.crt)));
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_roots), &g.roots, sizeof(g.roots)));
-  HIPCHK(hipMalloc(&g.tws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
-  HIPCHK(hipMalloc(&g.itws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
-  hipLaunchKernelGGL(k_build_tws, dim3(32, CAT_NPRIMES), dim3(256), 0, 0, g.tws, g.itws);
+  if (as == 0) {
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_primes), S.prc, sizeof(S.prc)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_crt), &S.crt, sizeof(S.crt)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_roots), &S.roots, sizeof(S.roots)));
+  } else {
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_primes1), S.prc, sizeof(S.prc)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_crt1), &S.crt, sizeof(S.crt)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_roots1), &S.roots, sizeof(S.roots)));
+  }
+  HIPCHK(hipMalloc(&S.tws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&S.itws, sizeof(uint2) * TWS_ENTRIES * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&S.tw2lo, sizeof(uint2) * TW2_LO * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&S.itw2lo, sizeof(uint2) * TW2_LO * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&S.tw2hi, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
+  HIPCHK(hipMalloc(&S.itw2hi, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
+  HIPCHK(hipMemset(S.tw2hi, 0, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
+  HIPCHK(hipMemset(S.itw2hi, 0, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
+  if (as == 0) {
+    hipLaunchKernelGGL(k_build_tws<0>, dim3(32, CAT_NPRIMES), dim3(256), 0, 0, S.tws, S.itws);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_build_tw2<0>, dim3(64, CAT_NPRIMES), dim3(256), 0, 0, S.tw2lo, S.tw2hi, S.itw2lo, S.itw2hi);
+  } else {
+    hipLaunchKernelGGL(k_build_tws<1>, dim3(32, CAT_NPRIMES), dim3(256), 0, 0, S.tws, S.itws);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_build_tw2<1>, dim3(64, CAT_NPRIMES), dim3(256), 0, 0, S.tw2lo, S.tw2hi, S.itw2lo, S.itw2hi);
+  }
   LAUNCHCHK();
-  HIPCHK(hipMalloc(&g.tw2lo, sizeof(uint2) * TW2_LO * CAT_NPRIMES));
-  HIPCHK(hipMalloc(&g.itw2lo, sizeof(uint2) * TW2_LO * CAT_NPRIMES));
-  HIPCHK(hipMalloc(&g.tw2hi, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
-  HIPCHK(hipMalloc(&g.itw2hi, sizeof(uint32_t) * TW2_HI * CAT_NPRIMES));
-  hipLaunchKernelGGL(k_build_tw2, dim3(64, CAT_NPRIMES), dim3(256), 0, 0, g.tw2lo, g.tw2hi, g.itw2lo, g.itw2hi);
-  LAUNCHCHK();
+  return CAT_OK;
+}
+
+cat_status init_locked(int device) {
+  if (g.inited) return CAT_OK;
+  if (device < 0) HIPCHK(hipGetDevice(&device));
+  g.device = device;
+  HIPCHK(hipSetDevice(device));
+  STCHK(init_prime_set(0, kP, kGen, CAT_MAX_LOGN));
+  STCHK(init_prime_set(1, kQ, kQGen, CAT_LAZY_MAX_LOGN));
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipHostMalloc(&g.pin, 1 << 16, hipHostMallocDefault));
   // the device's own copy of the static scratch (the device is current here)
@@ -238,15 +280,15 @@ cat_status init_locked(int device) {
   return CAT_OK;
 }
 
-NttTables tables_for(int logN) {
-  (void)logN;
+NttTables tables_for(int as) {
+  const PrimeSet& S = g.set[as];
   NttTables tb;
-  tb.tws = g.tws;
-  tb.itws = g.itws;
-  tb.tw2lo = g.tw2lo;
-  tb.tw2hi = g.tw2hi;
-  tb.itw2lo = g.itw2lo;
-  tb.itw2hi = g.itw2hi;
+  tb.tws = S.tws;
+  tb.itws = S.itws;
+  tb.tw2lo = S.tw2lo;
+  tb.tw2hi = S.tw2hi;
+  tb.itw2lo = S.itw2lo;
+  tb.itw2hi = S.itw2hi;
   return tb;
 }
 
@@ -273,8 +315,8 @@ PassPlan pass_plan(int logN, int logM, int maxL, int logT = NTT_COL_LOGT) {
 
 // scale constant 2^32 * N^-1 (Montgomery pair): the pointwise product
 // mont_mul(x, y) = x*y/2^32 times it gives x*y/N, undoing the unscaled inverse.
-uint2 scale_pair(int prime, int logN) {
-  const PrimeC& pc = g.prc[prime];
+uint2 scale_pair(int prime, int logN, int as = 0) {
+  const PrimeC& pc = g.set[as].prc[prime];
   const uint32_t p = pc.p;
   const uint32_t ninv = h_inv(h_powmod(2, logN, p), p);
   const uint32_t W = h_mulmod(ninv, (uint32_t)((1ull << 32) % p), p);
@@ -400,6 +442,11 @@ struct Stage {
 // (C(10^8): 5.91 vs 6.05 ms; C(2,050,572,903): 136.5 vs 137.9 ms).
 uint32_t g_fuse_logn = FT_LOGT;
 #define FUSE_MAX_LEAVES (1ull << 22)
+
+// Transforms of up to 2^g_lazy_logn points take the lazy prime set (0: none).
+// Its three primes cover every coefficient of a product with
+// min(la, lb) <= 2^22 limbs, which holds for N <= 2^23.
+uint32_t g_lazy_logn = CAT_LAZY_MAX_LOGN;
 
 // host mirror of DescView::get in tree mode
 MulDesc tree_desc(const TreeLevel& t, uint64_t i) {
@@ -1132,7 +1179,7 @@ struct Exec {
 };
 
 cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const CopyList* tails = nullptr,
-                      const uint32_t* tin = nullptr, uint32_t* tout = nullptr, bool raw = false) {
+                      const uint32_t* tin = nullptr, uint32_t* tout = nullptr, bool raw = false, int as = 0) {
   static const CopyList none{};
   const CopyList& cl = tails ? *tails : none;
   const uint32_t grid = nblk + tail_blocks(cl);
@@ -1141,11 +1188,14 @@ cat_status launch_crt(Exec& X, uint32_t* out, SegView sv, uint32_t nblk, const C
     KTime kt("k_crt", X.st, (double)nblk * CAT_CRT_BLOCK);
     X.crt_epoch++;
     if (raw)
-      hipLaunchKernelGGL(k_crt<true>, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk,
-                         X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
+      hipLaunchKernelGGL((k_crt<true, 0>), dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out,
+                         nblk, X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
+    else if (as == 0)
+      hipLaunchKernelGGL((k_crt<false, 0>), dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out,
+                         nblk, X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
     else
-      hipLaunchKernelGGL(k_crt<false>, dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out, nblk,
-                         X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
+      hipLaunchKernelGGL((k_crt<false, 1>), dim3(grid), dim3(CAT_CRT_THREADS), 0, X.st, sv, X.res, X.res_stride, out,
+                         nblk, X.flags, X.crt_epoch, crt_polls(nblk), cl, tin, tout, X.err);
   }
   LAUNCHCHK();
   X.launches++;
@@ -1170,6 +1220,13 @@ cat_status launch_crt10(Exec& X, uint32_t* out, const SegView& sv, uint32_t nblk
 
 // Products of a stage given by `dv` (cnt of them): the NTT or schoolbook part.
 uint32_t* out_base(Exec& X, const Stage& s) { return X.C ? X.C : X.W + s.c_base; }
+
+// prime set of a transform stage (radix-10^9 products keep the first set,
+// whose CRT kernel carries in that radix)
+int stage_as(const Stage& s) {
+  if (s.dec || (s.cls != CLS_LDS && s.cls != CLS_LARGE)) return 0;
+  return (uint32_t)s.logN <= g_lazy_logn ? 1 : 0;
+}
 
 cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, bool with_tails = false) {
   const uint32_t* ain = X.A ? X.A : X.W + s.a_base;
@@ -1211,8 +1268,9 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     X.launches++;
     return CAT_OK;
   }
-  const NttTables tb = tables_for(s.logN);
-  const uint2 s0 = scale_pair(0, s.logN), s1 = scale_pair(1, s.logN), s2 = scale_pair(2, s.logN);
+  const int as = stage_as(s);
+  const NttTables tb = tables_for(as);
+  const uint2 s0 = scale_pair(0, s.logN, as), s1 = scale_pair(1, s.logN, as), s2 = scale_pair(2, s.logN, as);
   if (s.cls == CLS_LDS) {
     // tile 2^lt (2^lt / 16 threads, 2^(lt - logN) products per workgroup): the
     // schedule's tile for the bucket (log_row of a one-workgroup bucket)
@@ -1226,9 +1284,15 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     // large enough for the saved transforms to outweigh the extra launch
     const bool constb = dv.uni && dv.u.sb == 0 && cnt > 1 && (cnt << s.logN) >= (1ull << 21);
     KTime kt("k_ntt_lds", X.st, constb ? bfly(6.0 * cnt + 3.0, s.logN) : bfly(9.0 * cnt, s.logN));
-#define LDS_LAUNCH(LT, BM, G)                                                                                      \
-  hipLaunchKernelGGL((k_ntt_lds<LT, BM>), G, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res, X.res_stride, tb, s0, \
-                     s1, s2, X.F)
+#define LDS_LAUNCH(LT, BM, G)                                                                                \
+  do {                                                                                                         \
+    if (as == 0)                                                                                               \
+      hipLaunchKernelGGL((k_ntt_lds<LT, BM, 0>), G, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res,          \
+                         X.res_stride, tb, s0, s1, s2, X.F);                                                   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_ntt_lds<LT, BM, 1>), G, block, 0, X.st, dv, cnt, s.logN, ain, bin, X.res,          \
+                         X.res_stride, tb, s0, s1, s2, X.F);                                                   \
+  } while (0)
     if (constb) {
       if (lt == 12) LDS_LAUNCH(12, 1, dim3(CAT_NPRIMES));
       else if (lt == 13) LDS_LAUNCH(13, 1, dim3(CAT_NPRIMES));
@@ -1268,12 +1332,17 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
   const bool constb = dv.uni && dv.u.sb == 0 && cnt > 1;
   auto pass_fwd = [&](const PassGeom& pg, int k, int plS, int plL, uint64_t gx, uint32_t nop, int op_base) {
     const dim3 grid((uint32_t)(gx * CAT_NPRIMES), 1, nop);
-    if (logT == NTT_COL_LOGT_SMALL)
-      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT_SMALL>, grid, dim3(NTT_COL_THREADS), 0, X.st, dv, pg, k == 0 ? 1 : 0,
-                         self_tw(k), pre_tw(k), plS, plL, op_base, ain, bin, X.F, tb);
-    else
-      hipLaunchKernelGGL(k_pass_fwd<NTT_COL_LOGT>, grid, dim3(NTT_COL_THREADS), 0, X.st, dv, pg, k == 0 ? 1 : 0,
-                         self_tw(k), pre_tw(k), plS, plL, op_base, ain, bin, X.F, tb);
+#define PASS_FWD(LT, A)                                                                                            \
+  hipLaunchKernelGGL((k_pass_fwd<LT, A>), grid, dim3(NTT_COL_THREADS), 0, X.st, dv, pg, k == 0 ? 1 : 0, self_tw(k), \
+                     pre_tw(k), plS, plL, op_base, ain, bin, X.F, tb)
+    if (logT == NTT_COL_LOGT_SMALL) {
+      if (as == 0) PASS_FWD(NTT_COL_LOGT_SMALL, 0);
+      else PASS_FWD(NTT_COL_LOGT_SMALL, 1);
+    } else {
+      if (as == 0) PASS_FWD(NTT_COL_LOGT, 0);
+      else PASS_FWD(NTT_COL_LOGT, 1);
+    }
+#undef PASS_FWD
   };
   for (int k = 0; k < pp.P; k++) {
     PassGeom pg{s.logN, pp.logS[k], pp.logL[k], pp.logC[k]};
@@ -1299,15 +1368,20 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     const dim3 block((1u << lt) / 16);
     auto row = [&](uint64_t nprod, int bmode) {
       const dim3 grid((uint32_t)(nprod << logR1), CAT_NPRIMES);
-      if (lt == 12)
-        hipLaunchKernelGGL(k_row<12>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], bmode,
-                           X.F, tb, s0, s1, s2);
-      else if (lt == 13)
-        hipLaunchKernelGGL(k_row<13>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], bmode,
-                           X.F, tb, s0, s1, s2);
-      else
-        hipLaunchKernelGGL(k_row<14>, grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], bmode,
-                           X.F, tb, s0, s1, s2);
+#define ROW(LT, A)                                                                                              \
+  hipLaunchKernelGGL((k_row<LT, A>), grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], \
+                     bmode, X.F, tb, s0, s1, s2)
+      if (lt == 12) {
+        if (as == 0) ROW(12, 0);
+        else ROW(12, 1);
+      } else if (lt == 13) {
+        if (as == 0) ROW(13, 0);
+        else ROW(13, 1);
+      } else {
+        if (as == 0) ROW(14, 0);
+        else ROW(14, 1);
+      }
+#undef ROW
     };
     KTime kt("k_row", X.st, constb ? bfly(6.0 * rows + 3.0 * (1ull << logR1), logM) : bfly(9.0 * rows, logM));
     if (constb) {
@@ -1325,12 +1399,17 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
     const int plS = k >= 1 ? pp.logS[k - 1] : 0, plL = k >= 1 ? pp.logL[k - 1] : 0;
     const uint64_t gx = cnt << (s.logN - pp.logL[k] - pp.logC[k]);
     KTime kt("k_pass_inv", X.st, 3.0 * cnt * N / 2 * pp.logL[k]);
-    if (logT == NTT_COL_LOGT_SMALL)
-      hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT_SMALL>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st,
-                         dv, pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, X.F, X.res, X.res_stride, tb);
-    else
-      hipLaunchKernelGGL(k_pass_inv<NTT_COL_LOGT>, dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv,
-                         pg, k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, X.F, X.res, X.res_stride, tb);
+#define PASS_INV(LT, A)                                                                                         \
+  hipLaunchKernelGGL((k_pass_inv<LT, A>), dim3((uint32_t)gx, CAT_NPRIMES), dim3(NTT_COL_THREADS), 0, X.st, dv, pg, \
+                     k == 0 ? 1 : 0, self_tw(k), pre_tw(k), plS, plL, X.F, X.res, X.res_stride, tb)
+    if (logT == NTT_COL_LOGT_SMALL) {
+      if (as == 0) PASS_INV(NTT_COL_LOGT_SMALL, 0);
+      else PASS_INV(NTT_COL_LOGT_SMALL, 1);
+    } else {
+      if (as == 0) PASS_INV(NTT_COL_LOGT, 0);
+      else PASS_INV(NTT_COL_LOGT, 1);
+    }
+#undef PASS_INV
     LAUNCHCHK();
   }
   X.launches += 2 * pp.P + 1;
@@ -1396,7 +1475,7 @@ cat_status run_stage_batched(Exec& X, const Stage& s) {
     STCHK(launch_products(X, s, s.dv, s.nmul, s.cls == CLS_SCHOOL));
     if (s.cls != CLS_SCHOOL)
       STCHK(launch_crt(X, out_base(X, s), stage_segs(s), s.nblk, &s.tails, X.W + s.tail_in_base,
-                       X.W + s.tail_out_base, s.cls == CLS_COLSUM));
+                       X.W + s.tail_out_base, s.cls == CLS_COLSUM, stage_as(s)));
     return CAT_OK;
   }
   return copy_tails(X, s);
@@ -1432,7 +1511,7 @@ cat_status run_stage_plain(Exec& X, const Stage& s) {
       const uint32_t nb = (uint32_t)((sv.iseg[0].len + CAT_CRT_BLOCK - 1) / CAT_CRT_BLOCK);
       sv.ipref[0] = 0;
       sv.ipref[1] = nb;
-      STCHK(launch_crt(X, out_base(X, s), sv, nb, nullptr, nullptr, nullptr, s.cls == CLS_COLSUM));
+      STCHK(launch_crt(X, out_base(X, s), sv, nb, nullptr, nullptr, nullptr, s.cls == CLS_COLSUM, stage_as(s)));
     }
   }
   return copy_tails(X, s);
@@ -2315,6 +2394,22 @@ cat_status cat_fused_levels_set(uint32_t max_logn) {
   for (auto& kv : g.noalloc_plans) free_plan(kv.second);
   g.noalloc_plans.clear();
   g.noalloc_order.clear();
+  return CAT_OK;
+}
+
+cat_status cat_lazy_primes_set(uint32_t max_logn) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  if (max_logn > CAT_LAZY_MAX_LOGN) return CAT_EINVAL;
+  g_lazy_logn = max_logn;
+  // cached plans and their graphs were made with the old setting
+  if (!g.plans.empty() || !g.noalloc_plans.empty()) HIPCHK(hipDeviceSynchronize());
+  for (auto& kv : g.plans) free_plan(kv.second);
+  g.plans.clear();
+  g.plan_order.clear();
+  for (auto& kv : g.noalloc_plans) free_plan(kv.second);
+  g.noalloc_plans.clear();
+  g.noalloc_order.clear();
+  mul_cache_clear();
   return CAT_OK;
 }
 

@@ -32,6 +32,31 @@
 
 __constant__ PrimeC c_primes[CAT_NPRIMES];
 __constant__ CrtC c_crt;
+// The second (lazy) prime set; its w16 / iw16 entries are Shoup pairs.
+__constant__ PrimeC c_primes1[CAT_NPRIMES];
+__constant__ CrtC c_crt1;
+// AS: the prime set of a kernel (0: p in (2^31, 2^32), values reduced after
+// every operation; 1: q < 2^30, lazy ranges as described in common.hpp)
+template <int AS>
+__device__ __forceinline__ const PrimeC& primec(uint32_t i) {
+  if constexpr (AS == 0) return c_primes[i];
+  else return c_primes1[i];
+}
+template <int AS>
+__device__ __forceinline__ const CrtC& crtc() {
+  if constexpr (AS == 0) return c_crt;
+  else return c_crt1;
+}
+// largest transform of a prime set (log2): the column twiddles are powers of
+// omega_{2^tw_logn}
+template <int AS>
+__host__ __device__ constexpr int tw_logn() { return AS == 0 ? CAT_MAX_LOGN : CAT_LAZY_MAX_LOGN; }
+// twiddle product: Montgomery pair (set 0, exact) or Shoup pair (set 1, [0, 2q))
+template <int AS>
+__device__ __forceinline__ uint32_t tw_mul(uint32_t a, uint32_t w, uint32_t ws, uint32_t p) {
+  if constexpr (AS == 0) return mul_tw(a, w, ws, p);
+  else return shoup(a, w, ws, p);
+}
 
 // bit reversal of an r-bit index, compile-time
 __host__ __device__ constexpr int brev_c(int x, int r) {
@@ -43,11 +68,14 @@ __host__ __device__ constexpr int brev_c(int x, int r) {
 __host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
 
 // Radix-R DFT on registers, decimation in frequency: natural input, output
-// y[k] in v[brev(k)].
-template <int LOGR>
+// y[k] in v[brev(k)].  Set 1: inputs and outputs in [0, 2q); a butterfly
+// gives red(a + b) and (a - b + 2q) * w (the sum below 4q, the Shoup product
+// below 2q).
+template <int LOGR, int AS = 0>
 __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t p = pc.p;
+  const uint32_t p2 = 2 * p;
 #pragma unroll
   for (int h = R / 2; h >= 1; h /= 2) {
 #pragma unroll
@@ -55,12 +83,17 @@ __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
 #pragma unroll
       for (int i = 0; i < h; i++) {
         uint32_t a = v[s + i], b = v[s + i + h];
-        v[s + i] = add_mod(a, b, p);
-        uint32_t d = sub_mod(a, b, p);
-        if (i == 0) v[s + i + h] = d;
-        else {
-          const int wi = i * (8 / h);   // omega_{2h}^i = omega_16^{i*8/h}
-          v[s + i + h] = mul_tw(d, pc.w16[wi], pc.w16q[wi], p);
+        const int wi = i * (8 / h);   // omega_{2h}^i = omega_16^{i*8/h}
+        if constexpr (AS == 0) {
+          v[s + i] = add_mod(a, b, p);
+          uint32_t d = sub_mod(a, b, p);
+          if (i == 0) v[s + i + h] = d;
+          else v[s + i + h] = mul_tw(d, pc.w16[wi], pc.w16q[wi], p);
+        } else {
+          v[s + i] = red2(a + b, p2);
+          const uint32_t t = a + (p2 - b);
+          if (i == 0) v[s + i + h] = red2(t, p2);
+          else v[s + i + h] = shoup(t, pc.w16[wi], pc.w16q[wi], p);
         }
       }
     }
@@ -68,11 +101,14 @@ __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
 }
 
 // Inverse: input y[k] in v[brev(k)], decimation in time with inverse roots,
-// output x[j] (times R) in v[j].
-template <int LOGR>
+// output x[j] (times R) in v[j].  Set 1: inputs and outputs in [0, 4q); a
+// butterfly reduces a to [0, 2q), takes t = w b in [0, 2q) and gives a + t and
+// a - t + 2q.
+template <int LOGR, int AS = 0>
 __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t p = pc.p;
+  const uint32_t p2 = 2 * p;
 #pragma unroll
   for (int h = 1; h < R; h *= 2) {
 #pragma unroll
@@ -81,9 +117,16 @@ __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
       for (int i = 0; i < h; i++) {
         uint32_t a = v[s + i], b = v[s + i + h];
         const int wi = i * (8 / h);
-        uint32_t t = (i == 0) ? b : mul_tw(b, pc.iw16[wi], pc.iw16q[wi], p);
-        v[s + i] = add_mod(a, t, p);
-        v[s + i + h] = sub_mod(a, t, p);
+        if constexpr (AS == 0) {
+          uint32_t t = (i == 0) ? b : mul_tw(b, pc.iw16[wi], pc.iw16q[wi], p);
+          v[s + i] = add_mod(a, t, p);
+          v[s + i + h] = sub_mod(a, t, p);
+        } else {
+          a = red2(a, p2);
+          const uint32_t t = (i == 0) ? red2(b, p2) : shoup(b, pc.iw16[wi], pc.iw16q[wi], p);
+          v[s + i] = a + t;
+          v[s + i + h] = a + (p2 - t);
+        }
       }
     }
   }
@@ -133,7 +176,7 @@ __device__ __forceinline__ uint2 tw_at(__amdgpu_buffer_rsrc_t rs, uint32_t k1, u
   return make_uint2(v[0], v[1]);
 }
 
-template <int LOGR, bool PAD, int U>
+template <int LOGR, bool PAD, int U, int AS>
 __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ tw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
@@ -146,17 +189,19 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
 #pragma unroll
     for (int j1 = 0; j1 < R; j1++) v[u][j1] = lds[b[u] + j1 * stride];
   }
+  // (j2 = 0 reads the pair of 1, which multiplies exactly: no divergent
+  // branch around the twiddles)
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    dft_fwd<LOGR>(v[u], pc);
-    if (logSR > 0 && jj[u] != 0) {
+    dft_fwd<LOGR, AS>(v[u], pc);
+    if (logSR > 0) {
       const uint32_t jo = jj[u] * (uint32_t)sizeof(uint2);
       const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << logSR);
 #pragma unroll
       for (int k1 = 1; k1 < R; k1++) {
         const uint2 t = tw_at(rs, (uint32_t)k1, logSR, jo);
         const int r = brev_c(k1, LOGR);
-        v[u][r] = mul_tw(v[u][r], t.x, t.y, pc.p);
+        v[u][r] = tw_mul<AS>(v[u][r], t.x, t.y, pc.p);
       }
     }
   }
@@ -167,7 +212,7 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
   }
 }
 
-template <int LOGR, bool PAD, int U>
+template <int LOGR, bool PAD, int U, int AS>
 __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ itw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
@@ -182,17 +227,17 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
   }
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    if (logSR > 0 && jj[u] != 0) {
+    if (logSR > 0) {
       const uint32_t jo = jj[u] * (uint32_t)sizeof(uint2);
       const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, (uint32_t)R << logSR);
 #pragma unroll
       for (int k1 = 1; k1 < R; k1++) {
         const uint2 t = tw_at(rs, (uint32_t)k1, logSR, jo);
         const int r = brev_c(k1, LOGR);
-        v[u][r] = mul_tw(v[u][r], t.x, t.y, pc.p);
+        v[u][r] = tw_mul<AS>(v[u][r], t.x, t.y, pc.p);
       }
     }
-    dft_inv<LOGR>(v[u], pc);
+    dft_inv<LOGR, AS>(v[u], pc);
   }
 #pragma unroll
   for (int u = 0; u < U; u++) {
@@ -203,22 +248,22 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
 
 // Thread `tid` of the `nthr` threads that share the tile (the workgroup, or
 // one prime's part of a workgroup that holds several tiles).
-template <int LOGR, bool PAD>
+template <int LOGR, bool PAD, int AS>
 __device__ __forceinline__ void pass_fwd(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
                                          const uint2* __restrict__ tw, const PrimeC& pc, uint32_t tid,
                                          uint32_t nthr) {
   uint32_t g = tid;
-  for (; g + nthr < ngroups; g += 2 * nthr) groups_fwd<LOGR, PAD, 2>(lds, g, nthr, logSR, logC, tw, pc);
-  for (; g < ngroups; g += nthr) groups_fwd<LOGR, PAD, 1>(lds, g, nthr, logSR, logC, tw, pc);
+  for (; g + nthr < ngroups; g += 2 * nthr) groups_fwd<LOGR, PAD, 2, AS>(lds, g, nthr, logSR, logC, tw, pc);
+  for (; g < ngroups; g += nthr) groups_fwd<LOGR, PAD, 1, AS>(lds, g, nthr, logSR, logC, tw, pc);
 }
 
-template <int LOGR, bool PAD>
+template <int LOGR, bool PAD, int AS>
 __device__ __forceinline__ void pass_inv(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
                                          const uint2* __restrict__ itw, const PrimeC& pc, uint32_t tid,
                                          uint32_t nthr) {
   uint32_t g = tid;
-  for (; g + nthr < ngroups; g += 2 * nthr) groups_inv<LOGR, PAD, 2>(lds, g, nthr, logSR, logC, itw, pc);
-  for (; g < ngroups; g += nthr) groups_inv<LOGR, PAD, 1>(lds, g, nthr, logSR, logC, itw, pc);
+  for (; g + nthr < ngroups; g += 2 * nthr) groups_inv<LOGR, PAD, 2, AS>(lds, g, nthr, logSR, logC, itw, pc);
+  for (; g < ngroups; g += nthr) groups_inv<LOGR, PAD, 1, AS>(lds, g, nthr, logSR, logC, itw, pc);
 }
 
 // radix of the pass at sub-problem size 2^logS
@@ -249,7 +294,7 @@ __device__ __forceinline__ void pass_sync(int logSmall, uint32_t logC) {
 // return (logC = 0) thread g of the last pass holds the outputs at
 // [16 g, 16 g + 16) of its groups; the caller synchronises before other
 // threads read them.
-template <bool PAD>
+template <bool PAD, int AS = 0>
 __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ tws, const PrimeC& pc, uint32_t tid = threadIdx.x,
                              uint32_t nthr = blockDim.x) {
@@ -259,10 +304,10 @@ __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t t
     const uint32_t logSR = (uint32_t)(logS - lr);
     const uint2* tw = tws + tws_off(logS);
     switch (lr) {
-      case 1: pass_fwd<1, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      case 2: pass_fwd<2, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      case 3: pass_fwd<3, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      default: pass_fwd<4, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 1: pass_fwd<1, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 2: pass_fwd<2, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 3: pass_fwd<3, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      default: pass_fwd<4, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
     }
     logS -= lr;
     if (logS > 0) {
@@ -275,7 +320,7 @@ __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t t
 // Inverse; the caller synchronises before the first pass as needed (with
 // logC = 0 the first pass reads [16 g, 16 g + 16) in thread g) and the
 // transform ends with a workgroup barrier.
-template <bool PAD>
+template <bool PAD, int AS = 0>
 __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ itws, const PrimeC& pc, uint32_t tid = threadIdx.x,
                              uint32_t nthr = blockDim.x) {
@@ -283,7 +328,7 @@ __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t t
   // 2^4, 2^8, ... first, the (possibly smaller-radix) pass of size 2^logS last
   const int lr0 = pass_logr(logS);
   for (int ls = 4; ls <= logS - lr0; ls += 4) {
-    pass_inv<4, PAD>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc, tid, nthr);
+    pass_inv<4, PAD, AS>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc, tid, nthr);
     if (ls + 4 <= logS - lr0 || lr0 == 4) pass_sync(ls, logC);   // the next pass has radix 16
     else __syncthreads();
   }
@@ -292,10 +337,10 @@ __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t t
     const uint32_t logSR = (uint32_t)(logS - lr0);
     const uint2* tw = itws + tws_off(logS);
     switch (lr0) {
-      case 1: pass_inv<1, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      case 2: pass_inv<2, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      case 3: pass_inv<3, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      default: pass_inv<4, PAD>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 1: pass_inv<1, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 2: pass_inv<2, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      case 3: pass_inv<3, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      default: pass_inv<4, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
     }
   }
   __syncthreads();
@@ -337,6 +382,40 @@ struct NttTables {
   const uint32_t* itw2hi;
 };
 
+// A limb entering a transform: reduced (set 0) or brought into [0, 2q) (set 1).
+template <int AS>
+__device__ __forceinline__ uint32_t in_limb(uint32_t x, uint32_t p) {
+  if constexpr (AS == 0) return reduce_limb(x, p);
+  else return limb_lazy(x, p);
+}
+// Pointwise product of two forward outputs times the scale pair sc (2^32/N):
+// exact (set 0) or in (0, 2q) (set 1).
+template <int AS>
+__device__ __forceinline__ uint32_t pointwise(uint32_t x, uint32_t y, uint2 sc, const PrimeC& pc) {
+  if constexpr (AS == 0) return mul_tw(mont_mul(x, y, pc.p, pc.pinv), sc.x, sc.y, pc.p);
+  else return mont_lazy(mont_mul_lazy(x, y, pc.p, pc.pinv), sc.x, sc.y, pc.p);
+}
+// Data times a computed twiddle (Montgomery pair, fully reduced): exact
+// (set 0) or in (0, 2q) for any 32-bit input (set 1).
+template <int AS>
+__device__ __forceinline__ uint32_t data_tw(uint32_t x, uint2 w, uint32_t p) {
+  if constexpr (AS == 0) return mul_tw(x, w.x, w.y, p);
+  else return mont_lazy(x, w.x, w.y, p);
+}
+// Pointwise product without the scale (the row kernel applies it with the
+// inverse twiddles): x y / 2^32, exact (set 0) or in (0, 2q) (set 1).
+template <int AS>
+__device__ __forceinline__ uint32_t pointwise_raw(uint32_t x, uint32_t y, const PrimeC& pc) {
+  if constexpr (AS == 0) return mont_mul(x, y, pc.p, pc.pinv);
+  else return mont_mul_lazy(x, y, pc.p, pc.pinv);
+}
+// An inverse-transform output leaving as a residue in [0, p).
+template <int AS>
+__device__ __forceinline__ uint32_t out_residue(uint32_t x, uint32_t p) {
+  if constexpr (AS == 0) return x;
+  else return red4(x, p);
+}
+
 // ---------------------------------------------------------------------------
 // Whole product in one workgroup, N = 2^logN <= 2^LOGT <= 2^14.
 // Writes res[prime][r_off + j] = (a*b)_j mod p for j < la+lb.
@@ -350,7 +429,7 @@ struct NttTables {
 // is 3 x tiles workgroups; workgroup ids are renumbered so that each XCD takes
 // a contiguous run of (tile, prime) pairs: the three primes of a tile run one
 // after another on one XCD and read the operands once from HBM into its L2.
-template <int LOGT, int BMODE>
+template <int LOGT, int BMODE, int AS>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
 k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
           uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb, uint2 scale0, uint2 scale1, uint2 scale2,
@@ -360,7 +439,7 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   __shared__ MulDesc ds[64];
   const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t prime = wid % CAT_NPRIMES;
-  const PrimeC& pc = c_primes[prime];
+  const PrimeC& pc = primec<AS>(prime);
   const uint32_t p = pc.p;
   const uint32_t N = 1u << logN;
   const uint32_t per = TT >> logN;                 // products per tile (<= 64)
@@ -378,9 +457,9 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   if constexpr (BMODE == 1) {
     const MulDesc d = ds[0];
     for (uint32_t t = threadIdx.x; t < N; t += blockDim.x)
-      lds[lds_pad(t)] = reduce_limb(t < d.lb ? bin[d.b_off + t] : 0u, p);
+      lds[lds_pad(t)] = in_limb<AS>(t < d.lb ? bin[d.b_off + t] : 0u, p);
     __syncthreads();
-    ntt_fwd_tile<true>(lds, logN, N, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logN, N, 0, tws, pc);
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < N; t += blockDim.x) fb[(size_t)prime * N + t] = lds[lds_pad(t)];
     return;
@@ -406,8 +485,8 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
 #pragma unroll
     for (int i = 0; i < 16; i++) {
       const uint32_t t = threadIdx.x + i * NT;
-      lds[lds_pad(t)] = reduce_limb(xa[i], p);
-      lds[lds_pad(TT + t)] = BMODE == 2 ? xb[i] : reduce_limb(xb[i], p);
+      lds[lds_pad(t)] = in_limb<AS>(xa[i], p);
+      lds[lds_pad(TT + t)] = BMODE == 2 ? xb[i] : in_limb<AS>(xb[i], p);
     }
   }
   // slots past T of a partial tile repeat the last live slot; their
@@ -415,12 +494,12 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   __syncthreads();
   // A occupies [0, T), B [TT, TT + T); transform both as one tile
   if constexpr (BMODE == 2) {
-    ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
   } else if (T == TT) {
-    ntt_fwd_tile<true>(lds, logN, 2 * TT, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logN, 2 * TT, 0, tws, pc);
   } else {
-    ntt_fwd_tile<true>(lds, logN, T, 0, tws, pc);
-    ntt_fwd_tile<true>(lds + lds_pad(TT), logN, T, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds + lds_pad(TT), logN, T, 0, tws, pc);
   }
   // pointwise product on the 16 positions whose forward outputs this thread
   // wrote last (A and B alike), which the first inverse pass reads back in the
@@ -431,16 +510,16 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
     for (int k = 0; k < 16; k++) {
       const uint32_t t = 16 * threadIdx.x + k;
       const uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(TT + t)];
-      lds[lds_pad(t)] = mul_tw(mont_mul(x, y, p, pc.pinv), sc.x, sc.y, p);
+      lds[lds_pad(t)] = pointwise<AS>(x, y, sc, pc);
     }
   }
-  ntt_inv_tile<true>(lds, logN, T, 0, itws, pc);
+  ntt_inv_tile<true, AS>(lds, logN, T, 0, itws, pc);
   uint32_t* out = res + (size_t)prime * res_stride;
   for (uint32_t m = 0; m < cnt; m++) {
     const MulDesc d = ds[m];
     const uint32_t L = d.la + d.lb;
     for (uint32_t j = threadIdx.x; j < L; j += blockDim.x)
-      out[d.r_off + j] = j < N ? lds[lds_pad((m << logN) + j)] : 0u;
+      out[d.r_off + j] = j < N ? out_residue<AS>(lds[lds_pad((m << logN) + j)], p) : 0u;
   }
 }
 
@@ -490,7 +569,7 @@ struct PassGeom {
   }
 };
 
-template <int LOGT>
+template <int LOGT, int AS>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int plogL, int op_base,
            const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin, uint32_t* __restrict__ F,
@@ -500,7 +579,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
   // first pass read the same operand words
   const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t prime = wid % CAT_NPRIMES, op = op_base + blockIdx.z;
-  const PrimeC& pc = c_primes[prime];
+  const PrimeC& pc = primec<AS>(prime);
   const uint32_t p = pc.p;
   uint64_t m, base;
   uint32_t j0;
@@ -528,7 +607,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
 #pragma unroll
       for (int i = 0; i < COL_BATCH; i++) {
         const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
-        if (t < T) lds[t] = reduce_limb(v[i], p);
+        if (t < T) lds[t] = in_limb<AS>(v[i], p);
       }
     }
   } else {
@@ -538,7 +617,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
     uint2 w = make_uint2(0, 0), R = make_uint2(0, 0);
     if (pre) {
       const uint32_t fr = out_freq((uint32_t)(base >> pg.logS) & ((1u << plogL) - 1), plogL);
-      const uint32_t ysh = CAT_MAX_LOGN - plogS, ymask = (1u << CAT_MAX_LOGN) - 1;
+      const uint32_t ysh = tw_logn<AS>() - plogS, ymask = (1u << tw_logn<AS>()) - 1;
       const uint2* plo = tb.tw2lo + (size_t)prime * TW2_LO;
       const uint32_t* phi = tb.tw2hi + (size_t)prime * TW2_HI;
       const uint32_t jt = ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1));
@@ -557,7 +636,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
       for (int i = 0; i < COL_BATCH; i++) {
         const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
         if (pre) {
-          v[i] = mul_tw(v[i], w.x, w.y, p);
+          v[i] = data_tw<AS>(v[i], w, p);
           w.x = mul_tw(w.x, R.x, R.y, p);
           w.y = w.x * pc.pinv;
         }
@@ -566,7 +645,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
     }
   }
   __syncthreads();
-  ntt_fwd_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
+  ntt_fwd_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
   __syncthreads();
   if (!tw) {
     // the pass next to the rows: k_row applies this pass's twiddles
@@ -576,7 +655,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
   }
   const uint2* lo = tb.tw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.tw2hi + (size_t)prime * TW2_HI;
-  const uint32_t ysh = CAT_MAX_LOGN - pg.logS;
+  const uint32_t ysh = tw_logn<AS>() - pg.logS;
   for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
     uint2 l[COL_BATCH];
     uint32_t h[COL_BATCH];
@@ -587,7 +666,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
       const uint32_t q = tc >> pg.logC, j = j0 + (tc & (C - 1));
       // omega_S^(j f(q)) = omega_{2^27}^y, y = (j f(q) 2^(27 - logS)) mod 2^27:
       // the bits of j f(q) above 2^32 do not reach y
-      const uint32_t y = ((j * out_freq(q, pg.logL)) << ysh) & ((1u << CAT_MAX_LOGN) - 1);
+      const uint32_t y = ((j * out_freq(q, pg.logL)) << ysh) & ((1u << tw_logn<AS>()) - 1);
       l[i] = lo[y & (TW2_LO - 1)];
       h[i] = hi[y >> TW2_LO_BITS];
     }
@@ -597,13 +676,13 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
       if (t < T) {
         const uint32_t q = t >> pg.logC, j = j0 + (t & (C - 1));
         const uint32_t w = mul_tw(h[i], l[i].x, l[i].y, p);
-        f[base + ((uint64_t)q << logSig) + j] = mul_tw(lds[t], w, w * pc.pinv, p);
+        f[base + ((uint64_t)q << logSig) + j] = data_tw<AS>(lds[t], make_uint2(w, w * pc.pinv), p);
       }
     }
   }
 }
 
-template <int LOGT>
+template <int LOGT, int AS>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int plogL, uint32_t* __restrict__ F,
            uint32_t* __restrict__ res, uint64_t res_stride, NttTables tb) {
@@ -611,7 +690,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   __shared__ uint32_t fq[1u << NTT_COL_MAXL];    // frequency at each output row
   const uint32_t T = 1u << (pg.logL + pg.logC);
   const uint32_t prime = blockIdx.y;
-  const PrimeC& pc = c_primes[prime];
+  const PrimeC& pc = primec<AS>(prime);
   const uint32_t p = pc.p;
   uint64_t m, base;
   uint32_t j0;
@@ -622,7 +701,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   uint32_t* f = F + ((m * 3 + prime) * 2 + 0) * N;
   const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
-  const uint32_t ysh = CAT_MAX_LOGN - pg.logS;
+  const uint32_t ysh = tw_logn<AS>() - pg.logS;
   if (!tw) {
     // the pass next to the rows: k_row applied this pass's twiddles
     for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
@@ -650,7 +729,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
       const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
       const uint32_t tc = t < T ? t : T - 1;
       const uint32_t q = tc >> pg.logC, j = j0 + (tc & (C - 1));
-      const uint32_t y = ((j * fq[q]) << ysh) & ((1u << CAT_MAX_LOGN) - 1);
+      const uint32_t y = ((j * fq[q]) << ysh) & ((1u << tw_logn<AS>()) - 1);
       l[i] = lo[y & (TW2_LO - 1)];
       h[i] = hi[y >> TW2_LO_BITS];
       v[i] = f[base + ((uint64_t)q << logSig) + j];
@@ -660,13 +739,13 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
       const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
       if (t < T) {
         const uint32_t w = mul_tw(h[i], l[i].x, l[i].y, p);
-        lds[t] = mul_tw(v[i], w, w * pc.pinv, p);
+        lds[t] = data_tw<AS>(v[i], make_uint2(w, w * pc.pinv), p);
       }
     }
   }
   }
   __syncthreads();
-  ntt_inv_tile<false>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  ntt_inv_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   if (!last) {
     if (!post) {
       for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
@@ -676,14 +755,14 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
     // post: the inverse twiddles of the previous (outer) pass, at the same
     // positions the forward load of this pass took them, by the same steps
     const uint32_t fr = out_freq((uint32_t)(base >> pg.logS) & ((1u << plogL) - 1), plogL);
-    const uint32_t ysh2 = CAT_MAX_LOGN - plogS, ymask = (1u << CAT_MAX_LOGN) - 1;
+    const uint32_t ysh2 = tw_logn<AS>() - plogS, ymask = (1u << tw_logn<AS>()) - 1;
     const uint2* plo = tb.itw2lo + (size_t)prime * TW2_LO;
     const uint32_t* phi = tb.itw2hi + (size_t)prime * TW2_HI;
     const uint32_t jt = ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1));
     uint2 w = tw2(plo, phi, ((jt * fr) << ysh2) & ymask, pc);
     const uint2 R = tw2(plo, phi, ((((NTT_COL_THREADS >> pg.logC) << logSig) * fr) << ysh2) & ymask, pc);
     for (uint32_t t = threadIdx.x; t < T; t += NTT_COL_THREADS) {
-      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = mul_tw(lds[t], w.x, w.y, p);
+      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = data_tw<AS>(lds[t], w, p);
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
     }
@@ -695,7 +774,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   const uint64_t L = (uint64_t)d.la + d.lb;
   for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
     const uint64_t j = base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1));
-    if (j < L) out[j] = lds[t];
+    if (j < L) out[j] = out_residue<AS>(lds[t], p);
   }
   // coefficient positions in [N, L) (only when L = N + 1) are zero
   if (base == 0 && j0 == 0)
@@ -703,7 +782,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
 }
 
 // Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
-template <int LOGT>
+template <int LOGT, int AS>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
 // bmode 0: both operands per product.  A stage whose second operand is the
 // same for every product computes that operand's row transforms once:
@@ -715,7 +794,7 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
   constexpr uint32_t TT = 1u << LOGT;
   __shared__ uint32_t lds[lds_pad(2 * TT)];
   const uint32_t prime = blockIdx.y;
-  const PrimeC& pc = c_primes[prime];
+  const PrimeC& pc = primec<AS>(prime);
   const uint32_t p = pc.p;
   const int logR1 = logN - logM;
   const uint32_t M = 1u << logM;
@@ -731,7 +810,7 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
   // inverse on the way back.  A thread's positions j = tid + i NT form a
   // geometric sequence: w_i = w_0 R^i, R = omega_S^(NT f).
   const uint32_t fr = out_freq(q & ((1u << logLl) - 1), logLl);
-  const uint32_t ysh = CAT_MAX_LOGN - logSl, ymask = (1u << CAT_MAX_LOGN) - 1;
+  const uint32_t ysh = tw_logn<AS>() - logSl, ymask = (1u << tw_logn<AS>()) - 1;
   const uint2* flo = tb.tw2lo + (size_t)prime * TW2_LO;
   const uint32_t* fhi = tb.tw2hi + (size_t)prime * TW2_HI;
   uint2 w = tw2(flo, fhi, ((threadIdx.x * fr) << ysh) & ymask, pc);
@@ -739,19 +818,19 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
   const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
   if (bmode == 1) {
     for (uint32_t t = threadIdx.x; t < M; t += NT) {
-      lds[lds_pad(t)] = mul_tw(fb[t], w.x, w.y, p);
+      lds[lds_pad(t)] = data_tw<AS>(fb[t], w, p);
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
     }
     __syncthreads();
-    ntt_fwd_tile<true>(lds, logM, M, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logM, M, 0, tws, pc);
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < M; t += NT) fb[t] = lds[lds_pad(t)];
     return;
   }
   if (bmode == 2) {
     for (uint32_t t = threadIdx.x; t < M; t += NT) {
-      lds[lds_pad(t)] = mul_tw(fa[t], w.x, w.y, p);
+      lds[lds_pad(t)] = data_tw<AS>(fa[t], w, p);
       lds[lds_pad(M + t)] = fb[t];
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
@@ -766,21 +845,21 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-      lds[lds_pad(threadIdx.x + i * NT)] = mul_tw(va[i], w.x, w.y, p);
-      lds[lds_pad(TT + threadIdx.x + i * NT)] = mul_tw(vb[i], w.x, w.y, p);
+      lds[lds_pad(threadIdx.x + i * NT)] = data_tw<AS>(va[i], w, p);
+      lds[lds_pad(TT + threadIdx.x + i * NT)] = data_tw<AS>(vb[i], w, p);
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
     }
   } else {
     for (uint32_t t = threadIdx.x; t < M; t += NT) {
-      lds[lds_pad(t)] = mul_tw(fa[t], w.x, w.y, p);
-      lds[lds_pad(M + t)] = mul_tw(fb[t], w.x, w.y, p);
+      lds[lds_pad(t)] = data_tw<AS>(fa[t], w, p);
+      lds[lds_pad(M + t)] = data_tw<AS>(fb[t], w, p);
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
     }
   }
   __syncthreads();
-  ntt_fwd_tile<true>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
+  ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
   if (M == TT) {
     // thread g wrote A and B at [16 g, 16 g + 16): pointwise in place, and the
@@ -789,17 +868,17 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     for (int k = 0; k < 16; k++) {
       const uint32_t t = 16 * threadIdx.x + k;
       const uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
-      lds[lds_pad(t)] = mont_mul(x, y, p, pc.pinv);
+      lds[lds_pad(t)] = pointwise_raw<AS>(x, y, pc);
     }
   } else {
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < M; t += blockDim.x) {
       uint32_t x = lds[lds_pad(t)], y = lds[lds_pad(M + t)];
-      lds[lds_pad(t)] = mont_mul(x, y, p, pc.pinv);
+      lds[lds_pad(t)] = pointwise_raw<AS>(x, y, pc);
     }
     __syncthreads();
   }
-  ntt_inv_tile<true>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  ntt_inv_tile<true, AS>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   const uint2* ilo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* ihi = tb.itw2hi + (size_t)prime * TW2_HI;
   // the pointwise scale (2^32 / N) rides on the inverse twiddles: every step
@@ -809,7 +888,7 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
   wi.y = wi.x * pc.pinv;
   const uint2 Ri = tw2(ilo, ihi, ((NT * fr) << ysh) & ymask, pc);
   for (uint32_t t = threadIdx.x; t < M; t += NT) {
-    fa[t] = mul_tw(lds[lds_pad(t)], wi.x, wi.y, p);
+    fa[t] = data_tw<AS>(lds[lds_pad(t)], wi, p);
     wi.x = mul_tw(wi.x, Ri.x, Ri.y, p);
     wi.y = wi.x * pc.pinv;
   }
@@ -817,9 +896,11 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
 
 // ---------------------------------------------------------------------------
 // Garner CRT of the three residues into V = x0 + p0*x1 + p0*p1*x2 < 2^96.
+template <int AS = 0>
 __device__ __forceinline__ void garner3(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t& v0, uint32_t& v1,
                                         uint32_t& v2) {
-  const uint32_t P1 = c_primes[1].p, P2 = c_primes[2].p;
+  const CrtC& c_crt = crtc<AS>();
+  const uint32_t P1 = primec<AS>(1).p, P2 = primec<AS>(2).p;
   const uint32_t x0 = r0;
   const uint32_t x1 = mul_tw(sub_mod(r1, x0, P1), c_crt.c01, c_crt.c01q, P1);
   const uint32_t t = mul_tw(x1, c_crt.p0m2, c_crt.p0m2q, P2);
@@ -922,7 +1003,7 @@ struct CrtWords {
 // Garner's recombination of the three residues, or (RAW) the three words
 // themselves when they already hold V = v0 + v1 2^32 + v2 2^64 (exact column
 // sums of a schoolbook product).
-template <bool RAW>
+template <bool RAW, int AS>
 __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __restrict__ r0,
                                           const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
                                           uint64_t kb, uint32_t (*xv)[9], uint32_t* tmp, uint64_t* u, bool* Gt,
@@ -973,7 +1054,7 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
           v1[i + 3] = x1[i];
           v2[i + 3] = x2[i];
         } else {
-          garner3(x0[i], x1[i], x2[i], v0[i + 3], v1[i + 3], v2[i + 3]);
+          garner3<AS>(x0[i], x1[i], x2[i], v0[i + 3], v1[i + 3], v2[i + 3]);
         }
       }
       else { v0[i + 3] = 0; v1[i + 3] = 0; v2[i + 3] = 0; }
@@ -994,7 +1075,7 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
         a1 = y1;
         a2 = y2;
       } else {
-        garner3(y0, y1, y2, a0, a1, a2);
+        garner3<AS>(y0, y1, y2, a0, a1, a2);
       }
     }
     xv[0][3 * tid + 0] = a0;
@@ -1039,7 +1120,7 @@ __device__ __forceinline__ uint32_t crt_block_pair(const uint32_t* tmp) {
   return bG | (bP << 1);
 }
 
-template <bool RAW>
+template <bool RAW, int AS>
 __global__ void __launch_bounds__(CAT_CRT_THREADS)
 k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_t* __restrict__ out, uint32_t nblk,
       uint32_t* __restrict__ flags, uint32_t epoch, uint32_t polls, CopyList tails, const uint32_t* __restrict__ tin,
@@ -1061,7 +1142,7 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
   const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
   uint64_t u[CAT_CRT_E];
   bool G, P;
-  crt_local<RAW>(sg, r0, r1, r2, kb, xv, tmp, u, &G, &P);
+  crt_local<RAW, AS>(sg, r0, r1, r2, kb, xv, tmp, u, &G, &P);
   const uint32_t own = crt_block_pair(tmp);
   if (tid == 0)
     __hip_atomic_store(flags + b, (epoch << 3) | (own << 1) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1089,7 +1170,7 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
       // not published yet: recompute block k's pair from its residues
       uint64_t u2[CAT_CRT_E];
       bool G2, P2;
-      crt_local<RAW>(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      crt_local<RAW, AS>(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
       pair = crt_block_pair(tmp2);
     }
     if (pair & 1u) { cin = 1; done = true; }           // block k generates a carry

@@ -511,13 +511,20 @@ __global__ void __launch_bounds__(RES_T) k_residues(const uint32_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Twiddle tables.  roots[prime][s] = omega_{2^s} in Montgomery form.
+// Twiddle tables.  roots[prime][s] = omega_{2^s} in Montgomery form, for
+// each prime set (the second set has roots up to 2^CAT_LAZY_MAX_LOGN).
 struct RootsC {
   uint32_t r[CAT_NPRIMES][CAT_MAX_LOGN + 1];     // forward, Montgomery form
   uint32_t ir[CAT_NPRIMES][CAT_MAX_LOGN + 1];    // inverse
   uint32_t one[CAT_NPRIMES];                     // R mod p
 };
 __constant__ RootsC c_roots;
+__constant__ RootsC c_roots1;
+template <int AS>
+__device__ __forceinline__ const RootsC& rootsc() {
+  if constexpr (AS == 0) return c_roots;
+  else return c_roots1;
+}
 
 __device__ __forceinline__ uint32_t mont_pow(uint32_t b, uint64_t e, uint32_t one, uint32_t p, uint32_t pinv) {
   uint32_t r = one;
@@ -529,12 +536,21 @@ __device__ __forceinline__ uint32_t mont_pow(uint32_t b, uint64_t e, uint32_t on
   return r;
 }
 __device__ __forceinline__ uint2 tw_pair(uint32_t w, uint32_t pinv) { return make_uint2(w, w * pinv); }
+// Shoup pair of the value whose Montgomery form is w: (W, floor(W 2^32 / p))
+__device__ __forceinline__ uint2 shoup_pair(uint32_t w, uint32_t p, uint32_t pinv) {
+  const uint32_t W = mont_mul(w, 1u, p, pinv);
+  return make_uint2(W, (uint32_t)(((uint64_t)W << 32) / p));
+}
 
-// Pass tables: for s = 1..12, S = 2^s, radix R = 2^pass_logr(s), entry
-// (k1, j2) at tws_off(s) + (k1 << (s - r)) + j2 = omega_S^{+-j2*k1}.
+// Pass tables: for s = 1..14, S = 2^s, radix R = 2^pass_logr(s), entry
+// (k1, j2) at tws_off(s) + (k1 << (s - r)) + j2 = omega_S^{+-j2*k1}:
+// Montgomery pairs (set 0) or Shoup pairs (set 1).
+template <int AS>
 __global__ void k_build_tws(uint2* __restrict__ tws, uint2* __restrict__ itws) {
   const uint32_t prime = blockIdx.y;
-  const uint32_t p = c_primes[prime].p, pinv = c_primes[prime].pinv;
+  const PrimeC& pc = primec<AS>(prime);
+  const RootsC& rc = rootsc<AS>();
+  const uint32_t p = pc.p, pinv = pc.pinv;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < TWS_ENTRIES; i += gridDim.x * blockDim.x) {
     int s = 1;
     while (tws_off(s + 1) <= i) s++;
@@ -542,25 +558,30 @@ __global__ void k_build_tws(uint2* __restrict__ tws, uint2* __restrict__ itws) {
     const int r = pass_logr(s);
     const uint32_t k1 = li >> (s - r), j2 = li & ((1u << (s - r)) - 1);
     const uint64_t e = (uint64_t)j2 * k1;
-    const uint32_t w = mont_pow(c_roots.r[prime][s], e, c_roots.one[prime], p, pinv);
-    const uint32_t iw = mont_pow(c_roots.ir[prime][s], e, c_roots.one[prime], p, pinv);
-    tws[(size_t)prime * TWS_ENTRIES + i] = tw_pair(w, pinv);
-    itws[(size_t)prime * TWS_ENTRIES + i] = tw_pair(iw, pinv);
+    const uint32_t w = mont_pow(rc.r[prime][s], e, rc.one[prime], p, pinv);
+    const uint32_t iw = mont_pow(rc.ir[prime][s], e, rc.one[prime], p, pinv);
+    tws[(size_t)prime * TWS_ENTRIES + i] = AS == 0 ? tw_pair(w, pinv) : shoup_pair(w, p, pinv);
+    itws[(size_t)prime * TWS_ENTRIES + i] = AS == 0 ? tw_pair(iw, pinv) : shoup_pair(iw, p, pinv);
   }
 }
 
-// Two-level tables of omega_{2^27}: lo[i] = omega^i (i < 2^14, Montgomery
-// pairs), hi[i] = omega^{i*2^14} (i < 2^13, Montgomery form); and the inverse.
+// Two-level tables of omega = omega_{2^tw_logn}: lo[i] = omega^i (i < 2^14,
+// Montgomery pairs), hi[i] = omega^{i*2^14} (i < 2^(tw_logn - 14), Montgomery
+// form); and the inverse.
+template <int AS>
 __global__ void k_build_tw2(uint2* __restrict__ lo, uint32_t* __restrict__ hi, uint2* __restrict__ ilo,
                             uint32_t* __restrict__ ihi) {
   const uint32_t prime = blockIdx.y;
-  const uint32_t p = c_primes[prime].p, pinv = c_primes[prime].pinv;
-  const uint32_t one = c_roots.one[prime];
-  const uint32_t r = c_roots.r[prime][CAT_MAX_LOGN], ir = c_roots.ir[prime][CAT_MAX_LOGN];
+  const PrimeC& pc = primec<AS>(prime);
+  const RootsC& rc = rootsc<AS>();
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  const uint32_t one = rc.one[prime];
+  const uint32_t r = rc.r[prime][tw_logn<AS>()], ir = rc.ir[prime][tw_logn<AS>()];
+  const uint32_t nhi = 1u << (tw_logn<AS>() - TW2_LO_BITS);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < TW2_LO; i += gridDim.x * blockDim.x) {
     lo[(size_t)prime * TW2_LO + i] = tw_pair(mont_pow(r, i, one, p, pinv), pinv);
     ilo[(size_t)prime * TW2_LO + i] = tw_pair(mont_pow(ir, i, one, p, pinv), pinv);
-    if (i < TW2_HI) {
+    if (i < nhi) {
       hi[(size_t)prime * TW2_HI + i] = mont_pow(r, (uint64_t)i << TW2_LO_BITS, one, p, pinv);
       ihi[(size_t)prime * TW2_HI + i] = mont_pow(ir, (uint64_t)i << TW2_LO_BITS, one, p, pinv);
     }

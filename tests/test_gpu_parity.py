@@ -346,6 +346,68 @@ def test_fused_levels_same_bits(cat, logn):
         cat.set_fused_levels(12)
 
 
+@pytest.mark.parametrize("lazy", [0, 12, 23])
+@pytest.mark.parametrize("fused", [0, 12])
+def test_lazy_primes_same_bits(cat, lazy, fused):
+    """Transform products on the three primes below 2^30 with unreduced
+    butterfly ranges give the same products and C(n) as the three primes above
+    2^31: both against the oracle, with all-ones operands (the largest
+    coefficients, which the second set's CRT range must cover), ragged tiles
+    and products of N + 1 limbs, with the lower tree levels fused or not."""
+    try:
+        cat.set_lazy_primes(lazy)
+        cat.set_fused_levels(fused)
+        la, lb, kinds = [], [], []
+        for x, y in [(1, 1), (129, 129), (255, 256), (2047, 2049), (2048, 2048), (2049, 2048), (4095, 2),
+                     (3000, 1100), (4097, 4096), (8192, 8192), (8193, 8192), (5000, 3)]:
+            for k in ["rand", "ones", "zero"]:
+                la.append(x)
+                lb.append(y)
+                kinds.append(k)
+        _say("lazy", lazy, "fused", fused, "edges")
+        _run_batch(cat, la, lb, kinds, "batched", seed=lazy + fused)
+        _run_batch(cat, la, lb, kinds, "plain", seed=lazy + fused + 1)
+        _say("lazy", lazy, "fused", fused, "four-step")
+        _run_batch(cat, [40000, 65536, 70000, 131072, 1 << 17], [30000, 65536, 100, 131071, 1 << 17],
+                   ["rand", "ones", "rand", "ones", "ones"], "batched", seed=9)
+        for n in (300, 5000, 13337, 100000, 1000003):
+            _say("lazy", lazy, "fused", fused, "C", n)
+            got = cat.to_numpy(cat.exact(n, mode="graph"))
+            assert np.array_equal(got, oracle.catalan(n)), (lazy, fused, n)
+        with open(os.path.join(GOLDEN, "oracle_catalan.json")) as f:
+            gold = json.load(f)["10000000"]
+        got = cat.to_numpy(cat.exact(10**7, mode="graph"))
+        assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
+    finally:
+        cat.set_lazy_primes(23)
+        cat.set_fused_levels(12)
+
+
+def _ones_square(a):
+    """(B^a - 1)^2 = B^(2a) - 2 B^a + 1, B = 2^32: limb 0 is 1, limbs 1..a-1
+    are 0, limb a is B - 2 and limbs a+1..2a-1 are B - 1."""
+    c = np.zeros(2 * a, dtype=np.uint32)
+    c[0] = 1
+    c[a] = 0xFFFFFFFE
+    c[a + 1:] = 0xFFFFFFFF
+    return c
+
+
+@pytest.mark.parametrize("a", [1 << 22, (1 << 22) + 1, 1 << 23])
+def test_largest_coefficients_closed_form(cat, a):
+    """The all-ones square has the largest convolution coefficients a product
+    of its size can have, (B - 1)^2 times the overlap; at a = 2^22 (the last
+    size of the primes below 2^30, N = 2^23), 2^22 + 1 and 2^23 (the primes
+    above 2^31) it must still come out exactly, against the closed form."""
+    x = np.full(a, 0xFFFFFFFF, dtype=np.uint32)
+    off = np.array([0, a], dtype=np.uint64)
+    d = cat.from_numpy(x)
+    c, c_off = cat.mul_batched(d, off, d, off, mode="batched")
+    got = cat.to_numpy(c)
+    assert int(c_off[-1]) == 2 * a
+    assert np.array_equal(got, _ones_square(a))
+
+
 def test_mul_batched_is_asynchronous(cat):
     """bigint_mul_batched returns once the products are queued; the device
     check comes from bigint_mul_check.  The same shape again (plan from the
