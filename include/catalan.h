@@ -312,7 +312,10 @@ cat_status bigint_residues(const uint32_t* d_x, size_t n, uint64_t* h_res, void*
 
 /* Statistics of the last catalan_exact / bigint_mul_batched call on this
  * process (host side): number of products, kernel launches (graph nodes count
- * once per kernel), and the sum of la+lb over all products. */
+ * once per kernel), and the sum of la+lb over all products; outer_level is
+ * the level of Q_1's product tree at which R = prod_{e>=2} P_e entered as a
+ * node (-1: C was formed as Q_1 R after the tree; 0 for calls without a
+ * product tree, such as bigint_mul_batched). */
 typedef struct {
   uint64_t products;
   uint64_t launches;
@@ -320,6 +323,8 @@ typedef struct {
   uint64_t n_primes;
   uint32_t levels;
   uint32_t graph_replayed;
+  int32_t outer_level;
+  uint32_t reserved;
 } cat_stats;
 cat_status cat_get_stats(cat_stats* out);
 
@@ -354,6 +359,17 @@ cat_status cat_tune_get(cat_tuning* t);
  * and a carry launch); otherwise 4..12 (default 12).  The result is the same
  * bit for bit either way.  Cached C(n) plans are dropped. */
 cat_status cat_fused_levels_set(uint32_t max_logn);
+
+/* Order of the outer product (Alg. 2: C is the product of the P_e).  With
+ * on = 1 (the default) R = prod_{e>=2} P_e, which is short, enters the
+ * product tree of Q_1 as one more node of 2^j limbs (R, then zero limbs) at
+ * a level j two above the completion of the last group with e >= 2, so that
+ * the top product of that tree is C itself; the powers and R run beside the
+ * tree's levels below j.  It is used when Q_1's tree has at least 2^(j+2)
+ * leaves and the arenas hold 2^j more (otherwise, and with on = 0, C is the
+ * product Q_1 R after the tree).  The result is the same bit for bit either
+ * way.  Cached C(n) plans are dropped.  Returns CAT_EINVAL above 1. */
+cat_status cat_outer_node_set(uint32_t on);
 
 /* Prime set of the transform products (Sec. 3.2: every multiplication of
  * the reconstruction phase).  Products whose transform has at most

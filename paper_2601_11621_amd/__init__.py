@@ -34,7 +34,7 @@ EXPORTS = [
     "factorial_ratio_sizes", "factorial_ratio_factor", "factorial_ratio_exact",
     "prime_power_product_sizes", "prime_power_product", "bigint_compare",
     "decimal_sizes", "bigint_to_decimal", "catalan_exact_noalloc", "catalan_noalloc_max_bytes",
-    "cat_fused_levels_set", "cat_lazy_primes_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
+    "cat_fused_levels_set", "cat_lazy_primes_set", "cat_outer_node_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
     "catalan_batch_sizes", "catalan_batch_begin", "catalan_batch_continue", "catalan_batch_end",
 ]
 
@@ -56,7 +56,8 @@ class cat_tuning(ctypes.Structure):
 class cat_stats(ctypes.Structure):
     _fields_ = [("products", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("product_limbs", ctypes.c_uint64), ("n_primes", ctypes.c_uint64),
-                ("levels", ctypes.c_uint32), ("graph_replayed", ctypes.c_uint32)]
+                ("levels", ctypes.c_uint32), ("graph_replayed", ctypes.c_uint32),
+                ("outer_level", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -129,6 +130,7 @@ def load(path: str = LIB_PATH):
         "catalan_noalloc_max_bytes": ([szp], st),
         "cat_fused_levels_set": ([ctypes.c_uint32], st),
         "cat_lazy_primes_set": ([ctypes.c_uint32], st),
+        "cat_outer_node_set": ([ctypes.c_uint32], st),
         "bigint_decimal_digits_workspace": ([ctypes.c_size_t, szp], st),
         "bigint_decimal_digits": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
         "bigint_mul_check": ([vp, vp], st),
@@ -226,6 +228,13 @@ def set_lazy_primes(max_logn: int = 23) -> None:
     with unreduced butterfly ranges (0: the primes above 2^31 everywhere).
     The results are the same bit for bit either way."""
     _check(load().cat_lazy_primes_set(int(max_logn)), "cat_lazy_primes_set")
+
+
+def set_outer_node(on: bool = True) -> None:
+    """R, the product of the powers P_e with e >= 2, as a node of Q_1's
+    product tree (True) or multiplied onto Q_1 after the tree (False).  The
+    results are the same bit for bit either way."""
+    _check(load().cat_outer_node_set(1 if on else 0), "cat_outer_node_set")
 
 
 def set_tuning(d: Optional[dict]) -> None:

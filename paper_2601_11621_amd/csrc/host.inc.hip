@@ -600,6 +600,17 @@ struct Plan {
   // for both.  fork_count < 0: no side branch.
   int fork_count = -1;
   size_t post_final = 0;
+  // R = prod_{e>=2} P_e as a node of Q_1's tree (rins_j >= 0): from level
+  // rins_j on, group 0 (exponent 1) starts with one node of 2^rins_j limbs
+  // that holds R (zero above its limbs), so the tree's top product is C
+  // itself and no long-by-short product follows.  The other nodes of every
+  // group sit 2^rins_j limbs further into the arenas than in the primes
+  // buffer.  The powers and R run before stage rins_stage[form] (batched,
+  // plain); R's product writes into that level's input arena.
+  int rins_j = -1;
+  int rins_stage[2] = {-1, -1};
+  uint64_t rins_fill_pos = 0, rins_fill_len = 0;   // R's zero limbs above its product
+  uint64_t r_limbs = 0, r_bits = 0;                // size of R's product output, bit bound of R
   void* dev = nullptr;          // device tables (segments, prefixes, descriptors)
   uint64_t products = 0, product_limbs = 0;
   uint32_t levels = 0;
@@ -629,46 +640,76 @@ void cache_graph(std::map<K, hipGraphExec_t>& m, std::vector<K>& order, const K&
   }
 }
 
+// Shape of the forest of one plan: levels until one node per group (J),
+// levels folded into the leaf kernel (0..jleaf-1) and the fused one-workgroup
+// levels jf0..jf1 of the batched form (jf0 < 0: none).
+struct TreeShape {
+  int J = 0, jleaf = 0, jf0 = -1, jf1 = -2;
+};
+TreeShape tree_shape(const Plan& P) {
+  TreeShape sh;
+  uint64_t Kmax_g = 0, leaves = 0;
+  for (uint32_t gi = 0; gi < P.ng; gi++) {
+    Kmax_g = std::max(Kmax_g, P.off[gi + 1] - P.off[gi]);
+    leaves += P.off[gi + 1] - P.off[gi];
+  }
+  const int LF = 5;
+  sh.J = ceil_log2(std::max<uint64_t>(Kmax_g, 1));
+  sh.jleaf = Kmax_g > 1 ? std::min(sh.J, LF) : 0;
+  // the consecutive levels above the leaf and schoolbook levels whose
+  // products are one-workgroup transforms of at most 2^g_fuse_logn coefficients
+  for (int j = std::max(sh.jleaf, 3); j < sh.J && j + 1 <= (int)g_fuse_logn && leaves <= FUSE_MAX_LEAVES; j++) {
+    if (classify2(1ull << j, 1ull << j).cls == CLS_LDS) {
+      if (sh.jf0 < 0) sh.jf0 = j;
+      sh.jf1 = j;
+    } else if (sh.jf0 >= 0) {
+      break;
+    }
+  }
+  return sh;
+}
+
 // Forest levels of the product trees over the groups (one tree per group).
-// out(j) = A for even j, B for odd j; in(0) = primes.
+// out(j) = A for even j, B for odd j; in(0) = primes.  Node positions: group
+// g's leaf k sits at off[g] + k in the primes buffer and at D + off[g] + k in
+// the arenas, D = 2^rins_j when R is a node of Q_1's tree (else 0); from
+// level rins_j on group 0 covers [0, D + K_0): R's node first.
 void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   std::vector<Stage>& st = batched ? P.batched : P.plain;
   const uint32_t ng = P.ng;
   auto out_of = [&](int j) -> uint64_t { return (j % 2 == 0) ? Ly.arenaA : Ly.arenaB; };
   auto in_of = [&](int j) -> uint64_t { return j == 0 ? Ly.primes : out_of(j - 1); };
-  uint64_t Kmax_g = 0;
-  for (uint32_t gi = 0; gi < ng; gi++) Kmax_g = std::max(Kmax_g, P.off[gi + 1] - P.off[gi]);
+  const int jR = P.rins_j;
+  const uint64_t D = jR >= 0 ? (1ull << jR) : 0;
+  // first leaf and leaf count of group g at level j (input side)
+  auto gpos = [&](uint32_t gi, int j) -> uint64_t {
+    if (j == 0) return P.off[gi];
+    if (jR >= 0 && gi == 0 && j >= jR) return 0;
+    return D + P.off[gi];
+  };
+  auto gK = [&](uint32_t gi, int j) -> uint64_t {
+    const uint64_t K = P.off[gi + 1] - P.off[gi];
+    return (jR >= 0 && gi == 0 && j >= jR) ? K + D : K;
+  };
+  const TreeShape sh = tree_shape(P);
   const int LF = 5;
-  const int J = ceil_log2(std::max<uint64_t>(Kmax_g, 1));   // levels until one node per group
-  // levels folded into the leaf kernel of the batched form
-  const int jleaf = Kmax_g > 1 ? std::min(J, LF) : 0;
-  // levels jf0..jf1 of the batched form run as one fused launch: the
-  // consecutive levels above the leaf and schoolbook levels whose products
-  // are one-workgroup transforms of at most 2^g_fuse_logn coefficients
-  int jf0 = -1, jf1 = -2;
-  uint64_t leaves = 0;
-  for (uint32_t gi = 0; gi < ng; gi++) leaves += P.off[gi + 1] - P.off[gi];
-  for (int j = std::max(jleaf, 3); j < J && j + 1 <= (int)g_fuse_logn && leaves <= FUSE_MAX_LEAVES; j++) {
-    if (classify2(1ull << j, 1ull << j).cls == CLS_LDS) {
-      if (jf0 < 0) jf0 = j;
-      jf1 = j;
-    } else if (jf0 >= 0) {
-      break;
-    }
-  }
+  const int jleaf = sh.jleaf, jf0 = sh.jf0, jf1 = sh.jf1;
+  int J = sh.J;
+  if (jR >= 0) J = std::max(J, ceil_log2(gK(0, jR)));
   // Q_e is complete after level jdone - 1 (at least the leaf levels), in
   // in_of(jdone); the plain form carries early roots up to the same place.
   // A root completed inside the fused levels is where the fused launch
   // leaves it, in in_of(jf1 + 1), in both forms.
   int jdone[CAT_MAX_GROUPS];
   for (uint32_t gi = 0; gi < ng; gi++) {
-    jdone[gi] = std::max(ceil_log2(P.off[gi + 1] - P.off[gi]), jleaf);
+    jdone[gi] = std::max(ceil_log2(gK(gi, jR >= 0 ? J : 0)), jleaf);
     if (jf0 >= 0 && jdone[gi] > jf0 && jdone[gi] <= jf1 + 1) jdone[gi] = jf1 + 1;
-    P.root[gi] = in_of(jdone[gi]) + P.off[gi];
+    P.root[gi] = in_of(jdone[gi]) + gpos(gi, jdone[gi]);
   }
+  P.rins_stage[batched ? 0 : 1] = -1;
   int jstart = 0;
-  if (batched && Kmax_g > 1) {
-    // leaf packing covers levels 0..LF-1
+  if (batched && sh.J > 0) {
+    // leaf packing covers levels 0..LF-1 (reads the primes, writes the arena)
     Stage s;
     s.is_leaf = true;
     s.leaf.ngroups = ng;
@@ -684,7 +725,7 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
     s.leaf_nodes = nodes;
     s.a_base = Ly.primes;
     // the buffer the pairwise levels would have written last
-    s.c_base = out_of(jleaf - 1);
+    s.c_base = out_of(jleaf - 1) + D;
     for (uint32_t gi = 0; gi < ng; gi++) {
       const uint64_t K = P.off[gi + 1] - P.off[gi];
       // products inside the packed levels: K - nodes
@@ -695,9 +736,10 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   }
   int j = jstart;
   for (; j < J; j++) {
+    if (jR >= 0 && j == jR) P.rins_stage[batched ? 0 : 1] = (int)st.size();
     if (batched && j == jf0) {
       // the fused levels: one workgroup per 2^FT_LOGT leaves of every group
-      // that still has products there
+      // that still has products there (below rins_j: positions D + off)
       Stage s;
       s.is_fused = true;
       s.jfirst = jf0;
@@ -707,8 +749,8 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
       uint32_t tiles = 0;
       for (uint32_t gi = 0; gi < ng; gi++) {
         if (jdone[gi] <= jf0) continue;
-        const uint64_t K = P.off[gi + 1] - P.off[gi];
-        f.base[f.ngroups] = P.off[gi];
+        const uint64_t K = gK(gi, jf0);
+        f.base[f.ngroups] = gpos(gi, jf0);
         f.K[f.ngroups] = K;
         f.tpref[f.ngroups] = tiles;
         tiles += (uint32_t)((K + FT_SLOTS - 1) / FT_SLOTS);
@@ -726,6 +768,8 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
       j = jf1;
       continue;
     }
+    // a stage reading the primes (level 0) writes its nodes D further on
+    const uint64_t dout = j == 0 ? D : 0;
     Stage s;
     s.jfirst = j;
     s.dv.table = nullptr;
@@ -735,22 +779,22 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
     uint64_t m = 0;
     s.tails.n = 0;
     for (uint32_t gi = 0; gi < ng; gi++) {
-      const uint64_t K = P.off[gi + 1] - P.off[gi];
+      const uint64_t K = gK(gi, j), b = gpos(gi, j);
       const uint64_t nodes = (K + (1ull << j) - 1) >> j;
-      t.base[gi] = P.off[gi];
+      t.base[gi] = b;
       t.K[gi] = K;
       t.mpref[gi] = m;
       m += nodes / 2;
       // the odd last node moves up; a finished root moves until jdone
       if ((nodes & 1) && (nodes > 1 || j < jdone[gi])) {
-        const uint64_t o = P.off[gi] + (nodes - 1) * (1ull << j);
+        const uint64_t o = b + (nodes - 1) * (1ull << j);
         s.tails.off[s.tails.n] = o;
-        s.tails.len[s.tails.n] = P.off[gi + 1] - o;
+        s.tails.len[s.tails.n] = b + K - o;
         s.tails.n++;
       }
       // CRT segment: this group's products, contiguous from its base
       const uint64_t seglen = std::min<uint64_t>(K, (nodes / 2) * (2ull << j));
-      if (nodes / 2 > 0) s.host_segs.push_back(CrtSeg{P.off[gi], P.off[gi], seglen});
+      if (nodes / 2 > 0) s.host_segs.push_back(CrtSeg{b, b, seglen});
     }
     t.mpref[ng] = m;
     s.nmul = m;
@@ -764,9 +808,9 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
       s.maxL = c.maxL;
     }
     s.a_base = s.b_base = in_of(j);
-    s.c_base = out_of(j);
+    s.c_base = out_of(j) + dout;
     s.tail_in_base = in_of(j);
-    s.tail_out_base = out_of(j);
+    s.tail_out_base = out_of(j) + dout;
     build_crt_segs(s);
     P.products += m;
     P.product_limbs += s.limbs;
@@ -966,6 +1010,45 @@ void plan_post(const Layout& Ly, Plan& P) {
     pe = next;
   }
   P.post_final = P.post.size();
+  // the product that leaves R (one request): its output size, for the choice
+  // of R as a node of Q_1's tree
+  Stage* r_stage = nullptr;
+  size_t r_k = 0;
+  if (nr == 1 && has_q1[0] && !pe[0].empty()) {
+    for (Stage& t : P.post)
+      for (size_t k = 0; k < t.host_desc.size(); k++)
+        if (t.host_desc[k].c_off == pe[0][0].pos) {
+          r_stage = &t;
+          r_k = k;
+        }
+    if (r_stage) {
+      P.r_limbs = (uint64_t)r_stage->host_desc[r_k].la + r_stage->host_desc[r_k].lb;
+      P.r_bits = pe[0][0].bits;
+    }
+  }
+  if (P.rins_j >= 0) {
+    // R's product writes its limbs to R's node (position 0 of the arena
+    // that level rins_j reads, the limbs above them cleared by a fill), and
+    // the root of group 0 is C itself
+    const uint64_t npos = ((P.rins_j - 1) % 2 == 0) ? Ly.arenaA : Ly.arenaB;
+    MulDesc& d = r_stage->host_desc[r_k];
+    const uint64_t old = d.c_off;
+    d.c_off = npos;
+    for (CrtSeg& sg : r_stage->host_segs)
+      if (sg.out_pos == old) sg.out_pos = npos;
+    P.rins_fill_pos = npos + P.r_limbs;
+    P.rins_fill_len = (1ull << P.rins_j) - P.r_limbs;
+    const uint64_t K0 = P.off[1] - P.off[0] + (1ull << P.rins_j);
+    const uint64_t bits = P.gbits[0] + P.r_bits;
+    P.rpos[0] = P.root[0];
+    P.rcap[0] = cap_of(K0, bits);
+    P.rone[0] = false;
+    P.result_pos = P.rpos[0];
+    P.result_cap = P.rcap[0];
+    P.result_is_one = false;
+    P.post_end = bump;
+    return;
+  }
   bool any_final = false;
   for (uint32_t r = 0; r < nr; r++) any_final = any_final || (has_q1[r] && !pe[r].empty());
   // nothing runs beside the Q_1 tree (one request only: batches run in line)
@@ -1093,6 +1176,28 @@ void free_plan(Plan* P) {
   delete P;
 }
 
+// R = prod_{e>=2} P_e enters Q_1's tree as a node of level j (returned; -1:
+// the final product Q_1 R stays).  j leaves two levels of Q_1 between the
+// completion of the last group with e >= 2 and R's level, for the powers and
+// R to run beside them; it lies above the leaf and fused levels and holds R's
+// product.  Taken when R's node is at most a quarter of Q_1's tree and the
+// arenas have room for the extra 2^j leaves.
+bool g_rins = true;
+int rins_level(const Layout& Ly, const Plan& P) {
+  if (!g_rins || P.nreq != 1 || P.ng < 2 || P.exps[0] != 1 || P.r_limbs == 0) return -1;
+  const TreeShape sh = tree_shape(P);
+  int jdone2 = -1;
+  for (uint32_t gi = 1; gi < P.ng; gi++) {
+    int jd = std::max(ceil_log2(P.off[gi + 1] - P.off[gi]), sh.jleaf);
+    if (sh.jf0 >= 0 && jd > sh.jf0 && jd <= sh.jf1 + 1) jd = sh.jf1 + 1;
+    if (P.exps[gi] >= 2) jdone2 = std::max(jdone2, jd);
+  }
+  const int j = std::max({ceil_log2(P.r_limbs), jdone2 + 2, sh.jleaf + 1, sh.jf1 + 1});
+  if (ceil_log2(P.off[1] - P.off[0]) < j + 2) return -1;
+  if ((1ull << j) + P.off[P.ng] > Ly.Kmax) return -1;
+  return j;
+}
+
 cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out, bool device_tables = true,
                      const uint32_t* req = nullptr, uint32_t nreq = 1) {
   Plan* P = new Plan();
@@ -1106,13 +1211,26 @@ cat_status make_plan(const Layout& Ly, const GroupTable& gt, Plan** out, bool de
     P->gbits[gi] = gt.gbits[gi];
   }
   for (uint32_t gi = 0; gi <= gt.ngroups; gi++) P->off[gi] = gt.off[gi];
-  plan_tree(Ly, *P, true);
-  // products and their limbs are counted from the pairwise levels of the plain
-  // form (the leaf kernel of the batched form folds the lowest levels)
-  P->products = 0;
-  P->product_limbs = 0;
-  plan_tree(Ly, *P, false);
-  plan_post(Ly, *P);
+  auto plan_all = [&]() {
+    P->batched.clear();
+    P->plain.clear();
+    P->post.clear();
+    P->fork_count = -1;
+    P->post_final = 0;
+    plan_tree(Ly, *P, true);
+    // products and their limbs are counted from the pairwise levels of the
+    // plain form (the leaf kernel of the batched form folds the lowest levels)
+    P->products = 0;
+    P->product_limbs = 0;
+    plan_tree(Ly, *P, false);
+    plan_post(Ly, *P);
+  };
+  plan_all();
+  const int jR = rins_level(Ly, *P);
+  if (jR >= 0) {
+    P->rins_j = jR;
+    plan_all();
+  }
   std::vector<Stage*> all;
   for (auto& s : P->batched) all.push_back(&s);
   for (auto& s : P->plain) all.push_back(&s);
@@ -1540,8 +1658,50 @@ cat_status capture_graph(F&& rec, hipGraphExec_t* out) {
   return CAT_OK;
 }
 
+// R's node: clear the limbs above R's product, then the powers and R
+cat_status run_rins_side(Exec& S, Plan& P, bool plain) {
+  if (P.rins_fill_len > 0) {
+    hipLaunchKernelGGL(k_fill, dim3((uint32_t)std::min<uint64_t>((P.rins_fill_len + 255) / 256, 1024)), dim3(256), 0,
+                       S.st, S.W + P.rins_fill_pos, P.rins_fill_len, 0u);
+    LAUNCHCHK();
+    S.launches++;
+  }
+  for (size_t k = 0; k < P.post_final; k++) STCHK(plain ? run_stage_plain(S, P.post[k]) : run_stage_batched(S, P.post[k]));
+  return CAT_OK;
+}
+
 cat_status run_phase2(Exec& X, Plan& P, bool plain) {
   std::vector<Stage>& st = plain ? P.plain : P.batched;
+  if (P.rins_j >= 0) {
+    // R is a node of Q_1's tree at the level of stage sr: the powers and R
+    // run before it (beside the levels that follow the completion of the
+    // groups with e >= 2 when the call has a side stream)
+    const size_t sr = std::min<size_t>((size_t)P.rins_stage[plain ? 1 : 0], st.size());
+    if (!plain && X.side && P.fork_count >= 0) {
+      const size_t nf = std::min<size_t>((size_t)P.fork_count, sr);
+      for (size_t k = 0; k < nf; k++) STCHK(run_stage_batched(X, st[k]));
+      HIPCHK(hipEventRecord(g.ev_fork, X.st));
+      HIPCHK(hipStreamWaitEvent(X.side, g.ev_fork, 0));
+      for (size_t k = nf; k < sr; k++) STCHK(run_stage_batched(X, st[k]));
+      Exec S = X;
+      S.st = X.side;
+      S.res = X.res2;
+      S.res_stride = X.res2_stride;
+      S.F = X.F2;
+      S.flags = X.flags2;
+      S.crt_epoch = 0;
+      S.launches = 0;
+      STCHK(run_rins_side(S, P, false));
+      HIPCHK(hipEventRecord(g.ev_join, S.st));
+      HIPCHK(hipStreamWaitEvent(X.st, g.ev_join, 0));
+      X.launches += S.launches;
+    } else {
+      for (size_t k = 0; k < sr; k++) STCHK(plain ? run_stage_plain(X, st[k]) : run_stage_batched(X, st[k]));
+      STCHK(run_rins_side(X, P, plain));
+    }
+    for (size_t k = sr; k < st.size(); k++) STCHK(plain ? run_stage_plain(X, st[k]) : run_stage_batched(X, st[k]));
+    return CAT_OK;
+  }
   if (!plain && X.side && P.fork_count >= 0) {
     // Q_1's upper levels on st; the powers and R on the side stream with
     // their own scratch; C = Q_1 R once both are done.  Q_1's levels are
@@ -2110,10 +2270,17 @@ cat_status groups_in(const uint32_t* h_exps, const uint64_t* h_off, uint32_t ngr
   return CAT_OK;
 }
 
+// Arena room for R's node in Q_1's tree (at most a quarter of the longest
+// tree, rounded to a power of two): 2^(ceil(log2 K) - 2) leaves beyond K.
+uint64_t rins_room(uint64_t K) {
+  const int c = ceil_log2(std::max<uint64_t>(K, 1));
+  return c >= 2 ? (1ull << (c - 2)) : 0;
+}
+
 Layout make_layout_groups(const GroupsIn& G) {
   Layout L;
   L.n = 0;
-  L.Kmax = std::max<uint64_t>(G.total, 16);
+  L.Kmax = std::max<uint64_t>(G.total + rins_room(G.total), 16);
   // the power chains (about twice their results), the outer tree (one pass
   // over the powers per level) and the final product
   uint32_t nchain = 0;
@@ -2180,7 +2347,7 @@ Layout make_layout_ratio(const RatioSpec& r) {
   // bit t needs p <= S / 2^t + 1
   uint64_t ent = 0;
   for (uint64_t x = r.S; x >= 1; x >>= 1) ent += pi_bound(std::min<uint64_t>(r.A, x + 1));
-  L.Kmax = std::max<uint64_t>(ent, 16);
+  L.Kmax = std::max<uint64_t>(ent + rins_room(ent), 16);
   // post-tree allocations: the power chains, the outer tree and the final
   // product together stay below 16 log2(N) / 32 limbs plus the operands' slack
   L.post_cap = (uint64_t)(16.0 * (r.log2N + 64.0) / 32.0) + L.Kmax + 8192;
@@ -2338,6 +2505,7 @@ static cat_status exact_in_workspace(uint64_t n, const Layout& Ly, char* wb, uin
   stats.launches = launches;
   stats.n_primes = gt.off[gt.ngroups];
   stats.levels = P->levels;
+  stats.outer_level = P->rins_j;
   stats.graph_replayed = replayed ? 1 : 0;
   g.stats = stats;
   if (cap < L) return CAT_ERANGE;
@@ -2387,6 +2555,21 @@ cat_status cat_fused_levels_set(uint32_t max_logn) {
   if (max_logn != 0 && (max_logn < 4 || max_logn > FT_LOGT)) return CAT_EINVAL;
   g_fuse_logn = max_logn;
   // cached plans were made with the old setting
+  if (!g.plans.empty() || !g.noalloc_plans.empty()) HIPCHK(hipDeviceSynchronize());
+  for (auto& kv : g.plans) free_plan(kv.second);
+  g.plans.clear();
+  g.plan_order.clear();
+  for (auto& kv : g.noalloc_plans) free_plan(kv.second);
+  g.noalloc_plans.clear();
+  g.noalloc_order.clear();
+  return CAT_OK;
+}
+
+cat_status cat_outer_node_set(uint32_t on) {
+  std::lock_guard<std::recursive_mutex> lk(g.mu);
+  if (on > 1) return CAT_EINVAL;
+  g_rins = on != 0;
+  // cached plans and their graphs were made with the old setting
   if (!g.plans.empty() || !g.noalloc_plans.empty()) HIPCHK(hipDeviceSynchronize());
   for (auto& kv : g.plans) free_plan(kv.second);
   g.plans.clear();
@@ -2569,6 +2752,7 @@ cat_status catalan_exact_ex(uint64_t n, uint32_t* d_limbs, size_t cap, size_t* n
     stats.launches = replayed ? 1 : launches;
     stats.n_primes = gt.off[gt.ngroups];
     stats.levels = P->levels;
+  stats.outer_level = P->rins_j;
     stats.graph_replayed = replayed ? 1 : 0;
     g.stats = stats;
     if (cap < L) return CAT_ERANGE;
@@ -3245,6 +3429,7 @@ cat_status factorial_ratio_exact(const uint64_t* a, uint32_t k, const uint64_t* 
   stats.launches = launches + X.launches + 1;
   stats.n_primes = gt.off[gt.ngroups];
   stats.levels = P->levels;
+  stats.outer_level = P->rins_j;
   free_plan(P);
   g.stats = stats;
   if (res != CAT_OK) return res;
@@ -3354,6 +3539,7 @@ cat_status prime_power_product(const uint32_t* d_entries, const uint32_t* h_exps
   stats.launches = X.launches + 4;
   stats.n_primes = G.total;
   stats.levels = P->levels;
+  stats.outer_level = P->rins_j;
   free_plan(P);
   g.stats = stats;
   if (res != CAT_OK) return res;

@@ -383,6 +383,38 @@ def test_lazy_primes_same_bits(cat, lazy, fused):
         cat.set_fused_levels(12)
 
 
+@pytest.mark.parametrize("fused", [0, 12])
+@pytest.mark.parametrize("on", [False, True])
+def test_outer_node_same_bits(cat, on, fused):
+    """R, the product of the powers P_e with e >= 2, entering Q_1's product
+    tree as one more node (on) or multiplied onto Q_1 after the tree (off):
+    the same C(n) in every mode against the oracle, at sizes where the node is
+    taken and where Q_1's tree is too short for it, with the lower levels
+    fused or not, and the full-size digest at 10^7."""
+    try:
+        cat.set_outer_node(on)
+        cat.set_fused_levels(fused)
+        for n in (2000, 5000, 13337, 100000, 262147, 524287, 1000003):
+            _say("outer node", on, "fused", fused, n)
+            exp = oracle.catalan(n)
+            for mode in (["graph", "batched", "plain"] if n <= 100000 else ["graph", "batched"]):
+                got = cat.to_numpy(cat.exact(n, mode=mode))
+                assert np.array_equal(got, exp), (on, fused, n, mode)
+                lvl = cat.stats()["outer_level"]
+                if not on:
+                    assert lvl == -1, (n, lvl)
+                if on and n >= 100000:
+                    assert lvl >= 6, (n, lvl)
+        with open(os.path.join(GOLDEN, "oracle_catalan.json")) as f:
+            gold = json.load(f)["10000000"]
+        got = cat.to_numpy(cat.exact(10**7, mode="graph"))
+        assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
+        assert (cat.stats()["outer_level"] >= 6) == on
+    finally:
+        cat.set_outer_node(True)
+        cat.set_fused_levels(12)
+
+
 def _ones_square(a):
     """(B^a - 1)^2 = B^(2a) - 2 B^a + 1, B = 2^32: limb 0 is 1, limbs 1..a-1
     are 0, limb a is B - 2 and limbs a+1..2a-1 are B - 1."""
