@@ -12,44 +12,85 @@
 // ---------------------------------------------------------------------------
 // Leaf packing.  Tree view: level LF, node i of group g is written at
 // base[g] + i*2^LF; `tl.mpref` is the prefix count of NODES per group.
+// The leaves and the nodes pass through LDS (row t of the tile holds thread
+// t's node, padded to 2^LF + 1 words so that the row-wise reads of the
+// threads hit distinct banks), so that the global loads and stores of a wave
+// cover whole runs of consecutive words.
 template <int LF>
 __global__ void __launch_bounds__(256)
 k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint32_t* __restrict__ out) {
   constexpr int W = 1 << LF;
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nnodes) return;
-  uint32_t g = 0;
-  while (g + 1 < tl.ngroups && i >= tl.mpref[g + 1]) g++;
-  const uint64_t il = i - tl.mpref[g];
-  const uint64_t off = tl.base[g] + il * W;
-  const uint64_t rem = tl.K[g] - il * W;
-  const uint32_t cnt = (uint32_t)(rem < (uint64_t)W ? rem : (uint64_t)W);
-  // all 2^LF loads first (clamped to the node's last leaf; leaves past cnt are
-  // never multiplied in)
-  uint32_t qv[W];
+  constexpr int RW = W + 1;
+  constexpr int NT = 256;
+  __shared__ uint32_t tile[NT * RW];
+  __shared__ uint64_t noff[NT];
+  __shared__ uint32_t ncnt[NT];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t i0 = (uint64_t)blockIdx.x * NT;
+  {
+    const uint64_t i = i0 + tid;
+    uint64_t off = 0;
+    uint32_t cnt = 0;
+    if (i < nnodes) {
+      uint32_t g = 0;
+      while (g + 1 < tl.ngroups && i >= tl.mpref[g + 1]) g++;
+      const uint64_t il = i - tl.mpref[g];
+      off = tl.base[g] + il * W;
+      const uint64_t rem = tl.K[g] - il * W;
+      cnt = (uint32_t)(rem < (uint64_t)W ? rem : (uint64_t)W);
+    }
+    noff[tid] = off;
+    ncnt[tid] = cnt;
+  }
+  __syncthreads();
+  // leaf k of node t at tile[t RW + k]: lane group of W threads per node,
+  // every load in flight before the first LDS store
+  constexpr int NPR = NT / W;     // nodes per round
+  {
+    uint32_t v[W];
 #pragma unroll
-  for (int k = 0; k < W; k++) qv[k] = primes[off + ((uint32_t)k < cnt ? (uint32_t)k : cnt - 1)];
+    for (int r = 0; r < W; r++) {
+      const uint32_t t = r * NPR + tid / W, k = tid % W, c = ncnt[t];
+      v[r] = c ? primes[noff[t] + (k < c ? k : c - 1)] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < W; r++) tile[(r * NPR + tid / W) * RW + tid % W] = v[r];
+  }
+  __syncthreads();
+  const uint32_t cnt = ncnt[tid];
   uint32_t acc[W];
-  acc[0] = qv[0];
+  {
+    uint32_t qv[W];
 #pragma unroll
-  for (int k = 1; k < W; k++) acc[k] = 0;
+    for (int k = 0; k < W; k++) qv[k] = tile[tid * RW + k];
+    acc[0] = qv[0];
 #pragma unroll
-  for (int k = 1; k < W; k++) {
-    if ((uint32_t)k < cnt) {
-      const uint32_t q = qv[k];
-      uint32_t carry = 0;
+    for (int k = 1; k < W; k++) acc[k] = 0;
 #pragma unroll
-      for (int l = 0; l < k; l++) {
-        const uint64_t t = (uint64_t)acc[l] * q + carry;
-        acc[l] = (uint32_t)t;
-        carry = (uint32_t)(t >> 32);
+    for (int k = 1; k < W; k++) {
+      if ((uint32_t)k < cnt) {
+        const uint32_t q = qv[k];
+        uint32_t carry = 0;
+#pragma unroll
+        for (int l = 0; l < k; l++) {
+          const uint64_t t = (uint64_t)acc[l] * q + carry;
+          acc[l] = (uint32_t)t;
+          carry = (uint32_t)(t >> 32);
+        }
+        acc[k] = carry;
       }
-      acc[k] = carry;
     }
   }
+  // each thread rewrites only its own row: no barrier between its reads and
+  // its writes
 #pragma unroll
-  for (int k = 0; k < W; k++)
-    if ((uint32_t)k < cnt) out[off + k] = acc[k];
+  for (int k = 0; k < W; k++) tile[tid * RW + k] = acc[k];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < W; r++) {
+    const uint32_t t = r * NPR + tid / W, k = tid % W;
+    if (k < ncnt[t]) out[noff[t] + k] = tile[t * RW + k];
+  }
 }
 
 // ---------------------------------------------------------------------------
