@@ -17,6 +17,7 @@
 #define CAT_MAX_LOGN 27
 #define CAT_MAX_GROUPS 32       // e_p <= log2(2n) < 32
 #define CAT_LDS_LOGT 12         // row length of the LDS-resident transforms
+#define CAT_LEAF_LF 6         // tree levels folded into the leaf kernel (nodes of 2^LF leaves)
 #define CAT_CRT_E 3             // limbs per thread in the CRT/carry kernel (>= 3)
 #define CAT_CRT_THREADS 256
 #define CAT_CRT_BLOCK (CAT_CRT_E * CAT_CRT_THREADS)

@@ -415,7 +415,7 @@ struct Stage {
   // carried-up nodes
   CopyList tails{};
   uint64_t tail_in_base = 0, tail_out_base = 0;
-  bool is_leaf = false;    // k_leaf<5>
+  bool is_leaf = false;    // k_leaf<CAT_LEAF_LF>
   TreeLevel leaf{};
   uint64_t leaf_nodes = 0;
   bool dec = false;        // radix-10^9 products (k_crt10; addends in the segments)
@@ -653,7 +653,7 @@ TreeShape tree_shape(const Plan& P) {
     Kmax_g = std::max(Kmax_g, P.off[gi + 1] - P.off[gi]);
     leaves += P.off[gi + 1] - P.off[gi];
   }
-  const int LF = 5;
+  const int LF = CAT_LEAF_LF;
   sh.J = ceil_log2(std::max<uint64_t>(Kmax_g, 1));
   sh.jleaf = Kmax_g > 1 ? std::min(sh.J, LF) : 0;
   // the consecutive levels above the leaf and schoolbook levels whose
@@ -673,7 +673,7 @@ TreeShape tree_shape(const Plan& P) {
 // out(j) = A for even j, B for odd j; in(0) = primes.  Node positions: group
 // g's leaf k sits at off[g] + k in the primes buffer and at D + off[g] + k in
 // the arenas, D = 2^rins_j when R is a node of Q_1's tree (else 0); from
-// level rins_j on group 0 covers [0, D + K_0): R's node first.
+// level rins_j on group 0 covers [off[0], off[0] + D + K_0): R's node first.
 void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   std::vector<Stage>& st = batched ? P.batched : P.plain;
   const uint32_t ng = P.ng;
@@ -684,7 +684,7 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
   // first leaf and leaf count of group g at level j (input side)
   auto gpos = [&](uint32_t gi, int j) -> uint64_t {
     if (j == 0) return P.off[gi];
-    if (jR >= 0 && gi == 0 && j >= jR) return 0;
+    if (jR >= 0 && gi == 0 && j >= jR) return P.off[0];   // R's node, then the shifted leaves
     return D + P.off[gi];
   };
   auto gK = [&](uint32_t gi, int j) -> uint64_t {
@@ -692,7 +692,7 @@ void plan_tree(const Layout& Ly, Plan& P, bool batched) {
     return (jR >= 0 && gi == 0 && j >= jR) ? K + D : K;
   };
   const TreeShape sh = tree_shape(P);
-  const int LF = 5;
+  const int LF = CAT_LEAF_LF;
   const int jleaf = sh.jleaf, jf0 = sh.jf0, jf1 = sh.jf1;
   int J = sh.J;
   if (jR >= 0) J = std::max(J, ceil_log2(gK(0, jR)));
@@ -1030,7 +1030,7 @@ void plan_post(const Layout& Ly, Plan& P) {
     // R's product writes its limbs to R's node (position 0 of the arena
     // that level rins_j reads, the limbs above them cleared by a fill), and
     // the root of group 0 is C itself
-    const uint64_t npos = ((P.rins_j - 1) % 2 == 0) ? Ly.arenaA : Ly.arenaB;
+    const uint64_t npos = (((P.rins_j - 1) % 2 == 0) ? Ly.arenaA : Ly.arenaB) + P.off[0];
     MulDesc& d = r_stage->host_desc[r_k];
     const uint64_t old = d.c_off;
     d.c_off = npos;
@@ -1576,7 +1576,7 @@ cat_status run_stage_batched(Exec& X, const Stage& s) {
     const uint32_t blocks = (uint32_t)((s.leaf_nodes + 255) / 256);
     {
       KTime kt("k_leaf", X.st, (double)s.leaf_nodes);
-      hipLaunchKernelGGL(k_leaf<5>, dim3(blocks), dim3(256), 0, X.st, s.leaf, s.leaf_nodes, X.W + s.a_base,
+      hipLaunchKernelGGL(k_leaf<CAT_LEAF_LF>, dim3(blocks), dim3(256), 0, X.st, s.leaf, s.leaf_nodes, X.W + s.a_base,
                          X.W + s.c_base);
     }
     LAUNCHCHK();

@@ -60,16 +60,13 @@ k_leaf(TreeLevel tl, uint64_t nnodes, const uint32_t* __restrict__ primes, uint3
   const uint32_t cnt = ncnt[tid];
   uint32_t acc[W];
   {
-    uint32_t qv[W];
-#pragma unroll
-    for (int k = 0; k < W; k++) qv[k] = tile[tid * RW + k];
-    acc[0] = qv[0];
+    acc[0] = tile[tid * RW];
 #pragma unroll
     for (int k = 1; k < W; k++) acc[k] = 0;
 #pragma unroll
     for (int k = 1; k < W; k++) {
       if ((uint32_t)k < cnt) {
-        const uint32_t q = qv[k];
+        const uint32_t q = tile[tid * RW + k];
         uint32_t carry = 0;
 #pragma unroll
         for (int l = 0; l < k; l++) {
