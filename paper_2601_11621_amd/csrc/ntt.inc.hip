@@ -464,7 +464,42 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
     for (uint32_t t = threadIdx.x; t < N; t += blockDim.x) fb[(size_t)prime * N + t] = lds[lds_pad(t)];
     return;
   }
-  {
+  // Packed tiles (every tree level): the tile's products have la = lb = N/2
+  // and lie back to back, a then b, in one array, with their residues at the
+  // same relative positions, so the tile reads T consecutive words and writes
+  // T consecutive residues
+  bool packed = false;
+  if constexpr (BMODE == 0) {
+    bool ok = true;
+    if (threadIdx.x < cnt) {
+      const MulDesc d = ds[threadIdx.x], d0 = ds[0];
+      const uint64_t rel = (uint64_t)threadIdx.x << logN;
+      ok = d.la == (N >> 1) && d.lb == (N >> 1) && d.a_off == d0.a_off + rel && d.b_off == d.a_off + (N >> 1) &&
+           d.r_off == d0.r_off + rel;
+    }
+    packed = __syncthreads_and(ok ? 1 : 0) != 0 && ain == bin;
+  }
+  if (packed) {
+    constexpr uint32_t NT = TT / 16;               // blockDim.x
+    const uint32_t* src = ain + ds[0].a_off;
+    const uint32_t half = N >> 1;
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t w = threadIdx.x + i * NT;
+      x[i] = src[w < T ? w : T - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t w = threadIdx.x + i * NT;
+      if (w < T) {
+        // word w: product w / N, operand bit logN - 1 of w, position w mod N/2
+        const uint32_t dst = ((w >> (logN - 1)) & 1u ? TT : 0u) + (w & ~(N - 1)) + (w & (half - 1));
+        lds[lds_pad(dst)] = in_limb<AS>(x[i], p);
+        lds[lds_pad(dst + half)] = 0u;
+      }
+    }
+  } else {
     // every load of the thread is issued before the first is used: clamped,
     // in-bounds addresses and masks instead of branches around the loads
     constexpr uint32_t NT = TT / 16;               // blockDim.x
@@ -515,6 +550,16 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   }
   ntt_inv_tile<true, AS>(lds, logN, T, 0, itws, pc);
   uint32_t* out = res + (size_t)prime * res_stride;
+  if (packed) {
+    constexpr uint32_t NT = TT / 16;
+    uint32_t* dst = out + ds[0].r_off;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t t = threadIdx.x + i * NT;
+      if (t < T) dst[t] = out_residue<AS>(lds[lds_pad(t)], p);
+    }
+    return;
+  }
   for (uint32_t m = 0; m < cnt; m++) {
     const MulDesc d = ds[m];
     const uint32_t L = d.la + d.lb;
