@@ -70,8 +70,10 @@ __host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4)
 // Radix-R DFT on registers, decimation in frequency: natural input, output
 // y[k] in v[brev(k)].  Set 1: inputs and outputs in [0, 2q); a butterfly
 // gives red(a + b) and (a - b + 2q) * w (the sum below 4q, the Shoup product
-// below 2q).
-template <int LOGR, int AS = 0>
+// below 2q).  TW (set 1): every output but v[0] is multiplied next by a
+// twiddle (Shoup, any 32-bit input), so the last stage leaves those in
+// [0, 4q) unreduced.
+template <int LOGR, int AS = 0, bool TW = false>
 __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t p = pc.p;
@@ -90,9 +92,10 @@ __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
           if (i == 0) v[s + i + h] = d;
           else v[s + i + h] = mul_tw(d, pc.w16[wi], pc.w16q[wi], p);
         } else {
-          v[s + i] = red2(a + b, p2);
+          const bool keep = TW && h == 1;   // the twiddle that follows reduces it
+          v[s + i] = (keep && s + i != 0) ? a + b : red2(a + b, p2);
           const uint32_t t = a + (p2 - b);
-          if (i == 0) v[s + i + h] = red2(t, p2);
+          if (i == 0) v[s + i + h] = keep ? t : red2(t, p2);
           else v[s + i + h] = shoup(t, pc.w16[wi], pc.w16q[wi], p);
         }
       }
@@ -103,8 +106,9 @@ __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
 // Inverse: input y[k] in v[brev(k)], decimation in time with inverse roots,
 // output x[j] (times R) in v[j].  Set 1: inputs and outputs in [0, 4q); a
 // butterfly reduces a to [0, 2q), takes t = w b in [0, 2q) and gives a + t and
-// a - t + 2q.
-template <int LOGR, int AS = 0>
+// a - t + 2q.  TW (set 1): every input but v[0] comes from a twiddle (Shoup,
+// in [0, 2q)), so the first stage does not reduce those again.
+template <int LOGR, int AS = 0, bool TW = false>
 __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t p = pc.p;
@@ -122,8 +126,9 @@ __device__ __forceinline__ void dft_inv(uint32_t* v, const PrimeC& pc) {
           v[s + i] = add_mod(a, t, p);
           v[s + i + h] = sub_mod(a, t, p);
         } else {
-          a = red2(a, p2);
-          const uint32_t t = (i == 0) ? red2(b, p2) : shoup(b, pc.iw16[wi], pc.iw16q[wi], p);
+          const bool fresh = TW && h == 1;   // inputs straight from the twiddles
+          if (!(fresh && s + i != 0)) a = red2(a, p2);
+          const uint32_t t = (i == 0) ? (fresh ? b : red2(b, p2)) : shoup(b, pc.iw16[wi], pc.iw16q[wi], p);
           v[s + i] = a + t;
           v[s + i + h] = a + (p2 - t);
         }
@@ -193,8 +198,8 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
   // branch around the twiddles)
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    dft_fwd<LOGR, AS>(v[u], pc);
     if (logSR > 0) {
+      dft_fwd<LOGR, AS, true>(v[u], pc);
       const uint32_t jo = jj[u] * (uint32_t)sizeof(uint2);
       const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << logSR);
 #pragma unroll
@@ -203,6 +208,8 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
         const int r = brev_c(k1, LOGR);
         v[u][r] = tw_mul<AS>(v[u][r], t.x, t.y, pc.p);
       }
+    } else {
+      dft_fwd<LOGR, AS, false>(v[u], pc);
     }
   }
 #pragma unroll
@@ -236,8 +243,10 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
         const int r = brev_c(k1, LOGR);
         v[u][r] = tw_mul<AS>(v[u][r], t.x, t.y, pc.p);
       }
+      dft_inv<LOGR, AS, true>(v[u], pc);
+    } else {
+      dft_inv<LOGR, AS, false>(v[u], pc);
     }
-    dft_inv<LOGR, AS>(v[u], pc);
   }
 #pragma unroll
   for (int u = 0; u < U; u++) {
