@@ -181,6 +181,20 @@ __device__ __forceinline__ uint2 tw_at(__amdgpu_buffer_rsrc_t rs, uint32_t k1, u
   return make_uint2(v[0], v[1]);
 }
 
+// Word arrays read and written through raw buffer resources with byte
+// offsets in one VGPR: loads past the array's end return 0 and stores there
+// are dropped (the range check of an unswizzled buffer), which the column
+// kernels use for the zero padding of their operands and the end of a product.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const uint32_t* p, uint64_t words) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(uint32_t)(words * 4u), CAT_BUF_DW3);
+}
+__device__ __forceinline__ uint32_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)byte_off, 0, 0);
+}
+
 template <int LOGR, bool PAD, int U, int AS>
 __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ tw, const PrimeC& pc) {
@@ -643,8 +657,30 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
   const uint64_t N = 1ull << pg.logN;
   const uint32_t T = 1u << (pg.logL + pg.logC);
   uint32_t* f = F + ((m * 3 + prime) * 2 + op) * N;
+  // Tiles of at most 256 columns: element t = t0 + tid + 256 i of the tile
+  // (row t >> logC, column t mod C) sits at the thread's byte offset off0 plus
+  // a step that is the same for the whole workgroup; the sub-problem offsets
+  // stay below N <= 2^27 words.
+  const bool lin = pg.logC <= 8;
+  const uint32_t RI = NTT_COL_THREADS >> (lin ? pg.logC : 0);   // rows per step of i
+  const uint32_t rowB = 4u << logSig;                           // bytes per row
+  const uint32_t off0 = ((uint32_t)base + ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1))) * 4u;
   // loads in batches of COL_BATCH per thread, all issued before the first use
-  if (first) {
+  if (first && lin) {
+    const MulDesc d = dv.get(m);
+    const __amdgpu_buffer_rsrc_t rs = words_rsrc(op ? bin + d.b_off : ain + d.a_off, op ? d.lb : d.la);
+    for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+      const uint32_t ob = off0 + (t0 >> pg.logC) * rowB;
+      uint32_t v[COL_BATCH];
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) v[i] = buf_ld(rs, ob + i * RI * rowB);
+#pragma unroll
+      for (int i = 0; i < COL_BATCH; i++) {
+        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+        if (t < T) lds[t] = in_limb<AS>(v[i], p);
+      }
+    }
+  } else if (first) {
     const MulDesc d = dv.get(m);
     const uint32_t* src = op ? bin + d.b_off : ain + d.a_off;
     const uint64_t len = op ? d.lb : d.la;
@@ -678,13 +714,20 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
       w = tw2(plo, phi, ((jt * fr) << ysh) & ymask, pc);
       R = tw2(plo, phi, ((((NTT_COL_THREADS >> pg.logC) << logSig) * fr) << ysh) & ymask, pc);
     }
+    const __amdgpu_buffer_rsrc_t rs = words_rsrc(f, N);
     for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
       uint32_t v[COL_BATCH];
+      if (lin) {
+        const uint32_t ob = off0 + (t0 >> pg.logC) * rowB;
 #pragma unroll
-      for (int i = 0; i < COL_BATCH; i++) {
-        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
-        const uint32_t tc = t < T ? t : T - 1;
-        v[i] = f[base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1))];
+        for (int i = 0; i < COL_BATCH; i++) v[i] = buf_ld(rs, ob + i * RI * rowB);
+      } else {
+#pragma unroll
+        for (int i = 0; i < COL_BATCH; i++) {
+          const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+          const uint32_t tc = t < T ? t : T - 1;
+          v[i] = f[base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1))];
+        }
       }
 #pragma unroll
       for (int i = 0; i < COL_BATCH; i++) {
@@ -703,8 +746,16 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
   __syncthreads();
   if (!tw) {
     // the pass next to the rows: k_row applies this pass's twiddles
-    for (uint32_t t = threadIdx.x; t < T; t += NTT_COL_THREADS)
-      f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+    if (lin) {
+      const __amdgpu_buffer_rsrc_t rs = words_rsrc(f, N);
+      for (uint32_t k = 0; (k << 8) < T; k++) {
+        const uint32_t t = threadIdx.x + (k << 8);
+        if (t < T) buf_st(rs, off0 + k * RI * rowB, lds[t]);
+      }
+    } else {
+      for (uint32_t t = threadIdx.x; t < T; t += NTT_COL_THREADS)
+        f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+    }
     return;
   }
   const uint2* lo = tb.tw2lo + (size_t)prime * TW2_LO;
@@ -756,15 +807,27 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   const uint2* lo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* hi = tb.itw2hi + (size_t)prime * TW2_HI;
   const uint32_t ysh = tw_logn<AS>() - pg.logS;
+  // element addressing of tiles of at most 256 columns, as in k_pass_fwd
+  const bool lin = pg.logC <= 8;
+  const uint32_t RI = NTT_COL_THREADS >> (lin ? pg.logC : 0);
+  const uint32_t rowB = 4u << logSig;
+  const uint32_t off0 = ((uint32_t)base + ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1))) * 4u;
   if (!tw) {
     // the pass next to the rows: k_row applied this pass's twiddles
+    const __amdgpu_buffer_rsrc_t rs = words_rsrc(f, N);
     for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
       uint32_t v[COL_BATCH];
+      if (lin) {
+        const uint32_t ob = off0 + (t0 >> pg.logC) * rowB;
 #pragma unroll
-      for (int i = 0; i < COL_BATCH; i++) {
-        const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
-        const uint32_t tc = t < T ? t : T - 1;
-        v[i] = f[base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1))];
+        for (int i = 0; i < COL_BATCH; i++) v[i] = buf_ld(rs, ob + i * RI * rowB);
+      } else {
+#pragma unroll
+        for (int i = 0; i < COL_BATCH; i++) {
+          const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
+          const uint32_t tc = t < T ? t : T - 1;
+          v[i] = f[base + ((uint64_t)(tc >> pg.logC) << logSig) + j0 + (tc & (C - 1))];
+        }
       }
 #pragma unroll
       for (int i = 0; i < COL_BATCH; i++) {
@@ -802,8 +865,16 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   ntt_inv_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
   if (!last) {
     if (!post) {
-      for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
-        f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+      if (lin) {
+        const __amdgpu_buffer_rsrc_t rs = words_rsrc(f, N);
+        for (uint32_t k = 0; (k << 8) < T; k++) {
+          const uint32_t t = threadIdx.x + (k << 8);
+          if (t < T) buf_st(rs, off0 + k * RI * rowB, lds[t]);
+        }
+      } else {
+        for (uint32_t t = threadIdx.x; t < T; t += blockDim.x)
+          f[base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1))] = lds[t];
+      }
       return;
     }
     // post: the inverse twiddles of the previous (outer) pass, at the same
@@ -826,9 +897,18 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   const MulDesc d = dv.get(m);
   uint32_t* out = res + (size_t)prime * res_stride + d.r_off;
   const uint64_t L = (uint64_t)d.la + d.lb;
-  for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint64_t j = base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1));
-    if (j < L) out[j] = out_residue<AS>(lds[t], p);
+  if (lin) {
+    // positions at or past L fall outside the buffer's range: not written
+    const __amdgpu_buffer_rsrc_t rs = words_rsrc(out, L);
+    for (uint32_t k = 0; (k << 8) < T; k++) {
+      const uint32_t t = threadIdx.x + (k << 8);
+      if (t < T) buf_st(rs, off0 + k * RI * rowB, out_residue<AS>(lds[t], p));
+    }
+  } else {
+    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) {
+      const uint64_t j = base + ((uint64_t)(t >> pg.logC) << logSig) + j0 + (t & (C - 1));
+      if (j < L) out[j] = out_residue<AS>(lds[t], p);
+    }
   }
   // coefficient positions in [N, L) (only when L = N + 1) are zero
   if (base == 0 && j0 == 0)
