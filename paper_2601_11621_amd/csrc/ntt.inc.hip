@@ -73,7 +73,7 @@ __host__ __device__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4)
 // below 2q).  TW (set 1): every output but v[0] is multiplied next by a
 // twiddle (Shoup, any 32-bit input), so the last stage leaves those in
 // [0, 4q) unreduced.
-template <int LOGR, int AS = 0, bool TW = false>
+template <int LOGR, int AS = 0, bool TW = false, bool ZHI = false>
 __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
   const uint32_t p = pc.p;
@@ -86,6 +86,14 @@ __device__ __forceinline__ void dft_fwd(uint32_t* v, const PrimeC& pc) {
       for (int i = 0; i < h; i++) {
         uint32_t a = v[s + i], b = v[s + i + h];
         const int wi = i * (8 / h);   // omega_{2h}^i = omega_16^{i*8/h}
+        if constexpr (ZHI) {
+          if (h == R / 2) {
+            // ZHI: the upper half of the input is zero (a zero-padded
+            // operand), so the first stage gives a and a * w
+            v[s + i + h] = (i == 0) ? a : tw_mul<AS>(a, pc.w16[wi], pc.w16q[wi], p);
+            continue;
+          }
+        }
         if constexpr (AS == 0) {
           v[s + i] = add_mod(a, b, p);
           uint32_t d = sub_mod(a, b, p);
@@ -195,7 +203,7 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t byte_o
   __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)byte_off, 0, 0);
 }
 
-template <int LOGR, bool PAD, int U, int AS>
+template <int LOGR, bool PAD, int U, int AS, bool ZHI = false>
 __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t nthr, uint32_t logSR, uint32_t logC,
                                            const uint2* __restrict__ tw, const PrimeC& pc) {
   constexpr int R = 1 << LOGR;
@@ -206,14 +214,14 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
   for (int u = 0; u < U; u++) {
     b[u] = group_base<LOGR, PAD>(g0 + u * nthr, logSR, logC, &jj[u]);
 #pragma unroll
-    for (int j1 = 0; j1 < R; j1++) v[u][j1] = lds[b[u] + j1 * stride];
+    for (int j1 = 0; j1 < R; j1++) v[u][j1] = (ZHI && j1 >= R / 2) ? 0u : lds[b[u] + j1 * stride];
   }
   // (j2 = 0 reads the pair of 1, which multiplies exactly: no divergent
   // branch around the twiddles)
 #pragma unroll
   for (int u = 0; u < U; u++) {
     if (logSR > 0) {
-      dft_fwd<LOGR, AS, true>(v[u], pc);
+      dft_fwd<LOGR, AS, true, ZHI>(v[u], pc);
       const uint32_t jo = jj[u] * (uint32_t)sizeof(uint2);
       const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << logSR);
 #pragma unroll
@@ -223,7 +231,7 @@ __device__ __forceinline__ void groups_fwd(uint32_t* lds, uint32_t g0, uint32_t 
         v[u][r] = tw_mul<AS>(v[u][r], t.x, t.y, pc.p);
       }
     } else {
-      dft_fwd<LOGR, AS, false>(v[u], pc);
+      dft_fwd<LOGR, AS, false, ZHI>(v[u], pc);
     }
   }
 #pragma unroll
@@ -271,13 +279,13 @@ __device__ __forceinline__ void groups_inv(uint32_t* lds, uint32_t g0, uint32_t 
 
 // Thread `tid` of the `nthr` threads that share the tile (the workgroup, or
 // one prime's part of a workgroup that holds several tiles).
-template <int LOGR, bool PAD, int AS>
+template <int LOGR, bool PAD, int AS, bool ZHI = false>
 __device__ __forceinline__ void pass_fwd(uint32_t* lds, uint32_t ngroups, uint32_t logSR, uint32_t logC,
                                          const uint2* __restrict__ tw, const PrimeC& pc, uint32_t tid,
                                          uint32_t nthr) {
   uint32_t g = tid;
-  for (; g + nthr < ngroups; g += 2 * nthr) groups_fwd<LOGR, PAD, 2, AS>(lds, g, nthr, logSR, logC, tw, pc);
-  for (; g < ngroups; g += nthr) groups_fwd<LOGR, PAD, 1, AS>(lds, g, nthr, logSR, logC, tw, pc);
+  for (; g + nthr < ngroups; g += 2 * nthr) groups_fwd<LOGR, PAD, 2, AS, ZHI>(lds, g, nthr, logSR, logC, tw, pc);
+  for (; g < ngroups; g += nthr) groups_fwd<LOGR, PAD, 1, AS, ZHI>(lds, g, nthr, logSR, logC, tw, pc);
 }
 
 template <int LOGR, bool PAD, int AS>
@@ -317,21 +325,34 @@ __device__ __forceinline__ void pass_sync(int logSmall, uint32_t logC) {
 // return (logC = 0) thread g of the last pass holds the outputs at
 // [16 g, 16 g + 16) of its groups; the caller synchronises before other
 // threads read them.
+// zhi: the upper half of every sub-problem is zero (zero-padded operands):
+// the first pass reads only the lower half and its first stage multiplies.
 template <bool PAD, int AS = 0>
 __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ tws, const PrimeC& pc, uint32_t tid = threadIdx.x,
-                             uint32_t nthr = blockDim.x) {
+                             uint32_t nthr = blockDim.x, bool zhi = false) {
+  bool firstp = true;
   while (logS > 0) {
     const int lr = pass_logr(logS);
     const uint32_t ng = total >> lr;
     const uint32_t logSR = (uint32_t)(logS - lr);
     const uint2* tw = tws + tws_off(logS);
-    switch (lr) {
-      case 1: pass_fwd<1, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      case 2: pass_fwd<2, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      case 3: pass_fwd<3, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
-      default: pass_fwd<4, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+    if (firstp && zhi) {
+      switch (lr) {
+        case 1: pass_fwd<1, PAD, AS, true>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+        case 2: pass_fwd<2, PAD, AS, true>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+        case 3: pass_fwd<3, PAD, AS, true>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+        default: pass_fwd<4, PAD, AS, true>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      }
+    } else {
+      switch (lr) {
+        case 1: pass_fwd<1, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+        case 2: pass_fwd<2, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+        case 3: pass_fwd<3, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+        default: pass_fwd<4, PAD, AS>(lds, ng, logSR, logC, tw, pc, tid, nthr); break;
+      }
     }
+    firstp = false;
     logS -= lr;
     if (logS > 0) {
       if (lr == 4) pass_sync(logS, logC);   // every later pass has radix 16
@@ -554,10 +575,10 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   if constexpr (BMODE == 2) {
     ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
   } else if (T == TT) {
-    ntt_fwd_tile<true, AS>(lds, logN, 2 * TT, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logN, 2 * TT, 0, tws, pc, threadIdx.x, blockDim.x, packed);
   } else {
-    ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
-    ntt_fwd_tile<true, AS>(lds + lds_pad(TT), logN, T, 0, tws, pc);
+    ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc, threadIdx.x, blockDim.x, packed);
+    ntt_fwd_tile<true, AS>(lds + lds_pad(TT), logN, T, 0, tws, pc, threadIdx.x, blockDim.x, packed);
   }
   // pointwise product on the 16 positions whose forward outputs this thread
   // wrote last (A and B alike), which the first inverse pass reads back in the
@@ -665,11 +686,20 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
   const uint32_t RI = NTT_COL_THREADS >> (lin ? pg.logC : 0);   // rows per step of i
   const uint32_t rowB = 4u << logSig;                           // bytes per row
   const uint32_t off0 = ((uint32_t)base + ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1))) * 4u;
+  // zhi: an operand of at most N/2 limbs leaves the lower half of the rows of
+  // the first pass (rows L/2 .. L-1, tile elements T/2 .. T-1) zero, which
+  // the first radix pass never reads
+  bool zhi = false;
+  if (first) {
+    const MulDesc d0 = dv.get(m);
+    zhi = (uint64_t)(op ? d0.lb : d0.la) <= (N >> 1);
+  }
+  const uint32_t Tl = zhi ? T >> 1 : T;
   // loads in batches of COL_BATCH per thread, all issued before the first use
   if (first && lin) {
     const MulDesc d = dv.get(m);
     const __amdgpu_buffer_rsrc_t rs = words_rsrc(op ? bin + d.b_off : ain + d.a_off, op ? d.lb : d.la);
-    for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
+    for (uint32_t t0 = 0; t0 < Tl; t0 += COL_BATCH * NTT_COL_THREADS) {
       const uint32_t ob = off0 + (t0 >> pg.logC) * rowB;
       uint32_t v[COL_BATCH];
 #pragma unroll
@@ -677,7 +707,7 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
 #pragma unroll
       for (int i = 0; i < COL_BATCH; i++) {
         const uint32_t t = t0 + threadIdx.x + i * NTT_COL_THREADS;
-        if (t < T) lds[t] = in_limb<AS>(v[i], p);
+        if (t < Tl) lds[t] = in_limb<AS>(v[i], p);
       }
     }
   } else if (first) {
@@ -742,7 +772,8 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
     }
   }
   __syncthreads();
-  ntt_fwd_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc);
+  ntt_fwd_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc, threadIdx.x,
+                          blockDim.x, zhi);
   __syncthreads();
   if (!tw) {
     // the pass next to the rows: k_row applies this pass's twiddles
