@@ -123,26 +123,30 @@ __device__ void mark_segment(uint32_t* bits, uint64_t i_lo, uint32_t len, const 
     bits[w] = v;
   }
   __syncthreads();
-  const uint64_t m_lo = 2 * i_lo + 1;
+  // m_lo = 2 i_lo + 1 <= 2n + 1 < 2^32: the first odd multiple q t >= m_lo
+  // (t >= q) comes from one 32-bit division (a 64-bit one is a long software
+  // sequence on the GPU); the product q t may reach 2^32 and stays 64-bit
+  const uint32_t m_lo = (uint32_t)(2 * i_lo + 1);
+  auto first_index = [&](uint32_t q) -> uint64_t {
+    uint32_t t = m_lo / q;
+    if (t * q != m_lo) t++;   // ceil(m_lo / q); before the increment t q <= m_lo
+    if (t < q) t = q;
+    if (!(t & 1)) t++;
+    return ((uint64_t)q * t - 1) / 2 - i_lo;
+  };
   // small odd seeds: every thread marks a share of the multiples of q
   uint32_t k = 1;
   for (; k < nseeds; k++) {
-    uint64_t q = seeds[k];
-    if (q * SIEVE_THREADS > 2 * SIEVE_SEG) break;   // fewer multiples than 2 per thread
-    uint64_t t = (m_lo + q - 1) / q;
-    if (t < q) t = q;
-    if (!(t & 1)) t++;
-    uint64_t idx = (q * t - 1) / 2 - i_lo;
+    const uint32_t q = seeds[k];
+    if ((uint64_t)q * SIEVE_THREADS > 2 * SIEVE_SEG) break;   // fewer multiples than 2 per thread
+    const uint64_t idx = first_index(q);
     for (uint64_t x = idx + (uint64_t)tid * q; x < len; x += (uint64_t)T * q)
       atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
   }
   // large seeds: one thread per prime
   for (uint32_t kk = k + tid; kk < nseeds; kk += T) {
-    uint64_t q = seeds[kk];
-    uint64_t t = (m_lo + q - 1) / q;
-    if (t < q) t = q;
-    if (!(t & 1)) t++;
-    uint64_t idx = (q * t - 1) / 2 - i_lo;
+    const uint32_t q = seeds[kk];
+    const uint64_t idx = first_index(q);
     for (uint64_t x = idx; x < len; x += q)
       atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
   }
