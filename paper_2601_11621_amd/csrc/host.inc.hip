@@ -483,6 +483,7 @@ void build_crt_segs(Stage& s) {
 // ----------------------------------------------------------------------------
 struct Layout {
   uint64_t n = 0, s = 0, i0 = 0, i_end = 0, nseg = 0;
+  int seg_log = SIEVE_SEG_LOG;   // odd numbers per sieve segment (log2)
   // factorial ratios: all primes with v_p(N) > 0 (capacity np_cap) before grouping
   uint64_t np_cap = 0, nchunks = 0;
   size_t P = 0, E = 0, chunk_cnt = 0, chunk_off = 0;      // in uint32 units
@@ -498,6 +499,12 @@ struct Layout {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Sieve segment size of the range of odd indices [i0, i_end): 2^16 odd
+// numbers when that still gives 2^10 segments (four per CU), else 2^14.
+int sieve_seg_log(uint64_t i0, uint64_t i_end) {
+  return (i_end > i0 && i_end - i0 >= (1024ull << SIEVE_SEG_LOG_BIG)) ? SIEVE_SEG_LOG_BIG : SIEVE_SEG_LOG;
+}
+
 // byte offsets inside the control block
 #define CTL_TOP 1024
 #define CTL_ERR 1032
@@ -508,7 +515,8 @@ static_assert(sizeof(GroupTable) <= CTL_TOP, "group table must fit the control b
 // Offsets of every buffer, given the sizes set in L (sieve range, Kmax,
 // post_cap, res2_len, and np_cap / nchunks for ratios).
 Layout layout_finish(Layout L) {
-  L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + SIEVE_SEG - 1) / SIEVE_SEG : 0;
+  const uint64_t seg = 1ull << L.seg_log;
+  L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + seg - 1) / seg : 0;
   // residues of one stage: by default bounded by everything the tree and the
   // post area can hold; callers with long power chains set a tighter bound
   if (L.res_len == 0) L.res_len = std::max(L.Kmax, L.post_cap) + 64;
@@ -535,7 +543,7 @@ Layout layout_finish(Layout L) {
   L.seed_e = take(SEED_MAX * 4) / 4;
   L.seg_cnt = take((L.nseg + 1) * 4) / 4;
   L.seg_off = take((L.nseg + 1) * 4) / 4;
-  L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
+  L.bitmap = take(L.nseg * (seg / 32) * 4) / 4;
   if (L.np_cap) {
     L.P = take(L.np_cap * 4) / 4;
     L.E = take(L.np_cap * 4) / 4;
@@ -567,6 +575,7 @@ Layout make_layout(uint64_t n) {
   // sqrt(2n), each prime power below 2^32: every step of them fits 64 limbs
   // per seed prime.
   L.res2_len = 64 * sb + 4096;
+  L.seg_log = sieve_seg_log(L.i0, L.i_end);
   return layout_finish(L);
 }
 
@@ -1743,17 +1752,28 @@ cat_status run_phase1(const Layout& Ly, char* wb, uint32_t* primes, uint64_t cap
                      gt, (uint32_t*)gt, (uint64_t)Ly.ctl_words);
   LAUNCHCHK();
   if (Ly.nseg > 0) {
-    hipLaunchKernelGGL(k_sieve, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0, Ly.i_end,
-                       (const uint32_t*)(W + Ly.seeds), (const GroupTable*)gt, W + Ly.bitmap, W + Ly.seg_cnt);
+    if (Ly.seg_log == SIEVE_SEG_LOG_BIG)
+      hipLaunchKernelGGL(k_sieve<SIEVE_SEG_LOG_BIG>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0,
+                         Ly.i_end, (const uint32_t*)(W + Ly.seeds), (const GroupTable*)gt, W + Ly.bitmap,
+                         W + Ly.seg_cnt);
+    else
+      hipLaunchKernelGGL(k_sieve<SIEVE_SEG_LOG>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0,
+                         Ly.i_end, (const uint32_t*)(W + Ly.seeds), (const GroupTable*)gt, W + Ly.bitmap,
+                         W + Ly.seg_cnt);
     LAUNCHCHK();
   }
   hipLaunchKernelGGL(k_groups, dim3(1), dim3(1024), 0, st, (uint32_t)Ly.nseg, (const uint32_t*)(W + Ly.seg_cnt),
                      W + Ly.seg_off, (const uint32_t*)(W + Ly.seeds), (const int32_t*)(W + Ly.seed_e), primes, cap, gt);
   LAUNCHCHK();
   if (Ly.nseg > 0) {
-    hipLaunchKernelGGL(k_scatter, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.i0,
-                       (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
-                       primes, cap);
+    if (Ly.seg_log == SIEVE_SEG_LOG_BIG)
+      hipLaunchKernelGGL(k_scatter<SIEVE_SEG_LOG_BIG>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.i0,
+                         (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
+                         primes, cap);
+    else
+      hipLaunchKernelGGL(k_scatter<SIEVE_SEG_LOG>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.i0,
+                         (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
+                         primes, cap);
     LAUNCHCHK();
   }
   *launches += Ly.nseg > 0 ? 4 : 2;
@@ -2145,7 +2165,9 @@ Layout layout_phase1(uint64_t n) {
   L.s = isqrt64(2 * n);
   L.i0 = (L.s + 1) / 2;
   L.i_end = n;
-  L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + SIEVE_SEG - 1) / SIEVE_SEG : 0;
+  L.seg_log = sieve_seg_log(L.i0, L.i_end);
+  const uint64_t seg = 1ull << L.seg_log;
+  L.nseg = L.i_end > L.i0 ? (L.i_end - L.i0 + seg - 1) / seg : 0;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -2156,7 +2178,7 @@ Layout layout_phase1(uint64_t n) {
   L.seed_e = take(SEED_MAX * 4) / 4;
   L.seg_cnt = take((L.nseg + 1) * 4) / 4;
   L.seg_off = take((L.nseg + 1) * 4) / 4;
-  L.bitmap = take(L.nseg * SIEVE_WORDS * 4) / 4;
+  L.bitmap = take(L.nseg * (seg / 32) * 4) / 4;
   L.gtab = take(CTL_READ);
   L.top = L.gtab + CTL_TOP;
   L.err = L.gtab + CTL_ERR;

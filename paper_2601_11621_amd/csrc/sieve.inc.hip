@@ -19,8 +19,12 @@
 // Every group ends up with its primes ascending; G_1 = {seeds with e = 1}
 // followed by the large primes with e = 1.
 
+// Segments of 2^14 odd numbers (2 KB bit maps) by default; ranges of at
+// least 2^10 segments of 2^16 (n above about 6.7e7) use 2^16, which divides
+// the per-seed start computations of a segment over four times the numbers.
 #define SIEVE_SEG_LOG 14
-#define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment
+#define SIEVE_SEG_LOG_BIG 16
+#define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment (default)
 #define SIEVE_WORDS (SIEVE_SEG / 32)
 #define SIEVE_THREADS 256
 #define SEED_MAX 6544                           // pi(65535) = 6542
@@ -113,9 +117,11 @@ __device__ uint32_t build_seeds(uint32_t s, uint8_t* comp, uint32_t* tmp, uint32
 // Bit map of the odd numbers 2i+1, i in [i_lo, i_lo + len), that no odd seed
 // divides (seeds[0] = 2 is skipped; every seed q has q*q above the segment's
 // composites it must strike, so what stays is prime).  bits: SIEVE_WORDS words.
+template <int SL = SIEVE_SEG_LOG>
 __device__ void mark_segment(uint32_t* bits, uint64_t i_lo, uint32_t len, const uint32_t* seeds, uint32_t nseeds) {
+  constexpr uint32_t SEG = 1u << SL, WORDS = SEG / 32;
   const uint32_t T = blockDim.x, tid = threadIdx.x;
-  for (uint32_t w = tid; w < SIEVE_WORDS; w += T) {
+  for (uint32_t w = tid; w < WORDS; w += T) {
     uint32_t b0 = w * 32;
     uint32_t v = 0;
     if (b0 + 32 <= len) v = 0xFFFFFFFFu;
@@ -138,7 +144,7 @@ __device__ void mark_segment(uint32_t* bits, uint64_t i_lo, uint32_t len, const 
   uint32_t k = 1;
   for (; k < nseeds; k++) {
     const uint32_t q = seeds[k];
-    if ((uint64_t)q * SIEVE_THREADS > 2 * SIEVE_SEG) break;   // fewer multiples than 2 per thread
+    if ((uint64_t)q * SIEVE_THREADS > 2 * SEG) break;   // fewer multiples than 2 per thread
     const uint64_t idx = first_index(q);
     for (uint64_t x = idx + (uint64_t)tid * q; x < len; x += (uint64_t)T * q)
       atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
@@ -187,20 +193,22 @@ __global__ void __launch_bounds__(1024) k_seeds(uint64_t n, uint32_t s, uint32_t
 // ---------------------------------------------------------------------------
 // Segment k covers odd indices i in [i0 + k*SEG, min(i0 + (k+1)*SEG, i_end)),
 // i.e. odd numbers m = 2i+1 in (s, 2n].
+template <int SL>
 __global__ void __launch_bounds__(SIEVE_THREADS) k_sieve(uint64_t n, uint64_t i0, uint64_t i_end,
                                                 const uint32_t* seeds, const GroupTable* gt,
                                                 uint32_t* bitmap, uint32_t* seg_cnt) {
-  __shared__ uint32_t bits[SIEVE_WORDS];
+  constexpr uint32_t SEG = 1u << SL, WORDS = SEG / 32;
+  __shared__ uint32_t bits[WORDS];
   __shared__ uint32_t tmp[40];
   const uint32_t T = blockDim.x, tid = threadIdx.x;
-  const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SIEVE_SEG;
-  const uint64_t i_hi = min(i_lo + SIEVE_SEG, i_end);
+  const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SEG;
+  const uint64_t i_hi = min(i_lo + SEG, i_end);
   const uint32_t len = (uint32_t)(i_hi - i_lo);
-  mark_segment(bits, i_lo, len, seeds, gt->nseeds);
+  mark_segment<SL>(bits, i_lo, len, seeds, gt->nseeds);
   // keep primes with e_p = 1, count them
   uint32_t cnt = 0;
   const uint32_t n32 = (uint32_t)n;   // n < 2^31
-  for (uint32_t w = tid; w < SIEVE_WORDS; w += T) {
+  for (uint32_t w = tid; w < WORDS; w += T) {
     uint32_t v = bits[w], keep = 0;
     while (v) {
       uint32_t b = __ffs(v) - 1;
@@ -210,7 +218,7 @@ __global__ void __launch_bounds__(SIEVE_THREADS) k_sieve(uint64_t n, uint64_t i0
       uint32_t e = ((uint64_t)2 * r >= p ? 1u : 0u) - (r == p - 1 ? 1u : 0u);
       if (e == 1) keep |= 1u << b;
     }
-    bitmap[(uint64_t)blockIdx.x * SIEVE_WORDS + w] = keep;
+    bitmap[(uint64_t)blockIdx.x * WORDS + w] = keep;
     cnt += __popc(keep);
   }
   uint32_t total;
@@ -304,13 +312,15 @@ __global__ void __launch_bounds__(1024) k_groups(uint32_t nseg, const uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
+template <int SL>
 __global__ void __launch_bounds__(SIEVE_THREADS) k_scatter(uint64_t i0, const uint32_t* bitmap, const uint32_t* seg_off,
                                                   const GroupTable* gt, uint32_t* primes, uint64_t cap) {
   __shared__ uint32_t tmp[40];
   const uint32_t tid = threadIdx.x;
-  constexpr uint32_t WPT = SIEVE_WORDS / SIEVE_THREADS;   // words per thread
-  const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SIEVE_SEG;
-  const uint32_t* bm = bitmap + (uint64_t)blockIdx.x * SIEVE_WORDS;
+  constexpr uint32_t SEG = 1u << SL, WORDS = SEG / 32;
+  constexpr uint32_t WPT = WORDS / SIEVE_THREADS;   // words per thread
+  const uint64_t i_lo = i0 + (uint64_t)blockIdx.x * SEG;
+  const uint32_t* bm = bitmap + (uint64_t)blockIdx.x * WORDS;
   uint32_t w[WPT];
   uint32_t c = 0;
 #pragma unroll
