@@ -1491,14 +1491,19 @@ cat_status launch_products(Exec& X, const Stage& s, DescView dv, uint64_t cnt, b
   {
     // row DFTs: two forward and one inverse per row, 3 primes
     const double rows = (double)cnt * (1ull << logR1);
-    const int lt = std::max(logM, CAT_LDS_LOGT);
+    // rows of 2^11 run in their own tile (full rows, 128 threads); shorter
+    // rows share the 2^12 tile
+    const int lt = logM == 11 ? 11 : std::max(logM, CAT_LDS_LOGT);
     const dim3 block((1u << lt) / 16);
     auto row = [&](uint64_t nprod, int bmode) {
       const dim3 grid((uint32_t)(nprod << logR1), CAT_NPRIMES);
 #define ROW(LT, A)                                                                                              \
   hipLaunchKernelGGL((k_row<LT, A>), grid, block, 0, X.st, s.logN, logM, pp.logS[pp.P - 1], pp.logL[pp.P - 1], \
                      bmode, X.F, tb, s0, s1, s2)
-      if (lt == 12) {
+      if (lt == 11) {
+        if (as == 0) ROW(11, 0);
+        else ROW(11, 1);
+      } else if (lt == 12) {
         if (as == 0) ROW(12, 0);
         else ROW(12, 1);
       } else if (lt == 13) {

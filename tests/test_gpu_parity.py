@@ -287,7 +287,17 @@ def _schedule_wide(t):
         t["log_pass"][k] = 8
 
 
-@pytest.mark.parametrize("schedule", [_schedule_short, _schedule_wide], ids=["short", "wide"])
+def _schedule_rows11(t):
+    """four-step transforms with rows of 2^11 words (the 128-thread row tile)
+    from 2^12 up"""
+    for k in range(12, 28):
+        t["cls"][k] = 2
+        t["log_row"][k] = 11
+        t["log_pass"][k] = 10 if k < 24 else 8
+
+
+@pytest.mark.parametrize("schedule", [_schedule_short, _schedule_wide, _schedule_rows11],
+                         ids=["short", "wide", "rows11"])
 def test_schedules_change_speed_not_bits(cat, schedule):
     """A non-default product schedule gives the same C(n) and the same
     products as the default one."""
