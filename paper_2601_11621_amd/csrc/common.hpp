@@ -36,12 +36,11 @@ struct PrimeC {
 };
 
 struct CrtC {
-  // Garner: x0 = r0; x1 = (r1 - x0) * c01 mod p1; x2 = (r2 - x0 - p0*x1) * c012 mod p2
+  // Garner: x0 = r0; x1 = (r1 - x0) * c01 mod p1; x2 = (r2 - x0) * c012 - x1 * c12 mod p2
   uint32_t c01, c01q;       // p0^-1 mod p1 (Montgomery pair for p1)
-  uint32_t p0m2, p0m2q;     // p0 mod p2 (Montgomery pair for p2)
+  uint32_t c12, c12q;       // p1^-1 mod p2 (Montgomery pair for p2)
   uint32_t c012, c012q;     // (p0*p1)^-1 mod p2 (Montgomery pair for p2)
-  uint32_t p0;              // p0
-  uint32_t p01_lo, p01_hi;  // p0*p1 as 64-bit
+  uint32_t p0, p1;
 };
 
 // ----------------------------------------------------------------------------

@@ -222,13 +222,11 @@ cat_status init_prime_set(int as, const uint32_t* P, const uint32_t* G, int maxl
     CrtC& c = S.crt;
     const uint32_t p0 = P[0], p1 = P[1], p2 = P[2];
     h_pair(h_inv(p0 % p1, p1), S.prc[1], &c.c01, &c.c01q);
-    h_pair(p0 % p2, S.prc[2], &c.p0m2, &c.p0m2q);
+    h_pair(h_inv(p1 % p2, p2), S.prc[2], &c.c12, &c.c12q);
     const uint32_t p01m2 = h_mulmod(p0 % p2, p1 % p2, p2);
     h_pair(h_inv(p01m2, p2), S.prc[2], &c.c012, &c.c012q);
     c.p0 = p0;
-    const uint64_t p01 = (uint64_t)p0 * p1;
-    c.p01_lo = (uint32_t)p01;
-    c.p01_hi = (uint32_t)(p01 >> 32);
+    c.p1 = p1;
   }
   if (as == 0) {
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_primes), S.prc, sizeof(S.prc)));

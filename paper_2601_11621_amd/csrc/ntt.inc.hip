@@ -1061,6 +1061,9 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
 
 // ---------------------------------------------------------------------------
 // Garner CRT of the three residues into V = x0 + p0*x1 + p0*p1*x2 < 2^96.
+// x2 = (r2 - x0) (p0 p1)^-1 - x1 p1^-1 mod p2 (both products independent of
+// each other), and V in Horner form x0 + p0 (x1 + p1 x2): three 32x32+32-bit
+// multiply-adds, none of which can overflow 64 bits.
 template <int AS = 0>
 __device__ __forceinline__ void garner3(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t& v0, uint32_t& v1,
                                         uint32_t& v2) {
@@ -1068,17 +1071,14 @@ __device__ __forceinline__ void garner3(uint32_t r0, uint32_t r1, uint32_t r2, u
   const uint32_t P1 = primec<AS>(1).p, P2 = primec<AS>(2).p;
   const uint32_t x0 = r0;
   const uint32_t x1 = mul_tw(sub_mod(r1, x0, P1), c_crt.c01, c_crt.c01q, P1);
-  const uint32_t t = mul_tw(x1, c_crt.p0m2, c_crt.p0m2q, P2);
-  const uint32_t y = add_mod(x0, t, P2);
-  const uint32_t x2 = mul_tw(sub_mod(r2, y, P2), c_crt.c012, c_crt.c012q, P2);
-  const uint64_t a = (uint64_t)c_crt.p0 * x1 + x0;
-  const uint64_t lo = (uint64_t)c_crt.p01_lo * x2;
-  const uint64_t hi = (uint64_t)c_crt.p01_hi * x2;
-  const uint64_t s0 = (a & 0xFFFFFFFFull) + (lo & 0xFFFFFFFFull);
-  const uint64_t s1 = (a >> 32) + (lo >> 32) + (hi & 0xFFFFFFFFull) + (s0 >> 32);
-  v0 = (uint32_t)s0;
-  v1 = (uint32_t)s1;
-  v2 = (uint32_t)((hi >> 32) + (s1 >> 32));
+  const uint32_t e = mul_tw(sub_mod(r2, x0, P2), c_crt.c012, c_crt.c012q, P2);
+  const uint32_t x2 = sub_mod(e, mul_tw(x1, c_crt.c12, c_crt.c12q, P2), P2);
+  const uint64_t t = (uint64_t)c_crt.p1 * x2 + x1;                        // < p1 p2
+  const uint64_t m1 = (uint64_t)c_crt.p0 * (uint32_t)t + x0;
+  const uint64_t m2 = (uint64_t)c_crt.p0 * (uint32_t)(t >> 32) + (uint32_t)(m1 >> 32);
+  v0 = (uint32_t)m1;
+  v1 = (uint32_t)m2;
+  v2 = (uint32_t)(m2 >> 32);
 }
 
 // Carry resolution.  Given 96-bit column values V(k) = v0 + v1 2^32 + v2 2^64,
@@ -1154,7 +1154,10 @@ struct SegView {
 // the call; the flags are cleared when the call starts) and reads its
 // predecessor's; a pair that has not appeared after a few polls is recomputed
 // from that block's residues instead, so no block ever waits on another
-// (nothing is assumed about which workgroups run at the same time).
+// (nothing is assumed about which workgroups run at the same time).  Most
+// blocks need none of this: the u of the few positions below the block, which
+// they compute anyway for their left context, decide the carry in unless all
+// of them propagate.
 #define CAT_SCAN_POLLS 16   // default number of polls of a predecessor's flag
 
 // A thread's CAT_CRT_E consecutive words: one vector access in a block that
@@ -1163,106 +1166,126 @@ struct CrtWords {
   uint32_t w[CAT_CRT_E];
 };
 
-// Values V of this thread's CAT_CRT_E positions of the block starting at kb,
-// their sums u and the thread's (G, P); wave pairs go to tmp[wave].  V is
-// Garner's recombination of the three residues, or (RAW) the three words
-// themselves when they already hold V = v0 + v1 2^32 + v2 2^64 (exact column
-// sums of a schoolbook product).
+// V of one position: Garner's recombination of its three residues, or (RAW)
+// the three words themselves when they already hold V = v0 + v1 2^32 + v2 2^64
+// (exact column sums of a schoolbook product).  Zero residues give V = 0.
+template <bool RAW, int AS>
+__device__ __forceinline__ void crt_value(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t& a0, uint32_t& a1,
+                                          uint32_t& a2) {
+  if constexpr (RAW) {
+    a0 = x0;
+    a1 = x1;
+    a2 = x2;
+  } else {
+    garner3<AS>(x0, x1, x2, a0, a1, a2);
+  }
+}
+
+// s = a + b + c as s mod 2^32 and the carry h = s >> 32 (h <= 2)
+__device__ __forceinline__ uint32_t col_sum(uint32_t a, uint32_t b, uint32_t c, uint32_t* h) {
+  unsigned c1, c2;
+  const uint32_t t = __builtin_addc(a, b, 0u, &c1);
+  const uint32_t s = __builtin_addc(t, c, 0u, &c2);
+  *h = c1 + c2;
+  return s;
+}
+
+// The thread's CAT_CRT_E positions k0 .. k0+E-1 of the block starting at kb:
+// u_k mod 2^32 in ul, the generate bits in gk, the thread's (G, P); wave pairs
+// go to tmp[wave].  Column k needs V0(k), V1(k-1), V2(k-2) and the carry
+// y_{k-1} of column k-1; from its left neighbour a thread takes V1(k0-1),
+// V2(k0-1), V2(k0-2) and y_{k0-1} (which the neighbour has for its own last
+// column), through xv[tid] = {V1, V2, V2', y}.  For thread 0 the first
+// CRT_CTX lanes of the first wave recompute positions kb-CRT_CTX .. kb-1 from
+// their residues.  Their u (positions kb-CRT_CTX+3 .. kb-1) also decide the
+// carry into the block unless every one of them propagates: the carry out of
+// position kb-1 is the generate bit of the highest position below kb that
+// does not propagate.  *spec gets that carry (0 or 1), or 2 when undecided.
+#define CRT_CTX 16
 template <bool RAW, int AS>
 __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __restrict__ r0,
                                           const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
-                                          uint64_t kb, uint32_t (*xv)[9], uint32_t* tmp, uint64_t* u, bool* Gt,
-                                          bool* Pt) {
+                                          uint64_t kb, uint4* xv, uint32_t* tmp, uint32_t* ul, bool* gk, bool* Gt,
+                                          bool* Pt, uint32_t* spec) {
+  static_assert(CAT_CRT_E >= 3, "a thread's last column must lie inside the thread");
   const uint32_t tid = threadIdx.x;
   const uint64_t k0 = kb + (uint64_t)tid * CAT_CRT_E;
-  // V for positions k0-3 .. k0+E-1: the thread's own E, the 3 before it from
-  // its left neighbour (for thread 0 the block's left context kb-3 .. kb-1,
-  // recomputed from the residues by threads 0, 1 and 2, one position each)
-  uint32_t v0[CAT_CRT_E + 3], v1[CAT_CRT_E + 3], v2[CAT_CRT_E + 3];
-  const bool lctx = tid < 3 && kb + tid >= 3;
+  const bool lctx = tid < CRT_CTX && kb + tid >= CRT_CTX;
+  uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E];
   uint32_t y0 = 0, y1 = 0, y2 = 0;
-  {
-    // the thread's 3*E residue loads, and its left-context position, in
-    // flight together (clamped addresses; positions past the segment count
-    // as zero)
-    uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E];
-    if (kb + CAT_CRT_BLOCK <= sg.len) {
-      const CrtWords a0 = *(const CrtWords*)(r0 + k0), a1 = *(const CrtWords*)(r1 + k0),
-                     a2 = *(const CrtWords*)(r2 + k0);
-#pragma unroll
-      for (int i = 0; i < CAT_CRT_E; i++) {
-        x0[i] = a0.w[i];
-        x1[i] = a1.w[i];
-        x2[i] = a2.w[i];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < CAT_CRT_E; i++) {
-        const uint64_t k = k0 + i;
-        const uint64_t kc = k < sg.len ? k : 0;
-        x0[i] = r0[kc];
-        x1[i] = r1[kc];
-        x2[i] = r2[kc];
-      }
-    }
-    if (tid < 3) {
-      const uint64_t kl = lctx ? kb + tid - 3 : 0;
-      y0 = r0[kl];
-      y1 = r1[kl];
-      y2 = r2[kl];
-    }
+  // the thread's 3*E residue loads, and its left-context position, in flight
+  // together; positions past the segment read as zero residues (V = 0)
+  if (kb + CAT_CRT_BLOCK <= sg.len) {
+    const CrtWords a0 = *(const CrtWords*)(r0 + k0), a1 = *(const CrtWords*)(r1 + k0),
+                   a2 = *(const CrtWords*)(r2 + k0);
 #pragma unroll
     for (int i = 0; i < CAT_CRT_E; i++) {
-      if (k0 + i < sg.len) {
-        if constexpr (RAW) {
-          v0[i + 3] = x0[i];
-          v1[i + 3] = x1[i];
-          v2[i + 3] = x2[i];
-        } else {
-          garner3<AS>(x0[i], x1[i], x2[i], v0[i + 3], v1[i + 3], v2[i + 3]);
-        }
-      }
-      else { v0[i + 3] = 0; v1[i + 3] = 0; v2[i + 3] = 0; }
+      x0[i] = a0.w[i];
+      x1[i] = a1.w[i];
+      x2[i] = a2.w[i];
     }
+  } else {
+#pragma unroll
+    for (int i = 0; i < CAT_CRT_E; i++) {
+      const uint64_t k = k0 + i;
+      const bool in = k < sg.len;
+      const uint64_t kc = in ? k : 0;
+      const uint32_t msk = in ? 0xFFFFFFFFu : 0u;
+      x0[i] = r0[kc] & msk;
+      x1[i] = r1[kc] & msk;
+      x2[i] = r2[kc] & msk;
+    }
+  }
+  if (tid < CRT_CTX) {
+    const uint64_t kl = lctx ? kb + tid - CRT_CTX : 0;
+    const uint32_t msk = lctx ? 0xFFFFFFFFu : 0u;
+    y0 = r0[kl] & msk;
+    y1 = r1[kl] & msk;
+    y2 = r2[kl] & msk;
+  }
+  uint32_t a0[CAT_CRT_E], a1[CAT_CRT_E], a2[CAT_CRT_E];
+#pragma unroll
+  for (int i = 0; i < CAT_CRT_E; i++) crt_value<RAW, AS>(x0[i], x1[i], x2[i], a0[i], a1[i], a2[i]);
+  uint32_t lo[CAT_CRT_E], h[CAT_CRT_E];
+#pragma unroll
+  for (int i = 2; i < CAT_CRT_E; i++) lo[i] = col_sum(a0[i], a1[i - 1], a2[i - 2], &h[i]);
+  // the block's context: lane l of the first wave holds V(kb-CRT_CTX+l) for
+  // l < CRT_CTX (zero outside the segment)
+  uint4 bctx = make_uint4(0, 0, 0, 0);
+  uint32_t sp = 2;
+  if (tid < 64) {
+    uint32_t c0, c1, c2;
+    crt_value<RAW, AS>(y0, y1, y2, c0, c1, c2);
+    const uint32_t b1 = __shfl_up(c1, 1, 64), b2 = __shfl_up(c2, 1, 64), d2 = __shfl_up(c2, 2, 64);
+    uint32_t hh;
+    const uint32_t cl = col_sum(c0, b1, d2, &hh);   // column kb-CRT_CTX+l (lanes >= 2)
+    const uint32_t hq = __shfl_up(hh, 1, 64);
+    unsigned g;
+    const uint32_t cu = __builtin_addc(cl, hq, 0u, &g);   // u of that position (lanes >= 3)
+    const bool valid = tid >= 3 && tid < CRT_CTX;
+    const uint64_t gm = __ballot(valid && g != 0);
+    const uint64_t dm = gm | __ballot(valid && g == 0 && cu != 0xFFFFFFFFu);
+    if (dm) sp = (uint32_t)((gm >> (63 - __builtin_clzll(dm))) & 1ull);
+    bctx = make_uint4(c1, c2, b2, hh);
   }
   __syncthreads();   // xv may still be read by a previous call
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    xv[tid + 1][3 * i + 0] = v0[CAT_CRT_E + i];
-    xv[tid + 1][3 * i + 1] = v1[CAT_CRT_E + i];
-    xv[tid + 1][3 * i + 2] = v2[CAT_CRT_E + i];
-  }
-  if (tid < 3) {
-    uint32_t a0 = 0, a1 = 0, a2 = 0;
-    if (lctx) {
-      if constexpr (RAW) {
-        a0 = y0;
-        a1 = y1;
-        a2 = y2;
-      } else {
-        garner3<AS>(y0, y1, y2, a0, a1, a2);
-      }
-    }
-    xv[0][3 * tid + 0] = a0;
-    xv[0][3 * tid + 1] = a1;
-    xv[0][3 * tid + 2] = a2;
-  }
+  xv[tid + 1] = make_uint4(a1[CAT_CRT_E - 1], a2[CAT_CRT_E - 1], a2[CAT_CRT_E - 2], h[CAT_CRT_E - 1]);
+  if (tid == CRT_CTX - 1) xv[0] = bctx;
+  if (tid == 0) *spec = sp;
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    v0[i] = xv[tid][3 * i + 0];
-    v1[i] = xv[tid][3 * i + 1];
-    v2[i] = xv[tid][3 * i + 2];
-  }
-  uint32_t yprev = (uint32_t)(((uint64_t)v0[2] + v1[1] + v2[0]) >> 32);   // position k0-1
+  const uint4 z = xv[tid];
+  lo[0] = col_sum(a0[0], z.x, z.z, &h[0]);
+  lo[1] = col_sum(a0[1], a1[0], z.y, &h[1]);
   bool G = false, P = true;
+  uint32_t hp = z.w;
 #pragma unroll
   for (int i = 0; i < CAT_CRT_E; i++) {
-    const uint64_t s = (uint64_t)v0[i + 3] + v1[i + 2] + v2[i + 1];
-    u[i] = (s & 0xFFFFFFFFull) + yprev;
-    yprev = (uint32_t)(s >> 32);
-    const bool g = u[i] >= (1ull << 32), pr = u[i] == 0xFFFFFFFFull;
-    G = g || (pr && G);
+    unsigned g;
+    ul[i] = __builtin_addc(lo[i], hp, 0u, &g);
+    hp = h[i];
+    gk[i] = g != 0;
+    const bool pr = ul[i] == 0xFFFFFFFFu;
+    G = gk[i] || (pr && G);
     P = P && pr;
   }
   *Gt = G;
@@ -1291,8 +1314,8 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
       uint32_t* __restrict__ flags, uint32_t epoch, uint32_t polls, CopyList tails, const uint32_t* __restrict__ tin,
       uint32_t* __restrict__ tout, uint32_t* __restrict__ err) {
   __shared__ uint32_t tmp[16], tmp2[16];
-  __shared__ uint32_t xv[CAT_CRT_THREADS + 1][9];   // last three V of each thread
-  __shared__ uint32_t s_state, s_pair;
+  __shared__ uint4 xv[CAT_CRT_THREADS + 1];   // each thread's context for its right neighbour
+  __shared__ uint32_t s_state, s_pair, s_spec, s_spec2;
   const uint32_t b = blockIdx.x, tid = threadIdx.x;
   if (b >= nblk) {
     copy_tail_block(tails, tin, tout, b - nblk);
@@ -1305,15 +1328,22 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
   const uint32_t* r1 = r0 + res_stride;
   const uint32_t* r2 = r1 + res_stride;
   const uint64_t kb = (uint64_t)(b - first) * CAT_CRT_BLOCK;
-  uint64_t u[CAT_CRT_E];
+  uint32_t ul[CAT_CRT_E];
+  bool gk[CAT_CRT_E];
   bool G, P;
-  crt_local<RAW, AS>(sg, r0, r1, r2, kb, xv, tmp, u, &G, &P);
+  crt_local<RAW, AS>(sg, r0, r1, r2, kb, xv, tmp, ul, gk, &G, &P, &s_spec);
   const uint32_t own = crt_block_pair(tmp);
   if (tid == 0)
     __hip_atomic_store(flags + b, (epoch << 3) | (own << 1) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // look back over the predecessors k = b-1, b-2, ... >= first (block-uniform)
+  // the carry in from the positions just below the block when they decide
+  // it, else a look-back over the predecessors k = b-1, b-2, ... >= first
+  // (block-uniform)
   uint32_t cin = 0, k = b;
   bool done = (b == first);
+  if (!done && s_spec < 2u) {
+    cin = s_spec;
+    done = true;
+  }
   while (!done) {
     k--;
     if (tid == 0) {
@@ -1333,9 +1363,11 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
     __syncthreads();
     if (state == 2u) {
       // not published yet: recompute block k's pair from its residues
-      uint64_t u2[CAT_CRT_E];
+      uint32_t ul2[CAT_CRT_E];
+      bool gk2[CAT_CRT_E];
       bool G2, P2;
-      crt_local<RAW, AS>(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      crt_local<RAW, AS>(sg, r0, r1, r2, (uint64_t)(k - first) * CAT_CRT_BLOCK, xv, tmp2, ul2, gk2, &G2, &P2,
+                         &s_spec2);
       pair = crt_block_pair(tmp2);
     }
     if (pair & 1u) { cin = 1; done = true; }           // block k generates a carry
@@ -1357,9 +1389,9 @@ k_crt(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint32_
   CrtWords r;
 #pragma unroll
   for (int i = 0; i < CAT_CRT_E; i++) {
-    const uint64_t t = u[i] + c;
-    c = (uint32_t)(t >> 32);
-    r.w[i] = (uint32_t)t;
+    unsigned co;
+    r.w[i] = __builtin_addc(ul[i], 0u, c, &co);
+    c = (co | (gk[i] ? 1u : 0u));
   }
   if (kb + CAT_CRT_BLOCK <= sg.len) {
     *(CrtWords*)(o + k0) = r;

@@ -267,6 +267,52 @@ def test_carry_lookback_recompute(cat, polls):
         cat.set_lookback_polls(None)
 
 
+def _carry_run(runs):
+    """limbs 5, 3, 3, ..., 3 per run: times 2^32 - 1, the position after the
+    first 3 of a run generates a carry and every later position of the run
+    propagates it (pre-carry value 2^32 - 1)"""
+    a = []
+    for r in runs:
+        a += [5] + [3] * r
+    return np.array(a, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("polls", [None, 0, 16])
+def test_carry_runs_across_blocks(cat, polls):
+    """Carries that cross many whole CRT blocks: the positions just below a
+    block do not decide its carry in, so the block looks back over its
+    predecessors (or recomputes them).  Products from every transform class
+    and from exact column sums, against the oracle."""
+    mixed = [10, 12, 13, 14, 20, 767, 768, 769, 2000] * 4
+    cases = [
+        (_carry_run([300000]), 5000),     # four-step transform, one carry through 300,000 limbs
+        (_carry_run([40000]), 5000),
+        (_carry_run(mixed), 5000),        # runs ending at every offset around the block edges
+        (_carry_run([8000]), 100),        # one-workgroup transform
+        (_carry_run([40000]), 1),         # column sums (long times one limb)
+        (np.full(50000, 0xFFFFFFFF, dtype=np.uint32), 3000),   # propagate everywhere, no carry
+    ]
+    a = [x for x, _ in cases]
+    b = [np.concatenate([[0xFFFFFFFF], np.zeros(lb - 1, dtype=np.uint32)]).astype(np.uint32) for _, lb in cases]
+    la = [len(x) for x in a]
+    lb = [len(x) for x in b]
+    a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
+    af, bf = np.concatenate(a), np.concatenate(b)
+    oc, oc_off = oracle.mul_batched(af, a_off, bf, b_off)
+    try:
+        cat.set_lookback_polls(polls)
+        for mode in ("batched", "plain"):
+            c, c_off = cat.mul_batched(cat.from_numpy(af), a_off, cat.from_numpy(bf), b_off, mode=mode)
+            assert np.array_equal(c_off, oc_off)
+            got = cat.to_numpy(c)
+            for i in range(len(cases)):
+                s, e = int(c_off[i]), int(c_off[i + 1])
+                assert np.array_equal(got[s:e], oc[s:e]), (i, la[i], lb[i], mode)
+    finally:
+        cat.set_lookback_polls(None)
+
+
 def _schedule_short(t):
     """small schoolbook threshold, four-step transforms with short rows and
     short column passes from 2^11 up"""
