@@ -72,20 +72,24 @@ __device__ __forceinline__ void dec_split(uint32_t r0, uint32_t r1, uint32_t r2,
 // the carries left are binary: generate u_k >= B, propagate u_k = B - 1.
 // Thread positions k0 .. k0+E-1; the four components of the positions
 // k0-4 .. k0-1 that enter these sums (10 words) come from the left neighbour
-// (thread 0: recomputed from the residues).
+// (thread 0: recomputed from the residues by the first DEC_CTX lanes, one
+// position kb-DEC_CTX+l each).  As in the binary carry step, the u of those
+// positions decide the carry into the block unless all of them propagate:
+// *spec gets that carry, or 2 when undecided.
 #define DEC_XV 10
+#define DEC_CTX 16
 __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __restrict__ r0,
                                             const uint32_t* __restrict__ r1, const uint32_t* __restrict__ r2,
                                             const uint32_t* __restrict__ add, uint64_t kb, uint32_t (*xv)[DEC_XV],
-                                            uint32_t* tmp, uint64_t* u, bool* Gt, bool* Pt) {
+                                            uint32_t* tmp, uint64_t* u, bool* Gt, bool* Pt, uint32_t* spec) {
   const uint32_t tid = threadIdx.x;
   const uint64_t k0 = kb + (uint64_t)tid * DEC_CRT_E;
   // c[i][.] for positions k0-4+i (i < 4 from the neighbour, own from i = 4)
   uint32_t c[DEC_CRT_E + 4][4];
-  // threads 0..3 also fetch the block's left context kb-4 .. kb-1, one
-  // position each, with their own loads
-  const int64_t kl = (int64_t)kb - 4 + (int64_t)tid;
-  const bool lctx = tid < 4 && kl >= 0 && (uint64_t)kl < sg.len;
+  // the first DEC_CTX lanes also fetch the block's left context
+  // kb-DEC_CTX .. kb-1, one position each, with their own loads
+  const int64_t kl = (int64_t)kb - DEC_CTX + (int64_t)tid;
+  const bool lctx = tid < DEC_CTX && kl >= 0 && (uint64_t)kl < sg.len;
   uint32_t y0 = 0, y1 = 0, y2 = 0, ya = 0;
   {
     uint32_t x0[DEC_CRT_E], x1[DEC_CRT_E], x2[DEC_CRT_E], xa[DEC_CRT_E];
@@ -98,7 +102,7 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
       x2[i] = r2[kc];
       xa[i] = add[sg.add_pos + (k < sg.add_len ? k : 0)];
     }
-    if (tid < 4) {
+    if (tid < DEC_CTX) {
       const uint64_t kc = lctx ? (uint64_t)kl : 0;
       y0 = r0[kc];
       y1 = r1[kc];
@@ -124,15 +128,29 @@ __device__ __forceinline__ void crt_local10(const CrtSeg& sg, const uint32_t* __
     o[7] = c[e + 1][2]; o[8] = c[e + 1][3];
     o[9] = c[e][3];
   }
-  if (tid < 4) {
-    // threads 0..3 recompute positions kb-4 .. kb-1, one each
+  if (tid < 64) {
+    // lane l < DEC_CTX recomputes position kb-DEC_CTX+l (zero outside the
+    // segment); the last lane gathers the block's context, and the u of the
+    // lanes from 4 on decide the carry in when one of them does not propagate
     uint32_t q[4] = {0, 0, 0, 0};
     if (lctx) dec_split(y0, y1, y2, (uint64_t)kl < sg.add_len ? ya : 0u, q);
-    uint32_t* o = xv[0];
-    if (tid == 3) { o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; }
-    if (tid == 2) { o[4] = q[1]; o[5] = q[2]; o[6] = q[3]; }
-    if (tid == 1) { o[7] = q[2]; o[8] = q[3]; }
-    if (tid == 0) o[9] = q[3];
+    const uint32_t q1a = __shfl_up(q[1], 1, 64), q2a = __shfl_up(q[2], 1, 64), q3a = __shfl_up(q[3], 1, 64);
+    const uint32_t q2b = __shfl_up(q[2], 2, 64), q3b = __shfl_up(q[3], 2, 64), q3c = __shfl_up(q[3], 3, 64);
+    const uint32_t sl = q[0] + q1a + q2b + q3c;   // digit sum of the lane's position (lanes >= 3)
+    const uint32_t yl = (sl >= DEC_B) + (sl >= 2 * DEC_B) + (sl >= 3 * DEC_B);
+    const uint32_t yp = __shfl_up(yl, 1, 64);
+    const uint32_t ul = sl - yl * DEC_B + yp;     // u of the lane's position (lanes >= 4)
+    const bool valid = tid >= 4 && tid < DEC_CTX;
+    const uint64_t gm = __ballot(valid && ul >= DEC_B);
+    const uint64_t dm = gm | __ballot(valid && ul < DEC_B - 1);
+    if (tid == 0) *spec = dm ? (uint32_t)((gm >> (63 - __builtin_clzll(dm))) & 1ull) : 2u;
+    if (tid == DEC_CTX - 1) {
+      uint32_t* o = xv[0];
+      o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3];
+      o[4] = q1a; o[5] = q2a; o[6] = q3a;
+      o[7] = q2b; o[8] = q3b;
+      o[9] = q3c;
+    }
   }
   __syncthreads();
   {
@@ -174,7 +192,7 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
         uint32_t* __restrict__ err) {
   __shared__ uint32_t tmp[16], tmp2[16];
   __shared__ uint32_t xv[DEC_CRT_THREADS + 1][DEC_XV];
-  __shared__ uint32_t s_state, s_pair;
+  __shared__ uint32_t s_state, s_pair, s_spec, s_spec2;
   const uint32_t b = blockIdx.x, tid = threadIdx.x;
   if (b >= nblk) {
     copy_tail_block(tails, tin, tout, b - nblk);
@@ -189,12 +207,16 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
   const uint64_t kb = (uint64_t)(b - first) * DEC_CRT_BLOCK;
   uint64_t u[DEC_CRT_E];
   bool G, P;
-  crt_local10(sg, r0, r1, r2, add, kb, xv, tmp, u, &G, &P);
+  crt_local10(sg, r0, r1, r2, add, kb, xv, tmp, u, &G, &P, &s_spec);
   const uint32_t own = crt_block_pair(tmp);
   if (tid == 0)
     __hip_atomic_store(flags + b, (epoch << 3) | (own << 1) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t cin = 0, k = b;
   bool done = (b == first);
+  if (!done && s_spec < 2u) {
+    cin = s_spec;
+    done = true;
+  }
   while (!done) {
     k--;
     if (tid == 0) {
@@ -215,7 +237,7 @@ k_crt10(SegView sv, const uint32_t* __restrict__ res, uint64_t res_stride, uint3
     if (state == 2u) {
       uint64_t u2[DEC_CRT_E];
       bool G2, P2;
-      crt_local10(sg, r0, r1, r2, add, (uint64_t)(k - first) * DEC_CRT_BLOCK, xv, tmp2, u2, &G2, &P2);
+      crt_local10(sg, r0, r1, r2, add, (uint64_t)(k - first) * DEC_CRT_BLOCK, xv, tmp2, u2, &G2, &P2, &s_spec2);
       pair = crt_block_pair(tmp2);
     }
     if (pair & 1u) { cin = 1; done = true; }
