@@ -946,6 +946,36 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
     for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
 }
 
+// The outermost radix-16 pass of a 2^12-point tile on registers: group j
+// (elements j + 256 k, k < 16) is what thread j of a full 2^12 row loads and
+// stores, so the first forward pass can start from the loaded values and the
+// last inverse pass can end in the stored ones.  Same arithmetic as
+// groups_fwd / groups_inv at logSR = 8.
+template <int AS>
+__device__ __forceinline__ void row_pass_fwd(uint32_t* v, uint32_t j, const uint2* __restrict__ tw, const PrimeC& pc) {
+  dft_fwd<4, AS, true, false>(v, pc);
+  const uint32_t jo = j * (uint32_t)sizeof(uint2);
+  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, 16u << 8);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; k1++) {
+    const uint2 t = tw_at(rs, (uint32_t)k1, 8, jo);
+    const int r = brev_c(k1, 4);
+    v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+  }
+}
+template <int AS>
+__device__ __forceinline__ void row_pass_inv(uint32_t* v, uint32_t j, const uint2* __restrict__ itw, const PrimeC& pc) {
+  const uint32_t jo = j * (uint32_t)sizeof(uint2);
+  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, 16u << 8);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; k1++) {
+    const uint2 t = tw_at(rs, (uint32_t)k1, 8, jo);
+    const int r = brev_c(k1, 4);
+    v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+  }
+  dft_inv<4, AS, true>(v, pc);
+}
+
 // Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
 template <int LOGT, int AS>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
@@ -1010,10 +1040,26 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-      lds[lds_pad(threadIdx.x + i * NT)] = data_tw<AS>(va[i], w, p);
-      lds[lds_pad(TT + threadIdx.x + i * NT)] = data_tw<AS>(vb[i], w, p);
+      va[i] = data_tw<AS>(va[i], w, p);
+      vb[i] = data_tw<AS>(vb[i], w, p);
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
+    }
+    if constexpr (LOGT == 12) {
+      // the first radix-16 pass of both operands on the loaded values
+      row_pass_fwd<AS>(va, threadIdx.x, tws + tws_off(12), pc);
+      row_pass_fwd<AS>(vb, threadIdx.x, tws + tws_off(12), pc);
+#pragma unroll
+      for (int k1 = 0; k1 < 16; k1++) {
+        lds[lds_pad(threadIdx.x) + k1 * 272u] = va[brev_c(k1, 4)];
+        lds[lds_pad(TT + threadIdx.x) + k1 * 272u] = vb[brev_c(k1, 4)];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        lds[lds_pad(threadIdx.x + i * NT)] = va[i];
+        lds[lds_pad(TT + threadIdx.x + i * NT)] = vb[i];
+      }
     }
   } else {
     for (uint32_t t = threadIdx.x; t < M; t += NT) {
@@ -1024,7 +1070,8 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
   }
   __syncthreads();
-  ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
+  if (LOGT == 12 && M == TT && bmode == 0) ntt_fwd_tile<true, AS>(lds, logM - 4, 2 * M, 0, tws, pc);
+  else ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
   if (M == TT) {
     // thread g wrote A and B at [16 g, 16 g + 16): pointwise in place, and the
@@ -1043,7 +1090,19 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
     __syncthreads();
   }
-  ntt_inv_tile<true, AS>(lds, logM, M, 0, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
+  // rows of 2^12: the last inverse pass (group threadIdx.x) on registers
+  constexpr bool RP = LOGT == 12;
+  const bool rp = RP && M == TT;
+  uint32_t vo[16];
+  if (rp) {
+    ntt_inv_tile<true, AS>(lds, logM - 4, M, 0, itws, pc);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; k1++) vo[brev_c(k1, 4)] = lds[lds_pad(threadIdx.x) + k1 * 272u];
+    row_pass_inv<AS>(vo, threadIdx.x, itws + tws_off(12), pc);
+  } else {
+    ntt_inv_tile<true, AS>(lds, logM, M, 0, itws, pc);
+  }
   const uint2* ilo = tb.itw2lo + (size_t)prime * TW2_LO;
   const uint32_t* ihi = tb.itw2hi + (size_t)prime * TW2_HI;
   // the pointwise scale (2^32 / N) rides on the inverse twiddles: every step
@@ -1052,6 +1111,15 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
   wi.x = mul_tw(wi.x, sc.x, sc.y, p);
   wi.y = wi.x * pc.pinv;
   const uint2 Ri = tw2(ilo, ihi, ((NT * fr) << ysh) & ymask, pc);
+  if (rp) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      fa[threadIdx.x + i * NT] = data_tw<AS>(vo[i], wi, p);
+      wi.x = mul_tw(wi.x, Ri.x, Ri.y, p);
+      wi.y = wi.x * pc.pinv;
+    }
+    return;
+  }
   for (uint32_t t = threadIdx.x; t < M; t += NT) {
     fa[t] = data_tw<AS>(lds[lds_pad(t)], wi, p);
     wi.x = mul_tw(wi.x, Ri.x, Ri.y, p);
