@@ -946,34 +946,37 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
     for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
 }
 
-// The outermost radix-16 pass of a 2^12-point tile on registers: group j
-// (elements j + 256 k, k < 16) is what thread j of a full 2^12 row loads and
-// stores, so the first forward pass can start from the loaded values and the
+// The outermost pass of a 2^11- or 2^12-point row tile on registers (radix
+// 8 or 16, groups of elements j + 256 k): a thread of a full row loads and
+// stores exactly its groups (one per operand at 2^12; two, j and j + 128, at
+// 2^11), so the first forward pass can start from the loaded values and the
 // last inverse pass can end in the stored ones.  Same arithmetic as
 // groups_fwd / groups_inv at logSR = 8.
-template <int AS>
+template <int LOGR, int AS>
 __device__ __forceinline__ void row_pass_fwd(uint32_t* v, uint32_t j, const uint2* __restrict__ tw, const PrimeC& pc) {
-  dft_fwd<4, AS, true, false>(v, pc);
+  constexpr int R = 1 << LOGR;
+  dft_fwd<LOGR, AS, true, false>(v, pc);
   const uint32_t jo = j * (uint32_t)sizeof(uint2);
-  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, 16u << 8);
+  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << 8);
 #pragma unroll
-  for (int k1 = 1; k1 < 16; k1++) {
+  for (int k1 = 1; k1 < R; k1++) {
     const uint2 t = tw_at(rs, (uint32_t)k1, 8, jo);
-    const int r = brev_c(k1, 4);
+    const int r = brev_c(k1, LOGR);
     v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
   }
 }
-template <int AS>
+template <int LOGR, int AS>
 __device__ __forceinline__ void row_pass_inv(uint32_t* v, uint32_t j, const uint2* __restrict__ itw, const PrimeC& pc) {
+  constexpr int R = 1 << LOGR;
   const uint32_t jo = j * (uint32_t)sizeof(uint2);
-  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, 16u << 8);
+  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, (uint32_t)R << 8);
 #pragma unroll
-  for (int k1 = 1; k1 < 16; k1++) {
+  for (int k1 = 1; k1 < R; k1++) {
     const uint2 t = tw_at(rs, (uint32_t)k1, 8, jo);
-    const int r = brev_c(k1, 4);
+    const int r = brev_c(k1, LOGR);
     v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
   }
-  dft_inv<4, AS, true>(v, pc);
+  dft_inv<LOGR, AS, true>(v, pc);
 }
 
 // Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
@@ -1047,12 +1050,32 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
     if constexpr (LOGT == 12) {
       // the first radix-16 pass of both operands on the loaded values
-      row_pass_fwd<AS>(va, threadIdx.x, tws + tws_off(12), pc);
-      row_pass_fwd<AS>(vb, threadIdx.x, tws + tws_off(12), pc);
+      row_pass_fwd<4, AS>(va, threadIdx.x, tws + tws_off(12), pc);
+      row_pass_fwd<4, AS>(vb, threadIdx.x, tws + tws_off(12), pc);
 #pragma unroll
       for (int k1 = 0; k1 < 16; k1++) {
         lds[lds_pad(threadIdx.x) + k1 * 272u] = va[brev_c(k1, 4)];
         lds[lds_pad(TT + threadIdx.x) + k1 * 272u] = vb[brev_c(k1, 4)];
+      }
+    } else if constexpr (LOGT == 11) {
+      // the first radix-8 pass: groups threadIdx.x (even i) and threadIdx.x +
+      // 128 (odd i) of each operand
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        uint32_t xa[8], xb[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          xa[k] = va[2 * k + u];
+          xb[k] = vb[2 * k + u];
+        }
+        const uint32_t j = threadIdx.x + 128u * u;
+        row_pass_fwd<3, AS>(xa, j, tws + tws_off(11), pc);
+        row_pass_fwd<3, AS>(xb, j, tws + tws_off(11), pc);
+#pragma unroll
+        for (int k1 = 0; k1 < 8; k1++) {
+          lds[lds_pad(j) + k1 * 272u] = xa[brev_c(k1, 3)];
+          lds[lds_pad(TT + j) + k1 * 272u] = xb[brev_c(k1, 3)];
+        }
       }
     } else {
 #pragma unroll
@@ -1070,7 +1093,8 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
   }
   __syncthreads();
-  if (LOGT == 12 && M == TT && bmode == 0) ntt_fwd_tile<true, AS>(lds, logM - 4, 2 * M, 0, tws, pc);
+  if ((LOGT == 12 || LOGT == 11) && M == TT && bmode == 0)
+    ntt_fwd_tile<true, AS>(lds, 8, 2 * M, 0, tws, pc);   // the passes after the first
   else ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
   if (M == TT) {
@@ -1091,15 +1115,29 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     __syncthreads();
   }
   const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
-  // rows of 2^12: the last inverse pass (group threadIdx.x) on registers
-  constexpr bool RP = LOGT == 12;
+  // full rows of 2^12 or 2^11: the last inverse pass (the thread's groups)
+  // on registers, vo[i] the value for position threadIdx.x + i NT
+  constexpr bool RP = LOGT == 12 || LOGT == 11;
   const bool rp = RP && M == TT;
   uint32_t vo[16];
   if (rp) {
-    ntt_inv_tile<true, AS>(lds, logM - 4, M, 0, itws, pc);
+    ntt_inv_tile<true, AS>(lds, 8, M, 0, itws, pc);   // every pass but the last
+    if constexpr (LOGT == 12) {
 #pragma unroll
-    for (int k1 = 0; k1 < 16; k1++) vo[brev_c(k1, 4)] = lds[lds_pad(threadIdx.x) + k1 * 272u];
-    row_pass_inv<AS>(vo, threadIdx.x, itws + tws_off(12), pc);
+      for (int k1 = 0; k1 < 16; k1++) vo[brev_c(k1, 4)] = lds[lds_pad(threadIdx.x) + k1 * 272u];
+      row_pass_inv<4, AS>(vo, threadIdx.x, itws + tws_off(12), pc);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const uint32_t j = threadIdx.x + 128u * u;
+        uint32_t x[8];
+#pragma unroll
+        for (int k1 = 0; k1 < 8; k1++) x[brev_c(k1, 3)] = lds[lds_pad(j) + k1 * 272u];
+        row_pass_inv<3, AS>(x, j, itws + tws_off(11), pc);
+#pragma unroll
+        for (int k = 0; k < 8; k++) vo[2 * k + u] = x[k];
+      }
+    }
   } else {
     ntt_inv_tile<true, AS>(lds, logM, M, 0, itws, pc);
   }
