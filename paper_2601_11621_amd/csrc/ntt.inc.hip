@@ -658,6 +658,44 @@ struct PassGeom {
   }
 };
 
+// The first forward column pass on registers for an operand of at most N/2
+// words: in a tile of NV * 256 words and at most 256 columns, group
+// threadIdx.x + 256 u of that pass (radix 2^LR) has its lower half at the
+// elements threadIdx.x + 256 (u + j1 NV / 2^LR), j1 < 2^LR / 2, which are the
+// thread's loaded values v[u + j1 NV / 2^LR]; the upper half is zero.  Same
+// arithmetic as groups_fwd with ZHI.
+template <int LR, int AS, int NV>
+__device__ __forceinline__ void col_first_fwd(uint32_t* lds, const uint32_t* v, uint32_t logL, uint32_t logC,
+                                              const uint2* __restrict__ tw, const PrimeC& pc) {
+  constexpr int R = 1 << LR;
+  constexpr int U = NV >> LR;
+  const uint32_t logSR = logL - LR;
+  const uint32_t stride = 1u << (logSR + logC);
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    uint32_t jj;
+    const uint32_t b = group_base<LR, false>(threadIdx.x + 256u * u, logSR, logC, &jj);
+    uint32_t x[R];
+#pragma unroll
+    for (int j1 = 0; j1 < R; j1++) x[j1] = j1 < R / 2 ? v[u + j1 * U] : 0u;
+    if (logSR > 0) {
+      dft_fwd<LR, AS, true, true>(x, pc);
+      const uint32_t jo = jj * (uint32_t)sizeof(uint2);
+      const __amdgpu_buffer_rsrc_t rt = tw_rsrc(tw, (uint32_t)R << logSR);
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        const uint2 t = tw_at(rt, (uint32_t)k1, logSR, jo);
+        const int r = brev_c(k1, LR);
+        x[r] = tw_mul<AS>(x[r], t.x, t.y, pc.p);
+      }
+    } else {
+      dft_fwd<LR, AS, false, true>(x, pc);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) lds[b + k1 * stride] = x[brev_c(k1, LR)];
+  }
+}
+
 template <int LOGT, int AS>
 __global__ void __launch_bounds__(NTT_COL_THREADS)
 k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int plogL, int op_base,
@@ -696,7 +734,29 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
   }
   const uint32_t Tl = zhi ? T >> 1 : T;
   // loads in batches of COL_BATCH per thread, all issued before the first use
-  if (first && lin) {
+  const bool regp = first && lin && zhi && T == (1u << LOGT);
+  if (regp) {
+    // the whole lower half in registers, the first pass on them
+    constexpr int NV = (1 << LOGT) / NTT_COL_THREADS;
+    const MulDesc d = dv.get(m);
+    const __amdgpu_buffer_rsrc_t rs = words_rsrc(op ? bin + d.b_off : ain + d.a_off, op ? d.lb : d.la);
+    uint32_t v[NV / 2];
+#pragma unroll
+    for (int i = 0; i < NV / 2; i++) v[i] = buf_ld(rs, off0 + i * RI * rowB);
+#pragma unroll
+    for (int i = 0; i < NV / 2; i++) v[i] = in_limb<AS>(v[i], p);
+    const int lr = pass_logr(pg.logL);
+    const uint2* tws = tb.tws + (size_t)prime * TWS_ENTRIES;
+    const uint2* tw1 = tws + tws_off(pg.logL);
+    switch (lr) {
+      case 1: col_first_fwd<1, AS, NV>(lds, v, pg.logL, pg.logC, tw1, pc); break;
+      case 2: col_first_fwd<2, AS, NV>(lds, v, pg.logL, pg.logC, tw1, pc); break;
+      case 3: col_first_fwd<3, AS, NV>(lds, v, pg.logL, pg.logC, tw1, pc); break;
+      default: col_first_fwd<4, AS, NV>(lds, v, pg.logL, pg.logC, tw1, pc); break;
+    }
+    __syncthreads();
+    ntt_fwd_tile<false, AS>(lds, pg.logL - lr, T, (uint32_t)pg.logC, tws, pc, threadIdx.x, blockDim.x, false);
+  } else if (first && lin) {
     const MulDesc d = dv.get(m);
     const __amdgpu_buffer_rsrc_t rs = words_rsrc(op ? bin + d.b_off : ain + d.a_off, op ? d.lb : d.la);
     for (uint32_t t0 = 0; t0 < Tl; t0 += COL_BATCH * NTT_COL_THREADS) {
@@ -771,9 +831,11 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
       }
     }
   }
-  __syncthreads();
-  ntt_fwd_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc, threadIdx.x,
-                          blockDim.x, zhi);
+  if (!regp) {
+    __syncthreads();
+    ntt_fwd_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.tws + (size_t)prime * TWS_ENTRIES, pc,
+                            threadIdx.x, blockDim.x, zhi);
+  }
   __syncthreads();
   if (!tw) {
     // the pass next to the rows: k_row applies this pass's twiddles
@@ -815,6 +877,45 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
         f[base + ((uint64_t)q << logSig) + j] = data_tw<AS>(lds[t], make_uint2(w, w * pc.pinv), p);
       }
     }
+  }
+}
+
+// The last (outermost) inverse column pass on registers, stored as exact
+// residues: in a tile of NV * 256 words and at most 256 columns, group
+// threadIdx.x + 256 u of that pass (radix 2^LR) holds the elements
+// threadIdx.x + 256 (u + j1 NV / 2^LR), all of them stored by this thread, so
+// its outputs go to memory without a round trip through LDS.  Same arithmetic
+// as groups_inv.
+template <int LR, int AS, int NV>
+__device__ __forceinline__ void col_last_inv(const uint32_t* lds, uint32_t logL, uint32_t logC,
+                                             const uint2* __restrict__ itw, const PrimeC& pc,
+                                             __amdgpu_buffer_rsrc_t rs, uint32_t off0, uint32_t stepB) {
+  constexpr int R = 1 << LR;
+  constexpr int U = NV >> LR;
+  const uint32_t logSR = logL - LR;
+  const uint32_t stride = 1u << (logSR + logC);
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    uint32_t jj;
+    const uint32_t b = group_base<LR, false>(threadIdx.x + 256u * u, logSR, logC, &jj);
+    uint32_t x[R];
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) x[brev_c(k1, LR)] = lds[b + k1 * stride];
+    if (logSR > 0) {
+      const uint32_t jo = jj * (uint32_t)sizeof(uint2);
+      const __amdgpu_buffer_rsrc_t rt = tw_rsrc(itw, (uint32_t)R << logSR);
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        const uint2 t = tw_at(rt, (uint32_t)k1, logSR, jo);
+        const int r = brev_c(k1, LR);
+        x[r] = tw_mul<AS>(x[r], t.x, t.y, pc.p);
+      }
+      dft_inv<LR, AS, true>(x, pc);
+    } else {
+      dft_inv<LR, AS, false>(x, pc);
+    }
+#pragma unroll
+    for (int j1 = 0; j1 < R; j1++) buf_st(rs, off0 + (uint32_t)(u + j1 * U) * stepB, out_residue<AS>(x[j1], pc.p));
   }
 }
 
@@ -893,7 +994,31 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   }
   }
   __syncthreads();
-  ntt_inv_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, tb.itws + (size_t)prime * TWS_ENTRIES, pc);
+  const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
+  if (last && lin && T == (1u << LOGT)) {
+    // the outermost pass: every pass but the last through LDS, the last on
+    // registers straight to the residues (positions at or past L fall
+    // outside the buffer's range: not written)
+    const int lr0 = pass_logr(pg.logL);
+    ntt_inv_tile<false, AS>(lds, pg.logL - lr0, T, (uint32_t)pg.logC, itws, pc);
+    const MulDesc d = dv.get(m);
+    const uint64_t L = (uint64_t)d.la + d.lb;
+    uint32_t* out = res + (size_t)prime * res_stride + d.r_off;
+    const __amdgpu_buffer_rsrc_t rs = words_rsrc(out, L);
+    constexpr int NV = (1 << LOGT) / NTT_COL_THREADS;
+    const uint2* itw = itws + tws_off(pg.logL);
+    const uint32_t stepB = RI * rowB;
+    switch (lr0) {
+      case 1: col_last_inv<1, AS, NV>(lds, pg.logL, pg.logC, itw, pc, rs, off0, stepB); break;
+      case 2: col_last_inv<2, AS, NV>(lds, pg.logL, pg.logC, itw, pc, rs, off0, stepB); break;
+      case 3: col_last_inv<3, AS, NV>(lds, pg.logL, pg.logC, itw, pc, rs, off0, stepB); break;
+      default: col_last_inv<4, AS, NV>(lds, pg.logL, pg.logC, itw, pc, rs, off0, stepB); break;
+    }
+    if (base == 0 && j0 == 0)
+      for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
+    return;
+  }
+  ntt_inv_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, itws, pc);
   if (!last) {
     if (!post) {
       if (lin) {
