@@ -473,6 +473,68 @@ __device__ __forceinline__ uint32_t out_residue(uint32_t x, uint32_t p) {
 // is 3 x tiles workgroups; workgroup ids are renumbered so that each XCD takes
 // a contiguous run of (tile, prime) pairs: the three primes of a tile run one
 // after another on one XCD and read the operands once from HBM into its L2.
+// First forward and last inverse pass of a packed 2^12-slot tile on
+// registers (transforms of N = 2^9 .. 2^12 points, radix 2^LR = N / 256):
+// thread j loaded the words j + 256 i, i < 16, of the tile's array (product
+// m, operand o occupies words (2 m + o) N/2 .. + N/2), so its group u of the
+// first pass (product u / 2, operand u mod 2, positions j + 256 k) has the
+// loaded words i = u 2^(LR-1) + k in its lower half and zeros above; of the
+// last inverse pass it holds group u (product u, positions j + 256 k), which
+// it stores as words j + 256 (u 2^LR + k).  Same arithmetic as groups_fwd
+// (with ZHI) and groups_inv at logSR = 8.
+template <int LR, int AS>
+__device__ __forceinline__ void lds_first_fwd(uint32_t* lds, const uint32_t* x, uint32_t N, uint32_t TT, uint32_t cnt,
+                                              const uint2* __restrict__ tw, const PrimeC& pc) {
+  constexpr int R = 1 << LR;
+  constexpr int U = 32 >> LR;
+  const uint32_t j = threadIdx.x;
+  const uint32_t jo = j * (uint32_t)sizeof(uint2);
+  const __amdgpu_buffer_rsrc_t rt = tw_rsrc(tw, (uint32_t)R << 8);
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if ((uint32_t)(u >> 1) >= cnt) continue;
+    uint32_t v[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) v[k] = k < R / 2 ? x[u * (R / 2) + k] : 0u;
+    dft_fwd<LR, AS, true, true>(v, pc);
+#pragma unroll
+    for (int k1 = 1; k1 < R; k1++) {
+      const uint2 t = tw_at(rt, (uint32_t)k1, 8, jo);
+      const int r = brev_c(k1, LR);
+      v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+    }
+    const uint32_t b = lds_pad(((u & 1) ? TT : 0u) + (uint32_t)(u >> 1) * N + j);
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) lds[b + k1 * 272u] = v[brev_c(k1, LR)];
+  }
+}
+template <int LR, int AS>
+__device__ __forceinline__ void lds_last_inv(const uint32_t* lds, uint32_t* dst, uint32_t N, uint32_t T,
+                                             const uint2* __restrict__ itw, const PrimeC& pc) {
+  constexpr int R = 1 << LR;
+  constexpr int U = 16 >> LR;
+  const uint32_t j = threadIdx.x;
+  const uint32_t jo = j * (uint32_t)sizeof(uint2);
+  const __amdgpu_buffer_rsrc_t rt = tw_rsrc(itw, (uint32_t)R << 8);
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if ((uint32_t)u * N >= T) continue;
+    uint32_t v[R];
+    const uint32_t b = lds_pad((uint32_t)u * N + j);
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) v[brev_c(k1, LR)] = lds[b + k1 * 272u];
+#pragma unroll
+    for (int k1 = 1; k1 < R; k1++) {
+      const uint2 t = tw_at(rt, (uint32_t)k1, 8, jo);
+      const int r = brev_c(k1, LR);
+      v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+    }
+    dft_inv<LR, AS, true>(v, pc);
+#pragma unroll
+    for (int k = 0; k < R; k++) dst[j + 256u * (u * R + k)] = out_residue<AS>(v[k], pc.p);
+  }
+}
+
 template <int LOGT, int BMODE, int AS>
 __global__ void __launch_bounds__((1 << LOGT) / 16)
 k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain, const uint32_t* __restrict__ bin,
@@ -523,7 +585,27 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
     }
     packed = __syncthreads_and(ok ? 1 : 0) != 0 && ain == bin;
   }
-  if (packed) {
+  // 2^12-slot packed tiles of transforms of 2^9 .. 2^12 points: the first
+  // forward pass (radix 2^lr, groups of positions j + 256 k) and the last
+  // inverse pass run on registers, since a thread's loaded and stored words
+  // are exactly its groups of those passes
+  const bool regp = LOGT == 12 && BMODE == 0 && packed && logN >= 9;
+  if (regp) {
+    const uint32_t* src = ain + ds[0].a_off;
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t w = threadIdx.x + i * 256u;
+      x[i] = in_limb<AS>(src[w < T ? w : T - 1], p);
+    }
+    const uint2* tw1 = tws + tws_off(logN);
+    switch (logN) {
+      case 9: lds_first_fwd<1, AS>(lds, x, N, TT, cnt, tw1, pc); break;
+      case 10: lds_first_fwd<2, AS>(lds, x, N, TT, cnt, tw1, pc); break;
+      case 11: lds_first_fwd<3, AS>(lds, x, N, TT, cnt, tw1, pc); break;
+      default: lds_first_fwd<4, AS>(lds, x, N, TT, cnt, tw1, pc); break;
+    }
+  } else if (packed) {
     constexpr uint32_t NT = TT / 16;               // blockDim.x
     const uint32_t* src = ain + ds[0].a_off;
     const uint32_t half = N >> 1;
@@ -574,6 +656,14 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   // A occupies [0, T), B [TT, TT + T); transform both as one tile
   if constexpr (BMODE == 2) {
     ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
+  } else if (regp) {
+    // the passes after the first, of sizes 2^8 and 2^4
+    if (T == TT) {
+      ntt_fwd_tile<true, AS>(lds, 8, 2 * TT, 0, tws, pc);
+    } else {
+      ntt_fwd_tile<true, AS>(lds, 8, T, 0, tws, pc);
+      ntt_fwd_tile<true, AS>(lds + lds_pad(TT), 8, T, 0, tws, pc);
+    }
   } else if (T == TT) {
     ntt_fwd_tile<true, AS>(lds, logN, 2 * TT, 0, tws, pc, threadIdx.x, blockDim.x, packed);
   } else {
@@ -592,8 +682,20 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
       lds[lds_pad(t)] = pointwise<AS>(x, y, sc, pc);
     }
   }
-  ntt_inv_tile<true, AS>(lds, logN, T, 0, itws, pc);
   uint32_t* out = res + (size_t)prime * res_stride;
+  if (regp) {
+    ntt_inv_tile<true, AS>(lds, 8, T, 0, itws, pc);   // every pass but the last
+    uint32_t* dst = out + ds[0].r_off;
+    const uint2* itw1 = itws + tws_off(logN);
+    switch (logN) {
+      case 9: lds_last_inv<1, AS>(lds, dst, N, T, itw1, pc); break;
+      case 10: lds_last_inv<2, AS>(lds, dst, N, T, itw1, pc); break;
+      case 11: lds_last_inv<3, AS>(lds, dst, N, T, itw1, pc); break;
+      default: lds_last_inv<4, AS>(lds, dst, N, T, itw1, pc); break;
+    }
+    return;
+  }
+  ntt_inv_tile<true, AS>(lds, logN, T, 0, itws, pc);
   if (packed) {
     constexpr uint32_t NT = TT / 16;
     uint32_t* dst = out + ds[0].r_off;
