@@ -473,65 +473,71 @@ __device__ __forceinline__ uint32_t out_residue(uint32_t x, uint32_t p) {
 // is 3 x tiles workgroups; workgroup ids are renumbered so that each XCD takes
 // a contiguous run of (tile, prime) pairs: the three primes of a tile run one
 // after another on one XCD and read the operands once from HBM into its L2.
-// First forward and last inverse pass of a packed 2^12-slot tile on
-// registers (transforms of N = 2^9 .. 2^12 points, radix 2^LR = N / 256):
-// thread j loaded the words j + 256 i, i < 16, of the tile's array (product
-// m, operand o occupies words (2 m + o) N/2 .. + N/2), so its group u of the
-// first pass (product u / 2, operand u mod 2, positions j + 256 k) has the
-// loaded words i = u 2^(LR-1) + k in its lower half and zeros above; of the
-// last inverse pass it holds group u (product u, positions j + 256 k), which
-// it stores as words j + 256 (u 2^LR + k).  Same arithmetic as groups_fwd
-// (with ZHI) and groups_inv at logSR = 8.
-template <int LR, int AS>
-__device__ __forceinline__ void lds_first_fwd(uint32_t* lds, const uint32_t* x, uint32_t N, uint32_t TT, uint32_t cnt,
-                                              const uint2* __restrict__ tw, const PrimeC& pc) {
-  constexpr int R = 1 << LR;
-  constexpr int U = 32 >> LR;
-  const uint32_t j = threadIdx.x;
-  const uint32_t jo = j * (uint32_t)sizeof(uint2);
-  const __amdgpu_buffer_rsrc_t rt = tw_rsrc(tw, (uint32_t)R << 8);
+// First forward and last inverse pass of a packed tile on registers: the
+// tile's products lie back to back as a then b (N/2 words each), and thread
+// t of the NT loaded the words t + NT i, i < 16.  With a first pass of radix
+// 2^LR = 2^pass_logr(logN) over positions j + 2^logSR k (logSR = logN - LR,
+// 2^logSR = D NT), the lower half of its group (block b = 2 m + o, j = t +
+// NT d) is the loaded words i = b 2^(LR-1) D + d + D k, the upper half zero;
+// of the last inverse pass it holds the groups (product m, j = t + NT d),
+// whose outputs k are its stored words i = m 2^LR D + d + D k.  Same
+// arithmetic as groups_fwd (with ZHI) and groups_inv.
+template <int LR, int D, int AS>
+__device__ __forceinline__ void lds_first_fwd(uint32_t* lds, const uint32_t* x, uint32_t NT, uint32_t N, uint32_t TT,
+                                              uint32_t cnt, const uint2* __restrict__ tw, const PrimeC& pc) {
+  constexpr int R = 1 << LR, H = R / 2, NB = 16 / (H * D);
+  const uint32_t SR = NT * D, stride = SR + SR / 16, logSR = 31 - __builtin_clz(SR);
+  const __amdgpu_buffer_rsrc_t rt = tw_rsrc(tw, (uint32_t)R << logSR);
 #pragma unroll
-  for (int u = 0; u < U; u++) {
-    if ((uint32_t)(u >> 1) >= cnt) continue;
-    uint32_t v[R];
+  for (int b = 0; b < NB; b++) {
+    if ((uint32_t)(b >> 1) >= cnt) continue;
 #pragma unroll
-    for (int k = 0; k < R; k++) v[k] = k < R / 2 ? x[u * (R / 2) + k] : 0u;
-    dft_fwd<LR, AS, true, true>(v, pc);
+    for (int d = 0; d < D; d++) {
+      uint32_t v[R];
 #pragma unroll
-    for (int k1 = 1; k1 < R; k1++) {
-      const uint2 t = tw_at(rt, (uint32_t)k1, 8, jo);
-      const int r = brev_c(k1, LR);
-      v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+      for (int k = 0; k < R; k++) v[k] = k < H ? x[b * H * D + d + D * k] : 0u;
+      dft_fwd<LR, AS, true, true>(v, pc);
+      const uint32_t j = threadIdx.x + NT * d;
+      const uint32_t jo = j * (uint32_t)sizeof(uint2);
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        const uint2 t = tw_at(rt, (uint32_t)k1, logSR, jo);
+        const int r = brev_c(k1, LR);
+        v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+      }
+      const uint32_t base = lds_pad(((b & 1) ? TT : 0u) + (uint32_t)(b >> 1) * N + j);
+#pragma unroll
+      for (int k1 = 0; k1 < R; k1++) lds[base + k1 * stride] = v[brev_c(k1, LR)];
     }
-    const uint32_t b = lds_pad(((u & 1) ? TT : 0u) + (uint32_t)(u >> 1) * N + j);
-#pragma unroll
-    for (int k1 = 0; k1 < R; k1++) lds[b + k1 * 272u] = v[brev_c(k1, LR)];
   }
 }
-template <int LR, int AS>
-__device__ __forceinline__ void lds_last_inv(const uint32_t* lds, uint32_t* dst, uint32_t N, uint32_t T,
+template <int LR, int D, int AS>
+__device__ __forceinline__ void lds_last_inv(const uint32_t* lds, uint32_t* dst, uint32_t NT, uint32_t N, uint32_t T,
                                              const uint2* __restrict__ itw, const PrimeC& pc) {
-  constexpr int R = 1 << LR;
-  constexpr int U = 16 >> LR;
-  const uint32_t j = threadIdx.x;
-  const uint32_t jo = j * (uint32_t)sizeof(uint2);
-  const __amdgpu_buffer_rsrc_t rt = tw_rsrc(itw, (uint32_t)R << 8);
+  constexpr int R = 1 << LR, NP = 16 / (R * D);
+  const uint32_t SR = NT * D, stride = SR + SR / 16, logSR = 31 - __builtin_clz(SR);
+  const __amdgpu_buffer_rsrc_t rt = tw_rsrc(itw, (uint32_t)R << logSR);
 #pragma unroll
-  for (int u = 0; u < U; u++) {
-    if ((uint32_t)u * N >= T) continue;
-    uint32_t v[R];
-    const uint32_t b = lds_pad((uint32_t)u * N + j);
+  for (int m = 0; m < NP; m++) {
+    if ((uint32_t)m * N >= T) continue;
 #pragma unroll
-    for (int k1 = 0; k1 < R; k1++) v[brev_c(k1, LR)] = lds[b + k1 * 272u];
+    for (int d = 0; d < D; d++) {
+      const uint32_t j = threadIdx.x + NT * d;
+      const uint32_t base = lds_pad((uint32_t)m * N + j);
+      uint32_t v[R];
 #pragma unroll
-    for (int k1 = 1; k1 < R; k1++) {
-      const uint2 t = tw_at(rt, (uint32_t)k1, 8, jo);
-      const int r = brev_c(k1, LR);
-      v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+      for (int k1 = 0; k1 < R; k1++) v[brev_c(k1, LR)] = lds[base + k1 * stride];
+      const uint32_t jo = j * (uint32_t)sizeof(uint2);
+#pragma unroll
+      for (int k1 = 1; k1 < R; k1++) {
+        const uint2 t = tw_at(rt, (uint32_t)k1, logSR, jo);
+        const int r = brev_c(k1, LR);
+        v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
+      }
+      dft_inv<LR, AS, true>(v, pc);
+#pragma unroll
+      for (int k = 0; k < R; k++) dst[threadIdx.x + NT * (m * R * D + d + D * k)] = out_residue<AS>(v[k], pc.p);
     }
-    dft_inv<LR, AS, true>(v, pc);
-#pragma unroll
-    for (int k = 0; k < R; k++) dst[j + 256u * (u * R + k)] = out_residue<AS>(v[k], pc.p);
   }
 }
 
@@ -589,21 +595,34 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   // forward pass (radix 2^lr, groups of positions j + 256 k) and the last
   // inverse pass run on registers, since a thread's loaded and stored words
   // are exactly its groups of those passes
-  const bool regp = LOGT == 12 && BMODE == 0 && packed && logN >= 9;
+  constexpr uint32_t NTL = TT / 16;                // blockDim.x
+  // (2^12 tiles: transforms of 2^9 .. 2^12 points; 2^13: 2^13; 2^14: 2^13
+  // and 2^14, where 2^(logN - pass_logr(logN)) is a multiple of the thread
+  // count)
+  const bool regp = BMODE == 0 && packed &&
+                    (LOGT == 12 ? logN >= 9 : LOGT == 13 ? logN == 13 : LOGT == 14 ? logN >= 13 : false);
+  const int logSR1 = logN - pass_logr(logN);
   if (regp) {
     const uint32_t* src = ain + ds[0].a_off;
     uint32_t x[16];
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-      const uint32_t w = threadIdx.x + i * 256u;
+      const uint32_t w = threadIdx.x + i * NTL;
       x[i] = in_limb<AS>(src[w < T ? w : T - 1], p);
     }
     const uint2* tw1 = tws + tws_off(logN);
-    switch (logN) {
-      case 9: lds_first_fwd<1, AS>(lds, x, N, TT, cnt, tw1, pc); break;
-      case 10: lds_first_fwd<2, AS>(lds, x, N, TT, cnt, tw1, pc); break;
-      case 11: lds_first_fwd<3, AS>(lds, x, N, TT, cnt, tw1, pc); break;
-      default: lds_first_fwd<4, AS>(lds, x, N, TT, cnt, tw1, pc); break;
+    if constexpr (LOGT == 12) {
+      switch (logN) {
+        case 9: lds_first_fwd<1, 1, AS>(lds, x, NTL, N, TT, cnt, tw1, pc); break;
+        case 10: lds_first_fwd<2, 1, AS>(lds, x, NTL, N, TT, cnt, tw1, pc); break;
+        case 11: lds_first_fwd<3, 1, AS>(lds, x, NTL, N, TT, cnt, tw1, pc); break;
+        default: lds_first_fwd<4, 1, AS>(lds, x, NTL, N, TT, cnt, tw1, pc); break;
+      }
+    } else if constexpr (LOGT == 13) {
+      lds_first_fwd<1, 8, AS>(lds, x, NTL, N, TT, cnt, tw1, pc);
+    } else if constexpr (LOGT == 14) {
+      if (logN == 13) lds_first_fwd<1, 4, AS>(lds, x, NTL, N, TT, cnt, tw1, pc);
+      else lds_first_fwd<2, 4, AS>(lds, x, NTL, N, TT, cnt, tw1, pc);
     }
   } else if (packed) {
     constexpr uint32_t NT = TT / 16;               // blockDim.x
@@ -657,12 +676,12 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   if constexpr (BMODE == 2) {
     ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
   } else if (regp) {
-    // the passes after the first, of sizes 2^8 and 2^4
+    // the passes after the first
     if (T == TT) {
-      ntt_fwd_tile<true, AS>(lds, 8, 2 * TT, 0, tws, pc);
+      ntt_fwd_tile<true, AS>(lds, logSR1, 2 * TT, 0, tws, pc);
     } else {
-      ntt_fwd_tile<true, AS>(lds, 8, T, 0, tws, pc);
-      ntt_fwd_tile<true, AS>(lds + lds_pad(TT), 8, T, 0, tws, pc);
+      ntt_fwd_tile<true, AS>(lds, logSR1, T, 0, tws, pc);
+      ntt_fwd_tile<true, AS>(lds + lds_pad(TT), logSR1, T, 0, tws, pc);
     }
   } else if (T == TT) {
     ntt_fwd_tile<true, AS>(lds, logN, 2 * TT, 0, tws, pc, threadIdx.x, blockDim.x, packed);
@@ -684,14 +703,21 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   }
   uint32_t* out = res + (size_t)prime * res_stride;
   if (regp) {
-    ntt_inv_tile<true, AS>(lds, 8, T, 0, itws, pc);   // every pass but the last
+    ntt_inv_tile<true, AS>(lds, logSR1, T, 0, itws, pc);   // every pass but the last
     uint32_t* dst = out + ds[0].r_off;
     const uint2* itw1 = itws + tws_off(logN);
-    switch (logN) {
-      case 9: lds_last_inv<1, AS>(lds, dst, N, T, itw1, pc); break;
-      case 10: lds_last_inv<2, AS>(lds, dst, N, T, itw1, pc); break;
-      case 11: lds_last_inv<3, AS>(lds, dst, N, T, itw1, pc); break;
-      default: lds_last_inv<4, AS>(lds, dst, N, T, itw1, pc); break;
+    if constexpr (LOGT == 12) {
+      switch (logN) {
+        case 9: lds_last_inv<1, 1, AS>(lds, dst, NTL, N, T, itw1, pc); break;
+        case 10: lds_last_inv<2, 1, AS>(lds, dst, NTL, N, T, itw1, pc); break;
+        case 11: lds_last_inv<3, 1, AS>(lds, dst, NTL, N, T, itw1, pc); break;
+        default: lds_last_inv<4, 1, AS>(lds, dst, NTL, N, T, itw1, pc); break;
+      }
+    } else if constexpr (LOGT == 13) {
+      lds_last_inv<1, 8, AS>(lds, dst, NTL, N, T, itw1, pc);
+    } else if constexpr (LOGT == 14) {
+      if (logN == 13) lds_last_inv<1, 4, AS>(lds, dst, NTL, N, T, itw1, pc);
+      else lds_last_inv<2, 4, AS>(lds, dst, NTL, N, T, itw1, pc);
     }
     return;
   }
@@ -1173,37 +1199,85 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
     for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
 }
 
-// The outermost pass of a 2^11- or 2^12-point row tile on registers (radix
-// 8 or 16, groups of elements j + 256 k): a thread of a full row loads and
-// stores exactly its groups (one per operand at 2^12; two, j and j + 128, at
-// 2^11), so the first forward pass can start from the loaded values and the
-// last inverse pass can end in the stored ones.  Same arithmetic as
-// groups_fwd / groups_inv at logSR = 8.
-template <int LOGR, int AS>
-__device__ __forceinline__ void row_pass_fwd(uint32_t* v, uint32_t j, const uint2* __restrict__ tw, const PrimeC& pc) {
-  constexpr int R = 1 << LOGR;
-  dft_fwd<LOGR, AS, true, false>(v, pc);
+// The outermost pass of a full row tile of 2^LOGT points on registers (radix
+// 2^LR = 2^pass_logr(LOGT), groups of elements j + 2^(LOGT-LR) k): thread t
+// of the 2^LOGT / 16 loads and stores the elements t + (2^LOGT / 16) i, which
+// are exactly its D = 2^(4-LR) groups j = t + (2^LOGT / 16) d of that pass
+// (element i = d + D k of group d), so the first forward pass can start from
+// the loaded values and the last inverse pass can end in the stored ones.
+// Same arithmetic as groups_fwd / groups_inv.
+template <int LR, int AS>
+__device__ __forceinline__ void row_pass_fwd(uint32_t* v, uint32_t j, uint32_t logSR, const uint2* __restrict__ tw,
+                                             const PrimeC& pc) {
+  constexpr int R = 1 << LR;
+  dft_fwd<LR, AS, true, false>(v, pc);
   const uint32_t jo = j * (uint32_t)sizeof(uint2);
-  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << 8);
+  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(tw, (uint32_t)R << logSR);
 #pragma unroll
   for (int k1 = 1; k1 < R; k1++) {
-    const uint2 t = tw_at(rs, (uint32_t)k1, 8, jo);
-    const int r = brev_c(k1, LOGR);
+    const uint2 t = tw_at(rs, (uint32_t)k1, logSR, jo);
+    const int r = brev_c(k1, LR);
     v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
   }
 }
-template <int LOGR, int AS>
-__device__ __forceinline__ void row_pass_inv(uint32_t* v, uint32_t j, const uint2* __restrict__ itw, const PrimeC& pc) {
-  constexpr int R = 1 << LOGR;
+template <int LR, int AS>
+__device__ __forceinline__ void row_pass_inv(uint32_t* v, uint32_t j, uint32_t logSR, const uint2* __restrict__ itw,
+                                             const PrimeC& pc) {
+  constexpr int R = 1 << LR;
   const uint32_t jo = j * (uint32_t)sizeof(uint2);
-  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, (uint32_t)R << 8);
+  const __amdgpu_buffer_rsrc_t rs = tw_rsrc(itw, (uint32_t)R << logSR);
 #pragma unroll
   for (int k1 = 1; k1 < R; k1++) {
-    const uint2 t = tw_at(rs, (uint32_t)k1, 8, jo);
-    const int r = brev_c(k1, LOGR);
+    const uint2 t = tw_at(rs, (uint32_t)k1, logSR, jo);
+    const int r = brev_c(k1, LR);
     v[r] = tw_mul<AS>(v[r], t.x, t.y, pc.p);
   }
-  dft_inv<LOGR, AS, true>(v, pc);
+  dft_inv<LR, AS, true>(v, pc);
+}
+// The first forward pass of both operands of a full row (A at [0, 2^LOGT),
+// B at [2^LOGT, 2^(LOGT+1)) of the padded tile) from the loaded values.
+template <int LOGT, int AS>
+__device__ __forceinline__ void row_first_fwd(uint32_t* lds, const uint32_t* va, const uint32_t* vb,
+                                              const uint2* __restrict__ tws, const PrimeC& pc) {
+  constexpr int LR = pass_logr(LOGT), R = 1 << LR, D = 1 << (4 - LR);
+  constexpr uint32_t NT = (1u << LOGT) / 16, SR = 1u << (LOGT - LR), STRIDE = SR + SR / 16;
+  const uint2* tw = tws + tws_off(LOGT);
+#pragma unroll
+  for (int d = 0; d < D; d++) {
+    uint32_t xa[R], xb[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+      xa[k] = va[d + D * k];
+      xb[k] = vb[d + D * k];
+    }
+    const uint32_t j = threadIdx.x + NT * d;
+    row_pass_fwd<LR, AS>(xa, j, LOGT - LR, tw, pc);
+    row_pass_fwd<LR, AS>(xb, j, LOGT - LR, tw, pc);
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) {
+      lds[lds_pad(j) + k1 * STRIDE] = xa[brev_c(k1, LR)];
+      lds[lds_pad((1u << LOGT) + j) + k1 * STRIDE] = xb[brev_c(k1, LR)];
+    }
+  }
+}
+// The last inverse pass of operand A of a full row into vo[i], the value of
+// element t + (2^LOGT / 16) i.
+template <int LOGT, int AS>
+__device__ __forceinline__ void row_last_inv(const uint32_t* lds, uint32_t* vo, const uint2* __restrict__ itws,
+                                             const PrimeC& pc) {
+  constexpr int LR = pass_logr(LOGT), R = 1 << LR, D = 1 << (4 - LR);
+  constexpr uint32_t NT = (1u << LOGT) / 16, SR = 1u << (LOGT - LR), STRIDE = SR + SR / 16;
+  const uint2* itw = itws + tws_off(LOGT);
+#pragma unroll
+  for (int d = 0; d < D; d++) {
+    const uint32_t j = threadIdx.x + NT * d;
+    uint32_t x[R];
+#pragma unroll
+    for (int k1 = 0; k1 < R; k1++) x[brev_c(k1, LR)] = lds[lds_pad(j) + k1 * STRIDE];
+    row_pass_inv<LR, AS>(x, j, LOGT - LR, itw, pc);
+#pragma unroll
+    for (int k = 0; k < R; k++) vo[d + D * k] = x[k];
+  }
 }
 
 // Rows of M = 2^logM <= 2^LOGT elements; 2^LOGT/16 threads.
@@ -1275,42 +1349,7 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
       w.x = mul_tw(w.x, R.x, R.y, p);
       w.y = w.x * pc.pinv;
     }
-    if constexpr (LOGT == 12) {
-      // the first radix-16 pass of both operands on the loaded values
-      row_pass_fwd<4, AS>(va, threadIdx.x, tws + tws_off(12), pc);
-      row_pass_fwd<4, AS>(vb, threadIdx.x, tws + tws_off(12), pc);
-#pragma unroll
-      for (int k1 = 0; k1 < 16; k1++) {
-        lds[lds_pad(threadIdx.x) + k1 * 272u] = va[brev_c(k1, 4)];
-        lds[lds_pad(TT + threadIdx.x) + k1 * 272u] = vb[brev_c(k1, 4)];
-      }
-    } else if constexpr (LOGT == 11) {
-      // the first radix-8 pass: groups threadIdx.x (even i) and threadIdx.x +
-      // 128 (odd i) of each operand
-#pragma unroll
-      for (int u = 0; u < 2; u++) {
-        uint32_t xa[8], xb[8];
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-          xa[k] = va[2 * k + u];
-          xb[k] = vb[2 * k + u];
-        }
-        const uint32_t j = threadIdx.x + 128u * u;
-        row_pass_fwd<3, AS>(xa, j, tws + tws_off(11), pc);
-        row_pass_fwd<3, AS>(xb, j, tws + tws_off(11), pc);
-#pragma unroll
-        for (int k1 = 0; k1 < 8; k1++) {
-          lds[lds_pad(j) + k1 * 272u] = xa[brev_c(k1, 3)];
-          lds[lds_pad(TT + j) + k1 * 272u] = xb[brev_c(k1, 3)];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 16; i++) {
-        lds[lds_pad(threadIdx.x + i * NT)] = va[i];
-        lds[lds_pad(TT + threadIdx.x + i * NT)] = vb[i];
-      }
-    }
+    row_first_fwd<LOGT, AS>(lds, va, vb, tws, pc);
   } else {
     for (uint32_t t = threadIdx.x; t < M; t += NT) {
       lds[lds_pad(t)] = data_tw<AS>(fa[t], w, p);
@@ -1320,8 +1359,8 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
   }
   __syncthreads();
-  if ((LOGT == 12 || LOGT == 11) && M == TT && bmode == 0)
-    ntt_fwd_tile<true, AS>(lds, 8, 2 * M, 0, tws, pc);   // the passes after the first
+  if (M == TT && bmode == 0)
+    ntt_fwd_tile<true, AS>(lds, LOGT - pass_logr(LOGT), 2 * M, 0, tws, pc);   // the passes after the first
   else ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
   if (M == TT) {
@@ -1342,29 +1381,13 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     __syncthreads();
   }
   const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
-  // full rows of 2^12 or 2^11: the last inverse pass (the thread's groups)
-  // on registers, vo[i] the value for position threadIdx.x + i NT
-  constexpr bool RP = LOGT == 12 || LOGT == 11;
-  const bool rp = RP && M == TT;
+  // full rows: the last inverse pass (the thread's groups) on registers,
+  // vo[i] the value for position threadIdx.x + i NT
+  const bool rp = M == TT;
   uint32_t vo[16];
   if (rp) {
-    ntt_inv_tile<true, AS>(lds, 8, M, 0, itws, pc);   // every pass but the last
-    if constexpr (LOGT == 12) {
-#pragma unroll
-      for (int k1 = 0; k1 < 16; k1++) vo[brev_c(k1, 4)] = lds[lds_pad(threadIdx.x) + k1 * 272u];
-      row_pass_inv<4, AS>(vo, threadIdx.x, itws + tws_off(12), pc);
-    } else {
-#pragma unroll
-      for (int u = 0; u < 2; u++) {
-        const uint32_t j = threadIdx.x + 128u * u;
-        uint32_t x[8];
-#pragma unroll
-        for (int k1 = 0; k1 < 8; k1++) x[brev_c(k1, 3)] = lds[lds_pad(j) + k1 * 272u];
-        row_pass_inv<3, AS>(x, j, itws + tws_off(11), pc);
-#pragma unroll
-        for (int k = 0; k < 8; k++) vo[2 * k + u] = x[k];
-      }
-    }
+    ntt_inv_tile<true, AS>(lds, LOGT - pass_logr(LOGT), M, 0, itws, pc);   // every pass but the last
+    row_last_inv<LOGT, AS>(lds, vo, itws, pc);
   } else {
     ntt_inv_tile<true, AS>(lds, logM, M, 0, itws, pc);
   }

@@ -342,8 +342,16 @@ def _schedule_rows11(t):
         t["log_pass"][k] = 10 if k < 24 else 8
 
 
-@pytest.mark.parametrize("schedule", [_schedule_short, _schedule_wide, _schedule_rows11],
-                         ids=["short", "wide", "rows11"])
+def _schedule_tiles14(t):
+    """one-workgroup transforms of 2^9 .. 2^14 points all in 2^14-slot tiles
+    (1,024 threads, up to 32 products per tile)"""
+    for k in range(9, 15):
+        t["cls"][k] = 1
+        t["log_row"][k] = 14
+
+
+@pytest.mark.parametrize("schedule", [_schedule_short, _schedule_wide, _schedule_rows11, _schedule_tiles14],
+                         ids=["short", "wide", "rows11", "tiles14"])
 def test_schedules_change_speed_not_bits(cat, schedule):
     """A non-default product schedule gives the same C(n) and the same
     products as the default one."""
