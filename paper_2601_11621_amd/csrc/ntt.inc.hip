@@ -330,9 +330,11 @@ __device__ __forceinline__ void pass_sync(int logSmall, uint32_t logC) {
 template <bool PAD, int AS = 0>
 __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ tws, const PrimeC& pc, uint32_t tid = threadIdx.x,
-                             uint32_t nthr = blockDim.x, bool zhi = false) {
+                             uint32_t nthr = blockDim.x, bool zhi = false, int stop = 0) {
+  // stop = 4: the last pass (sub-problems of 16) is left to the caller, after
+  // the synchronisation before it
   bool firstp = true;
-  while (logS > 0) {
+  while (logS > stop) {
     const int lr = pass_logr(logS);
     const uint32_t ng = total >> lr;
     const uint32_t logSR = (uint32_t)(logS - lr);
@@ -367,11 +369,12 @@ __device__ __forceinline__ void ntt_fwd_tile(uint32_t* lds, int logS, uint32_t t
 template <bool PAD, int AS = 0>
 __device__ __forceinline__ void ntt_inv_tile(uint32_t* lds, int logS, uint32_t total, uint32_t logC,
                              const uint2* __restrict__ itws, const PrimeC& pc, uint32_t tid = threadIdx.x,
-                             uint32_t nthr = blockDim.x) {
+                             uint32_t nthr = blockDim.x, int ls0 = 4) {
   // passes in the reverse order of ntt_fwd_tile: the radix-16 passes of sizes
   // 2^4, 2^8, ... first, the (possibly smaller-radix) pass of size 2^logS last
+  // (ls0 = 8: the caller did the pass of size 2^4 and synchronised after it)
   const int lr0 = pass_logr(logS);
-  for (int ls = 4; ls <= logS - lr0; ls += 4) {
+  for (int ls = ls0; ls <= logS - lr0; ls += 4) {
     pass_inv<4, PAD, AS>(lds, total >> 4, (uint32_t)(ls - 4), logC, itws + tws_off(ls), pc, tid, nthr);
     if (ls + 4 <= logS - lr0 || lr0 == 4) pass_sync(ls, logC);   // the next pass has radix 16
     else __syncthreads();
@@ -453,6 +456,32 @@ __device__ __forceinline__ uint32_t pointwise_raw(uint32_t x, uint32_t y, const 
   if constexpr (AS == 0) return mont_mul(x, y, pc.p, pc.pinv);
   else return mont_mul_lazy(x, y, pc.p, pc.pinv);
 }
+
+// The innermost passes around the pointwise product on registers: thread g
+// holds the forward sub-problems of 16 at [16 g, 16 g + 16) of A and of B
+// (the groups of the last forward pass, logSR = 0), takes both DFTs, the
+// pointwise product (in the outputs' bit-reversed order, which both share)
+// and the inverse DFT of the first inverse pass, and writes that group back:
+// the two passes and the product without their LDS round trips.  SCALED:
+// pointwise with the scale pair (the one-workgroup kernel), else the raw
+// product (the row kernel, whose inverse twiddles carry the scale).
+template <int AS, bool SCALED>
+__device__ __forceinline__ void mid_passes(uint32_t* lds, uint32_t a0, uint32_t b0, uint2 sc, const PrimeC& pc) {
+  uint32_t x[16], y[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    x[k] = lds[a0 + k];
+    y[k] = lds[b0 + k];
+  }
+  dft_fwd<4, AS, false, false>(x, pc);
+  dft_fwd<4, AS, false, false>(y, pc);
+#pragma unroll
+  for (int k = 0; k < 16; k++) x[k] = SCALED ? pointwise<AS>(x[k], y[k], sc, pc) : pointwise_raw<AS>(x[k], y[k], pc);
+  dft_inv<4, AS, false>(x, pc);
+#pragma unroll
+  for (int k = 0; k < 16; k++) lds[a0 + k] = x[k];
+}
+
 // An inverse-transform output leaving as a residue in [0, p).
 template <int AS>
 __device__ __forceinline__ uint32_t out_residue(uint32_t x, uint32_t p) {
@@ -676,12 +705,12 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   if constexpr (BMODE == 2) {
     ntt_fwd_tile<true, AS>(lds, logN, T, 0, tws, pc);
   } else if (regp) {
-    // the passes after the first
+    // the passes after the first but the last
     if (T == TT) {
-      ntt_fwd_tile<true, AS>(lds, logSR1, 2 * TT, 0, tws, pc);
+      ntt_fwd_tile<true, AS>(lds, logSR1, 2 * TT, 0, tws, pc, threadIdx.x, blockDim.x, false, 4);
     } else {
-      ntt_fwd_tile<true, AS>(lds, logSR1, T, 0, tws, pc);
-      ntt_fwd_tile<true, AS>(lds + lds_pad(TT), logSR1, T, 0, tws, pc);
+      ntt_fwd_tile<true, AS>(lds, logSR1, T, 0, tws, pc, threadIdx.x, blockDim.x, false, 4);
+      ntt_fwd_tile<true, AS>(lds + lds_pad(TT), logSR1, T, 0, tws, pc, threadIdx.x, blockDim.x, false, 4);
     }
   } else if (T == TT) {
     ntt_fwd_tile<true, AS>(lds, logN, 2 * TT, 0, tws, pc, threadIdx.x, blockDim.x, packed);
@@ -693,7 +722,11 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   // wrote last (A and B alike), which the first inverse pass reads back in the
   // same thread: no barrier on either side
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
-  if (16 * threadIdx.x < T) {
+  if (regp) {
+    // with the last forward pass and the first inverse pass on registers
+    if (16 * threadIdx.x < T) mid_passes<AS, true>(lds, lds_pad(16 * threadIdx.x), lds_pad(TT + 16 * threadIdx.x), sc, pc);
+    pass_sync(4, 0);
+  } else if (16 * threadIdx.x < T) {
 #pragma unroll
     for (int k = 0; k < 16; k++) {
       const uint32_t t = 16 * threadIdx.x + k;
@@ -703,7 +736,8 @@ k_ntt_lds(DescView dv, uint64_t nmul, int logN, const uint32_t* __restrict__ ain
   }
   uint32_t* out = res + (size_t)prime * res_stride;
   if (regp) {
-    ntt_inv_tile<true, AS>(lds, logSR1, T, 0, itws, pc);   // every pass but the last
+    // every pass but the first and the last
+    ntt_inv_tile<true, AS>(lds, logSR1, T, 0, itws, pc, threadIdx.x, blockDim.x, 8);
     uint32_t* dst = out + ds[0].r_off;
     const uint2* itw1 = itws + tws_off(logN);
     if constexpr (LOGT == 12) {
@@ -1359,11 +1393,24 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
     }
   }
   __syncthreads();
-  if (M == TT && bmode == 0)
-    ntt_fwd_tile<true, AS>(lds, LOGT - pass_logr(LOGT), 2 * M, 0, tws, pc);   // the passes after the first
-  else ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
   const uint2 sc = prime == 0 ? scale0 : (prime == 1 ? scale1 : scale2);
-  if (M == TT) {
+  // full rows: the first forward pass ran on registers at the load; the last
+  // forward pass, the pointwise product and the first inverse pass run on
+  // registers too (mid), except in rows of 2^13, where the extra registers
+  // would cost that tile its second workgroup per CU
+  const bool full = M == TT && bmode == 0;
+  const bool mid = full && LOGT != 13;
+  if (mid) {
+    ntt_fwd_tile<true, AS>(lds, LOGT - pass_logr(LOGT), 2 * M, 0, tws, pc, threadIdx.x, blockDim.x, false, 4);
+    mid_passes<AS, false>(lds, lds_pad(16 * threadIdx.x), lds_pad(TT + 16 * threadIdx.x), sc, pc);
+    pass_sync(4, 0);
+  } else if (full) {
+    ntt_fwd_tile<true, AS>(lds, LOGT - pass_logr(LOGT), 2 * M, 0, tws, pc);   // the passes after the first
+  } else {
+    ntt_fwd_tile<true, AS>(lds, logM, bmode == 2 ? M : 2 * M, 0, tws, pc);
+  }
+  if (mid) {
+  } else if (M == TT) {
     // thread g wrote A and B at [16 g, 16 g + 16): pointwise in place, and the
     // first inverse pass reads the same positions in the same thread
 #pragma unroll
@@ -1386,7 +1433,8 @@ k_row(int logN, int logM, int logSl, int logLl, int bmode, uint32_t* __restrict_
   const bool rp = M == TT;
   uint32_t vo[16];
   if (rp) {
-    ntt_inv_tile<true, AS>(lds, LOGT - pass_logr(LOGT), M, 0, itws, pc);   // every pass but the last
+    // every pass but the last (and but the first when it ran on registers)
+    ntt_inv_tile<true, AS>(lds, LOGT - pass_logr(LOGT), M, 0, itws, pc, threadIdx.x, blockDim.x, mid ? 8 : 4);
     row_last_inv<LOGT, AS>(lds, vo, itws, pc);
   } else {
     ntt_inv_tile<true, AS>(lds, logM, M, 0, itws, pc);
