@@ -820,6 +820,67 @@ struct PassGeom {
   }
 };
 
+// The innermost column pass (sub-problems of 16 rows, logSR = 0) on
+// registers: group threadIdx.x + 256 u of a tile of NV * 256 words (C =
+// 2^logC <= 256 columns) holds rows 16 h .. 16 h + 15 of column c (h = g >>
+// logC, c = g mod C).  Forward: the pass's outputs go straight to F, with the
+// pass's own twiddles omega_S^(j f(q)) when tw (q the row, j = j0 + c);
+// inverse: the pass's inputs come straight from F.  Same arithmetic as
+// groups_fwd / groups_inv at logSR = 0.
+template <int AS, int NV>
+__device__ __forceinline__ void col_last_fwd_store(const uint32_t* lds, __amdgpu_buffer_rsrc_t rf, uint32_t cbase,
+                                                   uint32_t rowB, uint32_t logC, int tw, uint32_t j0, int logL,
+                                                   uint32_t ysh, const uint2* __restrict__ lo,
+                                                   const uint32_t* __restrict__ hi, const PrimeC& pc) {
+  const uint32_t C = 1u << logC;
+#pragma unroll
+  for (int u = 0; u < NV / 16; u++) {
+    const uint32_t g = threadIdx.x + 256u * u;
+    const uint32_t h = g >> logC, c = g & (C - 1);
+    const uint32_t b = (h << (4 + logC)) + c;
+    uint32_t x[16];
+#pragma unroll
+    for (int j1 = 0; j1 < 16; j1++) x[j1] = lds[b + j1 * C];
+    dft_fwd<4, AS, false, false>(x, pc);
+    const uint32_t ob = (cbase + c) * 4u;
+#pragma unroll
+    for (int k1 = 0; k1 < 16; k1++) {
+      const uint32_t q = 16 * h + k1;
+      uint32_t val = x[brev_c(k1, 4)];
+      if (tw) {
+        const uint32_t y = (((j0 + c) * out_freq(q, logL)) << ysh) & ((1u << tw_logn<AS>()) - 1);
+        const uint2 l = lo[y & (TW2_LO - 1)];
+        const uint32_t w = mul_tw(hi[y >> TW2_LO_BITS], l.x, l.y, pc.p);
+        val = data_tw<AS>(val, make_uint2(w, w * pc.pinv), pc.p);
+      }
+      buf_st(rf, ob + q * rowB, val);
+    }
+  }
+}
+template <int AS, int NV>
+__device__ __forceinline__ void col_first_inv_load(uint32_t* lds, __amdgpu_buffer_rsrc_t rf, uint32_t cbase,
+                                                   uint32_t rowB, uint32_t logC, const PrimeC& pc) {
+  const uint32_t C = 1u << logC;
+  uint32_t v[NV / 16][16];
+#pragma unroll
+  for (int u = 0; u < NV / 16; u++) {
+    const uint32_t g = threadIdx.x + 256u * u;
+    const uint32_t h = g >> logC, c = g & (C - 1);
+    const uint32_t ob = (cbase + c) * 4u + 16 * h * rowB;
+#pragma unroll
+    for (int k1 = 0; k1 < 16; k1++) v[u][brev_c(k1, 4)] = buf_ld(rf, ob + k1 * rowB);
+  }
+#pragma unroll
+  for (int u = 0; u < NV / 16; u++) {
+    const uint32_t g = threadIdx.x + 256u * u;
+    const uint32_t h = g >> logC, c = g & (C - 1);
+    const uint32_t b = (h << (4 + logC)) + c;
+    dft_inv<4, AS, false>(v[u], pc);
+#pragma unroll
+    for (int j1 = 0; j1 < 16; j1++) lds[b + j1 * C] = v[u][j1];
+  }
+}
+
 // The first forward column pass on registers for an operand of at most N/2
 // words: in a tile of NV * 256 words and at most 256 columns, group
 // threadIdx.x + 256 u of that pass (radix 2^LR) has its lower half at the
@@ -917,7 +978,18 @@ k_pass_fwd(DescView dv, PassGeom pg, int first, int tw, int pre, int plogS, int 
       default: col_first_fwd<4, AS, NV>(lds, v, pg.logL, pg.logC, tw1, pc); break;
     }
     __syncthreads();
-    ntt_fwd_tile<false, AS>(lds, pg.logL - lr, T, (uint32_t)pg.logC, tws, pc, threadIdx.x, blockDim.x, false);
+    const int rest = pg.logL - lr;
+    if (rest >= 4) {
+      // the passes between the first and the last through LDS, the last on
+      // registers straight to F
+      if (rest > 4)
+        ntt_fwd_tile<false, AS>(lds, rest, T, (uint32_t)pg.logC, tws, pc, threadIdx.x, blockDim.x, false, 4);
+      col_last_fwd_store<AS, NV>(lds, words_rsrc(f, N), (uint32_t)base + j0, rowB, (uint32_t)pg.logC, tw, j0,
+                                 pg.logL, tw_logn<AS>() - pg.logS, tb.tw2lo + (size_t)prime * TW2_LO,
+                                 tb.tw2hi + (size_t)prime * TW2_HI, pc);
+      return;
+    }
+    ntt_fwd_tile<false, AS>(lds, rest, T, (uint32_t)pg.logC, tws, pc, threadIdx.x, blockDim.x, false);
   } else if (first && lin) {
     const MulDesc d = dv.get(m);
     const __amdgpu_buffer_rsrc_t rs = words_rsrc(op ? bin + d.b_off : ain + d.a_off, op ? d.lb : d.la);
@@ -1106,7 +1178,12 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   const uint32_t RI = NTT_COL_THREADS >> (lin ? pg.logC : 0);
   const uint32_t rowB = 4u << logSig;
   const uint32_t off0 = ((uint32_t)base + ((threadIdx.x >> pg.logC) << logSig) + j0 + (threadIdx.x & (C - 1))) * 4u;
-  if (!tw) {
+  // the first inverse pass (sub-problems of 16 rows) on the loaded words
+  constexpr int NVT = (1 << LOGT) / NTT_COL_THREADS;
+  const bool regf = !tw && lin && T == (1u << LOGT) && pg.logL > 4;
+  if (regf) {
+    col_first_inv_load<AS, NVT>(lds, words_rsrc(f, N), (uint32_t)base + j0, rowB, (uint32_t)pg.logC, pc);
+  } else if (!tw) {
     // the pass next to the rows: k_row applied this pass's twiddles
     const __amdgpu_buffer_rsrc_t rs = words_rsrc(f, N);
     for (uint32_t t0 = 0; t0 < T; t0 += COL_BATCH * NTT_COL_THREADS) {
@@ -1158,11 +1235,14 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
   __syncthreads();
   const uint2* itws = tb.itws + (size_t)prime * TWS_ENTRIES;
   if (last && lin && T == (1u << LOGT)) {
-    // the outermost pass: every pass but the last through LDS, the last on
-    // registers straight to the residues (positions at or past L fall
-    // outside the buffer's range: not written)
+    // the outermost pass: every pass but the last (and but the first when it
+    // ran on registers) through LDS, the last on registers straight to the
+    // residues (positions at or past L fall outside the buffer's range: not
+    // written)
     const int lr0 = pass_logr(pg.logL);
-    ntt_inv_tile<false, AS>(lds, pg.logL - lr0, T, (uint32_t)pg.logC, itws, pc);
+    if (!regf || pg.logL - lr0 > 4)
+      ntt_inv_tile<false, AS>(lds, pg.logL - lr0, T, (uint32_t)pg.logC, itws, pc, threadIdx.x, blockDim.x,
+                              regf ? 8 : 4);
     const MulDesc d = dv.get(m);
     const uint64_t L = (uint64_t)d.la + d.lb;
     uint32_t* out = res + (size_t)prime * res_stride + d.r_off;
@@ -1180,7 +1260,7 @@ k_pass_inv(DescView dv, PassGeom pg, int last, int tw, int post, int plogS, int 
       for (uint64_t j = N + threadIdx.x; j < L; j += blockDim.x) out[j] = 0u;
     return;
   }
-  ntt_inv_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, itws, pc);
+  ntt_inv_tile<false, AS>(lds, pg.logL, T, (uint32_t)pg.logC, itws, pc, threadIdx.x, blockDim.x, regf ? 8 : 4);
   if (!last) {
     if (!post) {
       if (lin) {
