@@ -735,6 +735,13 @@ def main():
     roof = step_roof = kms_step = None
     if not args.no_roofline:
         roof, step_roof, kms_step, dom = roofline(cat, n, out, args.steps, st, ms)
+        # Phase 2 alone: the step less the separately timed Phase 1 (which runs
+        # first in the same graph), and the separate Phase 2 call
+        p2 = ms - phases["phase1_ms"]
+        bf = step_roof["butterflies_per_step"]
+        step_roof["phase2_ms_in_step"] = round(p2, 4)
+        step_roof["phase2_frac"] = round(bf / (p2 / 1e3) / PEAK_BFLY, 4)
+        step_roof["phase2_separate_call_frac"] = round(bf / (phases["phase2_ms"] / 1e3) / PEAK_BFLY, 4)
         if dom == "k_ntt_lds":
             roof["steady_state"] = steady_state(cat)
         log("bench: dominant kernel %s: %.4f ms avg over %d launches, frac %.3f" % (
