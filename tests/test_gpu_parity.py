@@ -363,12 +363,25 @@ def test_schedules_change_speed_not_bits(cat, schedule):
     rng = np.random.default_rng(4)
     la = np.rint(2 ** rng.uniform(3, 15, 40)).astype(np.int64)
     lb = np.rint(2 ** rng.uniform(3, 15, 40)).astype(np.int64)
+    # and transforms of 2^19 and 2^20 points (two column passes under the
+    # short schedule, the first applying its own twiddles)
+    la = np.concatenate([la, [(1 << 18) - 5, 300000]])
+    lb = np.concatenate([lb, [(1 << 18) - 3, 70000]])
     a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
     b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
     da = cat.from_numpy(_rand(rng, int(a_off[-1])))
     db = cat.from_numpy(_rand(rng, int(b_off[-1])))
-    c0, _ = cat.mul_batched(da, a_off, db, b_off)
+    c0, c_off = cat.mul_batched(da, a_off, db, b_off)
     c0 = c0.clone()
+    if schedule is _schedule_short:
+        # the two large products of the default schedule against the oracle
+        av, bv, cv = cat.to_numpy(da), cat.to_numpy(db), cat.to_numpy(c0)
+        for i in (len(la) - 2, len(la) - 1):
+            xa = av[int(a_off[i]):int(a_off[i + 1])]
+            xb = bv[int(b_off[i]):int(b_off[i + 1])]
+            oc, _ = oracle.mul_batched(xa, np.array([0, len(xa)], dtype=np.uint64), xb,
+                                       np.array([0, len(xb)], dtype=np.uint64))
+            assert np.array_equal(cv[int(c_off[i]):int(c_off[i + 1])], oc), i
     t = cat.get_tuning()
     schedule(t)
     try:
