@@ -120,15 +120,11 @@ __device__ uint32_t build_seeds(uint32_t s, uint8_t* comp, uint32_t* tmp, uint32
 template <int SL = SIEVE_SEG_LOG>
 __device__ void mark_segment(uint32_t* bits, uint64_t i_lo, uint32_t len, const uint32_t* seeds, uint32_t nseeds) {
   constexpr uint32_t SEG = 1u << SL, WORDS = SEG / 32;
+  constexpr int NPRE = 17;   // odd primes below 64
+  __shared__ uint32_t pre_q[NPRE], pre_r[NPRE], pre_d[NPRE];
+  __shared__ uint64_t pre_pat[NPRE];
+  __shared__ uint32_t pre_n;
   const uint32_t T = blockDim.x, tid = threadIdx.x;
-  for (uint32_t w = tid; w < WORDS; w += T) {
-    uint32_t b0 = w * 32;
-    uint32_t v = 0;
-    if (b0 + 32 <= len) v = 0xFFFFFFFFu;
-    else if (b0 < len) v = (1u << (len - b0)) - 1u;
-    bits[w] = v;
-  }
-  __syncthreads();
   // m_lo = 2 i_lo + 1 <= 2n + 1 < 2^32: the first odd multiple q t >= m_lo
   // (t >= q) comes from one 32-bit division (a 64-bit one is a long software
   // sequence on the GPU); the product q t may reach 2^32 and stays 64-bit
@@ -140,8 +136,58 @@ __device__ void mark_segment(uint32_t* bits, uint64_t i_lo, uint32_t len, const 
     if (!(t & 1)) t++;
     return ((uint64_t)q * t - 1) / 2 - i_lo;
   };
+  // Odd seeds q < 64 with q^2 <= m_lo (every odd multiple of q in the segment
+  // is marked, at the positions idx, idx + q, ...) are cleared word by word
+  // with a periodic bit pattern instead of one LDS atomic per multiple: word w
+  // loses the bits r, r + q, ... < 32 with r = (idx - 32 w) mod q, i.e. the
+  // pattern sum_k 2^(k q) shifted left by r.
+  if (tid == 0) {
+    uint32_t c = 0;
+    for (uint32_t k = 1; k < nseeds && c < NPRE; k++) {
+      const uint32_t q = seeds[k];
+      if (q >= 64 || (uint64_t)q * q > m_lo) break;
+      pre_q[c++] = q;
+    }
+    pre_n = c;
+  }
+  __syncthreads();
+  const uint32_t npre = pre_n;
+  if (tid < npre) {
+    const uint32_t q = pre_q[tid];
+    pre_r[tid] = (uint32_t)(first_index(q) % q);
+    pre_d[tid] = (32u * T) % q;   // the step of r between a thread's words
+    uint64_t pat = 0;
+    for (uint32_t b = 0; b < 64; b += q) pat |= 1ull << b;
+    pre_pat[tid] = pat;
+  }
+  __syncthreads();
+  uint32_t rr[NPRE];
+#pragma unroll
+  for (int j = 0; j < NPRE; j++) {
+    if (j < (int)npre) {
+      const uint32_t q = pre_q[j];
+      const uint32_t s0 = (32u * tid) % q;
+      rr[j] = pre_r[j] >= s0 ? pre_r[j] - s0 : pre_r[j] + q - s0;
+    }
+  }
+  for (uint32_t w = tid; w < WORDS; w += T) {
+    uint32_t b0 = w * 32;
+    uint32_t v = 0;
+    if (b0 + 32 <= len) v = 0xFFFFFFFFu;
+    else if (b0 < len) v = (1u << (len - b0)) - 1u;
+#pragma unroll
+    for (int j = 0; j < NPRE; j++) {
+      if (j < (int)npre) {
+        v &= ~(uint32_t)(pre_pat[j] << rr[j]);
+        const uint32_t q = pre_q[j], d = pre_d[j];
+        rr[j] = rr[j] >= d ? rr[j] - d : rr[j] + q - d;
+      }
+    }
+    bits[w] = v;
+  }
+  __syncthreads();
   // small odd seeds: every thread marks a share of the multiples of q
-  uint32_t k = 1;
+  uint32_t k = 1 + npre;
   for (; k < nseeds; k++) {
     const uint32_t q = seeds[k];
     if ((uint64_t)q * SIEVE_THREADS > 2 * SEG) break;   // fewer multiples than 2 per thread
