@@ -27,6 +27,7 @@
 #define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment (default)
 #define SIEVE_WORDS (SIEVE_SEG / 32)
 #define SIEVE_THREADS 256
+#define SCATTER_STAGE 8192                      // primes of a segment staged in LDS by k_scatter (32 KB)
 #define SEED_MAX 6544                           // pi(65535) = 6542
 
 struct GroupTable {
@@ -371,8 +372,28 @@ __global__ void __launch_bounds__(SIEVE_THREADS) k_scatter(uint64_t i0, const ui
   uint32_t c = 0;
 #pragma unroll
   for (uint32_t k = 0; k < WPT; k++) { w[k] = bm[tid * WPT + k]; c += __popc(w[k]); }
-  uint32_t r = block_excl_scan_1024(c, tmp, nullptr);
-  uint64_t at = (uint64_t)gt->n_seed_e1 + seg_off[blockIdx.x] + r;
+  uint32_t total;
+  uint32_t r = block_excl_scan_1024(c, tmp, &total);
+  const uint64_t base = (uint64_t)gt->n_seed_e1 + seg_off[blockIdx.x];
+  if (total <= SCATTER_STAGE) {
+    // the segment's primes are one contiguous run: staged in LDS in order,
+    // then written by consecutive threads to consecutive words
+    __shared__ uint32_t stage[SCATTER_STAGE];
+#pragma unroll
+    for (uint32_t k = 0; k < WPT; k++) {
+      uint32_t v = w[k];
+      while (v) {
+        uint32_t b = __ffs(v) - 1;
+        v &= v - 1;
+        stage[r++] = (uint32_t)(2 * (i_lo + (tid * WPT + k) * 32 + b) + 1);
+      }
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < total; j += SIEVE_THREADS)
+      if (base + j < cap) primes[base + j] = stage[j];
+    return;
+  }
+  uint64_t at = base + r;
 #pragma unroll
   for (uint32_t k = 0; k < WPT; k++) {
     uint32_t v = w[k];
