@@ -3508,7 +3508,8 @@ cat_status prime_power_product(const uint32_t* d_entries, const uint32_t* h_exps
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (uint32_t*)d_bits, (uint64_t)(2 * CAT_MAX_GROUPS), 0u);
   LAUNCHCHK();
   if (G.ng) {
-    hipLaunchKernelGGL(k_group_bits, dim3(256, G.ng), dim3(256), 0, st, (const uint32_t*)(W + Ly.primes),
+    // enough workgroups per group to keep HBM busy on the largest group
+    hipLaunchKernelGGL(k_group_bits, dim3(2048, G.ng), dim3(256), 0, st, (const uint32_t*)(W + Ly.primes),
                        (const uint64_t*)d_off, G.ng, d_bits);
     LAUNCHCHK();
   }
