@@ -40,7 +40,7 @@ def test_factor_small_n_all(cat):
         assert np.array_equal(cat.to_numpy(pr), op), n
 
 
-@pytest.mark.parametrize("n", [401, 1000, 4096, 65535, 65536, 100000, 262143, 1000000])
+@pytest.mark.parametrize("n", [401, 1000, 2047, 2048, 2049, 4096, 65535, 65536, 100000, 262143, 1000000, 3000000])
 def test_factor_selected(cat, n):
     _say("factor", n)
     exps, off, pr = cat.factor(n)
