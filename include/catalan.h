@@ -347,17 +347,21 @@ typedef struct {
 cat_status cat_tune_set(const cat_tuning* t);
 cat_status cat_tune_get(cat_tuning* t);
 
-/* Lower tree levels fused into one launch (the batched form of C(n) and of
- * the other Phase-2 entry points): the consecutive levels above the
- * schoolbook levels whose products are one-workgroup transforms of at most
- * 2^max_logn coefficients run in one kernel that keeps each 4,096-leaf tile
- * of a group in LDS from the first of them to the last (three-prime
- * transforms, Garner recombination and carries inside the workgroup), in
- * trees of at most 2^22 leaves (larger levels fill the GPU, where the
- * separate launches are faster).
- * max_logn = 0 turns the fusion off (every level is then a transform launch
- * and a carry launch); otherwise 4..12 (default 12).  The result is the same
- * bit for bit either way.  Cached C(n) plans are dropped. */
+/* Fused launches of one-workgroup transforms.  Tree levels (the batched form
+ * of C(n) and of the other Phase-2 entry points): the consecutive levels
+ * above the schoolbook levels whose products are one-workgroup transforms of
+ * at most 2^max_logn coefficients run in one kernel that keeps each
+ * 4,096-leaf tile of a group in LDS from the first of them to the last
+ * (three-prime transforms, Garner recombination and carries inside the
+ * workgroup), in trees of at most 2^22 leaves.  Generic batches
+ * (bigint_mul_batched, batched form): the buckets of at most 2^max_logn
+ * coefficients in one launch over a tile table.
+ * max_logn = 0 turns both off (every level or bucket is then a transform
+ * launch and a carry launch); 4..12 turns both on up to 2^max_logn;
+ * CAT_FUSED_DEFAULT restores the defaults: generic batches fused up to 2^12,
+ * tree levels not fused (the separate launches are at least as fast).  The
+ * result is the same bit for bit either way.  Cached C(n) plans are dropped. */
+#define CAT_FUSED_DEFAULT 0xFFFFFFFFu
 cat_status cat_fused_levels_set(uint32_t max_logn);
 
 /* Order of the outer product (Alg. 2: C is the product of the P_e).  With

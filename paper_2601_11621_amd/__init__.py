@@ -216,11 +216,17 @@ def set_lookback_polls(polls: Optional[int]) -> None:
     _check(load().cat_lookback_polls_set(POLLS_AUTO if polls is None else int(polls)), "cat_lookback_polls_set")
 
 
-def set_fused_levels(max_logn: int = 12) -> None:
-    """Fuse the tree levels with transforms of up to 2^max_logn coefficients
-    into one launch (0: every level is a transform and a carry launch).  Same
-    results either way."""
-    _check(load().cat_fused_levels_set(int(max_logn)), "cat_fused_levels_set")
+FUSED_DEFAULT = 0xFFFFFFFF
+
+
+def set_fused_levels(max_logn: Optional[int] = 12) -> None:
+    """Fuse the tree levels, and the buckets of a generic batch, with
+    transforms of up to 2^max_logn coefficients into one launch (0: every
+    level or bucket is a transform and a carry launch; None: the library's
+    defaults, generic batches fused up to 2^12 and tree levels not fused).
+    Same results either way."""
+    v = FUSED_DEFAULT if max_logn is None else int(max_logn)
+    _check(load().cat_fused_levels_set(v), "cat_fused_levels_set")
 
 
 def set_lazy_primes(max_logn: int = 23) -> None:

@@ -429,16 +429,19 @@ struct Stage {
 };
 
 // Tree levels fused into one launch: consecutive one-workgroup levels with
-// transforms of up to 2^g_fuse_logn coefficients (0: none, each level then
-// is a transform launch plus a carry launch), for trees of at most
+// transforms of up to 2^g_fuse_tree_logn coefficients (0: none, each level
+// then is a transform launch plus a carry launch), for trees of at most
 // FUSE_MAX_LEAVES leaves in the groups concerned.  A fused workgroup holds
 // the tiles of all three primes (121 KB of LDS, one workgroup and 12 waves per
 // CU) and pays a barrier per transform pass across them; the separate
-// launches run four 4-wave workgroups per CU.  Below about 2^22 leaves a
-// level cannot fill the GPU and the saved launches and carry round trips
-// win (C(10^7): 0.96 -> 0.92 ms); above it the separate launches are faster
-// (C(10^8): 5.91 vs 6.05 ms; C(2,050,572,903): 136.5 vs 137.9 ms).
+// launches run four 4-wave workgroups per CU.  Off by default: since the
+// one-workgroup transform runs its outermost and innermost passes on
+// registers, the separate launches are as fast at n = 10^7 and faster at
+// every other n measured (C(10^5): 0.28 vs 0.32 ms, C(3·10^7): 1.48 vs 1.60
+// ms).  Generic batches fuse their one-workgroup buckets of up to
+// 2^g_fuse_logn coefficients into one k_mul_fused launch.
 uint32_t g_fuse_logn = FT_LOGT;
+uint32_t g_fuse_tree_logn = 0;
 #define FUSE_MAX_LEAVES (1ull << 22)
 
 // Transforms of up to 2^g_lazy_logn points take the lazy prime set (0: none).
@@ -665,7 +668,7 @@ TreeShape tree_shape(const Plan& P) {
   sh.jleaf = Kmax_g > 1 ? std::min(sh.J, LF) : 0;
   // the consecutive levels above the leaf and schoolbook levels whose
   // products are one-workgroup transforms of at most 2^g_fuse_logn coefficients
-  for (int j = std::max(sh.jleaf, 3); j < sh.J && j + 1 <= (int)g_fuse_logn && leaves <= FUSE_MAX_LEAVES; j++) {
+  for (int j = std::max(sh.jleaf, 3); j < sh.J && j + 1 <= (int)g_fuse_tree_logn && leaves <= FUSE_MAX_LEAVES; j++) {
     if (classify2(1ull << j, 1ull << j).cls == CLS_LDS) {
       if (sh.jf0 < 0) sh.jf0 = j;
       sh.jf1 = j;
@@ -2577,8 +2580,14 @@ cat_status cat_tune_set(const cat_tuning* t) {
 
 cat_status cat_fused_levels_set(uint32_t max_logn) {
   std::lock_guard<std::recursive_mutex> lk(g.mu);
-  if (max_logn != 0 && (max_logn < 4 || max_logn > FT_LOGT)) return CAT_EINVAL;
-  g_fuse_logn = max_logn;
+  if (max_logn == CAT_FUSED_DEFAULT) {
+    g_fuse_logn = FT_LOGT;
+    g_fuse_tree_logn = 0;
+  } else {
+    if (max_logn != 0 && (max_logn < 4 || max_logn > FT_LOGT)) return CAT_EINVAL;
+    g_fuse_logn = max_logn;
+    g_fuse_tree_logn = max_logn;
+  }
   // cached plans were made with the old setting
   if (!g.plans.empty() || !g.noalloc_plans.empty()) HIPCHK(hipDeviceSynchronize());
   for (auto& kv : g.plans) free_plan(kv.second);

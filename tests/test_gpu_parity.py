@@ -420,7 +420,7 @@ def test_fused_levels_same_bits(cat, logn):
         got = cat.to_numpy(cat.exact(10**7, mode="graph"))
         assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
     finally:
-        cat.set_fused_levels(12)
+        cat.set_fused_levels(None)
 
 
 @pytest.mark.parametrize("lazy", [0, 12, 23])
@@ -457,7 +457,7 @@ def test_lazy_primes_same_bits(cat, lazy, fused):
         assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == gold["sha256_le_limbs"]
     finally:
         cat.set_lazy_primes(23)
-        cat.set_fused_levels(12)
+        cat.set_fused_levels(None)
 
 
 @pytest.mark.parametrize("fused", [0, 12])
@@ -489,7 +489,7 @@ def test_outer_node_same_bits(cat, on, fused):
         assert (cat.stats()["outer_level"] >= 6) == on
     finally:
         cat.set_outer_node(True)
-        cat.set_fused_levels(12)
+        cat.set_fused_levels(None)
 
 
 def _ones_square(a):
