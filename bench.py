@@ -45,7 +45,8 @@ HEADLINE_N = 2050572903
 # peak.  This library's own butterfly issues 14 instructions (the primes
 # exceed 2^31, which leaves no room for lazy reduction); the fraction against
 # that count is reported as a labelled secondary figure.
-VALU_LANE_OPS = 256 * 64 * 2.4e9
+CLOCK_HZ = 2.4e9
+VALU_LANE_OPS = 256 * 64 * CLOCK_HZ
 BFLY_OPS = 9.0
 BFLY_OPS_CODE = 14.0
 PEAK_BFLY = VALU_LANE_OPS / BFLY_OPS
@@ -673,6 +674,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--only-kernel", default="", help="profiling aid: run graph steps only")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only measure the issue rate of the VALU instruction forms the butterflies use")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -697,6 +700,21 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "reps": 5}))
+        return
+
+    if args.valu_rates:
+        cat.init(0)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        lane_rate = cus * 64 * CLOCK_HZ          # one lane-op per lane per clock
+        rates = {}
+        for op in cat.VALU_OPS:
+            r, ms = cat.valu_rate(op, 4096)
+            r, ms = cat.valu_rate(op, max(64, int(4096 * 40.0 / max(ms, 1e-3))))   # about 40 ms per launch
+            rates[op] = {"lane_ops_per_s": r, "ms": round(ms, 3), "of_full_rate": round(r / lane_rate, 4),
+                         "cycles_per_wave64_instr": round(4.0 * lane_rate / r, 2)}
+            log("bench: %-14s %.3e lane-ops/s = %.3f of %d CU x 64 lanes x %.1f GHz" %
+                (op, r, r / lane_rate, cus, CLOCK_HZ / 1e9))
+        print(json.dumps({"valu_rates": rates, "compute_units": cus, "clock_hz": CLOCK_HZ}))
         return
 
     cat.init(0)

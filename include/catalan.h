@@ -412,6 +412,26 @@ cat_status cat_lookback_polls_set(uint32_t polls);
 cat_status cat_timer_set(const char* kernel);
 cat_status cat_timer_get(double* ms, uint64_t* launches, double* work);
 
+/* VALU issue-rate probe (measurement only).  Times one launch of a kernel in
+ * which every lane runs iters x 32 dependent-chain copies of one instruction
+ * form, 8 independent chains per lane and 8 waves per SIMD on every compute
+ * unit, on the default stream after one untimed launch, and returns the lane
+ * operations per second (and the launch time in ms when `ms` is not NULL).
+ * The integer forms are the ones the transform butterflies are built from, so
+ * the figures state the cost of a butterfly in cycles.  op: CAT_VALU_* below;
+ * iters in 1 .. 2^20.  Allocates and frees a small device buffer.
+ * CAT_EINVAL for a bad op, iters or a NULL rate pointer. */
+enum {
+  CAT_VALU_ADD_U32 = 0,     /* v_add_u32 */
+  CAT_VALU_MIN_U32 = 1,     /* v_min_u32 */
+  CAT_VALU_MUL_LO_U32 = 2,  /* v_mul_lo_u32 */
+  CAT_VALU_MUL_HI_U32 = 3,  /* v_mul_hi_u32 */
+  CAT_VALU_MAD_U64_U32 = 4, /* v_mad_u64_u32 */
+  CAT_VALU_FMA_F32 = 5,     /* v_fma_f32 (reference: the published fp32 vector rate counts 2 flops per lane-op) */
+  CAT_VALU_NOPS = 6
+};
+cat_status cat_valu_rate(int op, uint32_t iters, double* lane_ops_per_s, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

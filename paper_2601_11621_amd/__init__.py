@@ -36,6 +36,7 @@ EXPORTS = [
     "decimal_sizes", "bigint_to_decimal", "catalan_exact_noalloc", "catalan_noalloc_max_bytes",
     "cat_fused_levels_set", "cat_lazy_primes_set", "cat_outer_node_set", "bigint_decimal_digits_workspace", "bigint_decimal_digits", "bigint_mul_check",
     "catalan_batch_sizes", "catalan_batch_begin", "catalan_batch_continue", "catalan_batch_end",
+    "cat_valu_rate",
 ]
 
 
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH):
         "bigint_residues": ([vp, ctypes.c_size_t, u64p, vp, ctypes.c_size_t, vp], st),
         "cat_timer_set": ([ctypes.c_char_p], st),
         "cat_timer_get": ([ctypes.POINTER(ctypes.c_double), u64p, ctypes.POINTER(ctypes.c_double)], st),
+        "cat_valu_rate": ([ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)], st),
         "catalan_begin": ([ctypes.c_uint64, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
         "cat_ticket_query": ([vp], st),
         "catalan_continue": ([vp, vp, ctypes.c_size_t], st),
@@ -601,6 +604,18 @@ def timer_get():
     wk = ctypes.c_double()
     _check(load().cat_timer_get(ctypes.byref(ms), ctypes.byref(ln), ctypes.byref(wk)), "cat_timer_get")
     return ms.value, ln.value, wk.value
+
+
+# instruction forms of the issue-rate probe, in the C ABI's order
+VALU_OPS = ("v_add_u32", "v_min_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_fma_f32")
+
+
+def valu_rate(op: str, iters: int = 4096):
+    """(lane operations per second, launch ms) of one VALU instruction form."""
+    rate = ctypes.c_double()
+    ms = ctypes.c_double()
+    _check(load().cat_valu_rate(VALU_OPS.index(op), iters, ctypes.byref(rate), ctypes.byref(ms)), "cat_valu_rate")
+    return rate.value, ms.value
 
 
 def residues(x, stream=None):

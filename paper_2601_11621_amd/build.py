@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcatalan.so")
 SOURCES = ["catalan.hip"]
 DEPS = ["catalan.hip", "common.hpp", "ntt.inc.hip", "small.inc.hip", "fused.inc.hip", "sieve.inc.hip", "ratio.inc.hip",
-        "decimal.inc.hip", "host.inc.hip", "decimal_host.inc.hip"]
+        "decimal.inc.hip", "host.inc.hip", "decimal_host.inc.hip", "rates.inc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

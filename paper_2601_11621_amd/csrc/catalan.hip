@@ -9,3 +9,4 @@
 #include "decimal.inc.hip"
 #include "host.inc.hip"
 #include "decimal_host.inc.hip"
+#include "rates.inc.hip"

@@ -555,3 +555,24 @@ def test_mul_batched_is_asynchronous(cat):
     # a different shape (one product more) is planned afresh
     c2, c2_off = cat.mul_batched(da, a_off[:31], db, b_off[:31])
     assert np.array_equal(cat.to_numpy(c2), oc[: int(c2_off[-1])])
+
+
+def test_valu_rate_probe(cat):
+    """The instruction issue-rate probe runs every form it names and rejects
+    bad arguments; no form issues faster than two lane-ops per lane per clock
+    at 2.4 GHz (a loose bound that catches a timing or counting slip)."""
+    import ctypes
+
+    import torch
+
+    lib = cat.load()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for op in cat.VALU_OPS:
+        r, ms = cat.valu_rate(op, 64)
+        assert ms > 0 and 0 < r < 2 * cus * 64 * 2.4e9, (op, r, ms)
+    rate = ctypes.c_double()
+    assert lib.cat_valu_rate(len(cat.VALU_OPS), 64, ctypes.byref(rate), None) == cat.CAT_EINVAL
+    assert lib.cat_valu_rate(-1, 64, ctypes.byref(rate), None) == cat.CAT_EINVAL
+    assert lib.cat_valu_rate(0, 0, ctypes.byref(rate), None) == cat.CAT_EINVAL
+    assert lib.cat_valu_rate(0, (1 << 20) + 1, ctypes.byref(rate), None) == cat.CAT_EINVAL
+    assert lib.cat_valu_rate(0, 64, None, None) == cat.CAT_EINVAL
