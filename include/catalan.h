@@ -427,7 +427,7 @@ enum {
   CAT_VALU_MUL_LO_U32 = 2,  /* v_mul_lo_u32 */
   CAT_VALU_MUL_HI_U32 = 3,  /* v_mul_hi_u32 */
   CAT_VALU_MAD_U64_U32 = 4, /* v_mad_u64_u32 */
-  CAT_VALU_FMA_F32 = 5,     /* v_fma_f32 (reference: the published fp32 vector rate counts 2 flops per lane-op) */
+  CAT_VALU_FMA_F32 = 5,     /* v_fma_f32, for reference (2 flops per lane-op; the published fp32 vector peak assumes packed FMAs) */
   CAT_VALU_NOPS = 6
 };
 cat_status cat_valu_rate(int op, uint32_t iters, double* lane_ops_per_s, double* ms);
