@@ -503,6 +503,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Sieve segment size of the range of odd indices [i0, i_end): 2^16 odd
 // numbers when that still gives 2^10 segments (four per CU), else 2^14.
 int sieve_seg_log(uint64_t i0, uint64_t i_end) {
+  if (i_end > i0 && i_end - i0 >= (1024ull << SIEVE_SEG_LOG_HUGE)) return SIEVE_SEG_LOG_HUGE;
   return (i_end > i0 && i_end - i0 >= (1024ull << SIEVE_SEG_LOG_BIG)) ? SIEVE_SEG_LOG_BIG : SIEVE_SEG_LOG;
 }
 
@@ -1758,7 +1759,11 @@ cat_status run_phase1(const Layout& Ly, char* wb, uint32_t* primes, uint64_t cap
                      gt, (uint32_t*)gt, (uint64_t)Ly.ctl_words);
   LAUNCHCHK();
   if (Ly.nseg > 0) {
-    if (Ly.seg_log == SIEVE_SEG_LOG_BIG)
+    if (Ly.seg_log == SIEVE_SEG_LOG_HUGE)
+      hipLaunchKernelGGL(k_sieve<SIEVE_SEG_LOG_HUGE>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0,
+                         Ly.i_end, (const uint32_t*)(W + Ly.seeds), (const GroupTable*)gt, W + Ly.bitmap,
+                         W + Ly.seg_cnt);
+    else if (Ly.seg_log == SIEVE_SEG_LOG_BIG)
       hipLaunchKernelGGL(k_sieve<SIEVE_SEG_LOG_BIG>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.n, Ly.i0,
                          Ly.i_end, (const uint32_t*)(W + Ly.seeds), (const GroupTable*)gt, W + Ly.bitmap,
                          W + Ly.seg_cnt);
@@ -1772,7 +1777,11 @@ cat_status run_phase1(const Layout& Ly, char* wb, uint32_t* primes, uint64_t cap
                      W + Ly.seg_off, (const uint32_t*)(W + Ly.seeds), (const int32_t*)(W + Ly.seed_e), primes, cap, gt);
   LAUNCHCHK();
   if (Ly.nseg > 0) {
-    if (Ly.seg_log == SIEVE_SEG_LOG_BIG)
+    if (Ly.seg_log == SIEVE_SEG_LOG_HUGE)
+      hipLaunchKernelGGL(k_scatter<SIEVE_SEG_LOG_HUGE>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.i0,
+                         (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
+                         primes, cap);
+    else if (Ly.seg_log == SIEVE_SEG_LOG_BIG)
       hipLaunchKernelGGL(k_scatter<SIEVE_SEG_LOG_BIG>, dim3((uint32_t)Ly.nseg), dim3(SIEVE_THREADS), 0, st, Ly.i0,
                          (const uint32_t*)(W + Ly.bitmap), (const uint32_t*)(W + Ly.seg_off), (const GroupTable*)gt,
                          primes, cap);

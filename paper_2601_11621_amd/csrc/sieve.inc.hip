@@ -20,14 +20,16 @@
 // followed by the large primes with e = 1.
 
 // Segments of 2^14 odd numbers (2 KB bit maps) by default; ranges of at
-// least 2^10 segments of 2^16 (n above about 6.7e7) use 2^16, which divides
-// the per-seed start computations of a segment over four times the numbers.
+// least 2^10 segments of 2^16 (n above about 6.7e7) use 2^16, and ranges of
+// at least 2^10 segments of 2^17 (n above about 1.3e8) use 2^17: the
+// per-seed start computations of a segment are spread over 4 or 8 times the
+// numbers.
 #define SIEVE_SEG_LOG 14
 #define SIEVE_SEG_LOG_BIG 16
+#define SIEVE_SEG_LOG_HUGE 17
 #define SIEVE_SEG (1u << SIEVE_SEG_LOG)        // odd numbers per segment (default)
 #define SIEVE_WORDS (SIEVE_SEG / 32)
 #define SIEVE_THREADS 256
-#define SCATTER_STAGE 8192                      // primes of a segment staged in LDS by k_scatter (32 KB)
 #define SEED_MAX 6544                           // pi(65535) = 6542
 
 struct GroupTable {
@@ -375,10 +377,13 @@ __global__ void __launch_bounds__(SIEVE_THREADS) k_scatter(uint64_t i0, const ui
   uint32_t total;
   uint32_t r = block_excl_scan_1024(c, tmp, &total);
   const uint64_t base = (uint64_t)gt->n_seed_e1 + seg_off[blockIdx.x];
-  if (total <= SCATTER_STAGE) {
+  // primes of a segment staged in LDS: 32 KB, 64 KB for segments of 2^17
+  // (about 12,000 primes near 4e9)
+  constexpr uint32_t STAGE = SL >= SIEVE_SEG_LOG_HUGE ? 16384 : 8192;
+  if (total <= STAGE) {
     // the segment's primes are one contiguous run: staged in LDS in order,
     // then written by consecutive threads to consecutive words
-    __shared__ uint32_t stage[SCATTER_STAGE];
+    __shared__ uint32_t stage[STAGE];
 #pragma unroll
     for (uint32_t k = 0; k < WPT; k++) {
       uint32_t v = w[k];
