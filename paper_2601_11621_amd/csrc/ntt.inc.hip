@@ -1698,15 +1698,14 @@ __device__ __forceinline__ void crt_local(const CrtSeg& sg, const uint32_t* __re
   uint32_t x0[CAT_CRT_E], x1[CAT_CRT_E], x2[CAT_CRT_E];
   uint32_t y0 = 0, y1 = 0, y2 = 0;
   // the thread's 3*E residue loads, and its left-context position, in flight
-  // together; positions past the segment read as zero residues (V = 0)
+  // together; positions past the segment read as zero residues (V = 0).
+  // The residues are read once, so those loads are non-temporal.
   if (kb + CAT_CRT_BLOCK <= sg.len) {
-    const CrtWords a0 = *(const CrtWords*)(r0 + k0), a1 = *(const CrtWords*)(r1 + k0),
-                   a2 = *(const CrtWords*)(r2 + k0);
 #pragma unroll
     for (int i = 0; i < CAT_CRT_E; i++) {
-      x0[i] = a0.w[i];
-      x1[i] = a1.w[i];
-      x2[i] = a2.w[i];
+      x0[i] = __builtin_nontemporal_load(r0 + k0 + i);
+      x1[i] = __builtin_nontemporal_load(r1 + k0 + i);
+      x2[i] = __builtin_nontemporal_load(r2 + k0 + i);
     }
   } else {
 #pragma unroll
